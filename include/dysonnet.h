@@ -1,0 +1,155 @@
+/*
+ * dysonnet.h -- C ABI of the MI355X (gfx950) DysonNet local-estimator library.
+ *
+ * What it computes (paper: "DysonNet: Constant-Time Local Updates for Neural Quantum
+ * States"): for a batch of spin configurations s[B,N] it evaluates log psi(s) with a
+ * DysonNet (Sec. II, Eq. (wavefunc); S4 Green's-function mixers, Sec. V and App.
+ * "Details on the implementation of the DysonNet block"), the log-amplitude ratio
+ * log psi(s')/psi(s) of every connected configuration s' of a Hamiltonian -- either by
+ * the ABACUS local update (Sec. III, Algorithm 1, Eqs. (recur_step)-(recur_out),
+ * Theorem 1) or by full re-evaluation -- and the local energy
+ * E_loc(s) = sum_s' <s|H|s'> psi(s')/psi(s) (Eq. (local-estimator)).
+ *
+ * Conventions shared by every call
+ *  - Every function returns dn_status (0 = DN_OK). On failure nothing is promised about
+ *    the outputs; dn_last_error() returns a thread-local message.
+ *  - Array arguments are DEVICE pointers unless stated otherwise. The caller allocates
+ *    and owns them; the library never frees them. All calls are asynchronous on the
+ *    given stream (a hipStream_t passed as void*; NULL = the default stream); outputs
+ *    are valid once the stream has synchronised.
+ *  - The library owns each model: its parameters, the derived tables (Green's-function
+ *    taps, transposed weights) and a growable workspace. A model must not be used from
+ *    two streams at the same time.
+ *  - spins: int8, values +1/-1, row-major [B, N]. Other values give undefined results.
+ *  - sites: int32 [B, M_max, 2]; element m of sample b flips sites[b,m,0] and, unless it
+ *    is -1, sites[b,m,1]. Entries m >= n_conn[b] are ignored on input.
+ *  - logpsi, logratio, eloc, helem, hdiag are float64 in every precision mode.
+ */
+#ifndef DYSONNET_H
+#define DYSONNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DN_OK = 0,
+  DN_EINVAL = 1,        /* bad argument: shape, enum, null pointer, M_max too small */
+  DN_ENOMEM = 2,        /* device allocation failed or the workspace limit was hit */
+  DN_EHIP = 3,          /* a HIP runtime call failed */
+  DN_EUNSUPPORTED = 4,  /* valid request outside what the kernels implement */
+  DN_ESTATE = 5         /* call out of order (e.g. no parameters set yet) */
+} dn_status;
+
+typedef enum { DN_BC_OPEN = 0, DN_BC_PERIODIC = 1 } dn_bc;
+typedef enum { DN_ACT_SILU = 0, DN_ACT_TANH = 1, DN_ACT_IDENTITY = 2 } dn_act;
+/* Arithmetic of the network fields and channel mixing. FP64: everything float64.
+ * FP32: float32 fields, float32 MFMA with float32 accumulation. BF16_MIXED: the channel
+ * mixing products take bfloat16 operands (round to nearest even) with float32
+ * accumulation; everything else as FP32. Kernel generation, the read-out sums and the
+ * log-ratio are float64 in every mode. */
+typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_prec;
+typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
+
+/* Network hyper-parameters (Sec. II; App. "Details on the implementation ...").
+ * N chain length; L blocks; d channels (d <= 64); s S4 state size (s <= 64);
+ * d_out log-cosh read-out units (must be 2); w_c half-width of the phi-stream CNN
+ * (0..3); bc network boundary condition (dn_bc); act local nonlinearity g (dn_act);
+ * inject_phi 1 adds phi^(l) to the h stream before each mixer (Fig. 1c form);
+ * prec arithmetic (dn_prec). */
+typedef struct {
+  int32_t N, L, d, s, d_out, w_c;
+  int32_t bc, act, inject_phi, prec;
+} dn_model_desc;
+
+typedef enum { DN_H_LRTFIM = 0, DN_H_J1J2 = 1 } dn_ham_kind;
+
+/* Hamiltonian. DN_H_LRTFIM (Sec. VI): paper_form = 0 gives
+ *   H = sum_{i<j} J sz_i sz_j / dist^alpha + h sum_i sx_i,
+ * paper_form = 1 gives H = -(J/N_alpha) sum_{i!=j} sz sz / dist^alpha - h sum sx with
+ * N_alpha = 2 sum_{r=1}^{floor(N/2)} r^-alpha; dist = |i-j| (bc open) or
+ * min(|i-j|, N-|i-j|) (periodic). Connected elements: the N single flips, m = site.
+ * DN_H_J1J2 (Eq. (j1j2_hamiltonian), S = sigma/2): J1 on bonds (i,i+1), J2 on (i,i+2);
+ * diagonal (J/4) s_i s_j per bond, element J/2 per antiparallel bond, emitted in the
+ * order i = 0..N-1, then delta = 1, 2 (bonds leaving an open chain are skipped); N >= 5. */
+typedef struct {
+  int32_t kind, bc;
+  double J, alpha, h;
+  int32_t paper_form;
+  double J1, J2;
+} dn_ham_desc;
+
+typedef struct dn_model dn_model; /* opaque */
+
+/* Length of the flat float64 parameter vector for this shape (-1 if the shape is
+ * invalid). Order: E[d], E_phi[d]; per block: W_D[d,d], w[d], K[2w_c+1,d], k[d],
+ * A_D[d,d], b[d], U[d,d], V[d,d]; per mixer (blocks 1..L then the final mixer), per
+ * channel: 12 vectors of length s (Lambda raw real part, Lambda imaginary part, p re/im,
+ * q re/im, B re/im, C+ re/im, C- re/im) and one step offset; A[d, d_out]. Matrices are
+ * row-major, output index first. Lambda = -exp(raw) + i*raw';
+ * Delta_c = exp(ln 0.01 + ln 10 * c/(d-1) + offset_c). */
+int64_t dn_param_count(const dn_model_desc* desc);
+
+/* Create a model (no parameters yet). Validates the shape; DN_EUNSUPPORTED for shapes
+ * the kernels do not cover (d > 64, s > 64, d_out != 2, N > 512, or a float64 field of
+ * one configuration larger than the on-chip tile). *out receives the handle. */
+dn_status dn_model_create(const dn_model_desc* desc, dn_model** out);
+
+/* Cap the workspace the model may allocate (bytes; 0 = no cap). Calls that would need
+ * more fail with DN_ENOMEM. */
+dn_status dn_set_workspace_limit(dn_model* m, size_t bytes);
+
+/* Copy the flat float64 parameter vector (host pointer if params_on_device == 0, else
+ * device) and derive every parameter-only table on the GPU: S4 Green's-function taps of
+ * every mixer by bilinear discretisation and state-matrix powers in float64 (Sec. V,
+ * Eq. (discretization)), transposed/padded weight copies, read-out weights. Synchronises
+ * the stream once to check that the taps are finite (DN_EINVAL otherwise). */
+dn_status dn_model_set_params(dn_model* m, const double* params, int params_on_device, void* stream);
+
+/* Copy the float64 Green's-function taps to taps_out (device), layout [L+1][d][2N-1],
+ * offset r = i - i' stored at r + N - 1 (periodic: the aliased kernel g_(r mod N)). */
+dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream);
+
+/* log psi(s) for B configurations (Eq. (wavefunc) with f = log cosh). */
+dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
+
+/* Connected configurations, matrix elements and diagonal energies of H for B samples.
+ * M_max must be >= N (Ising) or >= 2N (J1-J2). Outputs: sites [B,M_max,2] (unused rows
+ * set to -1), helem [B,M_max] (0 beyond n_conn), n_conn [B], hdiag [B]. */
+dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, int32_t N,
+                       int32_t M_max, int32_t* sites, double* helem, int32_t* n_conn,
+                       double* hdiag, void* stream);
+
+/* log psi(s'_m)/psi(s) for every listed element, by DN_PATH_ABACUS (background caches,
+ * output links and the slice recurrence; clusters must be one site or two sites at
+ * distance <= 2, else DN_EUNSUPPORTED) or DN_PATH_FULL (each s' evaluated from scratch).
+ * logpsi (nullable) receives log psi(s); logratio [B, M_max] gets 0 beyond n_conn. */
+dn_status dn_logratio(dn_model* m, int32_t path, const int8_t* spins, int32_t B,
+                      const int32_t* sites, const int32_t* n_conn, int32_t M_max,
+                      double* logpsi, double* logratio, void* stream);
+
+/* E_loc = hdiag + sum_{m < n_conn} helem_m exp(logratio_m) (Eq. (local-estimator)). */
+dn_status dn_local_energy(const double* hdiag, const double* helem, const int32_t* n_conn,
+                          const double* logratio, int32_t B, int32_t M_max, double* eloc,
+                          void* stream);
+
+/* Whole local estimator: connected elements, log-ratios by `path`, E_loc. logpsi [B]
+ * and eloc [B] are required; logratio [B, M_max] may be NULL (then the library keeps it
+ * in its workspace). */
+dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_t* spins,
+                  int32_t B, int32_t M_max, double* logpsi, double* logratio, double* eloc,
+                  void* stream);
+
+/* Thread-local text of the last error (never NULL). */
+const char* dn_last_error(void);
+
+/* Release the model and its device memory (NULL is ignored). */
+void dn_model_destroy(dn_model* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DYSONNET_H */

@@ -1,0 +1,186 @@
+"""ctypes binding of libdysonnet.so (include/dysonnet.h): argument marshalling only.
+
+Every function here has the name of the C entry point without the ``dn_`` prefix and
+passes device pointers of torch tensors plus the current HIP stream. No arithmetic of the
+method happens in Python. Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdysonnet.so")
+
+DN_OK, DN_EINVAL, DN_ENOMEM, DN_EHIP, DN_EUNSUPPORTED, DN_ESTATE = range(6)
+BC = {"open": 0, "periodic": 1}
+ACT = {"silu": 0, "tanh": 1, "identity": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PATH = {"abacus": 0, "full": 1}
+HAM = {"lrtfim": 0, "j1j2": 1}
+
+# Names declared in include/dysonnet.h (checked against the shared library by the tests).
+EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
+           "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
+           "dn_eloc", "dn_last_error", "dn_model_destroy")
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("N", "L", "d", "s", "d_out", "w_c", "bc", "act", "inject_phi", "prec")]
+
+
+class HamDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("bc", ctypes.c_int32), ("J", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("h", ctypes.c_double), ("paper_form", ctypes.c_int32),
+                ("J1", ctypes.c_double), ("J2", ctypes.c_double)]
+
+
+class DysonNetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dysonnet status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2603_11189_amd.build` (the HIP path has no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.dn_param_count.argtypes = [ctypes.POINTER(ModelDesc)]
+        L.dn_param_count.restype = i64
+        L.dn_model_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(vp)]
+        L.dn_set_workspace_limit.argtypes = [vp, ctypes.c_size_t]
+        L.dn_model_set_params.argtypes = [vp, vp, ctypes.c_int, vp]
+        L.dn_model_get_taps.argtypes = [vp, vp, vp]
+        L.dn_logpsi.argtypes = [vp, vp, i32, vp, vp]
+        L.dn_connected.argtypes = [ctypes.POINTER(HamDesc), vp, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.dn_logratio.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp]
+        L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+        L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
+        L.dn_last_error.restype = ctypes.c_char_p
+        L.dn_model_destroy.argtypes = [vp]
+        L.dn_model_destroy.restype = None
+        for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
+                   "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != DN_OK:
+        raise DysonNetError(st, lib().dn_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def make_desc(shape, prec: str = "fp32") -> ModelDesc:
+    return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c, BC[shape.bc],
+                     ACT[shape.act], shape.inject_phi, PREC[prec])
+
+
+def make_ham(ham) -> HamDesc:
+    return HamDesc(HAM[ham.kind], BC[ham.bc], ham.J, ham.alpha, ham.h, ham.paper_form, ham.J1, ham.J2)
+
+
+def param_count(shape) -> int:
+    return int(lib().dn_param_count(ctypes.byref(make_desc(shape))))
+
+
+class Model:
+    """Owner of one dn_model handle."""
+
+    def __init__(self, shape, prec: str = "fp32"):
+        self.shape, self.prec = shape, prec
+        self._desc = make_desc(shape, prec)
+        h = ctypes.c_void_p()
+        _check(lib().dn_model_create(ctypes.byref(self._desc), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dn_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_workspace_limit(self, nbytes: int):
+        _check(lib().dn_set_workspace_limit(self.handle, nbytes))
+
+    def set_params(self, params: torch.Tensor):
+        """params: float64 tensor (host or device), flat, canonical order."""
+        p = params.contiguous()
+        assert p.dtype == torch.float64
+        _check(lib().dn_model_set_params(self.handle, _ptr(p), int(p.is_cuda), _stream()))
+
+    def get_taps(self) -> torch.Tensor:
+        s = self.shape
+        out = torch.empty((s.L + 1, s.d, 2 * s.N - 1), dtype=torch.float64, device="cuda")
+        _check(lib().dn_model_get_taps(self.handle, _ptr(out), _stream()))
+        return out
+
+    def logpsi(self, spins: torch.Tensor) -> torch.Tensor:
+        B = spins.shape[0]
+        out = torch.empty(B, dtype=torch.float64, device=spins.device)
+        _check(lib().dn_logpsi(self.handle, _ptr(spins), B, _ptr(out), _stream()))
+        return out
+
+    def logratio(self, spins, sites, n_conn, path: str = "abacus", want_logpsi: bool = True):
+        B, M_max = sites.shape[0], sites.shape[1]
+        lr = torch.empty((B, M_max), dtype=torch.float64, device=spins.device)
+        lp = torch.empty(B, dtype=torch.float64, device=spins.device) if want_logpsi else None
+        _check(lib().dn_logratio(self.handle, PATH[path], _ptr(spins), B, _ptr(sites), _ptr(n_conn), M_max,
+                                 _ptr(lp), _ptr(lr), _stream()))
+        return lp, lr
+
+    def eloc(self, ham, spins, M_max: int, path: str = "abacus", out=None):
+        B = spins.shape[0]
+        if out is None:
+            out = (torch.empty(B, dtype=torch.float64, device=spins.device),
+                   torch.empty((B, M_max), dtype=torch.float64, device=spins.device),
+                   torch.empty(B, dtype=torch.float64, device=spins.device))
+        lp, lr, el = out
+        hd = make_ham(ham)
+        _check(lib().dn_eloc(self.handle, PATH[path], ctypes.byref(hd), _ptr(spins), B, M_max, _ptr(lp), _ptr(lr),
+                             _ptr(el), _stream()))
+        return lp, lr, el
+
+
+def connected(ham, spins: torch.Tensor, M_max: int):
+    B, N = spins.shape
+    dev = spins.device
+    sites = torch.empty((B, M_max, 2), dtype=torch.int32, device=dev)
+    helem = torch.empty((B, M_max), dtype=torch.float64, device=dev)
+    n_conn = torch.empty(B, dtype=torch.int32, device=dev)
+    hdiag = torch.empty(B, dtype=torch.float64, device=dev)
+    hd = make_ham(ham)
+    _check(lib().dn_connected(ctypes.byref(hd), _ptr(spins), B, N, M_max, _ptr(sites), _ptr(helem), _ptr(n_conn),
+                              _ptr(hdiag), _stream()))
+    return sites, helem, n_conn, hdiag
+
+
+def local_energy(hdiag, helem, n_conn, logratio):
+    B, M_max = helem.shape
+    out = torch.empty(B, dtype=torch.float64, device=helem.device)
+    _check(lib().dn_local_energy(_ptr(hdiag), _ptr(helem), _ptr(n_conn), _ptr(logratio), B, M_max, _ptr(out),
+                                 _stream()))
+    return out

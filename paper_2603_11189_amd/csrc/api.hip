@@ -1,0 +1,678 @@
+// C ABI of the DysonNet local-estimator library (declared in include/dysonnet.h).
+//
+// Host orchestration only: argument checks, workspace management, and the order of kernel
+// launches on the caller's stream. Every arithmetic step runs in the kernels of
+// s4gen.h, kernels.h and ham.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dysonnet.h"
+#include "common.h"
+#include "ham.h"
+#include "kernels.h"
+#include "s4gen.h"
+
+using namespace dn;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+dn_status fail(dn_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(DN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+#define STCHK(expr)                     \
+  do {                                  \
+    dn_status s_ = (expr);              \
+    if (s_ != DN_OK) return s_;         \
+  } while (0)
+
+int pad_to(int x, int m) { return (x + m - 1) / m * m; }
+
+struct Layout {
+  long off_layers, off_s4, off_A, P;
+};
+
+bool layout_of(const dn_model_desc& d, Layout* lo) {
+  if (d.N < 1 || d.L < 1 || d.d < 1 || d.s < 1 || d.d_out < 1 || d.w_c < 0) return false;
+  const long dd = d.d, Wc = 2 * d.w_c + 1;
+  lo->off_layers = 2 * dd;
+  const long lay = 4 * dd * dd + 3 * dd + Wc * dd;
+  lo->off_s4 = lo->off_layers + d.L * lay;
+  lo->off_A = lo->off_s4 + (long)(d.L + 1) * dd * (12L * d.s + 1);
+  lo->P = lo->off_A + dd * d.d_out;
+  return true;
+}
+
+// Parameter-derived tables in one element type.
+template <typename T> struct TableBufs {
+  std::vector<void*> owned;
+  Tables<T> tb{};
+  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk;
+};
+
+struct Workspace {
+  std::map<std::string, std::pair<void*, size_t>> slots;
+  size_t limit = 0, used = 0;
+  ~Workspace() {
+    for (auto& kv : slots) if (kv.second.first) (void)hipFree(kv.second.first);
+  }
+};
+
+}  // namespace
+
+struct dn_model {
+  dn_model_desc desc{};
+  Layout lay{};
+  int DP = 0, Np = 0, Wc = 0;
+  bool have_params = false;
+  double* params = nullptr;   // [P]
+  double* taps64 = nullptr;   // [L+1][d][2N-1]
+  double* A64 = nullptr;      // [DP][2]
+  double* omega = nullptr;    // [DP][Np]
+  // float64 tables (always) and float32 tables (FP32 / BF16 modes)
+  TableBufs<double> t64;
+  TableBufs<float> t32;
+  Workspace ws;
+  std::vector<void*> owned;
+  ~dn_model() {
+    for (void* p : owned) (void)hipFree(p);
+    for (void* p : t64.owned) (void)hipFree(p);
+    for (void* p : t32.owned) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+dn_status ws_get(dn_model* m, const char* name, size_t bytes, void** out) {
+  bytes = std::max<size_t>(bytes, 256);
+  auto& slot = m->ws.slots[name];
+  if (slot.second >= bytes) { *out = slot.first; return DN_OK; }
+  size_t newused = m->ws.used - slot.second + bytes;
+  if (m->ws.limit && newused > m->ws.limit)
+    return fail(DN_ENOMEM, std::string("workspace limit exceeded for ") + name);
+  if (slot.first) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(slot.first));
+    m->ws.used -= slot.second;
+    slot = {nullptr, 0};
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(DN_ENOMEM, std::string("hipMalloc failed for ") + name);
+  slot = {p, bytes};
+  m->ws.used += bytes;
+  *out = p;
+  return DN_OK;
+}
+
+template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m) {
+  const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
+  auto get = [&](T** p, long n) -> bool {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<long>(n, 1) * sizeof(T)) != hipSuccess) return false;
+    tb.owned.push_back(q);
+    *p = (T*)q;
+    return true;
+  };
+  bool ok = get(&tb.E, DP) && get(&tb.Ephi, DP) && get(&tb.wE1, DP) && get(&tb.WDt, L * DP * DP) &&
+            get(&tb.ADt, L * DP * DP) && get(&tb.Ut, L * DP * DP) && get(&tb.Vt, L * DP * DP) &&
+            get(&tb.Um, L * DP * DP) && get(&tb.Vm, L * DP * DP) && get(&tb.wv, L * DP) &&
+            get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
+            get(&tb.taps, L * DP * 2 * Np) && get(&tb.tapsR, DP * 2 * Np) && get(&tb.Wk, 2 * DP * Np);
+  if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
+  tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
+                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk};
+  return DN_OK;
+}
+
+long table_elems(const dn_model& m) {
+  const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
+  return 3 * DP + 6 * L * DP * DP + 3 * L * DP + L * Wc * DP + L * DP * 2 * Np + DP * 2 * Np + 2 * DP * Np;
+}
+
+// Copy double tables into float tables (same member order).
+dn_status convert_tables(dn_model* m, hipStream_t st) {
+  TableBufs<double>& a = m->t64;
+  TableBufs<float>& b = m->t32;
+  const long DP = m->DP, Np = m->Np, L = m->desc.L, Wc = m->Wc;
+  struct P { double* s; float* d; long n; } items[] = {
+      {a.E, b.E, DP}, {a.Ephi, b.Ephi, DP}, {a.wE1, b.wE1, DP}, {a.WDt, b.WDt, L * DP * DP},
+      {a.ADt, b.ADt, L * DP * DP}, {a.Ut, b.Ut, L * DP * DP}, {a.Vt, b.Vt, L * DP * DP},
+      {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
+      {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
+      {a.taps, b.taps, L * DP * 2 * Np}, {a.tapsR, b.tapsR, DP * 2 * Np}, {a.Wk, b.Wk, 2 * DP * Np}};
+  for (auto& it : items) {
+    int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
+    convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);
+  }
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+template <typename K> void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+// ------------------------------------------------------------------------------------------
+// Network passes, templated on element type T and padded channel count DP.
+
+template <typename T> const Tables<T>& tables_of(dn_model* m);
+template <> const Tables<double>& tables_of<double>(dn_model* m) { return m->t64.tb; }
+template <> const Tables<float>& tables_of<float>(dn_model* m) { return m->t32.tb; }
+
+template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const T* taps, int C, hipStream_t st) {
+  if (C <= 0) return DN_OK;
+  const int Np = m->Np;
+  ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP};
+  const size_t lds = (CONV_MC * CONV_LD + 2 * Np) * sizeof(T);
+  const int nt = Np >= 256 ? 4 : Np / 64;  // 16-site tiles per wave
+  dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
+  switch (nt) {
+    case 1: allow_lds(conv_kernel<T, 1>, lds); conv_kernel<T, 1><<<grid, 256, lds, st>>>(a); break;
+    case 2: allow_lds(conv_kernel<T, 2>, lds); conv_kernel<T, 2><<<grid, 256, lds, st>>>(a); break;
+    case 3: allow_lds(conv_kernel<T, 3>, lds); conv_kernel<T, 3><<<grid, 256, lds, st>>>(a); break;
+    default: allow_lds(conv_kernel<T, 4>, lds); conv_kernel<T, 4><<<grid, 256, lds, st>>>(a); break;
+  }
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>& a, int C, hipStream_t st) {
+  if (C <= 0) return DN_OK;
+  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c) + m->Np) * sizeof(T);
+  if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "phi stream tile exceeds LDS");
+  allow_lds(phi_kernel<T, DP>, lds);
+  phi_kernel<T, DP><<<C, 256, lds, st>>>(a);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+template <typename T, int DP, int MODE, bool FIRST, bool LAST>
+dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
+  if (C <= 0) return DN_OK;
+  const size_t lds = (size_t)DP * m->Np * sizeof(T);
+  if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "mixing tile exceeds LDS");
+  allow_lds(mix_kernel<T, DP, MODE, FIRST, LAST>, lds);
+  mix_kernel<T, DP, MODE, FIRST, LAST><<<C, 256, lds, st>>>(a);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+// Forward of C configurations listed by `map` entries [cfg0, cfg0+C). rho[C][2] receives
+// Omega. With caches (ABACUS background), a/chi/p0 of every block are written layer-major
+// [L][C][DP][Np].
+template <typename T, int DP>
+dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, int C, double* rho,
+                        T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  const int Np = m->Np, L = d.L;
+  const long fld = (long)C * DP * Np;
+  void *pphi, *pchi0, *pchi1, *pu, *pv;
+  STCHK(ws_get(m, "fw_phi", fld * sizeof(T), &pphi));
+  STCHK(ws_get(m, "fw_chi0", fld * sizeof(T), &pchi0));
+  STCHK(ws_get(m, "fw_chi1", fld * sizeof(T), &pchi1));
+  STCHK(ws_get(m, "fw_u", fld * sizeof(T), &pu));
+  STCHK(ws_get(m, "fw_v", fld * sizeof(T), &pv));
+  T* phi = (T*)pphi;
+  T* chib[2] = {(T*)pchi0, (T*)pchi1};
+  T* u = (T*)pu;
+  T* v = (T*)pv;
+  const Tables<T>& tb = tables_of<T>(m);
+  auto chi_of = [&](int l) -> T* { return cache_chi ? cache_chi + (long)l * fld : chib[l & 1]; };
+  auto phi_pass = [&](int l) -> dn_status {
+    PhiArgs<T> a{};
+    a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.w_c = d.w_c; a.periodic = d.bc == DN_BC_PERIODIC;
+    a.act = d.act; a.inject = d.inject_phi; a.first = (l == 0); a.spins = spins; a.map = map;
+    a.cfg0 = cfg0; a.C = C; a.phi_in = phi;
+    a.phi_out = (l + 1 < L || d.inject_phi) ? phi : nullptr;
+    a.chi_out = chi_of(l);
+    a.a_out = cache_a ? cache_a + (long)l * fld : nullptr;
+    a.u_out = u; a.rho = rho;
+    return launch_phi<T, DP>(m, a, C, st);
+  };
+  STCHK(phi_pass(0));
+  for (int l = 0; l < L; ++l) {
+    STCHK(launch_conv<T>(m, u, v, tb.taps + (long)l * DP * 2 * Np, C, st));
+    if (l + 1 < L) STCHK(phi_pass(l + 1));
+    MixArgs<T> a{};
+    a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = d.w_c;
+    a.periodic = d.bc == DN_BC_PERIODIC; a.inject = d.inject_phi; a.C = C; a.cfg0 = cfg0;
+    a.X = v; a.chi = chi_of(l); a.p0_out = cache_p0 ? cache_p0 + (long)l * fld : nullptr;
+    a.phi_next = phi; a.out = (l + 1 < L) ? u : nullptr; a.rho = rho;
+    STCHK((launch_mix<T, DP, MIX_FWD, false, false>(m, a, C, st)));
+  }
+  return DN_OK;
+}
+
+// Builds the (sample, element) work list on the device and validates n_conn and sites; the
+// offsets come back to the host (one stream synchronisation) to size the launches.
+dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, int M_max, int with_base,
+               int32_t** offs, int32_t** cb, int32_t** cm, int upper, std::vector<int32_t>* h_offs,
+               hipStream_t st) {
+  void *po, *pb, *pm;
+  STCHK(ws_get(m, "plan_offs", (size_t)(B + 2) * 4, &po));
+  STCHK(ws_get(m, "plan_cb", (size_t)upper * 4, &pb));
+  STCHK(ws_get(m, "plan_cm", (size_t)upper * 4, &pm));
+  *offs = (int32_t*)po; *cb = (int32_t*)pb; *cm = (int32_t*)pm;
+  plan_kernel<<<1, 1024, 0, st>>>(n_conn, sites, B, m->desc.N, M_max, with_base, *offs, *cb, *cm);
+  HIPCHK(hipGetLastError());
+  h_offs->resize(B + 2);
+  HIPCHK(hipMemcpyAsync(h_offs->data(), *offs, (size_t)(B + 2) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if ((*h_offs)[B + 1] & 1) return fail(DN_EINVAL, "n_conn outside [0, M_max]");
+  if ((*h_offs)[B + 1] & 2) return fail(DN_EINVAL, "a site index is outside the chain (or a pair repeats a site)");
+  return DN_OK;
+}
+
+size_t chunk_configs(const dn_model* m, size_t elem, int fields, size_t budget) {
+  size_t per = (size_t)m->DP * m->Np * elem * fields;
+  size_t c = budget / std::max<size_t>(per, 1);
+  return std::max<size_t>(64, std::min<size_t>(c, 1 << 20) / 64 * 64);
+}
+
+template <typename T, int DP>
+dn_status logratio_full(dn_model* m, const int8_t* spins, int B, const int32_t* sites, const int32_t* n_conn,
+                        int M_max, double* logpsi, double* logratio, hipStream_t st) {
+  int32_t *offs, *cb, *cm;
+  std::vector<int32_t> h_offs;
+  STCHK(plan(m, n_conn, sites, B, M_max, 1, &offs, &cb, &cm, B * (M_max + 1), &h_offs, st));
+  const int total = h_offs[B];
+  void* prho;
+  STCHK(ws_get(m, "full_rho", (size_t)std::max(total, 1) * 2 * sizeof(double), &prho));
+  double* rho = (double*)prho;
+  CfgMap map{cb, cm, sites, M_max};
+  const size_t chunk = chunk_configs(m, sizeof(T), 5, (size_t)6 << 30);
+  for (int c0 = 0; c0 < total; c0 += (int)chunk) {
+    const int C = (int)std::min<size_t>(chunk, total - c0);
+    STCHK((forward_chunk<T, DP>(m, spins, map, c0, C, rho + 2L * c0, nullptr, nullptr, nullptr, st)));
+  }
+  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
+  plain_ratio_kernel<<<(total + 255) / 256, 256, 0, st>>>(rho, offs, cb, cm, total, M_max, logratio);
+  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(rho, offs, B, logpsi);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+// ABACUS: background forward with caches, the adjoint tau of the last block, the slice
+// recompute, the background propagation of each flip's perturbation through blocks
+// 1..L-1, the last block's slice and the float64 log-ratio.
+template <typename T, int DP>
+dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t* sites, const int32_t* n_conn,
+                          int M_max, double* logpsi, double* logratio, hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  const int Np = m->Np, L = d.L, wc = d.w_c;
+  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 is not implemented on the GPU");
+  int32_t *offs, *cb, *cm;
+  std::vector<int32_t> h_offs;
+  STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
+  // identity map for the background forward
+  void *pib, *pim, *pOm, *perr;
+  STCHK(ws_get(m, "ab_idb", (size_t)B * 4, &pib));
+  STCHK(ws_get(m, "ab_idm", (size_t)B * 4, &pim));
+  STCHK(ws_get(m, "ab_Om0", (size_t)B * 2 * sizeof(double), &pOm));
+  STCHK(ws_get(m, "ab_err", 4, &perr));
+  std::vector<int32_t> iota(B), neg(B, -1);
+  for (int b = 0; b < B; ++b) iota[b] = b;
+  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  fill_kernel<int><<<1, 64, 0, st>>>((int*)perr, 1, 0);
+  double* Om0 = (double*)pOm;
+  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, sites, M_max};
+  CfgMap fmap{cb, cm, sites, M_max};
+  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
+  const Tables<T>& tb = tables_of<T>(m);
+  const int Wmax = 2 + 2 * L * wc + 1;
+  // samples per chunk: the flip fields dominate (2 fields of [F][DP][Np])
+  const size_t per_flip = (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T);
+  const size_t flips_budget = std::max<size_t>(1024, ((size_t)3 << 30) / per_flip);
+  const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
+  for (int b0 = 0; b0 < B; b0 += Bc_max) {
+    const int Bc = std::min(Bc_max, B - b0);
+    const int f0 = h_offs[b0], F = h_offs[b0 + Bc] - f0;
+    const long fldB = (long)Bc * DP * Np;
+    void *pa, *pc, *pp, *ptz, *ptau;
+    STCHK(ws_get(m, "ab_a0", (size_t)L * fldB * sizeof(T), &pa));
+    STCHK(ws_get(m, "ab_chi0", (size_t)L * fldB * sizeof(T), &pc));
+    STCHK(ws_get(m, "ab_p0", (size_t)L * fldB * sizeof(T), &pp));
+    STCHK(ws_get(m, "ab_tz", (size_t)2 * fldB * sizeof(T), &ptz));
+    STCHK(ws_get(m, "ab_tau", (size_t)2 * fldB * sizeof(T), &ptau));
+    T *a0 = (T*)pa, *chi0 = (T*)pc, *p0 = (T*)pp, *tz = (T*)ptz, *tau = (T*)ptau;
+    STCHK((forward_chunk<T, DP>(m, spins, idmap, b0, Bc, Om0 + 2L * b0, a0, chi0, p0, st)));
+    // tau = G^(L)T D0^(L)T Wk
+    {
+      MixArgs<T> a{};
+      a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
+      a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bc; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
+      STCHK((launch_mix<T, DP, MIX_TAU, false, false>(m, a, 2 * Bc, st)));
+      STCHK(launch_conv<T>(m, tz, tau, tb.tapsR, 2 * Bc, st));
+    }
+    if (F == 0) continue;
+    void *pdchi, *pgeom, *prho, *pdu, *pw, *pyL;
+    STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
+    STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
+    STCHK(ws_get(m, "ab_rho", (size_t)F * 2 * sizeof(double), &prho));
+    STCHK(ws_get(m, "ab_yL", (size_t)F * Wmax * DP * sizeof(T), &pyL));
+    T* dchi = (T*)pdchi;
+    int4* geom = (int4*)pgeom;
+    double* rho = (double*)prho;
+    T* yL = (T*)pyL;
+    {
+      SliceArgs<T> a{};
+      a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
+      a.act = d.act; a.F = F; a.f0 = f0; a.b0 = b0; a.Bc = Bc; a.map = fmap; a.spins = spins;
+      a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
+      const size_t lds = 2 * (size_t)Wmax * DP * sizeof(T);
+      slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
+      HIPCHK(hipGetLastError());
+    }
+    fill_kernel<double><<<256, 256, 0, st>>>(rho, 2L * F, 0.0);
+    if (L >= 2) {
+      STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
+      STCHK(ws_get(m, "ab_w", (size_t)F * DP * Np * sizeof(T), &pw));
+      T* du = (T*)pdu;
+      T* w = (T*)pw;
+      for (int l = 1; l <= L - 1; ++l) {
+        MixArgs<T> a{};
+        a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
+        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0;
+        a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
+        a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
+        a.dchi = dchi; a.Wmax = Wmax; a.tau = tau; a.yL = yL;
+        a.tapsL = tb.taps + (long)(L - 1) * DP * 2 * Np; a.taps1 = tb.taps;
+        const bool first = (l == 1), last = (l == L - 1);
+        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * 2 * Np, F, st));
+        // l-1 is the 0-based index of block l in the tables
+        a.l = l;
+        dn_status s;
+        if (first && last) s = launch_mix<T, DP, MIX_DEEP, true, true>(m, a, F, st);
+        else if (first) s = launch_mix<T, DP, MIX_DEEP, true, false>(m, a, F, st);
+        else if (last) s = launch_mix<T, DP, MIX_DEEP, false, true>(m, a, F, st);
+        else s = launch_mix<T, DP, MIX_DEEP, false, false>(m, a, F, st);
+        STCHK(s);
+      }
+    }
+    {
+      TailArgs<T> a{};
+      a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
+      a.F = F; a.f0 = f0; a.b0 = b0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
+      a.yL = yL; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
+      a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax;
+      tail_kernel<T, DP><<<F, 64, 2 * DP * sizeof(T), st>>>(a);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(Om0, nullptr, B, logpsi);
+  int herr = 0;
+  HIPCHK(hipMemcpyAsync(&herr, perr, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (herr) return fail(DN_EUNSUPPORTED, "a cluster is wider than the ABACUS slice recurrence supports (pairs at distance <= 2, slice narrower than the ring)");
+  return DN_OK;
+}
+
+template <typename T, int DP>
+dn_status logpsi_only(dn_model* m, const int8_t* spins, int B, double* logpsi, hipStream_t st) {
+  void *pib, *pim, *prho;
+  STCHK(ws_get(m, "lp_idb", (size_t)B * 4, &pib));
+  STCHK(ws_get(m, "lp_idm", (size_t)B * 4, &pim));
+  STCHK(ws_get(m, "lp_rho", (size_t)B * 2 * sizeof(double), &prho));
+  std::vector<int32_t> iota(B), neg(B, -1);
+  for (int b = 0; b < B; ++b) iota[b] = b;
+  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, nullptr, 0};
+  const size_t chunk = chunk_configs(m, sizeof(T), 5, (size_t)4 << 30);
+  for (int c0 = 0; c0 < B; c0 += (int)chunk) {
+    const int C = (int)std::min<size_t>(chunk, B - c0);
+    STCHK((forward_chunk<T, DP>(m, spins, idmap, c0, C, (double*)prho + 2L * c0, nullptr, nullptr, nullptr, st)));
+  }
+  logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>((double*)prho, nullptr, B, logpsi);
+  HIPCHK(hipGetLastError());
+  // the host iota buffers must outlive the async copies
+  HIPCHK(hipStreamSynchronize(st));
+  return DN_OK;
+}
+
+// Dispatch on element type and padded width.
+template <template <typename, int> class F, typename... Args>
+dn_status dispatch(dn_model* m, Args... args) {
+  const bool dbl = m->desc.prec == DN_PREC_FP64;
+  switch (m->DP) {
+    case 16: return dbl ? F<double, 16>::run(m, args...) : F<float, 16>::run(m, args...);
+    case 32: return dbl ? F<double, 32>::run(m, args...) : F<float, 32>::run(m, args...);
+    case 64: return dbl ? F<double, 64>::run(m, args...) : F<float, 64>::run(m, args...);
+  }
+  return fail(DN_EUNSUPPORTED, "channel width");
+}
+
+template <typename T, int DP> struct RunFull {
+  static dn_status run(dn_model* m, const int8_t* s, int B, const int32_t* si, const int32_t* nc, int M,
+                       double* lp, double* lr, hipStream_t st) {
+    return logratio_full<T, DP>(m, s, B, si, nc, M, lp, lr, st);
+  }
+};
+template <typename T, int DP> struct RunAbacus {
+  static dn_status run(dn_model* m, const int8_t* s, int B, const int32_t* si, const int32_t* nc, int M,
+                       double* lp, double* lr, hipStream_t st) {
+    return logratio_abacus<T, DP>(m, s, B, si, nc, M, lp, lr, st);
+  }
+};
+template <typename T, int DP> struct RunLogpsi {
+  static dn_status run(dn_model* m, const int8_t* s, int B, double* lp, hipStream_t st) {
+    return logpsi_only<T, DP>(m, s, B, lp, st);
+  }
+};
+
+bool check_desc(const dn_model_desc* d, std::string* why) {
+  if (!d) { *why = "null descriptor"; return false; }
+  if (d->N < 2 || d->N > 512) { *why = "N must be in [2, 512]"; return false; }
+  if (d->L < 1 || d->L > 8) { *why = "L must be in [1, 8]"; return false; }
+  if (d->d < 1 || d->d > 64) { *why = "d must be in [1, 64]"; return false; }
+  if (d->s < 1 || d->s > S4_SMAX) { *why = "s must be in [1, 32]"; return false; }
+  if (d->d_out != 2) { *why = "d_out must be 2"; return false; }
+  if (d->w_c < 0 || d->w_c > 3) { *why = "w_c must be in [0, 3]"; return false; }
+  if (d->N <= 2 * d->w_c) { *why = "N must exceed 2 w_c"; return false; }
+  if (d->bc != DN_BC_OPEN && d->bc != DN_BC_PERIODIC) { *why = "bad bc"; return false; }
+  if (d->act < 0 || d->act > 2) { *why = "bad act"; return false; }
+  if (d->inject_phi != 0 && d->inject_phi != 1) { *why = "inject_phi must be 0 or 1"; return false; }
+  if (d->prec < 0 || d->prec > 2) { *why = "bad prec"; return false; }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t dn_param_count(const dn_model_desc* desc) {
+  Layout lo;
+  if (!desc || !layout_of(*desc, &lo)) return -1;
+  return lo.P;
+}
+
+const char* dn_last_error(void) { return g_err.c_str(); }
+
+dn_status dn_model_create(const dn_model_desc* desc, dn_model** out) {
+  std::string why;
+  if (!out) return fail(DN_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!check_desc(desc, &why)) return fail(desc ? DN_EUNSUPPORTED : DN_EINVAL, why);
+  if (desc->prec == DN_PREC_BF16_MIXED) return fail(DN_EUNSUPPORTED, "BF16-mixed precision is not implemented");
+  dn_model* m = new dn_model();
+  m->desc = *desc;
+  layout_of(*desc, &m->lay);
+  m->DP = desc->d <= 16 ? 16 : desc->d <= 32 ? 32 : 64;
+  m->Np = pad_to(desc->N, 64);
+  m->Wc = 2 * desc->w_c + 1;
+  const size_t elem = desc->prec == DN_PREC_FP64 ? 8 : 4;
+  if ((size_t)m->DP * (m->Np + 2 * desc->w_c) * elem + m->Np * elem > LDS_MAX) {
+    delete m;
+    return fail(DN_EUNSUPPORTED, "one configuration's field does not fit the on-chip tile at this precision");
+  }
+  auto get = [&](double** p, long n) -> bool {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<long>(n, 1) * sizeof(double)) != hipSuccess) return false;
+    m->owned.push_back(q);
+    *p = (double*)q;
+    return true;
+  };
+  const long L = desc->L;
+  bool ok = get(&m->params, m->lay.P) && get(&m->taps64, (L + 1) * desc->d * (2L * desc->N - 1)) &&
+            get(&m->A64, 2L * m->DP) && get(&m->omega, (long)m->DP * m->Np);
+  if (!ok) { delete m; return fail(DN_ENOMEM, "hipMalloc failed for model storage"); }
+  if (alloc_tables(m->t64, *m) != DN_OK) { delete m; return DN_ENOMEM; }
+  if (desc->prec != DN_PREC_FP64 && alloc_tables(m->t32, *m) != DN_OK) { delete m; return DN_ENOMEM; }
+  *out = m;
+  return DN_OK;
+}
+
+dn_status dn_set_workspace_limit(dn_model* m, size_t bytes) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  m->ws.limit = bytes;
+  return DN_OK;
+}
+
+dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, void* stream) {
+  if (!m || !params) return fail(DN_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const dn_model_desc& d = m->desc;
+  HIPCHK(hipMemcpyAsync(m->params, params, m->lay.P * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  const size_t lds = 2 * (size_t)(d.N + 1) * sizeof(double);
+  s4_taps_kernel<<<(d.L + 1) * d.d, S4_THREADS, lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s,
+                                                           d.bc == DN_BC_PERIODIC, m->taps64);
+  HIPCHK(hipGetLastError());
+  PrepArgs a{};
+  a.params = m->params; a.taps64 = m->taps64; a.N = d.N; a.Np = m->Np; a.L = d.L; a.d = d.d; a.DP = m->DP;
+  a.s = d.s; a.w_c = d.w_c; a.d_out = d.d_out; a.off_layers = m->lay.off_layers; a.off_A = m->lay.off_A;
+  TableBufs<double>& t = m->t64;
+  a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
+  a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;
+  a.tapsR = t.tapsR; a.omega = m->omega; a.Wk = t.Wk; a.A = m->A64;
+  prep_kernel<<<256, 256, 0, st>>>(a);
+  HIPCHK(hipGetLastError());
+  if (d.prec != DN_PREC_FP64) STCHK(convert_tables(m, st));
+  void* pbad;
+  STCHK(ws_get(m, "sp_bad", 4, &pbad));
+  fill_kernel<int><<<1, 64, 0, st>>>((int*)pbad, 1, 0);
+  const long nt = (d.L + 1L) * d.d * (2L * d.N - 1);
+  finite_check_kernel<<<256, 256, 0, st>>>(m->taps64, nt, (int*)pbad);
+  int hbad = 0;
+  HIPCHK(hipMemcpyAsync(&hbad, pbad, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hbad) return fail(DN_EINVAL, "Green's-function taps are not finite (unstable state matrix?)");
+  m->have_params = true;
+  return DN_OK;
+}
+
+dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream) {
+  if (!m || !taps_out) return fail(DN_EINVAL, "null argument");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  const long n = (m->desc.L + 1L) * m->desc.d * (2L * m->desc.N - 1);
+  HIPCHK(hipMemcpyAsync(taps_out, m->taps64, n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return DN_OK;
+}
+
+dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0) return fail(DN_EINVAL, "B < 0");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if (B == 0) return DN_OK;
+  if (!spins || !logpsi) return fail(DN_EINVAL, "null argument");
+  return dispatch<RunLogpsi>(m, spins, (int)B, logpsi, (hipStream_t)stream);
+}
+
+dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, int32_t N, int32_t M_max,
+                       int32_t* sites, double* helem, int32_t* n_conn, double* hdiag, void* stream) {
+  if (!ham) return fail(DN_EINVAL, "null argument");
+  if (B < 0 || N < 2) return fail(DN_EINVAL, "bad B or N");
+  if (B > 0 && (!spins || !sites || !helem || !n_conn || !hdiag)) return fail(DN_EINVAL, "null argument");
+  if (ham->kind != DN_H_LRTFIM && ham->kind != DN_H_J1J2) return fail(DN_EINVAL, "bad Hamiltonian kind");
+  if (ham->bc != DN_BC_OPEN && ham->bc != DN_BC_PERIODIC) return fail(DN_EINVAL, "bad Hamiltonian bc");
+  if (ham->kind == DN_H_LRTFIM && M_max < N) return fail(DN_EINVAL, "M_max must be >= N for the Ising chain");
+  if (ham->kind == DN_H_J1J2 && M_max < 2 * N) return fail(DN_EINVAL, "M_max must be >= 2N for the J1-J2 chain");
+  if (ham->kind == DN_H_J1J2 && N < 5) return fail(DN_EINVAL, "the J1-J2 chain needs N >= 5");
+  if (B == 0) return DN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  double* Jr = nullptr;
+  thread_local double* tl_Jr = nullptr;
+  thread_local int tl_N = 0;
+  if (ham->kind == DN_H_LRTFIM) {
+    if (tl_N < N) {
+      if (tl_Jr) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(tl_Jr)); tl_Jr = nullptr; }
+      if (hipMalloc(&tl_Jr, (size_t)N * sizeof(double)) != hipSuccess) return fail(DN_ENOMEM, "coupling table");
+      tl_N = N;
+    }
+    Jr = tl_Jr;
+    ising_table_kernel<<<1, 64, 0, st>>>(N, ham->bc == DN_BC_PERIODIC, ham->J, ham->alpha, ham->paper_form, Jr);
+  }
+  const double cx = ham->paper_form ? -ham->h : ham->h;
+  connected_kernel<<<B, 64, 0, st>>>(ham->kind, ham->bc == DN_BC_PERIODIC, cx, ham->J1, ham->J2, Jr, spins, N,
+                                     M_max, sites, helem, n_conn, hdiag);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status dn_logratio(dn_model* m, int32_t path, const int8_t* spins, int32_t B, const int32_t* sites,
+                      const int32_t* n_conn, int32_t M_max, double* logpsi, double* logratio, void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0 || M_max < 1) return fail(DN_EINVAL, "bad B or M_max");
+  if (path != DN_PATH_ABACUS && path != DN_PATH_FULL) return fail(DN_EINVAL, "bad path");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if ((long)B * (M_max + 1) > (1L << 31) - 1) return fail(DN_EINVAL, "B * (M_max + 1) too large");
+  if (B == 0) return DN_OK;
+  if (!spins || !sites || !n_conn || !logratio) return fail(DN_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (path == DN_PATH_FULL) return dispatch<RunFull>(m, spins, (int)B, sites, n_conn, (int)M_max, logpsi, logratio, st);
+  return dispatch<RunAbacus>(m, spins, (int)B, sites, n_conn, (int)M_max, logpsi, logratio, st);
+}
+
+dn_status dn_local_energy(const double* hdiag, const double* helem, const int32_t* n_conn, const double* logratio,
+                          int32_t B, int32_t M_max, double* eloc, void* stream) {
+  if (B < 0 || M_max < 1) return fail(DN_EINVAL, "bad B or M_max");
+  if (B == 0) return DN_OK;
+  if (!hdiag || !helem || !n_conn || !logratio || !eloc) return fail(DN_EINVAL, "null argument");
+  eloc_kernel<<<B, 64, 0, (hipStream_t)stream>>>(hdiag, helem, n_conn, logratio, M_max, eloc);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_t* spins, int32_t B, int32_t M_max,
+                  double* logpsi, double* logratio, double* eloc, void* stream) {
+  if (!m || !ham) return fail(DN_EINVAL, "null argument");
+  if (B < 0) return fail(DN_EINVAL, "B < 0");
+  if (B == 0) return DN_OK;
+  if (!spins || !logpsi || !eloc) return fail(DN_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  void *ps, *ph, *pn, *pd, *pl;
+  STCHK(ws_get(m, "el_sites", (size_t)B * M_max * 2 * 4, &ps));
+  STCHK(ws_get(m, "el_helem", (size_t)B * M_max * 8, &ph));
+  STCHK(ws_get(m, "el_nconn", (size_t)B * 4, &pn));
+  STCHK(ws_get(m, "el_hdiag", (size_t)B * 8, &pd));
+  if (!logratio) {
+    STCHK(ws_get(m, "el_lr", (size_t)B * M_max * 8, &pl));
+    logratio = (double*)pl;
+  }
+  STCHK(dn_connected(ham, spins, B, m->desc.N, M_max, (int32_t*)ps, (double*)ph, (int32_t*)pn, (double*)pd, stream));
+  STCHK(dn_logratio(m, path, spins, B, (int32_t*)ps, (int32_t*)pn, M_max, logpsi, logratio, stream));
+  return dn_local_energy((double*)pd, (double*)ph, (int32_t*)pn, logratio, B, M_max, eloc, stream);
+}
+
+void dn_model_destroy(dn_model* m) { delete m; }
+
+}  // extern "C"

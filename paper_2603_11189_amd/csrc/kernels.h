@@ -1,0 +1,654 @@
+// Network kernels: phi stream, Green's-function mixer (Toeplitz products on the matrix
+// cores), vertex + channel mixing with the read-out, and the ABACUS update.
+//
+// Field layout in HBM: [configuration][channel DP][site Np], sites fastest, DP = d padded
+// to a multiple of 16, Np = N padded to a multiple of 64. Padded channels hold exact
+// zeros (their weights are zero); padded sites are written as zeros and never read as
+// inputs of real sites.
+#pragma once
+#include "common.h"
+
+namespace dn {
+
+template <typename T> struct Tables {
+  const T *E, *Ephi, *wE1;
+  const T *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP]
+  const T *wv, *Kc, *kv, *bv;              // [L][DP], K [L][2w_c+1][DP]
+  const T *taps, *tapsR;                   // [L][DP][2Np], [DP][2Np]
+  const T *Wk;                             // [2][DP][Np]
+};
+
+// Which configuration a block works on. Plain path: cfg g -> sample b, element m (m = -1
+// is the unflipped sample). ABACUS: flip f -> (b, m).
+struct CfgMap {
+  const int32_t* cb;  // [count]
+  const int32_t* cm;  // [count]
+  const int32_t* sites;  // [B][M_max][2]
+  int M_max;
+};
+
+// ---------------------------------------------------------------------------------------
+// phi stream of block l (App. "Details on the implementation of the DysonNet block"):
+//   a = W_D phi^(l-1) + w;  phi^(l) = g(sum_r K_r * a_{i+r} + k);  chi^(l) = g(A_D phi^(l) + b)
+// Block 1 uses phi^(0) = E_phi s', so a = s'_i (W_D E_phi) + w (rank one). Block 1 also
+// writes u^(1) = E s' (+ phi^(1) when injected) and starts the read-out sum with h^(0).
+// One workgroup (4 waves) per configuration; a is staged in LDS with a halo of w_c.
+template <typename T> struct PhiArgs {
+  Tables<T> tb;
+  int N, Np, l, w_c, periodic, act, inject;
+  int first;
+  const int8_t* spins;  // [B][N]
+  CfgMap map;
+  int cfg0, C;          // configurations [cfg0, cfg0 + C)
+  const T* phi_in;      // [C][DP][Np]
+  T* phi_out;           // nullable
+  T* chi_out;
+  T* a_out;             // cache, nullable
+  T* u_out;             // first block only
+  double* rho;          // first block only: [C][2]
+};
+
+template <typename T, int DP>
+__global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* as = reinterpret_cast<T*>(smem_raw);
+  const int g = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int N = A.N, Np = A.Np, wc = A.w_c;
+  const int ld = Np + 2 * wc;
+  T* sp_s = as + DP * ld;  // s' (first block), [Np]
+  __shared__ double red[2][4];
+  const long fo = (long)g * DP * Np;
+  constexpr int MT = DP / 16, KS = DP / 4;
+  using M = Mma<T>;
+  const int l = A.l;
+  if (A.first) {
+    const int gg = A.cfg0 + g;
+    const int b = A.map.cb[gg], m = A.map.cm[gg];
+    int f0 = -1, f1 = -1;
+    if (m >= 0) {
+      f0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
+      f1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
+    }
+    const int8_t* sp = A.spins + (long)b * N;
+    for (int i = threadIdx.x; i < Np; i += 256) {
+      T v = 0;
+      if (i < N) {
+        v = (T)sp[i];
+        if (i == f0 || i == f1) v = -v;
+      }
+      sp_s[i] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < DP * Np; idx += 256) {
+      int c = idx / Np, i = idx % Np;
+      T v = (i < N) ? sp_s[i] * A.tb.wE1[c] + A.tb.wv[c] : T(0);
+      as[c * ld + i + wc] = v;
+      if (A.a_out) A.a_out[fo + idx] = v;
+    }
+  } else {
+    const T* WDt = A.tb.WDt + (long)l * DP * DP;
+    const T* x = A.phi_in + fo;
+    for (int nt = wave; nt < Np / 16; nt += 4) {
+      typename M::acc acc[MT];
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
+      const int i = nt * 16 + (lane & 15);
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kc = 4 * ks + (lane >> 4);
+        const T bv = x[kc * Np + i];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(WDt[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * mt + M::row(lane, r);
+          T v = (i < N) ? acc[mt][r] + A.tb.wv[l * DP + ch] : T(0);
+          as[ch * ld + i + wc] = v;
+          if (A.a_out) A.a_out[fo + (long)ch * Np + i] = v;
+        }
+    }
+  }
+  __syncthreads();
+  // halos of width w_c (open: zero; periodic: wrap-around), plus wrap for padded tail
+  if (wc > 0) {
+    for (int idx = threadIdx.x; idx < DP * 2 * wc; idx += 256) {
+      int c = idx / (2 * wc), h = idx % (2 * wc);
+      int col, src;
+      if (h < wc) { col = h; src = N - wc + h; }           // sites -wc..-1
+      else { col = N + wc + (h - wc); src = h - wc; }      // sites N..N+wc-1
+      as[c * ld + col] = A.periodic ? as[c * ld + src + wc] : T(0);
+    }
+  }
+  __syncthreads();
+  const T* ADt = A.tb.ADt + (long)l * DP * DP;
+  const T* Kc = A.tb.Kc + (long)l * (2 * wc + 1) * DP;
+  double part0 = 0.0, part1 = 0.0;
+  for (int nt = wave; nt < Np / 16; nt += 4) {
+    typename M::acc acc[MT];
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
+    const int i = nt * 16 + (lane & 15);
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + (lane >> 4);
+      T ph = 0;
+      if (i < N) {
+        T s = A.tb.kv[l * DP + kc];
+        for (int r = -wc; r <= wc; ++r) s += Kc[(r + wc) * DP + kc] * as[kc * ld + i + r + wc];
+        ph = act_fn<T>(A.act, s);
+      }
+      if (A.phi_out) A.phi_out[fo + (long)kc * Np + i] = ph;
+      if (A.first) {
+        T h0 = (i < N) ? A.tb.E[kc] * sp_s[i] : T(0);
+        A.u_out[fo + (long)kc * Np + i] = h0 + (A.inject ? ph : T(0));
+        part0 += (double)A.tb.Wk[(long)kc * Np + i] * (double)h0;
+        part1 += (double)A.tb.Wk[(long)(DP + kc) * Np + i] * (double)h0;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(ADt[kc * DP + 16 * mt + (lane & 15)], ph, acc[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        T v = (i < N) ? act_fn<T>(A.act, acc[mt][r] + A.tb.bv[l * DP + ch]) : T(0);
+        A.chi_out[fo + (long)ch * Np + i] = v;
+      }
+  }
+  if (A.first) {
+    part0 = wave_sum(part0);
+    part1 = wave_sum(part1);
+    if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      A.rho[2 * g] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      A.rho[2 * g + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Green's-function mixer for a batch of fields, per channel c: Y[cfg, c, :] = X[cfg, c, :] G_c^T,
+// i.e. Y_i = sum_i' g_c(i - i') X_i'. The Toeplitz operand is generated on the fly from the
+// taps staged in LDS; the field operand is staged in LDS in 64-site chunks (row stride 66
+// floats: conflict-free fragment reads). One workgroup: 64 configurations x 256 output
+// sites of one channel; each wave owns 64 (or fewer) output sites.
+template <typename T> struct ConvArgs {
+  const T* X;
+  T* Y;
+  const T* taps;  // [DP][2Np] for this mixer
+  int N, Np, C, DP;
+};
+
+constexpr int CONV_MC = 64;   // configurations per workgroup
+constexpr int CONV_KC = 64;   // input sites per LDS chunk
+constexpr int CONV_LD = 66;   // LDS row stride of the field chunk
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);   // [CONV_MC][CONV_LD]
+  T* ts = xs + CONV_MC * CONV_LD;           // [2Np]
+  using M = Mma<T>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.y;
+  const int cfg0 = blockIdx.x * CONV_MC;
+  const int Np = A.Np;
+  const int site0 = blockIdx.z * 64 * NT;                // output block of 4 waves x 16*NT sites
+  const int wsite0 = site0 + wave * 16 * NT;              // this wave's first output site
+  const T* tp = A.taps + (long)c * 2 * Np;
+  for (int q = threadIdx.x; q < 2 * Np; q += 256) ts[q] = tp[q];
+  typename M::acc acc[4][NT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[a][n] = typename M::acc{0, 0, 0, 0};
+  const long cstride = (long)A.DP * Np;
+  for (int k0 = 0; k0 < Np; k0 += CONV_KC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < CONV_MC * CONV_KC; idx += 256) {
+      int mrow = idx / CONV_KC, kk = idx % CONV_KC;
+      int cfg = cfg0 + mrow;
+      xs[mrow * CONV_LD + kk] = (cfg < A.C) ? A.X[(long)cfg * cstride + (long)c * Np + k0 + kk] : T(0);
+    }
+    __syncthreads();
+    if (wsite0 < Np) {
+#pragma unroll 2
+      for (int ks = 0; ks < CONV_KC / 4; ++ks) {
+        const int kk = 4 * ks + (lane >> 4);
+        T av[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = xs[(16 * a + (lane & 15)) * CONV_LD + kk];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          // B[k][n] = g(i - i') with i = output site, i' = input site
+          const int off = (wsite0 + 16 * n + (lane & 15)) - (k0 + kk) + Np - 1;
+          const T bv = ts[off];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) acc[a][n] = M::mma(av[a], bv, acc[a][n]);
+        }
+      }
+    }
+  }
+  if (wsite0 >= Np) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int cfg = cfg0 + 16 * a + M::row(lane, r);
+        const int i = wsite0 + 16 * n + (lane & 15);
+        if (cfg < A.C) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
+      }
+}
+
+// ---------------------------------------------------------------------------------------
+// Vertex and channel mixing, fused with the read-out. Per configuration (one workgroup):
+//   phase 1: q = M1 X (matrix cores), x = elementwise(q, ...) -> LDS [DP][Np]
+//   phase 2: y = M2 x, written out and contracted with the read-out weights.
+// Modes:
+//   FWD:  X = v, x = chi * q (q = V v cached as p0 when requested), y = h = U x;
+//         out = h (+ phi^(l+1) when injected) as the next mixer input; rho += Wk . h.
+//   TAU:  X = Wk[k] (cfg = 2b + k), x = chi0[b] * (U^T X), y = V^T x  (the adjoint
+//         D0^T of the last block applied to the read-out weights; a conv with reversed
+//         taps then gives tau = G^T D0^T Wk).
+//   DEEP: X = w = G^(l) du (full chain, per flip), x = chi0 q + [i in S_l] dchi (p0 + q),
+//         y = dh = U x: the background propagation of the perturbation plus the vertex
+//         change on the slice. rho += Wk . dh. LAST (l = L-1) also adds tau . dh and writes
+//         the slice of the next mixer's output, y_L = P_{S_L} G^(L) dh, for the tail.
+//         FIRST (l = 1) builds w = G^(1) e^(0) from the taps and the cluster instead of X.
+enum { MIX_FWD = 0, MIX_TAU = 1, MIX_DEEP = 2 };
+
+template <typename T> struct MixArgs {
+  Tables<T> tb;
+  int N, Np, l, L, w_c, periodic, inject;
+  int C;                 // configurations (flips) in this launch
+  int cfg0;              // global index of the first (DEEP: flip map offset)
+  const T* X;            // [C][DP][Np] (FWD/DEEP non-first)
+  const T* chi;          // FWD: [C][DP][Np]; TAU/DEEP: chi0 of the block [B][DP][Np] (per sample)
+  const T* p0;           // DEEP: V v0 of the block [B][DP][Np]; FWD: cache out (nullable, written)
+  T* p0_out;             // FWD cache of q
+  const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
+  T* out;                // [C][DP][Np] (nullable for DEEP LAST)
+  double* rho;           // [C][2] accumulated (FWD, DEEP)
+  // DEEP
+  CfgMap map;            // flip -> (b, m)
+  int b0;                // first sample of the chunk (caches are chunk-local)
+  const int8_t* spins;
+  const int4* geom;      // [F] (clo, ext, j0, j1)
+  const T* dchi;         // [F][L][Wmax][DP]
+  int Wmax;
+  const T* tau;          // [B][2][DP][Np] (chunk-local)
+  T* yL;                 // [F][Wmax][DP]
+  const T* tapsL;        // taps of block L [DP][2Np] (LAST)
+  const T* taps1;        // taps of block 1 [DP][2Np] (FIRST)
+};
+
+template <typename T, int DP, int MODE, bool FIRST, bool LAST>
+__global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [DP][Np]
+  __shared__ double red[2][4];
+  __shared__ int4 sg;
+  using M = Mma<T>;
+  constexpr int MT = DP / 16, KS = DP / 4;
+  const int g = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int N = A.N, Np = A.Np, l = A.l;
+  const long fo = (long)g * DP * Np;
+  int b = 0;        // sample (chunk-local) whose caches are used
+  int kk_tau = 0;
+  if (MODE == MIX_TAU) { b = g >> 1; kk_tau = g & 1; }
+  if (MODE == MIX_DEEP) b = A.map.cb[A.cfg0 + g] - A.b0;
+  const long bo = (long)b * DP * Np;
+  // table index of the block: FWD/TAU pass the 0-based block, DEEP the 1-based block l
+  const int tl = (MODE == MIX_DEEP) ? l - 1 : l;
+  const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)tl * DP * DP : A.tb.Vt + (long)tl * DP * DP;
+  const T* M2 = (MODE == MIX_TAU) ? A.tb.Vm + (long)tl * DP * DP : A.tb.Ut + (long)tl * DP * DP;
+  int lo = 0, W = 0;
+  if (MODE == MIX_DEEP) {
+    if (threadIdx.x == 0) sg = A.geom[g];
+    __syncthreads();
+    lo = sg.x - l * A.w_c;
+    W = sg.y + 2 * l * A.w_c + 1;
+  }
+  const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
+  // ---- phase 1
+  for (int nt = wave; nt < Np / 16; nt += 4) {
+    typename M::acc acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
+    const int i = nt * 16 + (lane & 15);
+#pragma unroll 4
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + (lane >> 4);
+      T bv;
+      if (MODE == MIX_DEEP && FIRST) {
+        // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
+        bv = 0;
+        if (i < N) {
+          const int8_t* sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+          const T* t1 = A.taps1 + (long)kc * 2 * Np;
+          T e = A.tb.E[kc];
+          bv = t1[i - sg.z + Np - 1] * (T)(-2 * sp[sg.z]) * e;
+          if (sg.w >= 0) bv += t1[i - sg.w + Np - 1] * (T)(-2 * sp[sg.w]) * e;
+        }
+      } else {
+        bv = X[(long)kc * Np + i];
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(M1[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        const T q = acc[mt][r];
+        T x;
+        if (MODE == MIX_FWD) {
+          x = A.chi[fo + (long)ch * Np + i] * q;
+          if (A.p0_out) A.p0_out[fo + (long)ch * Np + i] = q;
+        } else if (MODE == MIX_TAU) {
+          x = A.chi[bo + (long)ch * Np + i] * q;
+        } else {
+          x = A.chi[bo + (long)ch * Np + i] * q;
+          int sidx = i - lo;
+          if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
+          if (i < N && sidx >= 0 && sidx < W) {
+            const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
+            x += dc * (A.p0[bo + (long)ch * Np + i] + q);
+          }
+        }
+        xs[ch * Np + i] = (i < N) ? x : T(0);
+      }
+  }
+  __syncthreads();
+  // ---- phase 2
+  double part0 = 0.0, part1 = 0.0;
+  for (int nt = wave; nt < Np / 16; nt += 4) {
+    typename M::acc acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
+    const int i = nt * 16 + (lane & 15);
+#pragma unroll 4
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + (lane >> 4);
+      const T bv = xs[kc * Np + i];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(M2[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        const T y = (i < N) ? acc[mt][r] : T(0);
+        const long o = (long)ch * Np + i;
+        if (MODE == MIX_TAU) {
+          A.out[fo + o] = y;
+        } else {
+          T w0 = A.tb.Wk[o], w1 = A.tb.Wk[(long)DP * Np + o];
+          if (MODE == MIX_DEEP && LAST) {
+            w0 += A.tau[(long)(2 * b) * DP * Np + o];
+            w1 += A.tau[(long)(2 * b + 1) * DP * Np + o];
+          }
+          part0 += (double)w0 * (double)y;
+          part1 += (double)w1 * (double)y;
+          if (MODE == MIX_FWD && A.out) A.out[fo + o] = y + (A.inject ? A.phi_next[fo + o] : T(0));
+          if (MODE == MIX_DEEP && !LAST) A.out[fo + o] = y;
+        }
+      }
+    if (MODE == MIX_DEEP && LAST) {
+      // the wave owns these columns of xs: overwrite them with dh for the slice conv
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * mt + M::row(lane, r);
+          xs[ch * Np + i] = (i < N) ? acc[mt][r] : T(0);
+        }
+    }
+  }
+  if (MODE != MIX_TAU) {
+    part0 = wave_sum(part0);
+    part1 = wave_sum(part1);
+    if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
+  }
+  __syncthreads();
+  if (MODE != MIX_TAU && threadIdx.x == 0) {
+    A.rho[2 * g] += red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    A.rho[2 * g + 1] += red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+  if (MODE == MIX_DEEP && LAST) {
+    // y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i'] for the W_L slice sites
+    const int loL = sg.x - A.L * A.w_c;
+    const int WL = sg.y + 2 * A.L * A.w_c + 1;
+    for (int pair = wave; pair < WL * DP; pair += 4) {
+      const int t = pair / DP, c = pair % DP;
+      int site = loL + t;
+      if (A.periodic) { site %= N; if (site < 0) site += N; }
+      T acc = 0;
+      if (site >= 0 && site < N) {
+        const T* tl = A.tapsL + (long)c * 2 * Np + site + Np - 1;
+        for (int ip = lane; ip < N; ip += 64) acc += tl[-ip] * xs[c * Np + ip];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) A.yL[((long)g * A.Wmax + t) * DP + c] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-flip slice recompute of the phi stream and vertices (ABACUS, Sec. III: the vertex
+// changes only on S_l = sites within l*w_c of the cluster). One wave per flip; lanes
+// own output channels. Writes dchi^(l) = chi'^(l) - chi0^(l) on S_l for l = 1..L and the
+// cluster geometry (clo, ext, j0, j1): S_l covers sites clo - l*w_c .. clo + ext + l*w_c.
+template <typename T> struct SliceArgs {
+  Tables<T> tb;
+  int N, Np, L, w_c, periodic, act;
+  int F, f0, b0, Bc;      // flips [f0, f0+F), chunk's first sample b0, samples in chunk
+  CfgMap map;
+  const int8_t* spins;
+  const T* a0;            // [L][Bc][DP][Np]
+  const T* chi0;          // [L][Bc][DP][Np]
+  T* dchi;                // [F][L][Wmax][DP]
+  int4* geom;             // [F]
+  int Wmax;
+  int* err;               // set to 1 for a cluster the slice recurrence does not cover
+};
+
+template <typename T, int DP>
+__global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* phs = reinterpret_cast<T*>(smem_raw);  // phi' on the current slice [Wmax][DP]
+  T* as = phs + A.Wmax * DP;                // a' on the previous slice   [Wmax][DP]
+  const int f = blockIdx.x;
+  const int c = threadIdx.x;  // channel; lanes c >= DP only join the barriers
+  const bool on = c < DP;
+  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
+  const int b = A.map.cb[A.f0 + f], m = A.map.cm[A.f0 + f];
+  const int bl = b - A.b0;
+  const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
+  const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
+  int clo = j0, ext = 0;
+  if (j1 >= 0) {
+    if (A.periodic) {
+      int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
+      if (d1 <= 2) { clo = j0; ext = d1; }
+      else if (d2 <= 2) { clo = j1; ext = d2; }
+      else ext = -1;
+    } else {
+      clo = j0 < j1 ? j0 : j1;
+      ext = j0 < j1 ? j1 - j0 : j0 - j1;
+      if (ext > 2) ext = -1;
+    }
+  }
+  if (ext < 0 || (A.periodic && ext + 2 * L * wc + 1 > N)) {
+    if (c == 0) atomicOr(A.err, 1);
+    ext = 0;
+  }
+  if (c == 0) A.geom[f] = make_int4(clo, ext, j0, j1);
+  if (!on) {  // idle lanes still take part in every barrier below
+    for (int l = 1; l <= L; ++l) { __syncthreads(); __syncthreads(); __syncthreads(); }
+    return;
+  }
+  const int8_t* sp = A.spins + (long)b * N;
+  auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
+  auto inside = [&](int i) { return A.periodic || (i >= 0 && i < N); };
+  for (int l = 1; l <= L; ++l) {
+    const int lp = l - 1;  // layer index into tables
+    const int loP = clo - lp * wc, WP = ext + 2 * lp * wc + 1;  // S_{l-1}
+    const int lo = clo - l * wc, Wl = ext + 2 * l * wc + 1;     // S_l
+    // a' on S_{l-1}
+    for (int t = 0; t < WP; ++t) {
+      const int site = wrap(loP + t);
+      T v = 0;
+      if (inside(loP + t)) {
+        if (l == 1) {
+          T s = (T)sp[site];
+          if (site == j0 || site == j1) s = -s;
+          v = s * A.tb.wE1[c] + A.tb.wv[c];
+        } else {
+          const T* Wt = A.tb.WDt + (long)lp * DP * DP;
+          T acc = A.tb.wv[lp * DP + c];
+          for (int k = 0; k < DP; ++k) acc += Wt[k * DP + c] * phs[t * DP + k];
+          v = acc;
+        }
+      }
+      as[t * DP + c] = v;
+    }
+    __syncthreads();
+    // phi' and chi' on S_l
+    const T* Kc = A.tb.Kc + (long)lp * (2 * wc + 1) * DP;
+    const T* a0 = A.a0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
+    for (int t = 0; t < Wl; ++t) {
+      const int ii = lo + t;
+      T s = A.tb.kv[lp * DP + c];
+      for (int r = -wc; r <= wc; ++r) {
+        const int tp = t + r - wc;  // position in S_{l-1}
+        T av;
+        if (tp >= 0 && tp < WP) av = as[tp * DP + c];
+        else {
+          const int jj = ii + r;
+          av = inside(jj) ? a0[wrap(jj)] : T(0);
+        }
+        s += Kc[(r + wc) * DP + c] * av;
+      }
+      phs[t * DP + c] = inside(ii) ? act_fn<T>(A.act, s) : T(0);  // phs no longer read above
+    }
+    __syncthreads();
+    const T* Adt = A.tb.ADt + (long)lp * DP * DP;
+    const T* chi0 = A.chi0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
+    T* out = A.dchi + ((long)f * L + lp) * A.Wmax * DP;
+    for (int t = 0; t < Wl; ++t) {
+      const int ii = lo + t;
+      T acc = A.tb.bv[lp * DP + c];
+      for (int k = 0; k < DP; ++k) acc += Adt[k * DP + c] * phs[t * DP + k];
+      T dc = inside(ii) ? act_fn<T>(A.act, acc) - chi0[wrap(ii)] : T(0);
+      out[t * DP + c] = dc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// ABACUS tail, one wave per flip: vertex change of the last block on its slice,
+// e^(L) = U (dchi^(L) * (p0^(L) + V y_L)); e^(0) = -2 s_j E on the cluster;
+// dOmega = rho_f + Wk . (e^(0) + e^(L)) [+ tau . e^(0) and y_1 = G^(1) e^(0) when L = 1];
+// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
+template <typename T> struct TailArgs {
+  Tables<T> tb;
+  int N, Np, L, w_c, periodic;
+  int F, f0, b0;
+  CfgMap map;
+  const int8_t* spins;
+  const int4* geom;
+  const T* dchi;        // [F][L][Wmax][DP]
+  const T* yL;          // [F][Wmax][DP] (L >= 2)
+  const T* p0L;         // [Bc][DP][Np] p0 of block L
+  const T* tau;         // [Bc][2][DP][Np]
+  const T* taps1;       // block-1 taps (L == 1)
+  const double* rho;    // [F][2] (L >= 2)
+  const double* Om0;    // [B][2] global
+  double* logratio;     // [B][M_max] global
+  int Wmax;
+};
+
+template <typename T, int DP>
+__global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ys = reinterpret_cast<T*>(smem_raw);  // [DP]
+  T* xs = ys + DP;                          // [DP]
+  const int f = blockIdx.x, c = threadIdx.x;
+  const bool on = c < DP;                   // lanes c >= DP contribute zeros
+  const int N = A.N, Np = A.Np, L = A.L, wc = A.w_c;
+  const int b = A.map.cb[A.f0 + f], m = A.map.cm[A.f0 + f];
+  const int bl = b - A.b0;
+  const int4 gm = A.geom[f];
+  const int8_t* sp = A.spins + (long)b * N;
+  auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
+  auto inside = [&](int i) { return A.periodic || (i >= 0 && i < N); };
+  const long DPNp = (long)DP * Np;
+  double o0 = 0.0, o1 = 0.0;
+  // e^(0) read-out (and tau . e^(0) when the cluster feeds the last block directly)
+  for (int q = 0; q < 2 && on; ++q) {
+    const int j = q == 0 ? gm.z : gm.w;
+    if (j < 0) continue;
+    const T e0 = (T)(-2 * sp[j]) * A.tb.E[c];
+    T w0 = A.tb.Wk[(long)c * Np + j], w1 = A.tb.Wk[DPNp + (long)c * Np + j];
+    if (L == 1) {
+      w0 += A.tau[(2L * bl) * DPNp + (long)c * Np + j];
+      w1 += A.tau[(2L * bl + 1) * DPNp + (long)c * Np + j];
+    }
+    o0 += (double)w0 * (double)e0;
+    o1 += (double)w1 * (double)e0;
+  }
+  const int lo = gm.x - L * wc, WL = gm.y + 2 * L * wc + 1;
+  const T* Vt = A.tb.Vt + (long)(L - 1) * DP * DP;
+  const T* Ut = A.tb.Ut + (long)(L - 1) * DP * DP;
+  const T* dchi = A.dchi + ((long)f * L + (L - 1)) * A.Wmax * DP;
+  for (int t = 0; t < WL; ++t) {
+    const int ii = lo + t;
+    if (!inside(ii)) continue;  // uniform across the wave
+    const int site = wrap(ii);
+    if (on) {
+      T y;
+      if (L == 1) {
+        const T* t1 = A.taps1 + (long)c * 2 * Np;
+        y = t1[site - gm.z + Np - 1] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
+        if (gm.w >= 0) y += t1[site - gm.w + Np - 1] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
+      } else {
+        y = A.yL[((long)f * A.Wmax + t) * DP + c];
+      }
+      ys[c] = y;
+    }
+    __syncthreads();
+    if (on) {
+      T q = 0;
+      for (int k = 0; k < DP; ++k) q += Vt[k * DP + c] * ys[k];
+      xs[c] = dchi[t * DP + c] * (A.p0L[(long)bl * DPNp + (long)c * Np + site] + q);
+    }
+    __syncthreads();
+    if (on) {
+      T e = 0;
+      for (int k = 0; k < DP; ++k) e += Ut[k * DP + c] * xs[k];
+      o0 += (double)A.tb.Wk[(long)c * Np + site] * (double)e;
+      o1 += (double)A.tb.Wk[DPNp + (long)c * Np + site] * (double)e;
+    }
+    __syncthreads();
+  }
+  o0 = wave_sum(o0);
+  o1 = wave_sum(o1);
+  if (c == 0) {
+    double d0 = o0, d1 = o1;
+    if (L >= 2) { d0 += A.rho[2 * f]; d1 += A.rho[2 * f + 1]; }
+    const double a0 = A.Om0[2 * b], a1 = A.Om0[2 * b + 1];
+    A.logratio[(long)b * A.map.M_max + m] = lcd_d(a0, d0) + lcd_d(a1, d1);
+  }
+}
+
+}  // namespace dn
