@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the DysonNet local estimator on one MI355X: E_loc samples per second with
+log-ratios by ABACUS, next to full re-evaluation on the same GPU.
+
+A step is one pass of the whole hot path over one batch of synthetic samples already
+resident in HBM: connected elements of H, log psi, every log-ratio, E_loc. Parameter-only
+work (S4 taps and tables) happens once per parameter update and is reported separately.
+The default workload is the long-range Ising chain with N=256, four blocks, d=64, state 32,
+2048 samples, FP32 (alpha=2, h=0.5). One JSON line is printed.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # dense MFMA TFLOP/s of one MI355X
+HBM_PEAK = 8000.0                      # GB/s
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_11189_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tfim_n256_l4_d64")
+    ap.add_argument("--scale", default="baseline", choices=["baseline", "stress"])
+    ap.add_argument("--paths", default="abacus,full")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the estimator shards by "
+              "sample; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import dn_inputs as di
+    from paper_2603_11189_amd import _lib as L
+
+    w = di.WORKLOADS[args.workload]
+    shape, ham = w.model, w.ham
+    prec = w.prec if w.prec != "bf16" else "fp32"
+    B = w.B
+    M_max = shape.N if ham.kind == "lrtfim" else 2 * shape.N
+    theta = torch.tensor(w.params(args.scale))
+    spins_np = w.spin_batch()
+    dev = torch.device("cuda")
+    torch.cuda.init()
+    L.lib()
+    model = L.Model(shape, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model.set_params(theta)
+    torch.cuda.synchronize()
+    set_params_ms = (time.perf_counter() - t0) * 1e3
+    spins = torch.tensor(spins_np, device=dev)
+    bufs = {p: (torch.empty(B, dtype=torch.float64, device=dev),
+                torch.empty((B, M_max), dtype=torch.float64, device=dev),
+                torch.empty(B, dtype=torch.float64, device=dev)) for p in ("abacus", "full")}
+    results = {}
+    for path in args.paths.split(","):
+        log(f"[bench] {args.workload} path={path} warmup={args.warmup}")
+        for _ in range(args.warmup):
+            model.eloc(ham, spins, M_max, path=path, out=bufs[path])
+        torch.cuda.synchronize()
+        if not args.no_profile:
+            model.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            model.eloc(ham, spins, M_max, path=path, out=bufs[path])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = model.profile_read() if not args.no_profile else {}
+        model.profile_enable(False)
+        results[path] = {"sec": el, "prof": prof}
+        log(f"[bench] {path}: {el / args.steps * 1e3:.2f} ms/step, {B * args.steps / el:.1f} samples/s")
+
+    main_path = "abacus" if "abacus" in results else list(results)[0]
+    el = results[main_path]["sec"]
+    value = B * args.steps / el
+    out = {
+        "metric": "E_loc samples/sec, ABACUS vs full re-eval, N=256, at stated rel err vs FP64",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": shape.N, "L": shape.L, "d": shape.d, "s": shape.s,
+                   "B": B, "hamiltonian": f"{ham.kind} {ham.bc} J={ham.J} alpha={ham.alpha} h={ham.h}"
+                   if ham.kind == "lrtfim" else f"j1j2 {ham.bc} J1={ham.J1} J2={ham.J2}",
+                   "params": f"N(0,0.1^2) seed {w.param_seed}" if args.scale == "baseline" else "stress draw",
+                   "path": main_path},
+        "set_params_ms": set_params_ms,
+    }
+    if "full" in results and main_path != "full":
+        fv = B * args.steps / results["full"]["sec"]
+        out["full_reeval"] = {"value": fv, "ms_per_step": results["full"]["sec"] / args.steps * 1e3}
+        out["speedup_vs_full"] = value / fv
+
+    # roofline of the dominant kernel of the timed path, from the library's event profile
+    prof = results[main_path]["prof"]
+    if prof:
+        per = {}
+        for kind, (ms, n, fl, by) in prof.items():
+            if n:
+                per[kind] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+                             "tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
+                             "gbps": by / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        out["per_kernel"] = per
+        dom = max(prof, key=lambda k: prof[k][0])
+        ms, n, fl, by = prof[dom]
+        achieved = fl / (ms * 1e-3) / 1e12
+        peak = PEAK["fp32" if prec == "fp32" else "fp64"]
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tpath):
+            with open(tpath) as f:
+                tj = json.load(f)
+            ent = tj.get(args.workload, {}).get(dom)
+            if ent and tj.get("source_hash") == source_hash():
+                traffic = ent["bytes_per_launch"]
+        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
+                           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                           "avg_launch_ms": ms / n, "algorithmic_flops_per_launch": fl / n,
+                           "algorithmic_bytes_per_launch": by / n}
+
+    # CPU baseline (the oracle, untuned) on a bounded sample, and the error of both GPU paths
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle.model import ModelDesc
+        desc = ModelDesc.of(shape)
+        gpu = {p: tuple(t.cpu() for t in bufs[p]) for p in results}
+        budget = args.cpu_seconds
+        t0 = time.perf_counter()
+        done, errs = [], {p: {"eloc": 0.0, "lr": 0.0, "logpsi": 0.0} for p in results}
+        ref_mag = {"eloc": 0.0, "lr": 0.0, "logpsi": 0.0}
+        while time.perf_counter() - t0 < budget and len(done) < B:
+            b = len(done) * max(1, B // 64)
+            ref = O.eloc_plain(desc, ham, theta, spins_np[b:b + 1], M_max)
+            done.append(b)
+            for key, idx in (("logpsi", 0), ("lr", 1), ("eloc", 2)):
+                r = {"logpsi": ref["logpsi"], "lr": ref["logratio"], "eloc": ref["eloc"]}[key]
+                ref_mag[key] = max(ref_mag[key], r.abs().max().item())
+                for p in results:
+                    g = gpu[p][idx][b:b + 1]
+                    errs[p][key] = max(errs[p][key], (g - r).abs().max().item())
+        cpu_sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(done) / cpu_sec, "unit": "samples/s",
+                               "cores": torch.get_num_threads(), "kind": "oracle",
+                               "sample": f"{len(done)} of the {B} samples (every {max(1, B // 64)}th), "
+                                         f"float64 oracle, log-ratios by full re-evaluation, {cpu_sec:.1f} s"}
+        out["err_vs_fp64_oracle"] = {
+            p: {k: (errs[p][k] / ref_mag[k] if ref_mag[k] > 0 else 0.0) for k in errs[p]} for p in results}
+        out["err_vs_fp64_oracle"]["measure"] = "max|x - x*| / max|x*| over the CPU sample"
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,7 +55,7 @@ typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_p
 typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
 
 /* Network hyper-parameters (Sec. II; App. "Details on the implementation ...").
- * N chain length; L blocks; d channels (d <= 64); s S4 state size (s <= 64);
+ * N chain length; L blocks; d channels (d <= 64); s S4 state size (s <= 32);
  * d_out log-cosh read-out units (must be 2); w_c half-width of the phi-stream CNN
  * (0..3); bc network boundary condition (dn_bc); act local nonlinearity g (dn_act);
  * inject_phi 1 adds phi^(l) to the h stream before each mixer (Fig. 1c form);
@@ -94,7 +94,7 @@ typedef struct dn_model dn_model; /* opaque */
 int64_t dn_param_count(const dn_model_desc* desc);
 
 /* Create a model (no parameters yet). Validates the shape; DN_EUNSUPPORTED for shapes
- * the kernels do not cover (d > 64, s > 64, d_out != 2, N > 512, or a float64 field of
+ * the kernels do not cover (d > 64, s > 32, d_out != 2, N > 512, or a float64 field of
  * one configuration larger than the on-chip tile). *out receives the handle. */
 dn_status dn_model_create(const dn_model_desc* desc, dn_model** out);
 
@@ -113,7 +113,8 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int params_on_d
  * offset r = i - i' stored at r + N - 1 (periodic: the aliased kernel g_(r mod N)). */
 dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream);
 
-/* log psi(s) for B configurations (Eq. (wavefunc) with f = log cosh). */
+/* log psi(s) for B configurations (Eq. (wavefunc) with f = log cosh). Synchronises the
+ * stream before returning. */
 dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
 
 /* Connected configurations, matrix elements and diagonal energies of H for B samples.
@@ -126,7 +127,10 @@ dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, i
 /* log psi(s'_m)/psi(s) for every listed element, by DN_PATH_ABACUS (background caches,
  * output links and the slice recurrence; clusters must be one site or two sites at
  * distance <= 2, else DN_EUNSUPPORTED) or DN_PATH_FULL (each s' evaluated from scratch).
- * logpsi (nullable) receives log psi(s); logratio [B, M_max] gets 0 beyond n_conn. */
+ * logpsi (nullable) receives log psi(s); logratio [B, M_max] gets 0 beyond n_conn.
+ * n_conn and sites are validated on the device (DN_EINVAL for n_conn outside [0, M_max],
+ * a site outside [0, N) or a pair repeating a site); the per-sample work list comes back to
+ * the host, so the call synchronises the stream once before its main launches. */
 dn_status dn_logratio(dn_model* m, int32_t path, const int8_t* spins, int32_t B,
                       const int32_t* sites, const int32_t* n_conn, int32_t M_max,
                       double* logpsi, double* logratio, void* stream);
@@ -142,6 +146,33 @@ dn_status dn_local_energy(const double* hdiag, const double* helem, const int32_
 dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_t* spins,
                   int32_t B, int32_t M_max, double* logpsi, double* logratio, double* eloc,
                   void* stream);
+
+/* Kernel classes of the per-launch profile. */
+typedef enum {
+  DN_K_S4GEN = 0,    /* S4 taps (float64) */
+  DN_K_PREP = 1,     /* parameter tables */
+  DN_K_PHI = 2,      /* phi stream + vertex of one block */
+  DN_K_CONV = 3,     /* Green's-function mixer (Toeplitz product on the matrix cores) */
+  DN_K_MIX_FWD = 4,  /* vertex + channel mixing + read-out, forward */
+  DN_K_MIX_TAU = 5,  /* adjoint of the last block's vertex (ABACUS output link) */
+  DN_K_MIX_DEEP = 6, /* background propagation of the flips' perturbations (ABACUS) */
+  DN_K_SLICE = 7,    /* slice recompute of phi / vertices (ABACUS) */
+  DN_K_TAIL = 8,     /* last block's slice + float64 log-ratio (ABACUS) */
+  DN_K_GEN = 9,      /* Hamiltonian connected elements */
+  DN_K_ELOC = 10,    /* local energy */
+  DN_K_OTHER = 11,   /* planning, fills, read-out finalisation */
+  DN_K_COUNT = 12
+} dn_kernel_kind;
+
+/* Per-launch profile of a model's kernels. While enabled, every launch the model makes is
+ * bracketed by HIP events on its own stream, and its algorithmic work is recorded: flops
+ * of the operation as defined (a Toeplitz mixer of n sites counts 2 n^2 per channel, a
+ * d x d channel mix 2 d^2 per site) and bytes of its unavoidable HBM traffic (fields read
+ * and written once). dn_profile_enable(m, 1) clears the counters; (m, 0) stops recording.
+ * dn_profile_read synchronises the device and returns the totals of one kernel class. */
+dn_status dn_profile_enable(dn_model* m, int enable);
+dn_status dn_profile_read(dn_model* m, int32_t kind, double* total_ms, int64_t* launches,
+                          double* flops, double* bytes);
 
 /* Thread-local text of the last error (never NULL). */
 const char* dn_last_error(void);

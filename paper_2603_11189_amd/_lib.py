@@ -24,7 +24,9 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
-           "dn_eloc", "dn_last_error", "dn_model_destroy")
+           "dn_eloc", "dn_profile_enable", "dn_profile_read", "dn_last_error", "dn_model_destroy")
+KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
+                "eloc", "other")
 
 
 class ModelDesc(ctypes.Structure):
@@ -66,11 +68,15 @@ def lib():
         L.dn_logratio.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp]
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
+        L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.dn_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.dn_last_error.restype = ctypes.c_char_p
         L.dn_model_destroy.argtypes = [vp]
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
-                   "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc"):
+                   "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
+                   "dn_profile_enable", "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -163,6 +169,21 @@ class Model:
         _check(lib().dn_eloc(self.handle, PATH[path], ctypes.byref(hd), _ptr(spins), B, M_max, _ptr(lp), _ptr(lr),
                              _ptr(el), _stream()))
         return lp, lr, el
+
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().dn_profile_enable(self.handle, int(on)))
+
+    def profile_read(self) -> dict:
+        """{kind: (total_ms, launches, flops, bytes)} for every kernel class."""
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            fl, by = ctypes.c_double(), ctypes.c_double()
+            _check(lib().dn_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                         ctypes.byref(by)))
+            out[name] = (ms.value, n.value, fl.value, by.value)
+        return out
 
 
 def connected(ham, spins: torch.Tensor, M_max: int):

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dysonnet.h"
@@ -66,6 +67,24 @@ template <typename T> struct TableBufs {
   T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk;
 };
 
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> free_ev;
+  std::vector<ProfRec> pending;
+  double ms[DN_K_COUNT] = {}, fl[DN_K_COUNT] = {}, by[DN_K_COUNT] = {};
+  long n[DN_K_COUNT] = {};
+  ~Prof() {
+    for (auto e : free_ev) (void)hipEventDestroy(e);
+    for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  }
+};
+
 struct Workspace {
   std::map<std::string, std::pair<void*, size_t>> slots;
   size_t limit = 0, used = 0;
@@ -89,6 +108,7 @@ struct dn_model {
   TableBufs<double> t64;
   TableBufs<float> t32;
   Workspace ws;
+  Prof prof;
   std::vector<void*> owned;
   ~dn_model() {
     for (void* p : owned) (void)hipFree(p);
@@ -120,6 +140,48 @@ dn_status ws_get(dn_model* m, const char* name, size_t bytes, void** out) {
   return DN_OK;
 }
 
+hipEvent_t prof_event(dn_model* m) {
+  hipEvent_t e = nullptr;
+  if (!m->prof.free_ev.empty()) { e = m->prof.free_ev.back(); m->prof.free_ev.pop_back(); }
+  else (void)hipEventCreate(&e);
+  return e;
+}
+
+// Brackets one launch with events on its stream while profiling is on.
+struct PScope {
+  dn_model* m;
+  int kind;
+  hipStream_t st;
+  double fl, by;
+  hipEvent_t a = nullptr;
+  PScope(dn_model* m_, int k, hipStream_t s, double f, double b) : m(m_), kind(k), st(s), fl(f), by(b) {
+    if (m && m->prof.on) { a = prof_event(m); (void)hipEventRecord(a, st); }
+  }
+  ~PScope() {
+    if (a) {
+      hipEvent_t b = prof_event(m);
+      (void)hipEventRecord(b, st);
+      m->prof.pending.push_back({kind, a, b, fl, by});
+    }
+  }
+};
+
+dn_status prof_harvest(dn_model* m) {
+  HIPCHK(hipDeviceSynchronize());
+  for (auto& r : m->prof.pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    m->prof.ms[r.kind] += ms;
+    m->prof.fl[r.kind] += r.flops;
+    m->prof.by[r.kind] += r.bytes;
+    m->prof.n[r.kind] += 1;
+    m->prof.free_ev.push_back(r.a);
+    m->prof.free_ev.push_back(r.b);
+  }
+  m->prof.pending.clear();
+  return DN_OK;
+}
+
 template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m) {
   const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
   auto get = [&](T** p, long n) -> bool {
@@ -133,7 +195,7 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
             get(&tb.ADt, L * DP * DP) && get(&tb.Ut, L * DP * DP) && get(&tb.Vt, L * DP * DP) &&
             get(&tb.Um, L * DP * DP) && get(&tb.Vm, L * DP * DP) && get(&tb.wv, L * DP) &&
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
-            get(&tb.taps, L * DP * 2 * Np) && get(&tb.tapsR, DP * 2 * Np) && get(&tb.Wk, 2 * DP * Np);
+            get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, DP * tap_stride(Np)) && get(&tb.Wk, 2 * DP * Np);
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
                     tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk};
@@ -142,7 +204,7 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
 
 long table_elems(const dn_model& m) {
   const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
-  return 3 * DP + 6 * L * DP * DP + 3 * L * DP + L * Wc * DP + L * DP * 2 * Np + DP * 2 * Np + 2 * DP * Np;
+  return 3 * DP + 6 * L * DP * DP + 3 * L * DP + L * Wc * DP + (L + 1) * DP * tap_stride(Np) + 2 * DP * Np;
 }
 
 // Copy double tables into float tables (same member order).
@@ -155,7 +217,7 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
       {a.ADt, b.ADt, L * DP * DP}, {a.Ut, b.Ut, L * DP * DP}, {a.Vt, b.Vt, L * DP * DP},
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
-      {a.taps, b.taps, L * DP * 2 * Np}, {a.tapsR, b.tapsR, DP * 2 * Np}, {a.Wk, b.Wk, 2 * DP * Np}};
+      {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
     convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);
@@ -181,6 +243,8 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   if (C <= 0) return DN_OK;
   const int Np = m->Np;
   ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP};
+  const double Nr = m->desc.N, dr = m->desc.d;
+  PScope ps(m, DN_K_CONV, st, 2.0 * C * Nr * Nr * dr, 2.0 * C * Nr * dr * sizeof(T));
   const size_t lds = (CONV_MC * CONV_LD + 2 * Np) * sizeof(T);
   const int nt = Np >= 256 ? 4 : Np / 64;  // 16-site tiles per wave
   dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
@@ -194,23 +258,69 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   return DN_OK;
 }
 
+template <typename T, int DP, int NT> void phi_go(const PhiArgs<T>& a, int C, size_t lds, hipStream_t st) {
+  allow_lds(phi_kernel<T, DP, NT>, lds);
+  phi_kernel<T, DP, NT><<<C, 256, lds, st>>>(a);
+}
+
 template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>& a, int C, hipStream_t st) {
   if (C <= 0) return DN_OK;
-  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c) + m->Np) * sizeof(T);
+  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c + 1) + m->Np) * sizeof(T);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "phi stream tile exceeds LDS");
-  allow_lds(phi_kernel<T, DP>, lds);
-  phi_kernel<T, DP><<<C, 256, lds, st>>>(a);
+  const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T);
+  const double nfield = (a.first ? 0 : 1) + (a.phi_out ? 1 : 0) + 1 + (a.a_out ? 1 : 0) + (a.first ? 1 : 0);
+  PScope ps(m, DN_K_PHI, st, (a.first ? 2.0 : 4.0) * C * Nr * dr * dr, nfield * C * Nr * dr * e);
+  if constexpr (std::is_same<T, double>::value) {
+    phi_go<T, DP, 1>(a, C, lds, st);
+  } else {
+    switch (tiles_per_wave(m->Np)) {
+      case 1: phi_go<T, DP, 1>(a, C, lds, st); break;
+      case 2: phi_go<T, DP, 2>(a, C, lds, st); break;
+      case 3: phi_go<T, DP, 3>(a, C, lds, st); break;
+      default: phi_go<T, DP, 4>(a, C, lds, st); break;
+    }
+  }
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
 
+template <typename T, int DP, int NT, int MODE, bool FIRST, bool LAST>
+void mix_go(const MixArgs<T>& a, int C, size_t lds, hipStream_t st) {
+  allow_lds(mix_kernel<T, DP, NT, MODE, FIRST, LAST>, lds);
+  mix_kernel<T, DP, NT, MODE, FIRST, LAST><<<C, 256, lds, st>>>(a);
+}
+
 template <typename T, int DP, int MODE, bool FIRST, bool LAST>
-dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
+dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, int Bc = 0) {
   if (C <= 0) return DN_OK;
-  const size_t lds = (size_t)DP * m->Np * sizeof(T);
+  const size_t lds = (size_t)DP * (m->Np + 17) * sizeof(T);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "mixing tile exceeds LDS");
-  allow_lds(mix_kernel<T, DP, MODE, FIRST, LAST>, lds);
-  mix_kernel<T, DP, MODE, FIRST, LAST><<<C, 256, lds, st>>>(a);
+  const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T), fld = Nr * dr * e;
+  double fl = 4.0 * C * Nr * dr * dr, by;
+  int kind;
+  if (MODE == MIX_FWD) {
+    kind = DN_K_MIX_FWD;
+    by = C * fld * (2 + (a.out ? 1 : 0) + (a.p0_out ? 1 : 0) + (a.inject ? 1 : 0));
+  } else if (MODE == MIX_TAU) {
+    kind = DN_K_MIX_TAU;
+    by = C * fld + (C / 2) * fld;
+  } else {
+    kind = DN_K_MIX_DEEP;
+    const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
+    if (LAST) fl += 2.0 * C * WL * Nr * dr;
+    by = C * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
+  }
+  PScope ps(m, kind, st, fl, by);
+  if constexpr (std::is_same<T, double>::value) {
+    mix_go<T, DP, 1, MODE, FIRST, LAST>(a, C, lds, st);
+  } else {
+    switch (tiles_per_wave(m->Np)) {
+      case 1: mix_go<T, DP, 1, MODE, FIRST, LAST>(a, C, lds, st); break;
+      case 2: mix_go<T, DP, 2, MODE, FIRST, LAST>(a, C, lds, st); break;
+      case 3: mix_go<T, DP, 3, MODE, FIRST, LAST>(a, C, lds, st); break;
+      default: mix_go<T, DP, 4, MODE, FIRST, LAST>(a, C, lds, st); break;
+    }
+  }
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -249,7 +359,7 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
   };
   STCHK(phi_pass(0));
   for (int l = 0; l < L; ++l) {
-    STCHK(launch_conv<T>(m, u, v, tb.taps + (long)l * DP * 2 * Np, C, st));
+    STCHK(launch_conv<T>(m, u, v, tb.taps + (long)l * DP * tap_stride(Np), C, st));
     if (l + 1 < L) STCHK(phi_pass(l + 1));
     MixArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = d.w_c;
@@ -319,6 +429,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
   if (d.inject_phi) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 is not implemented on the GPU");
+  if (2 + 2 * L * wc + 1 > SLICE_WIN) return fail(DN_EUNSUPPORTED, "ABACUS slice wider than 16 sites (needs L * w_c <= 6)");
   int32_t *offs, *cb, *cm;
   std::vector<int32_t> h_offs;
   STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
@@ -360,7 +471,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       MixArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
       a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bc; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
-      STCHK((launch_mix<T, DP, MIX_TAU, false, false>(m, a, 2 * Bc, st)));
+      STCHK((launch_mix<T, DP, MIX_TAU, false, false>(m, a, 2 * Bc, st, Bc)));
       STCHK(launch_conv<T>(m, tz, tau, tb.tapsR, 2 * Bc, st));
     }
     if (F == 0) continue;
@@ -379,6 +490,9 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       a.act = d.act; a.F = F; a.f0 = f0; a.b0 = b0; a.Bc = Bc; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
       const size_t lds = 2 * (size_t)Wmax * DP * sizeof(T);
+      double fl = 0.0;
+      for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
+      PScope ps(m, DN_K_SLICE, st, fl * F, (double)F * L * Wmax * d.d * sizeof(T));
       slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
       HIPCHK(hipGetLastError());
     }
@@ -395,16 +509,16 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau; a.yL = yL;
-        a.tapsL = tb.taps + (long)(L - 1) * DP * 2 * Np; a.taps1 = tb.taps;
+        a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
         const bool first = (l == 1), last = (l == L - 1);
-        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * 2 * Np, F, st));
+        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st));
         // l-1 is the 0-based index of block l in the tables
         a.l = l;
         dn_status s;
-        if (first && last) s = launch_mix<T, DP, MIX_DEEP, true, true>(m, a, F, st);
-        else if (first) s = launch_mix<T, DP, MIX_DEEP, true, false>(m, a, F, st);
-        else if (last) s = launch_mix<T, DP, MIX_DEEP, false, true>(m, a, F, st);
-        else s = launch_mix<T, DP, MIX_DEEP, false, false>(m, a, F, st);
+        if (first && last) s = launch_mix<T, DP, MIX_DEEP, true, true>(m, a, F, st, Bc);
+        else if (first) s = launch_mix<T, DP, MIX_DEEP, true, false>(m, a, F, st, Bc);
+        else if (last) s = launch_mix<T, DP, MIX_DEEP, false, true>(m, a, F, st, Bc);
+        else s = launch_mix<T, DP, MIX_DEEP, false, false>(m, a, F, st, Bc);
         STCHK(s);
       }
     }
@@ -414,6 +528,8 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       a.F = F; a.f0 = f0; a.b0 = b0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
       a.yL = yL; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
       a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax;
+      const int WL = 2 * L * wc + 1;
+      PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d, (double)F * (WL * 2 + 1) * d.d * sizeof(T));
       tail_kernel<T, DP><<<F, 64, 2 * DP * sizeof(T), st>>>(a);
       HIPCHK(hipGetLastError());
     }
@@ -554,17 +670,25 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   HIPCHK(hipMemcpyAsync(m->params, params, m->lay.P * sizeof(double),
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   const size_t lds = 2 * (size_t)(d.N + 1) * sizeof(double);
-  s4_taps_kernel<<<(d.L + 1) * d.d, S4_THREADS, lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s,
-                                                           d.bc == DN_BC_PERIODIC, m->taps64);
+  {
+    // N state-matrix products of s x s complex entries (8 real flops per complex MAC)
+    PScope ps(m, DN_K_S4GEN, st, 8.0 * (d.L + 1) * d.d * (double)d.N * d.s * d.s,
+              (d.L + 1.0) * d.d * (2.0 * d.N - 1) * 8);
+    s4_taps_kernel<<<(d.L + 1) * d.d, S4_THREADS, lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s,
+                                                             d.bc == DN_BC_PERIODIC, m->taps64);
+  }
   HIPCHK(hipGetLastError());
   PrepArgs a{};
   a.params = m->params; a.taps64 = m->taps64; a.N = d.N; a.Np = m->Np; a.L = d.L; a.d = d.d; a.DP = m->DP;
-  a.s = d.s; a.w_c = d.w_c; a.d_out = d.d_out; a.off_layers = m->lay.off_layers; a.off_A = m->lay.off_A;
+  a.s = d.s; a.w_c = d.w_c; a.d_out = d.d_out; a.periodic = d.bc == DN_BC_PERIODIC; a.off_layers = m->lay.off_layers; a.off_A = m->lay.off_A;
   TableBufs<double>& t = m->t64;
   a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
   a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;
   a.tapsR = t.tapsR; a.omega = m->omega; a.Wk = t.Wk; a.A = m->A64;
-  prep_kernel<<<256, 256, 0, st>>>(a);
+  {
+    PScope ps(m, DN_K_PREP, st, 0.0, (double)table_elems(*m) * 8);
+    prep_kernel<<<256, 256, 0, st>>>(a);
+  }
   HIPCHK(hipGetLastError());
   if (d.prec != DN_PREC_FP64) STCHK(convert_tables(m, st));
   void* pbad;
@@ -668,11 +792,42 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
     STCHK(ws_get(m, "el_lr", (size_t)B * M_max * 8, &pl));
     logratio = (double*)pl;
   }
-  STCHK(dn_connected(ham, spins, B, m->desc.N, M_max, (int32_t*)ps, (double*)ph, (int32_t*)pn, (double*)pd, stream));
+  {
+    const double N = m->desc.N;
+    PScope g(m, DN_K_GEN, st, ham->kind == DN_H_LRTFIM ? (double)B * N * N : (double)B * 8 * N,
+             (double)B * (N + M_max * 16.0 + 12));
+    STCHK(dn_connected(ham, spins, B, m->desc.N, M_max, (int32_t*)ps, (double*)ph, (int32_t*)pn, (double*)pd, stream));
+  }
   STCHK(dn_logratio(m, path, spins, B, (int32_t*)ps, (int32_t*)pn, M_max, logpsi, logratio, stream));
+  PScope e(m, DN_K_ELOC, st, 3.0 * B * M_max, (double)B * M_max * 16.0 + B * 20.0);
   return dn_local_energy((double*)pd, (double*)ph, (int32_t*)pn, logratio, B, M_max, eloc, stream);
 }
 
-void dn_model_destroy(dn_model* m) { delete m; }
+dn_status dn_profile_enable(dn_model* m, int enable) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  STCHK(prof_harvest(m));
+  if (enable) {
+    for (int k = 0; k < DN_K_COUNT; ++k) { m->prof.ms[k] = m->prof.fl[k] = m->prof.by[k] = 0.0; m->prof.n[k] = 0; }
+  }
+  m->prof.on = enable != 0;
+  return DN_OK;
+}
+
+dn_status dn_profile_read(dn_model* m, int32_t kind, double* total_ms, int64_t* launches, double* flops,
+                          double* bytes) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (kind < 0 || kind >= DN_K_COUNT) return fail(DN_EINVAL, "bad kernel kind");
+  STCHK(prof_harvest(m));
+  if (total_ms) *total_ms = m->prof.ms[kind];
+  if (launches) *launches = m->prof.n[kind];
+  if (flops) *flops = m->prof.fl[kind];
+  if (bytes) *bytes = m->prof.by[kind];
+  return DN_OK;
+}
+
+void dn_model_destroy(dn_model* m) {
+  if (m) (void)hipDeviceSynchronize();
+  delete m;
+}
 
 }  // extern "C"

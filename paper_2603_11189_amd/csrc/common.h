@@ -30,6 +30,13 @@ template <> struct Mma<double> {
   __device__ static inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
+// Green's-function tap tables: per channel TS = 2 Np + 128 entries, offset r = i - i' stored
+// at r + TOFF. Offsets |r| < N hold the taps (periodic chains: the aliased g(r mod N) for every
+// stored r); the 64-entry margins let slice windows run past the chain ends without bounds
+// checks (open chains: zeros there).
+__host__ __device__ inline int tap_stride(int Np) { return 2 * Np + 128; }
+__host__ __device__ inline int tap_off(int Np) { return Np - 1 + 64; }
+
 template <typename T> __device__ inline T act_fn(int act, T x) {
   if (act == 0) return x / (T(1) + exp(-x));          // SiLU
   if (act == 1) return tanh(x);                      // tanh

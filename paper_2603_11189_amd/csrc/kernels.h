@@ -28,6 +28,44 @@ struct CfgMap {
 };
 
 // ---------------------------------------------------------------------------------------
+// Channel-mixing tile on the matrix cores: acc[mt][n] += W x for the DP x DP weight W whose
+// operand table Wt (row = input channel) is given, over NT 16-site tiles starting at site i0.
+// B operands come from a caller-supplied loader bload(kc, n) = x[kc][i0 + 16 n + lane % 16].
+// float: the weight fragments are held in registers across tiles (wreg); double: read per step.
+template <typename T, int DP> struct WFrag {
+  static constexpr int MT = DP / 16, KS = DP / 4;
+  T f[MT][KS];
+  __device__ void load(const T* __restrict__ Wt, int lane) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) f[mt][ks] = Wt[(4 * ks + (lane >> 4)) * DP + 16 * mt + (lane & 15)];
+  }
+};
+
+template <typename T, int DP, int NT, typename BL>
+__device__ inline void mix_tile(const WFrag<T, DP>& w, BL bload, typename Mma<T>::acc (&acc)[DP / 16][NT]) {
+  constexpr int MT = DP / 16, KS = DP / 4;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[mt][n] = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {  // fully unrolled: the weight fragments stay in registers
+    T bv[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) bv[n] = bload(4 * ks + (threadIdx.x & 63) / 16, n);
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = Mma<T>::mma(w.f[mt][ks], bv[n], acc[mt][n]);
+  }
+}
+
+// Site tiles per wave for a padded chain of Np sites and 4 waves per workgroup.
+__host__ __device__ inline int tiles_per_wave(int Np) { return Np >= 256 ? 4 : Np / 64; }
+
+// ---------------------------------------------------------------------------------------
 // phi stream of block l (App. "Details on the implementation of the DysonNet block"):
 //   a = W_D phi^(l-1) + w;  phi^(l) = g(sum_r K_r * a_{i+r} + k);  chi^(l) = g(A_D phi^(l) + b)
 // Block 1 uses phi^(0) = E_phi s', so a = s'_i (W_D E_phi) + w (rank one). Block 1 also
@@ -48,20 +86,22 @@ template <typename T> struct PhiArgs {
   double* rho;          // first block only: [C][2]
 };
 
-template <typename T, int DP>
+template <typename T, int DP, int NT>
 __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* as = reinterpret_cast<T*>(smem_raw);
   const int g = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int N = A.N, Np = A.Np, wc = A.w_c;
-  const int ld = Np + 2 * wc;
-  T* sp_s = as + DP * ld;  // s' (first block), [Np]
+  const int ld = Np + 2 * wc + 1;  // odd row stride
+  T* sp_s = as + DP * ld;          // s' (first block), [Np]
   __shared__ double red[2][4];
   const long fo = (long)g * DP * Np;
-  constexpr int MT = DP / 16, KS = DP / 4;
+  constexpr int MT = DP / 16;
   using M = Mma<T>;
+  using acc_t = typename M::acc;
   const int l = A.l;
+  const int span = 16 * NT;  // sites per wave per pass
   if (A.first) {
     const int gg = A.cfg0 + g;
     const int b = A.map.cb[gg], m = A.map.cm[gg];
@@ -87,32 +127,29 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
       if (A.a_out) A.a_out[fo + idx] = v;
     }
   } else {
-    const T* WDt = A.tb.WDt + (long)l * DP * DP;
+    WFrag<T, DP> wd;
+    wd.load(A.tb.WDt + (long)l * DP * DP, lane);
     const T* x = A.phi_in + fo;
-    for (int nt = wave; nt < Np / 16; nt += 4) {
-      typename M::acc acc[MT];
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
-      const int i = nt * 16 + (lane & 15);
-#pragma unroll 4
-      for (int ks = 0; ks < KS; ++ks) {
-        const int kc = 4 * ks + (lane >> 4);
-        const T bv = x[kc * Np + i];
+    for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
+      acc_t acc[MT][NT];
+      mix_tile<T, DP, NT>(wd, [&](int kc, int n) { return x[(long)kc * Np + i0 + 16 * n + (lane & 15)]; }, acc);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(WDt[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
+      for (int n = 0; n < NT; ++n) {
+        const int i = i0 + 16 * n + (lane & 15);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ch = 16 * mt + M::row(lane, r);
+            T v = (i < N) ? acc[mt][n][r] + A.tb.wv[l * DP + ch] : T(0);
+            as[ch * ld + i + wc] = v;
+            if (A.a_out) A.a_out[fo + (long)ch * Np + i] = v;
+          }
       }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ch = 16 * mt + M::row(lane, r);
-          T v = (i < N) ? acc[mt][r] + A.tb.wv[l * DP + ch] : T(0);
-          as[ch * ld + i + wc] = v;
-          if (A.a_out) A.a_out[fo + (long)ch * Np + i] = v;
-        }
     }
   }
   __syncthreads();
-  // halos of width w_c (open: zero; periodic: wrap-around), plus wrap for padded tail
+  // halos of width w_c (open: zero; periodic: wrap-around)
   if (wc > 0) {
     for (int idx = threadIdx.x; idx < DP * 2 * wc; idx += 256) {
       int c = idx / (2 * wc), h = idx % (2 * wc);
@@ -123,15 +160,14 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
     }
   }
   __syncthreads();
-  const T* ADt = A.tb.ADt + (long)l * DP * DP;
+  WFrag<T, DP> ad;
+  ad.load(A.tb.ADt + (long)l * DP * DP, lane);
   const T* Kc = A.tb.Kc + (long)l * (2 * wc + 1) * DP;
   double part0 = 0.0, part1 = 0.0;
-  for (int nt = wave; nt < Np / 16; nt += 4) {
-    typename M::acc acc[MT];
-    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
-    const int i = nt * 16 + (lane & 15);
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + (lane >> 4);
+  for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
+    acc_t acc[MT][NT];
+    auto phi_at = [&](int kc, int n) -> T {
+      const int i = i0 + 16 * n + (lane & 15);
       T ph = 0;
       if (i < N) {
         T s = A.tb.kv[l * DP + kc];
@@ -145,17 +181,21 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
         part0 += (double)A.tb.Wk[(long)kc * Np + i] * (double)h0;
         part1 += (double)A.tb.Wk[(long)(DP + kc) * Np + i] * (double)h0;
       }
+      return ph;
+    };
+    mix_tile<T, DP, NT>(ad, phi_at, acc);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(ADt[kc * DP + 16 * mt + (lane & 15)], ph, acc[mt]);
+    for (int n = 0; n < NT; ++n) {
+      const int i = i0 + 16 * n + (lane & 15);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * mt + M::row(lane, r);
+          T v = (i < N) ? act_fn<T>(A.act, acc[mt][n][r] + A.tb.bv[l * DP + ch]) : T(0);
+          A.chi_out[fo + (long)ch * Np + i] = v;
+        }
     }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ch = 16 * mt + M::row(lane, r);
-        T v = (i < N) ? act_fn<T>(A.act, acc[mt][r] + A.tb.bv[l * DP + ch]) : T(0);
-        A.chi_out[fo + (long)ch * Np + i] = v;
-      }
   }
   if (A.first) {
     part0 = wave_sum(part0);
@@ -178,7 +218,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
 template <typename T> struct ConvArgs {
   const T* X;
   T* Y;
-  const T* taps;  // [DP][2Np] for this mixer
+  const T* taps;  // [DP][tap_stride(Np)] for this mixer
   int N, Np, C, DP;
 };
 
@@ -198,7 +238,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
   const int Np = A.Np;
   const int site0 = blockIdx.z * 64 * NT;                // output block of 4 waves x 16*NT sites
   const int wsite0 = site0 + wave * 16 * NT;              // this wave's first output site
-  const T* tp = A.taps + (long)c * 2 * Np;
+  const T* tp = A.taps + (long)c * tap_stride(Np) + 64;  // offsets -(Np-1).. at ts[0..]
   for (int q = threadIdx.x; q < 2 * Np; q += 256) ts[q] = tp[q];
   typename M::acc acc[4][NT];
 #pragma unroll
@@ -283,21 +323,26 @@ template <typename T> struct MixArgs {
   int Wmax;
   const T* tau;          // [B][2][DP][Np] (chunk-local)
   T* yL;                 // [F][Wmax][DP]
-  const T* tapsL;        // taps of block L [DP][2Np] (LAST)
-  const T* taps1;        // taps of block 1 [DP][2Np] (FIRST)
+  const T* tapsL;        // taps of block L [DP][tap_stride] (LAST)
+  const T* taps1;        // taps of block 1 [DP][tap_stride] (FIRST)
 };
 
-template <typename T, int DP, int MODE, bool FIRST, bool LAST>
+constexpr int SLICE_WIN = 16;  // register window of the last block's slice convolution
+
+template <typename T, int DP, int NT, int MODE, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [DP][Np]
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [DP][S], S = Np + 17 (odd: conflict-free column reads)
   __shared__ double red[2][4];
   __shared__ int4 sg;
   using M = Mma<T>;
-  constexpr int MT = DP / 16, KS = DP / 4;
+  using acc_t = typename M::acc;
+  constexpr int MT = DP / 16;
   const int g = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int N = A.N, Np = A.Np, l = A.l;
+  const int S = Np + 17;
+  const int span = 16 * NT;
   const long fo = (long)g * DP * Np;
   int b = 0;        // sample (chunk-local) whose caches are used
   int kk_tau = 0;
@@ -316,101 +361,94 @@ __global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
     W = sg.y + 2 * l * A.w_c + 1;
   }
   const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
-  // ---- phase 1
-  for (int nt = wave; nt < Np / 16; nt += 4) {
-    typename M::acc acc[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
-    const int i = nt * 16 + (lane & 15);
-#pragma unroll 4
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + (lane >> 4);
-      T bv;
-      if (MODE == MIX_DEEP && FIRST) {
-        // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
-        bv = 0;
-        if (i < N) {
-          const int8_t* sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
-          const T* t1 = A.taps1 + (long)kc * 2 * Np;
+  const int TO = tap_off(Np);
+  // ---- phase 1: q = M1 X, x = elementwise(q) -> LDS
+  {
+    WFrag<T, DP> w1;
+    w1.load(M1, lane);
+    const int8_t* sp = nullptr;
+    T e0a = 0, e0b = 0;
+    if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+    for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
+      acc_t acc[MT][NT];
+      auto bload = [&](int kc, int n) -> T {
+        const int i = i0 + 16 * n + (lane & 15);
+        if (MODE == MIX_DEEP && FIRST) {
+          // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
+          const T* t1 = A.taps1 + (long)kc * tap_stride(Np) + TO;
           T e = A.tb.E[kc];
-          bv = t1[i - sg.z + Np - 1] * (T)(-2 * sp[sg.z]) * e;
-          if (sg.w >= 0) bv += t1[i - sg.w + Np - 1] * (T)(-2 * sp[sg.w]) * e;
+          T v = t1[i - sg.z] * (T)(-2 * sp[sg.z]) * e;
+          if (sg.w >= 0) v += t1[i - sg.w] * (T)(-2 * sp[sg.w]) * e;
+          return (i < N) ? v : T(0);
         }
-      } else {
-        bv = X[(long)kc * Np + i];
-      }
+        return X[(long)kc * Np + i];
+      };
+      mix_tile<T, DP, NT>(w1, bload, acc);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(M1[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
-    }
+      for (int n = 0; n < NT; ++n) {
+        const int i = i0 + 16 * n + (lane & 15);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ch = 16 * mt + M::row(lane, r);
-        const T q = acc[mt][r];
-        T x;
-        if (MODE == MIX_FWD) {
-          x = A.chi[fo + (long)ch * Np + i] * q;
-          if (A.p0_out) A.p0_out[fo + (long)ch * Np + i] = q;
-        } else if (MODE == MIX_TAU) {
-          x = A.chi[bo + (long)ch * Np + i] * q;
-        } else {
-          x = A.chi[bo + (long)ch * Np + i] * q;
-          int sidx = i - lo;
-          if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
-          if (i < N && sidx >= 0 && sidx < W) {
-            const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
-            x += dc * (A.p0[bo + (long)ch * Np + i] + q);
+          for (int r = 0; r < 4; ++r) {
+            const int ch = 16 * mt + M::row(lane, r);
+            const T q = acc[mt][n][r];
+            T x;
+            if (MODE == MIX_FWD) {
+              x = A.chi[fo + (long)ch * Np + i] * q;
+              if (A.p0_out) A.p0_out[fo + (long)ch * Np + i] = q;
+            } else if (MODE == MIX_TAU) {
+              x = A.chi[bo + (long)ch * Np + i] * q;
+            } else {
+              x = A.chi[bo + (long)ch * Np + i] * q;
+              int sidx = i - lo;
+              if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
+              if (i < N && sidx >= 0 && sidx < W) {
+                const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
+                x += dc * (A.p0[bo + (long)ch * Np + i] + q);
+              }
+            }
+            xs[ch * S + i] = (i < N) ? x : T(0);
           }
-        }
-        xs[ch * Np + i] = (i < N) ? x : T(0);
       }
+    }
   }
   __syncthreads();
-  // ---- phase 2
+  // ---- phase 2: y = M2 x (the wave reads only its own columns of xs)
   double part0 = 0.0, part1 = 0.0;
-  for (int nt = wave; nt < Np / 16; nt += 4) {
-    typename M::acc acc[MT];
+  {
+    WFrag<T, DP> w2;
+    w2.load(M2, lane);
+    for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
+      acc_t acc[MT][NT];
+      mix_tile<T, DP, NT>(w2, [&](int kc, int n) { return xs[kc * S + i0 + 16 * n + (lane & 15)]; }, acc);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[mt] = typename M::acc{0, 0, 0, 0};
-    const int i = nt * 16 + (lane & 15);
-#pragma unroll 4
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + (lane >> 4);
-      const T bv = xs[kc * Np + i];
+      for (int n = 0; n < NT; ++n) {
+        const int i = i0 + 16 * n + (lane & 15);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(M2[kc * DP + 16 * mt + (lane & 15)], bv, acc[mt]);
-    }
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ch = 16 * mt + M::row(lane, r);
-        const T y = (i < N) ? acc[mt][r] : T(0);
-        const long o = (long)ch * Np + i;
-        if (MODE == MIX_TAU) {
-          A.out[fo + o] = y;
-        } else {
-          T w0 = A.tb.Wk[o], w1 = A.tb.Wk[(long)DP * Np + o];
-          if (MODE == MIX_DEEP && LAST) {
-            w0 += A.tau[(long)(2 * b) * DP * Np + o];
-            w1 += A.tau[(long)(2 * b + 1) * DP * Np + o];
+          for (int r = 0; r < 4; ++r) {
+            const int ch = 16 * mt + M::row(lane, r);
+            const T y = (i < N) ? acc[mt][n][r] : T(0);
+            const long o = (long)ch * Np + i;
+            if (MODE == MIX_TAU) {
+              A.out[fo + o] = y;
+            } else {
+              T w0 = A.tb.Wk[o], w1v = A.tb.Wk[(long)DP * Np + o];
+              if (MODE == MIX_DEEP && LAST) {
+                w0 += A.tau[(long)(2 * b) * DP * Np + o];
+                w1v += A.tau[(long)(2 * b + 1) * DP * Np + o];
+              }
+              part0 += (double)w0 * (double)y;
+              part1 += (double)w1v * (double)y;
+              if (MODE == MIX_FWD && A.out) A.out[fo + o] = y + (A.inject ? A.phi_next[fo + o] : T(0));
+              if (MODE == MIX_DEEP && !LAST) A.out[fo + o] = y;
+              // the tile's K loop is done: its columns of xs can hold dh for the slice conv
+              if (MODE == MIX_DEEP && LAST) xs[ch * S + i] = y;
+            }
           }
-          part0 += (double)w0 * (double)y;
-          part1 += (double)w1 * (double)y;
-          if (MODE == MIX_FWD && A.out) A.out[fo + o] = y + (A.inject ? A.phi_next[fo + o] : T(0));
-          if (MODE == MIX_DEEP && !LAST) A.out[fo + o] = y;
-        }
       }
-    if (MODE == MIX_DEEP && LAST) {
-      // the wave owns these columns of xs: overwrite them with dh for the slice conv
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ch = 16 * mt + M::row(lane, r);
-          xs[ch * Np + i] = (i < N) ? acc[mt][r] : T(0);
-        }
     }
   }
   if (MODE != MIX_TAU) {
@@ -424,20 +462,39 @@ __global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
     A.rho[2 * g + 1] += red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
   if (MODE == MIX_DEEP && LAST) {
-    // y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i'] for the W_L slice sites
-    const int loL = sg.x - A.L * A.w_c;
+    // y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i'] on the W_L (<= SLICE_WIN) slice sites.
+    // Lane = channel, wave = quarter of the chain; the taps slide through a register window.
+    int loL = sg.x - A.L * A.w_c;
     const int WL = sg.y + 2 * A.L * A.w_c + 1;
-    for (int pair = wave; pair < WL * DP; pair += 4) {
-      const int t = pair / DP, c = pair % DP;
-      int site = loL + t;
-      if (A.periodic) { site %= N; if (site < 0) site += N; }
-      T acc = 0;
-      if (site >= 0 && site < N) {
-        const T* tl = A.tapsL + (long)c * 2 * Np + site + Np - 1;
-        for (int ip = lane; ip < N; ip += 64) acc += tl[-ip] * xs[c * Np + ip];
+    if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+    const int c = lane;
+    const int q = (N + 3) / 4, ib = wave * q, ie = min(N, ib + q);
+    T acc[SLICE_WIN], win[SLICE_WIN];
+#pragma unroll
+    for (int t = 0; t < SLICE_WIN; ++t) acc[t] = 0;
+    if (c < DP) {
+      const T* tc = A.tapsL + (long)c * tap_stride(Np) + TO + loL;  // tc[t - i'] = g(loL + t - i')
+#pragma unroll
+      for (int t = 0; t < SLICE_WIN; ++t) win[t] = tc[t - ib];
+      for (int ip = ib; ip < ie; ++ip) {
+        const T v = xs[c * S + ip];
+#pragma unroll
+        for (int t = 0; t < SLICE_WIN; ++t) acc[t] += win[t] * v;
+#pragma unroll
+        for (int t = SLICE_WIN - 1; t > 0; --t) win[t] = win[t - 1];
+        win[0] = tc[-(ip + 1)];
       }
-      acc = wave_sum(acc);
-      if (lane == 0) A.yL[((long)g * A.Wmax + t) * DP + c] = acc;
+    }
+    __syncthreads();  // every wave is done reading dh: reuse xs for the partial sums
+    if (c < DP)
+#pragma unroll
+      for (int t = 0; t < SLICE_WIN; ++t) xs[(wave * SLICE_WIN + t) * DP + c] = acc[t];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < WL * DP; idx += 256) {
+      const int t = idx / DP, cc = idx % DP;
+      T s = 0;
+      for (int w = 0; w < 4; ++w) s += xs[(w * SLICE_WIN + t) * DP + cc];
+      A.yL[((long)g * A.Wmax + t) * DP + cc] = s;
     }
   }
 }
@@ -618,9 +675,9 @@ __global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
     if (on) {
       T y;
       if (L == 1) {
-        const T* t1 = A.taps1 + (long)c * 2 * Np;
-        y = t1[site - gm.z + Np - 1] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
-        if (gm.w >= 0) y += t1[site - gm.w + Np - 1] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
+        const T* t1 = A.taps1 + (long)c * tap_stride(Np) + tap_off(Np);
+        y = t1[site - gm.z] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
+        if (gm.w >= 0) y += t1[site - gm.w] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
       } else {
         y = A.yL[((long)f * A.Wmax + t) * DP + c];
       }

@@ -199,13 +199,13 @@ __global__ __launch_bounds__(S4_THREADS) void s4_taps_kernel(const double* __res
 struct PrepArgs {
   const double* params;
   const double* taps64;  // [L+1][d][2N-1]
-  int N, Np, L, d, DP, s, w_c, d_out;
+  int N, Np, L, d, DP, s, w_c, d_out, periodic;
   long off_layers, off_A;
   // outputs (double tables)
   double *E, *Ephi, *wE1;
   double *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP]; *t transposed (t[k][m] = M[m][k])
   double *wv, *Kc, *kv, *bv;               // [L][DP], K: [L][2w_c+1][DP]
-  double *taps, *tapsR;                    // [L][DP][2Np], reversed taps of block L-1: [DP][2Np]
+  double *taps, *tapsR;                    // [L][DP][TS], transposed mixer of block L: [DP][TS]
   double *omega, *Wk, *A;                  // [DP][Np], [2][DP][Np], [DP][2]
 };
 
@@ -251,20 +251,18 @@ __global__ void prep_kernel(PrepArgs a) {
     a.bv[idx] = in ? base[d * d + d + Wc * d + d + d * d + c] : 0.0;
     for (int r = 0; r < Wc; ++r) a.Kc[(l * Wc + r) * DP + c] = in ? base[d * d + d + r * d + c] : 0.0;
   }
-  const int N = a.N, Np = a.Np;
-  for (long idx = tid; idx < (long)L * DP * 2 * Np; idx += nth) {
-    int l = idx / (DP * 2 * Np), c = (idx / (2 * Np)) % DP, q = idx % (2 * Np);
-    int r = q - (Np - 1);
-    double v = 0.0;
-    if (c < d && q < 2 * Np - 1 && r > -N && r < N) v = a.taps64[((long)l * d + c) * (2 * N - 1) + r + N - 1];
-    a.taps[idx] = v;
-    if (l == L - 1) {
-      // reversed taps: tapsR[c][q] = taps[c][2Np-2-q] (offset -r), for the transposed mixer
-      int rr = -r;
-      double vr = 0.0;
-      if (c < d && q < 2 * Np - 1 && rr > -N && rr < N) vr = a.taps64[((long)l * d + c) * (2 * N - 1) + rr + N - 1];
-      a.tapsR[c * 2L * Np + q] = vr;
-    }
+  const int N = a.N, Np = a.Np, TS = tap_stride(Np), TO = tap_off(Np);
+  const int periodic = a.periodic;
+  auto tap = [&](int l, int c, int r) -> double {  // g of mixer l, channel c at offset r
+    if (periodic) { int p = ((r % N) + N) % N; return a.taps64[((long)l * d + c) * (2 * N - 1) + p + N - 1]; }
+    if (r <= -N || r >= N) return 0.0;
+    return a.taps64[((long)l * d + c) * (2 * N - 1) + r + N - 1];
+  };
+  for (long idx = tid; idx < (long)L * DP * TS; idx += nth) {
+    int l = idx / ((long)DP * TS), c = (idx / TS) % DP, q = idx % TS;
+    int r = q - TO;
+    a.taps[idx] = (c < d) ? tap(l, c, r) : 0.0;
+    if (l == L - 1) a.tapsR[(long)c * TS + q] = (c < d) ? tap(l, c, -r) : 0.0;  // transposed mixer
   }
   for (long idx = tid; idx < (long)DP * Np; idx += nth) {
     int c = idx / Np, i = idx % Np;
