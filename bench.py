@@ -40,6 +40,80 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_class(name: str) -> str:
+    """Map a demangled kernel name to the library's profile class."""
+    if "mix_kernel" in name:
+        mode = name.split("mix_kernel<")[1].split(",")[2].strip()
+        return {"0": "mix_fwd", "1": "mix_tau", "2": "mix_deep"}[mode]
+    for key, cls in (("conv_kernel", "conv"), ("phi_kernel", "phi"), ("slice_kernel", "slice"),
+                     ("tail_kernel", "tail"), ("s4_taps_kernel", "s4gen"), ("prep_kernel", "prep"),
+                     ("connected_kernel", "gen"), ("eloc_kernel", "eloc")):
+        if key in name:
+            return cls
+    return "other"
+
+
+def summarize(args) -> None:
+    """Turn raw rocprofv3 CSVs (gpurun_out/) into the short summaries kept in profiles/."""
+    import csv
+    import collections
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    wl = args.workload
+    if args.stats_dir:
+        rows = list(csv.DictReader(open(os.path.join(args.stats_dir, "kt_kernel_stats.csv"))))
+        total = sum(float(r["TotalDurationNs"]) for r in rows)
+        out = [f"# Kernel time, {wl}, ABACUS path\n",
+               f"Command: `{args.stats_cmd}`\n",
+               f"Source hash of csrc/: `{source_hash()}`\n",
+               "| kernel | class | calls | total ms | avg us | share |", "|---|---|---|---|---|---|"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
+            out.append(f"| `{r['Name'][:80]}` | {kernel_class(r['Name'])} | {r['Calls']} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{100 * float(r['TotalDurationNs']) / total:.1f}% |")
+        cls = collections.defaultdict(lambda: [0.0, 0])
+        for r in rows:
+            c = cls[kernel_class(r["Name"])]
+            c[0] += float(r["TotalDurationNs"])
+            c[1] += int(r["Calls"])
+        out += ["", "Per class (the grouping `bench.py` uses for its roofline):", "",
+                "| class | calls | avg us per launch |", "|---|---|---|"]
+        for k, (ns, n) in sorted(cls.items(), key=lambda kv: -kv[1][0]):
+            out.append(f"| {k} | {n} | {ns / n / 1e3:.1f} |")
+        with open(os.path.join(ROOT, "profiles", f"kernel_stats_{wl}.md"), "w") as f:
+            f.write("\n".join(out) + "\n")
+    if args.pmc_dirs:
+        per = {}
+        for d in args.pmc_dirs.split(","):
+            rows = list(csv.DictReader(open(os.path.join(d, "pmc_counter_collection.csv"))))
+            for r in rows:
+                per.setdefault(r["Counter_Name"], []).append(r)
+        calib = {}
+        for ctr, rows in per.items():
+            big = max((r for r in rows if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+            calib[ctr] = (256 << 20) / (float(big["Counter_Value"]) * 1024)
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for ctr, rows in per.items():
+            for r in rows:
+                agg[kernel_class(r["Kernel_Name"])][ctr].append(float(r["Counter_Value"]) * 1024 * calib[ctr])
+        res = {"source_hash": source_hash(), "command": args.pmc_cmd,
+               "calibration": {k: f"x{v:.3f} (256 MiB device copy)" for k, v in calib.items()}, wl: {}}
+        md = [f"# HBM traffic per launch, {wl}, ABACUS path\n", f"Command (one run per counter): `{args.pmc_cmd}`\n",
+              "Scale factors from a 256 MiB device copy in the same process: " +
+              ", ".join(f"{k} x{v:.3f}" for k, v in calib.items()) + "\n",
+              "| class | launches | fetch MB/launch | write MB/launch | total MB/launch |", "|---|---|---|---|---|"]
+        for k, v in agg.items():
+            if "FETCH_SIZE" in v and "WRITE_SIZE" in v:
+                fe = sum(v["FETCH_SIZE"]) / len(v["FETCH_SIZE"])
+                wr = sum(v["WRITE_SIZE"]) / len(v["WRITE_SIZE"])
+                res[wl][k] = {"fetch_bytes_per_launch": fe, "write_bytes_per_launch": wr, "bytes_per_launch": fe + wr,
+                              "launches": len(v["FETCH_SIZE"])}
+                md.append(f"| {k} | {len(v['FETCH_SIZE'])} | {fe / 1e6:.1f} | {wr / 1e6:.1f} | {(fe + wr) / 1e6:.1f} |")
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        with open(os.path.join(ROOT, "profiles", f"traffic_{wl}.md"), "w") as f:
+            f.write("\n".join(md) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,7 +125,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain device copy of 256 MiB (reference for HBM counters)")
+    ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
+    ap.add_argument("--stats-dir", default="")
+    ap.add_argument("--stats-cmd", default="")
+    ap.add_argument("--pmc-dirs", default="")
+    ap.add_argument("--pmc-cmd", default="")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the estimator shards by "
@@ -84,6 +168,13 @@ def main():
     bufs = {p: (torch.empty(B, dtype=torch.float64, device=dev),
                 torch.empty((B, M_max), dtype=torch.float64, device=dev),
                 torch.empty(B, dtype=torch.float64, device=dev)) for p in ("abacus", "full")}
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     results = {}
     for path in args.paths.split(","):
         log(f"[bench] {args.workload} path={path} warmup={args.warmup}")

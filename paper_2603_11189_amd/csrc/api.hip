@@ -284,16 +284,11 @@ template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>
   return DN_OK;
 }
 
-template <typename T, int DP, int NT, int MODE, bool FIRST, bool LAST>
-void mix_go(const MixArgs<T>& a, int C, size_t lds, hipStream_t st) {
-  allow_lds(mix_kernel<T, DP, NT, MODE, FIRST, LAST>, lds);
-  mix_kernel<T, DP, NT, MODE, FIRST, LAST><<<C, 256, lds, st>>>(a);
-}
-
 template <typename T, int DP, int MODE, bool FIRST, bool LAST>
 dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, int Bc = 0) {
   if (C <= 0) return DN_OK;
-  const size_t lds = (size_t)DP * (m->Np + 17) * sizeof(T);
+  const int nw = m->Np / 64;
+  const size_t lds = (size_t)nw * DP * MIX_XS * sizeof(T);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "mixing tile exceeds LDS");
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T), fld = Nr * dr * e;
   double fl = 4.0 * C * Nr * dr * dr, by;
@@ -307,20 +302,13 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, in
   } else {
     kind = DN_K_MIX_DEEP;
     const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
-    if (LAST) fl += 2.0 * C * WL * Nr * dr;
-    by = C * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
+    // the last block also forms the slice of its mixer output and the two slice products
+    if (LAST) fl += 2.0 * C * WL * Nr * dr + 4.0 * C * WL * dr * dr;
+    by = C * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 5 : 2);
   }
   PScope ps(m, kind, st, fl, by);
-  if constexpr (std::is_same<T, double>::value) {
-    mix_go<T, DP, 1, MODE, FIRST, LAST>(a, C, lds, st);
-  } else {
-    switch (tiles_per_wave(m->Np)) {
-      case 1: mix_go<T, DP, 1, MODE, FIRST, LAST>(a, C, lds, st); break;
-      case 2: mix_go<T, DP, 2, MODE, FIRST, LAST>(a, C, lds, st); break;
-      case 3: mix_go<T, DP, 3, MODE, FIRST, LAST>(a, C, lds, st); break;
-      default: mix_go<T, DP, 4, MODE, FIRST, LAST>(a, C, lds, st); break;
-    }
-  }
+  allow_lds(mix_kernel<T, DP, MODE, FIRST, LAST>, lds);
+  mix_kernel<T, DP, MODE, FIRST, LAST><<<C, 64 * nw, lds, st>>>(a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -475,15 +463,13 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       STCHK(launch_conv<T>(m, tz, tau, tb.tapsR, 2 * Bc, st));
     }
     if (F == 0) continue;
-    void *pdchi, *pgeom, *prho, *pdu, *pw, *pyL;
+    void *pdchi, *pgeom, *prho, *pdu, *pw;
     STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
     STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
     STCHK(ws_get(m, "ab_rho", (size_t)F * 2 * sizeof(double), &prho));
-    STCHK(ws_get(m, "ab_yL", (size_t)F * Wmax * DP * sizeof(T), &pyL));
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
     double* rho = (double*)prho;
-    T* yL = (T*)pyL;
     {
       SliceArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
@@ -508,8 +494,9 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
         a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0;
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
-        a.dchi = dchi; a.Wmax = Wmax; a.tau = tau; a.yL = yL;
+        a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
         a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
+        a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio;
         const bool first = (l == 1), last = (l == L - 1);
         if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st));
         // l-1 is the 0-based index of block l in the tables
@@ -522,11 +509,11 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
         STCHK(s);
       }
     }
-    {
+    if (L == 1) {
       TailArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.F = F; a.f0 = f0; a.b0 = b0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
-      a.yL = yL; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
+      a.yL = nullptr; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
       a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax;
       const int WL = 2 * L * wc + 1;
       PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d, (double)F * (WL * 2 + 1) * d.d * sizeof(T));

@@ -286,8 +286,10 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Vertex and channel mixing, fused with the read-out. Per configuration (one workgroup):
-//   phase 1: q = M1 X (matrix cores), x = elementwise(q, ...) -> LDS [DP][Np]
+// Vertex and channel mixing, fused with the read-out. One workgroup per configuration,
+// one wave per 64-site block; a wave's 16 matrix-core columns j and 4 tiles n cover sites
+// 64 w + 4 j + n, so every lane moves 4 consecutive sites as one vector.
+//   phase 1: q = M1 X (matrix cores), x = elementwise(q, ...) -> the wave's LDS tile
 //   phase 2: y = M2 x, written out and contracted with the read-out weights.
 // Modes:
 //   FWD:  X = v, x = chi * q (q = V v cached as p0 when requested), y = h = U x;
@@ -297,9 +299,11 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
 //         taps then gives tau = G^T D0^T Wk).
 //   DEEP: X = w = G^(l) du (full chain, per flip), x = chi0 q + [i in S_l] dchi (p0 + q),
 //         y = dh = U x: the background propagation of the perturbation plus the vertex
-//         change on the slice. rho += Wk . dh. LAST (l = L-1) also adds tau . dh and writes
-//         the slice of the next mixer's output, y_L = P_{S_L} G^(L) dh, for the tail.
-//         FIRST (l = 1) builds w = G^(1) e^(0) from the taps and the cluster instead of X.
+//         change on the slice. rho += Wk . dh. FIRST (l = 1) builds w = G^(1) e^(0) from the
+//         taps and the cluster instead of reading X. LAST (l = L-1) adds tau . dh, forms the
+//         slice of the last mixer's output y_L = P_{S_L} G^(L) dh and finishes the flip:
+//         e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, dOmega = rho + Wk . (e^(0) + e^(L)),
+//         log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
 enum { MIX_FWD = 0, MIX_TAU = 1, MIX_DEEP = 2 };
 
 template <typename T> struct MixArgs {
@@ -308,11 +312,11 @@ template <typename T> struct MixArgs {
   int C;                 // configurations (flips) in this launch
   int cfg0;              // global index of the first (DEEP: flip map offset)
   const T* X;            // [C][DP][Np] (FWD/DEEP non-first)
-  const T* chi;          // FWD: [C][DP][Np]; TAU/DEEP: chi0 of the block [B][DP][Np] (per sample)
-  const T* p0;           // DEEP: V v0 of the block [B][DP][Np]; FWD: cache out (nullable, written)
-  T* p0_out;             // FWD cache of q
+  const T* chi;          // FWD: [C][DP][Np]; TAU/DEEP: chi0 of the block [Bc][DP][Np]
+  const T* p0;           // DEEP: V v0 of the block [Bc][DP][Np]
+  T* p0_out;             // FWD cache of q (nullable)
   const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
-  T* out;                // [C][DP][Np] (nullable for DEEP LAST)
+  T* out;                // [C][DP][Np] (unused for DEEP LAST)
   double* rho;           // [C][2] accumulated (FWD, DEEP)
   // DEEP
   CfgMap map;            // flip -> (b, m)
@@ -321,36 +325,65 @@ template <typename T> struct MixArgs {
   const int4* geom;      // [F] (clo, ext, j0, j1)
   const T* dchi;         // [F][L][Wmax][DP]
   int Wmax;
-  const T* tau;          // [B][2][DP][Np] (chunk-local)
-  T* yL;                 // [F][Wmax][DP]
+  const T* tau;          // [Bc][2][DP][Np]
   const T* tapsL;        // taps of block L [DP][tap_stride] (LAST)
   const T* taps1;        // taps of block 1 [DP][tap_stride] (FIRST)
+  const T* p0L;          // LAST: V v0 of block L [Bc][DP][Np]
+  const double* Om0;     // LAST: [B][2]
+  double* logratio;      // LAST: [B][M_max]
 };
 
-constexpr int SLICE_WIN = 16;  // register window of the last block's slice convolution
+constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4)
+constexpr int SLICE_WIN = 16;   // slice positions handled by the last block's window
 
-template <typename T, int DP, int NT, int MODE, bool FIRST, bool LAST>
-__global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
+template <typename T> struct V4 { T v[4]; };
+template <typename T> __device__ inline V4<T> ld4(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    float4 f = *reinterpret_cast<const float4*>(p);
+    r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
+  } else {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) r.v[n] = p[n];
+  }
+  return r;
+}
+template <typename T> __device__ inline void st4(T* p, const T* v) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) p[n] = v[n];
+  }
+}
+
+// Wave-scope ordering of LDS traffic between lanes of one wave.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int DP, int MODE, bool FIRST, bool LAST>
+__global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [DP][S], S = Np + 17 (odd: conflict-free column reads)
-  __shared__ double red[2][4];
-  __shared__ int4 sg;
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  constexpr int MT = DP / 16;
+  constexpr int MT = DP / 16, KS = DP / 4;
+  __shared__ double red[2][8];
+  __shared__ int4 sg;
   const int g = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   const int N = A.N, Np = A.Np, l = A.l;
-  const int S = Np + 17;
-  const int span = 16 * NT;
+  const int j = lane & 15, kq = lane >> 4;
+  T* xs = reinterpret_cast<T*>(smem_raw) + wave * DP * MIX_XS;  // this wave's tile [DP][68]
   const long fo = (long)g * DP * Np;
-  int b = 0;        // sample (chunk-local) whose caches are used
-  int kk_tau = 0;
+  int b = 0, kk_tau = 0;
   if (MODE == MIX_TAU) { b = g >> 1; kk_tau = g & 1; }
   if (MODE == MIX_DEEP) b = A.map.cb[A.cfg0 + g] - A.b0;
   const long bo = (long)b * DP * Np;
-  // table index of the block: FWD/TAU pass the 0-based block, DEEP the 1-based block l
-  const int tl = (MODE == MIX_DEEP) ? l - 1 : l;
+  const int tl = (MODE == MIX_DEEP) ? l - 1 : l;  // table index (DEEP passes the 1-based block)
   const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)tl * DP * DP : A.tb.Vt + (long)tl * DP * DP;
   const T* M2 = (MODE == MIX_TAU) ? A.tb.Vm + (long)tl * DP * DP : A.tb.Ut + (long)tl * DP * DP;
   int lo = 0, W = 0;
@@ -360,142 +393,269 @@ __global__ __launch_bounds__(256) void mix_kernel(MixArgs<T> A) {
     lo = sg.x - l * A.w_c;
     W = sg.y + 2 * l * A.w_c + 1;
   }
-  const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
   const int TO = tap_off(Np);
-  // ---- phase 1: q = M1 X, x = elementwise(q) -> LDS
-  {
-    WFrag<T, DP> w1;
-    w1.load(M1, lane);
-    const int8_t* sp = nullptr;
-    T e0a = 0, e0b = 0;
-    if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
-    for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
-      acc_t acc[MT][NT];
-      auto bload = [&](int kc, int n) -> T {
-        const int i = i0 + 16 * n + (lane & 15);
-        if (MODE == MIX_DEEP && FIRST) {
-          // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
-          const T* t1 = A.taps1 + (long)kc * tap_stride(Np) + TO;
-          T e = A.tb.E[kc];
-          T v = t1[i - sg.z] * (T)(-2 * sp[sg.z]) * e;
-          if (sg.w >= 0) v += t1[i - sg.w] * (T)(-2 * sp[sg.w]) * e;
-          return (i < N) ? v : T(0);
+  const int s0 = 64 * wave + 4 * j;  // first of this lane's 4 sites
+  const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
+  // ---- phase 1
+  acc_t acc[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+  const int8_t* sp = nullptr;
+  if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+#pragma unroll 4
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    T bv[4];
+    if (MODE == MIX_DEEP && FIRST) {
+      // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
+      const T* t1 = A.taps1 + (long)kc * tap_stride(Np) + TO;
+      const T e = A.tb.E[kc];
+      const T c0 = (T)(-2 * sp[sg.z]) * e;
+      const T c1 = sg.w >= 0 ? (T)(-2 * sp[sg.w]) * e : T(0);
+      const int j1 = sg.w >= 0 ? sg.w : sg.z;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int i = s0 + n;
+        bv[n] = (i < N) ? t1[i - sg.z] * c0 + t1[i - j1] * c1 : T(0);
+      }
+    } else {
+      V4<T> v = ld4(X + (long)kc * Np + s0);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
+    }
+    T af[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) af[mt] = M1[kc * DP + 16 * mt + j];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], bv[n], acc[mt][n]);
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ch = 16 * mt + M::row(lane, r);
+      const long o = (long)ch * Np + s0;
+      T q[4], x[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) q[n] = acc[mt][n][r];
+      if (MODE == MIX_FWD) {
+        V4<T> c = ld4(A.chi + fo + o);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) x[n] = c.v[n] * q[n];
+        if (A.p0_out) st4(A.p0_out + fo + o, q);
+      } else {
+        V4<T> c = ld4(A.chi + bo + o);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) x[n] = c.v[n] * q[n];
+        if (MODE == MIX_DEEP) {
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            const int i = s0 + n;
+            int sidx = i - lo;
+            if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
+            if (i < N && sidx >= 0 && sidx < W) {
+              const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
+              x[n] += dc * (A.p0[bo + o + n] + q[n]);
+            }
+          }
         }
-        return X[(long)kc * Np + i];
-      };
-      mix_tile<T, DP, NT>(w1, bload, acc);
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int i = i0 + 16 * n + (lane & 15);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ch = 16 * mt + M::row(lane, r);
-            const T q = acc[mt][n][r];
-            T x;
-            if (MODE == MIX_FWD) {
-              x = A.chi[fo + (long)ch * Np + i] * q;
-              if (A.p0_out) A.p0_out[fo + (long)ch * Np + i] = q;
-            } else if (MODE == MIX_TAU) {
-              x = A.chi[bo + (long)ch * Np + i] * q;
-            } else {
-              x = A.chi[bo + (long)ch * Np + i] * q;
-              int sidx = i - lo;
-              if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
-              if (i < N && sidx >= 0 && sidx < W) {
-                const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
-                x += dc * (A.p0[bo + (long)ch * Np + i] + q);
-              }
-            }
-            xs[ch * S + i] = (i < N) ? x : T(0);
-          }
       }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) if (s0 + n >= N) x[n] = T(0);
+      st4(xs + ch * MIX_XS + 4 * j, x);
     }
+  wave_sync();
+  // ---- phase 2
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    V4<T> v = ld4(xs + kc * MIX_XS + 4 * j);
+    T af[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) af[mt] = M2[kc * DP + 16 * mt + j];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], v.v[n], acc[mt][n]);
   }
-  __syncthreads();
-  // ---- phase 2: y = M2 x (the wave reads only its own columns of xs)
+  wave_sync();
   double part0 = 0.0, part1 = 0.0;
-  {
-    WFrag<T, DP> w2;
-    w2.load(M2, lane);
-    for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
-      acc_t acc[MT][NT];
-      mix_tile<T, DP, NT>(w2, [&](int kc, int n) { return xs[kc * S + i0 + 16 * n + (lane & 15)]; }, acc);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int i = i0 + 16 * n + (lane & 15);
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+    for (int r = 0; r < 4; ++r) {
+      const int ch = 16 * mt + M::row(lane, r);
+      const long o = (long)ch * Np + s0;
+      T y[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ch = 16 * mt + M::row(lane, r);
-            const T y = (i < N) ? acc[mt][n][r] : T(0);
-            const long o = (long)ch * Np + i;
-            if (MODE == MIX_TAU) {
-              A.out[fo + o] = y;
-            } else {
-              T w0 = A.tb.Wk[o], w1v = A.tb.Wk[(long)DP * Np + o];
-              if (MODE == MIX_DEEP && LAST) {
-                w0 += A.tau[(long)(2 * b) * DP * Np + o];
-                w1v += A.tau[(long)(2 * b + 1) * DP * Np + o];
-              }
-              part0 += (double)w0 * (double)y;
-              part1 += (double)w1v * (double)y;
-              if (MODE == MIX_FWD && A.out) A.out[fo + o] = y + (A.inject ? A.phi_next[fo + o] : T(0));
-              if (MODE == MIX_DEEP && !LAST) A.out[fo + o] = y;
-              // the tile's K loop is done: its columns of xs can hold dh for the slice conv
-              if (MODE == MIX_DEEP && LAST) xs[ch * S + i] = y;
-            }
+      for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? acc[mt][n][r] : T(0);
+      if (MODE == MIX_TAU) {
+        st4(A.out + fo + o, y);
+      } else {
+        V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + (long)DP * Np + o);
+        if (MODE == MIX_DEEP && LAST) {
+          V4<T> t0 = ld4(A.tau + (long)(2 * b) * DP * Np + o), t1 = ld4(A.tau + (long)(2 * b + 1) * DP * Np + o);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          part0 += (double)w0.v[n] * (double)y[n];
+          part1 += (double)w1.v[n] * (double)y[n];
+        }
+        if (MODE == MIX_FWD && A.out) {
+          if (A.inject) {
+            V4<T> ph = ld4(A.phi_next + fo + o);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) y[n] += ph.v[n];
           }
+          st4(A.out + fo + o, y);
+        }
+        if (MODE == MIX_DEEP && !LAST) st4(A.out + fo + o, y);
+        if (MODE == MIX_DEEP && LAST) st4(xs + ch * MIX_XS + 4 * j, y);  // dh for the slice conv
       }
     }
-  }
   if (MODE != MIX_TAU) {
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
     if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
   }
   __syncthreads();
-  if (MODE != MIX_TAU && threadIdx.x == 0) {
-    A.rho[2 * g] += red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    A.rho[2 * g + 1] += red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  double r0 = 0.0, r1 = 0.0;
+  if (MODE != MIX_TAU) {
+    for (int w = 0; w < nw; ++w) { r0 += red[0][w]; r1 += red[1][w]; }
   }
-  if (MODE == MIX_DEEP && LAST) {
-    // y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i'] on the W_L (<= SLICE_WIN) slice sites.
-    // Lane = channel, wave = quarter of the chain; the taps slide through a register window.
-    int loL = sg.x - A.L * A.w_c;
-    const int WL = sg.y + 2 * A.L * A.w_c + 1;
-    if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+  if (MODE != MIX_TAU && !(MODE == MIX_DEEP && LAST)) {
+    if (threadIdx.x == 0) { A.rho[2 * g] += r0; A.rho[2 * g + 1] += r1; }
+    return;
+  }
+  if (!(MODE == MIX_DEEP && LAST)) return;
+  // ---- last block: slice of the mixer output, y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i']
+  int loL = sg.x - A.L * A.w_c;
+  const int WL = sg.y + 2 * A.L * A.w_c + 1;
+  if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+  {
     const int c = lane;
-    const int q = (N + 3) / 4, ib = wave * q, ie = min(N, ib + q);
-    T acc[SLICE_WIN], win[SLICE_WIN];
+    T ya[SLICE_WIN], rg[SLICE_WIN];
 #pragma unroll
-    for (int t = 0; t < SLICE_WIN; ++t) acc[t] = 0;
-    if (c < DP) {
-      const T* tc = A.tapsL + (long)c * tap_stride(Np) + TO + loL;  // tc[t - i'] = g(loL + t - i')
+    for (int t = 0; t < SLICE_WIN; ++t) ya[t] = 0;
+    const int ib = 64 * wave, cnt = min(64, N - ib);
+    if (c < DP && cnt > 0) {
+      // rg[x mod 16] holds h(x) = g(loL + x); at chain site ib + k the window needs h(t - ib - k)
+      const T* tc = A.tapsL + (long)c * tap_stride(Np) + TO + loL - ib;  // tc[t - k] = h(t - ib - k)
 #pragma unroll
-      for (int t = 0; t < SLICE_WIN; ++t) win[t] = tc[t - ib];
-      for (int ip = ib; ip < ie; ++ip) {
-        const T v = xs[c * S + ip];
+      for (int t = 0; t < SLICE_WIN; ++t) rg[t] = tc[t];
+      const T* xr = xs + c * MIX_XS;
+      for (int k0 = 0; k0 < cnt; k0 += SLICE_WIN) {
 #pragma unroll
-        for (int t = 0; t < SLICE_WIN; ++t) acc[t] += win[t] * v;
+        for (int u = 0; u < SLICE_WIN; ++u) {
+          const int k = k0 + u;
+          if (k < cnt) {
+            const T v = xr[k];
 #pragma unroll
-        for (int t = SLICE_WIN - 1; t > 0; --t) win[t] = win[t - 1];
-        win[0] = tc[-(ip + 1)];
+            for (int t = 0; t < SLICE_WIN; ++t) ya[t] += rg[(t - u + SLICE_WIN * 4) % SLICE_WIN] * v;
+            rg[(SLICE_WIN * 4 - u - 1) % SLICE_WIN] = tc[-(k + 1)];
+          }
+        }
       }
     }
-    __syncthreads();  // every wave is done reading dh: reuse xs for the partial sums
+    __syncthreads();  // every wave is done with its dh tile: reuse the LDS for partial sums
+    T* part = reinterpret_cast<T*>(smem_raw);  // [nw][SLICE_WIN][DP]
     if (c < DP)
 #pragma unroll
-      for (int t = 0; t < SLICE_WIN; ++t) xs[(wave * SLICE_WIN + t) * DP + c] = acc[t];
+      for (int t = 0; t < SLICE_WIN; ++t) part[(wave * SLICE_WIN + t) * DP + c] = ya[t];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < WL * DP; idx += 256) {
-      const int t = idx / DP, cc = idx % DP;
-      T s = 0;
-      for (int w = 0; w < 4; ++w) s += xs[(w * SLICE_WIN + t) * DP + cc];
-      A.yL[((long)g * A.Wmax + t) * DP + cc] = s;
+  }
+  if (wave != 0) return;
+  // wave 0: e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on the slice, read-outs, log-ratio
+  T* part = reinterpret_cast<T*>(smem_raw);
+  T* Y = part + nw * SLICE_WIN * DP;  // [DP][16]: Y[c][t]
+  for (int idx = lane; idx < DP * SLICE_WIN; idx += 64) {
+    const int c = idx / SLICE_WIN, t = idx % SLICE_WIN;
+    T s = 0;
+    for (int w = 0; w < nw; ++w) s += part[(w * SLICE_WIN + t) * DP + c];
+    Y[c * SLICE_WIN + t] = (t < WL) ? s : T(0);
+  }
+  wave_sync();
+  const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
+  const T* Ut = A.tb.Ut + (long)(A.L - 1) * DP * DP;
+  acc_t a2[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    const T bvv = Y[kc * SLICE_WIN + j];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Vt[kc * DP + 16 * mt + j], bvv, a2[mt]);
+  }
+  const int t_me = j;  // this lane's slice position (matrix-core column)
+  int site = loL + t_me;
+  bool valid = t_me < WL;
+  if (A.periodic) { site %= N; }
+  else valid = valid && site >= 0 && site < N;
+  const long bL = (long)b * DP * Np;
+  const T* dchiL = A.dchi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP;
+  T* X2 = Y + DP * SLICE_WIN;  // [DP][16]
+  wave_sync();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ch = 16 * mt + M::row(lane, r);
+      T x = 0;
+      if (valid) x = dchiL[t_me * DP + ch] * (A.p0L[bL + (long)ch * Np + site] + a2[mt][r]);
+      X2[ch * SLICE_WIN + t_me] = x;
     }
+  wave_sync();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    const T bvv = X2[kc * SLICE_WIN + j];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Ut[kc * DP + 16 * mt + j], bvv, a2[mt]);
+  }
+  double o0 = 0.0, o1 = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        const long o = (long)ch * Np + site;
+        o0 += (double)A.tb.Wk[o] * (double)a2[mt][r];
+        o1 += (double)A.tb.Wk[(long)DP * Np + o] * (double)a2[mt][r];
+      }
+  }
+  // e^(0) = -2 s_j E on the cluster, read out directly (lanes over channels)
+  {
+    const int8_t* spb = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+    for (int q = 0; q < 2; ++q) {
+      const int js = q == 0 ? sg.z : sg.w;
+      if (js < 0) continue;
+      for (int c = lane; c < DP; c += 64) {
+        const double e0 = (double)(-2 * spb[js]) * (double)A.tb.E[c];
+        o0 += (double)A.tb.Wk[(long)c * Np + js] * e0;
+        o1 += (double)A.tb.Wk[(long)DP * Np + (long)c * Np + js] * e0;
+      }
+    }
+  }
+  o0 = wave_sum(o0);
+  o1 = wave_sum(o1);
+  if (lane == 0) {
+    const int bg = A.map.cb[A.cfg0 + g], m = A.map.cm[A.cfg0 + g];
+    const double d0 = A.rho[2 * g] + r0 + o0, d1 = A.rho[2 * g + 1] + r1 + o1;
+    A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], d0) + lcd_d(A.Om0[2 * bg + 1], d1);
   }
 }
 
@@ -625,7 +785,7 @@ template <typename T> struct TailArgs {
   const int8_t* spins;
   const int4* geom;
   const T* dchi;        // [F][L][Wmax][DP]
-  const T* yL;          // [F][Wmax][DP] (L >= 2)
+  const T* yL;          // unused: deep networks finish each flip in the last mixing launch
   const T* p0L;         // [Bc][DP][Np] p0 of block L
   const T* tau;         // [Bc][2][DP][Np]
   const T* taps1;       // block-1 taps (L == 1)
