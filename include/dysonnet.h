@@ -147,6 +147,18 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
                   int32_t B, int32_t M_max, double* logpsi, double* logratio, double* eloc,
                   void* stream);
 
+/* Per-sample log-derivatives O[b][p] = d log psi(s_b) / d theta_p for every raw parameter,
+ * the quantities variational Monte Carlo with stochastic reconfiguration consumes (Sec. VI).
+ * Hand-written reverse mode: a forward pass keeps layer-boundary checkpoints, each block is
+ * recomputed from its checkpoint while the adjoints flow back; the S4 parameters follow through
+ * the Jacobian of the Green's-function taps (float64, shared by all samples, rebuilt after each
+ * dn_model_set_params). grads: [B][P] in the model's field type (float for DN_PREC_FP32, double
+ * for DN_PREC_FP64), nullable (then kept in the workspace); logpsi [B] nullable; weights [B] and
+ * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open chains with
+ * inject_phi = 0 only (DN_EUNSUPPORTED otherwise). Synchronises the stream. */
+dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
+                         const double* weights, double* wsum, void* stream);
+
 /* Kernel classes of the per-launch profile. */
 typedef enum {
   DN_K_S4GEN = 0,    /* S4 taps (float64) */

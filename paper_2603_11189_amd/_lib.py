@@ -24,7 +24,8 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
-           "dn_eloc", "dn_profile_enable", "dn_profile_read", "dn_last_error", "dn_model_destroy")
+           "dn_eloc", "dn_grad_logpsi", "dn_profile_enable", "dn_profile_read", "dn_last_error",
+           "dn_model_destroy")
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
                 "eloc", "other")
 
@@ -68,6 +69,7 @@ def lib():
         L.dn_logratio.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp]
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
+        L.dn_grad_logpsi.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dn_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -76,7 +78,7 @@ def lib():
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
-                   "dn_profile_enable", "dn_profile_read"):
+                   "dn_grad_logpsi", "dn_profile_enable", "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -170,6 +172,18 @@ class Model:
                              _ptr(el), _stream()))
         return lp, lr, el
 
+
+    def grad_logpsi(self, spins: torch.Tensor, weights: torch.Tensor | None = None, want_grads: bool = True):
+        """(logpsi [B], grads [B, P] or None, wsum [P] or None) of d log psi / d theta per sample."""
+        B = spins.shape[0]
+        P = param_count(self.shape)
+        dt = torch.float64 if self.prec == "fp64" else torch.float32
+        lp = torch.empty(B, dtype=torch.float64, device=spins.device)
+        g = torch.empty((B, P), dtype=dt, device=spins.device) if want_grads else None
+        ws = torch.empty(P, dtype=torch.float64, device=spins.device) if weights is not None else None
+        w = weights.to(torch.float64).contiguous() if weights is not None else None
+        _check(lib().dn_grad_logpsi(self.handle, _ptr(spins), B, _ptr(lp), _ptr(g), _ptr(w), _ptr(ws), _stream()))
+        return lp, g, ws
 
     def profile_enable(self, on: bool = True):
         _check(lib().dn_profile_enable(self.handle, int(on)))

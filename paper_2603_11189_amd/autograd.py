@@ -1,0 +1,33 @@
+"""torch.autograd.Function over the library's log psi and its hand-written backward.
+
+``logpsi(model, params, spins)`` returns log psi(s_b) for every sample; its backward returns
+d loss / d params = sum_b (d loss / d log psi_b) * O[b, :], where O are the per-sample
+log-derivatives computed by dn_grad_logpsi (the contraction with the incoming gradient runs
+in the library's kernels). The spins carry no gradient.
+"""
+from __future__ import annotations
+
+import torch
+
+from ._lib import Model
+
+
+class _LogPsi(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, spins: torch.Tensor, model: Model):
+        model.set_params(params.detach().to(torch.float64))
+        out = model.logpsi(spins)
+        ctx.model = model
+        ctx.save_for_backward(spins)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        (spins,) = ctx.saved_tensors
+        _, _, wsum = ctx.model.grad_logpsi(spins, weights=grad_out.detach(), want_grads=False)
+        return wsum, None, None
+
+
+def logpsi(model: Model, params: torch.Tensor, spins: torch.Tensor) -> torch.Tensor:
+    """log psi(s) [B] (float64), differentiable with respect to the flat parameter vector."""
+    return _LogPsi.apply(params, spins, model)

@@ -18,6 +18,7 @@
 #include "ham.h"
 #include "kernels.h"
 #include "s4gen.h"
+#include "grad.h"
 
 using namespace dn;
 
@@ -64,7 +65,7 @@ bool layout_of(const dn_model_desc& d, Layout* lo) {
 template <typename T> struct TableBufs {
   std::vector<void*> owned;
   Tables<T> tb{};
-  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk;
+  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk, *ADm, *WDm;
 };
 
 struct ProfRec {
@@ -109,8 +110,14 @@ struct dn_model {
   TableBufs<float> t32;
   Workspace ws;
   Prof prof;
+  // S4 tap Jacobian (float64 master + float32 copy), valid for the current parameters
+  bool have_jac = false;
+  double* jac64 = nullptr;
+  float* jac32 = nullptr;
   std::vector<void*> owned;
   ~dn_model() {
+    if (jac64) (void)hipFree(jac64);
+    if (jac32) (void)hipFree(jac32);
     for (void* p : owned) (void)hipFree(p);
     for (void* p : t64.owned) (void)hipFree(p);
     for (void* p : t32.owned) (void)hipFree(p);
@@ -195,16 +202,17 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
             get(&tb.ADt, L * DP * DP) && get(&tb.Ut, L * DP * DP) && get(&tb.Vt, L * DP * DP) &&
             get(&tb.Um, L * DP * DP) && get(&tb.Vm, L * DP * DP) && get(&tb.wv, L * DP) &&
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
-            get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, DP * tap_stride(Np)) && get(&tb.Wk, 2 * DP * Np);
+            get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, L * DP * tap_stride(Np)) &&
+            get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP);
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
-                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk};
+                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm};
   return DN_OK;
 }
 
 long table_elems(const dn_model& m) {
   const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
-  return 3 * DP + 6 * L * DP * DP + 3 * L * DP + L * Wc * DP + (L + 1) * DP * tap_stride(Np) + 2 * DP * Np;
+  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + 2 * L * DP * tap_stride(Np) + 2 * DP * Np;
 }
 
 // Copy double tables into float tables (same member order).
@@ -217,7 +225,8 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
       {a.ADt, b.ADt, L * DP * DP}, {a.Ut, b.Ut, L * DP * DP}, {a.Vt, b.Vt, L * DP * DP},
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
-      {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np}};
+      {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, L * DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np},
+      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
     convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);
@@ -316,9 +325,15 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, in
 // Forward of C configurations listed by `map` entries [cfg0, cfg0+C). rho[C][2] receives
 // Omega. With caches (ABACUS background), a/chi/p0 of every block are written layer-major
 // [L][C][DP][Np].
+// Checkpoints of the gradient forward: h^(l) for l = 0..L-1 and phi^(l) for l = 1..L-1
+// ([L][C][DP][Np] each, phi slot 0 unused) and the residual sum R ([C][DP][Np]).
+template <typename T> struct Ckpt {
+  T *h = nullptr, *phi = nullptr, *R = nullptr;
+};
+
 template <typename T, int DP>
 dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, int C, double* rho,
-                        T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st) {
+                        T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st, Ckpt<T> ck = Ckpt<T>()) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L;
   const long fld = (long)C * DP * Np;
@@ -342,18 +357,22 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
     a.phi_out = (l + 1 < L || d.inject_phi) ? phi : nullptr;
     a.chi_out = chi_of(l);
     a.a_out = cache_a ? cache_a + (long)l * fld : nullptr;
-    a.u_out = u; a.rho = rho;
+    a.u_out = ck.h ? ck.h : u; a.rho = rho; a.R_out = ck.R;
+    if (ck.phi && l >= 1) a.phi_in = ck.phi + (long)l * fld;       // phi^(l) checkpoint (block l+1 reads it)
+    if (ck.phi && l + 1 < L) a.phi_out = ck.phi + (long)(l + 1) * fld;
     return launch_phi<T, DP>(m, a, C, st);
   };
   STCHK(phi_pass(0));
   for (int l = 0; l < L; ++l) {
-    STCHK(launch_conv<T>(m, u, v, tb.taps + (long)l * DP * tap_stride(Np), C, st));
+    const T* hin = ck.h ? ck.h + (long)l * fld : u;
+    STCHK(launch_conv<T>(m, hin, v, tb.taps + (long)l * DP * tap_stride(Np), C, st));
     if (l + 1 < L) STCHK(phi_pass(l + 1));
     MixArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = d.w_c;
     a.periodic = d.bc == DN_BC_PERIODIC; a.inject = d.inject_phi; a.C = C; a.cfg0 = cfg0;
     a.X = v; a.chi = chi_of(l); a.p0_out = cache_p0 ? cache_p0 + (long)l * fld : nullptr;
-    a.phi_next = phi; a.out = (l + 1 < L) ? u : nullptr; a.rho = rho;
+    a.phi_next = phi; a.out = (l + 1 < L) ? (ck.h ? ck.h + (long)(l + 1) * fld : u) : nullptr; a.rho = rho;
+    a.R_acc = ck.R;
     STCHK((launch_mix<T, DP, MIX_FWD, false, false>(m, a, C, st)));
   }
   return DN_OK;
@@ -460,7 +479,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
       a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bc; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
       STCHK((launch_mix<T, DP, MIX_TAU, false, false>(m, a, 2 * Bc, st, Bc)));
-      STCHK(launch_conv<T>(m, tz, tau, tb.tapsR, 2 * Bc, st));
+      STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bc, st));
     }
     if (F == 0) continue;
     void *pdchi, *pgeom, *prho, *pdu, *pw;
@@ -551,6 +570,216 @@ dn_status logpsi_only(dn_model* m, const int8_t* spins, int B, double* logpsi, h
   HIPCHK(hipStreamSynchronize(st));
   return DN_OK;
 }
+
+// ------------------------------------------------------------------------------------------
+// Per-sample log-derivatives (hand-written reverse mode with layer-boundary checkpoints).
+
+dn_status ensure_jac(dn_model* m, hipStream_t st) {
+  if (m->have_jac) return DN_OK;
+  const dn_model_desc& d = m->desc;
+  const long nch = (long)(d.L + 1) * d.d, TG = 2L * d.N - 1, NP = 12L * d.s + 1;
+  const long n = nch * TG * NP;
+  if (!m->jac64 && hipMalloc(&m->jac64, n * sizeof(double)) != hipSuccess)
+    return fail(DN_ENOMEM, "hipMalloc failed for the S4 tap Jacobian");
+  if (d.prec != DN_PREC_FP64 && !m->jac32 && hipMalloc(&m->jac32, n * sizeof(float)) != hipSuccess)
+    return fail(DN_ENOMEM, "hipMalloc failed for the S4 tap Jacobian");
+  void* pws;
+  const long per = 2L * (2L * d.s * d.s + d.s + 5L * d.N * d.s);
+  STCHK(ws_get(m, "jac_ws", (size_t)nch * per * sizeof(double), &pws));
+  {
+    PScope ps(m, DN_K_S4GEN, st, 8.0 * nch * (double)d.N * d.s * d.s * 6, (double)n * 8);
+    s4jac_prep_kernel<<<nch, S4_THREADS, 0, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws, m->jac64);
+    s4jac_dir_kernel<<<dim3(nch, 12 * d.s), 256, 3 * (size_t)d.N * sizeof(cx), st>>>(
+        m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws, m->jac64);
+  }
+  if (d.prec != DN_PREC_FP64) convert_kernel<<<1024, 256, 0, st>>>(m->jac64, m->jac32, n);
+  HIPCHK(hipGetLastError());
+  m->have_jac = true;
+  return DN_OK;
+}
+
+template <typename T> const T* jac_of(dn_model* m);
+template <> const double* jac_of<double>(dn_model* m) { return m->jac64; }
+template <> const float* jac_of<float>(dn_model* m) { return m->jac32; }
+
+template <typename T, int DP>
+dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int Bc, double* logpsi, T* grads,
+                     hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  const int N = d.N, Np = m->Np, L = d.L, wc = d.w_c, dd = d.d, Wc = 2 * wc + 1;
+  const long fld = (long)Bc * DP * Np;
+  const long Pn = m->lay.P;
+  const long lay = 4L * dd * dd + 3L * dd + (long)Wc * dd;
+  const int TG = 2 * N - 1, NPc = 12 * d.s + 1, nmix = L + 1;
+  const Tables<T>& tb = tables_of<T>(m);
+  auto field = [&](const char* name, long nfields, T** out) -> dn_status {
+    void* p;
+    STCHK(ws_get(m, name, (size_t)nfields * fld * sizeof(T), &p));
+    *out = (T*)p;
+    return DN_OK;
+  };
+  T *ckh, *ckphi, *R, *ta, *tphi, *tchi, *tz, *tzeta, *tv, *tq, *dh, *dq, *dchi, *dv, *du[2], *dzeta, *dz, *da, *dph[2];
+  STCHK(field("g_ckh", L, &ckh));
+  STCHK(field("g_ckphi", L, &ckphi));
+  STCHK(field("g_R", 1, &R));
+  T* tmp;
+  STCHK(field("g_tmp", 18, &tmp));
+  T** slots[] = {&ta, &tphi, &tchi, &tz, &tzeta, &tv, &tq, &dh, &dq, &dchi, &dv, &du[0], &du[1], &dzeta, &dz, &da, &dph[0], &dph[1]};
+  for (int i = 0; i < 18; ++i) *slots[i] = tmp + i * fld;
+  void *prho, *prho2, *pdom, *pdg;
+  STCHK(ws_get(m, "g_rho", (size_t)Bc * 2 * sizeof(double), &prho));
+  STCHK(ws_get(m, "g_rho2", (size_t)Bc * 2 * sizeof(double), &prho2));
+  STCHK(ws_get(m, "g_dom", (size_t)Bc * 2 * sizeof(double), &pdom));
+  STCHK(ws_get(m, "g_dg", (size_t)Bc * nmix * dd * TG * sizeof(T), &pdg));
+  double *rho = (double*)prho, *rho2 = (double*)prho2, *dOm = (double*)pdom;
+  T* dg = (T*)pdg;
+  // forward with checkpoints
+  Ckpt<T> ck;
+  ck.h = ckh; ck.phi = ckphi; ck.R = R;
+  STCHK((forward_chunk<T, DP>(m, spins, idmap, b0, Bc, rho, nullptr, nullptr, nullptr, st, ck)));
+  if (logpsi) logpsi_kernel<<<(Bc + 255) / 256, 256, 0, st>>>(rho, nullptr, Bc, logpsi + b0);
+  // read-out: dOmega, dA and the final mixer's tap gradients
+  {
+    ReadoutGradArgs<T> a{R, rho, m->omega, m->A64, N, Np, dd, DP, nmix, grads, Pn, m->lay.off_A, dg, dOm};
+    PScope ps(m, DN_K_OTHER, st, 4.0 * Bc * dd * (double)N, (double)fld * sizeof(T));
+    readout_grad_kernel<T><<<dim3(Bc, dd), 256, (size_t)(Np + 1) * sizeof(double), st>>>(a);
+  }
+  auto outer = [&](const T* P, const T* Q1, const T* Q2, const T* emb, long off) {
+    OuterArgs<T> a{P, Q1, Q2, emb, spins, b0, N, Np, dd, DP, grads, Pn, off};
+    PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * dd * dd * (double)N, 2.0 * fld * sizeof(T));
+    outer_kernel<T, DP><<<Bc, 256, 0, st>>>(a);
+  };
+  auto rowdot = [&](const T* P, const T* Q, int use_spins, int shift0, int nshift, long off, const double* dom) {
+    RowdotArgs<T> a{P, Q, spins, use_spins, b0, N, Np, dd, DP, d.bc == DN_BC_PERIODIC, shift0, nshift, grads, Pn,
+                    off, 0, dom ? tb.Wk : nullptr, dom};
+    rowdot_kernel<T><<<dim3(Bc, dd), 64, 0, st>>>(a);
+  };
+  T* du_next = nullptr;
+  T* dph_next = nullptr;
+  int flip = 0;
+  for (int l = L; l >= 1; --l) {
+    const int tl = l - 1;
+    const long base = 2L * dd + (long)tl * lay;
+    const long offWD = base, offw = base + dd * dd, offK = offw + dd, offk = offK + (long)Wc * dd,
+               offAD = offk + dd, offb = offAD + (long)dd * dd, offU = offb + dd, offV = offU + (long)dd * dd;
+    // recompute block l from its checkpoints
+    {
+      PhiArgs<T> a{};
+      a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC; a.act = d.act;
+      a.inject = 0; a.first = (l == 1); a.spins = spins; a.map = idmap; a.cfg0 = b0; a.C = Bc;
+      a.phi_in = (l >= 2) ? ckphi + (long)(l - 1) * fld : nullptr;
+      a.phi_out = tphi; a.chi_out = tchi; a.a_out = ta; a.u_out = tq; a.rho = rho2;
+      a.z_out = tz; a.zeta_out = tzeta;
+      STCHK((launch_phi<T, DP>(m, a, Bc, st)));
+    }
+    STCHK(launch_conv<T>(m, ckh + (long)tl * fld, tv, tb.taps + (long)tl * DP * tap_stride(Np), Bc, st));
+    {
+      MixArgs<T> a{};
+      a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
+      a.C = Bc; a.cfg0 = b0; a.X = tv; a.chi = tchi; a.p0_out = tq; a.out = nullptr; a.rho = rho2;
+      STCHK((launch_mix<T, DP, MIX_FWD, false, false>(m, a, Bc, st)));
+    }
+    // vertex and channel mixing backward
+    {
+      MixBwdArgs<T> a{tb.Um + (long)tl * DP * DP, tb.Vm + (long)tl * DP * DP, tb.Wk, N, Np, du_next, dOm,
+                      tchi, tq, dh, dq, dchi, dv};
+      const int nw = Np / 64;
+      const size_t lds = (size_t)nw * DP * MIX_XS * sizeof(T);
+      allow_lds(mixbwd_kernel<T, DP>, lds);
+      PScope ps(m, DN_K_OTHER, st, 4.0 * Bc * (double)N * dd * dd, 6.0 * fld * sizeof(T));
+      mixbwd_kernel<T, DP><<<Bc, 64 * nw, lds, st>>>(a);
+    }
+    outer(dh, tchi, tq, nullptr, offU);
+    outer(dq, tv, nullptr, nullptr, offV);
+    {
+      TapGradArgs<T> a{dv, ckh + (long)tl * fld, N, Np, dd, DP, dg, tl, nmix};
+      PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * dd * (double)N * N, 2.0 * fld * sizeof(T));
+      tapgrad_kernel<T><<<dim3(Bc, dd), 256, 2 * (size_t)Np * sizeof(T), st>>>(a);
+    }
+    T* du_cur = du[flip];
+    STCHK(launch_conv<T>(m, dv, du_cur, tb.tapsR + (long)tl * DP * tap_stride(Np), Bc, st));
+    // phi stream backward
+    T* dph_cur = dph[flip];
+    {
+      PhiBwdArgs<T> a{tb.ADm + (long)tl * DP * DP, tb.WDm + (long)tl * DP * DP, tb.Kc + (long)tl * Wc * DP,
+                      N, Np, wc, d.bc == DN_BC_PERIODIC, d.act, dchi, tzeta, tz, dph_next, dzeta, dz, da, dph_cur};
+      const size_t lds = (size_t)DP * (Np + 2 * wc + 1) * sizeof(T);
+      PScope ps(m, DN_K_OTHER, st, 4.0 * Bc * (double)N * dd * dd, 7.0 * fld * sizeof(T));
+      if constexpr (std::is_same<T, double>::value) {
+        allow_lds(phibwd_kernel<T, DP, 1>, lds);
+        phibwd_kernel<T, DP, 1><<<Bc, 256, lds, st>>>(a);
+      } else {
+        switch (tiles_per_wave(Np)) {
+          case 1: allow_lds(phibwd_kernel<T, DP, 1>, lds); phibwd_kernel<T, DP, 1><<<Bc, 256, lds, st>>>(a); break;
+          case 2: allow_lds(phibwd_kernel<T, DP, 2>, lds); phibwd_kernel<T, DP, 2><<<Bc, 256, lds, st>>>(a); break;
+          case 3: allow_lds(phibwd_kernel<T, DP, 3>, lds); phibwd_kernel<T, DP, 3><<<Bc, 256, lds, st>>>(a); break;
+          default: allow_lds(phibwd_kernel<T, DP, 4>, lds); phibwd_kernel<T, DP, 4><<<Bc, 256, lds, st>>>(a); break;
+        }
+      }
+    }
+    outer(dzeta, tphi, nullptr, nullptr, offAD);
+    if (l >= 2) outer(da, ckphi + (long)(l - 1) * fld, nullptr, nullptr, offWD);
+    else outer(da, nullptr, nullptr, tb.Ephi, offWD);
+    rowdot(dzeta, nullptr, 0, 0, 1, offb, nullptr);
+    rowdot(dz, nullptr, 0, 0, 1, offk, nullptr);
+    rowdot(da, nullptr, 0, 0, 1, offw, nullptr);
+    rowdot(dz, ta, 0, -wc, Wc, offK, nullptr);
+    du_next = du_cur;
+    dph_next = dph_cur;
+    flip ^= 1;
+  }
+  rowdot(du_next, nullptr, 1, 0, 1, 0, dOm);  // dE: h^(0) = E s gets du^(1) + the read-out adjoint
+  rowdot(dph_next, nullptr, 1, 0, 1, dd, nullptr);  // dE_phi: phi^(0) = E_phi s
+  {
+    S4GradArgs<T> a{dg, jac_of<T>(m), Bc, nmix * dd, TG, NPc, grads, Pn, m->lay.off_s4};
+    PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * nmix * dd * (double)TG * NPc, (double)Bc * nmix * dd * TG * sizeof(T));
+    s4grad_kernel<T><<<dim3(nmix * dd, (Bc + 63) / 64, (NPc + 63) / 64), 256, 0, st>>>(a);
+  }
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+template <typename T, int DP>
+dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, void* grads_out, const double* w,
+                      double* wsum, hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  if (d.bc != DN_BC_OPEN) return fail(DN_EUNSUPPORTED, "per-sample gradients are implemented for open chains only");
+  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "per-sample gradients need inject_phi = 0");
+  STCHK(ensure_jac(m, st));
+  T* grads = (T*)grads_out;
+  const long Pn = m->lay.P;
+  if (!grads) {
+    void* p;
+    STCHK(ws_get(m, "g_out", (size_t)B * Pn * sizeof(T), &p));
+    grads = (T*)p;
+  }
+  void *pib, *pim;
+  STCHK(ws_get(m, "g_idb", (size_t)B * 4, &pib));
+  STCHK(ws_get(m, "g_idm", (size_t)B * 4, &pim));
+  std::vector<int32_t> iota(B), neg(B, -1);
+  for (int b = 0; b < B; ++b) iota[b] = b;
+  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, nullptr, 0};
+  const size_t per = (size_t)DP * m->Np * sizeof(T) * (2 * d.L + 19) +
+                     (size_t)(d.L + 1) * d.d * (2 * d.N - 1) * sizeof(T);
+  const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)2 << 30) / per));
+  for (int b0 = 0; b0 < B; b0 += Bc_max) {
+    const int Bc = std::min(Bc_max, B - b0);
+    STCHK((grad_chunk<T, DP>(m, spins, idmap, b0, Bc, logpsi, grads + (long)b0 * Pn, st)));
+  }
+  if (w && wsum) wsum_kernel<T><<<(int)std::min<long>(4096, (Pn + 255) / 256), 256, 0, st>>>(grads, w, B, Pn, wsum);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));  // the host iota buffers must outlive the copies
+  return DN_OK;
+}
+
+template <typename T, int DP> struct RunGrad {
+  static dn_status run(dn_model* m, const int8_t* s, int B, double* lp, void* g, const double* w, double* ws,
+                       hipStream_t st) {
+    return grad_logpsi<T, DP>(m, s, B, lp, g, w, ws, st);
+  }
+};
 
 // Dispatch on element type and padded width.
 template <template <typename, int> class F, typename... Args>
@@ -671,7 +900,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   TableBufs<double>& t = m->t64;
   a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
   a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;
-  a.tapsR = t.tapsR; a.omega = m->omega; a.Wk = t.Wk; a.A = m->A64;
+  a.tapsR = t.tapsR; a.omega = m->omega; a.Wk = t.Wk; a.A = m->A64; a.ADm = t.ADm; a.WDm = t.WDm;
   {
     PScope ps(m, DN_K_PREP, st, 0.0, (double)table_elems(*m) * 8);
     prep_kernel<<<256, 256, 0, st>>>(a);
@@ -688,6 +917,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   HIPCHK(hipStreamSynchronize(st));
   if (hbad) return fail(DN_EINVAL, "Green's-function taps are not finite (unstable state matrix?)");
   m->have_params = true;
+  m->have_jac = false;
   return DN_OK;
 }
 
@@ -788,6 +1018,17 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
   STCHK(dn_logratio(m, path, spins, B, (int32_t*)ps, (int32_t*)pn, M_max, logpsi, logratio, stream));
   PScope e(m, DN_K_ELOC, st, 3.0 * B * M_max, (double)B * M_max * 16.0 + B * 20.0);
   return dn_local_energy((double*)pd, (double*)ph, (int32_t*)pn, logratio, B, M_max, eloc, stream);
+}
+
+dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
+                         const double* weights, double* wsum, void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0) return fail(DN_EINVAL, "B < 0");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if (B == 0) return DN_OK;
+  if (!spins) return fail(DN_EINVAL, "null spins");
+  if ((weights == nullptr) != (wsum == nullptr)) return fail(DN_EINVAL, "weights and wsum go together");
+  return dispatch<RunGrad>(m, spins, (int)B, logpsi, grads, weights, wsum, (hipStream_t)stream);
 }
 
 dn_status dn_profile_enable(dn_model* m, int enable) {

@@ -12,10 +12,11 @@ namespace dn {
 
 template <typename T> struct Tables {
   const T *E, *Ephi, *wE1;
-  const T *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP]
+  const T *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP] operand tables (row = input channel)
   const T *wv, *Kc, *kv, *bv;              // [L][DP], K [L][2w_c+1][DP]
-  const T *taps, *tapsR;                   // [L][DP][2Np], [DP][2Np]
+  const T *taps, *tapsR;                   // [L][DP][tap_stride]: mixers and their transposes
   const T *Wk;                             // [2][DP][Np]
+  const T *ADm, *WDm;                      // operand tables of A_D^T and W_D^T
 };
 
 // Which configuration a block works on. Plain path: cfg g -> sample b, element m (m = -1
@@ -84,6 +85,9 @@ template <typename T> struct PhiArgs {
   T* a_out;             // cache, nullable
   T* u_out;             // first block only
   double* rho;          // first block only: [C][2]
+  T* z_out;             // pre-activation of phi (nullable)
+  T* zeta_out;          // pre-activation of chi (nullable)
+  T* R_out;             // first block: residual sum initialised with h^(0) (nullable)
 };
 
 template <typename T, int DP, int NT>
@@ -173,10 +177,14 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
         T s = A.tb.kv[l * DP + kc];
         for (int r = -wc; r <= wc; ++r) s += Kc[(r + wc) * DP + kc] * as[kc * ld + i + r + wc];
         ph = act_fn<T>(A.act, s);
+        if (A.z_out) A.z_out[fo + (long)kc * Np + i] = s;
+      } else if (A.z_out) {
+        A.z_out[fo + (long)kc * Np + i] = T(0);
       }
       if (A.phi_out) A.phi_out[fo + (long)kc * Np + i] = ph;
       if (A.first) {
         T h0 = (i < N) ? A.tb.E[kc] * sp_s[i] : T(0);
+        if (A.R_out) A.R_out[fo + (long)kc * Np + i] = h0;
         A.u_out[fo + (long)kc * Np + i] = h0 + (A.inject ? ph : T(0));
         part0 += (double)A.tb.Wk[(long)kc * Np + i] * (double)h0;
         part1 += (double)A.tb.Wk[(long)(DP + kc) * Np + i] * (double)h0;
@@ -192,8 +200,10 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ch = 16 * mt + M::row(lane, r);
-          T v = (i < N) ? act_fn<T>(A.act, acc[mt][n][r] + A.tb.bv[l * DP + ch]) : T(0);
+          const T zt = acc[mt][n][r] + A.tb.bv[l * DP + ch];
+          T v = (i < N) ? act_fn<T>(A.act, zt) : T(0);
           A.chi_out[fo + (long)ch * Np + i] = v;
+          if (A.zeta_out) A.zeta_out[fo + (long)ch * Np + i] = (i < N) ? zt : T(0);
         }
     }
   }
@@ -318,6 +328,7 @@ template <typename T> struct MixArgs {
   const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
   T* out;                // [C][DP][Np] (unused for DEEP LAST)
   double* rho;           // [C][2] accumulated (FWD, DEEP)
+  T* R_acc;              // FWD: residual sum R += h (nullable)
   // DEEP
   CfgMap map;            // flip -> (b, m)
   int b0;                // first sample of the chunk (caches are chunk-local)
@@ -510,6 +521,12 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
         for (int n = 0; n < 4; ++n) {
           part0 += (double)w0.v[n] * (double)y[n];
           part1 += (double)w1.v[n] * (double)y[n];
+        }
+        if (MODE == MIX_FWD && A.R_acc) {
+          V4<T> rr = ld4(A.R_acc + fo + o);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) rr.v[n] += y[n];
+          st4(A.R_acc + fo + o, rr.v);
         }
         if (MODE == MIX_FWD && A.out) {
           if (A.inject) {

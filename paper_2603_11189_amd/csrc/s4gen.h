@@ -205,8 +205,9 @@ struct PrepArgs {
   double *E, *Ephi, *wE1;
   double *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP]; *t transposed (t[k][m] = M[m][k])
   double *wv, *Kc, *kv, *bv;               // [L][DP], K: [L][2w_c+1][DP]
-  double *taps, *tapsR;                    // [L][DP][TS], transposed mixer of block L: [DP][TS]
+  double *taps, *tapsR;                    // [L][DP][TS] mixers and their transposes
   double *omega, *Wk, *A;                  // [DP][Np], [2][DP][Np], [DP][2]
+  double *ADm, *WDm;                       // operand tables of A_D^T, W_D^T
 };
 
 __global__ void prep_kernel(PrepArgs a) {
@@ -241,6 +242,8 @@ __global__ void prep_kernel(PrepArgs a) {
     a.Vt[idx] = in ? V[col * d + row] : 0.0;
     a.Um[idx] = in ? U[row * d + col] : 0.0;
     a.Vm[idx] = in ? V[row * d + col] : 0.0;
+    a.ADm[idx] = in ? AD[row * d + col] : 0.0;
+    a.WDm[idx] = in ? WD[row * d + col] : 0.0;
   }
   for (long idx = tid; idx < (long)L * DP; idx += nth) {
     int l = idx / DP, c = idx % DP;
@@ -262,7 +265,7 @@ __global__ void prep_kernel(PrepArgs a) {
     int l = idx / ((long)DP * TS), c = (idx / TS) % DP, q = idx % TS;
     int r = q - TO;
     a.taps[idx] = (c < d) ? tap(l, c, r) : 0.0;
-    if (l == L - 1) a.tapsR[(long)c * TS + q] = (c < d) ? tap(l, c, -r) : 0.0;  // transposed mixer
+    a.tapsR[idx] = (c < d) ? tap(l, c, -r) : 0.0;  // transposed mixer
   }
   for (long idx = tid; idx < (long)DP * Np; idx += nth) {
     int c = idx / Np, i = idx % Np;
