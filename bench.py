@@ -8,6 +8,10 @@ work (S4 taps and tables) happens once per parameter update and is reported sepa
 The default workload is the long-range Ising chain with N=256, four blocks, d=64, state 32,
 2048 samples, FP32 (alpha=2, h=0.5). One JSON line is printed.
 
+With --workload ragged32 it measures the ragged batch instead: 32 instances of different
+chain lengths, depths and batch sizes (one model each) submitted together as one recorded
+HIP graph; a step is one pass over all 37011 samples.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
@@ -125,6 +129,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the per-sample log-derivative leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
@@ -148,6 +153,9 @@ def main():
     import dn_inputs as di
     from paper_2603_11189_amd import _lib as L
 
+    if args.workload == "ragged32":
+        bench_ragged(args)
+        return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
     prec = w.prec if w.prec != "bf16" else "fp32"
@@ -194,6 +202,24 @@ def main():
         results[path] = {"sec": el, "prof": prof}
         log(f"[bench] {path}: {el / args.steps * 1e3:.2f} ms/step, {B * args.steps / el:.1f} samples/s")
 
+    grad = None
+    if not args.no_grad and shape.bc == "open" and not shape.inject_phi:
+        # per-sample log-derivatives of the same batch (the consumer of E_loc in a VMC step)
+        log(f"[bench] {args.workload} per-sample gradients")
+        for _ in range(max(1, args.warmup)):
+            model.grad_logpsi(spins)
+        torch.cuda.synchronize()
+        g_steps = max(1, min(args.steps, 5))
+        t0 = time.perf_counter()
+        for _ in range(g_steps):
+            _, g, _ = model.grad_logpsi(spins)
+            del g
+        torch.cuda.synchronize()
+        gsec = (time.perf_counter() - t0) / g_steps
+        grad = {"ms_per_step": gsec * 1e3, "samples_per_s": B / gsec, "steps": g_steps,
+                "params_per_sample": L.param_count(shape), "dtype": "f32" if prec == "fp32" else "f64"}
+        log(f"[bench] gradients: {gsec * 1e3:.2f} ms/step")
+
     main_path = "abacus" if "abacus" in results else list(results)[0]
     el = results[main_path]["sec"]
     value = B * args.steps / el
@@ -217,6 +243,9 @@ def main():
                    "path": main_path},
         "set_params_ms": set_params_ms,
     }
+    if grad:
+        out["grad_logpsi"] = grad
+        out["eloc_plus_grad_samples_per_s"] = B / (el / args.steps + grad["ms_per_step"] * 1e-3)
     if "full" in results and main_path != "full":
         fv = B * args.steps / results["full"]["sec"]
         out["full_reeval"] = {"value": fv, "ms_per_step": results["full"]["sec"] / args.steps * 1e3}
@@ -277,6 +306,115 @@ def main():
         out["err_vs_fp64_oracle"] = {
             p: {k: (errs[p][k] / ref_mag[k] if ref_mag[k] > 0 else 0.0) for k in errs[p]} for p in results}
         out["err_vs_fp64_oracle"]["measure"] = "max|x - x*| / max|x*| over the CPU sample"
+    print(json.dumps(out), flush=True)
+
+
+def bench_ragged(args) -> None:
+    """The ragged batch: 32 instances in one recorded graph, against per-instance calls."""
+    import torch
+
+    import dn_inputs as di
+    from paper_2603_11189_amd import _lib as L
+
+    ws = di.ragged_instances()
+    dev = torch.device("cuda")
+    torch.cuda.init()
+    L.lib()
+    models, thetas, spins, lps, els = [], [], [], [], []
+    for w in ws:
+        th = torch.tensor(w.params(args.scale))
+        m = L.Model(w.model, "fp32")
+        m.set_params(th)
+        models.append(m)
+        thetas.append(th)
+        spins.append(torch.tensor(w.spin_batch(), device=dev))
+        lps.append(torch.empty(w.B, dtype=torch.float64, device=dev))
+        els.append(torch.empty(w.B, dtype=torch.float64, device=dev))
+    hams = [w.ham for w in ws]
+    Btot = sum(w.B for w in ws)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    graph = lambda: L.ragged_eloc(models, hams, spins, lps, els, n_streams=4, mode="graph")
+    log(f"[bench] ragged32: {len(ws)} instances, {Btot} samples; recording + warmup {args.warmup}")
+    for _ in range(max(1, args.warmup)):
+        graph()
+    sec = timed(graph, args.steps)
+    log(f"[bench] ragged32 graph: {sec * 1e3:.1f} ms/step, {Btot / sec:.1f} samples/s")
+    eager = lambda: L.ragged_eloc(models, hams, spins, lps, els, n_streams=4, mode="eager")
+    eager()
+    sec_eager = timed(eager, max(1, args.steps // 2))
+    log(f"[bench] ragged32 eager 4 streams: {sec_eager * 1e3:.1f} ms/step")
+    bufs = [(lps[i], torch.empty((w.B, w.model.N), dtype=torch.float64, device=dev), els[i])
+            for i, w in enumerate(ws)]
+
+    def per_instance():
+        for i, w in enumerate(ws):
+            models[i].eloc(w.ham, spins[i], w.model.N, path="abacus", out=bufs[i])
+
+    per_instance()
+    sec_seq = timed(per_instance, max(1, args.steps // 2))
+    log(f"[bench] ragged32 per-instance calls: {sec_seq * 1e3:.1f} ms/step")
+    out = {
+        "metric": "E_loc samples/sec, ragged batch of 32 instances, ABACUS",
+        "value": Btot / sec, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ragged32", "instances": len(ws), "N": "U{32..512}", "L": "U{2,3,4}",
+                   "B": "U{256..2048}", "samples": Btot, "d": 64, "s": 32,
+                   "hamiltonian": "lrtfim open J=1 alpha=3 h=1", "submission": "one HIP graph, 4 streams"},
+        "eager_4_streams": {"ms_per_step": sec_eager * 1e3, "value": Btot / sec_eager},
+        "per_instance_calls": {"ms_per_step": sec_seq * 1e3, "value": Btot / sec_seq},
+    }
+    if not args.no_profile:
+        # kernel classes from one eager pass on one stream, bracketed by events per launch
+        for m in models:
+            m.profile_enable(True)
+        L.ragged_eloc(models, hams, spins, lps, els, n_streams=1, mode="eager")
+        torch.cuda.synchronize()
+        tot = {}
+        for m in models:
+            for k, (ms, n, fl, by) in m.profile_read().items():
+                t = tot.setdefault(k, [0.0, 0, 0.0, 0.0])
+                t[0] += ms; t[1] += n; t[2] += fl; t[3] += by
+            m.profile_enable(False)
+        dom = max(tot, key=lambda k: tot[k][0])
+        ms, n, fl, by = tot[dom]
+        achieved = fl / (ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK["fp32"],
+                           "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
+                           "avg_launch_ms": ms / n, "algorithmic_flops_per_launch": fl / n,
+                           "measured_on": "one eager pass on one stream (graph replays record no events)"}
+        out["per_kernel"] = {k: {"ms_per_step": v[0], "launches_per_step": v[1],
+                                 "tflops": v[2] / (v[0] * 1e-3) / 1e12 if v[0] > 0 else None}
+                             for k, v in tot.items() if v[1]}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle.model import ModelDesc
+        t0 = time.perf_counter()
+        done, err, mag = 0, 0.0, 0.0
+        gpu = [e.cpu() for e in els]
+        i = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and i < len(ws):
+            w = ws[i]
+            sp = spins[i][:1].cpu().numpy()
+            ref = O.eloc_plain(ModelDesc.of(w.model), w.ham, thetas[i], sp, w.model.N)
+            err = max(err, abs(gpu[i][0].item() - ref["eloc"][0].item()))
+            mag = max(mag, abs(ref["eloc"][0].item()))
+            done += 1
+            i += 1
+        cpu_sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / cpu_sec, "unit": "samples/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle", "sample": f"sample 0 of instances 0..{done - 1}, float64 oracle, "
+                                                           f"log-ratios by full re-evaluation, {cpu_sec:.1f} s"}
+        out["err_vs_fp64_oracle"] = {"eloc": err / mag if mag else 0.0,
+                                     "measure": "max|E - E*| / max|E*| over the CPU sample"}
     print(json.dumps(out), flush=True)
 
 

@@ -113,8 +113,8 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int params_on_d
  * offset r = i - i' stored at r + N - 1 (periodic: the aliased kernel g_(r mod N)). */
 dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream);
 
-/* log psi(s) for B configurations (Eq. (wavefunc) with f = log cosh). Synchronises the
- * stream before returning. */
+/* log psi(s) for B configurations (Eq. (wavefunc) with f = log cosh). Asynchronous on the
+ * stream. */
 dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
 
 /* Connected configurations, matrix elements and diagonal energies of H for B samples.
@@ -155,9 +155,37 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
  * dn_model_set_params). grads: [B][P] in the model's field type (float for DN_PREC_FP32, double
  * for DN_PREC_FP64), nullable (then kept in the workspace); logpsi [B] nullable; weights [B] and
  * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open chains with
- * inject_phi = 0 only (DN_EUNSUPPORTED otherwise). Synchronises the stream. */
+ * inject_phi = 0 only (DN_EUNSUPPORTED otherwise). Asynchronous on the stream. */
 dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
                          const double* weights, double* wsum, void* stream);
+
+/* Execution modes of dn_ragged_eloc. */
+typedef enum {
+  DN_RAGGED_EAGER = 0, /* launch every instance's kernels on each call */
+  DN_RAGGED_GRAPH = 1  /* record the whole submission once as a HIP graph, then replay it */
+} dn_ragged_mode;
+
+/* Local estimator over a ragged batch: n_inst instances, each its own model (shape, width
+ * and depth may all differ) with its own Hamiltonian and B[i] samples, in one submission
+ * (the estimator of Eq. (local-estimator) through the ABACUS update of Alg. 1 per instance).
+ * Host arrays of length n_inst: models (distinct, parameters set, each ABACUS-capable),
+ * hams, spins (device [B_i][N_i] int8), B, logpsi (device [B_i] float64; the array or an
+ * entry may be NULL), eloc (device [B_i] float64). M_max is N_i (Ising) or 2 N_i (J1-J2).
+ * Instances are spread over n_streams (1..8; 0 = 4) HIP streams, heaviest first onto the
+ * least-loaded stream. In DN_RAGGED_GRAPH mode the first call with a given set of models,
+ * Hamiltonians, sizes and pointers runs eagerly, one instance after another, times each
+ * instance, checks every error word (synchronising), and records the submission as one
+ * graph with the measured times as costs; later calls with the same arguments replay it
+ * with one graph launch (the spins' values may change; the generator, work lists and
+ * counts are rebuilt on the device at each replay). A model used elsewhere in between whose
+ * workspace had to grow gets a new recording. Parameter updates (dn_model_set_params) act
+ * in place and need no new recording. Replays do not synchronise: a cluster error cannot
+ * arise there, since the instances' own generator lists the clusters. The library owns the
+ * graphs and streams; dn_model_destroy drops the graphs that use the model. Calls from
+ * several host threads are serialised. */
+dn_status dn_ragged_eloc(int32_t n_inst, dn_model* const* models, const dn_ham_desc* hams,
+                         const int8_t* const* spins, const int32_t* B, double* const* logpsi,
+                         double* const* eloc, int32_t n_streams, int32_t mode, void* stream);
 
 /* Kernel classes of the per-launch profile. */
 typedef enum {

@@ -24,8 +24,9 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
-           "dn_eloc", "dn_grad_logpsi", "dn_profile_enable", "dn_profile_read", "dn_last_error",
-           "dn_model_destroy")
+           "dn_eloc", "dn_grad_logpsi", "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read",
+           "dn_last_error", "dn_model_destroy")
+RAGGED_MODE = {"eager": 0, "graph": 1}
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
                 "eloc", "other")
 
@@ -70,6 +71,8 @@ def lib():
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
         L.dn_grad_logpsi.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+        L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
+                                     ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dn_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -78,7 +81,7 @@ def lib():
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
-                   "dn_grad_logpsi", "dn_profile_enable", "dn_profile_read"):
+                   "dn_grad_logpsi", "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -219,3 +222,21 @@ def local_energy(hdiag, helem, n_conn, logratio):
     _check(lib().dn_local_energy(_ptr(hdiag), _ptr(helem), _ptr(n_conn), _ptr(logratio), B, M_max, _ptr(out),
                                  _stream()))
     return out
+
+
+def ragged_eloc(models, hams, spins, logpsi, eloc, n_streams: int = 0, mode: str = "graph"):
+    """Local estimator over a ragged batch in one submission (dn_ragged_eloc).
+
+    models: list of Model (distinct); hams: HamSpec per instance; spins: int8 [B_i, N_i] device
+    tensors; logpsi (list or None) and eloc: float64 [B_i] device tensors written in place. In
+    graph mode the submission is recorded on the first call with these exact tensors and
+    replayed afterwards, so keep the tensors and refill the spins in place."""
+    n = len(models)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    mh = (vp * n)(*[m.handle for m in models])
+    hd = (HamDesc * n)(*[make_ham(h) for h in hams])
+    sp = (vp * n)(*[s.data_ptr() for s in spins])
+    bb = (i32 * n)(*[int(s.shape[0]) for s in spins])
+    lp = (vp * n)(*[t.data_ptr() if t is not None else 0 for t in logpsi]) if logpsi is not None else None
+    el = (vp * n)(*[t.data_ptr() for t in eloc])
+    _check(lib().dn_ragged_eloc(n, mh, hd, sp, bb, lp, el, n_streams, RAGGED_MODE[mode], _stream()))

@@ -6,9 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -25,6 +27,9 @@ using namespace dn;
 namespace {
 
 thread_local std::string g_err = "no error";
+// true while this thread records launches into a graph (profiling events are skipped)
+thread_local bool g_capturing = false;
+std::atomic<uint64_t> g_next_uid{1};
 
 dn_status fail(dn_status st, const std::string& msg) {
   g_err = msg;
@@ -97,6 +102,8 @@ struct Workspace {
 }  // namespace
 
 struct dn_model {
+  uint64_t uid = g_next_uid.fetch_add(1);  // never reused, unlike the address
+  uint64_t ws_gen = 0;                     // bumped whenever a workspace buffer moves
   dn_model_desc desc{};
   Layout lay{};
   int DP = 0, Np = 0, Wc = 0;
@@ -143,6 +150,7 @@ dn_status ws_get(dn_model* m, const char* name, size_t bytes, void** out) {
   if (hipMalloc(&p, bytes) != hipSuccess) return fail(DN_ENOMEM, std::string("hipMalloc failed for ") + name);
   slot = {p, bytes};
   m->ws.used += bytes;
+  ++m->ws_gen;
   *out = p;
   return DN_OK;
 }
@@ -162,7 +170,7 @@ struct PScope {
   double fl, by;
   hipEvent_t a = nullptr;
   PScope(dn_model* m_, int k, hipStream_t s, double f, double b) : m(m_), kind(k), st(s), fl(f), by(b) {
-    if (m && m->prof.on) { a = prof_event(m); (void)hipEventRecord(a, st); }
+    if (m && m->prof.on && !g_capturing) { a = prof_event(m); (void)hipEventRecord(a, st); }
   }
   ~PScope() {
     if (a) {
@@ -235,8 +243,16 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
   return DN_OK;
 }
 
+// Raises a kernel's dynamic LDS limit once (the value only grows).
 template <typename K> void allow_lds(K kernel, size_t bytes) {
-  if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  if (bytes <= 64 * 1024) return;
+  std::lock_guard<std::mutex> g(mu);
+  size_t& have = done[(const void*)kernel];
+  if (have >= bytes) return;
+  if (hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+    have = bytes;
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -248,10 +264,11 @@ template <typename T> const Tables<T>& tables_of(dn_model* m);
 template <> const Tables<double>& tables_of<double>(dn_model* m) { return m->t64.tb; }
 template <> const Tables<float>& tables_of<float>(dn_model* m) { return m->t32.tb; }
 
-template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const T* taps, int C, hipStream_t st) {
+template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const T* taps, int C, hipStream_t st,
+                                            DynRange dyn = DynRange{nullptr, 0, 0}) {
   if (C <= 0) return DN_OK;
   const int Np = m->Np;
-  ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP};
+  ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP, dyn};
   const double Nr = m->desc.N, dr = m->desc.d;
   PScope ps(m, DN_K_CONV, st, 2.0 * C * Nr * Nr * dr, 2.0 * C * Nr * dr * sizeof(T));
   const size_t lds = (CONV_MC * CONV_LD + 2 * Np) * sizeof(T);
@@ -378,11 +395,10 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
   return DN_OK;
 }
 
-// Builds the (sample, element) work list on the device and validates n_conn and sites; the
-// offsets come back to the host (one stream synchronisation) to size the launches.
-dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, int M_max, int with_base,
-               int32_t** offs, int32_t** cb, int32_t** cm, int upper, std::vector<int32_t>* h_offs,
-               hipStream_t st) {
+// Builds the (sample, element) work list on the device and validates n_conn and sites
+// (error bits in offs[B + 1]).
+dn_status plan_launch(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, int M_max, int with_base,
+                      int32_t** offs, int32_t** cb, int32_t** cm, int upper, hipStream_t st) {
   void *po, *pb, *pm;
   STCHK(ws_get(m, "plan_offs", (size_t)(B + 2) * 4, &po));
   STCHK(ws_get(m, "plan_cb", (size_t)upper * 4, &pb));
@@ -390,11 +406,37 @@ dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, 
   *offs = (int32_t*)po; *cb = (int32_t*)pb; *cm = (int32_t*)pm;
   plan_kernel<<<1, 1024, 0, st>>>(n_conn, sites, B, m->desc.N, M_max, with_base, *offs, *cb, *cm);
   HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status plan_errors(int bits) {
+  if (bits & 1) return fail(DN_EINVAL, "n_conn outside [0, M_max]");
+  if (bits & 2) return fail(DN_EINVAL, "a site index is outside the chain (or a pair repeats a site)");
+  return DN_OK;
+}
+
+// The work list with its offsets brought back to the host (one stream synchronisation) to
+// size the launches exactly.
+dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, int M_max, int with_base,
+               int32_t** offs, int32_t** cb, int32_t** cm, int upper, std::vector<int32_t>* h_offs,
+               hipStream_t st) {
+  STCHK(plan_launch(m, n_conn, sites, B, M_max, with_base, offs, cb, cm, upper, st));
   h_offs->resize(B + 2);
   HIPCHK(hipMemcpyAsync(h_offs->data(), *offs, (size_t)(B + 2) * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if ((*h_offs)[B + 1] & 1) return fail(DN_EINVAL, "n_conn outside [0, M_max]");
-  if ((*h_offs)[B + 1] & 2) return fail(DN_EINVAL, "a site index is outside the chain (or a pair repeats a site)");
+  return plan_errors((*h_offs)[B + 1]);
+}
+
+// Identity work list over B samples in the named workspace slots.
+dn_status identity_map(dn_model* m, const char* nb, const char* nm, int B, int32_t** cb, int32_t** cm,
+                       hipStream_t st) {
+  void *pb, *pm;
+  STCHK(ws_get(m, nb, (size_t)B * 4, &pb));
+  STCHK(ws_get(m, nm, (size_t)B * 4, &pm));
+  *cb = (int32_t*)pb;
+  *cm = (int32_t*)pm;
+  identity_map_kernel<<<(B + 255) / 256, 256, 0, st>>>(*cb, *cm, B);
+  HIPCHK(hipGetLastError());
   return DN_OK;
 }
 
@@ -429,30 +471,25 @@ dn_status logratio_full(dn_model* m, const int8_t* spins, int B, const int32_t* 
 
 // ABACUS: background forward with caches, the adjoint tau of the last block, the slice
 // recompute, the background propagation of each flip's perturbation through blocks
-// 1..L-1, the last block's slice and the float64 log-ratio.
+// 1..L-1, the last block's slice and the float64 log-ratio. With h_offs the flip counts of
+// each chunk are host values; without it every flip launch is sized for Bc * M_max and
+// reads its count from the device work list, so the sequence has no host round trip.
+// The error word ab_err is set for clusters wider than the slice recurrence covers.
 template <typename T, int DP>
-dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t* sites, const int32_t* n_conn,
-                          int M_max, double* logpsi, double* logratio, hipStream_t st) {
+dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* sites, int M_max,
+                      const int32_t* offs, const int32_t* cb, const int32_t* cm, const int32_t* h_offs,
+                      double* logpsi, double* logratio, hipStream_t st) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
-  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 is not implemented on the GPU");
-  if (2 + 2 * L * wc + 1 > SLICE_WIN) return fail(DN_EUNSUPPORTED, "ABACUS slice wider than 16 sites (needs L * w_c <= 6)");
-  int32_t *offs, *cb, *cm;
-  std::vector<int32_t> h_offs;
-  STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
   // identity map for the background forward
-  void *pib, *pim, *pOm, *perr;
-  STCHK(ws_get(m, "ab_idb", (size_t)B * 4, &pib));
-  STCHK(ws_get(m, "ab_idm", (size_t)B * 4, &pim));
+  int32_t *idb, *idm;
+  STCHK(identity_map(m, "ab_idb", "ab_idm", B, &idb, &idm, st));
+  void *pOm, *perr;
   STCHK(ws_get(m, "ab_Om0", (size_t)B * 2 * sizeof(double), &pOm));
   STCHK(ws_get(m, "ab_err", 4, &perr));
-  std::vector<int32_t> iota(B), neg(B, -1);
-  for (int b = 0; b < B; ++b) iota[b] = b;
-  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
   fill_kernel<int><<<1, 64, 0, st>>>((int*)perr, 1, 0);
   double* Om0 = (double*)pOm;
-  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, sites, M_max};
+  CfgMap idmap{idb, idm, sites, M_max};
   CfgMap fmap{cb, cm, sites, M_max};
   fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
   const Tables<T>& tb = tables_of<T>(m);
@@ -463,7 +500,9 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
   for (int b0 = 0; b0 < B; b0 += Bc_max) {
     const int Bc = std::min(Bc_max, B - b0);
-    const int f0 = h_offs[b0], F = h_offs[b0 + Bc] - f0;
+    const int f0 = h_offs ? h_offs[b0] : 0;
+    const int F = h_offs ? h_offs[b0 + Bc] - f0 : Bc * M_max;
+    const DynRange dyn{h_offs ? nullptr : offs, b0, Bc};
     const long fldB = (long)Bc * DP * Np;
     void *pa, *pc, *pp, *ptz, *ptau;
     STCHK(ws_get(m, "ab_a0", (size_t)L * fldB * sizeof(T), &pa));
@@ -494,6 +533,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.act = d.act; a.F = F; a.f0 = f0; a.b0 = b0; a.Bc = Bc; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
+      a.dyn = dyn;
       const size_t lds = 2 * (size_t)Wmax * DP * sizeof(T);
       double fl = 0.0;
       for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
@@ -510,14 +550,14 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       for (int l = 1; l <= L - 1; ++l) {
         MixArgs<T> a{};
         a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
-        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0;
+        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn;
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
         a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
         a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio;
         const bool first = (l == 1), last = (l == L - 1);
-        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st));
+        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
         // l-1 is the 0-based index of block l in the tables
         a.l = l;
         dn_status s;
@@ -533,7 +573,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.F = F; a.f0 = f0; a.b0 = b0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
       a.yL = nullptr; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
-      a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax;
+      a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax; a.dyn = dyn;
       const int WL = 2 * L * wc + 1;
       PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d, (double)F * (WL * 2 + 1) * d.d * sizeof(T));
       tail_kernel<T, DP><<<F, 64, 2 * DP * sizeof(T), st>>>(a);
@@ -541,6 +581,21 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
     }
   }
   if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(Om0, nullptr, B, logpsi);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status abacus_supported(const dn_model* m) {
+  const dn_model_desc& d = m->desc;
+  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 is not implemented on the GPU");
+  if (2 + 2 * d.L * d.w_c + 1 > SLICE_WIN) return fail(DN_EUNSUPPORTED, "ABACUS slice wider than 16 sites (needs L * w_c <= 6)");
+  return DN_OK;
+}
+
+// Reads the error word of the last ABACUS pass (synchronises the stream).
+dn_status abacus_check(dn_model* m, hipStream_t st) {
+  void* perr;
+  STCHK(ws_get(m, "ab_err", 4, &perr));
   int herr = 0;
   HIPCHK(hipMemcpyAsync(&herr, perr, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -549,16 +604,23 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
 }
 
 template <typename T, int DP>
+dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t* sites, const int32_t* n_conn,
+                          int M_max, double* logpsi, double* logratio, hipStream_t st) {
+  STCHK(abacus_supported(m));
+  int32_t *offs, *cb, *cm;
+  std::vector<int32_t> h_offs;
+  STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
+  STCHK((abacus_exec<T, DP>(m, spins, B, sites, M_max, offs, cb, cm, h_offs.data(), logpsi, logratio, st)));
+  return abacus_check(m, st);
+}
+
+template <typename T, int DP>
 dn_status logpsi_only(dn_model* m, const int8_t* spins, int B, double* logpsi, hipStream_t st) {
-  void *pib, *pim, *prho;
-  STCHK(ws_get(m, "lp_idb", (size_t)B * 4, &pib));
-  STCHK(ws_get(m, "lp_idm", (size_t)B * 4, &pim));
+  int32_t *idb, *idm;
+  STCHK(identity_map(m, "lp_idb", "lp_idm", B, &idb, &idm, st));
+  void* prho;
   STCHK(ws_get(m, "lp_rho", (size_t)B * 2 * sizeof(double), &prho));
-  std::vector<int32_t> iota(B), neg(B, -1);
-  for (int b = 0; b < B; ++b) iota[b] = b;
-  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
-  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, nullptr, 0};
+  CfgMap idmap{idb, idm, nullptr, 0};
   const size_t chunk = chunk_configs(m, sizeof(T), 5, (size_t)4 << 30);
   for (int c0 = 0; c0 < B; c0 += (int)chunk) {
     const int C = (int)std::min<size_t>(chunk, B - c0);
@@ -566,8 +628,6 @@ dn_status logpsi_only(dn_model* m, const int8_t* spins, int B, double* logpsi, h
   }
   logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>((double*)prho, nullptr, B, logpsi);
   HIPCHK(hipGetLastError());
-  // the host iota buffers must outlive the async copies
-  HIPCHK(hipStreamSynchronize(st));
   return DN_OK;
 }
 
@@ -753,14 +813,9 @@ dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, v
     STCHK(ws_get(m, "g_out", (size_t)B * Pn * sizeof(T), &p));
     grads = (T*)p;
   }
-  void *pib, *pim;
-  STCHK(ws_get(m, "g_idb", (size_t)B * 4, &pib));
-  STCHK(ws_get(m, "g_idm", (size_t)B * 4, &pim));
-  std::vector<int32_t> iota(B), neg(B, -1);
-  for (int b = 0; b < B; ++b) iota[b] = b;
-  HIPCHK(hipMemcpyAsync(pib, iota.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pim, neg.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
-  CfgMap idmap{(int32_t*)pib, (int32_t*)pim, nullptr, 0};
+  int32_t *idb, *idm;
+  STCHK(identity_map(m, "g_idb", "g_idm", B, &idb, &idm, st));
+  CfgMap idmap{idb, idm, nullptr, 0};
   const size_t per = (size_t)DP * m->Np * sizeof(T) * (2 * d.L + 19) +
                      (size_t)(d.L + 1) * d.d * (2 * d.N - 1) * sizeof(T);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)2 << 30) / per));
@@ -770,7 +825,6 @@ dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, v
   }
   if (w && wsum) wsum_kernel<T><<<(int)std::min<long>(4096, (Pn + 255) / 256), 256, 0, st>>>(grads, w, B, Pn, wsum);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));  // the host iota buffers must outlive the copies
   return DN_OK;
 }
 
@@ -825,6 +879,237 @@ bool check_desc(const dn_model_desc* d, std::string* why) {
   if (d->inject_phi != 0 && d->inject_phi != 1) { *why = "inject_phi must be 0 or 1"; return false; }
   if (d->prec < 0 || d->prec > 2) { *why = "bad prec"; return false; }
   return true;
+}
+
+// Connected elements with a caller-provided coupling table Jr [N].
+dn_status connected_launch(const dn_ham_desc* ham, const int8_t* spins, int B, int N, int M_max, double* Jr,
+                           int32_t* sites, double* helem, int32_t* n_conn, double* hdiag, hipStream_t st) {
+  if (ham->kind == DN_H_LRTFIM)
+    ising_table_kernel<<<1, 64, 0, st>>>(N, ham->bc == DN_BC_PERIODIC, ham->J, ham->alpha, ham->paper_form, Jr);
+  const double cx = ham->paper_form ? -ham->h : ham->h;
+  connected_kernel<<<B, 64, 0, st>>>(ham->kind, ham->bc == DN_BC_PERIODIC, cx, ham->J1, ham->J2, Jr, spins, N,
+                                     M_max, sites, helem, n_conn, hdiag);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status check_ham(const dn_ham_desc* ham, int N, int M_max) {
+  if (ham->kind != DN_H_LRTFIM && ham->kind != DN_H_J1J2) return fail(DN_EINVAL, "bad Hamiltonian kind");
+  if (ham->bc != DN_BC_OPEN && ham->bc != DN_BC_PERIODIC) return fail(DN_EINVAL, "bad Hamiltonian bc");
+  if (ham->kind == DN_H_LRTFIM && M_max < N) return fail(DN_EINVAL, "M_max must be >= N for the Ising chain");
+  if (ham->kind == DN_H_J1J2 && M_max < 2 * N) return fail(DN_EINVAL, "M_max must be >= 2N for the J1-J2 chain");
+  if (ham->kind == DN_H_J1J2 && N < 5) return fail(DN_EINVAL, "the J1-J2 chain needs N >= 5");
+  return DN_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Ragged batches: instances of different shapes, one model each, in one submission.
+
+struct RaggedInst {
+  dn_model* m;
+  dn_ham_desc ham;
+  const int8_t* spins;
+  int B, M_max;
+  double* logpsi;  // nullable
+  double* eloc;
+};
+
+// One instance: generator, work list, ABACUS log-ratios and E_loc, every flip launch
+// counted on the device. No host round trip; nothing is allocated once the model's
+// workspace has reached this instance's size.
+template <typename T, int DP> struct RunInst {
+  static dn_status run(dn_model* m, const RaggedInst* in, hipStream_t st) {
+    const int B = in->B, M = in->M_max, N = m->desc.N;
+    void *ps, *ph, *pn, *pd, *pl, *pj;
+    STCHK(ws_get(m, "rg_sites", (size_t)B * M * 2 * 4, &ps));
+    STCHK(ws_get(m, "rg_helem", (size_t)B * M * 8, &ph));
+    STCHK(ws_get(m, "rg_nconn", (size_t)B * 4, &pn));
+    STCHK(ws_get(m, "rg_hdiag", (size_t)B * 8, &pd));
+    STCHK(ws_get(m, "rg_lr", (size_t)B * M * 8, &pl));
+    STCHK(ws_get(m, "rg_Jr", (size_t)N * 8, &pj));
+    int32_t* sites = (int32_t*)ps;
+    int32_t* nconn = (int32_t*)pn;
+    {
+      const double Nr = N;
+      PScope g(m, DN_K_GEN, st, in->ham.kind == DN_H_LRTFIM ? (double)B * Nr * Nr : (double)B * 8 * Nr,
+               (double)B * (Nr + M * 16.0 + 12));
+      STCHK(connected_launch(&in->ham, in->spins, B, N, M, (double*)pj, sites, (double*)ph, nconn, (double*)pd, st));
+    }
+    int32_t *offs, *cb, *cm;
+    STCHK(plan_launch(m, nconn, sites, B, M, 0, &offs, &cb, &cm, std::max(B * M, 1), st));
+    STCHK((abacus_exec<T, DP>(m, in->spins, B, sites, M, offs, cb, cm, nullptr, in->logpsi, (double*)pl, st)));
+    PScope e(m, DN_K_ELOC, st, 3.0 * B * M, (double)B * M * 16.0 + B * 20.0);
+    eloc_kernel<<<B, 64, 0, st>>>((double*)pd, (double*)ph, nconn, (double*)pl, M, in->eloc);
+    HIPCHK(hipGetLastError());
+    return DN_OK;
+  }
+};
+
+// Synchronises st and reads an instance's error words (work list, then ABACUS).
+dn_status inst_check(dn_model* m, int B, hipStream_t st) {
+  void* po;
+  STCHK(ws_get(m, "plan_offs", (size_t)(B + 2) * 4, &po));
+  int bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, (int32_t*)po + B + 1, 4, hipMemcpyDeviceToHost, st));
+  STCHK(abacus_check(m, st));
+  return plan_errors(bits);
+}
+
+// Cost model of one instance (for the eager schedule): background forward plus, per flip,
+// the deep propagation (full-chain channel mixing and Toeplitz products of blocks 2..L).
+double inst_cost(const RaggedInst& in) {
+  const double Np = in.m->Np, d = in.m->DP, L = in.m->desc.L;
+  const double fwd = L * (8.0 * Np * d * d + 2.0 * Np * Np * d);
+  const double flip = 4.0 * Np * d * d * std::max(1.0, L - 1) + 2.0 * Np * Np * d * std::max(0.0, L - 2);
+  return in.B * (fwd + in.M_max * flip);
+}
+
+// Heaviest first onto the least-loaded of K lanes.
+std::vector<std::vector<int>> lpt_lanes(const std::vector<double>& cost, int K) {
+  std::vector<int> order(cost.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int>> lanes(K);
+  std::vector<double> load(K, 0.0);
+  for (int i : order) {
+    int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[k].push_back(i);
+    load[k] += cost[i];
+  }
+  return lanes;
+}
+
+// Library streams and events of one device (created on first use, kept until exit).
+struct StreamPool {
+  int dev = -1;
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;
+};
+
+struct RaggedPlan {
+  std::vector<uint64_t> key, uids;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+  ~RaggedPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+std::mutex g_rg_mu;
+std::vector<StreamPool> g_pools;
+std::vector<RaggedPlan*> g_rg_cache;  // at most RG_CACHE plans, least recently used dropped
+uint64_t g_rg_clock = 0;
+constexpr size_t RG_CACHE = 8;
+
+dn_status get_pool(int dev, int K, StreamPool** out) {
+  StreamPool* p = nullptr;
+  for (auto& q : g_pools) if (q.dev == dev) p = &q;
+  if (!p) { g_pools.push_back(StreamPool{}); p = &g_pools.back(); p->dev = dev; }
+  while ((int)p->st.size() < K) {
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    p->st.push_back(s);
+  }
+  while ((int)p->ev.size() < K + 1) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p->ev.push_back(e);
+  }
+  *out = p;
+  return DN_OK;
+}
+
+uint64_t dbits(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, 8);
+  return u;
+}
+
+std::vector<uint64_t> ragged_key(const std::vector<RaggedInst>& ins, int K, int dev) {
+  std::vector<uint64_t> k{(uint64_t)ins.size(), (uint64_t)K, (uint64_t)dev};
+  for (auto& in : ins) {
+    const dn_ham_desc& h = in.ham;
+    k.insert(k.end(), {in.m->uid, in.m->ws_gen, (uint64_t)in.B, (uint64_t)(uintptr_t)in.spins,
+                       (uint64_t)(uintptr_t)in.logpsi, (uint64_t)(uintptr_t)in.eloc, (uint64_t)h.kind,
+                       (uint64_t)h.bc, (uint64_t)h.paper_form, dbits(h.J), dbits(h.alpha), dbits(h.h),
+                       dbits(h.J1), dbits(h.J2)});
+  }
+  return k;
+}
+
+// Instances on K lanes: lane 0 is `main`, lanes 1..K-1 the pool's streams, forked from
+// and joined back into `main` by events.
+dn_status ragged_lanes(std::vector<RaggedInst>& ins, const std::vector<std::vector<int>>& lanes, StreamPool* pool,
+                       hipStream_t main) {
+  const int K = (int)lanes.size();
+  if (K > 1) HIPCHK(hipEventRecord(pool->ev[0], main));
+  for (int k = 1; k < K; ++k) HIPCHK(hipStreamWaitEvent(pool->st[k], pool->ev[0], 0));
+  for (int k = 0; k < K; ++k) {
+    hipStream_t sk = k == 0 ? main : pool->st[k];
+    for (int i : lanes[k]) STCHK(dispatch<RunInst>(ins[i].m, (const RaggedInst*)&ins[i], sk));
+  }
+  for (int k = 1; k < K; ++k) {
+    HIPCHK(hipEventRecord(pool->ev[k], pool->st[k]));
+    HIPCHK(hipStreamWaitEvent(main, pool->ev[k], 0));
+  }
+  return DN_OK;
+}
+
+// Records the submission into a graph on the pool's capture stream.
+dn_status ragged_capture(std::vector<RaggedInst>& ins, const std::vector<std::vector<int>>& lanes, StreamPool* pool,
+                         hipGraph_t* out) {
+  *out = nullptr;
+  hipStream_t cap = pool->st[0];
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  g_capturing = true;
+  dn_status s = ragged_lanes(ins, lanes, pool, cap);
+  g_capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  if (s != DN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  HIPCHK(e);
+  *out = g;
+  return DN_OK;
+}
+
+// First call of a graph-mode submission: every instance in turn on `st`, timed, checked.
+dn_status ragged_first(std::vector<RaggedInst>& ins, hipStream_t st, std::vector<double>* ms) {
+  std::vector<hipEvent_t> ev(ins.size() + 1, nullptr);
+  dn_status s = DN_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) s = fail(DN_EHIP, "hipEventCreate failed");
+  if (s == DN_OK && hipEventRecord(ev[0], st) != hipSuccess) s = fail(DN_EHIP, "hipEventRecord failed");
+  for (size_t i = 0; i < ins.size() && s == DN_OK; ++i) {
+    s = dispatch<RunInst>(ins[i].m, (const RaggedInst*)&ins[i], st);
+    if (s == DN_OK && hipEventRecord(ev[i + 1], st) != hipSuccess) s = fail(DN_EHIP, "hipEventRecord failed");
+  }
+  for (size_t i = 0; i < ins.size() && s == DN_OK; ++i) s = inst_check(ins[i].m, ins[i].B, st);
+  ms->assign(ins.size(), 0.0);
+  for (size_t i = 0; i < ins.size() && s == DN_OK; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) s = fail(DN_EHIP, "hipEventElapsedTime failed");
+    (*ms)[i] = t;
+  }
+  for (auto e : ev) if (e) (void)hipEventDestroy(e);
+  return s;
+}
+
+void ragged_forget(uint64_t uid) {
+  std::lock_guard<std::mutex> g(g_rg_mu);
+  for (size_t i = 0; i < g_rg_cache.size();) {
+    auto& u = g_rg_cache[i]->uids;
+    if (std::find(u.begin(), u.end(), uid) != u.end()) {
+      delete g_rg_cache[i];
+      g_rg_cache.erase(g_rg_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
 }
 
 }  // namespace
@@ -943,30 +1228,17 @@ dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, i
   if (!ham) return fail(DN_EINVAL, "null argument");
   if (B < 0 || N < 2) return fail(DN_EINVAL, "bad B or N");
   if (B > 0 && (!spins || !sites || !helem || !n_conn || !hdiag)) return fail(DN_EINVAL, "null argument");
-  if (ham->kind != DN_H_LRTFIM && ham->kind != DN_H_J1J2) return fail(DN_EINVAL, "bad Hamiltonian kind");
-  if (ham->bc != DN_BC_OPEN && ham->bc != DN_BC_PERIODIC) return fail(DN_EINVAL, "bad Hamiltonian bc");
-  if (ham->kind == DN_H_LRTFIM && M_max < N) return fail(DN_EINVAL, "M_max must be >= N for the Ising chain");
-  if (ham->kind == DN_H_J1J2 && M_max < 2 * N) return fail(DN_EINVAL, "M_max must be >= 2N for the J1-J2 chain");
-  if (ham->kind == DN_H_J1J2 && N < 5) return fail(DN_EINVAL, "the J1-J2 chain needs N >= 5");
+  STCHK(check_ham(ham, N, M_max));
   if (B == 0) return DN_OK;
   hipStream_t st = (hipStream_t)stream;
-  double* Jr = nullptr;
   thread_local double* tl_Jr = nullptr;
   thread_local int tl_N = 0;
-  if (ham->kind == DN_H_LRTFIM) {
-    if (tl_N < N) {
-      if (tl_Jr) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(tl_Jr)); tl_Jr = nullptr; }
-      if (hipMalloc(&tl_Jr, (size_t)N * sizeof(double)) != hipSuccess) return fail(DN_ENOMEM, "coupling table");
-      tl_N = N;
-    }
-    Jr = tl_Jr;
-    ising_table_kernel<<<1, 64, 0, st>>>(N, ham->bc == DN_BC_PERIODIC, ham->J, ham->alpha, ham->paper_form, Jr);
+  if (ham->kind == DN_H_LRTFIM && tl_N < N) {
+    if (tl_Jr) { HIPCHK(hipStreamSynchronize(st)); HIPCHK(hipFree(tl_Jr)); tl_Jr = nullptr; tl_N = 0; }
+    if (hipMalloc(&tl_Jr, (size_t)N * sizeof(double)) != hipSuccess) return fail(DN_ENOMEM, "coupling table");
+    tl_N = N;
   }
-  const double cx = ham->paper_form ? -ham->h : ham->h;
-  connected_kernel<<<B, 64, 0, st>>>(ham->kind, ham->bc == DN_BC_PERIODIC, cx, ham->J1, ham->J2, Jr, spins, N,
-                                     M_max, sites, helem, n_conn, hdiag);
-  HIPCHK(hipGetLastError());
-  return DN_OK;
+  return connected_launch(ham, spins, B, N, M_max, tl_Jr, sites, helem, n_conn, hdiag, st);
 }
 
 dn_status dn_logratio(dn_model* m, int32_t path, const int8_t* spins, int32_t B, const int32_t* sites,
@@ -1053,8 +1325,81 @@ dn_status dn_profile_read(dn_model* m, int32_t kind, double* total_ms, int64_t* 
   return DN_OK;
 }
 
+dn_status dn_ragged_eloc(int32_t n_inst, dn_model* const* models, const dn_ham_desc* hams,
+                         const int8_t* const* spins, const int32_t* B, double* const* logpsi,
+                         double* const* eloc, int32_t n_streams, int32_t mode, void* stream) {
+  if (n_inst < 0) return fail(DN_EINVAL, "n_inst < 0");
+  if (n_inst == 0) return DN_OK;
+  if (!models || !hams || !spins || !B || !eloc) return fail(DN_EINVAL, "null argument");
+  if (n_streams < 0 || n_streams > 8) return fail(DN_EINVAL, "n_streams must be in [0, 8]");
+  if (mode != DN_RAGGED_EAGER && mode != DN_RAGGED_GRAPH) return fail(DN_EINVAL, "bad ragged mode");
+  std::vector<RaggedInst> ins;
+  for (int i = 0; i < n_inst; ++i) {
+    dn_model* m = models[i];
+    const std::string at = " (instance " + std::to_string(i) + ")";
+    if (!m) return fail(DN_EINVAL, "null model" + at);
+    for (int j = 0; j < i; ++j)
+      if (models[j] == m) return fail(DN_EINVAL, "each instance needs its own model" + at);
+    if (!m->have_params) return fail(DN_ESTATE, "parameters not set" + at);
+    const int N = m->desc.N;
+    const int M = hams[i].kind == DN_H_J1J2 ? 2 * N : N;
+    STCHK(check_ham(&hams[i], N, M));
+    STCHK(abacus_supported(m));
+    if (B[i] < 0) return fail(DN_EINVAL, "B < 0" + at);
+    if ((long)B[i] * (M + 1) > (1L << 31) - 1) return fail(DN_EINVAL, "B * (M_max + 1) too large" + at);
+    if (B[i] == 0) continue;
+    if (!spins[i] || !eloc[i]) return fail(DN_EINVAL, "null spins or eloc" + at);
+    ins.push_back(RaggedInst{m, hams[i], spins[i], B[i], M, logpsi ? logpsi[i] : nullptr, eloc[i]});
+  }
+  if (ins.empty()) return DN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int K = std::min<int>(n_streams == 0 ? 4 : n_streams, (int)ins.size());
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> guard(g_rg_mu);
+  StreamPool* pool;
+  STCHK(get_pool(dev, K, &pool));
+  if (mode == DN_RAGGED_EAGER) {
+    std::vector<double> cost;
+    for (auto& in : ins) cost.push_back(inst_cost(in));
+    return ragged_lanes(ins, lpt_lanes(cost, K), pool, st);
+  }
+  const std::vector<uint64_t> key = ragged_key(ins, K, dev);
+  for (RaggedPlan* p : g_rg_cache) {
+    if (p->key == key) {
+      p->stamp = ++g_rg_clock;
+      HIPCHK(hipGraphLaunch(p->exec, st));
+      return DN_OK;
+    }
+  }
+  std::vector<double> ms;
+  STCHK(ragged_first(ins, st, &ms));
+  std::vector<uint64_t> gen;
+  for (auto& in : ins) gen.push_back(in.m->ws_gen);
+  RaggedPlan* p = new RaggedPlan();
+  dn_status s = ragged_capture(ins, lpt_lanes(ms, K), pool, &p->graph);
+  for (size_t i = 0; s == DN_OK && i < ins.size(); ++i)
+    if (ins[i].m->ws_gen != gen[i]) s = fail(DN_EHIP, "workspace moved while recording the ragged graph");
+  if (s == DN_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+    s = fail(DN_EHIP, "hipGraphInstantiate failed");
+  if (s != DN_OK) { delete p; return s; }
+  p->key = ragged_key(ins, K, dev);
+  for (auto& in : ins) p->uids.push_back(in.m->uid);
+  p->stamp = ++g_rg_clock;
+  if (g_rg_cache.size() >= RG_CACHE) {
+    auto old = std::min_element(g_rg_cache.begin(), g_rg_cache.end(),
+                                [](RaggedPlan* a, RaggedPlan* b) { return a->stamp < b->stamp; });
+    delete *old;
+    g_rg_cache.erase(old);
+  }
+  g_rg_cache.push_back(p);
+  return DN_OK;
+}
+
 void dn_model_destroy(dn_model* m) {
-  if (m) (void)hipDeviceSynchronize();
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  ragged_forget(m->uid);
   delete m;
 }
 

@@ -139,6 +139,14 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ 
   if (t == 1023) { offs[B] = part[1023]; offs[B + 1] = bad; }
 }
 
+// Identity work list: entry b is sample b, unflipped.
+__global__ void identity_map_kernel(int32_t* __restrict__ cb, int32_t* __restrict__ cm, int B) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    cb[b] = b;
+    cm[b] = -1;
+  }
+}
+
 template <typename T> __global__ void fill_kernel(T* __restrict__ x, long n, T v) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
 }

@@ -225,11 +225,23 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
 // taps staged in LDS; the field operand is staged in LDS in 64-site chunks (row stride 66
 // floats: conflict-free fragment reads). One workgroup: 64 configurations x 256 output
 // sites of one channel; each wave owns 64 (or fewer) output sites.
+// Launch-time work count. With offs == nullptr the host value holds; otherwise the launch
+// covers flips offs[b0] .. offs[b0 + Bc] of the device work list (a grid sized for the
+// upper bound Bc * M_max whose surplus workgroups return at once), so a launch sequence
+// needs no host round trip and can be captured once and replayed for any spins.
+struct DynRange {
+  const int32_t* offs;
+  int b0, Bc;
+  __device__ inline int first(int f0) const { return offs ? offs[b0] : f0; }
+  __device__ inline int count(int n) const { return offs ? offs[b0 + Bc] - offs[b0] : n; }
+};
+
 template <typename T> struct ConvArgs {
   const T* X;
   T* Y;
   const T* taps;  // [DP][tap_stride(Np)] for this mixer
   int N, Np, C, DP;
+  DynRange dyn;   // configurations counted on the device (nullable)
 };
 
 constexpr int CONV_MC = 64;   // configurations per workgroup
@@ -245,6 +257,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.y;
   const int cfg0 = blockIdx.x * CONV_MC;
+  const int C = A.dyn.count(A.C);
+  if (cfg0 >= C) return;
   const int Np = A.Np;
   const int site0 = blockIdx.z * 64 * NT;                // output block of 4 waves x 16*NT sites
   const int wsite0 = site0 + wave * 16 * NT;              // this wave's first output site
@@ -261,7 +275,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
     for (int idx = threadIdx.x; idx < CONV_MC * CONV_KC; idx += 256) {
       int mrow = idx / CONV_KC, kk = idx % CONV_KC;
       int cfg = cfg0 + mrow;
-      xs[mrow * CONV_LD + kk] = (cfg < A.C) ? A.X[(long)cfg * cstride + (long)c * Np + k0 + kk] : T(0);
+      xs[mrow * CONV_LD + kk] = (cfg < C) ? A.X[(long)cfg * cstride + (long)c * Np + k0 + kk] : T(0);
     }
     __syncthreads();
     if (wsite0 < Np) {
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
       for (int r = 0; r < 4; ++r) {
         const int cfg = cfg0 + 16 * a + M::row(lane, r);
         const int i = wsite0 + 16 * n + (lane & 15);
-        if (cfg < A.C) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
+        if (cfg < C) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
       }
 }
 
@@ -342,6 +356,7 @@ template <typename T> struct MixArgs {
   const T* p0L;          // LAST: V v0 of block L [Bc][DP][Np]
   const double* Om0;     // LAST: [B][2]
   double* logratio;      // LAST: [B][M_max]
+  DynRange dyn;          // DEEP: flips counted on the device (nullable)
 };
 
 constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4)
@@ -384,6 +399,11 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   __shared__ double red[2][8];
   __shared__ int4 sg;
   const int g = blockIdx.x;
+  int cfg0 = A.cfg0;
+  if (MODE == MIX_DEEP) {
+    if (g >= A.dyn.count(A.C)) return;
+    cfg0 = A.dyn.first(A.cfg0);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int N = A.N, Np = A.Np, l = A.l;
@@ -392,7 +412,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   const long fo = (long)g * DP * Np;
   int b = 0, kk_tau = 0;
   if (MODE == MIX_TAU) { b = g >> 1; kk_tau = g & 1; }
-  if (MODE == MIX_DEEP) b = A.map.cb[A.cfg0 + g] - A.b0;
+  if (MODE == MIX_DEEP) b = A.map.cb[cfg0 + g] - A.b0;
   const long bo = (long)b * DP * Np;
   const int tl = (MODE == MIX_DEEP) ? l - 1 : l;  // table index (DEEP passes the 1-based block)
   const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)tl * DP * DP : A.tb.Vt + (long)tl * DP * DP;
@@ -414,7 +434,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
   const int8_t* sp = nullptr;
-  if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+  if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[cfg0 + g] * N;
 #pragma unroll 4
   for (int ks = 0; ks < KS; ++ks) {
     const int kc = 4 * ks + kq;
@@ -656,7 +676,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   }
   // e^(0) = -2 s_j E on the cluster, read out directly (lanes over channels)
   {
-    const int8_t* spb = A.spins + (long)A.map.cb[A.cfg0 + g] * N;
+    const int8_t* spb = A.spins + (long)A.map.cb[cfg0 + g] * N;
     for (int q = 0; q < 2; ++q) {
       const int js = q == 0 ? sg.z : sg.w;
       if (js < 0) continue;
@@ -670,7 +690,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   o0 = wave_sum(o0);
   o1 = wave_sum(o1);
   if (lane == 0) {
-    const int bg = A.map.cb[A.cfg0 + g], m = A.map.cm[A.cfg0 + g];
+    const int bg = A.map.cb[cfg0 + g], m = A.map.cm[cfg0 + g];
     const double d0 = A.rho[2 * g] + r0 + o0, d1 = A.rho[2 * g + 1] + r1 + o1;
     A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], d0) + lcd_d(A.Om0[2 * bg + 1], d1);
   }
@@ -693,6 +713,7 @@ template <typename T> struct SliceArgs {
   int4* geom;             // [F]
   int Wmax;
   int* err;               // set to 1 for a cluster the slice recurrence does not cover
+  DynRange dyn;           // flips counted on the device (nullable)
 };
 
 template <typename T, int DP>
@@ -704,7 +725,9 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
   const int c = threadIdx.x;  // channel; lanes c >= DP only join the barriers
   const bool on = c < DP;
   const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
-  const int b = A.map.cb[A.f0 + f], m = A.map.cm[A.f0 + f];
+  if (f >= A.dyn.count(A.F)) return;
+  const int f0 = A.dyn.first(A.f0);
+  const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
   const int bl = b - A.b0;
   const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
   const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
@@ -810,6 +833,7 @@ template <typename T> struct TailArgs {
   const double* Om0;    // [B][2] global
   double* logratio;     // [B][M_max] global
   int Wmax;
+  DynRange dyn;         // flips counted on the device (nullable)
 };
 
 template <typename T, int DP>
@@ -820,7 +844,9 @@ __global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
   const int f = blockIdx.x, c = threadIdx.x;
   const bool on = c < DP;                   // lanes c >= DP contribute zeros
   const int N = A.N, Np = A.Np, L = A.L, wc = A.w_c;
-  const int b = A.map.cb[A.f0 + f], m = A.map.cm[A.f0 + f];
+  if (f >= A.dyn.count(A.F)) return;
+  const int f0 = A.dyn.first(A.f0);
+  const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
   const int bl = b - A.b0;
   const int4 gm = A.geom[f];
   const int8_t* sp = A.spins + (long)b * N;
