@@ -314,7 +314,8 @@ template <typename T, int DP, int MODE, bool FIRST, bool LAST>
 dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, int Bc = 0) {
   if (C <= 0) return DN_OK;
   const int nw = m->Np / 64;
-  const size_t lds = (size_t)nw * DP * MIX_XS * sizeof(T);
+  // only the last deep block stages its output (for the slice of the last mixer) in LDS
+  const size_t lds = (MODE == MIX_DEEP && LAST) ? (size_t)nw * DP * MIX_XS * sizeof(T) : 0;
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "mixing tile exceeds LDS");
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T), fld = Nr * dr * e;
   double fl = 4.0 * C * Nr * dr * dr, by;
@@ -335,6 +336,31 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, in
   PScope ps(m, kind, st, fl, by);
   allow_lds(mix_kernel<T, DP, MODE, FIRST, LAST>, lds);
   mix_kernel<T, DP, MODE, FIRST, LAST><<<C, 64 * nw, lds, st>>>(a);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+// Persistent tiled launch of a deep block before the last (see deep_kernel).
+template <typename T, int DP, bool FIRST>
+dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
+  if (F <= 0) return DN_OK;
+  const size_t lds = 2 * (size_t)DP * DP * sizeof(T);
+  static int per_cu = 0, cus = 0;
+  if (!per_cu) {
+    allow_lds(deep_kernel<T, DP, FIRST>, lds);
+    int dev = 0, n = 0, c = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST>, 256, lds));
+    cus = std::max(c, 1);
+    per_cu = std::max(n, 1);
+  }
+  const long tiles = (long)F * (m->Np / 64);
+  long grid = std::min<long>((tiles + DEEP_WAVES - 1) / DEEP_WAVES, (long)cus * per_cu);
+  grid = std::max<long>(NXCD, grid / NXCD * NXCD);
+  const double Nr = m->desc.N, dr = m->desc.d, fld = Nr * dr * sizeof(T);
+  PScope ps(m, DN_K_MIX_DEEP, st, 4.0 * F * Nr * dr * dr, F * fld * ((FIRST ? 0 : 1) + 1) + (double)Bc * fld * 2);
+  deep_kernel<T, DP, FIRST><<<(int)grid, 256, lds, st>>>(a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -524,7 +550,8 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     void *pdchi, *pgeom, *prho, *pdu, *pw;
     STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
     STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
-    STCHK(ws_get(m, "ab_rho", (size_t)F * 2 * sizeof(double), &prho));
+    const int nt = Np / 64;
+    STCHK(ws_get(m, "ab_rho", (size_t)F * nt * 2 * sizeof(double), &prho));
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
     double* rho = (double*)prho;
@@ -541,7 +568,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
       HIPCHK(hipGetLastError());
     }
-    fill_kernel<double><<<256, 256, 0, st>>>(rho, 2L * F, 0.0);
+    fill_kernel<double><<<256, 256, 0, st>>>(rho, 2L * F * nt, 0.0);
     if (L >= 2) {
       STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
       STCHK(ws_get(m, "ab_w", (size_t)F * DP * Np * sizeof(T), &pw));
@@ -550,7 +577,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       for (int l = 1; l <= L - 1; ++l) {
         MixArgs<T> a{};
         a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
-        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn;
+        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_nt = nt;
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
@@ -562,9 +589,9 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
         a.l = l;
         dn_status s;
         if (first && last) s = launch_mix<T, DP, MIX_DEEP, true, true>(m, a, F, st, Bc);
-        else if (first) s = launch_mix<T, DP, MIX_DEEP, true, false>(m, a, F, st, Bc);
         else if (last) s = launch_mix<T, DP, MIX_DEEP, false, true>(m, a, F, st, Bc);
-        else s = launch_mix<T, DP, MIX_DEEP, false, false>(m, a, F, st, Bc);
+        else if (first) s = launch_deep<T, DP, true>(m, a, F, st, Bc);
+        else s = launch_deep<T, DP, false>(m, a, F, st, Bc);
         STCHK(s);
       }
     }

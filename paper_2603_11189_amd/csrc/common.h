@@ -21,6 +21,9 @@ template <> struct Mma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  // row = lane_row(lane) + r_row(r): the first part per lane, the second the same for all
+  __device__ static inline int lane_row(int lane) { return 4 * (lane >> 4); }
+  __device__ static inline int r_row(int r) { return r; }
 };
 template <> struct Mma<double> {
   using acc = d4;
@@ -28,6 +31,8 @@ template <> struct Mma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  __device__ static inline int lane_row(int lane) { return lane >> 4; }
+  __device__ static inline int r_row(int r) { return 4 * r; }
 };
 
 // Green's-function tap tables: per channel TS = 2 Np + 128 entries, offset r = i - i' stored

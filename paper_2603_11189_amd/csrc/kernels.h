@@ -270,14 +270,29 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[a][n] = typename M::acc{0, 0, 0, 0};
   const long cstride = (long)A.DP * Np;
+  // The field chunk is staged through registers one chunk ahead: thread (wave, lane) moves
+  // element lane of configuration rows wave + 4u, so the loads of the next chunk are in
+  // flight while the matrix cores work on the current one.
+  constexpr int SU = CONV_MC * CONV_KC / 256;
+  const T* xrow = A.X + (long)c * Np + lane;
+  T pre[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int cfg = cfg0 + wave + 4 * u;
+    pre[u] = (cfg < C) ? xrow[(long)cfg * cstride] : T(0);
+  }
   for (int k0 = 0; k0 < Np; k0 += CONV_KC) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < CONV_MC * CONV_KC; idx += 256) {
-      int mrow = idx / CONV_KC, kk = idx % CONV_KC;
-      int cfg = cfg0 + mrow;
-      xs[mrow * CONV_LD + kk] = (cfg < C) ? A.X[(long)cfg * cstride + (long)c * Np + k0 + kk] : T(0);
-    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) xs[(wave + 4 * u) * CONV_LD + lane] = pre[u];
     __syncthreads();
+    if (k0 + CONV_KC < Np) {
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int cfg = cfg0 + wave + 4 * u;
+        pre[u] = (cfg < C) ? xrow[(long)cfg * cstride + k0 + CONV_KC] : T(0);
+      }
+    }
     if (wsite0 < Np) {
 #pragma unroll 2
       for (int ks = 0; ks < CONV_KC / 4; ++ks) {
@@ -341,7 +356,8 @@ template <typename T> struct MixArgs {
   T* p0_out;             // FWD cache of q (nullable)
   const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
   T* out;                // [C][DP][Np] (unused for DEEP LAST)
-  double* rho;           // [C][2] accumulated (FWD, DEEP)
+  double* rho;           // FWD: [C][2] accumulated; DEEP: [F][rho_nt][2] per 64-site tile
+  int rho_nt;            // DEEP: tiles per flip in rho
   T* R_acc;              // FWD: residual sum R += h (nullable)
   // DEEP
   CfgMap map;            // flip -> (b, m)
@@ -496,38 +512,33 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
         }
       }
 #pragma unroll
-      for (int n = 0; n < 4; ++n) if (s0 + n >= N) x[n] = T(0);
-      st4(xs + ch * MIX_XS + 4 * j, x);
+      for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? x[n] : T(0);
     }
-  wave_sync();
-  // ---- phase 2
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-  for (int ks = 0; ks < KS; ++ks) {
-    const int kc = 4 * ks + kq;
-    V4<T> v = ld4(xs + kc * MIX_XS + 4 * j);
-    T af[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) af[mt] = M2[kc * DP + 16 * mt + j];
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], v.v[n], acc[mt][n]);
-  }
-  wave_sync();
+  // ---- phase 2, one 16-channel output tile at a time. The contraction runs over the
+  // channels in accumulator order: at step (mi, r) the lanes of group kq hold channel
+  // 16 mi + row(lane, r) of their sites, which is a valid operand B for the matrix cores
+  // as long as operand A (M2) is gathered with the same channel per lane group.
   double part0 = 0.0, part1 = 0.0;
+#pragma unroll 1
+  for (int mo = 0; mo < MT; ++mo) {
+    acc_t a2[4];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T af = M2[(16 * mi + M::row(lane, r)) * DP + 16 * mo + j];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+      }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int ch = 16 * mt + M::row(lane, r);
+      const int ch = 16 * mo + M::row(lane, r);
       const long o = (long)ch * Np + s0;
       T y[4];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? acc[mt][n][r] : T(0);
+      for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
       if (MODE == MIX_TAU) {
         st4(A.out + fo + o, y);
       } else {
@@ -560,6 +571,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
         if (MODE == MIX_DEEP && LAST) st4(xs + ch * MIX_XS + 4 * j, y);  // dh for the slice conv
       }
     }
+  }
   if (MODE != MIX_TAU) {
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
@@ -691,8 +703,199 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   o1 = wave_sum(o1);
   if (lane == 0) {
     const int bg = A.map.cb[cfg0 + g], m = A.map.cm[cfg0 + g];
-    const double d0 = A.rho[2 * g] + r0 + o0, d1 = A.rho[2 * g + 1] + r1 + o1;
+    double p0s = 0.0, p1s = 0.0;  // read-outs of the earlier deep blocks, per 64-site tile
+    for (int t = 0; t < A.rho_nt; ++t) { p0s += A.rho[(2L * g) * A.rho_nt + 2 * t]; p1s += A.rho[(2L * g) * A.rho_nt + 2 * t + 1]; }
+    const double d0 = p0s + r0 + o0, d1 = p1s + r1 + o1;
     A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], d0) + lcd_d(A.Om0[2 * bg + 1], d1);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Deep blocks before the last one (ABACUS background propagation, blocks 1..L-2):
+// du^(l+1) = D0^(l) G^(l) du^(l) + z^(l) on the full chain, as in mix_kernel's DEEP mode,
+// but one 64-site tile per wave step instead of one flip per workgroup. Persistent
+// workgroups of four waves keep both channel-mixing matrices of the block in LDS in
+// fragment order (every operand read is one contiguous 64-lane access), and each wave
+// walks its tiles with the next tile's input already in flight while the current one is
+// mixed. Tiles are dealt out per XCD in contiguous ranges (workgroup w runs on XCD
+// w mod 8), so the flips of one sample, which share their background caches, meet in the
+// same L2. Each tile's read-out lands in rho[f][t], which the last block sums.
+constexpr int DEEP_WAVES = 4;
+constexpr int NXCD = 8;
+constexpr int DEEP_OCC = 2;
+
+template <typename T, int DP, bool FIRST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC))) void deep_kernel(MixArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  constexpr int MT = DP / 16, KS = DP / 4;
+  // the next tile's input is prefetched into registers unless that would not fit
+  constexpr bool PF = !FIRST && KS * 4 * sizeof(T) <= 256;
+  T* F1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of V, phase 1
+  T* F2 = F1 + DP * DP;                     // [MT][64][MT][4]: operand A of U, phase 2
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, kq = lane >> 4;
+  const int N = A.N, Np = A.Np, l = A.l;
+  const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
+  const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
+  for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
+    {
+      const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
+      F1[idx] = Vt[(4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
+    }
+    {
+      // phase 2 contracts over the channels in accumulator order (see mix_kernel)
+      const int r = idx & 3, mi = (idx >> 2) % MT, ln = (idx / (4 * MT)) % 64, mo = idx / (4 * MT * 64);
+      F2[idx] = Ut[(16 * mi + M::row(ln, r)) * DP + 16 * mo + (ln & 15)];
+    }
+  }
+  __syncthreads();  // the only workgroup barrier: the waves run independently from here
+  const int F = A.dyn.count(A.C);
+  const int cfg0 = A.dyn.first(A.cfg0);
+  const int nt = Np / 64;
+  const long total = (long)F * nt;
+  const int xcd = blockIdx.x % NXCD, bx = blockIdx.x / NXCD, nbx = gridDim.x / NXCD;
+  const long per = (total + NXCD - 1) / NXCD;
+  const long q_hi = min(total, (long)xcd * per + per);
+  const long wstride = (long)nbx * DEEP_WAVES;
+  long q = (long)xcd * per + (long)bx * DEEP_WAVES + wave;
+  const int TO = tap_off(Np), TS = tap_stride(Np);
+  // Addresses are a per-lane base plus an offset that is the same for every lane (kept in
+  // scalar registers), so that no per-lane 64-bit offsets stay live across the tile loop.
+  const int lrow = M::lane_row(lane);
+  V4<T> xb[PF ? KS : 1];
+  if (PF && q < q_hi) {
+    const T* src = A.X + (q / nt) * DP * Np + 64 * (q % nt) + kq * Np + 4 * j;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + 4 * ks * Np);
+  }
+  for (; q < q_hi; q += wstride) {
+    const int g = (int)(q / nt), t = (int)(q % nt);
+    const int4 sg = A.geom[g];
+    const int bglob = A.map.cb[cfg0 + g];
+    const long fo = (long)g * DP * Np, bo = (long)(bglob - A.b0) * DP * Np;
+    const int s0 = 64 * t + 4 * j;
+    const long lo_off = (long)lrow * Np + s0;  // this lane's part of a field offset
+    // ---- phase 1: q = V w
+    acc_t acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+    const int8_t* sp = A.spins + (long)bglob * N;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + kq;
+      T bv[4];
+      if (FIRST) {
+        // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
+        const T* t1 = A.taps1 + (long)kc * TS + TO;
+        const T e = A.tb.E[kc];
+        const T c0 = (T)(-2 * sp[sg.z]) * e;
+        const T c1 = sg.w >= 0 ? (T)(-2 * sp[sg.w]) * e : T(0);
+        const int j1 = sg.w >= 0 ? sg.w : sg.z;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int i = s0 + n;
+          bv[n] = (i < N) ? t1[i - sg.z] * c0 + t1[i - j1] * c1 : T(0);
+        }
+      } else if constexpr (PF) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bv[n] = xb[ks].v[n];
+      } else {
+        const V4<T> v = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
+      }
+      T af[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[mt] = F1[(ks * 64 + lane) * MT + mt];
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], bv[n], acc[mt][n]);
+      // keep the scheduler from hoisting every later operand load (register pressure)
+      if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    // ---- x = chi0 q + [i in S_l] dchi (p0 + q)
+    // slice positions of this lane's four sites (-1: outside S_l); the same for every channel
+    int sidx[4];
+    {
+      const int lo = sg.x - l * A.w_c, W = sg.y + 2 * l * A.w_c + 1;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        int sx = s0 + n - lo;
+        if (A.periodic) { sx %= N; if (sx < 0) sx += N; }
+        sidx[n] = (s0 + n < N && sx >= 0 && sx < W) ? sx : -1;
+      }
+    }
+    const bool in_slice = sidx[0] >= 0 || sidx[1] >= 0 || sidx[2] >= 0 || sidx[3] >= 0;
+    const T* dchi_l = A.dchi + ((long)g * A.L + (l - 1)) * A.Wmax * DP;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        const int uo = (16 * mt + M::r_row(r)) * Np;  // lane-independent part of the offset
+        const V4<T> c = ld4(A.chi + bo + lo_off + uo);
+        T x[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) x[n] = c.v[n] * acc[mt][n][r];
+        if (in_slice) {
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            if (sidx[n] >= 0) x[n] += dchi_l[sidx[n] * DP + ch] * (A.p0[bo + lo_off + uo + n] + acc[mt][n][r]);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? x[n] : T(0);
+        if (r == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    // the next tile's input travels while this one is mixed and stored
+    if (PF && q + wstride < q_hi) {
+      const long qn = q + wstride;
+      const T* src = A.X + (qn / nt) * DP * Np + 64 * (qn % nt) + kq * Np + 4 * j;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + 4 * ks * Np);
+    }
+    // ---- phase 2 per 16-channel output tile: du = U x, stored, and read out
+    double part0 = 0.0, part1 = 0.0;
+#pragma unroll 1
+    for (int mo = 0; mo < MT; ++mo) {
+      acc_t a2[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+#pragma unroll
+          for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+          if (r == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long o = lo_off + (16 * mo + M::r_row(r)) * Np;
+        T y[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
+        const V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          part0 += (double)w0.v[n] * (double)y[n];
+          part1 += (double)w1.v[n] * (double)y[n];
+        }
+        st4(A.out + fo + o, y);
+      }
+    }
+    part0 = wave_sum(part0);
+    part1 = wave_sum(part1);
+    if (lane == 0) {
+      double* rp = A.rho + ((long)g * nt + t) * 2;
+      rp[0] += part0;
+      rp[1] += part1;
+    }
   }
 }
 
