@@ -70,7 +70,7 @@ bool layout_of(const dn_model_desc& d, Layout* lo) {
 template <typename T> struct TableBufs {
   std::vector<void*> owned;
   Tables<T> tb{};
-  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk, *ADm, *WDm;
+  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk, *ADm, *WDm, *Pq;
 };
 
 struct ProfRec {
@@ -211,16 +211,17 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
             get(&tb.Um, L * DP * DP) && get(&tb.Vm, L * DP * DP) && get(&tb.wv, L * DP) &&
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
             get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, L * DP * tap_stride(Np)) &&
-            get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP);
+            get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP) &&
+            get(&tb.Pq, DP * tap_stride(Np));
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
-                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm};
+                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm, tb.Pq};
   return DN_OK;
 }
 
 long table_elems(const dn_model& m) {
   const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
-  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + 2 * L * DP * tap_stride(Np) + 2 * DP * Np;
+  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + (2 * L + 1) * DP * tap_stride(Np) + 2 * DP * Np;
 }
 
 // Copy double tables into float tables (same member order).
@@ -234,7 +235,7 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
       {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, L * DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np},
-      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}};
+      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, DP * tap_stride(Np)}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
     convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);
@@ -310,48 +311,40 @@ template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>
   return DN_OK;
 }
 
-template <typename T, int DP, int MODE, bool FIRST, bool LAST>
-dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, int Bc = 0) {
+template <typename T, int DP, int MODE>
+dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
   if (C <= 0) return DN_OK;
   const int nw = m->Np / 64;
-  // only the last deep block stages its output (for the slice of the last mixer) in LDS
-  const size_t lds = (MODE == MIX_DEEP && LAST) ? (size_t)nw * DP * MIX_XS * sizeof(T) : 0;
-  if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "mixing tile exceeds LDS");
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T), fld = Nr * dr * e;
-  double fl = 4.0 * C * Nr * dr * dr, by;
+  const double fl = 4.0 * C * Nr * dr * dr;
   int kind;
+  double by;
   if (MODE == MIX_FWD) {
     kind = DN_K_MIX_FWD;
     by = C * fld * (2 + (a.out ? 1 : 0) + (a.p0_out ? 1 : 0) + (a.inject ? 1 : 0));
-  } else if (MODE == MIX_TAU) {
+  } else {
     kind = DN_K_MIX_TAU;
     by = C * fld + (C / 2) * fld;
-  } else {
-    kind = DN_K_MIX_DEEP;
-    const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
-    // the last block also forms the slice of its mixer output and the two slice products
-    if (LAST) fl += 2.0 * C * WL * Nr * dr + 4.0 * C * WL * dr * dr;
-    by = C * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 5 : 2);
   }
   PScope ps(m, kind, st, fl, by);
-  allow_lds(mix_kernel<T, DP, MODE, FIRST, LAST>, lds);
-  mix_kernel<T, DP, MODE, FIRST, LAST><<<C, 64 * nw, lds, st>>>(a);
+  mix_kernel<T, DP, MODE><<<C, 64 * nw, 0, st>>>(a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
 
-// Persistent tiled launch of a deep block before the last (see deep_kernel).
-template <typename T, int DP, bool FIRST>
+// Persistent tiled launch of a deep block (see deep_kernel); the last one is followed by
+// last_finish_kernel, one wave per flip.
+template <typename T, int DP, bool FIRST, bool LAST>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
-  const size_t lds = 2 * (size_t)DP * DP * sizeof(T);
+  const size_t lds = LAST ? (size_t)DEEP_WAVES * DP * DH_LD * sizeof(T) : 2 * (size_t)DP * DP * sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
-    allow_lds(deep_kernel<T, DP, FIRST>, lds);
+    allow_lds(deep_kernel<T, DP, FIRST, LAST>, lds);
     int dev = 0, n = 0, c = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST>, 256, lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST, LAST>, 256, lds));
     cus = std::max(c, 1);
     per_cu = std::max(n, 1);
   }
@@ -359,9 +352,21 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   long grid = std::min<long>((tiles + DEEP_WAVES - 1) / DEEP_WAVES, (long)cus * per_cu);
   grid = std::max<long>(NXCD, grid / NXCD * NXCD);
   const double Nr = m->desc.N, dr = m->desc.d, fld = Nr * dr * sizeof(T);
-  PScope ps(m, DN_K_MIX_DEEP, st, 4.0 * F * Nr * dr * dr, F * fld * ((FIRST ? 0 : 1) + 1) + (double)Bc * fld * 2);
-  deep_kernel<T, DP, FIRST><<<(int)grid, 256, lds, st>>>(a);
-  HIPCHK(hipGetLastError());
+  const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
+  {
+    // the last block also forms the tiles' partial slices of the last mixer's output
+    const double fl = 4.0 * F * Nr * dr * dr + (LAST ? 2.0 * F * WL * Nr * dr : 0.0);
+    const double by = F * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
+    PScope ps(m, DN_K_MIX_DEEP, st, fl, by);
+    deep_kernel<T, DP, FIRST, LAST><<<(int)grid, 256, lds, st>>>(a);
+    HIPCHK(hipGetLastError());
+  }
+  if (LAST) {
+    PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * dr * dr,
+              (double)F * (m->Np / 64) * SLICE_WIN * dr * sizeof(T) + (double)F * WL * dr * sizeof(T) * 2);
+    last_finish_kernel<T, DP><<<F, 64, 2 * DP * SLICE_WIN * sizeof(T), st>>>(a);
+    HIPCHK(hipGetLastError());
+  }
   return DN_OK;
 }
 
@@ -416,7 +421,7 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
     a.X = v; a.chi = chi_of(l); a.p0_out = cache_p0 ? cache_p0 + (long)l * fld : nullptr;
     a.phi_next = phi; a.out = (l + 1 < L) ? (ck.h ? ck.h + (long)(l + 1) * fld : u) : nullptr; a.rho = rho;
     a.R_acc = ck.R;
-    STCHK((launch_mix<T, DP, MIX_FWD, false, false>(m, a, C, st)));
+    STCHK((launch_mix<T, DP, MIX_FWD>(m, a, C, st)));
   }
   return DN_OK;
 }
@@ -521,7 +526,8 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   const Tables<T>& tb = tables_of<T>(m);
   const int Wmax = 2 + 2 * L * wc + 1;
   // samples per chunk: the flip fields dominate (2 fields of [F][DP][Np])
-  const size_t per_flip = (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T);
+  const size_t per_flip = (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T) +
+                          (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
   const size_t flips_budget = std::max<size_t>(1024, ((size_t)3 << 30) / per_flip);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
   for (int b0 = 0; b0 < B; b0 += Bc_max) {
@@ -543,7 +549,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       MixArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
       a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bc; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
-      STCHK((launch_mix<T, DP, MIX_TAU, false, false>(m, a, 2 * Bc, st, Bc)));
+      STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bc, st)));
       STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bc, st));
     }
     if (F == 0) continue;
@@ -570,8 +576,10 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     }
     fill_kernel<double><<<256, 256, 0, st>>>(rho, 2L * F * nt, 0.0);
     if (L >= 2) {
+      void* psp;
       STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
       STCHK(ws_get(m, "ab_w", (size_t)F * DP * Np * sizeof(T), &pw));
+      STCHK(ws_get(m, "ab_spart", (size_t)F * nt * SLICE_WIN * DP * sizeof(T), &psp));
       T* du = (T*)pdu;
       T* w = (T*)pw;
       for (int l = 1; l <= L - 1; ++l) {
@@ -582,16 +590,16 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
         a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
-        a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio;
+        a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.slice_part = (T*)psp;
         const bool first = (l == 1), last = (l == L - 1);
         if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
         // l-1 is the 0-based index of block l in the tables
         a.l = l;
         dn_status s;
-        if (first && last) s = launch_mix<T, DP, MIX_DEEP, true, true>(m, a, F, st, Bc);
-        else if (last) s = launch_mix<T, DP, MIX_DEEP, false, true>(m, a, F, st, Bc);
-        else if (first) s = launch_deep<T, DP, true>(m, a, F, st, Bc);
-        else s = launch_deep<T, DP, false>(m, a, F, st, Bc);
+        if (first && last) s = launch_deep<T, DP, true, true>(m, a, F, st, Bc);
+        else if (last) s = launch_deep<T, DP, false, true>(m, a, F, st, Bc);
+        else if (first) s = launch_deep<T, DP, true, false>(m, a, F, st, Bc);
+        else s = launch_deep<T, DP, false, false>(m, a, F, st, Bc);
         STCHK(s);
       }
     }
@@ -764,7 +772,7 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
       MixArgs<T> a{};
       a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.C = Bc; a.cfg0 = b0; a.X = tv; a.chi = tchi; a.p0_out = tq; a.out = nullptr; a.rho = rho2;
-      STCHK((launch_mix<T, DP, MIX_FWD, false, false>(m, a, Bc, st)));
+      STCHK((launch_mix<T, DP, MIX_FWD>(m, a, Bc, st)));
     }
     // vertex and channel mixing backward
     {
@@ -1216,6 +1224,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   {
     PScope ps(m, DN_K_PREP, st, 0.0, (double)table_elems(*m) * 8);
     prep_kernel<<<256, 256, 0, st>>>(a);
+    ptab_kernel<<<256, 256, 0, st>>>(t.taps, t.Vt, t.E, m->DP, tap_stride(m->Np), t.Pq);
   }
   HIPCHK(hipGetLastError());
   if (d.prec != DN_PREC_FP64) STCHK(convert_tables(m, st));

@@ -17,6 +17,7 @@ template <typename T> struct Tables {
   const T *taps, *tapsR;                   // [L][DP][tap_stride]: mixers and their transposes
   const T *Wk;                             // [2][DP][Np]
   const T *ADm, *WDm;                      // operand tables of A_D^T and W_D^T
+  const T *Pq;                             // [DP][tap_stride]: V^(1) (E * g^(1)(r)), see ptab_kernel
 };
 
 // Which configuration a block works on. Plain path: cfg g -> sample b, element m (m = -1
@@ -328,38 +329,37 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
 // Vertex and channel mixing, fused with the read-out. One workgroup per configuration,
 // one wave per 64-site block; a wave's 16 matrix-core columns j and 4 tiles n cover sites
 // 64 w + 4 j + n, so every lane moves 4 consecutive sites as one vector.
-//   phase 1: q = M1 X (matrix cores), x = elementwise(q, ...) -> the wave's LDS tile
-//   phase 2: y = M2 x, written out and contracted with the read-out weights.
+//   phase 1: q = M1 X (matrix cores), x = elementwise(q, ...) in place in the accumulators;
+//   phase 2: y = M2 x, one 16-channel output tile at a time, written out and contracted
+//            with the read-out weights.
+// The contraction of phase 2 runs over the channels in accumulator order: at step (mi, r)
+// the lanes of group kq hold channel 16 mi + row(lane, r) of their sites, which is a valid
+// operand B for the matrix cores when operand A (M2) is gathered with the same channel per
+// lane group, so x never leaves the registers.
 // Modes:
 //   FWD:  X = v, x = chi * q (q = V v cached as p0 when requested), y = h = U x;
 //         out = h (+ phi^(l+1) when injected) as the next mixer input; rho += Wk . h.
 //   TAU:  X = Wk[k] (cfg = 2b + k), x = chi0[b] * (U^T X), y = V^T x  (the adjoint
 //         D0^T of the last block applied to the read-out weights; a conv with reversed
 //         taps then gives tau = G^T D0^T Wk).
-//   DEEP: X = w = G^(l) du (full chain, per flip), x = chi0 q + [i in S_l] dchi (p0 + q),
-//         y = dh = U x: the background propagation of the perturbation plus the vertex
-//         change on the slice. rho += Wk . dh. FIRST (l = 1) builds w = G^(1) e^(0) from the
-//         taps and the cluster instead of reading X. LAST (l = L-1) adds tau . dh, forms the
-//         slice of the last mixer's output y_L = P_{S_L} G^(L) dh and finishes the flip:
-//         e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, dOmega = rho + Wk . (e^(0) + e^(L)),
-//         log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
-enum { MIX_FWD = 0, MIX_TAU = 1, MIX_DEEP = 2 };
+// The per-flip blocks of ABACUS run in deep_kernel.
+enum { MIX_FWD = 0, MIX_TAU = 1 };
 
 template <typename T> struct MixArgs {
   Tables<T> tb;
   int N, Np, l, L, w_c, periodic, inject;
   int C;                 // configurations (flips) in this launch
-  int cfg0;              // global index of the first (DEEP: flip map offset)
-  const T* X;            // [C][DP][Np] (FWD/DEEP non-first)
-  const T* chi;          // FWD: [C][DP][Np]; TAU/DEEP: chi0 of the block [Bc][DP][Np]
-  const T* p0;           // DEEP: V v0 of the block [Bc][DP][Np]
+  int cfg0;              // global index of the first (flips: offset in the flip map)
+  const T* X;            // [C][DP][Np] (FWD; deep blocks after the first)
+  const T* chi;          // FWD: [C][DP][Np]; TAU/deep: chi0 of the block [Bc][DP][Np]
+  const T* p0;           // deep: V v0 of the block [Bc][DP][Np]
   T* p0_out;             // FWD cache of q (nullable)
   const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
-  T* out;                // [C][DP][Np] (unused for DEEP LAST)
-  double* rho;           // FWD: [C][2] accumulated; DEEP: [F][rho_nt][2] per 64-site tile
-  int rho_nt;            // DEEP: tiles per flip in rho
+  T* out;                // [C][DP][Np] (unused by the last deep block)
+  double* rho;           // FWD: [C][2] accumulated; deep: [F][rho_nt][2] per 64-site tile
+  int rho_nt;            // deep: tiles per flip in rho
   T* R_acc;              // FWD: residual sum R += h (nullable)
-  // DEEP
+  // deep blocks (per flip)
   CfgMap map;            // flip -> (b, m)
   int b0;                // first sample of the chunk (caches are chunk-local)
   const int8_t* spins;
@@ -367,15 +367,16 @@ template <typename T> struct MixArgs {
   const T* dchi;         // [F][L][Wmax][DP]
   int Wmax;
   const T* tau;          // [Bc][2][DP][Np]
-  const T* tapsL;        // taps of block L [DP][tap_stride] (LAST)
-  const T* taps1;        // taps of block 1 [DP][tap_stride] (FIRST)
-  const T* p0L;          // LAST: V v0 of block L [Bc][DP][Np]
-  const double* Om0;     // LAST: [B][2]
-  double* logratio;      // LAST: [B][M_max]
-  DynRange dyn;          // DEEP: flips counted on the device (nullable)
+  const T* tapsL;        // taps of block L [DP][tap_stride] (last block)
+  const T* taps1;        // taps of block 1 [DP][tap_stride] (first block)
+  const T* p0L;          // last block: V v0 of block L [Bc][DP][Np]
+  const double* Om0;     // last block: [B][2]
+  double* logratio;      // last block: [B][M_max]
+  DynRange dyn;          // flips counted on the device (nullable)
+  T* slice_part;         // last block: [F][Np/64][SLICE_WIN][DP] partial slices
 };
 
-constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4)
+constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4; gradient kernels)
 constexpr int SLICE_WIN = 16;   // slice positions handled by the last block's window
 
 template <typename T> struct V4 { T v[4]; };
@@ -406,41 +407,23 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int DP, int MODE, bool FIRST, bool LAST>
+template <typename T, int DP, int MODE>
 __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
   constexpr int MT = DP / 16, KS = DP / 4;
   __shared__ double red[2][8];
-  __shared__ int4 sg;
   const int g = blockIdx.x;
-  int cfg0 = A.cfg0;
-  if (MODE == MIX_DEEP) {
-    if (g >= A.dyn.count(A.C)) return;
-    cfg0 = A.dyn.first(A.cfg0);
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int N = A.N, Np = A.Np, l = A.l;
   const int j = lane & 15, kq = lane >> 4;
-  T* xs = reinterpret_cast<T*>(smem_raw) + wave * DP * MIX_XS;  // this wave's tile [DP][68]
   const long fo = (long)g * DP * Np;
   int b = 0, kk_tau = 0;
   if (MODE == MIX_TAU) { b = g >> 1; kk_tau = g & 1; }
-  if (MODE == MIX_DEEP) b = A.map.cb[cfg0 + g] - A.b0;
   const long bo = (long)b * DP * Np;
-  const int tl = (MODE == MIX_DEEP) ? l - 1 : l;  // table index (DEEP passes the 1-based block)
-  const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)tl * DP * DP : A.tb.Vt + (long)tl * DP * DP;
-  const T* M2 = (MODE == MIX_TAU) ? A.tb.Vm + (long)tl * DP * DP : A.tb.Ut + (long)tl * DP * DP;
-  int lo = 0, W = 0;
-  if (MODE == MIX_DEEP) {
-    if (threadIdx.x == 0) sg = A.geom[g];
-    __syncthreads();
-    lo = sg.x - l * A.w_c;
-    W = sg.y + 2 * l * A.w_c + 1;
-  }
-  const int TO = tap_off(Np);
+  const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)l * DP * DP : A.tb.Vt + (long)l * DP * DP;
+  const T* M2 = (MODE == MIX_TAU) ? A.tb.Vm + (long)l * DP * DP : A.tb.Ut + (long)l * DP * DP;
   const int s0 = 64 * wave + 4 * j;  // first of this lane's 4 sites
   const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
   // ---- phase 1
@@ -449,36 +432,17 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
-  const int8_t* sp = nullptr;
-  if (MODE == MIX_DEEP && FIRST) sp = A.spins + (long)A.map.cb[cfg0 + g] * N;
 #pragma unroll 4
   for (int ks = 0; ks < KS; ++ks) {
     const int kc = 4 * ks + kq;
-    T bv[4];
-    if (MODE == MIX_DEEP && FIRST) {
-      // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
-      const T* t1 = A.taps1 + (long)kc * tap_stride(Np) + TO;
-      const T e = A.tb.E[kc];
-      const T c0 = (T)(-2 * sp[sg.z]) * e;
-      const T c1 = sg.w >= 0 ? (T)(-2 * sp[sg.w]) * e : T(0);
-      const int j1 = sg.w >= 0 ? sg.w : sg.z;
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const int i = s0 + n;
-        bv[n] = (i < N) ? t1[i - sg.z] * c0 + t1[i - j1] * c1 : T(0);
-      }
-    } else {
-      V4<T> v = ld4(X + (long)kc * Np + s0);
-#pragma unroll
-      for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
-    }
+    const V4<T> v = ld4(X + (long)kc * Np + s0);
     T af[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) af[mt] = M1[kc * DP + 16 * mt + j];
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], bv[n], acc[mt][n]);
+      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], v.v[n], acc[mt][n]);
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -486,38 +450,15 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
     for (int r = 0; r < 4; ++r) {
       const int ch = 16 * mt + M::row(lane, r);
       const long o = (long)ch * Np + s0;
-      T q[4], x[4];
+      T q[4];
 #pragma unroll
       for (int n = 0; n < 4; ++n) q[n] = acc[mt][n][r];
-      if (MODE == MIX_FWD) {
-        V4<T> c = ld4(A.chi + fo + o);
+      const V4<T> c = ld4(A.chi + (MODE == MIX_FWD ? fo : bo) + o);
+      if (MODE == MIX_FWD && A.p0_out) st4(A.p0_out + fo + o, q);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) x[n] = c.v[n] * q[n];
-        if (A.p0_out) st4(A.p0_out + fo + o, q);
-      } else {
-        V4<T> c = ld4(A.chi + bo + o);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) x[n] = c.v[n] * q[n];
-        if (MODE == MIX_DEEP) {
-#pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            const int i = s0 + n;
-            int sidx = i - lo;
-            if (A.periodic) { sidx %= N; if (sidx < 0) sidx += N; }
-            if (i < N && sidx >= 0 && sidx < W) {
-              const T dc = A.dchi[(((long)g * A.L + (l - 1)) * A.Wmax + sidx) * DP + ch];
-              x[n] += dc * (A.p0[bo + o + n] + q[n]);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? x[n] : T(0);
+      for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? c.v[n] * q[n] : T(0);
     }
-  // ---- phase 2, one 16-channel output tile at a time. The contraction runs over the
-  // channels in accumulator order: at step (mi, r) the lanes of group kq hold channel
-  // 16 mi + row(lane, r) of their sites, which is a valid operand B for the matrix cores
-  // as long as operand A (M2) is gathered with the same channel per lane group.
+  // ---- phase 2, one 16-channel output tile at a time
   double part0 = 0.0, part1 = 0.0;
 #pragma unroll 1
   for (int mo = 0; mo < MT; ++mo) {
@@ -542,205 +483,80 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
       if (MODE == MIX_TAU) {
         st4(A.out + fo + o, y);
       } else {
-        V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + (long)DP * Np + o);
-        if (MODE == MIX_DEEP && LAST) {
-          V4<T> t0 = ld4(A.tau + (long)(2 * b) * DP * Np + o), t1 = ld4(A.tau + (long)(2 * b + 1) * DP * Np + o);
-#pragma unroll
-          for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
-        }
+        const V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + (long)DP * Np + o);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
           part0 += (double)w0.v[n] * (double)y[n];
           part1 += (double)w1.v[n] * (double)y[n];
         }
-        if (MODE == MIX_FWD && A.R_acc) {
+        if (A.R_acc) {
           V4<T> rr = ld4(A.R_acc + fo + o);
 #pragma unroll
           for (int n = 0; n < 4; ++n) rr.v[n] += y[n];
           st4(A.R_acc + fo + o, rr.v);
         }
-        if (MODE == MIX_FWD && A.out) {
+        if (A.out) {
           if (A.inject) {
-            V4<T> ph = ld4(A.phi_next + fo + o);
+            const V4<T> ph = ld4(A.phi_next + fo + o);
 #pragma unroll
             for (int n = 0; n < 4; ++n) y[n] += ph.v[n];
           }
           st4(A.out + fo + o, y);
         }
-        if (MODE == MIX_DEEP && !LAST) st4(A.out + fo + o, y);
-        if (MODE == MIX_DEEP && LAST) st4(xs + ch * MIX_XS + 4 * j, y);  // dh for the slice conv
       }
     }
   }
-  if (MODE != MIX_TAU) {
-    part0 = wave_sum(part0);
-    part1 = wave_sum(part1);
-    if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
-  }
+  if (MODE == MIX_TAU) return;
+  part0 = wave_sum(part0);
+  part1 = wave_sum(part1);
+  if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
   __syncthreads();
-  double r0 = 0.0, r1 = 0.0;
-  if (MODE != MIX_TAU) {
+  if (threadIdx.x == 0) {
+    double r0 = 0.0, r1 = 0.0;
     for (int w = 0; w < nw; ++w) { r0 += red[0][w]; r1 += red[1][w]; }
-  }
-  if (MODE != MIX_TAU && !(MODE == MIX_DEEP && LAST)) {
-    if (threadIdx.x == 0) { A.rho[2 * g] += r0; A.rho[2 * g + 1] += r1; }
-    return;
-  }
-  if (!(MODE == MIX_DEEP && LAST)) return;
-  // ---- last block: slice of the mixer output, y_L[t][c] = sum_i' g^(L)_c(site_t - i') dh[c][i']
-  int loL = sg.x - A.L * A.w_c;
-  const int WL = sg.y + 2 * A.L * A.w_c + 1;
-  if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
-  {
-    const int c = lane;
-    T ya[SLICE_WIN], rg[SLICE_WIN];
-#pragma unroll
-    for (int t = 0; t < SLICE_WIN; ++t) ya[t] = 0;
-    const int ib = 64 * wave, cnt = min(64, N - ib);
-    if (c < DP && cnt > 0) {
-      // rg[x mod 16] holds h(x) = g(loL + x); at chain site ib + k the window needs h(t - ib - k)
-      const T* tc = A.tapsL + (long)c * tap_stride(Np) + TO + loL - ib;  // tc[t - k] = h(t - ib - k)
-#pragma unroll
-      for (int t = 0; t < SLICE_WIN; ++t) rg[t] = tc[t];
-      const T* xr = xs + c * MIX_XS;
-      for (int k0 = 0; k0 < cnt; k0 += SLICE_WIN) {
-#pragma unroll
-        for (int u = 0; u < SLICE_WIN; ++u) {
-          const int k = k0 + u;
-          if (k < cnt) {
-            const T v = xr[k];
-#pragma unroll
-            for (int t = 0; t < SLICE_WIN; ++t) ya[t] += rg[(t - u + SLICE_WIN * 4) % SLICE_WIN] * v;
-            rg[(SLICE_WIN * 4 - u - 1) % SLICE_WIN] = tc[-(k + 1)];
-          }
-        }
-      }
-    }
-    __syncthreads();  // every wave is done with its dh tile: reuse the LDS for partial sums
-    T* part = reinterpret_cast<T*>(smem_raw);  // [nw][SLICE_WIN][DP]
-    if (c < DP)
-#pragma unroll
-      for (int t = 0; t < SLICE_WIN; ++t) part[(wave * SLICE_WIN + t) * DP + c] = ya[t];
-    __syncthreads();
-  }
-  if (wave != 0) return;
-  // wave 0: e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on the slice, read-outs, log-ratio
-  T* part = reinterpret_cast<T*>(smem_raw);
-  T* Y = part + nw * SLICE_WIN * DP;  // [DP][16]: Y[c][t]
-  for (int idx = lane; idx < DP * SLICE_WIN; idx += 64) {
-    const int c = idx / SLICE_WIN, t = idx % SLICE_WIN;
-    T s = 0;
-    for (int w = 0; w < nw; ++w) s += part[(w * SLICE_WIN + t) * DP + c];
-    Y[c * SLICE_WIN + t] = (t < WL) ? s : T(0);
-  }
-  wave_sync();
-  const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
-  const T* Ut = A.tb.Ut + (long)(A.L - 1) * DP * DP;
-  acc_t a2[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int kc = 4 * ks + kq;
-    const T bvv = Y[kc * SLICE_WIN + j];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Vt[kc * DP + 16 * mt + j], bvv, a2[mt]);
-  }
-  const int t_me = j;  // this lane's slice position (matrix-core column)
-  int site = loL + t_me;
-  bool valid = t_me < WL;
-  if (A.periodic) { site %= N; }
-  else valid = valid && site >= 0 && site < N;
-  const long bL = (long)b * DP * Np;
-  const T* dchiL = A.dchi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP;
-  T* X2 = Y + DP * SLICE_WIN;  // [DP][16]
-  wave_sync();
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ch = 16 * mt + M::row(lane, r);
-      T x = 0;
-      if (valid) x = dchiL[t_me * DP + ch] * (A.p0L[bL + (long)ch * Np + site] + a2[mt][r]);
-      X2[ch * SLICE_WIN + t_me] = x;
-    }
-  wave_sync();
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int kc = 4 * ks + kq;
-    const T bvv = X2[kc * SLICE_WIN + j];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Ut[kc * DP + 16 * mt + j], bvv, a2[mt]);
-  }
-  double o0 = 0.0, o1 = 0.0;
-  if (valid) {
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ch = 16 * mt + M::row(lane, r);
-        const long o = (long)ch * Np + site;
-        o0 += (double)A.tb.Wk[o] * (double)a2[mt][r];
-        o1 += (double)A.tb.Wk[(long)DP * Np + o] * (double)a2[mt][r];
-      }
-  }
-  // e^(0) = -2 s_j E on the cluster, read out directly (lanes over channels)
-  {
-    const int8_t* spb = A.spins + (long)A.map.cb[cfg0 + g] * N;
-    for (int q = 0; q < 2; ++q) {
-      const int js = q == 0 ? sg.z : sg.w;
-      if (js < 0) continue;
-      for (int c = lane; c < DP; c += 64) {
-        const double e0 = (double)(-2 * spb[js]) * (double)A.tb.E[c];
-        o0 += (double)A.tb.Wk[(long)c * Np + js] * e0;
-        o1 += (double)A.tb.Wk[(long)DP * Np + (long)c * Np + js] * e0;
-      }
-    }
-  }
-  o0 = wave_sum(o0);
-  o1 = wave_sum(o1);
-  if (lane == 0) {
-    const int bg = A.map.cb[cfg0 + g], m = A.map.cm[cfg0 + g];
-    double p0s = 0.0, p1s = 0.0;  // read-outs of the earlier deep blocks, per 64-site tile
-    for (int t = 0; t < A.rho_nt; ++t) { p0s += A.rho[(2L * g) * A.rho_nt + 2 * t]; p1s += A.rho[(2L * g) * A.rho_nt + 2 * t + 1]; }
-    const double d0 = p0s + r0 + o0, d1 = p1s + r1 + o1;
-    A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], d0) + lcd_d(A.Om0[2 * bg + 1], d1);
+    A.rho[2 * g] += r0;
+    A.rho[2 * g + 1] += r1;
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Deep blocks before the last one (ABACUS background propagation, blocks 1..L-2):
-// du^(l+1) = D0^(l) G^(l) du^(l) + z^(l) on the full chain, as in mix_kernel's DEEP mode,
-// but one 64-site tile per wave step instead of one flip per workgroup. Persistent
-// workgroups of four waves keep both channel-mixing matrices of the block in LDS in
-// fragment order (every operand read is one contiguous 64-lane access), and each wave
-// walks its tiles with the next tile's input already in flight while the current one is
-// mixed. Tiles are dealt out per XCD in contiguous ranges (workgroup w runs on XCD
-// w mod 8), so the flips of one sample, which share their background caches, meet in the
-// same L2. Each tile's read-out lands in rho[f][t], which the last block sums.
+// Deep blocks of the ABACUS background propagation: du^(l+1) = D0^(l) G^(l) du^(l) + z^(l)
+// on the full chain, as in mix_kernel's DEEP mode, but one 64-site tile per wave step
+// instead of one flip per workgroup. Each wave walks its tiles with the next tile's input
+// already in flight while the current one is mixed. Tiles are dealt out per XCD in
+// contiguous ranges (workgroup w runs on XCD w mod 8), so the flips of one sample, which
+// share their background caches, meet in the same L2. Each tile's read-out lands in
+// rho[f][t].
+// Blocks before the last keep both channel-mixing matrices in LDS in fragment order
+// (every operand read is one contiguous 64-lane access) and store du. The last block
+// (LAST) instead reads out dh with Wk + tau and, per tile, the partial slice of the last
+// mixer's output, part[f][t][s][c] = sum_{i' in tile} g^(L)_c(site_s - i') dh[c][i'],
+// from a channel-major copy of the tile in LDS (row stride DH_LD, odd, so the per-channel
+// reads hit distinct banks); last_finish_kernel completes the flip.
 constexpr int DEEP_WAVES = 4;
 constexpr int NXCD = 8;
 constexpr int DEEP_OCC = 2;
+constexpr int DH_LD = 65;
 
-template <typename T, int DP, bool FIRST>
+template <typename T, int DP, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC))) void deep_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
   constexpr int MT = DP / 16, KS = DP / 4;
   // the next tile's input is prefetched into registers unless that would not fit
-  constexpr bool PF = !FIRST && KS * 4 * sizeof(T) <= 256;
+  constexpr bool PF = !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
   T* F1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of V, phase 1
   T* F2 = F1 + DP * DP;                     // [MT][64][MT][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
+  T* dh = reinterpret_cast<T*>(smem_raw) + wave * DP * DH_LD;  // LAST: this wave's dh tile
   const int N = A.N, Np = A.Np, l = A.l;
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
+  if (!LAST)
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
-    {
+    if (!FIRST) {  // the first block reads its phase-1 product from a table
       const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
       F1[idx] = Vt[(4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
     }
@@ -750,7 +566,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
       F2[idx] = Ut[(16 * mi + M::row(ln, r)) * DP + 16 * mo + (ln & 15)];
     }
   }
-  __syncthreads();  // the only workgroup barrier: the waves run independently from here
+  if (!LAST) __syncthreads();  // the only workgroup barrier: the waves run independently from here
   const int F = A.dyn.count(A.C);
   const int cfg0 = A.dyn.first(A.cfg0);
   const int nt = Np / 64;
@@ -771,6 +587,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
     for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + 4 * ks * Np);
   }
   for (; q < q_hi; q += wstride) {
+    // compiler-only barrier: the weight operands are reloaded per tile rather than hoisted
+    // out of the loop into registers (which would halve the occupancy)
+    asm volatile("" ::: "memory");
     const int g = (int)(q / nt), t = (int)(q % nt);
     const int4 sg = A.geom[g];
     const int bglob = A.map.cb[cfg0 + g];
@@ -779,44 +598,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
     const long lo_off = (long)lrow * Np + s0;  // this lane's part of a field offset
     // ---- phase 1: q = V w
     acc_t acc[MT][4];
+    if constexpr (FIRST) {
+      // w = G^(1) e^(0) with e^(0)_c = -2 s_z E_c at the cluster sites z, so
+      // q(i) = -2 s_z Pq(i - z) summed over the cluster (Pq: parameter-only table)
+      const int8_t* sp = A.spins + (long)bglob * N;
+      const T c0 = (T)(-2 * sp[sg.z]);
+      const bool pair = sg.w >= 0;
+      const T c1 = pair ? (T)(-2 * sp[sg.w]) : T(0);
+      const T* pz = A.tb.Pq + (long)lrow * TS + TO + s0 - sg.z;
+      const T* pw = A.tb.Pq + (long)lrow * TS + TO + s0 - (pair ? sg.w : sg.z);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
-    const int8_t* sp = A.spins + (long)bglob * N;
+        for (int r = 0; r < 4; ++r) {
+          const int uo = (16 * mt + M::r_row(r)) * TS;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + kq;
-      T bv[4];
-      if (FIRST) {
-        // w = G^(1) e^(0), e^(0)_j = -2 s_j E at the cluster sites
-        const T* t1 = A.taps1 + (long)kc * TS + TO;
-        const T e = A.tb.E[kc];
-        const T c0 = (T)(-2 * sp[sg.z]) * e;
-        const T c1 = sg.w >= 0 ? (T)(-2 * sp[sg.w]) * e : T(0);
-        const int j1 = sg.w >= 0 ? sg.w : sg.z;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int i = s0 + n;
-          bv[n] = (i < N) ? t1[i - sg.z] * c0 + t1[i - j1] * c1 : T(0);
+          for (int n = 0; n < 4; ++n) {
+            T v = c0 * pz[uo + n];
+            if (pair) v += c1 * pw[uo + n];
+            acc[mt][n][r] = v;
+          }
         }
-      } else if constexpr (PF) {
+    } else {
 #pragma unroll
-        for (int n = 0; n < 4; ++n) bv[n] = xb[ks].v[n];
-      } else {
-        const V4<T> v = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
+        for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kc = 4 * ks + kq;
+        T bv[4];
+        if constexpr (PF) {
+#pragma unroll
+          for (int n = 0; n < 4; ++n) bv[n] = xb[ks].v[n];
+        } else {
+          const V4<T> v = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
+        }
+        T af[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = LAST ? Vt[kc * DP + 16 * mt + j] : F1[(ks * 64 + lane) * MT + mt];
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], bv[n], acc[mt][n]);
+        // keep the scheduler from hoisting every later operand load (register pressure)
+        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
-      T af[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) af[mt] = F1[(ks * 64 + lane) * MT + mt];
-#pragma unroll
-      for (int n = 0; n < 4; ++n)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], bv[n], acc[mt][n]);
-      // keep the scheduler from hoisting every later operand load (register pressure)
-      if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     // ---- x = chi0 q + [i in S_l] dchi (p0 + q)
     // slice positions of this lane's four sites (-1: outside S_l); the same for every channel
@@ -869,7 +698,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
       for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+          const T af = LAST ? Ut[(16 * mi + M::row(lane, r)) * DP + 16 * mo + j]
+                            : F2[((mo * 64 + lane) * MT + mi) * 4 + r];
 #pragma unroll
           for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
           if (r == 3) __builtin_amdgcn_sched_barrier(0);
@@ -880,14 +710,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
         T y[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
-        const V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
+        V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
+        if (LAST) {
+          const V4<T> t0 = ld4(A.tau + 2 * bo + o), t1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
+        }
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
           part0 += (double)w0.v[n] * (double)y[n];
           part1 += (double)w1.v[n] * (double)y[n];
         }
-        st4(A.out + fo + o, y);
+        if (LAST) {
+          const int ch = 16 * mo + M::row(lane, r);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) dh[ch * DH_LD + 4 * j + n] = y[n];
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          st4(A.out + fo + o, y);
+        }
       }
+    }
+    if (LAST) {
+      // partial slice of the last mixer's output from this tile; lane c owns channel c and
+      // runs a 16-entry register window over the taps h(x) = g^(L)(loL + x)
+      wave_sync();
+      int loL = sg.x - A.L * A.w_c;
+      if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+      const int c = lane, ib = 64 * t, cnt = min(64, N - ib);
+      T ya[SLICE_WIN], rg[SLICE_WIN];
+#pragma unroll
+      for (int u = 0; u < SLICE_WIN; ++u) ya[u] = 0;
+      if (c < DP) {
+        const T* tc = A.tapsL + (long)c * TS + TO + loL - ib;  // tc[u - k] = h(u - ib - k)
+#pragma unroll
+        for (int u = 0; u < SLICE_WIN; ++u) rg[u] = tc[u];
+        const T* xr = dh + c * DH_LD;
+        for (int k0 = 0; k0 < cnt; k0 += SLICE_WIN) {
+#pragma unroll
+          for (int u = 0; u < SLICE_WIN; ++u) {
+            const int k = k0 + u;
+            if (k < cnt) {
+              const T v = xr[k];
+#pragma unroll
+              for (int tt = 0; tt < SLICE_WIN; ++tt) ya[tt] += rg[(tt - u + SLICE_WIN * 4) % SLICE_WIN] * v;
+              rg[(SLICE_WIN * 4 - u - 1) % SLICE_WIN] = tc[-(k + 1)];
+            }
+          }
+        }
+        T* pp = A.slice_part + ((long)g * nt + t) * SLICE_WIN * DP + c;
+#pragma unroll
+        for (int u = 0; u < SLICE_WIN; ++u) pp[u * DP] = ya[u];
+      }
+      wave_sync();  // the tile in LDS is free for the next one
     }
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
@@ -897,6 +772,110 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
       rp[1] += part1;
     }
   }
+}
+
+// Finishes each flip after the tiled last block (one wave per flip): sums the tiles' partial
+// slices into y_L, forms e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, reads out e^(L)
+// and e^(0), adds the deep blocks' read-outs rho[f][t] and writes
+// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
+template <typename T, int DP>
+__global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  constexpr int MT = DP / 16, KS = DP / 4;
+  const int g = blockIdx.x;
+  if (g >= A.dyn.count(A.C)) return;
+  const int cfg0 = A.dyn.first(A.cfg0);
+  const int lane = threadIdx.x, j = lane & 15, kq = lane >> 4;
+  const int N = A.N, Np = A.Np, nt = Np / 64;
+  const int4 sg = A.geom[g];
+  const int bg = A.map.cb[cfg0 + g], m = A.map.cm[cfg0 + g];
+  const long bL = (long)(bg - A.b0) * DP * Np;
+  int loL = sg.x - A.L * A.w_c;
+  const int WL = sg.y + 2 * A.L * A.w_c + 1;
+  if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+  T* Y = reinterpret_cast<T*>(smem_raw);  // [DP][16]: Y[c][t]
+  T* X2 = Y + DP * SLICE_WIN;             // [DP][16]
+  const T* pp = A.slice_part + (long)g * nt * SLICE_WIN * DP;
+  for (int c = lane; c < DP; c += 64)
+    for (int t = 0; t < SLICE_WIN; ++t) {
+      T s = 0;
+      for (int tile = 0; tile < nt; ++tile) s += pp[((long)tile * SLICE_WIN + t) * DP + c];
+      Y[c * SLICE_WIN + t] = (t < WL) ? s : T(0);
+    }
+  wave_sync();
+  const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
+  const T* Ut = A.tb.Ut + (long)(A.L - 1) * DP * DP;
+  acc_t a2[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    const T bvv = Y[kc * SLICE_WIN + j];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Vt[kc * DP + 16 * mt + j], bvv, a2[mt]);
+  }
+  const int t_me = j;  // this lane's slice position (matrix-core column)
+  int site = loL + t_me;
+  bool valid = t_me < WL;
+  if (A.periodic) site %= N;
+  else valid = valid && site >= 0 && site < N;
+  const T* dchiL = A.dchi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ch = 16 * mt + M::row(lane, r);
+      T x = 0;
+      if (valid) x = dchiL[t_me * DP + ch] * (A.p0L[bL + (long)ch * Np + site] + a2[mt][r]);
+      X2[ch * SLICE_WIN + t_me] = x;
+    }
+  wave_sync();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) a2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kc = 4 * ks + kq;
+    const T bvv = X2[kc * SLICE_WIN + j];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Ut[kc * DP + 16 * mt + j], bvv, a2[mt]);
+  }
+  double o0 = 0.0, o1 = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + M::row(lane, r);
+        const long o = (long)ch * Np + site;
+        o0 += (double)A.tb.Wk[o] * (double)a2[mt][r];
+        o1 += (double)A.tb.Wk[(long)DP * Np + o] * (double)a2[mt][r];
+      }
+  }
+  // e^(0) = -2 s_j E on the cluster, read out directly (lanes over channels)
+  {
+    const int8_t* spb = A.spins + (long)bg * N;
+    for (int q = 0; q < 2; ++q) {
+      const int js = q == 0 ? sg.z : sg.w;
+      if (js < 0) continue;
+      for (int c = lane; c < DP; c += 64) {
+        const double e0 = (double)(-2 * spb[js]) * (double)A.tb.E[c];
+        o0 += (double)A.tb.Wk[(long)c * Np + js] * e0;
+        o1 += (double)A.tb.Wk[(long)DP * Np + (long)c * Np + js] * e0;
+      }
+    }
+  }
+  // read-outs of the tiled deep blocks (the last one included), lanes over tiles
+  for (int t = lane; t < nt; t += 64) {
+    o0 += A.rho[((long)g * nt + t) * 2];
+    o1 += A.rho[((long)g * nt + t) * 2 + 1];
+  }
+  o0 = wave_sum(o0);
+  o1 = wave_sum(o1);
+  if (lane == 0)
+    A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], o0) + lcd_d(A.Om0[2 * bg + 1], o1);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -292,4 +292,20 @@ __global__ void finite_check_kernel(const double* __restrict__ x, long n, int* _
     if (!isfinite(x[i])) atomicOr(bad, 1);
 }
 
+// First deep block of ABACUS for a unit flip: a flip at site z injects e^(0) = -2 s_z E there,
+// so the block's first channel-mixing product is q(i) = -2 s_z Pq(i - z) with the
+// parameter-only table Pq[k][r] = sum_c V^(1)[k][c] E_c g^(1)_c(r), formed here for every
+// stored offset r of the tap table (margins included). Vt is the operand table of V^(1)
+// (Vt[c][k] = V[k][c]).
+__global__ void ptab_kernel(const double* __restrict__ taps1, const double* __restrict__ Vt,
+                            const double* __restrict__ E, int DP, int TS, double* __restrict__ Pq) {
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long)DP * TS;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / TS), rr = (int)(idx % TS);
+    double acc = 0.0;
+    for (int c = 0; c < DP; ++c) acc += Vt[(long)c * DP + k] * E[c] * taps1[(long)c * TS + rr];
+    Pq[idx] = acc;
+  }
+}
+
 }  // namespace dn
