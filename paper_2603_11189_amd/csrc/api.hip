@@ -337,7 +337,7 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
 template <typename T, int DP, bool FIRST, bool LAST>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
-  const size_t lds = LAST ? (size_t)DEEP_WAVES * DP * DH_LD * sizeof(T) : 2 * (size_t)DP * DP * sizeof(T);
+  const size_t lds = (2 * (size_t)DP * DP + (LAST ? (size_t)DEEP_WAVES * std::min(DP, DH_CH) * DH_LD : 0)) * sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
     allow_lds(deep_kernel<T, DP, FIRST, LAST>, lds);

@@ -527,16 +527,19 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 // contiguous ranges (workgroup w runs on XCD w mod 8), so the flips of one sample, which
 // share their background caches, meet in the same L2. Each tile's read-out lands in
 // rho[f][t].
-// Blocks before the last keep both channel-mixing matrices in LDS in fragment order
-// (every operand read is one contiguous 64-lane access) and store du. The last block
-// (LAST) instead reads out dh with Wk + tau and, per tile, the partial slice of the last
-// mixer's output, part[f][t][s][c] = sum_{i' in tile} g^(L)_c(site_s - i') dh[c][i'],
-// from a channel-major copy of the tile in LDS (row stride DH_LD, odd, so the per-channel
-// reads hit distinct banks); last_finish_kernel completes the flip.
+// Every workgroup keeps both channel-mixing matrices in LDS in fragment order (every
+// operand read is one contiguous 64-lane access). Blocks before the last store du. The
+// last block (LAST) instead reads out dh with Wk + tau and forms, per tile, the partial
+// slice of the last mixer's output, part[f][t][s][c] = sum_{i' in tile} g^(L)_c(site_s - i')
+// dh[c][i'], 32 channels at a time from a channel-major copy in LDS (row stride DH_LD, odd,
+// so the per-channel reads hit distinct banks): lane (c, h) runs channel c over the h-th
+// part of the tile's sites with a register window over the taps, and the parts are added
+// across lanes. last_finish_kernel completes the flip.
 constexpr int DEEP_WAVES = 4;
 constexpr int NXCD = 8;
 constexpr int DEEP_OCC = 2;
 constexpr int DH_LD = 65;
+constexpr int DH_CH = 32;  // channels of the last block's LDS copy per group
 
 template <typename T, int DP, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC))) void deep_kernel(MixArgs<T> A) {
@@ -550,11 +553,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
   T* F2 = F1 + DP * DP;                     // [MT][64][MT][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
-  T* dh = reinterpret_cast<T*>(smem_raw) + wave * DP * DH_LD;  // LAST: this wave's dh tile
+  constexpr int CPG = DP < DH_CH ? DP : DH_CH;     // LAST: channels per slice group
+  T* dh = F2 + DP * DP + wave * CPG * DH_LD;       // LAST: this wave's [CPG][DH_LD] copy
   const int N = A.N, Np = A.Np, l = A.l;
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
-  if (!LAST)
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
     if (!FIRST) {  // the first block reads its phase-1 product from a table
       const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
@@ -566,7 +569,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
       F2[idx] = Ut[(16 * mi + M::row(ln, r)) * DP + 16 * mo + (ln & 15)];
     }
   }
-  if (!LAST) __syncthreads();  // the only workgroup barrier: the waves run independently from here
+  __syncthreads();  // the only workgroup barrier: the waves run independently from here
   const int F = A.dyn.count(A.C);
   const int cfg0 = A.dyn.first(A.cfg0);
   const int nt = Np / 64;
@@ -638,7 +641,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
         }
         T af[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) af[mt] = LAST ? Vt[kc * DP + 16 * mt + j] : F1[(ks * 64 + lane) * MT + mt];
+        for (int mt = 0; mt < MT; ++mt) af[mt] = F1[(ks * 64 + lane) * MT + mt];
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
@@ -689,67 +692,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
     }
     // ---- phase 2 per 16-channel output tile: du = U x, stored, and read out
     double part0 = 0.0, part1 = 0.0;
+    int loL = 0;
+    if (LAST) {
+      loL = sg.x - A.L * A.w_c;
+      if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
+    }
+    constexpr int GM = LAST ? CPG / 16 : 1;  // output tiles per group
 #pragma unroll 1
-    for (int mo = 0; mo < MT; ++mo) {
-      acc_t a2[4];
+    for (int mg = 0; mg < MT; mg += GM) {
+#pragma unroll 1
+      for (int mo = mg; mo < mg + GM; ++mo) {
+        acc_t a2[4];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
+        for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int mi = 0; mi < MT; ++mi)
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+            if (r == 3) __builtin_amdgcn_sched_barrier(0);
+          }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T af = LAST ? Ut[(16 * mi + M::row(lane, r)) * DP + 16 * mo + j]
-                            : F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+          const long o = lo_off + (16 * mo + M::r_row(r)) * Np;
+          T y[4];
 #pragma unroll
-          for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
-          if (r == 3) __builtin_amdgcn_sched_barrier(0);
-        }
+          for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
+          V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
+          if (LAST) {
+            const V4<T> t0 = ld4(A.tau + 2 * bo + o), t1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long o = lo_off + (16 * mo + M::r_row(r)) * Np;
-        T y[4];
+            for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
+          }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
-        V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
-        if (LAST) {
-          const V4<T> t0 = ld4(A.tau + 2 * bo + o), t1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
+          for (int n = 0; n < 4; ++n) {
+            part0 += (double)w0.v[n] * (double)y[n];
+            part1 += (double)w1.v[n] * (double)y[n];
+          }
+          if (LAST) {
+            const int cl = 16 * (mo - mg) + M::row(lane, r);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
-        }
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          part0 += (double)w0.v[n] * (double)y[n];
-          part1 += (double)w1.v[n] * (double)y[n];
-        }
-        if (LAST) {
-          const int ch = 16 * mo + M::row(lane, r);
-#pragma unroll
-          for (int n = 0; n < 4; ++n) dh[ch * DH_LD + 4 * j + n] = y[n];
-          __builtin_amdgcn_sched_barrier(0);
-        } else {
-          st4(A.out + fo + o, y);
+            for (int n = 0; n < 4; ++n) dh[cl * DH_LD + 4 * j + n] = y[n];
+            __builtin_amdgcn_sched_barrier(0);
+          } else {
+            st4(A.out + fo + o, y);
+          }
         }
       }
-    }
-    if (LAST) {
-      // partial slice of the last mixer's output from this tile; lane c owns channel c and
-      // runs a 16-entry register window over the taps h(x) = g^(L)(loL + x)
-      wave_sync();
-      int loL = sg.x - A.L * A.w_c;
-      if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
-      const int c = lane, ib = 64 * t, cnt = min(64, N - ib);
-      T ya[SLICE_WIN], rg[SLICE_WIN];
+      if (LAST) {
+        // partial slice of the last mixer's output from this tile and channel group; the
+        // window holds h(x) = g^(L)(loL + x): tc[u - k] = h(u - ib - k)
+        wave_sync();
+        constexpr int NPART = 64 / CPG, K = CPG;  // lanes (c, h): sites h K .. h K + K - 1
+        const int c = lane % CPG, hp = lane / CPG, cg = 16 * mg + c;
+        const int ib = 64 * t, cnt = min(64, N - ib), k0 = hp * K;
+        T ya[SLICE_WIN], rg[SLICE_WIN];
 #pragma unroll
-      for (int u = 0; u < SLICE_WIN; ++u) ya[u] = 0;
-      if (c < DP) {
-        const T* tc = A.tapsL + (long)c * TS + TO + loL - ib;  // tc[u - k] = h(u - ib - k)
+        for (int u = 0; u < SLICE_WIN; ++u) ya[u] = 0;
+        const T* tc = A.tapsL + (long)cg * TS + TO + loL - ib;
 #pragma unroll
-        for (int u = 0; u < SLICE_WIN; ++u) rg[u] = tc[u];
+        for (int u = 0; u < SLICE_WIN; ++u) rg[u] = tc[u - k0];
         const T* xr = dh + c * DH_LD;
-        for (int k0 = 0; k0 < cnt; k0 += SLICE_WIN) {
+        for (int kb = k0; kb < k0 + K && kb < cnt; kb += SLICE_WIN) {
 #pragma unroll
           for (int u = 0; u < SLICE_WIN; ++u) {
-            const int k = k0 + u;
+            const int k = kb + u;
             if (k < cnt) {
               const T v = xr[k];
 #pragma unroll
@@ -758,11 +767,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
             }
           }
         }
-        T* pp = A.slice_part + ((long)g * nt + t) * SLICE_WIN * DP + c;
 #pragma unroll
-        for (int u = 0; u < SLICE_WIN; ++u) pp[u * DP] = ya[u];
+        for (int sh = CPG; sh < 64; sh <<= 1)
+#pragma unroll
+          for (int u = 0; u < SLICE_WIN; ++u) ya[u] += __shfl_xor(ya[u], sh, 64);
+        if (hp == 0) {
+          T* pp = A.slice_part + ((long)g * nt + t) * SLICE_WIN * DP + cg;
+#pragma unroll
+          for (int u = 0; u < SLICE_WIN; ++u) pp[u * DP] = ya[u];
+        }
+        wave_sync();  // the copy in LDS is free for the next group
       }
-      wave_sync();  // the tile in LDS is free for the next one
     }
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
