@@ -212,7 +212,7 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
             get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, L * DP * tap_stride(Np)) &&
             get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP) &&
-            get(&tb.Pq, DP * tap_stride(Np));
+            get(&tb.Pq, 4 * DP * tap_stride(Np));
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
                     tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm, tb.Pq};
@@ -221,7 +221,7 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
 
 long table_elems(const dn_model& m) {
   const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
-  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + (2 * L + 1) * DP * tap_stride(Np) + 2 * DP * Np;
+  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + (2 * L + 4) * DP * tap_stride(Np) + 2 * DP * Np;
 }
 
 // Copy double tables into float tables (same member order).
@@ -235,7 +235,7 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
       {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, L * DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np},
-      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, DP * tap_stride(Np)}};
+      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, 4 * DP * tap_stride(Np)}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
     convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);

@@ -17,7 +17,7 @@ template <typename T> struct Tables {
   const T *taps, *tapsR;                   // [L][DP][tap_stride]: mixers and their transposes
   const T *Wk;                             // [2][DP][Np]
   const T *ADm, *WDm;                      // operand tables of A_D^T and W_D^T
-  const T *Pq;                             // [DP][tap_stride]: V^(1) (E * g^(1)(r)), see ptab_kernel
+  const T *Pq;                             // [4][DP][tap_stride]: V^(1) (E * g^(1)(r)), see ptab_kernel
 };
 
 // Which configuration a block works on. Plain path: cfg g -> sample b, element m (m = -1
@@ -608,19 +608,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
       const T c0 = (T)(-2 * sp[sg.z]);
       const bool pair = sg.w >= 0;
       const T c1 = pair ? (T)(-2 * sp[sg.w]) : T(0);
-      const T* pz = A.tb.Pq + (long)lrow * TS + TO + s0 - sg.z;
-      const T* pw = A.tb.Pq + (long)lrow * TS + TO + s0 - (pair ? sg.w : sg.z);
+      // the copy shifted by (TO - z) mod 4 makes the four sites one aligned vector
+      const int z1 = pair ? sg.w : sg.z, shz = (TO - sg.z) & 3, shw = (TO - z1) & 3;
+      const T* pz = A.tb.Pq + ((long)shz * DP + lrow) * TS + TO + s0 - sg.z - shz;
+      const T* pw = A.tb.Pq + ((long)shw * DP + lrow) * TS + TO + s0 - z1 - shw;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int uo = (16 * mt + M::r_row(r)) * TS;
+          const V4<T> vz = ld4(pz + uo);
+          V4<T> vw{};
+          if (pair) vw = ld4(pw + uo);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            T v = c0 * pz[uo + n];
-            if (pair) v += c1 * pw[uo + n];
-            acc[mt][n][r] = v;
-          }
+          for (int n = 0; n < 4; ++n) acc[mt][n][r] = c0 * vz.v[n] + c1 * vw.v[n];
         }
     } else {
 #pragma unroll

@@ -295,16 +295,20 @@ __global__ void finite_check_kernel(const double* __restrict__ x, long n, int* _
 // First deep block of ABACUS for a unit flip: a flip at site z injects e^(0) = -2 s_z E there,
 // so the block's first channel-mixing product is q(i) = -2 s_z Pq(i - z) with the
 // parameter-only table Pq[k][r] = sum_c V^(1)[k][c] E_c g^(1)_c(r), formed here for every
-// stored offset r of the tap table (margins included). Vt is the operand table of V^(1)
+// stored offset r of the tap table (margins included). It is stored four times, copy sh
+// shifted by sh entries (Pq4[sh][k][r] = Pq[k][r + sh]), so that four consecutive sites can
+// be read as one aligned vector whatever z is. Vt is the operand table of V^(1)
 // (Vt[c][k] = V[k][c]).
 __global__ void ptab_kernel(const double* __restrict__ taps1, const double* __restrict__ Vt,
-                            const double* __restrict__ E, int DP, int TS, double* __restrict__ Pq) {
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long)DP * TS;
+                            const double* __restrict__ E, int DP, int TS, double* __restrict__ Pq4) {
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < 4L * DP * TS;
        idx += (long)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / TS), rr = (int)(idx % TS);
+    const int sh = (int)(idx / ((long)DP * TS));
+    const int k = (int)((idx / TS) % DP), rr = (int)(idx % TS) + sh;
     double acc = 0.0;
-    for (int c = 0; c < DP; ++c) acc += Vt[(long)c * DP + k] * E[c] * taps1[(long)c * TS + rr];
-    Pq[idx] = acc;
+    if (rr < TS)
+      for (int c = 0; c < DP; ++c) acc += Vt[(long)c * DP + k] * E[c] * taps1[(long)c * TS + rr];
+    Pq4[idx] = acc;
   }
 }
 
