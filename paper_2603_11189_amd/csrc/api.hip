@@ -530,28 +530,35 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
                           (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
   const size_t flips_budget = std::max<size_t>(1024, ((size_t)3 << 30) / per_flip);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
-  for (int b0 = 0; b0 < B; b0 += Bc_max) {
-    const int Bc = std::min(Bc_max, B - b0);
+  // background samples per forward chunk: its caches (a0, chi0, p0 per block, tau and its
+  // mixer input) take (3L + 4) fields per sample; a large chunk keeps the forward launches
+  // wide, the flips then run in chunks of Bc_max samples inside it
+  const size_t per_sample = (size_t)(3 * L + 4) * DP * Np * sizeof(T);
+  const int Bf_max = (int)std::max<size_t>(1, std::min<size_t>(B, ((size_t)6 << 30) / per_sample));
+  for (int bf0 = 0; bf0 < B; bf0 += Bf_max) {
+  const int Bf = std::min(Bf_max, B - bf0);
+  const long fldB = (long)Bf * DP * Np;
+  void *pa, *pc, *pp, *ptz, *ptau;
+  STCHK(ws_get(m, "ab_a0", (size_t)L * fldB * sizeof(T), &pa));
+  STCHK(ws_get(m, "ab_chi0", (size_t)L * fldB * sizeof(T), &pc));
+  STCHK(ws_get(m, "ab_p0", (size_t)L * fldB * sizeof(T), &pp));
+  STCHK(ws_get(m, "ab_tz", (size_t)2 * fldB * sizeof(T), &ptz));
+  STCHK(ws_get(m, "ab_tau", (size_t)2 * fldB * sizeof(T), &ptau));
+  T *a0 = (T*)pa, *chi0 = (T*)pc, *p0 = (T*)pp, *tz = (T*)ptz, *tau = (T*)ptau;
+  STCHK((forward_chunk<T, DP>(m, spins, idmap, bf0, Bf, Om0 + 2L * bf0, a0, chi0, p0, st)));
+  // tau = G^(L)T D0^(L)T Wk
+  {
+    MixArgs<T> a{};
+    a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
+    a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bf; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
+    STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bf, st)));
+    STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bf, st));
+  }
+  for (int b0 = bf0; b0 < bf0 + Bf; b0 += Bc_max) {
+    const int Bc = std::min(Bc_max, bf0 + Bf - b0);
     const int f0 = h_offs ? h_offs[b0] : 0;
     const int F = h_offs ? h_offs[b0 + Bc] - f0 : Bc * M_max;
     const DynRange dyn{h_offs ? nullptr : offs, b0, Bc};
-    const long fldB = (long)Bc * DP * Np;
-    void *pa, *pc, *pp, *ptz, *ptau;
-    STCHK(ws_get(m, "ab_a0", (size_t)L * fldB * sizeof(T), &pa));
-    STCHK(ws_get(m, "ab_chi0", (size_t)L * fldB * sizeof(T), &pc));
-    STCHK(ws_get(m, "ab_p0", (size_t)L * fldB * sizeof(T), &pp));
-    STCHK(ws_get(m, "ab_tz", (size_t)2 * fldB * sizeof(T), &ptz));
-    STCHK(ws_get(m, "ab_tau", (size_t)2 * fldB * sizeof(T), &ptau));
-    T *a0 = (T*)pa, *chi0 = (T*)pc, *p0 = (T*)pp, *tz = (T*)ptz, *tau = (T*)ptau;
-    STCHK((forward_chunk<T, DP>(m, spins, idmap, b0, Bc, Om0 + 2L * b0, a0, chi0, p0, st)));
-    // tau = G^(L)T D0^(L)T Wk
-    {
-      MixArgs<T> a{};
-      a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
-      a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bc; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
-      STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bc, st)));
-      STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bc, st));
-    }
     if (F == 0) continue;
     void *pdchi, *pgeom, *prho, *pdu, *pw;
     STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
@@ -564,7 +571,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     {
       SliceArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
-      a.act = d.act; a.F = F; a.f0 = f0; a.b0 = b0; a.Bc = Bc; a.map = fmap; a.spins = spins;
+      a.act = d.act; a.F = F; a.f0 = f0; a.b0 = bf0; a.Bc = Bf; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
       a.dyn = dyn;
       const size_t lds = 2 * (size_t)Wmax * DP * sizeof(T);
@@ -587,7 +594,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
         a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
         a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_nt = nt;
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
-        a.out = du; a.rho = rho; a.map = fmap; a.b0 = b0; a.spins = spins; a.geom = geom;
+        a.out = du; a.rho = rho; a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
         a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
         a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.slice_part = (T*)psp;
@@ -606,7 +613,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     if (L == 1) {
       TailArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
-      a.F = F; a.f0 = f0; a.b0 = b0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
+      a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
       a.yL = nullptr; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
       a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax; a.dyn = dyn;
       const int WL = 2 * L * wc + 1;
@@ -614,6 +621,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       tail_kernel<T, DP><<<F, 64, 2 * DP * sizeof(T), st>>>(a);
       HIPCHK(hipGetLastError());
     }
+  }
   }
   if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(Om0, nullptr, B, logpsi);
   HIPCHK(hipGetLastError());
