@@ -26,7 +26,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "fp64": 78.6}  # dense MFMA TFLOP/s of one MI355X
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}  # dense MFMA TFLOP/s of one MI355X
 HBM_PEAK = 8000.0                      # GB/s
 
 
@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tfim_n256_l4_d64")
     ap.add_argument("--scale", default="baseline", choices=["baseline", "stress"])
+    ap.add_argument("--prec", default="", choices=["", "fp64", "fp32", "bf16"],
+                    help="arithmetic mode (default: the workload's own)")
     ap.add_argument("--paths", default="abacus,full")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -159,7 +161,7 @@ def main():
         return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
-    prec = w.prec if w.prec != "bf16" else "fp32"
+    prec = args.prec or w.prec
     B = w.B
     M_max = shape.N if ham.kind == "lrtfim" else 2 * shape.N
     theta = torch.tensor(w.params(args.scale))
@@ -235,7 +237,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mixed (bf16 channel mixing, f32 accumulate)"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "N": shape.N, "L": shape.L, "d": shape.d, "s": shape.s,
                    "B": B, "hamiltonian": f"{ham.kind} {ham.bc} J={ham.J} alpha={ham.alpha} h={ham.h}"
@@ -265,7 +267,7 @@ def main():
         dom = max(prof, key=lambda k: prof[k][0])
         ms, n, fl, by = prof[dom]
         achieved = fl / (ms * 1e-3) / 1e12
-        peak = PEAK["fp32" if prec == "fp32" else "fp64"]
+        peak = PEAK[prec]
         traffic = None
         tpath = os.path.join(ROOT, "profiles", "traffic.json")
         if os.path.exists(tpath):

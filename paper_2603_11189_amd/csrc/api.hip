@@ -311,8 +311,11 @@ template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>
   return DN_OK;
 }
 
+// Channel mixing on the bf16 matrix cores (DN_PREC_BF16_MIXED; float fields, d > 16).
+bool use_bf16(const dn_model* m) { return m->desc.prec == DN_PREC_BF16_MIXED; }
+
 template <typename T, int DP, int MODE>
-dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
+dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, bool allow_bf = true) {
   if (C <= 0) return DN_OK;
   const int nw = m->Np / 64;
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T), fld = Nr * dr * e;
@@ -327,24 +330,31 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st) {
     by = C * fld + (C / 2) * fld;
   }
   PScope ps(m, kind, st, fl, by);
-  mix_kernel<T, DP, MODE><<<C, 64 * nw, 0, st>>>(a);
+  bool done = false;
+  if constexpr (std::is_same<T, float>::value && DP >= 32) {
+    if (allow_bf && use_bf16(m)) {
+      mix_kernel<T, DP, MODE, true><<<C, 64 * nw, 0, st>>>(a);
+      done = true;
+    }
+  }
+  if (!done) mix_kernel<T, DP, MODE, false><<<C, 64 * nw, 0, st>>>(a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
 
 // Persistent tiled launch of a deep block (see deep_kernel); the last one is followed by
 // last_finish_kernel, one wave per flip.
-template <typename T, int DP, bool FIRST, bool LAST>
+template <typename T, int DP, bool FIRST, bool LAST, bool BF>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
   const size_t lds = (2 * (size_t)DP * DP + (LAST ? (size_t)DEEP_WAVES * std::min(DP, DH_CH) * DH_LD : 0)) * sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
-    allow_lds(deep_kernel<T, DP, FIRST, LAST>, lds);
+    allow_lds(deep_kernel<T, DP, FIRST, LAST, BF>, lds);
     int dev = 0, n = 0, c = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST, LAST>, 256, lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST, LAST, BF>, 256, lds));
     cus = std::max(c, 1);
     per_cu = std::max(n, 1);
   }
@@ -358,7 +368,7 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
     const double fl = 4.0 * F * Nr * dr * dr + (LAST ? 2.0 * F * WL * Nr * dr : 0.0);
     const double by = F * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
     PScope ps(m, DN_K_MIX_DEEP, st, fl, by);
-    deep_kernel<T, DP, FIRST, LAST><<<(int)grid, 256, lds, st>>>(a);
+    deep_kernel<T, DP, FIRST, LAST, BF><<<(int)grid, 256, lds, st>>>(a);
     HIPCHK(hipGetLastError());
   }
   if (LAST) {
@@ -368,6 +378,22 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
     HIPCHK(hipGetLastError());
   }
   return DN_OK;
+}
+
+template <typename T, int DP, bool BF>
+dn_status launch_deep_mode(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
+  if (first && last) return launch_deep<T, DP, true, true, BF>(m, a, F, st, Bc);
+  if (last) return launch_deep<T, DP, false, true, BF>(m, a, F, st, Bc);
+  if (first) return launch_deep<T, DP, true, false, BF>(m, a, F, st, Bc);
+  return launch_deep<T, DP, false, false, BF>(m, a, F, st, Bc);
+}
+
+template <typename T, int DP>
+dn_status launch_deep_any(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
+  if constexpr (std::is_same<T, float>::value && DP >= 32) {
+    if (use_bf16(m)) return launch_deep_mode<T, DP, true>(m, a, F, st, Bc, first, last);
+  }
+  return launch_deep_mode<T, DP, false>(m, a, F, st, Bc, first, last);
 }
 
 // Forward of C configurations listed by `map` entries [cfg0, cfg0+C). rho[C][2] receives
@@ -421,7 +447,8 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
     a.X = v; a.chi = chi_of(l); a.p0_out = cache_p0 ? cache_p0 + (long)l * fld : nullptr;
     a.phi_next = phi; a.out = (l + 1 < L) ? (ck.h ? ck.h + (long)(l + 1) * fld : u) : nullptr; a.rho = rho;
     a.R_acc = ck.R;
-    STCHK((launch_mix<T, DP, MIX_FWD>(m, a, C, st)));
+    // the gradient's forward (checkpoints) stays in float: its backward is float
+    STCHK((launch_mix<T, DP, MIX_FWD>(m, a, C, st, ck.h == nullptr)));
   }
   return DN_OK;
 }
@@ -603,10 +630,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
         // l-1 is the 0-based index of block l in the tables
         a.l = l;
         dn_status s;
-        if (first && last) s = launch_deep<T, DP, true, true>(m, a, F, st, Bc);
-        else if (last) s = launch_deep<T, DP, false, true>(m, a, F, st, Bc);
-        else if (first) s = launch_deep<T, DP, true, false>(m, a, F, st, Bc);
-        else s = launch_deep<T, DP, false, false>(m, a, F, st, Bc);
+        s = launch_deep_any<T, DP>(m, a, F, st, Bc, first, last);
         STCHK(s);
       }
     }
@@ -780,7 +804,7 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
       MixArgs<T> a{};
       a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.C = Bc; a.cfg0 = b0; a.X = tv; a.chi = tchi; a.p0_out = tq; a.out = nullptr; a.rho = rho2;
-      STCHK((launch_mix<T, DP, MIX_FWD>(m, a, Bc, st)));
+      STCHK((launch_mix<T, DP, MIX_FWD>(m, a, Bc, st, false)));
     }
     // vertex and channel mixing backward
     {
@@ -1172,7 +1196,8 @@ dn_status dn_model_create(const dn_model_desc* desc, dn_model** out) {
   if (!out) return fail(DN_EINVAL, "null output handle");
   *out = nullptr;
   if (!check_desc(desc, &why)) return fail(desc ? DN_EUNSUPPORTED : DN_EINVAL, why);
-  if (desc->prec == DN_PREC_BF16_MIXED) return fail(DN_EUNSUPPORTED, "BF16-mixed precision is not implemented");
+  if (desc->prec == DN_PREC_BF16_MIXED && desc->d <= 16)
+    return fail(DN_EUNSUPPORTED, "BF16-mixed precision needs d > 16 (k-steps of 32 channels)");
   dn_model* m = new dn_model();
   m->desc = *desc;
   layout_of(*desc, &m->lay);

@@ -35,6 +35,15 @@ template <> struct Mma<double> {
   __device__ static inline int r_row(int r) { return 4 * r; }
 };
 
+// 16x16x32 bf16 matrix-core tile (gfx950) with float accumulation. Operand A (16 x 32): lane l
+// holds A[l % 16][8 (l / 16) + e], e = 0..7; operand B (32 x 16): lane l holds
+// B[8 (l / 16) + e][l % 16]; the accumulator is laid out as Mma<float> (row 4 (l / 16) + r,
+// column l % 16). float -> bf16 conversion rounds to nearest even.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ inline f4 mma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // Green's-function tap tables: per channel TS = 2 Np + 128 entries, offset r = i - i' stored
 // at r + TOFF. Offsets |r| < N hold the taps (periodic chains: the aliased g(r mod N) for every
 // stored r); the 64-entry margins let slice windows run past the chain ends without bounds

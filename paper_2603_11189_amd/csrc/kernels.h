@@ -407,7 +407,9 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int DP, int MODE>
+// BF (float fields only): both channel-mixing products on the bf16 matrix cores with float
+// accumulation (operands rounded to bf16 as they are formed; fields stay float).
+template <typename T, int DP, int MODE, bool BF>
 __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
@@ -432,17 +434,40 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+  if constexpr (BF) {
+    // k-step s covers channels 32 s + 8 kq + e on lane group kq
+#pragma unroll
+    for (int s = 0; s < DP / 32; ++s) {
+      V4<T> xv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xv[e] = ld4(X + (long)(32 * s + 8 * kq + e) * Np + s0);
+      bf8 bb[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bb[n][e] = (__bf16)xv[e].v[n];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        bf8 af;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) af[e] = (__bf16)M1[(32 * s + 8 * kq + e) * DP + 16 * mt + j];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[mt][n] = mma_bf16(af, bb[n], acc[mt][n]);
+      }
+    }
+  } else {
 #pragma unroll 4
-  for (int ks = 0; ks < KS; ++ks) {
-    const int kc = 4 * ks + kq;
-    const V4<T> v = ld4(X + (long)kc * Np + s0);
-    T af[MT];
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + kq;
+      const V4<T> v = ld4(X + (long)kc * Np + s0);
+      T af[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) af[mt] = M1[kc * DP + 16 * mt + j];
+      for (int mt = 0; mt < MT; ++mt) af[mt] = M1[kc * DP + 16 * mt + j];
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+      for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], v.v[n], acc[mt][n]);
+        for (int mt = 0; mt < MT; ++mt) acc[mt][n] = M::mma(af[mt], v.v[n], acc[mt][n]);
+    }
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -458,6 +483,17 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 #pragma unroll
       for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? c.v[n] * q[n] : T(0);
     }
+  // BF: x as bf16 operands of phase 2, in accumulator channel order (step s: channels
+  // 16 (2 s + e / 4) + row(lane, e mod 4))
+  bf8 xh[BF ? DP / 32 : 1][4];
+  if constexpr (BF) {
+#pragma unroll
+    for (int s = 0; s < DP / 32; ++s)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xh[s][n][e] = (__bf16)acc[2 * s + (e >> 2)][n][e & 3];
+  }
   // ---- phase 2, one 16-channel output tile at a time
   double part0 = 0.0, part1 = 0.0;
 #pragma unroll 1
@@ -465,14 +501,26 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
     acc_t a2[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
+    if constexpr (BF) {
 #pragma unroll
-    for (int mi = 0; mi < MT; ++mi)
+      for (int s = 0; s < DP / 32; ++s) {
+        bf8 af;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const T af = M2[(16 * mi + M::row(lane, r)) * DP + 16 * mo + j];
+        for (int e = 0; e < 8; ++e)
+          af[e] = (__bf16)M2[(16 * (2 * s + (e >> 2)) + M::row(lane, e & 3)) * DP + 16 * mo + j];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+        for (int n = 0; n < 4; ++n) a2[n] = mma_bf16(af, xh[s][n], a2[n]);
       }
+    } else {
+#pragma unroll
+      for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T af = M2[(16 * mi + M::row(lane, r)) * DP + 16 * mo + j];
+#pragma unroll
+          for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+        }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int ch = 16 * mo + M::row(lane, r);
@@ -537,18 +585,22 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 // across lanes. last_finish_kernel completes the flip.
 constexpr int DEEP_WAVES = 4;
 constexpr int NXCD = 8;
-constexpr int DEEP_OCC = 2;
+// waves per SIMD each variant's register budget is sized for
+constexpr int deep_occ(int elem_bytes, bool prefetch) { return elem_bytes == 4 && !prefetch ? 3 : 2; }
+constexpr bool DEEP_PF = true;  // register prefetch of the next tile in the blocks between first and last
 constexpr int DH_LD = 65;
 constexpr int DH_CH = 32;  // channels of the last block's LDS copy per group
 
-template <typename T, int DP, bool FIRST, bool LAST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC))) void deep_kernel(MixArgs<T> A) {
+// BF (float fields only): both channel-mixing products on the bf16 matrix cores with float
+// accumulation, the weight fragments held in LDS as bf16.
+template <typename T, int DP, bool FIRST, bool LAST, bool BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST)))) void deep_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  constexpr int MT = DP / 16, KS = DP / 4;
+  constexpr int MT = DP / 16, KS = DP / 4, KB = DP / 32;
   // the next tile's input is prefetched into registers unless that would not fit
-  constexpr bool PF = !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
+  constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
   T* F1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of V, phase 1
   T* F2 = F1 + DP * DP;                     // [MT][64][MT][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -558,6 +610,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
   const int N = A.N, Np = A.Np, l = A.l;
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
+  __bf16* F1h = reinterpret_cast<__bf16*>(F1);  // BF: [KB][MT][64][8]
+  __bf16* F2h = reinterpret_cast<__bf16*>(F2);  // BF: [MT][KB][64][8]
+  if constexpr (BF)
+  for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
+    const int e = idx & 7, ln = (idx >> 3) & 63, hi = idx >> 9;
+    if (!FIRST) {
+      const int mt = hi % MT, sk = hi / MT;
+      F1h[idx] = (__bf16)Vt[(32 * sk + 8 * (ln >> 4) + e) * DP + 16 * mt + (ln & 15)];
+    }
+    const int sk = hi % KB, mo = hi / KB;
+    F2h[idx] = (__bf16)Ut[(16 * (2 * sk + (e >> 2)) + M::row(ln, e & 3)) * DP + 16 * mo + (ln & 15)];
+  }
+  else
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
     if (!FIRST) {  // the first block reads its phase-1 product from a table
       const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
@@ -583,11 +648,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
   // Addresses are a per-lane base plus an offset that is the same for every lane (kept in
   // scalar registers), so that no per-lane 64-bit offsets stay live across the tile loop.
   const int lrow = M::lane_row(lane);
+  // input row of slot ks on this lane: kq_row + urow(ks) (bf16 steps take 8 rows per lane group)
+  const int kq_row = BF ? 8 * kq : kq;
+  auto urow = [](int ks) { return BF ? 32 * (ks >> 3) + (ks & 7) : 4 * ks; };
   V4<T> xb[PF ? KS : 1];
   if (PF && q < q_hi) {
-    const T* src = A.X + (q / nt) * DP * Np + 64 * (q % nt) + kq * Np + 4 * j;
+    const T* src = A.X + (q / nt) * DP * Np + 64 * (q % nt) + kq_row * Np + 4 * j;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + 4 * ks * Np);
+    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
   }
   for (; q < q_hi; q += wstride) {
     // compiler-only barrier: the weight operands are reloaded per tile rather than hoisted
@@ -622,7 +690,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
           if (pair) vw = ld4(pw + uo);
 #pragma unroll
           for (int n = 0; n < 4; ++n) acc[mt][n][r] = c0 * vz.v[n] + c1 * vw.v[n];
+          if (r == 3) __builtin_amdgcn_sched_barrier(0);
         }
+    } else if constexpr (BF) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int sk = 0; sk < KB; ++sk) {
+        bf8 bb[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int ks = 8 * sk + e;
+          V4<T> v;
+          if constexpr (PF) v = xb[ks];
+          else v = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) bb[n][e] = (__bf16)v.v[n];
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const bf8 af = reinterpret_cast<const bf8*>(F1h)[(sk * MT + mt) * 64 + lane];
+#pragma unroll
+          for (int n = 0; n < 4; ++n) acc[mt][n] = mma_bf16(af, bb[n], acc[mt][n]);
+        }
+      }
     } else {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -687,9 +780,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
     // the next tile's input travels while this one is mixed and stored
     if (PF && q + wstride < q_hi) {
       const long qn = q + wstride;
-      const T* src = A.X + (qn / nt) * DP * Np + 64 * (qn % nt) + kq * Np + 4 * j;
+      const T* src = A.X + (qn / nt) * DP * Np + 64 * (qn % nt) + kq_row * Np + 4 * j;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + 4 * ks * Np);
+      for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
+    }
+    // BF: x as bf16 operands of phase 2, in accumulator channel order (step sk: channels
+    // 16 (2 sk + e / 4) + row(lane, e mod 4))
+    bf8 xh[BF ? KB : 1][4];
+    if constexpr (BF) {
+#pragma unroll
+      for (int sk = 0; sk < KB; ++sk)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) xh[sk][n][e] = (__bf16)acc[2 * sk + (e >> 2)][n][e & 3];
     }
     // ---- phase 2 per 16-channel output tile: du = U x, stored, and read out
     double part0 = 0.0, part1 = 0.0;
@@ -706,15 +810,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP_OCC)))
         acc_t a2[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
+        if constexpr (BF) {
 #pragma unroll
-        for (int mi = 0; mi < MT; ++mi)
+          for (int sk = 0; sk < KB; ++sk) {
+            const bf8 af = reinterpret_cast<const bf8*>(F2h)[(mo * KB + sk) * 64 + lane];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
-            if (r == 3) __builtin_amdgcn_sched_barrier(0);
+            for (int n = 0; n < 4; ++n) a2[n] = mma_bf16(af, xh[sk][n], a2[n]);
           }
+        } else {
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+#pragma unroll
+              for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
+              if (r == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const long o = lo_off + (16 * mo + M::r_row(r)) * Np;
