@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the per-sample log-derivative leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuner)")
+    ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
@@ -186,6 +188,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = None
+    if args.shapes:
+        nt, mib = (int(x) for x in args.shapes.split(","))
+        model.set_launch_shapes(nt, mib << 20)
+        tuned = {"conv_tiles_per_wave": nt, "flip_chunk_MiB": mib, "set_by": "--shapes"}
+    elif not args.no_tune:
+        t0 = time.perf_counter()
+        nt, bud = model.autotune(ham)
+        tuned = {"conv_tiles_per_wave": nt, "flip_chunk_MiB": bud >> 20,
+                 "tuning_s": round(time.perf_counter() - t0, 3)}
+        log(f"[bench] autotuned launch shapes: {tuned}")
     results = {}
     for path in args.paths.split(","):
         log(f"[bench] {args.workload} path={path} warmup={args.warmup}")
@@ -245,6 +258,7 @@ def main():
                    "params": f"N(0,0.1^2) seed {w.param_seed}" if args.scale == "baseline" else "stress draw",
                    "path": main_path},
         "set_params_ms": set_params_ms,
+        "launch_shapes": tuned or "defaults",
     }
     if grad:
         out["grad_logpsi"] = grad

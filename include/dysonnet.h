@@ -47,10 +47,12 @@ typedef enum {
 typedef enum { DN_BC_OPEN = 0, DN_BC_PERIODIC = 1 } dn_bc;
 typedef enum { DN_ACT_SILU = 0, DN_ACT_TANH = 1, DN_ACT_IDENTITY = 2 } dn_act;
 /* Arithmetic of the network fields and channel mixing. FP64: everything float64.
- * FP32: float32 fields, float32 MFMA with float32 accumulation. BF16_MIXED: the channel
- * mixing products take bfloat16 operands (round to nearest even) with float32
- * accumulation; everything else as FP32. Kernel generation, the read-out sums and the
- * log-ratio are float64 in every mode. */
+ * FP32: float32 fields, float32 MFMA with float32 accumulation. BF16_MIXED (d > 16): the
+ * two channel-mixing products of every block (V and U: forward, adjoint and the ABACUS
+ * propagation) take bfloat16 operands (round to nearest even) on the bf16 matrix cores
+ * with float32 accumulation; everything else as FP32 (phi stream, Green's-function mixer,
+ * slices; per-sample gradients run entirely in float32). Kernel generation, the read-out
+ * sums and the log-ratio are float64 in every mode. */
 typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_prec;
 typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
 
@@ -94,8 +96,9 @@ typedef struct dn_model dn_model; /* opaque */
 int64_t dn_param_count(const dn_model_desc* desc);
 
 /* Create a model (no parameters yet). Validates the shape; DN_EUNSUPPORTED for shapes
- * the kernels do not cover (d > 64, s > 32, d_out != 2, N > 512, or a float64 field of
- * one configuration larger than the on-chip tile). *out receives the handle. */
+ * the kernels do not cover (d > 64, s > 32, d_out != 2, N > 512, a float64 field of one
+ * configuration larger than the on-chip tile, or BF16_MIXED with d <= 16). *out receives
+ * the handle. */
 dn_status dn_model_create(const dn_model_desc* desc, dn_model** out);
 
 /* Cap the workspace the model may allocate (bytes; 0 = no cap). Calls that would need
@@ -159,6 +162,24 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
 dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
                          const double* weights, double* wsum, void* stream);
 
+/* Launch-shape autotuner: times the ABACUS estimator (dn_eloc) of this model on B_probe
+ * synthetic configurations (spins from an integer hash, generated on the device) for each
+ * candidate launch shape and keeps the fastest for every later call on the model: the
+ * number of 16-site output tiles per wave of the Toeplitz kernel (1..4) and the size of the
+ * ABACUS flip chunks (256 MiB, 1 GiB or 3 GiB of flip fields; smaller chunks can stay in
+ * the last-level cache, larger ones launch fewer, wider grids). The search is coordinate-wise
+ * (tiles first, then chunk size). conv_nt_out and flip_budget_out (nullable) receive the
+ * choice. Synchronises the stream; grows the workspace as the candidates need. The Ising
+ * model's M_max is N, the J1-J2 chain's 2N. Supports what dn_eloc's ABACUS path supports. */
+dn_status dn_autotune(dn_model* m, const dn_ham_desc* ham, int32_t B_probe, int32_t* conv_nt_out,
+                      int64_t* flip_budget_out, void* stream);
+
+/* Set the launch shapes dn_autotune would choose, by hand: conv_nt 16-site output tiles per
+ * wave of the Toeplitz kernel (0 = by chain length; else 1..4 with the chain length rounded
+ * up to 64 a multiple of 16 conv_nt, DN_EINVAL otherwise) and flip_budget bytes of flip
+ * fields per ABACUS chunk (0 = 3 GiB). Marks the model as tuned. */
+dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget);
+
 /* Execution modes of dn_ragged_eloc. */
 typedef enum {
   DN_RAGGED_EAGER = 0, /* launch every instance's kernels on each call */
@@ -175,7 +196,8 @@ typedef enum {
  * least-loaded stream. In DN_RAGGED_GRAPH mode the first call with a given set of models,
  * Hamiltonians, sizes and pointers runs eagerly, one instance after another, times each
  * instance, checks every error word (synchronising), and records the submission as one
- * graph with the measured times as costs; later calls with the same arguments replay it
+ * graph with the measured times as costs (models not yet tuned are first passed through
+ * dn_autotune on up to 256 of their own samples' shapes); later calls with the same arguments replay it
  * with one graph launch (the spins' values may change; the generator, work lists and
  * counts are rebuilt on the device at each replay). A model used elsewhere in between whose
  * workspace had to grow gets a new recording. Parameter updates (dn_model_set_params) act

@@ -24,7 +24,8 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
-           "dn_eloc", "dn_grad_logpsi", "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read",
+           "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_ragged_eloc",
+           "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
 RAGGED_MODE = {"eager": 0, "graph": 1}
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
@@ -71,6 +72,8 @@ def lib():
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
         L.dn_grad_logpsi.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+        L.dn_autotune.argtypes = [vp, ctypes.POINTER(HamDesc), i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
+        L.dn_set_launch_shapes.argtypes = [vp, i32, i64]
         L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -81,7 +84,8 @@ def lib():
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
-                   "dn_grad_logpsi", "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read"):
+                   "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_ragged_eloc", "dn_profile_enable",
+                   "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -187,6 +191,17 @@ class Model:
         w = weights.to(torch.float64).contiguous() if weights is not None else None
         _check(lib().dn_grad_logpsi(self.handle, _ptr(spins), B, _ptr(lp), _ptr(g), _ptr(w), _ptr(ws), _stream()))
         return lp, g, ws
+
+    def autotune(self, ham, B_probe: int = 256):
+        """Pick this model's launch shapes by timing; returns (conv_nt, flip_budget_bytes)."""
+        nt, bud = ctypes.c_int32(), ctypes.c_int64()
+        hd = make_ham(ham)
+        _check(lib().dn_autotune(self.handle, ctypes.byref(hd), B_probe, ctypes.byref(nt), ctypes.byref(bud),
+                                 _stream()))
+        return nt.value, bud.value
+
+    def set_launch_shapes(self, conv_nt: int = 0, flip_budget: int = 0):
+        _check(lib().dn_set_launch_shapes(self.handle, conv_nt, flip_budget))
 
     def profile_enable(self, on: bool = True):
         _check(lib().dn_profile_enable(self.handle, int(on)))

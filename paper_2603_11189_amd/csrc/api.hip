@@ -119,6 +119,11 @@ struct dn_model {
   Prof prof;
   // S4 tap Jacobian (float64 master + float32 copy), valid for the current parameters
   bool have_jac = false;
+  // launch shapes (dn_autotune): 16-site output tiles per wave of the Toeplitz kernel
+  // (0 = by chain length) and the bytes of flip fields per ABACUS chunk
+  int conv_nt = 0;
+  size_t flip_budget = (size_t)3 << 30;
+  bool tuned = false;
   double* jac64 = nullptr;
   float* jac32 = nullptr;
   std::vector<void*> owned;
@@ -273,7 +278,9 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   const double Nr = m->desc.N, dr = m->desc.d;
   PScope ps(m, DN_K_CONV, st, 2.0 * C * Nr * Nr * dr, 2.0 * C * Nr * dr * sizeof(T));
   const size_t lds = (CONV_MC * CONV_LD + 2 * Np) * sizeof(T);
-  const int nt = Np >= 256 ? 4 : Np / 64;  // 16-site tiles per wave
+  // 16-site tiles per wave; a wave's 16 nt sites must tile Np (so no wave straddles its end)
+  int nt = m->conv_nt ? m->conv_nt : (Np >= 256 ? 4 : Np / 64);
+  if (nt < 1 || nt > 4 || Np % (16 * nt) != 0) nt = Np >= 256 ? 4 : Np / 64;
   dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
   switch (nt) {
     case 1: allow_lds(conv_kernel<T, 1>, lds); conv_kernel<T, 1><<<grid, 256, lds, st>>>(a); break;
@@ -555,7 +562,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   // samples per chunk: the flip fields dominate (2 fields of [F][DP][Np])
   const size_t per_flip = (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T) +
                           (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
-  const size_t flips_budget = std::max<size_t>(1024, ((size_t)3 << 30) / per_flip);
+  const size_t flips_budget = std::max<size_t>(1024, m->flip_budget / per_flip);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
   // background samples per forward chunk: its caches (a0, chi0, p0 per block, tau and its
   // mixer input) take (3L + 4) fields per sample; a large chunk keeps the forward launches
@@ -1394,6 +1401,81 @@ dn_status dn_profile_read(dn_model* m, int32_t kind, double* total_ms, int64_t* 
   return DN_OK;
 }
 
+dn_status dn_autotune(dn_model* m, const dn_ham_desc* ham, int32_t B_probe, int32_t* conv_nt_out,
+                      int64_t* flip_budget_out, void* stream) {
+  if (!m || !ham) return fail(DN_EINVAL, "null argument");
+  if (B_probe < 1) return fail(DN_EINVAL, "B_probe < 1");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  const int N = m->desc.N, M = ham->kind == DN_H_J1J2 ? 2 * N : N;
+  STCHK(check_ham(ham, N, M));
+  STCHK(abacus_supported(m));
+  hipStream_t st = (hipStream_t)stream;
+  void *ps, *pl, *pe;
+  STCHK(ws_get(m, "tu_spins", (size_t)B_probe * N, &ps));
+  STCHK(ws_get(m, "tu_lp", (size_t)B_probe * 8, &pl));
+  STCHK(ws_get(m, "tu_el", (size_t)B_probe * 8, &pe));
+  probe_spins_kernel<<<256, 256, 0, st>>>((int8_t*)ps, (long)B_probe * N, 0x9e3779b9u);
+  HIPCHK(hipGetLastError());
+  const bool prof = m->prof.on;
+  m->prof.on = false;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto run = [&](int nt, size_t budget, float* ms) -> dn_status {
+    m->conv_nt = nt;
+    m->flip_budget = budget;
+    auto once = [&]() {
+      return dn_eloc(m, DN_PATH_ABACUS, ham, (const int8_t*)ps, B_probe, M, (double*)pl, nullptr, (double*)pe, st);
+    };
+    STCHK(once());  // sizes the workspace for this shape
+    HIPCHK(hipEventRecord(e0, st));
+    STCHK(once());
+    STCHK(once());
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return DN_OK;
+  };
+  // coordinate search: tiles of the Toeplitz kernel first, then the flip chunk size
+  const int Np = m->Np;
+  int best_nt = Np >= 256 ? 4 : Np / 64;
+  size_t best_budget = (size_t)3 << 30;
+  float best = 1e30f, t = 0.f;
+  dn_status s = DN_OK;
+  for (int nt = 1; nt <= 4 && s == DN_OK; ++nt) {
+    if (Np % (16 * nt) != 0) continue;  // the waves' site spans must tile the padded chain
+    s = run(nt, best_budget, &t);
+    if (s == DN_OK && t < best) { best = t; best_nt = nt; }
+  }
+  const size_t budgets[] = {(size_t)256 << 20, (size_t)1 << 30, (size_t)3 << 30};
+  for (size_t bud : budgets) {
+    if (s != DN_OK || bud == ((size_t)3 << 30)) continue;  // 3 GiB was timed above
+    s = run(best_nt, bud, &t);
+    if (s == DN_OK && t < best) { best = t; best_budget = bud; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  m->prof.on = prof;
+  m->conv_nt = best_nt;
+  m->flip_budget = best_budget;
+  if (s != DN_OK) return s;
+  m->tuned = true;
+  if (conv_nt_out) *conv_nt_out = best_nt;
+  if (flip_budget_out) *flip_budget_out = (int64_t)best_budget;
+  return DN_OK;
+}
+
+dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (conv_nt < 0 || conv_nt > 4 || (conv_nt && m->Np % (16 * conv_nt) != 0))
+    return fail(DN_EINVAL, "conv_nt must be 0 or 1..4 with the padded chain a multiple of 16 conv_nt");
+  if (flip_budget < 0) return fail(DN_EINVAL, "flip_budget < 0");
+  m->conv_nt = conv_nt;
+  m->flip_budget = flip_budget ? (size_t)flip_budget : ((size_t)3 << 30);
+  m->tuned = true;
+  return DN_OK;
+}
+
 dn_status dn_ragged_eloc(int32_t n_inst, dn_model* const* models, const dn_ham_desc* hams,
                          const int8_t* const* spins, const int32_t* B, double* const* logpsi,
                          double* const* eloc, int32_t n_streams, int32_t mode, void* stream) {
@@ -1441,6 +1523,8 @@ dn_status dn_ragged_eloc(int32_t n_inst, dn_model* const* models, const dn_ham_d
       return DN_OK;
     }
   }
+  for (auto& in : ins)
+    if (!in.m->tuned) STCHK(dn_autotune(in.m, &in.ham, std::min(in.B, 256), nullptr, nullptr, st));
   std::vector<double> ms;
   STCHK(ragged_first(ins, st, &ms));
   std::vector<uint64_t> gen;

@@ -139,6 +139,16 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ 
   if (t == 1023) { offs[B] = part[1023]; offs[B + 1] = bad; }
 }
 
+// Probe configurations for launch tuning: spin i = +-1 from the low bit of a 32-bit integer
+// hash of (i, seed) (a multiply-xorshift mixer); only timings are taken from them.
+__global__ void probe_spins_kernel(int8_t* __restrict__ spins, long n, uint32_t seed) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+    x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+    spins[i] = (x & 1u) ? 1 : -1;
+  }
+}
+
 // Identity work list: entry b is sample b, unflipped.
 __global__ void identity_map_kernel(int32_t* __restrict__ cb, int32_t* __restrict__ cm, int B) {
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {

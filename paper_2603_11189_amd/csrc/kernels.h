@@ -261,7 +261,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
   const int C = A.dyn.count(A.C);
   if (cfg0 >= C) return;
   const int Np = A.Np;
-  const int site0 = blockIdx.z * 64 * NT;                // output block of 4 waves x 16*NT sites
+  // output block of 4 waves x 16*NT sites; the host picks NT with Np a multiple of 16*NT
+  const int site0 = blockIdx.z * 64 * NT;
   const int wsite0 = site0 + wave * 16 * NT;              // this wave's first output site
   const T* tp = A.taps + (long)c * tap_stride(Np) + 64;  // offsets -(Np-1).. at ts[0..]
   for (int q = threadIdx.x; q < 2 * Np; q += 256) ts[q] = tp[q];
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
       for (int r = 0; r < 4; ++r) {
         const int cfg = cfg0 + 16 * a + M::row(lane, r);
         const int i = wsite0 + 16 * n + (lane & 15);
-        if (cfg < C) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
+        if (cfg < C && i < Np) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
       }
 }
 
@@ -1071,7 +1072,13 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
     const int lp = l - 1;  // layer index into tables
     const int loP = clo - lp * wc, WP = ext + 2 * lp * wc + 1;  // S_{l-1}
     const int lo = clo - l * wc, Wl = ext + 2 * l * wc + 1;     // S_l
-    // a' on S_{l-1}
+    // a' on S_{l-1}; this lane's column of the block's weight matrix stays in registers
+    T wcol[DP];
+    if (l > 1) {
+      const T* Wt = A.tb.WDt + (long)lp * DP * DP;
+#pragma unroll
+      for (int k = 0; k < DP; ++k) wcol[k] = Wt[k * DP + c];
+    }
     for (int t = 0; t < WP; ++t) {
       const int site = wrap(loP + t);
       T v = 0;
@@ -1081,9 +1088,9 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
           if (site == j0 || site == j1) s = -s;
           v = s * A.tb.wE1[c] + A.tb.wv[c];
         } else {
-          const T* Wt = A.tb.WDt + (long)lp * DP * DP;
           T acc = A.tb.wv[lp * DP + c];
-          for (int k = 0; k < DP; ++k) acc += Wt[k * DP + c] * phs[t * DP + k];
+#pragma unroll
+          for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
           v = acc;
         }
       }
@@ -1112,10 +1119,13 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
     const T* Adt = A.tb.ADt + (long)lp * DP * DP;
     const T* chi0 = A.chi0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
     T* out = A.dchi + ((long)f * L + lp) * A.Wmax * DP;
+#pragma unroll
+    for (int k = 0; k < DP; ++k) wcol[k] = Adt[k * DP + c];
     for (int t = 0; t < Wl; ++t) {
       const int ii = lo + t;
       T acc = A.tb.bv[lp * DP + c];
-      for (int k = 0; k < DP; ++k) acc += Adt[k * DP + c] * phs[t * DP + k];
+#pragma unroll
+      for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
       T dc = inside(ii) ? act_fn<T>(A.act, acc) - chi0[wrap(ii)] : T(0);
       out[t * DP + c] = dc;
     }

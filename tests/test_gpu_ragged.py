@@ -181,3 +181,20 @@ def test_ragged_full_size_sampled(L):
             assert bool(torch.isfinite(els[i]).all())
     for m in models:
         m.close()
+
+
+def test_autotune_keeps_results(L):
+    """The autotuner only changes launch shapes: results stay at the oracle's values."""
+    shape = di.ModelShape(70, 3, 32, 16, bc="open")
+    ham = di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5)
+    th = torch.tensor(di.draw_params(shape, 77, "stress"))
+    m = L.Model(shape, "fp32")
+    m.set_params(th)
+    nt, bud = m.autotune(ham, B_probe=64)
+    _say("autotune:", nt, bud >> 20, "MiB")
+    assert nt in (1, 2, 3, 4) and bud in (256 << 20, 1 << 30, 3 << 30)
+    sp = di.uniform_spins(5, shape.N, 78)
+    ref = O.eloc_plain(ModelDesc.of(shape), ham, th, sp, shape.N)
+    lp, lr, el = m.eloc(ham, torch.tensor(sp, device="cuda"), shape.N, path="abacus")
+    assert eps(el.cpu(), ref["eloc"]) <= 1e-4 and eps(lp.cpu(), ref["logpsi"]) <= 1e-4
+    m.close()
