@@ -70,7 +70,8 @@ bool layout_of(const dn_model_desc& d, Layout* lo) {
 template <typename T> struct TableBufs {
   std::vector<void*> owned;
   Tables<T> tb{};
-  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk, *ADm, *WDm, *Pq;
+  T *E, *Ephi, *wE1, *WDt, *ADt, *Ut, *Vt, *Um, *Vm, *wv, *Kc, *kv, *bv, *taps, *tapsR, *Wk, *ADm, *WDm, *Pq, *omN,
+      *Ac;
 };
 
 struct ProfRec {
@@ -217,10 +218,10 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
             get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, L * DP * tap_stride(Np)) &&
             get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP) &&
-            get(&tb.Pq, 4 * DP * tap_stride(Np));
+            get(&tb.Pq, 4 * DP * tap_stride(Np)) && get(&tb.omN, DP * Np) && get(&tb.Ac, 2 * DP);
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
-                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm, tb.Pq};
+                    tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm, tb.Pq, tb.omN, tb.Ac};
   return DN_OK;
 }
 
@@ -240,7 +241,8 @@ dn_status convert_tables(dn_model* m, hipStream_t st) {
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
       {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, L * DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np},
-      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, 4 * DP * tap_stride(Np)}};
+      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, 4 * DP * tap_stride(Np)},
+      {a.omN, b.omN, DP * Np}, {a.Ac, b.Ac, 2 * DP}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
     convert_kernel<<<grid, 256, 0, st>>>(it.s, it.d, it.n);
@@ -271,10 +273,10 @@ template <> const Tables<double>& tables_of<double>(dn_model* m) { return m->t64
 template <> const Tables<float>& tables_of<float>(dn_model* m) { return m->t32.tb; }
 
 template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const T* taps, int C, hipStream_t st,
-                                            DynRange dyn = DynRange{nullptr, 0, 0}) {
+                                            DynRange dyn = DynRange{nullptr, 0, 0}, const T* add = nullptr) {
   if (C <= 0) return DN_OK;
   const int Np = m->Np;
-  ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP, dyn};
+  ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP, dyn, add};
   const double Nr = m->desc.N, dr = m->desc.d;
   PScope ps(m, DN_K_CONV, st, 2.0 * C * Nr * Nr * dr, 2.0 * C * Nr * dr * sizeof(T));
   const size_t lds = (CONV_MC * CONV_LD + 2 * Np) * sizeof(T);
@@ -586,7 +588,9 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
     a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bf; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
     STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bf, st)));
-    STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bf, st));
+    // with deep blocks the last one reads out with Wk + tau: the conv adds Wk to tau
+    STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bf, st,
+                         DynRange{nullptr, 0, 0}, L >= 2 ? tb.Wk : nullptr));
   }
   for (int b0 = bf0; b0 < bf0 + Bf; b0 += Bc_max) {
     const int Bc = std::min(Bc_max, bf0 + Bf - b0);
@@ -1261,6 +1265,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
   a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;
   a.tapsR = t.tapsR; a.omega = m->omega; a.Wk = t.Wk; a.A = m->A64; a.ADm = t.ADm; a.WDm = t.WDm;
+  a.omN = t.omN; a.Ac = t.Ac;
   {
     PScope ps(m, DN_K_PREP, st, 0.0, (double)table_elems(*m) * 8);
     prep_kernel<<<256, 256, 0, st>>>(a);

@@ -18,6 +18,7 @@ template <typename T> struct Tables {
   const T *Wk;                             // [2][DP][Np]
   const T *ADm, *WDm;                      // operand tables of A_D^T and W_D^T
   const T *Pq;                             // [4][DP][tap_stride]: V^(1) (E * g^(1)(r)), see ptab_kernel
+  const T *omN, *Ac;                       // omega / N [DP][Np] and A^T [2][DP]: Wk = Ac omN
 };
 
 // Which configuration a block works on. Plain path: cfg g -> sample b, element m (m = -1
@@ -243,6 +244,7 @@ template <typename T> struct ConvArgs {
   const T* taps;  // [DP][tap_stride(Np)] for this mixer
   int N, Np, C, DP;
   DynRange dyn;   // configurations counted on the device (nullable)
+  const T* add;   // nullable: Y[cfg] += add[cfg mod 2] (field [2][DP][Np])
 };
 
 constexpr int CONV_MC = 64;   // configurations per workgroup
@@ -322,7 +324,11 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
       for (int r = 0; r < 4; ++r) {
         const int cfg = cfg0 + 16 * a + M::row(lane, r);
         const int i = wsite0 + 16 * n + (lane & 15);
-        if (cfg < C && i < Np) A.Y[(long)cfg * cstride + (long)c * Np + i] = (i < A.N) ? acc[a][n][r] : T(0);
+        if (cfg < C && i < Np) {
+          T y = (i < A.N) ? acc[a][n][r] : T(0);
+          if (A.add) y += A.add[(long)(cfg & 1) * cstride + (long)c * Np + i];
+          A.Y[(long)cfg * cstride + (long)c * Np + i] = y;
+        }
       }
 }
 
@@ -835,16 +841,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           T y[4];
 #pragma unroll
           for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
-          V4<T> w0 = ld4(A.tb.Wk + o), w1 = ld4(A.tb.Wk + DP * Np + o);
           if (LAST) {
-            const V4<T> t0 = ld4(A.tau + 2 * bo + o), t1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
+            // read-out with Wk + tau (tau already carries Wk when L >= 2)
+            const V4<T> w0 = ld4(A.tau + 2 * bo + o), w1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
 #pragma unroll
-            for (int n = 0; n < 4; ++n) { w0.v[n] += t0.v[n]; w1.v[n] += t1.v[n]; }
-          }
+            for (int n = 0; n < 4; ++n) {
+              part0 += (double)w0.v[n] * (double)y[n];
+              part1 += (double)w1.v[n] * (double)y[n];
+            }
+          } else {
+            // read-out with Wk = A^T omega / N: one site vector of omega / N per channel
+            const V4<T> wo = ld4(A.tb.omN + o);
+            const int ch = 16 * mo + M::row(lane, r);
+            double sw = 0.0;
 #pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            part0 += (double)w0.v[n] * (double)y[n];
-            part1 += (double)w1.v[n] * (double)y[n];
+            for (int n = 0; n < 4; ++n) sw += (double)wo.v[n] * (double)y[n];
+            part0 += (double)A.tb.Ac[ch] * sw;
+            part1 += (double)A.tb.Ac[DP + ch] * sw;
           }
           if (LAST) {
             const int cl = 16 * (mo - mg) + M::row(lane, r);

@@ -207,6 +207,7 @@ struct PrepArgs {
   double *wv, *Kc, *kv, *bv;               // [L][DP], K: [L][2w_c+1][DP]
   double *taps, *tapsR;                    // [L][DP][TS] mixers and their transposes
   double *omega, *Wk, *A;                  // [DP][Np], [2][DP][Np], [DP][2]
+  double *omN, *Ac;                        // omega / N [DP][Np]; A transposed [2][DP]
   double *ADm, *WDm;                       // operand tables of A_D^T, W_D^T
 };
 
@@ -275,9 +276,11 @@ __global__ void prep_kernel(PrepArgs a) {
       for (int j = 0; j < N; ++j) om += g[(j - i) + N - 1];  // column sum of the final mixer
     }
     a.omega[idx] = om;
+    a.omN[idx] = om / (double)N;
     for (int k = 0; k < 2; ++k) {
       double A = (c < d) ? a.params[a.off_A + c * a.d_out + k] : 0.0;
       a.Wk[(long)k * DP * Np + idx] = om * A / (double)N;
+      if (i == 0) a.Ac[k * DP + c] = A;
     }
   }
 }
