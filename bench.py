@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the per-sample log-derivative leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuner)")
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
+    ap.add_argument("--sweep", action="store_true",
+                    help="ABACUS vs full re-evaluation for N in 64..512 at L = 2 and 4 (one JSON line each)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
@@ -160,6 +162,9 @@ def main():
 
     if args.workload == "ragged32":
         bench_ragged(args)
+        return
+    if args.sweep:
+        bench_sweep(args)
         return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
@@ -305,8 +310,9 @@ def main():
         t0 = time.perf_counter()
         done, errs = [], {p: {"eloc": 0.0, "lr": 0.0, "logpsi": 0.0} for p in results}
         ref_mag = {"eloc": 0.0, "lr": 0.0, "logpsi": 0.0}
-        while time.perf_counter() - t0 < budget and len(done) < B:
-            b = len(done) * max(1, B // 64)
+        stride = max(1, B // 64)
+        while time.perf_counter() - t0 < budget and len(done) * stride < B:
+            b = len(done) * stride
             ref = O.eloc_plain(desc, ham, theta, spins_np[b:b + 1], M_max)
             done.append(b)
             for key, idx in (("logpsi", 0), ("lr", 1), ("eloc", 2)):
@@ -318,12 +324,55 @@ def main():
         cpu_sec = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": len(done) / cpu_sec, "unit": "samples/s",
                                "cores": torch.get_num_threads(), "kind": "oracle",
-                               "sample": f"{len(done)} of the {B} samples (every {max(1, B // 64)}th), "
+                               "sample": f"{len(done)} of the {B} samples (every {stride}th), "
                                          f"float64 oracle, log-ratios by full re-evaluation, {cpu_sec:.1f} s"}
         out["err_vs_fp64_oracle"] = {
             p: {k: (errs[p][k] / ref_mag[k] if ref_mag[k] > 0 else 0.0) for k in errs[p]} for p in results}
         out["err_vs_fp64_oracle"]["measure"] = "max|x - x*| / max|x*| over the CPU sample"
     print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args) -> None:
+    """Speedup of ABACUS over full re-evaluation on the same GPU across chain lengths: the
+    long-range Ising chain (alpha=2, h=0.5), d=64, state 32, float32, B samples per N."""
+    import torch
+
+    import dn_inputs as di
+    from paper_2603_11189_amd import _lib as L
+
+    dev = torch.device("cuda")
+    torch.cuda.init()
+    L.lib()
+    B = 512
+    ham = di.HamSpec("lrtfim", "open", J=1.0, alpha=2.0, h=0.5)
+    for depth in (2, 4):
+        for N in (64, 128, 256, 512):
+            shape = di.ModelShape(N, depth, 64, 32, act="silu", bc="open")
+            m = L.Model(shape, "fp32")
+            m.set_params(torch.tensor(di.draw_params(shape, 1005, "baseline")))
+            spins = torch.tensor(di.uniform_spins(B, N, 2005), device=dev)
+            if not args.no_tune:
+                m.autotune(ham)
+            rate = {}
+            for path in ("abacus", "full"):
+                out = (torch.empty(B, dtype=torch.float64, device=dev),
+                       torch.empty((B, N), dtype=torch.float64, device=dev),
+                       torch.empty(B, dtype=torch.float64, device=dev))
+                m.eloc(ham, spins, N, path=path, out=out)
+                torch.cuda.synchronize()
+                steps = 2
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    m.eloc(ham, spins, N, path=path, out=out)
+                torch.cuda.synchronize()
+                rate[path] = B * steps / (time.perf_counter() - t0)
+            m.close()
+            line = {"metric": "E_loc samples/sec, ABACUS vs full re-eval (sweep)", "N": N, "L": depth, "d": 64,
+                    "s": 32, "B": B, "dtype": "f32", "abacus": rate["abacus"], "full": rate["full"],
+                    "speedup": rate["abacus"] / rate["full"], "unit": "samples/s", "data": "synthetic"}
+            log(f"[sweep] N={N} L={depth}: abacus {rate['abacus']:.0f}/s full {rate['full']:.0f}/s "
+                f"x{line['speedup']:.2f}")
+            print(json.dumps(line), flush=True)
 
 
 def bench_ragged(args) -> None:
