@@ -649,7 +649,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       TailArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
-      a.yL = nullptr; a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps; a.rho = rho;
+      a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps;
       a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax; a.dyn = dyn;
       const int WL = 2 * L * wc + 1;
       PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d, (double)F * (WL * 2 + 1) * d.d * sizeof(T));

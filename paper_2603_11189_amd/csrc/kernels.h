@@ -576,9 +576,11 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 
 // ---------------------------------------------------------------------------------------
 // Deep blocks of the ABACUS background propagation: du^(l+1) = D0^(l) G^(l) du^(l) + z^(l)
-// on the full chain, as in mix_kernel's DEEP mode, but one 64-site tile per wave step
-// instead of one flip per workgroup. Each wave walks its tiles with the next tile's input
-// already in flight while the current one is mixed. Tiles are dealt out per XCD in
+// on the full chain, x = chi0 q + [i in S_l] dchi (p0 + q) with q = V w, w = G^(l) du (the
+// perturbation through the frozen vertex plus the vertex change on the slice), one 64-site
+// tile per wave step. Block 1 builds q from the unit-flip table Pq instead of reading w.
+// Each wave walks its tiles with the next tile's input already in flight while the current
+// one is mixed. Tiles are dealt out per XCD in
 // contiguous ranges (workgroup w runs on XCD w mod 8), so the flips of one sample, which
 // share their background caches, meet in the same L2. Each tile's read-out lands in
 // rho[f][t].
@@ -609,7 +611,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // the next tile's input is prefetched into registers unless that would not fit
   constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
   T* F1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of V, phase 1
-  T* F2 = F1 + DP * DP;                     // [MT][64][MT][4]: operand A of U, phase 2
+  T* F2 = F1 + DP * DP;                     // [MT][MT][64][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
   constexpr int CPG = DP < DH_CH ? DP : DH_CH;     // LAST: channels per slice group
@@ -637,7 +639,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     }
     {
       // phase 2 contracts over the channels in accumulator order (see mix_kernel)
-      const int r = idx & 3, mi = (idx >> 2) % MT, ln = (idx / (4 * MT)) % 64, mo = idx / (4 * MT * 64);
+      // lanes 16 bytes apart: the four r entries of a lane are one conflict-free vector read
+      const int r = idx & 3, ln = (idx >> 2) & 63, mi = (idx >> 8) % MT, mo = (idx >> 8) / MT;
       F2[idx] = Ut[(16 * mi + M::row(ln, r)) * DP + 16 * mo + (ln & 15)];
     }
   }
@@ -829,7 +832,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const T af = F2[((mo * 64 + lane) * MT + mi) * 4 + r];
+              const T af = F2[((mo * MT + mi) * 64 + lane) * 4 + r];
 #pragma unroll
               for (int n = 0; n < 4; ++n) a2[n] = M::mma(af, acc[mi][n][r], a2[n]);
               if (r == 3) __builtin_amdgcn_sched_barrier(0);
@@ -1147,10 +1150,11 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------------------
-// ABACUS tail, one wave per flip: vertex change of the last block on its slice,
-// e^(L) = U (dchi^(L) * (p0^(L) + V y_L)); e^(0) = -2 s_j E on the cluster;
-// dOmega = rho_f + Wk . (e^(0) + e^(L)) [+ tau . e^(0) and y_1 = G^(1) e^(0) when L = 1];
-// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
+// ABACUS for one-block networks (L = 1), one wave per flip: the block's mixer output on
+// the slice is y_1 = G^(1) e^(0) with e^(0) = -2 s_j E on the cluster; the vertex change
+// e^(1) = U (dchi^(1) * (p0^(1) + V y_1)); dOmega = (Wk + tau) . e^(0) + Wk . e^(1);
+// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64. (Deeper networks finish
+// their flips in last_finish_kernel.)
 template <typename T> struct TailArgs {
   Tables<T> tb;
   int N, Np, L, w_c, periodic;
@@ -1159,11 +1163,9 @@ template <typename T> struct TailArgs {
   const int8_t* spins;
   const int4* geom;
   const T* dchi;        // [F][L][Wmax][DP]
-  const T* yL;          // unused: deep networks finish each flip in the last mixing launch
-  const T* p0L;         // [Bc][DP][Np] p0 of block L
+  const T* p0L;         // [Bc][DP][Np] p0 of the block
   const T* tau;         // [Bc][2][DP][Np]
-  const T* taps1;       // block-1 taps (L == 1)
-  const double* rho;    // [F][2] (L >= 2)
+  const T* taps1;       // taps of the block's mixer
   const double* Om0;    // [B][2] global
   double* logratio;     // [B][M_max] global
   int Wmax;
@@ -1193,11 +1195,8 @@ __global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
     const int j = q == 0 ? gm.z : gm.w;
     if (j < 0) continue;
     const T e0 = (T)(-2 * sp[j]) * A.tb.E[c];
-    T w0 = A.tb.Wk[(long)c * Np + j], w1 = A.tb.Wk[DPNp + (long)c * Np + j];
-    if (L == 1) {
-      w0 += A.tau[(2L * bl) * DPNp + (long)c * Np + j];
-      w1 += A.tau[(2L * bl + 1) * DPNp + (long)c * Np + j];
-    }
+    const T w0 = A.tb.Wk[(long)c * Np + j] + A.tau[(2L * bl) * DPNp + (long)c * Np + j];
+    const T w1 = A.tb.Wk[DPNp + (long)c * Np + j] + A.tau[(2L * bl + 1) * DPNp + (long)c * Np + j];
     o0 += (double)w0 * (double)e0;
     o1 += (double)w1 * (double)e0;
   }
@@ -1210,14 +1209,9 @@ __global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
     if (!inside(ii)) continue;  // uniform across the wave
     const int site = wrap(ii);
     if (on) {
-      T y;
-      if (L == 1) {
-        const T* t1 = A.taps1 + (long)c * tap_stride(Np) + tap_off(Np);
-        y = t1[site - gm.z] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
-        if (gm.w >= 0) y += t1[site - gm.w] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
-      } else {
-        y = A.yL[((long)f * A.Wmax + t) * DP + c];
-      }
+      const T* t1 = A.taps1 + (long)c * tap_stride(Np) + tap_off(Np);
+      T y = t1[site - gm.z] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
+      if (gm.w >= 0) y += t1[site - gm.w] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
       ys[c] = y;
     }
     __syncthreads();
@@ -1238,10 +1232,8 @@ __global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
   o0 = wave_sum(o0);
   o1 = wave_sum(o1);
   if (c == 0) {
-    double d0 = o0, d1 = o1;
-    if (L >= 2) { d0 += A.rho[2 * f]; d1 += A.rho[2 * f + 1]; }
     const double a0 = A.Om0[2 * b], a1 = A.Om0[2 * b + 1];
-    A.logratio[(long)b * A.map.M_max + m] = lcd_d(a0, d0) + lcd_d(a1, d1);
+    A.logratio[(long)b * A.map.M_max + m] = lcd_d(a0, o0) + lcd_d(a1, o1);
   }
 }
 

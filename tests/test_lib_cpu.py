@@ -77,3 +77,33 @@ def test_connected_rejects_bad_arguments_on_host():
     assert st == L.DN_EINVAL
     st = lib.dn_connected(ctypes.byref(hd), None, 4, 16, 16, p, p, p, p, None)
     assert st == L.DN_EINVAL
+
+
+def test_bf16_mode_needs_wide_channels_on_host():
+    L = _lib()
+    lib = L.lib()
+    d = L.make_desc(di.ModelShape(32, 2, 16, 8), "bf16")
+    h = ctypes.c_void_p()
+    assert lib.dn_model_create(ctypes.byref(d), ctypes.byref(h)) == L.DN_EUNSUPPORTED
+    assert b"BF16" in lib.dn_last_error()
+
+
+def test_ragged_and_tuning_entry_points_reject_bad_arguments_on_host():
+    L = _lib()
+    lib = L.lib()
+    # an empty submission is a no-op; a negative count is an error
+    assert lib.dn_ragged_eloc(0, None, None, None, None, None, None, 0, 1, None) == L.DN_OK
+    assert lib.dn_ragged_eloc(-1, None, None, None, None, None, None, 0, 1, None) == L.DN_EINVAL
+    # null arrays, bad stream count and bad mode are caught before any device work
+    assert lib.dn_ragged_eloc(1, None, None, None, None, None, None, 0, 1, None) == L.DN_EINVAL
+    vp = ctypes.c_void_p
+    one = (vp * 1)(16)
+    hd = (L.HamDesc * 1)(L.make_ham(di.HamSpec("lrtfim", "open")))
+    bb = (ctypes.c_int32 * 1)(4)
+    st = lib.dn_ragged_eloc(1, one, hd, one, bb, None, one, 9, 1, None)
+    assert st == L.DN_EINVAL and b"n_streams" in lib.dn_last_error()
+    st = lib.dn_ragged_eloc(1, one, hd, one, bb, None, one, 0, 7, None)
+    assert st == L.DN_EINVAL and b"mode" in lib.dn_last_error()
+    h = L.make_ham(di.HamSpec("lrtfim", "open"))
+    assert lib.dn_autotune(None, ctypes.byref(h), 16, None, None, None) == L.DN_EINVAL
+    assert lib.dn_set_launch_shapes(None, 0, 0) == L.DN_EINVAL
