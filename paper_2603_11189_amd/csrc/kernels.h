@@ -662,11 +662,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   const int kq_row = BF ? 8 * kq : kq;
   auto urow = [](int ks) { return BF ? 32 * (ks >> 3) + (ks & 7) : 4 * ks; };
   V4<T> xb[PF ? KS : 1];
-  if (PF && q < q_hi) {
-    const T* src = A.X + (q / nt) * DP * Np + 64 * (q % nt) + kq_row * Np + 4 * j;
+  // with the input also the tile's background gate chi0 is fetched one tile ahead (float
+  // operands only: it does not fit the register budget of the other variants)
+  constexpr bool PFC = PF && !BF && sizeof(T) == 4;
+  V4<T> cb[PFC ? MT * 4 : 1];
+  auto prefetch = [&](long qq) {
+    const T* src = A.X + (qq / nt) * DP * Np + 64 * (qq % nt) + kq_row * Np + 4 * j;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
-  }
+    if constexpr (PFC) {
+      const int gq = (int)(qq / nt);
+      const T* cs = A.chi + (long)(A.map.cb[cfg0 + gq] - A.b0) * DP * Np + (long)lrow * Np + 64 * (qq % nt) + 4 * j;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cb[mt * 4 + r] = ld4(cs + (16 * mt + M::r_row(r)) * Np);
+    }
+  };
+  if (PF && q < q_hi) prefetch(q);
   for (; q < q_hi; q += wstride) {
     // compiler-only barrier: the weight operands are reloaded per tile rather than hoisted
     // out of the loop into registers (which would halve the occupancy)
@@ -774,7 +787,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
       for (int r = 0; r < 4; ++r) {
         const int ch = 16 * mt + M::row(lane, r);
         const int uo = (16 * mt + M::r_row(r)) * Np;  // lane-independent part of the offset
-        const V4<T> c = ld4(A.chi + bo + lo_off + uo);
+        V4<T> c;
+        if constexpr (PFC) c = cb[mt * 4 + r];
+        else c = ld4(A.chi + bo + lo_off + uo);
         T x[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) x[n] = c.v[n] * acc[mt][n][r];
@@ -788,12 +803,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         if (r == 3) __builtin_amdgcn_sched_barrier(0);
       }
     // the next tile's input travels while this one is mixed and stored
-    if (PF && q + wstride < q_hi) {
-      const long qn = q + wstride;
-      const T* src = A.X + (qn / nt) * DP * Np + 64 * (qn % nt) + kq_row * Np + 4 * j;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
-    }
+    if (PF && q + wstride < q_hi) prefetch(q + wstride);
     // BF: x as bf16 operands of phase 2, in accumulator channel order (step sk: channels
     // 16 (2 sk + e / 4) + row(lane, e mod 4))
     bf8 xh[BF ? KB : 1][4];
