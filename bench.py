@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
     ap.add_argument("--sweep", action="store_true",
                     help="ABACUS vs full re-evaluation for N in 64..512 at L = 2 and 4 (one JSON line each)")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="with --sweep: the paper's matched runtime shapes instead (L=2, d=2, s=12, periodic, "
+                         "Kac-normalised Ising J=-5, alpha=6, 1024 samples; N up to the library's 512)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
@@ -334,7 +337,8 @@ def main():
 
 def bench_sweep(args) -> None:
     """Speedup of ABACUS over full re-evaluation on the same GPU across chain lengths: the
-    long-range Ising chain (alpha=2, h=0.5), d=64, state 32, float32, B samples per N."""
+    long-range Ising chain (alpha=2, h=0.5), d=64, state 32, float32, B samples per N; or,
+    with --paper-shapes, the paper's matched runtime shapes (L=2, d=2, state 12, periodic)."""
     import torch
 
     import dn_inputs as di
@@ -343,36 +347,44 @@ def bench_sweep(args) -> None:
     dev = torch.device("cuda")
     torch.cuda.init()
     L.lib()
-    B = 512
-    ham = di.HamSpec("lrtfim", "open", J=1.0, alpha=2.0, h=0.5)
-    for depth in (2, 4):
-        for N in (64, 128, 256, 512):
-            shape = di.ModelShape(N, depth, 64, 32, act="silu", bc="open")
-            m = L.Model(shape, "fp32")
-            m.set_params(torch.tensor(di.draw_params(shape, 1005, "baseline")))
-            spins = torch.tensor(di.uniform_spins(B, N, 2005), device=dev)
-            if not args.no_tune:
-                m.autotune(ham)
-            rate = {}
-            for path in ("abacus", "full"):
-                out = (torch.empty(B, dtype=torch.float64, device=dev),
-                       torch.empty((B, N), dtype=torch.float64, device=dev),
-                       torch.empty(B, dtype=torch.float64, device=dev))
+    if args.paper_shapes:
+        B = 1024
+        ham = di.HamSpec("lrtfim", "periodic", J=-5.0, alpha=6.0, h=1.0, paper_form=1)
+        grid = [(di.ModelShape(N, 2, 2, 12, act="silu", bc="periodic"), 2) for N in (100, 250, 500)]
+    else:
+        B = 512
+        ham = di.HamSpec("lrtfim", "open", J=1.0, alpha=2.0, h=0.5)
+        grid = [(di.ModelShape(N, depth, 64, 32, act="silu", bc="open"), depth)
+                for depth in (2, 4) for N in (64, 128, 256, 512)]
+    for shape, depth in grid:
+        N = shape.N
+        m = L.Model(shape, "fp32")
+        m.set_params(torch.tensor(di.draw_params(shape, 1005, "baseline")))
+        spins = torch.tensor(di.uniform_spins(B, N, 2005), device=dev)
+        if not args.no_tune:
+            m.autotune(ham)
+        rate = {}
+        for path in ("abacus", "full"):
+            out = (torch.empty(B, dtype=torch.float64, device=dev),
+                   torch.empty((B, N), dtype=torch.float64, device=dev),
+                   torch.empty(B, dtype=torch.float64, device=dev))
+            m.eloc(ham, spins, N, path=path, out=out)
+            torch.cuda.synchronize()
+            steps = 2
+            t0 = time.perf_counter()
+            for _ in range(steps):
                 m.eloc(ham, spins, N, path=path, out=out)
-                torch.cuda.synchronize()
-                steps = 2
-                t0 = time.perf_counter()
-                for _ in range(steps):
-                    m.eloc(ham, spins, N, path=path, out=out)
-                torch.cuda.synchronize()
-                rate[path] = B * steps / (time.perf_counter() - t0)
-            m.close()
-            line = {"metric": "E_loc samples/sec, ABACUS vs full re-eval (sweep)", "N": N, "L": depth, "d": 64,
-                    "s": 32, "B": B, "dtype": "f32", "abacus": rate["abacus"], "full": rate["full"],
-                    "speedup": rate["abacus"] / rate["full"], "unit": "samples/s", "data": "synthetic"}
-            log(f"[sweep] N={N} L={depth}: abacus {rate['abacus']:.0f}/s full {rate['full']:.0f}/s "
-                f"x{line['speedup']:.2f}")
-            print(json.dumps(line), flush=True)
+            torch.cuda.synchronize()
+            rate[path] = B * steps / (time.perf_counter() - t0)
+        m.close()
+        line = {"metric": "E_loc samples/sec, ABACUS vs full re-eval (sweep)", "N": N, "L": depth,
+                "d": shape.d, "s": shape.s, "bc": shape.bc, "B": B, "dtype": "f32", "abacus": rate["abacus"],
+                "full": rate["full"], "speedup": rate["abacus"] / rate["full"],
+                "us_per_element": {p: 1e6 / (rate[p] * N) for p in rate}, "unit": "samples/s",
+                "data": "synthetic"}
+        log(f"[sweep] N={N} L={depth}: abacus {rate['abacus']:.0f}/s full {rate['full']:.0f}/s "
+            f"x{line['speedup']:.2f}")
+        print(json.dumps(line), flush=True)
 
 
 def bench_ragged(args) -> None:
