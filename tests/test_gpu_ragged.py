@@ -198,3 +198,24 @@ def test_autotune_keeps_results(L):
     lp, lr, el = m.eloc(ham, torch.tensor(sp, device="cuda"), shape.N, path="abacus")
     assert eps(el.cpu(), ref["eloc"]) <= 1e-4 and eps(lp.cpu(), ref["logpsi"]) <= 1e-4
     m.close()
+
+
+def test_ragged_rerecords_after_workspace_growth(L):
+    """A model used elsewhere between submissions may have to grow (move) its workspace; the
+    next ragged call must then record a new graph instead of replaying one that points at the
+    old buffers."""
+    cases = SMALL[2:4]
+    models, thetas, spins, lps, els = _setup(L, cases, 7500)
+    hams = [c[1] for c in cases]
+    L.ragged_eloc(models, hams, spins, lps, els, mode="graph")
+    L.ragged_eloc(models, hams, spins, lps, els, mode="graph")   # a replay
+    # a much larger batch on the first model grows its flip and cache buffers
+    shape, ham = cases[0][0], cases[0][1]
+    big = torch.tensor(di.uniform_spins(512, shape.N, 7600), device="cuda")
+    models[0].eloc(ham, big, shape.N, path="abacus")
+    for i, (shape, ham, B, prec, recipe) in enumerate(cases):
+        spins[i].copy_(torch.tensor(_spins(recipe, B, shape.N, 7700 + i)))
+    L.ragged_eloc(models, hams, spins, lps, els, mode="graph")
+    _check(cases, thetas, spins, lps, els, "after workspace growth")
+    for m in models:
+        m.close()
