@@ -594,8 +594,9 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 // across lanes. last_finish_kernel completes the flip.
 constexpr int DEEP_WAVES = 4;
 constexpr int NXCD = 8;
-// waves per SIMD each variant's register budget is sized for
-constexpr int deep_occ(int elem_bytes, bool prefetch) { return elem_bytes == 4 && !prefetch ? 3 : 2; }
+// waves per SIMD each variant's register budget is sized for (the last block's LDS holds it
+// to two workgroups per CU in any case)
+constexpr int deep_occ(int elem_bytes, bool prefetch, bool last) { return elem_bytes == 4 && !prefetch && !last ? 3 : 2; }
 constexpr bool DEEP_PF = true;  // register prefetch of the next tile in the blocks between first and last
 constexpr int DH_LD = 65;
 constexpr int DH_CH = 32;  // channels of the last block's LDS copy per group
@@ -603,7 +604,7 @@ constexpr int DH_CH = 32;  // channels of the last block's LDS copy per group
 // BF (float fields only): both channel-mixing products on the bf16 matrix cores with float
 // accumulation, the weight fragments held in LDS as bf16.
 template <typename T, int DP, bool FIRST, bool LAST, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST)))) void deep_kernel(MixArgs<T> A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST, LAST)))) void deep_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
@@ -823,8 +824,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
       if (A.periodic) { loL %= N; if (loL < 0) loL += N; }
     }
     constexpr int GM = LAST ? CPG / 16 : 1;  // output tiles per group
+    // LAST, float: lane (c, hp) of the slice below takes channel c over the tile sites
+    // hp K .. hp K + K - 1 (K = CPG); the taps it needs, h(u - k) for those sites k and
+    // u < SLICE_WIN, are fetched into registers before the group's products
+    constexpr bool TPR = LAST && sizeof(T) == 4;
+    constexpr int NTP = TPR ? CPG + SLICE_WIN - 1 : 1;
 #pragma unroll 1
     for (int mg = 0; mg < MT; mg += GM) {
+      T tp[NTP];  // tp[m] = tc[m - (K - 1) - hp K], tc the window of the slice below
+      if constexpr (TPR) {
+        const int c = lane % CPG, hp = lane / CPG;
+        const T* tc = A.tapsL + (long)(16 * mg + c) * TS + TO + loL - 64 * t - hp * CPG - (CPG - 1);
+#pragma unroll
+        for (int m = 0; m < NTP; ++m) tp[m] = tc[m];
+      }
 #pragma unroll 1
       for (int mo = mg; mo < mg + GM; ++mo) {
         acc_t a2[4];
@@ -892,19 +905,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         T ya[SLICE_WIN], rg[SLICE_WIN];
 #pragma unroll
         for (int u = 0; u < SLICE_WIN; ++u) ya[u] = 0;
-        const T* tc = A.tapsL + (long)cg * TS + TO + loL - ib;
+        if constexpr (TPR) {
+          // every site of the tile: those past the chain end hold zeros
+          const T* xr = dh + c * DH_LD + k0;
 #pragma unroll
-        for (int u = 0; u < SLICE_WIN; ++u) rg[u] = tc[u - k0];
-        const T* xr = dh + c * DH_LD;
-        for (int kb = k0; kb < k0 + K && kb < cnt; kb += SLICE_WIN) {
+          for (int kk = 0; kk < K; ++kk) {
+            const T v = xr[kk];
 #pragma unroll
-          for (int u = 0; u < SLICE_WIN; ++u) {
-            const int k = kb + u;
-            if (k < cnt) {
-              const T v = xr[k];
+            for (int u = 0; u < SLICE_WIN; ++u) ya[u] += tp[u - kk + K - 1] * v;
+          }
+        } else {
+          // float64: a sliding register window over the taps
+          const T* tc = A.tapsL + (long)cg * TS + TO + loL - ib;
 #pragma unroll
-              for (int tt = 0; tt < SLICE_WIN; ++tt) ya[tt] += rg[(tt - u + SLICE_WIN * 4) % SLICE_WIN] * v;
-              rg[(SLICE_WIN * 4 - u - 1) % SLICE_WIN] = tc[-(k + 1)];
+          for (int u = 0; u < SLICE_WIN; ++u) rg[u] = tc[u - k0];
+          const T* xr = dh + c * DH_LD;
+          for (int kb = k0; kb < k0 + K && kb < cnt; kb += SLICE_WIN) {
+#pragma unroll
+            for (int u = 0; u < SLICE_WIN; ++u) {
+              const int k = kb + u;
+              if (k < cnt) {
+                const T v = xr[k];
+#pragma unroll
+                for (int tt = 0; tt < SLICE_WIN; ++tt) ya[tt] += rg[(tt - u + SLICE_WIN * 4) % SLICE_WIN] * v;
+                rg[(SLICE_WIN * 4 - u - 1) % SLICE_WIN] = tc[-(k + 1)];
+              }
             }
           }
         }
