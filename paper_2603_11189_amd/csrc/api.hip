@@ -356,7 +356,11 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, bo
 template <typename T, int DP, bool FIRST, bool LAST, bool BF>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
-  const size_t lds = (2 * (size_t)DP * DP + (LAST ? (size_t)DEEP_WAVES * std::min(DP, DH_CH) * DH_LD : 0)) * sizeof(T);
+  // F1 (not in the first block) and F2, then the last block's per-wave copies of dh or the
+  // read-out weights of one tile position
+  const size_t lds = ((FIRST ? 1 : 2) * (size_t)DP * DP +
+                      (LAST ? (size_t)DEEP_WAVES * std::min(DP, DH_CH) * DH_LD : (size_t)DP * 64 + 2 * DP)) *
+                     sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
     allow_lds(deep_kernel<T, DP, FIRST, LAST, BF>, lds);
@@ -367,9 +371,12 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
     cus = std::max(c, 1);
     per_cu = std::max(n, 1);
   }
-  const long tiles = (long)F * (m->Np / 64);
+  const int nt = m->Np / 64;
+  const long tiles = (long)F * nt;
   long grid = std::min<long>((tiles + DEEP_WAVES - 1) / DEEP_WAVES, (long)cus * per_cu);
-  grid = std::max<long>(NXCD, grid / NXCD * NXCD);
+  // workgroups per XCD: a multiple of the tile positions (each workgroup keeps one)
+  const long nbx = std::max<long>(nt, grid / NXCD / nt * nt);
+  grid = nbx * NXCD;
   const double Nr = m->desc.N, dr = m->desc.d, fld = Nr * dr * sizeof(T);
   const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
   {
@@ -602,7 +609,8 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
     STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
     const int nt = Np / 64;
-    STCHK(ws_get(m, "ab_rho", (size_t)F * nt * 2 * sizeof(double), &prho));
+    // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
+    STCHK(ws_get(m, "ab_rho", (size_t)std::max(L - 1, 1) * F * nt * 2 * sizeof(double), &prho));
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
     double* rho = (double*)prho;
@@ -619,7 +627,6 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
       HIPCHK(hipGetLastError());
     }
-    fill_kernel<double><<<256, 256, 0, st>>>(rho, 2L * F * nt, 0.0);
     if (L >= 2) {
       void* psp;
       STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
@@ -630,7 +637,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       for (int l = 1; l <= L - 1; ++l) {
         MixArgs<T> a{};
         a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
-        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_nt = nt;
+        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_blk = 2L * F * nt;
         a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
         a.out = du; a.rho = rho; a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom;
         a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;

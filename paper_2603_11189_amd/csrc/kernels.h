@@ -363,8 +363,8 @@ template <typename T> struct MixArgs {
   T* p0_out;             // FWD cache of q (nullable)
   const T* phi_next;     // FWD inject: phi^(l+1) [C][DP][Np]
   T* out;                // [C][DP][Np] (unused by the last deep block)
-  double* rho;           // FWD: [C][2] accumulated; deep: [F][rho_nt][2] per 64-site tile
-  int rho_nt;            // deep: tiles per flip in rho
+  double* rho;           // FWD: [C][2] accumulated; deep: [L-1][Fa][Np/64][2] per block and tile
+  long rho_blk;          // deep: doubles between the blocks' parts of rho (Fa Np/64 2)
   T* R_acc;              // FWD: residual sum R += h (nullable)
   // deep blocks (per flip)
   CfgMap map;            // flip -> (b, m)
@@ -580,12 +580,13 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 // perturbation through the frozen vertex plus the vertex change on the slice), one 64-site
 // tile per wave step. Block 1 builds q from the unit-flip table Pq instead of reading w.
 // Each wave walks its tiles with the next tile's input already in flight while the current
-// one is mixed. Tiles are dealt out per XCD in
-// contiguous ranges (workgroup w runs on XCD w mod 8), so the flips of one sample, which
-// share their background caches, meet in the same L2. Each tile's read-out lands in
-// rho[f][t].
+// one is mixed. Flips are dealt out per XCD in contiguous ranges (workgroup w runs on XCD
+// w mod 8), so the flips of one sample, which share their background caches, meet in the
+// same L2; within an XCD every workgroup keeps one tile position t and runs over flips.
+// Each tile's read-out is stored (not accumulated) in the block's part of rho[l][f][t].
 // Every workgroup keeps both channel-mixing matrices in LDS in fragment order (every
-// operand read is one contiguous 64-lane access). Blocks before the last store du. The
+// operand read is one contiguous 64-lane access), and, before the last block, the read-out
+// weights omega / N of its tile position and A. Blocks before the last store du. The
 // last block (LAST) instead reads out dh with Wk + tau and forms, per tile, the partial
 // slice of the last mixer's output, part[f][t][s][c] = sum_{i' in tile} g^(L)_c(site_s - i')
 // dh[c][i'], 32 channels at a time from a channel-major copy in LDS (row stride DH_LD, odd,
@@ -611,13 +612,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   constexpr int MT = DP / 16, KS = DP / 4, KB = DP / 32;
   // the next tile's input is prefetched into registers unless that would not fit
   constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
-  T* F1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of V, phase 1
-  T* F2 = F1 + DP * DP;                     // [MT][MT][64][4]: operand A of U, phase 2
+  // LDS: F1 (not in the first block), F2, then the last block's per-wave copies of dh or
+  // the other blocks' read-out weights (deep_lds gives the size)
+  T* F1 = reinterpret_cast<T*>(smem_raw);    // [KS][64][MT]: operand A of V, phase 1
+  T* F2 = F1 + (FIRST ? 0 : DP * DP);         // [MT][MT][64][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
   constexpr int CPG = DP < DH_CH ? DP : DH_CH;     // LAST: channels per slice group
   T* dh = F2 + DP * DP + wave * CPG * DH_LD;       // LAST: this wave's [CPG][DH_LD] copy
+  T* om_s = F2 + DP * DP;                          // not LAST: omega / N [DP][64] of tile t
+  T* ac_s = om_s + DP * 64;                        // not LAST: A^T [2][DP]
   const int N = A.N, Np = A.Np, l = A.l;
+  const int nt = Np / 64;
+  const int xcd = blockIdx.x % NXCD, bx = blockIdx.x / NXCD, nbx = gridDim.x / NXCD;
+  const int t = bx % nt;  // this workgroup's tile position (the host makes nbx a multiple of nt)
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
   __bf16* F1h = reinterpret_cast<__bf16*>(F1);  // BF: [KB][MT][64][8]
@@ -645,16 +653,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
       F2[idx] = Ut[(16 * mi + M::row(ln, r)) * DP + 16 * mo + (ln & 15)];
     }
   }
+  if constexpr (!LAST) {
+    for (int idx = threadIdx.x; idx < DP * 64; idx += blockDim.x)
+      om_s[idx] = A.tb.omN[(long)(idx >> 6) * Np + 64 * t + (idx & 63)];
+    for (int idx = threadIdx.x; idx < 2 * DP; idx += blockDim.x) ac_s[idx] = A.tb.Ac[idx];
+  }
   __syncthreads();  // the only workgroup barrier: the waves run independently from here
   const int F = A.dyn.count(A.C);
   const int cfg0 = A.dyn.first(A.cfg0);
-  const int nt = Np / 64;
-  const long total = (long)F * nt;
-  const int xcd = blockIdx.x % NXCD, bx = blockIdx.x / NXCD, nbx = gridDim.x / NXCD;
-  const long per = (total + NXCD - 1) / NXCD;
-  const long q_hi = min(total, (long)xcd * per + per);
-  const long wstride = (long)nbx * DEEP_WAVES;
-  long q = (long)xcd * per + (long)bx * DEEP_WAVES + wave;
+  // flips of this XCD: [g_lo, g_hi); the nbx / nt workgroups of tile position t share them
+  const int perF = (F + NXCD - 1) / NXCD;
+  const int g_hi = min(F, xcd * perF + perF);
+  const int gstride = (nbx / nt) * DEEP_WAVES;
+  int g = xcd * perF + (bx / nt) * DEEP_WAVES + wave;
   const int TO = tap_off(Np), TS = tap_stride(Np);
   // Addresses are a per-lane base plus an offset that is the same for every lane (kept in
   // scalar registers), so that no per-lane 64-bit offsets stay live across the tile loop.
@@ -667,25 +678,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // operands only: it does not fit the register budget of the other variants)
   constexpr bool PFC = PF && !BF && sizeof(T) == 4;
   V4<T> cb[PFC ? MT * 4 : 1];
-  auto prefetch = [&](long qq) {
-    const T* src = A.X + (qq / nt) * DP * Np + 64 * (qq % nt) + kq_row * Np + 4 * j;
+  auto prefetch = [&](int gq) {
+    const T* src = A.X + (long)gq * DP * Np + 64 * t + kq_row * Np + 4 * j;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
     if constexpr (PFC) {
-      const int gq = (int)(qq / nt);
-      const T* cs = A.chi + (long)(A.map.cb[cfg0 + gq] - A.b0) * DP * Np + (long)lrow * Np + 64 * (qq % nt) + 4 * j;
+      const T* cs = A.chi + (long)(A.map.cb[cfg0 + gq] - A.b0) * DP * Np + (long)lrow * Np + 64 * t + 4 * j;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) cb[mt * 4 + r] = ld4(cs + (16 * mt + M::r_row(r)) * Np);
     }
   };
-  if (PF && q < q_hi) prefetch(q);
-  for (; q < q_hi; q += wstride) {
+  if (PF && g < g_hi) prefetch(g);
+  for (; g < g_hi; g += gstride) {
     // compiler-only barrier: the weight operands are reloaded per tile rather than hoisted
     // out of the loop into registers (which would halve the occupancy)
     asm volatile("" ::: "memory");
-    const int g = (int)(q / nt), t = (int)(q % nt);
     const int4 sg = A.geom[g];
     const int bglob = A.map.cb[cfg0 + g];
     const long fo = (long)g * DP * Np, bo = (long)(bglob - A.b0) * DP * Np;
@@ -804,7 +813,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         if (r == 3) __builtin_amdgcn_sched_barrier(0);
       }
     // the next tile's input travels while this one is mixed and stored
-    if (PF && q + wstride < q_hi) prefetch(q + wstride);
+    if (PF && g + gstride < g_hi) prefetch(g + gstride);
     // BF: x as bf16 operands of phase 2, in accumulator channel order (step sk: channels
     // 16 (2 sk + e / 4) + row(lane, e mod 4))
     bf8 xh[BF ? KB : 1][4];
@@ -876,14 +885,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
               part1 += (double)w1.v[n] * (double)y[n];
             }
           } else {
-            // read-out with Wk = A^T omega / N: one site vector of omega / N per channel
-            const V4<T> wo = ld4(A.tb.omN + o);
+            // read-out with Wk = A^T omega / N: one site vector of omega / N per channel,
+            // both from LDS
             const int ch = 16 * mo + M::row(lane, r);
+            const V4<T> wo = ld4(om_s + ch * 64 + 4 * j);
             double sw = 0.0;
 #pragma unroll
             for (int n = 0; n < 4; ++n) sw += (double)wo.v[n] * (double)y[n];
-            part0 += (double)A.tb.Ac[ch] * sw;
-            part1 += (double)A.tb.Ac[DP + ch] * sw;
+            part0 += (double)ac_s[ch] * sw;
+            part1 += (double)ac_s[DP + ch] * sw;
           }
           if (LAST) {
             const int cl = 16 * (mo - mg) + M::row(lane, r);
@@ -948,16 +958,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
     if (lane == 0) {
-      double* rp = A.rho + ((long)g * nt + t) * 2;
-      rp[0] += part0;
-      rp[1] += part1;
+      double* rp = A.rho + (long)(l - 1) * A.rho_blk + ((long)g * nt + t) * 2;
+      rp[0] = part0;
+      rp[1] = part1;
     }
   }
 }
 
 // Finishes each flip after the tiled last block (one wave per flip): sums the tiles' partial
 // slices into y_L, forms e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, reads out e^(L)
-// and e^(0), adds the deep blocks' read-outs rho[f][t] and writes
+// and e^(0), adds the deep blocks' read-outs rho[l][f][t] and writes
 // log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
 template <typename T, int DP>
 __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
@@ -1048,10 +1058,11 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
       }
     }
   }
-  // read-outs of the tiled deep blocks (the last one included), lanes over tiles
-  for (int t = lane; t < nt; t += 64) {
-    o0 += A.rho[((long)g * nt + t) * 2];
-    o1 += A.rho[((long)g * nt + t) * 2 + 1];
+  // read-outs of the tiled deep blocks 1 .. L-1, lanes over (block, tile)
+  for (int bt = lane; bt < (A.L - 1) * nt; bt += 64) {
+    const double* rp = A.rho + (long)(bt / nt) * A.rho_blk + ((long)g * nt + bt % nt) * 2;
+    o0 += rp[0];
+    o1 += rp[1];
   }
   o0 = wave_sum(o0);
   o1 = wave_sum(o1);
