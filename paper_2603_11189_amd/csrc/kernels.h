@@ -678,6 +678,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // operands only: it does not fit the register budget of the other variants)
   constexpr bool PFC = PF && !BF && sizeof(T) == 4;
   V4<T> cb[PFC ? MT * 4 : 1];
+  // without that prefetch (the last block, float) the whole input tile is requested at once
+  // when the tile starts, so its latency is met once rather than at every step
+  constexpr bool XL = !PF && !FIRST && sizeof(T) == 4;
+  V4<T> xl[XL ? KS : 1];
   auto prefetch = [&](int gq) {
     const T* src = A.X + (long)gq * DP * Np + 64 * t + kq_row * Np + 4 * j;
 #pragma unroll
@@ -726,6 +730,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           if (r == 3) __builtin_amdgcn_sched_barrier(0);
         }
     } else if constexpr (BF) {
+      if constexpr (XL) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -738,6 +746,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           const int ks = 8 * sk + e;
           V4<T> v;
           if constexpr (PF) v = xb[ks];
+          else if constexpr (XL) v = xl[ks];
           else v = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
 #pragma unroll
           for (int n = 0; n < 4; ++n) bb[n][e] = (__bf16)v.v[n];
@@ -750,6 +759,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         }
       }
     } else {
+      if constexpr (XL) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -761,6 +774,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         if constexpr (PF) {
 #pragma unroll
           for (int n = 0; n < 4; ++n) bv[n] = xb[ks].v[n];
+        } else if constexpr (XL) {
+#pragma unroll
+          for (int n = 0; n < 4; ++n) bv[n] = xl[ks].v[n];
         } else {
           const V4<T> v = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
 #pragma unroll
@@ -849,6 +865,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
       }
 #pragma unroll 1
       for (int mo = mg; mo < mg + GM; ++mo) {
+        // LAST, float: the read-out weights tau of this output tile travel during its products
+        constexpr bool TWP = LAST && sizeof(T) == 4;
+        V4<T> tw[TWP ? 8 : 1];
+        if constexpr (TWP) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const long o = 2 * bo + lo_off + (16 * mo + M::r_row(r)) * Np;
+            tw[2 * r] = ld4(A.tau + o);
+            tw[2 * r + 1] = ld4(A.tau + (long)DP * Np + o);
+          }
+        }
         acc_t a2[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
@@ -876,9 +903,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           T y[4];
 #pragma unroll
           for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
-          if (LAST) {
+          if constexpr (LAST) {
             // read-out with Wk + tau (tau already carries Wk when L >= 2)
-            const V4<T> w0 = ld4(A.tau + 2 * bo + o), w1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
+            V4<T> w0, w1;
+            if constexpr (TWP) {
+              w0 = tw[2 * r];
+              w1 = tw[2 * r + 1];
+            } else {
+              w0 = ld4(A.tau + 2 * bo + o);
+              w1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
+            }
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
               part0 += (double)w0.v[n] * (double)y[n];
