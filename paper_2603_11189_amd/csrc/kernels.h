@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // the next tile's input is prefetched into registers unless that would not fit
   constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
   // LDS: F1 (not in the first block), F2, then the last block's per-wave copies of dh or
-  // the other blocks' read-out weights (deep_lds gives the size)
+  // the other blocks' read-out weights (sized by the host in launch_deep)
   T* F1 = reinterpret_cast<T*>(smem_raw);    // [KS][64][MT]: operand A of V, phase 1
   T* F2 = F1 + (FIRST ? 0 : DP * DP);         // [MT][MT][64][4]: operand A of U, phase 2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -820,9 +820,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
         for (int n = 0; n < 4; ++n) x[n] = c.v[n] * acc[mt][n][r];
         if (in_slice) {
+          // the four sites' operands requested together (a site outside S_l reads the
+          // vertex change at position 0 and weights it by zero)
+          const V4<T> pv = ld4(A.p0 + bo + lo_off + uo);
+          T dv[4];
 #pragma unroll
-          for (int n = 0; n < 4; ++n)
-            if (sidx[n] >= 0) x[n] += dchi_l[sidx[n] * DP + ch] * (A.p0[bo + lo_off + uo + n] + acc[mt][n][r]);
+          for (int n = 0; n < 4; ++n) dv[n] = dchi_l[max(sidx[n], 0) * DP + ch];
+#pragma unroll
+          for (int n = 0; n < 4; ++n) x[n] += (sidx[n] >= 0 ? dv[n] : T(0)) * (pv.v[n] + acc[mt][n][r]);
         }
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? x[n] : T(0);
