@@ -123,6 +123,7 @@ struct dn_model {
   // launch shapes (dn_autotune): 16-site output tiles per wave of the Toeplitz kernel
   // (0 = by chain length) and the bytes of flip fields per ABACUS chunk
   int conv_nt = 0;
+  bool conv_split = true;  // DN_TOEPLITZ_SPLIT3: float Toeplitz products on conv_split_kernel
   size_t flip_budget = (size_t)3 << 30;
   bool tuned = false;
   double* jac64 = nullptr;
@@ -265,6 +266,19 @@ template <typename K> void allow_lds(K kernel, size_t bytes) {
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
+// Compute units of the current device (cached per device; 256 if the query fails).
+static int cu_count() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cached[dev].load();
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cached[dev].store(c);
+  }
+  return c;
+}
+
 // ------------------------------------------------------------------------------------------
 // Network passes, templated on element type T and padded channel count DP.
 
@@ -284,6 +298,23 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   int nt = m->conv_nt ? m->conv_nt : (Np >= 256 ? 4 : Np / 64);
   if (nt < 1 || nt > 4 || Np % (16 * nt) != 0) nt = Np >= 256 ? 4 : Np / 64;
   dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
+  if constexpr (std::is_same<T, float>::value) {
+    if (m->conv_split) {
+      const size_t lds3 = (3 * (size_t)CONV_MC * CS_LD + 3 * 8 * (size_t)(2 * Np + 16)) * sizeof(__bf16);
+      // workgroups run over configuration blocks: about two per CU in all (the split taps
+      // are then built once per workgroup)
+      const long nblk = grid.x;
+      grid.x = (unsigned)std::max<long>(1, std::min<long>(nblk, (2L * cu_count() + (long)m->DP * grid.z - 1) / ((long)m->DP * grid.z)));
+      switch (nt) {
+        case 1: allow_lds(conv_split_kernel<1>, lds3); conv_split_kernel<1><<<grid, 256, lds3, st>>>(a); break;
+        case 2: allow_lds(conv_split_kernel<2>, lds3); conv_split_kernel<2><<<grid, 256, lds3, st>>>(a); break;
+        case 3: allow_lds(conv_split_kernel<3>, lds3); conv_split_kernel<3><<<grid, 256, lds3, st>>>(a); break;
+        default: allow_lds(conv_split_kernel<4>, lds3); conv_split_kernel<4><<<grid, 256, lds3, st>>>(a); break;
+      }
+      HIPCHK(hipGetLastError());
+      return DN_OK;
+    }
+  }
   switch (nt) {
     case 1: allow_lds(conv_kernel<T, 1>, lds); conv_kernel<T, 1><<<grid, 256, lds, st>>>(a); break;
     case 2: allow_lds(conv_kernel<T, 2>, lds); conv_kernel<T, 2><<<grid, 256, lds, st>>>(a); break;
@@ -1116,6 +1147,8 @@ std::vector<uint64_t> ragged_key(const std::vector<RaggedInst>& ins, int K, int 
   std::vector<uint64_t> k{(uint64_t)ins.size(), (uint64_t)K, (uint64_t)dev};
   for (auto& in : ins) {
     const dn_ham_desc& h = in.ham;
+    // launch shapes and the Toeplitz mode are recorded into the graph as well
+    k.insert(k.end(), {(uint64_t)in.m->conv_nt, (uint64_t)in.m->flip_budget, (uint64_t)in.m->conv_split});
     k.insert(k.end(), {in.m->uid, in.m->ws_gen, (uint64_t)in.B, (uint64_t)(uintptr_t)in.spins,
                        (uint64_t)(uintptr_t)in.logpsi, (uint64_t)(uintptr_t)in.eloc, (uint64_t)h.kind,
                        (uint64_t)h.bc, (uint64_t)h.paper_form, dbits(h.J), dbits(h.alpha), dbits(h.h),
@@ -1485,6 +1518,13 @@ dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget
   m->conv_nt = conv_nt;
   m->flip_budget = flip_budget ? (size_t)flip_budget : ((size_t)3 << 30);
   m->tuned = true;
+  return DN_OK;
+}
+
+dn_status dn_set_toeplitz_mode(dn_model* m, int32_t mode) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (mode != DN_TOEPLITZ_SPLIT3 && mode != DN_TOEPLITZ_FP32) return fail(DN_EINVAL, "unknown Toeplitz mode");
+  m->conv_split = mode == DN_TOEPLITZ_SPLIT3;
   return DN_OK;
 }
 

@@ -332,6 +332,170 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs<T> A) {
       }
 }
 
+// Toeplitz product of float fields on the bf16 matrix cores. Both operands are split into
+// three bf16 terms, x = x0 + x1 + x2 (exactly: each term carries the next 8 significant
+// bits of what the previous ones left), and the six partial products x_a g_b with
+// a + b <= 2 are accumulated in float; the three dropped ones are below 2^-24 of |x g|, the
+// rounding unit of a float product, so the result has the error of a float dot product.
+// Workgroup: 64 configurations x 64 NT output sites of one channel (4 waves x 16 NT sites).
+// The field chunk (64 configurations x 64 input sites) is split into LDS as [3][64][CS_LD];
+// the Toeplitz operand uses the reversed taps R[p] = g(Np - 1 - p), split likewise and held
+// as eight shifted copies tsh[b][s][q] = R_b[q + s], so that the eight consecutive taps a
+// lane needs are one aligned 16-byte read.
+constexpr int CS_KC = 64;  // input sites per chunk
+constexpr int CS_LD = 72;  // bf16 row stride of the split field chunk (64 + 8: conflict-free rows)
+
+__device__ inline void split3(float v, __bf16& b0, __bf16& b1, __bf16& b2) {
+  b0 = (__bf16)v;
+  const float r1 = v - (float)b0;
+  b1 = (__bf16)r1;
+  b2 = (__bf16)(r1 - (float)b1);
+}
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+// the same for two values, each bf16 pair formed by one packed conversion
+__device__ inline void split3x2(f2v v, bf2& b0, bf2& b1, bf2& b2) {
+  b0 = __builtin_convertvector(v, bf2);
+  const f2v r1 = v - __builtin_convertvector(b0, f2v);
+  b1 = __builtin_convertvector(r1, bf2);
+  b2 = __builtin_convertvector(r1 - __builtin_convertvector(b1, f2v), bf2);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv_split_kernel(ConvArgs<float> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* xs = reinterpret_cast<__bf16*>(smem_raw);  // [3][CONV_MC][CS_LD]
+  __bf16* tsh = xs + 3 * CONV_MC * CS_LD;            // [3][8][TL]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.y;
+  const int C = A.dyn.count(A.C);
+  const int nblk = (C + CONV_MC - 1) / CONV_MC;  // blocks of 64 configurations
+  if ((int)blockIdx.x >= nblk) return;
+  // copy length: 2 Np - 1 taps and room for the last 8-wide read; 16 mod 64 (Np a multiple
+  // of 64) puts the eight shifted copies on different banks for the reads of 8 lanes
+  const int Np = A.Np, TL = 2 * Np + 16;
+  const int wsite0 = blockIdx.z * 64 * NT + wave * 16 * NT;  // this wave's first output site
+  {
+    // tp[-p] = g(Np - 1 - p) = R[p], p = 0 .. 2 Np - 2 (zero beyond); every thread requests
+    // its entries before splitting any
+    const float* tp = A.taps + (long)c * tap_stride(Np) + tap_off(Np) + Np - 1;
+    constexpr int PER = 8;  // entries per thread and pass
+    for (int base = 0; base < 8 * TL; base += 256 * PER) {
+      float v[PER];
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int idx = base + e * 256 + threadIdx.x;
+        const int s = idx / TL, p = idx - s * TL + s;
+        v[e] = (idx < 8 * TL && p <= 2 * Np - 2) ? tp[-p] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int idx = base + e * 256 + threadIdx.x;
+        if (idx < 8 * TL) {
+          __bf16 b0, b1, b2;
+          split3(v[e], b0, b1, b2);
+          tsh[idx] = b0;  // idx = s TL + q
+          tsh[8 * TL + idx] = b1;
+          tsh[16 * TL + idx] = b2;
+        }
+      }
+    }
+  }
+  const long cstride = (long)A.DP * Np;
+  // staging: thread t moves sites 2 (t mod 32) + {0, 1} of configuration rows t / 32 + 8 u,
+  // one chunk ahead through registers; the workgroup runs over configuration blocks
+  // blockIdx.x, blockIdx.x + gridDim.x, ... (the split taps are built once)
+  const int srow = threadIdx.x >> 5, scol = 2 * (threadIdx.x & 31);
+  const float* xrow = A.X + (long)c * Np + scol;
+  float2 pre[8];
+  auto fetch = [&](int blk, int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cfg = blk * CONV_MC + srow + 8 * u;
+      pre[u] = cfg < C ? *reinterpret_cast<const float2*>(xrow + (long)cfg * cstride + k0) : make_float2(0.f, 0.f);
+    }
+  };
+  // B operand of output tile n: R[p + e] with p = p0 + k0 + 32 ks; k0 and 32 ks are
+  // multiples of 8, so the shifted copy (p0 mod 8) and a per-lane base are fixed
+  int tbase[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int p0 = Np - 1 - (wsite0 + 16 * n + (lane & 15)) + 8 * (lane >> 4);
+    const int sh = p0 & 7;
+    tbase[n] = sh * TL + p0 - sh;
+  }
+  fetch(blockIdx.x, 0);
+  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int cfg0 = blk * CONV_MC;
+    f4 acc[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[a][n] = f4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < Np; k0 += CS_KC) {
+      __syncthreads();  // the previous chunk is consumed (and the taps are in place)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bf2 b0, b1, b2;
+        split3x2(f2v{pre[u].x, pre[u].y}, b0, b1, b2);
+        __bf16* d = xs + (srow + 8 * u) * CS_LD + scol;
+        *reinterpret_cast<bf2*>(d) = b0;
+        *reinterpret_cast<bf2*>(d + CONV_MC * CS_LD) = b1;
+        *reinterpret_cast<bf2*>(d + 2 * CONV_MC * CS_LD) = b2;
+      }
+      __syncthreads();
+      if (k0 + CS_KC < Np) fetch(blk, k0 + CS_KC);
+      else if (blk + (int)gridDim.x < nblk) fetch(blk + gridDim.x, 0);
+      if (wsite0 < Np) {
+#pragma unroll
+        for (int ks = 0; ks < CS_KC / 32; ++ks) {
+          // A: configuration rows 16 mt + (lane mod 16), sites 32 ks + 8 (lane / 16) + e
+          bf8 xa[3][4];
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+              xa[b][mt] = *reinterpret_cast<const bf8*>(xs + (b * CONV_MC + 16 * mt + (lane & 15)) * CS_LD + 32 * ks + 8 * (lane >> 4));
+          // B: g(i - k) for output site i = wsite0 + 16 n + (lane mod 16) and the lane's 8
+          // input sites k = k0 + 32 ks + 8 (lane / 16) + e, i.e. R[p + e]
+          bf8 tb[3][NT];
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+              tb[b][n] = *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
+          // the six products, smallest first; each step runs over all 4 NT accumulators
+#pragma unroll
+          for (int term = 0; term < 6; ++term) {
+            const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
+            const int tg = term == 0 ? 0 : term == 1 ? 1 : term == 2 ? 2 : term == 3 ? 0 : term == 4 ? 1 : 0;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
+          }
+        }
+      }
+    }
+    if (wsite0 < Np) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cfg = cfg0 + 16 * a + 4 * (lane >> 4) + r;
+            const int i = wsite0 + 16 * n + (lane & 15);
+            if (cfg < C && i < Np) {
+              float y = (i < A.N) ? acc[a][n][r] : 0.f;
+              if (A.add) y += A.add[(long)(cfg & 1) * cstride + (long)c * Np + i];
+              A.Y[(long)cfg * cstride + (long)c * Np + i] = y;
+            }
+          }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Vertex and channel mixing, fused with the read-out. One workgroup per configuration,
 // one wave per 64-site block; a wave's 16 matrix-core columns j and 4 tiles n cover sites
