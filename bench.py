@@ -30,6 +30,20 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}  # dense MFMA TFLOP/s of on
 HBM_PEAK = 8000.0                      # GB/s
 
 
+def mfma_peak(kind: str, prec: str, products: str, d: int):
+    """(peak TFLOP/s, basis) for the algorithmic (float) flops of a kernel class. With
+    three-term splits every float product costs six bf16 products, so the float-equivalent
+    peak is the bf16 dense peak / 6."""
+    split = products == "split3" and prec != "fp64"
+    if kind == "conv" and split:
+        return PEAK["bf16"] / 6, "bf16 dense peak / 6 (three-term split products)"
+    if kind == "mix_deep" and prec == "bf16" and d > 16:
+        return PEAK["bf16"], "bf16 dense peak"
+    if kind == "mix_deep" and split and d > 16:
+        return PEAK["bf16"] / 6, "bf16 dense peak / 6 (three-term split products)"
+    return PEAK[prec if prec != "bf16" else "fp32"], ("fp64" if prec == "fp64" else "fp32") + " dense peak"
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_11189_amd", "csrc")
@@ -135,6 +149,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the per-sample log-derivative leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuner)")
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
+    ap.add_argument("--products", default="split3", choices=["split3", "fp32"],
+                    help="float matrix-core products: three-term bf16 splits (default) or float32 matrix cores")
     ap.add_argument("--sweep", action="store_true",
                     help="ABACUS vs full re-evaluation for N in 64..512 at L = 2 and 4 (one JSON line each)")
     ap.add_argument("--paper-shapes", action="store_true",
@@ -196,6 +212,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    model.set_product_mode(args.products)
     tuned = None
     if args.shapes:
         nt, mib = (int(x) for x in args.shapes.split(","))
@@ -267,6 +284,9 @@ def main():
                    "path": main_path},
         "set_params_ms": set_params_ms,
         "launch_shapes": tuned or "defaults",
+        "products": ({"split3": "Toeplitz and deep channel-mixing products as three-term bf16 splits "
+                                "(six partial products, f32 accumulate: f32 error bound)",
+                      "fp32": "f32 matrix cores"}[args.products] if prec != "fp64" else "f64 matrix cores"),
     }
     if grad:
         out["grad_logpsi"] = grad
@@ -289,7 +309,7 @@ def main():
         dom = max(prof, key=lambda k: prof[k][0])
         ms, n, fl, by = prof[dom]
         achieved = fl / (ms * 1e-3) / 1e12
-        peak = PEAK[prec]
+        peak, basis = mfma_peak(dom, prec, args.products, shape.d)
         traffic = None
         tpath = os.path.join(ROOT, "profiles", "traffic.json")
         if os.path.exists(tpath):
@@ -300,8 +320,8 @@ def main():
                 traffic = ent["bytes_per_launch"]
         out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
                            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                           "avg_launch_ms": ms / n, "algorithmic_flops_per_launch": fl / n,
-                           "algorithmic_bytes_per_launch": by / n}
+                           "peak_basis": basis, "avg_launch_ms": ms / n,
+                           "algorithmic_flops_per_launch": fl / n, "algorithmic_bytes_per_launch": by / n}
 
     # CPU baseline (the oracle, untuned) on a bounded sample, and the error of both GPU paths
     if not args.no_cpu_baseline:
@@ -465,8 +485,9 @@ def bench_ragged(args) -> None:
         dom = max(tot, key=lambda k: tot[k][0])
         ms, n, fl, by = tot[dom]
         achieved = fl / (ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK["fp32"],
-                           "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
+        peak, basis = mfma_peak(dom, "fp32", "split3", 64)
+        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
+                           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None, "peak_basis": basis,
                            "avg_launch_ms": ms / n, "algorithmic_flops_per_launch": fl / n,
                            "measured_on": "one eager pass on one stream (graph replays record no events)"}
         out["per_kernel"] = {k: {"ms_per_step": v[0], "launches_per_step": v[1],

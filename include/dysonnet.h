@@ -48,8 +48,9 @@ typedef enum { DN_BC_OPEN = 0, DN_BC_PERIODIC = 1 } dn_bc;
 typedef enum { DN_ACT_SILU = 0, DN_ACT_TANH = 1, DN_ACT_IDENTITY = 2 } dn_act;
 /* Arithmetic of the network fields and channel mixing. FP64: everything float64.
  * FP32: float32 fields, float32 MFMA with float32 accumulation; the Green's-function
- * (Toeplitz) products by default on the bf16 matrix cores with both float operands split
- * into three bf16 terms, which keeps float32 accuracy (see dn_set_toeplitz_mode). BF16_MIXED (d > 16): the
+ * (Toeplitz) products and the ABACUS deep blocks' channel mixing by default on the bf16
+ * matrix cores with both float operands split into three bf16 terms, which keeps float32
+ * accuracy (see dn_set_product_mode). BF16_MIXED (d > 16): the
  * two channel-mixing products of every block (V and U: forward, adjoint and the ABACUS
  * propagation) take bfloat16 operands (round to nearest even) on the bf16 matrix cores
  * with float32 accumulation; everything else as FP32 (phi stream, Green's-function mixer,
@@ -182,16 +183,20 @@ dn_status dn_autotune(dn_model* m, const dn_ham_desc* ham, int32_t B_probe, int3
  * fields per ABACUS chunk (0 = 3 GiB). Marks the model as tuned. */
 dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget);
 
-/* Arithmetic of the Green's-function (Toeplitz mixer) products of a float32 or BF16-mixed
- * model, y_c(i) = sum_k g_c(i - k) x_c(k) (Sec. II, the S4 mixer as a Toeplitz matrix).
- * DN_TOEPLITZ_SPLIT3 (the default): each float operand is split into three bfloat16 terms,
+/* Arithmetic of the float matrix-core products of the estimator: the Green's-function
+ * (Toeplitz mixer) products y_c(i) = sum_k g_c(i - k) x_c(k) (Sec. II, the S4 mixer as a
+ * Toeplitz matrix) and the ABACUS deep blocks' channel mixing V and U (Sec. III).
+ * DN_PRODUCT_SPLIT3 (the default): each float operand is split into three bfloat16 terms,
  * x = x0 + x1 + x2 exactly (each term the next 8 significant bits), and the six partial
- * products x_a g_b with a + b <= 2 run on the bf16 matrix cores with float32 accumulation;
- * the dropped ones are below 2^-24 |x g|, so the result has the error bound of a float32 dot
- * product. DN_TOEPLITZ_FP32: the float32 matrix cores (one product per term). Float64
- * models ignore the setting. DN_EINVAL for another value. Takes effect on the next call. */
-typedef enum { DN_TOEPLITZ_SPLIT3 = 0, DN_TOEPLITZ_FP32 = 1 } dn_toeplitz_mode;
-dn_status dn_set_toeplitz_mode(dn_model* m, int32_t mode);
+ * products x_a y_b with a + b <= 2 run on the bf16 matrix cores with float32 accumulation;
+ * the dropped ones are below 2^-24 |x y|, so the result has the error bound of a float32
+ * dot product. DN_PRODUCT_FP32: the float32 matrix cores (one product per term).
+ * Float32 models use the setting for both kinds of product; BF16-mixed models for the
+ * Toeplitz products (their channel mixing is bf16 by definition); float64 models ignore it;
+ * the forward and adjoint background passes and the gradients stay on float32 matrix cores.
+ * DN_EINVAL for another value. Takes effect on the next call. */
+typedef enum { DN_PRODUCT_SPLIT3 = 0, DN_PRODUCT_FP32 = 1 } dn_product_mode;
+dn_status dn_set_product_mode(dn_model* m, int32_t mode);
 
 /* Execution modes of dn_ragged_eloc. */
 typedef enum {

@@ -24,11 +24,11 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
-           "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_toeplitz_mode",
+           "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
            "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
 RAGGED_MODE = {"eager": 0, "graph": 1}
-TOEPLITZ_MODE = {"split3": 0, "fp32": 1}
+PRODUCT_MODE = {"split3": 0, "fp32": 1}
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
                 "eloc", "other")
 
@@ -75,7 +75,7 @@ def lib():
         L.dn_grad_logpsi.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.dn_autotune.argtypes = [vp, ctypes.POINTER(HamDesc), i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
         L.dn_set_launch_shapes.argtypes = [vp, i32, i64]
-        L.dn_set_toeplitz_mode.argtypes = [vp, i32]
+        L.dn_set_product_mode.argtypes = [vp, i32]
         L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -86,7 +86,7 @@ def lib():
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
-                   "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_toeplitz_mode",
+                   "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
                    "dn_ragged_eloc", "dn_profile_enable",
                    "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
@@ -206,9 +206,9 @@ class Model:
     def set_launch_shapes(self, conv_nt: int = 0, flip_budget: int = 0):
         _check(lib().dn_set_launch_shapes(self.handle, conv_nt, flip_budget))
 
-    def set_toeplitz_mode(self, mode: str = "split3"):
-        """"split3" (three-term bf16 splits, the default) or "fp32" (float32 matrix cores)."""
-        _check(lib().dn_set_toeplitz_mode(self.handle, TOEPLITZ_MODE[mode]))
+    def set_product_mode(self, mode: str = "split3"):
+        """Float matrix-core products: "split3" (three-term bf16 splits, the default) or "fp32"."""
+        _check(lib().dn_set_product_mode(self.handle, PRODUCT_MODE[mode]))
 
     def profile_enable(self, on: bool = True):
         _check(lib().dn_profile_enable(self.handle, int(on)))

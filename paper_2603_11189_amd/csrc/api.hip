@@ -123,7 +123,7 @@ struct dn_model {
   // launch shapes (dn_autotune): 16-site output tiles per wave of the Toeplitz kernel
   // (0 = by chain length) and the bytes of flip fields per ABACUS chunk
   int conv_nt = 0;
-  bool conv_split = true;  // DN_TOEPLITZ_SPLIT3: float Toeplitz products on conv_split_kernel
+  bool split3 = true;  // DN_PRODUCT_SPLIT3: three-term bf16 splits (conv_split_kernel, deep_kernel BF = 3)
   size_t flip_budget = (size_t)3 << 30;
   bool tuned = false;
   double* jac64 = nullptr;
@@ -299,7 +299,7 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   if (nt < 1 || nt > 4 || Np % (16 * nt) != 0) nt = Np >= 256 ? 4 : Np / 64;
   dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
   if constexpr (std::is_same<T, float>::value) {
-    if (m->conv_split) {
+    if (m->split3) {
       const size_t lds3 = (3 * (size_t)CONV_MC * CS_LD + 3 * 8 * (size_t)(2 * Np + 16)) * sizeof(__bf16);
       // workgroups run over configuration blocks: about two per CU in all (the split taps
       // are then built once per workgroup)
@@ -384,14 +384,13 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, bo
 
 // Persistent tiled launch of a deep block (see deep_kernel); the last one is followed by
 // last_finish_kernel, one wave per flip.
-template <typename T, int DP, bool FIRST, bool LAST, bool BF>
+template <typename T, int DP, bool FIRST, bool LAST, int BF>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
   // F1 (not in the first block) and F2, then the last block's per-wave copies of dh or the
   // read-out weights of one tile position
-  const size_t lds = ((FIRST ? 1 : 2) * (size_t)DP * DP +
-                      (LAST ? (size_t)DEEP_WAVES * std::min(DP, DH_CH) * DH_LD : (size_t)DP * 64 + 2 * DP)) *
-                     sizeof(T);
+  const size_t lds = (size_t)deep_wbytes(DP, sizeof(T), FIRST, BF) +
+                     (LAST ? (size_t)DEEP_WAVES * deep_cpg(DP, BF) * DH_LD : (size_t)DP * 64 + 2 * DP) * sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
     allow_lds(deep_kernel<T, DP, FIRST, LAST, BF>, lds);
@@ -427,7 +426,7 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   return DN_OK;
 }
 
-template <typename T, int DP, bool BF>
+template <typename T, int DP, int BF>
 dn_status launch_deep_mode(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
   if (first && last) return launch_deep<T, DP, true, true, BF>(m, a, F, st, Bc);
   if (last) return launch_deep<T, DP, false, true, BF>(m, a, F, st, Bc);
@@ -438,9 +437,10 @@ dn_status launch_deep_mode(dn_model* m, const MixArgs<T>& a, int F, hipStream_t 
 template <typename T, int DP>
 dn_status launch_deep_any(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
   if constexpr (std::is_same<T, float>::value && DP >= 32) {
-    if (use_bf16(m)) return launch_deep_mode<T, DP, true>(m, a, F, st, Bc, first, last);
+    if (use_bf16(m)) return launch_deep_mode<T, DP, 1>(m, a, F, st, Bc, first, last);
+    if (m->split3) return launch_deep_mode<T, DP, 3>(m, a, F, st, Bc, first, last);
   }
-  return launch_deep_mode<T, DP, false>(m, a, F, st, Bc, first, last);
+  return launch_deep_mode<T, DP, 0>(m, a, F, st, Bc, first, last);
 }
 
 // Forward of C configurations listed by `map` entries [cfg0, cfg0+C). rho[C][2] receives
@@ -1147,8 +1147,8 @@ std::vector<uint64_t> ragged_key(const std::vector<RaggedInst>& ins, int K, int 
   std::vector<uint64_t> k{(uint64_t)ins.size(), (uint64_t)K, (uint64_t)dev};
   for (auto& in : ins) {
     const dn_ham_desc& h = in.ham;
-    // launch shapes and the Toeplitz mode are recorded into the graph as well
-    k.insert(k.end(), {(uint64_t)in.m->conv_nt, (uint64_t)in.m->flip_budget, (uint64_t)in.m->conv_split});
+    // launch shapes and the product mode are recorded into the graph as well
+    k.insert(k.end(), {(uint64_t)in.m->conv_nt, (uint64_t)in.m->flip_budget, (uint64_t)in.m->split3});
     k.insert(k.end(), {in.m->uid, in.m->ws_gen, (uint64_t)in.B, (uint64_t)(uintptr_t)in.spins,
                        (uint64_t)(uintptr_t)in.logpsi, (uint64_t)(uintptr_t)in.eloc, (uint64_t)h.kind,
                        (uint64_t)h.bc, (uint64_t)h.paper_form, dbits(h.J), dbits(h.alpha), dbits(h.h),
@@ -1521,10 +1521,10 @@ dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget
   return DN_OK;
 }
 
-dn_status dn_set_toeplitz_mode(dn_model* m, int32_t mode) {
+dn_status dn_set_product_mode(dn_model* m, int32_t mode) {
   if (!m) return fail(DN_EINVAL, "null model");
-  if (mode != DN_TOEPLITZ_SPLIT3 && mode != DN_TOEPLITZ_FP32) return fail(DN_EINVAL, "unknown Toeplitz mode");
-  m->conv_split = mode == DN_TOEPLITZ_SPLIT3;
+  if (mode != DN_PRODUCT_SPLIT3 && mode != DN_PRODUCT_FP32) return fail(DN_EINVAL, "unknown product mode");
+  m->split3 = mode == DN_PRODUCT_SPLIT3;
   return DN_OK;
 }
 

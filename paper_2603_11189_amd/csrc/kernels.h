@@ -760,31 +760,50 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 constexpr int DEEP_WAVES = 4;
 constexpr int NXCD = 8;
 // waves per SIMD each variant's register budget is sized for (the last block's LDS holds it
-// to two workgroups per CU in any case)
-constexpr int deep_occ(int elem_bytes, bool prefetch, bool last) { return elem_bytes == 4 && !prefetch && !last ? 3 : 2; }
+// to two workgroups per CU in any case; three-term bf16 operands need the room of two)
+constexpr int deep_occ(int elem_bytes, bool prefetch, bool last, int bf) {
+  return elem_bytes == 4 && !prefetch && !last && bf != 3 ? 3 : 2;
+}
+// bytes of LDS the weight fragments of a deep block take: F1 (not in the first block), F2
+constexpr int deep_wbytes(int DP, int elem_bytes, bool first, int bf) {
+  return (first ? 1 : 2) * DP * DP * (bf ? 2 * bf : elem_bytes);
+}
+
 constexpr bool DEEP_PF = true;  // register prefetch of the next tile in the blocks between first and last
 constexpr int DH_LD = 65;
 constexpr int DH_CH = 32;  // channels of the last block's LDS copy per group
+// LAST: channels of the LDS copy of dh per slice group (16 with three-term operands, whose
+// weight fragments take half as much LDS again)
+constexpr int deep_cpg(int DP, int bf) { return DP < (bf == 3 ? 16 : DH_CH) ? DP : (bf == 3 ? 16 : DH_CH); }
 
-// BF (float fields only): both channel-mixing products on the bf16 matrix cores with float
-// accumulation, the weight fragments held in LDS as bf16.
-template <typename T, int DP, bool FIRST, bool LAST, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST, LAST)))) void deep_kernel(MixArgs<T> A) {
+// BF (float fields only; the number of bf16 terms per operand, 0 = float matrix cores):
+// both channel-mixing products on the bf16 matrix cores with float accumulation, the weight
+// fragments held in LDS as bf16. BF = 1: operands rounded to bf16 (the BF16-mixed mode).
+// BF = 3: both operands split into three bf16 terms, x = x0 + x1 + x2 exactly, and the six
+// partial products with a + b <= 2 accumulated, which keeps the error bound of a float
+// product (the dropped ones are below 2^-24 |x v|).
+template <typename T, int DP, bool FIRST, bool LAST, int BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST, LAST, BF)))) void deep_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
   constexpr int MT = DP / 16, KS = DP / 4, KB = DP / 32;
   // the next tile's input is prefetched into registers unless that would not fit
   constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
+  constexpr bool BFM = BF != 0;     // bf16 matrix cores
+  constexpr int NS = BFM ? BF : 1;  // bf16 terms per operand
+  static_assert(BF == 0 || BF == 1 || BF == 3, "one or three bf16 terms");
   // LDS: F1 (not in the first block), F2, then the last block's per-wave copies of dh or
   // the other blocks' read-out weights (sized by the host in launch_deep)
-  T* F1 = reinterpret_cast<T*>(smem_raw);    // [KS][64][MT]: operand A of V, phase 1
-  T* F2 = F1 + (FIRST ? 0 : DP * DP);         // [MT][MT][64][4]: operand A of U, phase 2
+  constexpr int WB1 = deep_wbytes(DP, sizeof(T), true, BF);  // bytes of one weight matrix
+  T* F1 = reinterpret_cast<T*>(smem_raw);                                  // [KS][64][MT]: operand A of V, phase 1
+  T* F2 = reinterpret_cast<T*>(smem_raw + (FIRST ? 0 : WB1));              // [MT][MT][64][4]: operand A of U, phase 2
+  T* tail_s = reinterpret_cast<T*>(smem_raw + (FIRST ? 1 : 2) * WB1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
-  constexpr int CPG = DP < DH_CH ? DP : DH_CH;     // LAST: channels per slice group
-  T* dh = F2 + DP * DP + wave * CPG * DH_LD;       // LAST: this wave's [CPG][DH_LD] copy
-  T* om_s = F2 + DP * DP;                          // not LAST: omega / N [DP][64] of tile t
+  constexpr int CPG = deep_cpg(DP, BF);            // LAST: channels per slice group
+  T* dh = tail_s + wave * CPG * DH_LD;             // LAST: this wave's [CPG][DH_LD] copy
+  T* om_s = tail_s;                                // not LAST: omega / N [DP][64] of tile t
   T* ac_s = om_s + DP * 64;                        // not LAST: A^T [2][DP]
   const int N = A.N, Np = A.Np, l = A.l;
   const int nt = Np / 64;
@@ -792,17 +811,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   const int t = bx % nt;  // this workgroup's tile position (the host makes nbx a multiple of nt)
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
-  __bf16* F1h = reinterpret_cast<__bf16*>(F1);  // BF: [KB][MT][64][8]
-  __bf16* F2h = reinterpret_cast<__bf16*>(F2);  // BF: [MT][KB][64][8]
-  if constexpr (BF)
+  __bf16* F1h = reinterpret_cast<__bf16*>(F1);  // BF: [NS][KB][MT][64][8]
+  __bf16* F2h = reinterpret_cast<__bf16*>(F2);  // BF: [NS][MT][KB][64][8]
+  if constexpr (BFM)
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
     const int e = idx & 7, ln = (idx >> 3) & 63, hi = idx >> 9;
+    __bf16 b[3];
     if (!FIRST) {
       const int mt = hi % MT, sk = hi / MT;
-      F1h[idx] = (__bf16)Vt[(32 * sk + 8 * (ln >> 4) + e) * DP + 16 * mt + (ln & 15)];
+      const float v = Vt[(32 * sk + 8 * (ln >> 4) + e) * DP + 16 * mt + (ln & 15)];
+      if constexpr (NS == 3) split3(v, b[0], b[1], b[2]);
+      else b[0] = (__bf16)v;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) F1h[q * DP * DP + idx] = b[q];
     }
     const int sk = hi % KB, mo = hi / KB;
-    F2h[idx] = (__bf16)Ut[(16 * (2 * sk + (e >> 2)) + M::row(ln, e & 3)) * DP + 16 * mo + (ln & 15)];
+    const float v = Ut[(16 * (2 * sk + (e >> 2)) + M::row(ln, e & 3)) * DP + 16 * mo + (ln & 15)];
+    if constexpr (NS == 3) split3(v, b[0], b[1], b[2]);
+    else b[0] = (__bf16)v;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) F2h[q * DP * DP + idx] = b[q];
   }
   else
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
@@ -835,12 +863,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // scalar registers), so that no per-lane 64-bit offsets stay live across the tile loop.
   const int lrow = M::lane_row(lane);
   // input row of slot ks on this lane: kq_row + urow(ks) (bf16 steps take 8 rows per lane group)
-  const int kq_row = BF ? 8 * kq : kq;
-  auto urow = [](int ks) { return BF ? 32 * (ks >> 3) + (ks & 7) : 4 * ks; };
+  const int kq_row = BFM ? 8 * kq : kq;
+  auto urow = [](int ks) { return BFM ? 32 * (ks >> 3) + (ks & 7) : 4 * ks; };
   V4<T> xb[PF ? KS : 1];
   // with the input also the tile's background gate chi0 is fetched one tile ahead (float
   // operands only: it does not fit the register budget of the other variants)
-  constexpr bool PFC = PF && !BF && sizeof(T) == 4;
+  constexpr bool PFC = PF && !BFM && sizeof(T) == 4;
   V4<T> cb[PFC ? MT * 4 : 1];
   // without that prefetch (the last block, float) the whole input tile is requested at once
   // when the tile starts, so its latency is met once rather than at every step
@@ -893,7 +921,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           for (int n = 0; n < 4; ++n) acc[mt][n][r] = c0 * vz.v[n] + c1 * vw.v[n];
           if (r == 3) __builtin_amdgcn_sched_barrier(0);
         }
-    } else if constexpr (BF) {
+    } else if constexpr (BFM) {
       if constexpr (XL) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
@@ -904,7 +932,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         for (int n = 0; n < 4; ++n) acc[mt][n] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int sk = 0; sk < KB; ++sk) {
-        bf8 bb[4];
+        bf8 bb[NS][4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int ks = 8 * sk + e;
@@ -913,13 +941,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           else if constexpr (XL) v = xl[ks];
           else v = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) bb[n][e] = (__bf16)v.v[n];
+          for (int n = 0; n < 4; ++n) {
+            if constexpr (NS == 3) {
+              __bf16 b0, b1, b2;
+              split3(v.v[n], b0, b1, b2);
+              bb[0][n][e] = b0;
+              bb[1][n][e] = b1;
+              bb[2][n][e] = b2;
+            } else {
+              bb[0][n][e] = (__bf16)v.v[n];
+            }
+          }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const bf8 af = reinterpret_cast<const bf8*>(F1h)[(sk * MT + mt) * 64 + lane];
+          bf8 af[NS];
 #pragma unroll
-          for (int n = 0; n < 4; ++n) acc[mt][n] = mma_bf16(af, bb[n], acc[mt][n]);
+          for (int q = 0; q < NS; ++q) af[q] = reinterpret_cast<const bf8*>(F1h + q * DP * DP)[(sk * MT + mt) * 64 + lane];
+          // partial products a + b <= NS - 1, smallest first
+#pragma unroll
+          for (int sum = NS - 1; sum >= 0; --sum)
+#pragma unroll
+            for (int a = 0; a <= sum; ++a)
+#pragma unroll
+              for (int n = 0; n < 4; ++n) acc[mt][n] = mma_bf16(af[a], bb[sum - a][n], acc[mt][n]);
         }
       }
     } else {
@@ -1001,14 +1046,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     if (PF && g + gstride < g_hi) prefetch(g + gstride);
     // BF: x as bf16 operands of phase 2, in accumulator channel order (step sk: channels
     // 16 (2 sk + e / 4) + row(lane, e mod 4))
-    bf8 xh[BF ? KB : 1][4];
-    if constexpr (BF) {
+    bf8 xh[BFM ? NS : 1][BFM ? KB : 1][4];
+    if constexpr (BFM) {
 #pragma unroll
       for (int sk = 0; sk < KB; ++sk)
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) xh[sk][n][e] = (__bf16)acc[2 * sk + (e >> 2)][n][e & 3];
+          for (int e = 0; e < 8; ++e) {
+            const float v = acc[2 * sk + (e >> 2)][n][e & 3];
+            if constexpr (NS == 3) {
+              __bf16 b0, b1, b2;
+              split3(v, b0, b1, b2);
+              xh[0][sk][n][e] = b0;
+              xh[1][sk][n][e] = b1;
+              xh[2][sk][n][e] = b2;
+            } else {
+              xh[0][sk][n][e] = (__bf16)v;
+            }
+          }
     }
     // ---- phase 2 per 16-channel output tile: du = U x, stored, and read out
     double part0 = 0.0, part1 = 0.0;
@@ -1048,12 +1104,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         acc_t a2[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) a2[n] = acc_t{0, 0, 0, 0};
-        if constexpr (BF) {
+        if constexpr (BFM) {
 #pragma unroll
           for (int sk = 0; sk < KB; ++sk) {
-            const bf8 af = reinterpret_cast<const bf8*>(F2h)[(mo * KB + sk) * 64 + lane];
+            bf8 af[NS];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) a2[n] = mma_bf16(af, xh[sk][n], a2[n]);
+            for (int q = 0; q < NS; ++q) af[q] = reinterpret_cast<const bf8*>(F2h + q * DP * DP)[(mo * KB + sk) * 64 + lane];
+#pragma unroll
+            for (int sum = NS - 1; sum >= 0; --sum)
+#pragma unroll
+              for (int a = 0; a <= sum; ++a)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) a2[n] = mma_bf16(af[a], xh[sum - a][sk][n], a2[n]);
           }
         } else {
 #pragma unroll

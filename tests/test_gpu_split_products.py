@@ -1,6 +1,7 @@
-"""The Green's-function (Toeplitz) products of a float32 model in its two arithmetic modes:
-three-term bf16 splits on the bf16 matrix cores (the default) and plain float32 matrix cores.
-Both are compared with the FP64 oracle on the same inputs. The split mode keeps float32
+"""The float matrix-core products of a float32 model (Green's-function Toeplitz products and
+the ABACUS deep blocks' channel mixing) in their two arithmetic modes: three-term bf16 splits
+on the bf16 matrix cores (the default) and plain float32 matrix cores. Both are compared with
+the FP64 oracle on the same inputs. The split mode keeps float32
 accuracy: its error bound per product is that of a float32 product (the dropped partial
 products are below 2^-24 of each term), so its measured errors must be of the same size as
 the plain mode's (within a factor 8 plus 1e-7 absolute, for rounding-order scatter) and
@@ -53,7 +54,7 @@ def test_split_products_keep_float32_accuracy(L, shape, ham, B):
     m.set_params(th)
     err = {}
     for mode in ("fp32", "split3"):
-        m.set_toeplitz_mode(mode)
+        m.set_product_mode(mode)
         for path in ("abacus", "full"):
             lp, lr, el = (t.cpu() for t in m.eloc(ham, spd, M_max, path=path))
             err[mode, path] = (eps(lr, ref["logratio"]), eps(lp, ref["logpsi"]), eps(el, ref["eloc"]))
@@ -66,9 +67,9 @@ def test_split_products_keep_float32_accuracy(L, shape, ham, B):
     m.close()
 
 
-def test_toeplitz_mode_argument(L):
+def test_product_mode_argument(L):
     m = L.Model(di.ModelShape(32, 2, 16, 8), "fp32")
     with pytest.raises(L.DysonNetError) as ei:
-        L._check(L.lib().dn_set_toeplitz_mode(m.handle, 7))
+        L._check(L.lib().dn_set_product_mode(m.handle, 7))
     assert ei.value.status == L.DN_EINVAL
     m.close()

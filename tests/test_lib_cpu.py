@@ -107,4 +107,4 @@ def test_ragged_and_tuning_entry_points_reject_bad_arguments_on_host():
     h = L.make_ham(di.HamSpec("lrtfim", "open"))
     assert lib.dn_autotune(None, ctypes.byref(h), 16, None, None, None) == L.DN_EINVAL
     assert lib.dn_set_launch_shapes(None, 0, 0) == L.DN_EINVAL
-    assert lib.dn_set_toeplitz_mode(None, 0) == L.DN_EINVAL
+    assert lib.dn_set_product_mode(None, 0) == L.DN_EINVAL
