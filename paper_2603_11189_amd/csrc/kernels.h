@@ -869,7 +869,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // with the input also the tile's background gate chi0 is fetched one tile ahead (float
   // operands only: it does not fit the register budget of the other variants)
   constexpr bool PFC = PF && !BFM && sizeof(T) == 4;
-  V4<T> cb[PFC ? MT * 4 : 1];
+  // three-term variants after the first block: the gate is requested while phase 1 runs,
+  // half of it when the tile starts and half once the first half of the input is consumed
+  constexpr bool EC = BF == 3 && !FIRST && sizeof(T) == 4;
+  V4<T> cb[PFC || EC ? MT * 4 : 1];
   // without that prefetch (the last block, float) the whole input tile is requested at once
   // when the tile starts, so its latency is met once rather than at every step
   constexpr bool XL = !PF && !FIRST && sizeof(T) == 4;
@@ -926,6 +929,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
       }
+      auto fetch_chi = [&](int m0, int m1) {
+#pragma unroll
+        for (int mt = m0; mt < m1; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cb[mt * 4 + r] = ld4(A.chi + bo + lo_off + (16 * mt + M::r_row(r)) * Np);
+      };
+      if constexpr (EC) fetch_chi(0, MT / 2);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -952,6 +962,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
               bb[0][n][e] = (__bf16)v.v[n];
             }
           }
+        }
+        if constexpr (EC) {
+          if (sk == (KB == 1 ? 0 : KB / 2 - 1)) fetch_chi(MT / 2, MT);
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -1023,7 +1036,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         const int ch = 16 * mt + M::row(lane, r);
         const int uo = (16 * mt + M::r_row(r)) * Np;  // lane-independent part of the offset
         V4<T> c;
-        if constexpr (PFC) c = cb[mt * 4 + r];
+        if constexpr (PFC || EC) c = cb[mt * 4 + r];
         else c = ld4(A.chi + bo + lo_off + uo);
         T x[4];
 #pragma unroll
