@@ -869,9 +869,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // with the input also the tile's background gate chi0 is fetched one tile ahead (float
   // operands only: it does not fit the register budget of the other variants)
   constexpr bool PFC = PF && !BFM && sizeof(T) == 4;
-  // three-term variants after the first block: the gate is requested while phase 1 runs,
-  // half of it when the tile starts and half once the first half of the input is consumed
-  constexpr bool EC = BF == 3 && !FIRST && sizeof(T) == 4;
+  // three-term variants: the gate is requested while phase 1 runs (after the first block
+  // half of it when the tile starts and half once the first half of the input is consumed;
+  // in the first block all of it, ahead of the table reads)
+  constexpr bool EC = BF == 3 && sizeof(T) == 4;
   V4<T> cb[PFC || EC ? MT * 4 : 1];
   // without that prefetch (the last block, float) the whole input tile is requested at once
   // when the tile starts, so its latency is met once rather than at every step
@@ -912,6 +913,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
       const int z1 = pair ? sg.w : sg.z, shz = (TO - sg.z) & 3, shw = (TO - z1) & 3;
       const T* pz = A.tb.Pq + ((long)shz * DP + lrow) * TS + TO + s0 - sg.z - shz;
       const T* pw = A.tb.Pq + ((long)shw * DP + lrow) * TS + TO + s0 - z1 - shw;
+      if constexpr (EC) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cb[mt * 4 + r] = ld4(A.chi + bo + lo_off + (16 * mt + M::r_row(r)) * Np);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
