@@ -464,7 +464,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
             for (int b = 0; b < 3; ++b)
               tb[b][n] = *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
-          // the six products, smallest first; each step runs over all 4 NT accumulators
+          // the six products, smallest first; each step runs over all 4 NT accumulators.
+          // The taps are the first operand and the field the second, so an accumulator
+          // holds four consecutive output sites of one configuration per lane (one
+          // 16-byte store)
 #pragma unroll
           for (int term = 0; term < 6; ++term) {
             const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
@@ -472,26 +475,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
+              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(tb[tg][n], xa[ta][mt], acc[mt][n]);
           }
         }
       }
     }
     if (wsite0 < Np) {
+      // accumulator (mt, n): configuration 16 mt + (lane mod 16), sites 16 n + 4 (lane / 16)
+      // + r (the wave's sites all lie below Np)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a) {
+        const int cfg = cfg0 + 16 * a + (lane & 15);
+        if (cfg >= C) continue;
 #pragma unroll
-        for (int n = 0; n < NT; ++n)
+        for (int n = 0; n < NT; ++n) {
+          const int i0 = wsite0 + 16 * n + 4 * (lane >> 4);
+          float y[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int cfg = cfg0 + 16 * a + 4 * (lane >> 4) + r;
-            const int i = wsite0 + 16 * n + (lane & 15);
-            if (cfg < C && i < Np) {
-              float y = (i < A.N) ? acc[a][n][r] : 0.f;
-              if (A.add) y += A.add[(long)(cfg & 1) * cstride + (long)c * Np + i];
-              A.Y[(long)cfg * cstride + (long)c * Np + i] = y;
-            }
+          for (int r = 0; r < 4; ++r) y[r] = (i0 + r < A.N) ? acc[a][n][r] : 0.f;
+          if (A.add) {
+            const float4 ad = *reinterpret_cast<const float4*>(A.add + (long)(cfg & 1) * cstride + (long)c * Np + i0);
+            y[0] += ad.x; y[1] += ad.y; y[2] += ad.z; y[3] += ad.w;
           }
+          *reinterpret_cast<float4*>(A.Y + (long)cfg * cstride + (long)c * Np + i0) = make_float4(y[0], y[1], y[2], y[3]);
+        }
+      }
     }
   }
 }
