@@ -63,7 +63,7 @@ def kernel_class(name: str) -> str:
     if "mix_kernel" in name:
         mode = name.split("mix_kernel<")[1].split(",")[2].strip()
         return {"0": "mix_fwd", "1": "mix_tau", "2": "mix_deep"}[mode]
-    for key, cls in (("conv_kernel", "conv"), ("phi_kernel", "phi"), ("slice_kernel", "slice"),
+    for key, cls in (("conv_kernel", "conv"), ("conv_split_kernel", "conv"), ("phi_kernel", "phi"), ("slice_kernel", "slice"),
                      ("deep_kernel", "mix_deep"), ("last_finish_kernel", "tail"),
                      ("tail_kernel", "tail"), ("s4_taps_kernel", "s4gen"), ("prep_kernel", "prep"),
                      ("connected_kernel", "gen"), ("eloc_kernel", "eloc")):
