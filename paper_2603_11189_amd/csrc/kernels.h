@@ -1282,12 +1282,21 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   T* Y = reinterpret_cast<T*>(smem_raw);  // [DP][16]: Y[c][t]
   T* X2 = Y + DP * SLICE_WIN;             // [DP][16]
   const T* pp = A.slice_part + (long)g * nt * SLICE_WIN * DP;
-  for (int c = lane; c < DP; c += 64)
-    for (int t = 0; t < SLICE_WIN; ++t) {
-      T s = 0;
-      for (int tile = 0; tile < nt; ++tile) s += pp[((long)tile * SLICE_WIN + t) * DP + c];
-      Y[c * SLICE_WIN + t] = (t < WL) ? s : T(0);
+  for (int c = lane; c < DP; c += 64) {
+    // a tile's sixteen partials are requested together
+    T s[SLICE_WIN];
+#pragma unroll
+    for (int t = 0; t < SLICE_WIN; ++t) s[t] = 0;
+    for (int tile = 0; tile < nt; ++tile) {
+      T v[SLICE_WIN];
+#pragma unroll
+      for (int t = 0; t < SLICE_WIN; ++t) v[t] = pp[((long)tile * SLICE_WIN + t) * DP + c];
+#pragma unroll
+      for (int t = 0; t < SLICE_WIN; ++t) s[t] += v[t];
     }
+#pragma unroll
+    for (int t = 0; t < SLICE_WIN; ++t) Y[c * SLICE_WIN + t] = (t < WL) ? s[t] : T(0);
+  }
   wave_sync();
   const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(A.L - 1) * DP * DP;
