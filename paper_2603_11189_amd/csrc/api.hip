@@ -651,7 +651,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.act = d.act; a.F = F; a.f0 = f0; a.b0 = bf0; a.Bc = Bf; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
       a.dyn = dyn;
-      const size_t lds = 2 * (size_t)Wmax * DP * sizeof(T);
+      const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
       double fl = 0.0;
       for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
       PScope ps(m, DN_K_SLICE, st, fl * F, (double)F * L * Wmax * d.d * sizeof(T));

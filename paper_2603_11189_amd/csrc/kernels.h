@@ -1395,12 +1395,14 @@ template <typename T> struct SliceArgs {
 template <typename T, int DP>
 __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* phs = reinterpret_cast<T*>(smem_raw);  // phi' on the current slice [Wmax][DP]
-  T* as = phs + A.Wmax * DP;                // a' on the previous slice   [Wmax][DP]
+  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
+  // phi' on the current slice [Wmax][DP]; a on the previous slice with a halo of 2 w_c
+  // background sites on either side [2 w_c + Wmax + 2 w_c][DP] (as[t] = row t + 2 w_c)
+  T* phs = reinterpret_cast<T*>(smem_raw);
+  T* as = phs + A.Wmax * DP + 2 * wc * DP;
   const int f = blockIdx.x;
   const int c = threadIdx.x;  // channel; lanes c >= DP only join the barriers
   const bool on = c < DP;
-  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
   if (f >= A.dyn.count(A.F)) return;
   const int f0 = A.dyn.first(A.f0);
   const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
@@ -1443,6 +1445,14 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
 #pragma unroll
       for (int k = 0; k < DP; ++k) wcol[k] = Wt[k * DP + c];
     }
+    // the halo: background a at the 2 w_c sites on either side of S_{l-1}, requested before
+    // the products and stored with them
+    const T* a0 = A.a0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
+    for (int h = 0; h < 4 * wc; ++h) {
+      const int tp = h < 2 * wc ? h - 2 * wc : WP + h - 2 * wc;
+      const int jj = loP + tp;
+      as[tp * DP + c] = inside(jj) ? a0[wrap(jj)] : T(0);
+    }
     for (int t = 0; t < WP; ++t) {
       const int site = wrap(loP + t);
       T v = 0;
@@ -1463,35 +1473,33 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
     __syncthreads();
     // phi' and chi' on S_l
     const T* Kc = A.tb.Kc + (long)lp * (2 * wc + 1) * DP;
-    const T* a0 = A.a0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
     for (int t = 0; t < Wl; ++t) {
       const int ii = lo + t;
       T s = A.tb.kv[lp * DP + c];
-      for (int r = -wc; r <= wc; ++r) {
-        const int tp = t + r - wc;  // position in S_{l-1}
-        T av;
-        if (tp >= 0 && tp < WP) av = as[tp * DP + c];
-        else {
-          const int jj = ii + r;
-          av = inside(jj) ? a0[wrap(jj)] : T(0);
-        }
-        s += Kc[(r + wc) * DP + c] * av;
-      }
+      for (int r = -wc; r <= wc; ++r) s += Kc[(r + wc) * DP + c] * as[(t + r - wc) * DP + c];
       phs[t * DP + c] = inside(ii) ? act_fn<T>(A.act, s) : T(0);  // phs no longer read above
     }
     __syncthreads();
     const T* Adt = A.tb.ADt + (long)lp * DP * DP;
     const T* chi0 = A.chi0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
     T* out = A.dchi + ((long)f * L + lp) * A.Wmax * DP;
+    // the background gate on S_l, requested together (positions past Wl read the slice's
+    // first site and are not used)
+    T c0v[SLICE_WIN];
+#pragma unroll
+    for (int t = 0; t < SLICE_WIN; ++t) c0v[t] = chi0[wrap(t < Wl && inside(lo + t) ? lo + t : clo)];
 #pragma unroll
     for (int k = 0; k < DP; ++k) wcol[k] = Adt[k * DP + c];
-    for (int t = 0; t < Wl; ++t) {
-      const int ii = lo + t;
-      T acc = A.tb.bv[lp * DP + c];
 #pragma unroll
-      for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
-      T dc = inside(ii) ? act_fn<T>(A.act, acc) - chi0[wrap(ii)] : T(0);
-      out[t * DP + c] = dc;
+    for (int t = 0; t < SLICE_WIN; ++t) {
+      if (t < Wl) {
+        const int ii = lo + t;
+        T acc = A.tb.bv[lp * DP + c];
+#pragma unroll
+        for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
+        T dc = inside(ii) ? act_fn<T>(A.act, acc) - c0v[t] : T(0);
+        out[t * DP + c] = dc;
+      }
     }
     __syncthreads();
   }
