@@ -147,7 +147,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the per-sample log-derivative leg")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuner)")
+    ap.add_argument("--no-tune", action="store_true", help="no autotuner in the sweep and the ragged batch")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch shapes of the measured model first (default: the library's "
+                         "default shapes, so that repeated runs and their profiles use the same launches)")
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
     ap.add_argument("--products", default="split3", choices=["split3", "fp32"],
                     help="float matrix-core products: three-term bf16 splits (default) or float32 matrix cores")
@@ -187,6 +190,7 @@ def main():
         return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
+    Np = (shape.N + 63) // 64 * 64  # the library's padded chain length
     prec = args.prec or w.prec
     B = w.B
     M_max = shape.N if ham.kind == "lrtfim" else 2 * shape.N
@@ -218,7 +222,7 @@ def main():
         nt, mib = (int(x) for x in args.shapes.split(","))
         model.set_launch_shapes(nt, mib << 20)
         tuned = {"conv_tiles_per_wave": nt, "flip_chunk_MiB": mib, "set_by": "--shapes"}
-    elif not args.no_tune:
+    elif args.tune and not args.no_tune:
         t0 = time.perf_counter()
         nt, bud = model.autotune(ham)
         tuned = {"conv_tiles_per_wave": nt, "flip_chunk_MiB": bud >> 20,
@@ -283,7 +287,8 @@ def main():
                    "params": f"N(0,0.1^2) seed {w.param_seed}" if args.scale == "baseline" else "stress draw",
                    "path": main_path},
         "set_params_ms": set_params_ms,
-        "launch_shapes": tuned or "defaults",
+        "launch_shapes": tuned or {"conv_tiles_per_wave": 4 if Np >= 256 else Np // 64, "flip_chunk_MiB": 3072,
+                                   "set_by": "library defaults"},
         "products": ({"split3": "Toeplitz and deep channel-mixing products as three-term bf16 splits "
                                 "(six partial products, f32 accumulate: f32 error bound)",
                       "fp32": "f32 matrix cores"}[args.products] if prec != "fp64" else "f64 matrix cores"),
