@@ -509,7 +509,10 @@ dn_status plan_launch(dn_model* m, const int32_t* n_conn, const int32_t* sites, 
   STCHK(ws_get(m, "plan_cb", (size_t)upper * 4, &pb));
   STCHK(ws_get(m, "plan_cm", (size_t)upper * 4, &pm));
   *offs = (int32_t*)po; *cb = (int32_t*)pb; *cm = (int32_t*)pm;
-  plan_kernel<<<1, 1024, 0, st>>>(n_conn, sites, B, m->desc.N, M_max, with_base, *offs, *cb, *cm);
+  plan_kernel<<<1, 1024, 0, st>>>(n_conn, B, M_max, with_base, *offs);
+  const long slots = (long)B * (M_max + with_base);
+  plan_fill_kernel<<<(int)std::min<long>(4096, (slots + 255) / 256), 256, 0, st>>>(n_conn, sites, B, m->desc.N, M_max,
+                                                                                  with_base, *offs, *cb, *cm);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }

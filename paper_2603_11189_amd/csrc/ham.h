@@ -94,15 +94,14 @@ __global__ __launch_bounds__(64) void eloc_kernel(const double* __restrict__ hdi
 }
 
 // Work list: for each sample b, (with_base ? 1 : 0) + n_conn[b] entries (b, m), m = -1 for the
-// unflipped sample. One block; offs[b] = first entry of sample b, offs[B] = total. The inputs
-// are validated here (the host reads offs[B+1] before any other launch): offs[B+1] = 1 if some
-// n_conn is outside [0, M_max], 2 if a listed site is outside the chain (second site may be -1,
-// and must differ from the first).
-__global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ n_conn,
-                                                    const int32_t* __restrict__ sites, int B, int N,
-                                                    int M_max, int with_base, int32_t* __restrict__ offs,
-                                                    int32_t* __restrict__ cb,
-                                                    int32_t* __restrict__ cm) {
+// unflipped sample; offs[b] = first entry of sample b, offs[B] = total. The inputs are
+// validated on the way (the host reads offs[B+1] before any other launch): offs[B+1] gets bit
+// 1 if some n_conn is outside [0, M_max], bit 2 if a listed site is outside the chain (the
+// second site may be -1, and must differ from the first). plan_kernel (one block) counts and
+// scans; plan_fill_kernel (one thread per (sample, slot)) writes the entries and checks the
+// sites.
+__global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ n_conn, int B, int M_max,
+                                                    int with_base, int32_t* __restrict__ offs) {
   __shared__ int part[1024];
   __shared__ int bad;
   const int t = threadIdx.x;
@@ -114,10 +113,6 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ 
   for (int b = b0; b < b1; ++b) {
     int n = n_conn[b];
     if (n < 0 || n > M_max) { atomicOr(&bad, 1); n = n < 0 ? 0 : M_max; }
-    for (int m = 0; m < n; ++m) {
-      const int j0 = sites[((long)b * M_max + m) * 2], j1 = sites[((long)b * M_max + m) * 2 + 1];
-      if (j0 < 0 || j0 >= N || j1 < -1 || j1 >= N || j1 == j0) atomicOr(&bad, 2);
-    }
     cnt += with_base + n;
   }
   part[t] = cnt;
@@ -133,10 +128,28 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ 
     int n = n_conn[b];
     n = n < 0 ? 0 : (n > M_max ? M_max : n);
     offs[b] = pos;
-    if (with_base) { cb[pos] = b; cm[pos] = -1; ++pos; }
-    for (int m = 0; m < n; ++m) { cb[pos] = b; cm[pos] = m; ++pos; }
+    pos += with_base + n;
   }
   if (t == 1023) { offs[B] = part[1023]; offs[B + 1] = bad; }
+}
+
+__global__ void plan_fill_kernel(const int32_t* __restrict__ n_conn, const int32_t* __restrict__ sites, int B,
+                                 int N, int M_max, int with_base, int32_t* __restrict__ offs,
+                                 int32_t* __restrict__ cb, int32_t* __restrict__ cm) {
+  const int S = M_max + with_base;  // slots per sample
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)B * S; i += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / S), slot = (int)(i % S);
+    int n = n_conn[b];
+    n = n < 0 ? 0 : (n > M_max ? M_max : n);
+    if (slot >= with_base + n) continue;
+    const int pos = offs[b] + slot, m = slot - with_base;
+    cb[pos] = b;
+    cm[pos] = m;
+    if (m >= 0) {
+      const int j0 = sites[((long)b * M_max + m) * 2], j1 = sites[((long)b * M_max + m) * 2 + 1];
+      if (j0 < 0 || j0 >= N || j1 < -1 || j1 >= N || j1 == j0) atomicOr(&offs[B + 1], 2);
+    }
+  }
 }
 
 // Probe configurations for launch tuning: spin i = +-1 from the low bit of a 32-bit integer
