@@ -415,12 +415,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       pre[u] = cfg < C ? *reinterpret_cast<const float2*>(xrow + (long)cfg * cstride + k0) : make_float2(0.f, 0.f);
     }
   };
-  // B operand of output tile n: R[p + e] with p = p0 + k0 + 32 ks; k0 and 32 ks are
-  // multiples of 8, so the shifted copy (p0 mod 8) and a per-lane base are fixed
+  // matrix-core column j of output tile n is site wsite0 + NT j + n, so that a lane's NT
+  // tiles hold NT consecutive sites and 16 lanes a contiguous row segment of one
+  // configuration (full-line stores). B operand of tile n: R[p + e] with p = p0 + k0 + 32 ks;
+  // k0 and 32 ks are multiples of 8, so the shifted copy (p0 mod 8) and a per-lane base are
+  // fixed
   int tbase[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int p0 = Np - 1 - (wsite0 + 16 * n + (lane & 15)) + 8 * (lane >> 4);
+    const int p0 = Np - 1 - (wsite0 + NT * (lane & 15) + n) + 8 * (lane >> 4);
     const int sh = p0 & 7;
     tbase[n] = sh * TL + p0 - sh;
   }
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
               xa[b][mt] = *reinterpret_cast<const bf8*>(xs + (b * CONV_MC + 16 * mt + (lane & 15)) * CS_LD + 32 * ks + 8 * (lane >> 4));
-          // B: g(i - k) for output site i = wsite0 + 16 n + (lane mod 16) and the lane's 8
+          // B: g(i - k) for output site i = wsite0 + NT (lane mod 16) + n and the lane's 8
           // input sites k = k0 + 32 ks + 8 (lane / 16) + e, i.e. R[p + e]
           bf8 tb[3][NT];
 #pragma unroll
@@ -464,10 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
             for (int b = 0; b < 3; ++b)
               tb[b][n] = *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
-          // the six products, smallest first; each step runs over all 4 NT accumulators.
-          // The taps are the first operand and the field the second, so an accumulator
-          // holds four consecutive output sites of one configuration per lane (one
-          // 16-byte store)
+          // the six products, smallest first; each step runs over all 4 NT accumulators
 #pragma unroll
           for (int term = 0; term < 6; ++term) {
             const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
@@ -475,31 +475,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(tb[tg][n], xa[ta][mt], acc[mt][n]);
+              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
           }
         }
       }
     }
     if (wsite0 < Np) {
-      // accumulator (mt, n): configuration 16 mt + (lane mod 16), sites 16 n + 4 (lane / 16)
-      // + r (the wave's sites all lie below Np)
+      // accumulator (mt, n) entry r: configuration 16 mt + 4 (lane / 16) + r, site
+      // wsite0 + NT (lane mod 16) + n (the wave's sites all lie below Np)
+      const int i0 = wsite0 + NT * (lane & 15);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int cfg = cfg0 + 16 * a + (lane & 15);
-        if (cfg >= C) continue;
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          const int i0 = wsite0 + 16 * n + 4 * (lane >> 4);
-          float y[4];
+        for (int r = 0; r < 4; ++r) {
+          const int cfg = cfg0 + 16 * a + 4 * (lane >> 4) + r;
+          if (cfg >= C) continue;
+          float y[NT];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) y[r] = (i0 + r < A.N) ? acc[a][n][r] : 0.f;
+          for (int n = 0; n < NT; ++n) y[n] = (i0 + n < A.N) ? acc[a][n][r] : 0.f;
+          const long o = (long)cfg * cstride + (long)c * Np + i0;
           if (A.add) {
-            const float4 ad = *reinterpret_cast<const float4*>(A.add + (long)(cfg & 1) * cstride + (long)c * Np + i0);
-            y[0] += ad.x; y[1] += ad.y; y[2] += ad.z; y[3] += ad.w;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) y[n] += A.add[(long)(cfg & 1) * cstride + (long)c * Np + i0 + n];
           }
-          *reinterpret_cast<float4*>(A.Y + (long)cfg * cstride + (long)c * Np + i0) = make_float4(y[0], y[1], y[2], y[3]);
+          if constexpr (NT == 4) {
+            *reinterpret_cast<float4*>(A.Y + o) = make_float4(y[0], y[1], y[2], y[3]);
+          } else {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) A.Y[o + n] = y[n];
+          }
         }
-      }
     }
   }
 }
