@@ -402,17 +402,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     }
   }
   const long cstride = (long)A.DP * Np;
-  // staging: thread t moves sites 2 (t mod 32) + {0, 1} of configuration rows t / 32 + 8 u,
+  // staging: thread t moves sites 4 (t mod 16) .. + 3 of configuration rows t / 16 + 16 u,
   // one chunk ahead through registers; the workgroup runs over configuration blocks
   // blockIdx.x, blockIdx.x + gridDim.x, ... (the split taps are built once)
-  const int srow = threadIdx.x >> 5, scol = 2 * (threadIdx.x & 31);
+  const int srow = threadIdx.x >> 4, scol = 4 * (threadIdx.x & 15);
   const float* xrow = A.X + (long)c * Np + scol;
-  float2 pre[8];
+  float4 pre[4];
   auto fetch = [&](int blk, int k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int cfg = blk * CONV_MC + srow + 8 * u;
-      pre[u] = cfg < C ? *reinterpret_cast<const float2*>(xrow + (long)cfg * cstride + k0) : make_float2(0.f, 0.f);
+    for (int u = 0; u < 4; ++u) {
+      const int cfg = blk * CONV_MC + srow + 16 * u;
+      pre[u] = cfg < C ? *reinterpret_cast<const float4*>(xrow + (long)cfg * cstride + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   // matrix-core column j of output tile n is site wsite0 + NT j + n, so that a lane's NT
@@ -438,13 +438,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     for (int k0 = 0; k0 < Np; k0 += CS_KC) {
       __syncthreads();  // the previous chunk is consumed (and the taps are in place)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        bf2 b0, b1, b2;
-        split3x2(f2v{pre[u].x, pre[u].y}, b0, b1, b2);
-        __bf16* d = xs + (srow + 8 * u) * CS_LD + scol;
-        *reinterpret_cast<bf2*>(d) = b0;
-        *reinterpret_cast<bf2*>(d + CONV_MC * CS_LD) = b1;
-        *reinterpret_cast<bf2*>(d + 2 * CONV_MC * CS_LD) = b2;
+      for (int u = 0; u < 4; ++u) {
+        bf2 a0, a1, a2, b0, b1, b2;
+        split3x2(f2v{pre[u].x, pre[u].y}, a0, a1, a2);
+        split3x2(f2v{pre[u].z, pre[u].w}, b0, b1, b2);
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        __bf16* d = xs + (srow + 16 * u) * CS_LD + scol;
+        *reinterpret_cast<bf4*>(d) = bf4{a0[0], a0[1], b0[0], b0[1]};
+        *reinterpret_cast<bf4*>(d + CONV_MC * CS_LD) = bf4{a1[0], a1[1], b1[0], b1[1]};
+        *reinterpret_cast<bf4*>(d + 2 * CONV_MC * CS_LD) = bf4{a2[0], a2[1], b2[0], b2[1]};
       }
       __syncthreads();
       if (k0 + CS_KC < Np) fetch(blk, k0 + CS_KC);
