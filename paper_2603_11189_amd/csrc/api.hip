@@ -384,7 +384,7 @@ dn_status launch_mix(dn_model* m, const MixArgs<T>& a, int C, hipStream_t st, bo
 
 // Persistent tiled launch of a deep block (see deep_kernel); the last one is followed by
 // last_finish_kernel, one wave per flip.
-template <typename T, int DP, bool FIRST, bool LAST, int BF>
+template <typename T, int DP, bool FIRST, bool LAST, int BF, int NU = SLICE_WIN>
 dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
   if (F <= 0) return DN_OK;
   // F1 (not in the first block) and F2, then the last block's per-wave copies of dh or the
@@ -393,11 +393,11 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
                      (LAST ? (size_t)DEEP_WAVES * deep_cpg(DP, BF) * DH_LD : (size_t)DP * 64 + 2 * DP) * sizeof(T);
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
-    allow_lds(deep_kernel<T, DP, FIRST, LAST, BF>, lds);
+    allow_lds(deep_kernel<T, DP, FIRST, LAST, BF, NU>, lds);
     int dev = 0, n = 0, c = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST, LAST, BF>, 256, lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, deep_kernel<T, DP, FIRST, LAST, BF, NU>, 256, lds));
     cus = std::max(c, 1);
     per_cu = std::max(n, 1);
   }
@@ -414,7 +414,7 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
     const double fl = 4.0 * F * Nr * dr * dr + (LAST ? 2.0 * F * WL * Nr * dr : 0.0);
     const double by = F * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
     PScope ps(m, DN_K_MIX_DEEP, st, fl, by);
-    deep_kernel<T, DP, FIRST, LAST, BF><<<(int)grid, 256, lds, st>>>(a);
+    deep_kernel<T, DP, FIRST, LAST, BF, NU><<<(int)grid, 256, lds, st>>>(a);
     HIPCHK(hipGetLastError());
   }
   if (LAST) {
@@ -426,10 +426,22 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   return DN_OK;
 }
 
+// The last block of a float model computes its partial slices only over the widest slice
+// S_L any flip can have (2 + 2 L w_c + 1 sites), rounded up to 8, 12 or 16.
+template <typename T, int DP, bool FIRST, int BF>
+dn_status launch_deep_last(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc) {
+  if constexpr (sizeof(T) == 4) {
+    const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
+    if (WL <= 8) return launch_deep<T, DP, FIRST, true, BF, 8>(m, a, F, st, Bc);
+    if (WL <= 12) return launch_deep<T, DP, FIRST, true, BF, 12>(m, a, F, st, Bc);
+  }
+  return launch_deep<T, DP, FIRST, true, BF>(m, a, F, st, Bc);
+}
+
 template <typename T, int DP, int BF>
 dn_status launch_deep_mode(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
-  if (first && last) return launch_deep<T, DP, true, true, BF>(m, a, F, st, Bc);
-  if (last) return launch_deep<T, DP, false, true, BF>(m, a, F, st, Bc);
+  if (first && last) return launch_deep_last<T, DP, true, BF>(m, a, F, st, Bc);
+  if (last) return launch_deep_last<T, DP, false, BF>(m, a, F, st, Bc);
   if (first) return launch_deep<T, DP, true, false, BF>(m, a, F, st, Bc);
   return launch_deep<T, DP, false, false, BF>(m, a, F, st, Bc);
 }

@@ -77,10 +77,60 @@ __device__ inline double lcd_d(double a, double d) {
   return logcosh_d(a + d) - logcosh_d(a);
 }
 
-// Wave-level sum (all 64 lanes get the total).
+// Cross-lane exchanges without the LDS crossbar, word by word (T of 4 or 8 bytes).
+// dpp_get<CTRL>: the value of the lane the data-parallel-primitive control CTRL names.
+constexpr int DPP_XOR1 = 0xB1;         // quad permutation [1, 0, 3, 2]: lane l ^ 1
+constexpr int DPP_XOR2 = 0x4E;         // quad permutation [2, 3, 0, 1]: lane l ^ 2
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane 7 - l within each group of 8
+constexpr int DPP_MIRROR = 0x140;       // lane 15 - l within each group of 16
+template <int CTRL, typename T> __device__ inline T dpp_get(T v) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_update_dpp(0, w[i], CTRL, 0xF, 0xF, false);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+// v(l) + v(l ^ H) for H = 16 or 32 with the gfx950 row swaps: swapping the odd 16-lane rows
+// of one copy of v with the even rows of another (H = 16), or the upper half of one with
+// the lower half of the other (H = 32), leaves every lane holding v(l) in one copy and
+// v(l ^ H) in the other.
+template <int H, typename T> __device__ inline T swap_sum(T v) {
+  static_assert(H == 16 || H == 32, "row swaps pair lanes 16 or 32 apart");
+  constexpr int NW = sizeof(T) / 4;
+  unsigned w[NW], a[NW], b[NW];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if constexpr (H == 16) {
+      const auto r = __builtin_amdgcn_permlane16_swap(w[i], w[i], false, false);
+      a[i] = r[0];
+      b[i] = r[1];
+    } else {
+      const auto r = __builtin_amdgcn_permlane32_swap(w[i], w[i], false, false);
+      a[i] = r[0];
+      b[i] = r[1];
+    }
+  }
+  T x, y;
+  __builtin_memcpy(&x, a, sizeof(T));
+  __builtin_memcpy(&y, b, sizeof(T));
+  return x + y;
+}
+
+// Wave-level sum (all 64 lanes get the total; call with the whole wave active). Pairs of
+// lanes 1, 2, 4, 8, 16, 32 apart are added in turn; for 4 and 8 the mirrored lane holds the
+// same partial sum as lane l ^ 4 or l ^ 8, since the earlier steps made it uniform over
+// each group of 4 or 8.
 template <typename T> __device__ inline T wave_sum(T v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
+  v += dpp_get<DPP_XOR1>(v);
+  v += dpp_get<DPP_XOR2>(v);
+  v += dpp_get<DPP_HALF_MIRROR>(v);
+  v += dpp_get<DPP_MIRROR>(v);
+  v = swap_sum<16>(v);
+  return swap_sum<32>(v);
 }
 
 }  // namespace dn

@@ -797,7 +797,9 @@ constexpr int deep_cpg(int DP, int bf) { return DP < (bf == 3 ? 16 : DH_CH) ? DP
 // BF = 3: both operands split into three bf16 terms, x = x0 + x1 + x2 exactly, and the six
 // partial products with a + b <= 2 accumulated, which keeps the error bound of a float
 // product (the dropped ones are below 2^-24 |x v|).
-template <typename T, int DP, bool FIRST, bool LAST, int BF>
+// NU (last block, float): slice positions the partial slices cover, at least the widest
+// slice S_L of the launch (the others keep SLICE_WIN).
+template <typename T, int DP, bool FIRST, bool LAST, int BF, int NU = SLICE_WIN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(sizeof(T), DEEP_PF && !FIRST && !LAST, LAST, BF)))) void deep_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
@@ -808,6 +810,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   constexpr bool BFM = BF != 0;     // bf16 matrix cores
   constexpr int NS = BFM ? BF : 1;  // bf16 terms per operand
   static_assert(BF == 0 || BF == 1 || BF == 3, "one or three bf16 terms");
+  static_assert(NU == SLICE_WIN || (LAST && sizeof(T) == 4 && NU >= 1 && NU < SLICE_WIN), "narrow partial slices: last block, float");
   // LDS: F1 (not in the first block), F2, then the last block's per-wave copies of dh or
   // the other blocks' read-out weights (sized by the host in launch_deep)
   constexpr int WB1 = deep_wbytes(DP, sizeof(T), true, BF);  // bytes of one weight matrix
@@ -1111,9 +1114,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     constexpr int GM = LAST ? CPG / 16 : 1;  // output tiles per group
     // LAST, float: lane (c, hp) of the slice below takes channel c over the tile sites
     // hp K .. hp K + K - 1 (K = CPG); the taps it needs, h(u - k) for those sites k and
-    // u < SLICE_WIN, are fetched into registers before the group's products
+    // u < NU, are fetched into registers before the group's products
     constexpr bool TPR = LAST && sizeof(T) == 4;
-    constexpr int NTP = TPR ? CPG + SLICE_WIN - 1 : 1;
+    constexpr int NTP = TPR ? CPG + NU - 1 : 1;
+    static_assert(!LAST || CPG == 16 || CPG == 32, "the tile's parts are lanes 16 or 32 apart");
 #pragma unroll 1
     for (int mg = 0; mg < MT; mg += GM) {
       T tp[NTP];  // tp[m] = tc[m - (K - 1) - hp K], tc the window of the slice below
@@ -1212,9 +1216,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
         constexpr int NPART = 64 / CPG, K = CPG;  // lanes (c, h): sites h K .. h K + K - 1
         const int c = lane % CPG, hp = lane / CPG, cg = 16 * mg + c;
         const int ib = 64 * t, cnt = min(64, N - ib), k0 = hp * K;
-        T ya[SLICE_WIN], rg[SLICE_WIN];
+        T ya[NU], rg[SLICE_WIN];
 #pragma unroll
-        for (int u = 0; u < SLICE_WIN; ++u) ya[u] = 0;
+        for (int u = 0; u < NU; ++u) ya[u] = 0;
         if constexpr (TPR) {
           // every site of the tile: those past the chain end hold zeros
           const T* xr = dh + c * DH_LD + k0;
@@ -1222,7 +1226,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           for (int kk = 0; kk < K; ++kk) {
             const T v = xr[kk];
 #pragma unroll
-            for (int u = 0; u < SLICE_WIN; ++u) ya[u] += tp[u - kk + K - 1] * v;
+            for (int u = 0; u < NU; ++u) ya[u] += tp[u - kk + K - 1] * v;
           }
         } else {
           // float64: a sliding register window over the taps
@@ -1243,14 +1247,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
             }
           }
         }
+        // the parts of the tile (lanes CPG apart) are added with row swaps
 #pragma unroll
-        for (int sh = CPG; sh < 64; sh <<= 1)
-#pragma unroll
-          for (int u = 0; u < SLICE_WIN; ++u) ya[u] += __shfl_xor(ya[u], sh, 64);
+        for (int u = 0; u < NU; ++u) {
+          if constexpr (CPG <= 16) ya[u] = swap_sum<16>(ya[u]);
+          ya[u] = swap_sum<32>(ya[u]);
+        }
         if (hp == 0) {
           T* pp = A.slice_part + ((long)g * nt + t) * SLICE_WIN * DP + cg;
 #pragma unroll
-          for (int u = 0; u < SLICE_WIN; ++u) pp[u * DP] = ya[u];
+          for (int u = 0; u < NU; ++u) pp[u * DP] = ya[u];
         }
         wave_sync();  // the copy in LDS is free for the next group
       }
@@ -1290,14 +1296,15 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   T* X2 = Y + DP * SLICE_WIN;             // [DP][16]
   const T* pp = A.slice_part + (long)g * nt * SLICE_WIN * DP;
   for (int c = lane; c < DP; c += 64) {
-    // a tile's sixteen partials are requested together
+    // a tile's partials are requested together; rows past the slice (which the last block
+    // may not have written) re-read its last row and are dropped below
     T s[SLICE_WIN];
 #pragma unroll
     for (int t = 0; t < SLICE_WIN; ++t) s[t] = 0;
     for (int tile = 0; tile < nt; ++tile) {
       T v[SLICE_WIN];
 #pragma unroll
-      for (int t = 0; t < SLICE_WIN; ++t) v[t] = pp[((long)tile * SLICE_WIN + t) * DP + c];
+      for (int t = 0; t < SLICE_WIN; ++t) v[t] = pp[((long)tile * SLICE_WIN + min(t, WL - 1)) * DP + c];
 #pragma unroll
       for (int t = 0; t < SLICE_WIN; ++t) s[t] += v[t];
     }
