@@ -390,7 +390,8 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   // F1 (not in the first block) and F2, then the last block's per-wave copies of dh or the
   // read-out weights of one tile position
   const size_t lds = (size_t)deep_wbytes(DP, sizeof(T), FIRST, BF) +
-                     (LAST ? (size_t)DEEP_WAVES * deep_cpg(DP, BF) * DH_LD : (size_t)DP * 64 + 2 * DP) * sizeof(T);
+                     (LAST ? (size_t)DEEP_WAVES * deep_cpg(DP, BF) * DH_LD * sizeof(T)
+                           : (size_t)DP * 64 * sizeof(T) + 2 * DP * sizeof(double));
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
     allow_lds(deep_kernel<T, DP, FIRST, LAST, BF, NU>, lds);

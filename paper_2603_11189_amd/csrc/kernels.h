@@ -822,11 +822,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   constexpr int CPG = deep_cpg(DP, BF);            // LAST: channels per slice group
   T* dh = tail_s + wave * CPG * DH_LD;             // LAST: this wave's [CPG][DH_LD] copy
   T* om_s = tail_s;                                // not LAST: omega / N [DP][64] of tile t
-  T* ac_s = om_s + DP * 64;                        // not LAST: A^T [2][DP]
+  double* ac_s = reinterpret_cast<double*>(om_s + DP * 64);  // not LAST: A^T [2][DP], float64
   const int N = A.N, Np = A.Np, l = A.l;
   const int nt = Np / 64;
   const int xcd = blockIdx.x % NXCD, bx = blockIdx.x / NXCD, nbx = gridDim.x / NXCD;
   const int t = bx % nt;  // this workgroup's tile position (the host makes nbx a multiple of nt)
+  const bool full = 64 * t + 64 <= N;  // no site of the tile lies past the chain end
+  constexpr bool MXI = !FIRST && !LAST;
   const T* Vt = A.tb.Vt + (long)(l - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(l - 1) * DP * DP;
   __bf16* F1h = reinterpret_cast<__bf16*>(F1);  // BF: [NS][KB][MT][64][8]
@@ -866,7 +868,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   if constexpr (!LAST) {
     for (int idx = threadIdx.x; idx < DP * 64; idx += blockDim.x)
       om_s[idx] = A.tb.omN[(long)(idx >> 6) * Np + 64 * t + (idx & 63)];
-    for (int idx = threadIdx.x; idx < 2 * DP; idx += blockDim.x) ac_s[idx] = A.tb.Ac[idx];
+    for (int idx = threadIdx.x; idx < 2 * DP; idx += blockDim.x) ac_s[idx] = (double)A.tb.Ac[idx];
   }
   __syncthreads();  // the only workgroup barrier: the waves run independently from here
   const int F = A.dyn.count(A.C);
@@ -968,23 +970,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
       for (int sk = 0; sk < KB; ++sk) {
         bf8 bb[NS][4];
+        // slots e and e + 1 of a lane's operand are one 32-bit word: converted together
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int ks = 8 * sk + e;
-          V4<T> v;
-          if constexpr (PF) v = xb[ks];
-          else if constexpr (XL) v = xl[ks];
-          else v = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+        for (int e = 0; e < 8; e += 2) {
+          V4<T> v[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int ks = 8 * sk + e + h;
+            if constexpr (PF) v[h] = xb[ks];
+            else if constexpr (XL) v[h] = xl[ks];
+            else v[h] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+          }
 #pragma unroll
           for (int n = 0; n < 4; ++n) {
+            const f2v pr{v[0].v[n], v[1].v[n]};
             if constexpr (NS == 3) {
-              __bf16 b0, b1, b2;
-              split3(v.v[n], b0, b1, b2);
-              bb[0][n][e] = b0;
-              bb[1][n][e] = b1;
-              bb[2][n][e] = b2;
+              bf2 b0, b1, b2;
+              split3x2(pr, b0, b1, b2);
+              bb[0][n][e] = b0[0]; bb[0][n][e + 1] = b0[1];
+              bb[1][n][e] = b1[0]; bb[1][n][e + 1] = b1[1];
+              bb[2][n][e] = b2[0]; bb[2][n][e + 1] = b2[1];
             } else {
-              bb[0][n][e] = (__bf16)v.v[n];
+              const bf2 b0 = __builtin_convertvector(pr, bf2);
+              bb[0][n][e] = b0[0]; bb[0][n][e + 1] = b0[1];
             }
           }
         }
@@ -1077,9 +1085,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           for (int n = 0; n < 4; ++n) x[n] += (sidx[n] >= 0 ? dv[n] : T(0)) * (pv.v[n] + acc[mt][n][r]);
         }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? x[n] : T(0);
+        for (int n = 0; n < 4; ++n) acc[mt][n][r] = (!MXI || s0 + n < N) ? x[n] : T(0);
         if (r == 3) __builtin_amdgcn_sched_barrier(0);
       }
+    // sites past the chain end hold zeros (only the workgroups of the last tile position
+    // have any; the blocks between first and last mask as they go, since their register
+    // budget has no room for this separate pass)
+    if (!MXI && !full) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mt][n][r] = (s0 + n < N) ? acc[mt][n][r] : T(0);
+    }
     // the next tile's input travels while this one is mixed and stored
     if (PF && g + gstride < g_hi) prefetch(g + gstride);
     // BF: x as bf16 operands of phase 2, in accumulator channel order (step sk: channels
@@ -1091,16 +1110,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float v = acc[2 * sk + (e >> 2)][n][e & 3];
+          for (int e = 0; e < 8; e += 2) {
+            // slots e, e + 1: accumulator entries r, r + 1 of one tile, converted together
+            const f2v pr{acc[2 * sk + (e >> 2)][n][e & 3], acc[2 * sk + (e >> 2)][n][(e & 3) + 1]};
             if constexpr (NS == 3) {
-              __bf16 b0, b1, b2;
-              split3(v, b0, b1, b2);
-              xh[0][sk][n][e] = b0;
-              xh[1][sk][n][e] = b1;
-              xh[2][sk][n][e] = b2;
+              bf2 b0, b1, b2;
+              split3x2(pr, b0, b1, b2);
+              xh[0][sk][n][e] = b0[0]; xh[0][sk][n][e + 1] = b0[1];
+              xh[1][sk][n][e] = b1[0]; xh[1][sk][n][e + 1] = b1[1];
+              xh[2][sk][n][e] = b2[0]; xh[2][sk][n][e + 1] = b2[1];
             } else {
-              xh[0][sk][n][e] = (__bf16)v;
+              const bf2 b0 = __builtin_convertvector(pr, bf2);
+              xh[0][sk][n][e] = b0[0]; xh[0][sk][n][e + 1] = b0[1];
             }
           }
     }
@@ -1170,9 +1191,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const long o = lo_off + (16 * mo + M::r_row(r)) * Np;
+          // sites past the chain end: x is zero there, so du is too
           T y[4];
 #pragma unroll
-          for (int n = 0; n < 4; ++n) y[n] = (s0 + n < N) ? a2[n][r] : T(0);
+          for (int n = 0; n < 4; ++n) y[n] = a2[n][r];
           if constexpr (LAST) {
             // read-out with Wk + tau (tau already carries Wk when L >= 2)
             V4<T> w0, w1;
@@ -1183,21 +1205,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
               w0 = ld4(A.tau + 2 * bo + o);
               w1 = ld4(A.tau + 2 * bo + (long)DP * Np + o);
             }
+            // the lane's four sites in the field precision, the tile's sum in float64
+            T s0w = 0, s1w = 0;
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-              part0 += (double)w0.v[n] * (double)y[n];
-              part1 += (double)w1.v[n] * (double)y[n];
+              s0w += w0.v[n] * y[n];
+              s1w += w1.v[n] * y[n];
             }
+            part0 += (double)s0w;
+            part1 += (double)s1w;
           } else {
             // read-out with Wk = A^T omega / N: one site vector of omega / N per channel,
-            // both from LDS
+            // both from LDS; the lane's four sites in the field precision, the rest in float64
             const int ch = 16 * mo + M::row(lane, r);
             const V4<T> wo = ld4(om_s + ch * 64 + 4 * j);
-            double sw = 0.0;
+            T swt = 0;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) sw += (double)wo.v[n] * (double)y[n];
-            part0 += (double)ac_s[ch] * sw;
-            part1 += (double)ac_s[DP + ch] * sw;
+            for (int n = 0; n < 4; ++n) swt += wo.v[n] * y[n];
+            const double sw = (double)swt;
+            part0 += ac_s[ch] * sw;
+            part1 += ac_s[DP + ch] * sw;
           }
           if (LAST) {
             const int cl = 16 * (mo - mg) + M::row(lane, r);
