@@ -77,6 +77,17 @@ __device__ inline double lcd_d(double a, double d) {
   return logcosh_d(a + d) - logcosh_d(a);
 }
 
+// Workgroup barrier that orders LDS only: global requests stay in flight across it (for
+// kernels whose waves share no global data within the launch).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// fourth word of a raw buffer resource on gfx9-family devices (32-bit data format)
+constexpr int BUF_DW3 = 0x00020000;
+
 // Cross-lane exchanges without the LDS crossbar, word by word (T of 4 or 8 bytes).
 // dpp_get<CTRL>: the value of the lane the data-parallel-primitive control CTRL names.
 constexpr int DPP_XOR1 = 0xB1;         // quad permutation [1, 0, 3, 2]: lane l ^ 1

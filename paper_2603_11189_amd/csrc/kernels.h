@@ -402,18 +402,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     }
   }
   const long cstride = (long)A.DP * Np;
-  // staging: thread t moves sites 4 (t mod 16) .. + 3 of configuration rows t / 16 + 16 u,
-  // one chunk ahead through registers; the workgroup runs over configuration blocks
-  // blockIdx.x, blockIdx.x + gridDim.x, ... (the split taps are built once)
+  // staging: thread t moves sites 4 (t mod 16) .. + 3 of configuration rows t / 16 + 16 u.
+  // The workgroup runs over configuration blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+  // (the split taps are built once), each in chunks of CS_KC input sites; the chunks are
+  // numbered in that order and each is requested two chunks ahead, alternating between two
+  // register buffers
   const int srow = threadIdx.x >> 4, scol = 4 * (threadIdx.x & 15);
-  const float* xrow = A.X + (long)c * Np + scol;
-  float4 pre[4];
-  auto fetch = [&](int blk, int k0) {
+  const int nk = Np / CS_KC;
+  const int nmine = (nblk - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int nchunk = nmine * nk;
+  // buffer resource over the configuration rows cfg0 .. min(cfg0 + 64, C) - 1 of channel c
+  // (the last row's channel segment ends the byte range); on = false: an empty range.
+  // Requests outside the range read zeros, so every chunk issues the same four requests and
+  // the wait for a chunk's data is a fixed count (its barriers order LDS only)
+  auto rows_rsrc = [&](const float* base, int cfg0, bool on) __attribute__((always_inline)) {
+    const int nrow = min(C - cfg0, CONV_MC);
+    const int nbytes = on ? (int)(((long)(nrow - 1) * cstride + Np) * 4) : 0;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base + (long)cfg0 * cstride + (long)c * Np), 0, nbytes, BUF_DW3);
+  };
+  auto fetch = [&](float4 (&p)[4], int ci) __attribute__((always_inline)) {
+    const bool on = ci < nchunk;
+    const int blk = on ? blockIdx.x + (ci / nk) * gridDim.x : blockIdx.x, k0 = (ci % nk) * CS_KC;
+    const auto rx = rows_rsrc(A.X, blk * CONV_MC, on);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int cfg = blk * CONV_MC + srow + 16 * u;
-      pre[u] = cfg < C ? *reinterpret_cast<const float4*>(xrow + (long)cfg * cstride + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int u = 0; u < 4; ++u)
+      p[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(((long)(srow + 16 * u) * cstride + k0 + scol) * 4), 0, 0));
   };
   // matrix-core column j of output tile n is site wsite0 + NT j + n, so that a lane's NT
   // tiles hold NT consecutive sites and 16 lanes a contiguous row segment of one
@@ -427,62 +440,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int sh = p0 & 7;
     tbase[n] = sh * TL + p0 - sh;
   }
-  fetch(blockIdx.x, 0);
-  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  float4 preA[4], preB[4];
+  fetch(preA, 0);
+  fetch(preB, 1);
+  f4 acc[4][NT];
+  auto chunk = [&](float4 (&p)[4], int ci) __attribute__((always_inline)) {
+    const int blk = blockIdx.x + (ci / nk) * gridDim.x, k0 = (ci % nk) * CS_KC;
     const int cfg0 = blk * CONV_MC;
-    f4 acc[4][NT];
+    if (k0 == 0) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[a][n] = f4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < Np; k0 += CS_KC) {
-      __syncthreads();  // the previous chunk is consumed (and the taps are in place)
+        for (int n = 0; n < NT; ++n) acc[a][n] = f4{0, 0, 0, 0};
+    }
+    lds_barrier();  // the previous chunk is consumed (and the taps are in place)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        bf2 a0, a1, a2, b0, b1, b2;
-        split3x2(f2v{pre[u].x, pre[u].y}, a0, a1, a2);
-        split3x2(f2v{pre[u].z, pre[u].w}, b0, b1, b2);
-        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-        __bf16* d = xs + (srow + 16 * u) * CS_LD + scol;
-        *reinterpret_cast<bf4*>(d) = bf4{a0[0], a0[1], b0[0], b0[1]};
-        *reinterpret_cast<bf4*>(d + CONV_MC * CS_LD) = bf4{a1[0], a1[1], b1[0], b1[1]};
-        *reinterpret_cast<bf4*>(d + 2 * CONV_MC * CS_LD) = bf4{a2[0], a2[1], b2[0], b2[1]};
+    for (int u = 0; u < 4; ++u) {
+      bf2 a0, a1, a2, b0, b1, b2;
+      split3x2(f2v{p[u].x, p[u].y}, a0, a1, a2);
+      split3x2(f2v{p[u].z, p[u].w}, b0, b1, b2);
+      typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+      __bf16* d = xs + (srow + 16 * u) * CS_LD + scol;
+      *reinterpret_cast<bf4*>(d) = bf4{a0[0], a0[1], b0[0], b0[1]};
+      *reinterpret_cast<bf4*>(d + CONV_MC * CS_LD) = bf4{a1[0], a1[1], b1[0], b1[1]};
+      *reinterpret_cast<bf4*>(d + 2 * CONV_MC * CS_LD) = bf4{a2[0], a2[1], b2[0], b2[1]};
+    }
+    lds_barrier();
+    fetch(p, ci + 2);
+    if (wsite0 < Np) {
+      // A: configuration rows 16 mt + (lane mod 16), sites 32 ks + 8 (lane / 16) + e
+      auto lda = [&](int b, int ks, int mt) {
+        return *reinterpret_cast<const bf8*>(xs + (b * CONV_MC + 16 * mt + (lane & 15)) * CS_LD + 32 * ks + 8 * (lane >> 4));
+      };
+      // B: g(i - k) for output site i = wsite0 + NT (lane mod 16) + n and the lane's 8
+      // input sites k = k0 + 32 ks + 8 (lane / 16) + e, i.e. R[p + e]
+      auto ldb = [&](int b, int ks, int n) {
+        return *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
+      };
+      bf8 xa[3][4], tb[3][NT];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) xa[b][mt] = lda(b, 0, mt);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) tb[b][n] = ldb(b, 0, n);
       }
-      __syncthreads();
-      if (k0 + CS_KC < Np) fetch(blk, k0 + CS_KC);
-      else if (blk + (int)gridDim.x < nblk) fetch(blk + gridDim.x, 0);
-      if (wsite0 < Np) {
+      // the six products of a step, smallest first; an operand term is replaced by the next
+      // step's as soon as its last product of this step is issued
 #pragma unroll
-        for (int ks = 0; ks < CS_KC / 32; ++ks) {
-          // A: configuration rows 16 mt + (lane mod 16), sites 32 ks + 8 (lane / 16) + e
-          bf8 xa[3][4];
+      for (int ks = 0; ks < CS_KC / 32; ++ks) {
+        const bool more = ks + 1 < CS_KC / 32;
 #pragma unroll
-          for (int b = 0; b < 3; ++b)
+        for (int term = 0; term < 6; ++term) {
+          const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
+          const int tg = term == 0 ? 0 : term == 1 ? 1 : term == 2 ? 2 : term == 3 ? 0 : term == 4 ? 1 : 0;
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-              xa[b][mt] = *reinterpret_cast<const bf8*>(xs + (b * CONV_MC + 16 * mt + (lane & 15)) * CS_LD + 32 * ks + 8 * (lane >> 4));
-          // B: g(i - k) for output site i = wsite0 + NT (lane mod 16) + n and the lane's 8
-          // input sites k = k0 + 32 ks + 8 (lane / 16) + e, i.e. R[p + e]
-          bf8 tb[3][NT];
+          for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
+            for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
+          if (more) {
+            if (term == 0) {
 #pragma unroll
-            for (int b = 0; b < 3; ++b)
-              tb[b][n] = *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
-          // the six products, smallest first; each step runs over all 4 NT accumulators
+              for (int mt = 0; mt < 4; ++mt) xa[2][mt] = lda(2, ks + 1, mt);
+            } else if (term == 2) {
 #pragma unroll
-          for (int term = 0; term < 6; ++term) {
-            const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
-            const int tg = term == 0 ? 0 : term == 1 ? 1 : term == 2 ? 2 : term == 3 ? 0 : term == 4 ? 1 : 0;
+              for (int n = 0; n < NT; ++n) tb[2][n] = ldb(2, ks + 1, n);
+            } else if (term == 3) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+              for (int mt = 0; mt < 4; ++mt) xa[1][mt] = lda(1, ks + 1, mt);
+            } else if (term == 4) {
 #pragma unroll
-              for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
+              for (int n = 0; n < NT; ++n) tb[1][n] = ldb(1, ks + 1, n);
+            } else if (term == 5) {
+#pragma unroll
+              for (int mt = 0; mt < 4; ++mt) xa[0][mt] = lda(0, ks + 1, mt);
+#pragma unroll
+              for (int n = 0; n < NT; ++n) tb[0][n] = ldb(0, ks + 1, n);
+            }
           }
         }
       }
     }
-    if (wsite0 < Np) {
+    if (k0 + CS_KC >= Np && wsite0 < Np) {
       // accumulator (mt, n) entry r: configuration 16 mt + 4 (lane / 16) + r, site
       // wsite0 + NT (lane mod 16) + n (the wave's sites all lie below Np)
       const int i0 = wsite0 + NT * (lane & 15);
@@ -508,6 +547,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
           }
         }
     }
+  };
+  for (int ci = 0; ci < nchunk; ci += 2) {
+    chunk(preA, ci);
+    if (ci + 1 < nchunk) chunk(preB, ci + 1);
   }
 }
 
