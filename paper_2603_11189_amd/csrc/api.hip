@@ -340,7 +340,8 @@ template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>
   if constexpr (std::is_same<T, double>::value) {
     phi_go<T, DP, 1>(a, C, lds, st);
   } else {
-    switch (tiles_per_wave(m->Np)) {
+    // 64 channels: at most two site tiles per wave (more spill the weight fragments)
+    switch (DP >= 64 ? std::min(2, tiles_per_wave(m->Np)) : tiles_per_wave(m->Np)) {
       case 1: phi_go<T, DP, 1>(a, C, lds, st); break;
       case 2: phi_go<T, DP, 2>(a, C, lds, st); break;
       case 3: phi_go<T, DP, 3>(a, C, lds, st); break;
