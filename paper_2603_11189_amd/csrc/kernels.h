@@ -628,6 +628,16 @@ template <typename T> __device__ inline void st4(T* p, const T* v) {
     for (int n = 0; n < 4; ++n) p[n] = v[n];
   }
 }
+// the same into global memory as a streaming (non-temporal) store, for fields that are not
+// read again before they leave L2
+template <typename T> __device__ inline void st4_stream(T* p, const T* v) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_nontemporal_store(f4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f4*>(p));
+  } else {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) __builtin_nontemporal_store(v[n], p + n);
+  }
+}
 
 // Wave-scope ordering of LDS traffic between lanes of one wave.
 __device__ inline void wave_sync() {
@@ -1275,7 +1285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
             for (int n = 0; n < 4; ++n) dh[cl * DH_LD + 4 * j + n] = y[n];
             __builtin_amdgcn_sched_barrier(0);
           } else {
-            st4(A.out + fo + o, y);
+            st4_stream(A.out + fo + o, y);
           }
         }
       }
