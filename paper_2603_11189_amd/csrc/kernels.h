@@ -620,6 +620,19 @@ template <typename T> __device__ inline V4<T> ld4(const T* p) {
   }
   return r;
 }
+// ld4 as a streaming (non-temporal) load, for fields read once
+template <typename T> __device__ inline V4<T> ld4_stream(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    const f4 f = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+#pragma unroll
+    for (int n = 0; n < 4; ++n) r.v[n] = f[n];
+  } else {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) r.v[n] = __builtin_nontemporal_load(p + n);
+  }
+  return r;
+}
 template <typename T> __device__ inline void st4(T* p, const T* v) {
   if constexpr (sizeof(T) == 4) {
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
@@ -954,7 +967,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   auto prefetch = [&](int gq) {
     const T* src = A.X + (long)gq * DP * Np + 64 * t + kq_row * Np + 4 * j;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4(src + urow(ks) * Np);
+    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld4_stream(src + urow(ks) * Np);
     if constexpr (PFC) {
       const T* cs = A.chi + (long)(A.map.cb[cfg0 + gq] - A.b0) * DP * Np + (long)lrow * Np + 64 * t + 4 * j;
 #pragma unroll
@@ -1007,7 +1020,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     } else if constexpr (BFM) {
       if constexpr (XL) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4_stream(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
       }
       auto fetch_chi = [&](int m0, int m1) {
 #pragma unroll
@@ -1032,7 +1045,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
             const int ks = 8 * sk + e + h;
             if constexpr (PF) v[h] = xb[ks];
             else if constexpr (XL) v[h] = xl[ks];
-            else v[h] = ld4(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
+            else v[h] = ld4_stream(A.X + fo + kq_row * Np + urow(ks) * Np + s0);
           }
 #pragma unroll
           for (int n = 0; n < 4; ++n) {
@@ -1069,7 +1082,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     } else {
       if constexpr (XL) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+        for (int ks = 0; ks < KS; ++ks) xl[ks] = ld4_stream(A.X + fo + kq * Np + 4 * ks * Np + s0);
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -1086,7 +1099,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
           for (int n = 0; n < 4; ++n) bv[n] = xl[ks].v[n];
         } else {
-          const V4<T> v = ld4(A.X + fo + kq * Np + 4 * ks * Np + s0);
+          const V4<T> v = ld4_stream(A.X + fo + kq * Np + 4 * ks * Np + s0);
 #pragma unroll
           for (int n = 0; n < 4; ++n) bv[n] = v.v[n];
         }
