@@ -44,6 +44,23 @@ def mfma_peak(kind: str, prec: str, products: str, d: int):
     return PEAK[prec if prec != "bf16" else "fp32"], ("fp64" if prec == "fp64" else "fp32") + " dense peak"
 
 
+def products_label(prec: str, products: str, d: int) -> str:
+    """What the matrix cores compute in this run: the product mode selects the Toeplitz
+    products; channel mixing follows it for float models with d > 16, is on bf16-rounded
+    operands for BF16-mixed ones (d > 16), and on the float matrix cores otherwise."""
+    if prec == "fp64":
+        return "f64 matrix cores"
+    split = "three-term bf16 splits (six partial products, f32 accumulate: f32 error bound)"
+    toeplitz = split if products == "split3" else "f32 matrix cores"
+    if prec == "bf16" and d > 16:
+        mix = "bf16-rounded operands, f32 accumulate"
+    elif products == "split3" and d > 16:
+        mix = split
+    else:
+        mix = "f32 matrix cores"
+    return f"Toeplitz products: {toeplitz}; channel mixing: {mix}"
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_11189_amd", "csrc")
@@ -289,9 +306,7 @@ def main():
         "set_params_ms": set_params_ms,
         "launch_shapes": tuned or {"conv_tiles_per_wave": 4 if Np >= 256 else Np // 64, "flip_chunk_MiB": 3072,
                                    "set_by": "library defaults"},
-        "products": ({"split3": "Toeplitz and deep channel-mixing products as three-term bf16 splits "
-                                "(six partial products, f32 accumulate: f32 error bound)",
-                      "fp32": "f32 matrix cores"}[args.products] if prec != "fp64" else "f64 matrix cores"),
+        "products": products_label(prec, args.products, shape.d),
     }
     if grad:
         out["grad_logpsi"] = grad
