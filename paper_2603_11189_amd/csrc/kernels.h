@@ -1346,10 +1346,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           if constexpr (CPG <= 16) ya[u] = swap_sum<16>(ya[u]);
           ya[u] = swap_sum<32>(ya[u]);
         }
-        if (hp == 0) {
+        {
+          // every part holds the sums after the row swaps: lane (c, hp) stores the rows
+          // u = hp, hp + NPART, ... of channel cg
           T* pp = A.slice_part + ((long)g * nt + t) * SLICE_WIN * DP + cg;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) pp[u * DP] = ya[u];
+          for (int u0 = 0; u0 < NU; u0 += NPART) {
+            T v = ya[u0];
+#pragma unroll
+            for (int q = 1; q < NPART; ++q)
+              if (u0 + q < NU) v = (hp == q) ? ya[u0 + q] : v;
+            if (u0 + hp < NU) pp[(u0 + hp) * DP] = v;
+          }
         }
         wave_sync();  // the copy in LDS is free for the next group
       }
