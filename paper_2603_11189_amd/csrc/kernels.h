@@ -1396,6 +1396,16 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   T* Y = reinterpret_cast<T*>(smem_raw);  // [DP][16]: Y[c][t]
   T* X2 = Y + DP * SLICE_WIN;             // [DP][16]
   const T* pp = A.slice_part + (long)g * nt * SLICE_WIN * DP;
+  // float: the V operand does not depend on the partials and is requested before them
+  constexpr bool VH = sizeof(T) == 4;
+  const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
+  T vf[VH ? KS : 1][VH ? MT : 1];
+  if constexpr (VH) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) vf[ks][mt] = Vt[(4 * ks + kq) * DP + 16 * mt + j];
+  }
   for (int c = lane; c < DP; c += 64) {
     // a tile's partials are requested together; rows past the slice (which the last block
     // may not have written) re-read its last row and are dropped below
@@ -1413,7 +1423,6 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     for (int t = 0; t < SLICE_WIN; ++t) Y[c * SLICE_WIN + t] = (t < WL) ? s[t] : T(0);
   }
   wave_sync();
-  const T* Vt = A.tb.Vt + (long)(A.L - 1) * DP * DP;
   const T* Ut = A.tb.Ut + (long)(A.L - 1) * DP * DP;
   acc_t a2[MT];
 #pragma unroll
@@ -1423,7 +1432,7 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     const int kc = 4 * ks + kq;
     const T bvv = Y[kc * SLICE_WIN + j];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(Vt[kc * DP + 16 * mt + j], bvv, a2[mt]);
+    for (int mt = 0; mt < MT; ++mt) a2[mt] = M::mma(VH ? vf[VH ? ks : 0][VH ? mt : 0] : Vt[kc * DP + 16 * mt + j], bvv, a2[mt]);
   }
   const int t_me = j;  // this lane's slice position (matrix-core column)
   int site = loL + t_me;
