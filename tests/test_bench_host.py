@@ -1,0 +1,48 @@
+"""Host-side logic of bench.py (no GPU): the peak each kernel class is measured against and
+the description of what the matrix cores compute must agree for every precision and
+product mode, since the JSON line reports both."""
+import importlib.util
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_split_peak_is_a_sixth_of_bf16(bench):
+    bf16 = bench.PEAK["bf16"]
+    for kind in ("conv", "mix_deep"):
+        peak, basis = bench.mfma_peak(kind, "fp32", "split3", 64)
+        assert peak == pytest.approx(bf16 / 6) and "/ 6" in basis
+    # narrow models mix channels on the float matrix cores even in the split mode
+    assert bench.mfma_peak("mix_deep", "fp32", "split3", 16)[0] == bench.PEAK["fp32"]
+    assert bench.mfma_peak("conv", "fp32", "fp32", 64)[0] == bench.PEAK["fp32"]
+    assert bench.mfma_peak("conv", "fp64", "split3", 64)[0] == bench.PEAK["fp64"]
+    assert bench.mfma_peak("mix_deep", "bf16", "split3", 64)[0] == bf16
+
+
+@pytest.mark.parametrize("prec,products,d", [(p, m, d) for p in ("fp32", "bf16", "fp64")
+                                              for m in ("split3", "fp32") for d in (16, 64)])
+def test_products_label_matches_peaks(bench, prec, products, d):
+    label = bench.products_label(prec, products, d)
+    if prec == "fp64":
+        assert label == "f64 matrix cores"
+        return
+    toeplitz, mix = label.split("; channel mixing: ")
+    conv_split = "/ 6" in bench.mfma_peak("conv", prec, products, d)[1]
+    assert ("three-term" in toeplitz) == conv_split
+    deep_peak, deep_basis = bench.mfma_peak("mix_deep", prec, products, d)
+    if prec == "bf16" and d > 16:
+        assert mix.startswith("bf16-rounded") and deep_peak == bench.PEAK["bf16"]
+    elif products == "split3" and d > 16:
+        assert "three-term" in mix and "/ 6" in deep_basis
+    else:
+        assert mix == "f32 matrix cores" and deep_peak == bench.PEAK["fp32"]
