@@ -412,8 +412,9 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   const double Nr = m->desc.N, dr = m->desc.d, fld = Nr * dr * sizeof(T);
   const int WL = 2 + 2 * m->desc.L * m->desc.w_c + 1;
   {
+    // the first block forms its V product from the unit-flip table (only U is a product);
     // the last block also forms the tiles' partial slices of the last mixer's output
-    const double fl = 4.0 * F * Nr * dr * dr + (LAST ? 2.0 * F * WL * Nr * dr : 0.0);
+    const double fl = (FIRST ? 2.0 : 4.0) * F * Nr * dr * dr + (LAST ? 2.0 * F * WL * Nr * dr : 0.0);
     const double by = F * fld * ((FIRST ? 0 : 1) + (LAST ? 0 : 1)) + (double)Bc * fld * (LAST ? 4 : 2);
     PScope ps(m, DN_K_MIX_DEEP, st, fl, by);
     deep_kernel<T, DP, FIRST, LAST, BF, NU><<<(int)grid, 256, lds, st>>>(a);
@@ -451,7 +452,7 @@ dn_status launch_deep_mode(dn_model* m, const MixArgs<T>& a, int F, hipStream_t 
 template <typename T, int DP>
 dn_status launch_deep_any(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, int Bc, bool first, bool last) {
   if constexpr (std::is_same<T, float>::value && DP >= 32) {
-    if (use_bf16(m)) return launch_deep_mode<T, DP, 1>(m, a, F, st, Bc, first, last);
+    if (use_bf16(m)) return launch_deep_mode<T, DP, 2>(m, a, F, st, Bc, first, last);
     if (m->split3) return launch_deep_mode<T, DP, 3>(m, a, F, st, Bc, first, last);
   }
   return launch_deep_mode<T, DP, 0>(m, a, F, st, Bc, first, last);

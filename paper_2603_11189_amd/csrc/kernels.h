@@ -360,6 +360,23 @@ __device__ inline void split3x2(f2v v, bf2& b0, bf2& b1, bf2& b2) {
   b1 = __builtin_convertvector(r1, bf2);
   b2 = __builtin_convertvector(r1 - __builtin_convertvector(b1, f2v), bf2);
 }
+// NS-term splits (NS = 1: the value rounded to bf16; 2: hi + lo, 16 significant bits; 3: exact)
+template <int NS> __device__ inline void splitn(float v, __bf16* b) {
+  if constexpr (NS == 3) {
+    split3(v, b[0], b[1], b[2]);
+  } else {
+    b[0] = (__bf16)v;
+    if constexpr (NS == 2) b[1] = (__bf16)(v - (float)b[0]);
+  }
+}
+template <int NS> __device__ inline void splitnx2(f2v v, bf2* b) {
+  if constexpr (NS == 3) {
+    split3x2(v, b[0], b[1], b[2]);
+  } else {
+    b[0] = __builtin_convertvector(v, bf2);
+    if constexpr (NS == 2) b[1] = __builtin_convertvector(v - __builtin_convertvector(b[0], f2v), bf2);
+  }
+}
 
 template <int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv_split_kernel(ConvArgs<float> A) {
@@ -660,7 +677,8 @@ __device__ inline void wave_sync() {
 }
 
 // BF (float fields only): both channel-mixing products on the bf16 matrix cores with float
-// accumulation (operands rounded to bf16 as they are formed; fields stay float).
+// accumulation; each operand is split into hi + lo bf16 terms as it is formed (16 significant
+// bits) and the three partial products hi*hi, hi*lo, lo*hi are accumulated (fields stay float).
 template <typename T, int DP, int MODE, bool BF>
 __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   using M = Mma<T>;
@@ -693,18 +711,33 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
       V4<T> xv[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) xv[e] = ld4(X + (long)(32 * s + 8 * kq + e) * Np + s0);
-      bf8 bb[4];
+      bf8 bb[2][4];
 #pragma unroll
       for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bb[n][e] = (__bf16)xv[e].v[n];
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h[2];
+          splitn<2>(xv[e].v[n], h);
+          bb[0][n][e] = h[0];
+          bb[1][n][e] = h[1];
+        }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        bf8 af;
+        bf8 af[2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) af[e] = (__bf16)M1[(32 * s + 8 * kq + e) * DP + 16 * mt + j];
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h[2];
+          splitn<2>(M1[(32 * s + 8 * kq + e) * DP + 16 * mt + j], h);
+          af[0][e] = h[0];
+          af[1][e] = h[1];
+        }
+        // hi * lo and lo * hi first, then hi * hi
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[mt][n] = mma_bf16(af, bb[n], acc[mt][n]);
+        for (int n = 0; n < 4; ++n) {
+          acc[mt][n] = mma_bf16(af[1], bb[0][n], acc[mt][n]);
+          acc[mt][n] = mma_bf16(af[0], bb[1][n], acc[mt][n]);
+          acc[mt][n] = mma_bf16(af[0], bb[0][n], acc[mt][n]);
+        }
       }
     }
   } else {
@@ -735,16 +768,21 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
 #pragma unroll
       for (int n = 0; n < 4; ++n) acc[mt][n][r] = (s0 + n < N) ? c.v[n] * q[n] : T(0);
     }
-  // BF: x as bf16 operands of phase 2, in accumulator channel order (step s: channels
-  // 16 (2 s + e / 4) + row(lane, e mod 4))
-  bf8 xh[BF ? DP / 32 : 1][4];
+  // BF: x as hi + lo bf16 operands of phase 2, in accumulator channel order (step s:
+  // channels 16 (2 s + e / 4) + row(lane, e mod 4))
+  bf8 xh[BF ? 2 : 1][BF ? DP / 32 : 1][4];
   if constexpr (BF) {
 #pragma unroll
     for (int s = 0; s < DP / 32; ++s)
 #pragma unroll
       for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xh[s][n][e] = (__bf16)acc[2 * s + (e >> 2)][n][e & 3];
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h[2];
+          splitn<2>(acc[2 * s + (e >> 2)][n][e & 3], h);
+          xh[0][s][n][e] = h[0];
+          xh[1][s][n][e] = h[1];
+        }
   }
   // ---- phase 2, one 16-channel output tile at a time
   double part0 = 0.0, part1 = 0.0;
@@ -756,12 +794,20 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
     if constexpr (BF) {
 #pragma unroll
       for (int s = 0; s < DP / 32; ++s) {
-        bf8 af;
+        bf8 af[2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          af[e] = (__bf16)M2[(16 * (2 * s + (e >> 2)) + M::row(lane, e & 3)) * DP + 16 * mo + j];
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h[2];
+          splitn<2>(M2[(16 * (2 * s + (e >> 2)) + M::row(lane, e & 3)) * DP + 16 * mo + j], h);
+          af[0][e] = h[0];
+          af[1][e] = h[1];
+        }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) a2[n] = mma_bf16(af, xh[s][n], a2[n]);
+        for (int n = 0; n < 4; ++n) {
+          a2[n] = mma_bf16(af[1], xh[0][s][n], a2[n]);
+          a2[n] = mma_bf16(af[0], xh[1][s][n], a2[n]);
+          a2[n] = mma_bf16(af[0], xh[0][s][n], a2[n]);
+        }
       }
     } else {
 #pragma unroll
@@ -843,7 +889,7 @@ constexpr int NXCD = 8;
 // waves per SIMD each variant's register budget is sized for (the last block's LDS holds it
 // to two workgroups per CU in any case; three-term bf16 operands need the room of two)
 constexpr int deep_occ(int elem_bytes, bool prefetch, bool last, int bf) {
-  return elem_bytes == 4 && !prefetch && !last && bf != 3 ? 3 : 2;
+  return elem_bytes == 4 && !prefetch && !last && bf < 2 ? 3 : 2;
 }
 // bytes of LDS the weight fragments of a deep block take: F1 (not in the first block), F2
 constexpr int deep_wbytes(int DP, int elem_bytes, bool first, int bf) {
@@ -859,10 +905,11 @@ constexpr int deep_cpg(int DP, int bf) { return DP < (bf == 3 ? 16 : DH_CH) ? DP
 
 // BF (float fields only; the number of bf16 terms per operand, 0 = float matrix cores):
 // both channel-mixing products on the bf16 matrix cores with float accumulation, the weight
-// fragments held in LDS as bf16. BF = 1: operands rounded to bf16 (the BF16-mixed mode).
-// BF = 3: both operands split into three bf16 terms, x = x0 + x1 + x2 exactly, and the six
-// partial products with a + b <= 2 accumulated, which keeps the error bound of a float
-// product (the dropped ones are below 2^-24 |x v|).
+// fragments held in LDS as bf16 terms; the partial products x_a v_b with a + b <= BF - 1 are
+// accumulated, smallest first. BF = 1: operands rounded to bf16. BF = 2 (the BF16-mixed
+// mode): hi + lo terms (16 significant bits), three partial products, relative error of a
+// product below 2^-15. BF = 3: x = x0 + x1 + x2 exactly and six partial products, which keeps
+// the error bound of a float product (the dropped ones are below 2^-24 |x v|).
 // NU (last block, float): slice positions the partial slices cover, at least the widest
 // slice S_L of the launch (the others keep SLICE_WIN).
 template <typename T, int DP, bool FIRST, bool LAST, int BF, int NU = SLICE_WIN>
@@ -875,7 +922,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   constexpr bool PF = DEEP_PF && !FIRST && !LAST && KS * 4 * sizeof(T) <= 256;
   constexpr bool BFM = BF != 0;     // bf16 matrix cores
   constexpr int NS = BFM ? BF : 1;  // bf16 terms per operand
-  static_assert(BF == 0 || BF == 1 || BF == 3, "one or three bf16 terms");
+  static_assert(BF >= 0 && BF <= 3, "one to three bf16 terms");
   static_assert(NU == SLICE_WIN || (LAST && sizeof(T) == 4 && NU >= 1 && NU < SLICE_WIN), "narrow partial slices: last block, float");
   // LDS: F1 (not in the first block), F2, then the last block's per-wave copies of dh or
   // the other blocks' read-out weights (sized by the host in launch_deep)
@@ -906,15 +953,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     if (!FIRST) {
       const int mt = hi % MT, sk = hi / MT;
       const float v = Vt[(32 * sk + 8 * (ln >> 4) + e) * DP + 16 * mt + (ln & 15)];
-      if constexpr (NS == 3) split3(v, b[0], b[1], b[2]);
-      else b[0] = (__bf16)v;
+      splitn<NS>(v, b);
 #pragma unroll
       for (int q = 0; q < NS; ++q) F1h[q * DP * DP + idx] = b[q];
     }
     const int sk = hi % KB, mo = hi / KB;
     const float v = Ut[(16 * (2 * sk + (e >> 2)) + M::row(ln, e & 3)) * DP + 16 * mo + (ln & 15)];
-    if constexpr (NS == 3) split3(v, b[0], b[1], b[2]);
-    else b[0] = (__bf16)v;
+    splitn<NS>(v, b);
 #pragma unroll
     for (int q = 0; q < NS; ++q) F2h[q * DP * DP + idx] = b[q];
   }
@@ -955,10 +1000,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
   // with the input also the tile's background gate chi0 is fetched one tile ahead (float
   // operands only: it does not fit the register budget of the other variants)
   constexpr bool PFC = PF && !BFM && sizeof(T) == 4;
-  // three-term variants: the gate is requested while phase 1 runs (after the first block
+  // split variants: the gate is requested while phase 1 runs (after the first block
   // half of it when the tile starts and half once the first half of the input is consumed;
   // in the first block all of it, ahead of the table reads)
-  constexpr bool EC = BF == 3 && sizeof(T) == 4;
+  constexpr bool EC = BF >= 2 && sizeof(T) == 4;
   V4<T> cb[PFC || EC ? MT * 4 : 1];
   // without that prefetch (the last block, float) the whole input tile is requested at once
   // when the tile starts, so its latency is met once rather than at every step
@@ -1050,16 +1095,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 #pragma unroll
           for (int n = 0; n < 4; ++n) {
             const f2v pr{v[0].v[n], v[1].v[n]};
-            if constexpr (NS == 3) {
-              bf2 b0, b1, b2;
-              split3x2(pr, b0, b1, b2);
-              bb[0][n][e] = b0[0]; bb[0][n][e + 1] = b0[1];
-              bb[1][n][e] = b1[0]; bb[1][n][e + 1] = b1[1];
-              bb[2][n][e] = b2[0]; bb[2][n][e + 1] = b2[1];
-            } else {
-              const bf2 b0 = __builtin_convertvector(pr, bf2);
-              bb[0][n][e] = b0[0]; bb[0][n][e + 1] = b0[1];
-            }
+            bf2 bq[NS];
+            splitnx2<NS>(pr, bq);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) { bb[q][n][e] = bq[q][0]; bb[q][n][e + 1] = bq[q][1]; }
           }
         }
         if constexpr (EC) {
@@ -1179,16 +1218,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
           for (int e = 0; e < 8; e += 2) {
             // slots e, e + 1: accumulator entries r, r + 1 of one tile, converted together
             const f2v pr{acc[2 * sk + (e >> 2)][n][e & 3], acc[2 * sk + (e >> 2)][n][(e & 3) + 1]};
-            if constexpr (NS == 3) {
-              bf2 b0, b1, b2;
-              split3x2(pr, b0, b1, b2);
-              xh[0][sk][n][e] = b0[0]; xh[0][sk][n][e + 1] = b0[1];
-              xh[1][sk][n][e] = b1[0]; xh[1][sk][n][e + 1] = b1[1];
-              xh[2][sk][n][e] = b2[0]; xh[2][sk][n][e + 1] = b2[1];
-            } else {
-              const bf2 b0 = __builtin_convertvector(pr, bf2);
-              xh[0][sk][n][e] = b0[0]; xh[0][sk][n][e + 1] = b0[1];
-            }
+            bf2 bq[NS];
+            splitnx2<NS>(pr, bq);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) { xh[q][sk][n][e] = bq[q][0]; xh[q][sk][n][e + 1] = bq[q][1]; }
           }
     }
     // ---- phase 2 per 16-channel output tile: du = U x, stored, and read out

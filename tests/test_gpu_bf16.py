@@ -1,18 +1,21 @@
-"""GPU parity of the BF16-mixed precision mode against the FP64 oracle.
+"""GPU parity of the BF16-mixed precision mode against the FP64 oracle, at the 1e-4 target.
 
 In this mode both channel-mixing products of every block (forward, adjoint and the ABACUS
-deep propagation) run on the bf16 matrix cores with float accumulation; fields, the
-phi stream, the Toeplitz mixer, the slice recompute and the log-ratio read-out stay in
-float / float64. Error bounds follow from the bf16 unit roundoff u = 2^-8 (round to
-nearest even, 8 significant bits): each mixing product rounds its two operands, so each
-block changes Omega (and the propagated dOmega) by about 2u relative, and L blocks by
-about 2Lu. With a factor 2 of margin:
-  * ABACUS log-ratios:   |lr - lr*| <= 4 L u * lr_scale (lr_scale as in the float tests:
-                          max|lr*|, or for pair exchanges the larger single-flip ratios);
-  * plain log-ratios:    the difference of two evaluations, |Omega|^2 scale (as in float);
-  * log psi:             |d log psi| <= 4 L u * max|Omega| * max(1, max|Omega|);
-  * E_loc:               |dE| <= max_b sum_m |h_bm| psi(s'_m)/psi(s_b) * (bound on |d lr|).
-The measured errors are printed next to the bounds.
+deep propagation) run on the bf16 matrix cores with float accumulation, every operand split
+into hi + lo bf16 terms as it is formed (x = x_hi + x_lo + r with |r| <= 2^-17 |x|) and the
+three partial products hi*hi, hi*lo, lo*hi accumulated; the dropped lo*lo term and the two
+representation remainders bound a product's relative error by 3 * 2^-17 = 2.3e-5. The
+Toeplitz products use the three-term split (float accuracy); fields, the phi stream, the
+slice recompute and the log-ratio read-out stay in float / float64.
+Measures (printed with the bounds), all held to 1e-4:
+  * eps_lr   = max|lr - lr*| / lr_scale, lr_scale as in the float tests (max|lr*|, or for
+               pair exchanges the larger single-flip ratios); the plain path's difference of
+               two evaluations is judged against max(lr_scale, |Omega|^2);
+  * eps_logpsi normwise;
+  * eps_E,net = max|E - E*| / max|E* - E*_(psi=1)|, the error relative to the
+               network-dependent part of E_loc (E*_(psi=1) = hdiag + sum_m helem_m).
+The plain path's E_loc sums n_conn ratios that each carry the |Omega|^2 floor of a difference
+of two evaluations, so its eps_E,net is held to 1e-3.
 """
 import sys
 
@@ -25,7 +28,7 @@ from oracle.model import ModelDesc, forward
 
 pytestmark = pytest.mark.gpu
 
-U_BF16 = 2.0 ** -8
+TARGET = 1e-4
 
 
 def _say(*a):
@@ -42,17 +45,21 @@ def L():
 
 
 CASES = [
-    # the J1-J2 chain of the BF16 workload (N=128, four blocks, d=64, periodic, balanced spins)
-    (di.ModelShape(128, 4, 64, 32, bc="periodic"), di.HamSpec("j1j2", "periodic"), 6, "balanced"),
-    (di.ModelShape(96, 3, 32, 16, bc="open"), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6, "uniform"),
-    (di.ModelShape(70, 2, 48, 8, act="tanh", bc="open"), di.HamSpec("j1j2", "open"), 5, "uniform"),
+    # the J1-J2 chain of the BF16 workload (N=128, four blocks, d=64, periodic, balanced
+    # spins), 32 samples, stress draw: at the baseline draw this network's output vanishes
+    # by symmetry on zero-magnetisation configurations (|Omega| ~ 1e-8), so relative errors
+    # there measure float noise, not the mode
+    (di.ModelShape(128, 4, 64, 32, bc="periodic"), di.HamSpec("j1j2", "periodic"), 32, "balanced", "stress"),
+    (di.ModelShape(96, 3, 32, 16, bc="open"), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6, "uniform", "stress"),
+    (di.ModelShape(96, 3, 32, 16, bc="open"), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6, "uniform", "baseline"),
+    (di.ModelShape(70, 2, 48, 8, act="tanh", bc="open"), di.HamSpec("j1j2", "open"), 5, "uniform", "stress"),
+    (di.ModelShape(70, 2, 48, 8, act="tanh", bc="open"), di.HamSpec("j1j2", "open"), 5, "uniform", "baseline"),
 ]
 
 
-@pytest.mark.parametrize("shape,ham,B,spins", CASES, ids=lambda x: str(x)[:40])
-@pytest.mark.parametrize("scale", ["baseline", "stress"])
+@pytest.mark.parametrize("shape,ham,B,spins,scale", CASES, ids=lambda x: str(x)[:40])
 def test_bf16_logratio_and_eloc(L, shape, ham, B, spins, scale):
-    _say("bf16", shape, ham.kind, scale)
+    _say("bf16", shape, ham.kind, scale, B)
     th = torch.tensor(di.draw_params(shape, 41, scale))
     m = L.Model(shape, "bf16")
     m.set_params(th)
@@ -68,22 +75,19 @@ def test_bf16_logratio_and_eloc(L, shape, ham, B, spins, scale):
         single = O.connected(di.HamSpec("lrtfim", shape.bc), sp)
         _, lr1 = O.plain_logratio(desc, th, sp, single[0], single[2])
         lr_scale = max(lr_scale, lr1.abs().max().item())
-    b = 4 * shape.L * U_BF16
+    e_flat = ref["hdiag"] + ref["helem"].sum(-1)
+    net = (ref["eloc"] - e_flat).abs().max().item()
     spd = torch.tensor(sp, device="cuda")
-    mask = torch.arange(M_max)[None, :] < ref["n_conn"][:, None]
-    weight = (ref["helem"].abs() * torch.exp(ref["logratio"]) * mask).sum(-1).max().item()
     for path in ("abacus", "full"):
         lp, lr, el = (t.cpu() for t in m.eloc(ham, spd, M_max, path=path))
-        d_lr = (lr - ref["logratio"]).abs().max().item()
-        d_lp = (lp - ref["logpsi"]).abs().max().item()
-        d_el = (el - ref["eloc"]).abs().max().item()
-        lr_bound = b * (lr_scale if path == "abacus" else max(lr_scale, om * om))
-        lp_bound = b * om * max(1.0, om)
-        el_bound = weight * lr_bound
-        _say(f"  {path}: |d lr| {d_lr:.3e} (bound {lr_bound:.3e})  |d logpsi| {d_lp:.3e} "
-             f"(bound {lp_bound:.3e})  |d E| {d_el:.3e} (bound {el_bound:.3e})  "
-             f"eps_eloc {d_el / ref['eloc'].abs().max().item():.3e}")
-        assert d_lr <= lr_bound and d_lp <= lp_bound and d_el <= el_bound
+        allow = 1.0 if path == "abacus" else max(lr_scale, om * om) / lr_scale
+        e_lr = (lr - ref["logratio"]).abs().max().item() / lr_scale
+        e_lp = (lp - ref["logpsi"]).abs().max().item() / ref["logpsi"].abs().max().item()
+        e_net = (el - ref["eloc"]).abs().max().item() / net
+        _say(f"  {path}: eps_lr {e_lr:.3e} (bound {TARGET * allow:.1e})  eps_logpsi {e_lp:.3e}  "
+             f"eps_E,net {e_net:.3e}  (|Omega| <= {om:.2e}, lr_scale {lr_scale:.2e})")
+        assert e_lr <= TARGET * allow and e_lp <= TARGET
+        assert e_net <= (TARGET if path == "abacus" else 10 * TARGET)
     m.close()
 
 
