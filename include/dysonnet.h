@@ -52,10 +52,13 @@ typedef enum { DN_ACT_SILU = 0, DN_ACT_TANH = 1, DN_ACT_IDENTITY = 2 } dn_act;
  * matrix cores with both float operands split into three bf16 terms, which keeps float32
  * accuracy (see dn_set_product_mode). BF16_MIXED (d > 16): the
  * two channel-mixing products of every block (V and U: forward, adjoint and the ABACUS
- * propagation) take bfloat16 operands (round to nearest even) on the bf16 matrix cores
- * with float32 accumulation; everything else as FP32 (phi stream, Green's-function mixer,
- * slices; per-sample gradients run entirely in float32). Kernel generation, the read-out
- * sums and the log-ratio are float64 in every mode. */
+ * propagation) run on the bf16 matrix cores with float32 accumulation, each operand split
+ * into hi + lo bfloat16 terms (round to nearest even; 16 significant bits) and the three
+ * partial products hi*hi, hi*lo, lo*hi accumulated (relative error of a product below
+ * 3 * 2^-17); everything else as FP32 (phi stream, Green's-function mixer, slices, the
+ * per-flip update of one- and two-block networks; per-sample gradients run entirely in
+ * float32). Kernel generation, the read-out sums and the log-ratio are float64 in every
+ * mode. */
 typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_prec;
 typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
 
@@ -133,6 +136,12 @@ dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, i
 /* log psi(s'_m)/psi(s) for every listed element, by DN_PATH_ABACUS (background caches,
  * output links and the slice recurrence; clusters must be one site or two sites at
  * distance <= 2, else DN_EUNSUPPORTED) or DN_PATH_FULL (each s' evaluated from scratch).
+ * ABACUS cost per element: networks of one or two blocks do slice-sized work only (the
+ * per-sample links -- output links of every block and, for two blocks, block 2's pivot-0
+ * link from a frequency-domain composite correlation, App. "Efficient construction of
+ * link tensors" -- are built once per sample); deeper networks also propagate each
+ * element's change through the frozen blocks 1 .. L-1 over the whole chain (exact,
+ * O(N d^2) per element).
  * logpsi (nullable) receives log psi(s); logratio [B, M_max] gets 0 beyond n_conn.
  * n_conn and sites are validated on the device (DN_EINVAL for n_conn outside [0, M_max],
  * a site outside [0, N) or a pair repeating a site); the per-sample work list comes back to
@@ -237,11 +246,12 @@ typedef enum {
   DN_K_MIX_TAU = 5,  /* adjoint of the last block's vertex (ABACUS output link) */
   DN_K_MIX_DEEP = 6, /* background propagation of the flips' perturbations (ABACUS) */
   DN_K_SLICE = 7,    /* slice recompute of phi / vertices (ABACUS) */
-  DN_K_TAIL = 8,     /* last block's slice + float64 log-ratio (ABACUS) */
+  DN_K_TAIL = 8,     /* per-flip finish: last block's slice + float64 log-ratio (ABACUS) */
   DN_K_GEN = 9,      /* Hamiltonian connected elements */
   DN_K_ELOC = 10,    /* local energy */
   DN_K_OTHER = 11,   /* planning, fills, read-out finalisation */
-  DN_K_COUNT = 12
+  DN_K_LINK = 12,    /* block 2's pivot-0 link per sample: transforms + frequency contraction (ABACUS, L = 2) */
+  DN_K_COUNT = 13
 } dn_kernel_kind;
 
 /* Per-launch profile of a model's kernels. While enabled, every launch the model makes is

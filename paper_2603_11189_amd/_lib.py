@@ -30,7 +30,7 @@ EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_mo
 RAGGED_MODE = {"eager": 0, "graph": 1}
 PRODUCT_MODE = {"split3": 0, "fp32": 1}
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
-                "eloc", "other")
+                "eloc", "other", "link")
 
 
 class ModelDesc(ctypes.Structure):
@@ -149,6 +149,9 @@ class Model:
         p = params.contiguous()
         assert p.dtype == torch.float64
         _check(lib().dn_model_set_params(self.handle, _ptr(p), int(p.is_cuda), _stream()))
+        # which parameters the library holds (autograd checks it before a backward)
+        self.param_version = getattr(self, "param_version", 0) + 1
+        self.params = p.detach().clone()
 
     def get_taps(self) -> torch.Tensor:
         s = self.shape

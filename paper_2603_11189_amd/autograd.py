@@ -3,7 +3,9 @@
 ``logpsi(model, params, spins)`` returns log psi(s_b) for every sample; its backward returns
 d loss / d params = sum_b (d loss / d log psi_b) * O[b, :], where O are the per-sample
 log-derivatives computed by dn_grad_logpsi (the contraction with the incoming gradient runs
-in the library's kernels). The spins carry no gradient.
+in the library's kernels). The spins carry no gradient. The backward differentiates at the
+parameters its forward saw: if the model has been given other parameters in between, it sets
+the saved ones for the backward and restores the newer ones afterwards.
 """
 from __future__ import annotations
 
@@ -18,14 +20,24 @@ class _LogPsi(torch.autograd.Function):
         model.set_params(params.detach().to(torch.float64))
         out = model.logpsi(spins)
         ctx.model = model
+        ctx.version = model.param_version
+        ctx.params = model.params
         ctx.save_for_backward(spins)
         return out
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
         (spins,) = ctx.saved_tensors
-        _, _, wsum = ctx.model.grad_logpsi(spins, weights=grad_out.detach(), want_grads=False)
-        return wsum, None, None
+        model = ctx.model
+        newer = model.params if model.param_version != ctx.version else None
+        if newer is not None:
+            model.set_params(ctx.params)
+        try:
+            _, _, wsum = model.grad_logpsi(spins, weights=grad_out.detach(), want_grads=False)
+        finally:
+            if newer is not None:
+                model.set_params(newer)
+        return wsum.to(ctx.params.device), None, None
 
 
 def logpsi(model: Model, params: torch.Tensor, spins: torch.Tensor) -> torch.Tensor:

@@ -21,6 +21,7 @@
 #include "kernels.h"
 #include "s4gen.h"
 #include "grad.h"
+#include "link2.h"
 
 using namespace dn;
 
@@ -128,6 +129,12 @@ struct dn_model {
   bool tuned = false;
   double* jac64 = nullptr;
   float* jac32 = nullptr;
+  // pivot-0 link of block 2 (two-block networks): parameter-only spectra for the offsets
+  // [lam_dlo, lam_dlo + lam_nd) (clusters up to two sites apart), float64 and, for float
+  // models, float copies; transform length 2^lam_logn
+  int lam_logn = 0, lam_nd = 0, lam_dlo = 0;
+  double *lamM64r = nullptr, *lamM64i = nullptr;
+  float *lamM32r = nullptr, *lamM32i = nullptr;
   std::vector<void*> owned;
   ~dn_model() {
     if (jac64) (void)hipFree(jac64);
@@ -592,18 +599,165 @@ dn_status logratio_full(dn_model* m, const int8_t* spins, int B, const int32_t* 
   return DN_OK;
 }
 
-// ABACUS: background forward with caches, the adjoint tau of the last block, the slice
-// recompute, the background propagation of each flip's perturbation through blocks
-// 1..L-1, the last block's slice and the float64 log-ratio. With h_offs the flip counts of
-// each chunk are host values; without it every flip launch is sized for Bc * M_max and
-// reads its count from the device work list, so the sequence has no host round trip.
-// The error word ab_err is set for clusters wider than the slice recurrence covers.
+// Parameter-only spectra of block 2's pivot-0 link (two-block networks), float64, and float
+// copies for float models (see lam_param_kernel). Transform length: the power of two >= 2N - 1.
+dn_status build_lam_tables(dn_model* m, hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  if (d.L != 2) return DN_OK;
+  int logn = 1;
+  while ((1 << logn) < 2 * d.N - 1) ++logn;
+  const int nd = lam_nd(d.w_c, 2), n = 1 << logn, nh = n / 2 + 1;
+  const size_t elems = (size_t)nd * nh * m->DP * m->DP;
+  if (!m->lamM64r) {
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, elems * 8) != hipSuccess || hipMalloc(&b, elems * 8) != hipSuccess) {
+      if (a) (void)hipFree(a);
+      return fail(DN_ENOMEM, "hipMalloc failed for the pivot-0 link spectra");
+    }
+    m->owned.push_back(a);
+    m->owned.push_back(b);
+    m->lamM64r = (double*)a;
+    m->lamM64i = (double*)b;
+    if (d.prec != DN_PREC_FP64) {
+      void *c = nullptr, *e = nullptr;
+      if (hipMalloc(&c, elems * 4) != hipSuccess || hipMalloc(&e, elems * 4) != hipSuccess) {
+        if (c) (void)hipFree(c);
+        return fail(DN_ENOMEM, "hipMalloc failed for the pivot-0 link spectra");
+      }
+      m->owned.push_back(c);
+      m->owned.push_back(e);
+      m->lamM32r = (float*)c;
+      m->lamM32i = (float*)e;
+    }
+  }
+  m->lam_logn = logn;
+  m->lam_nd = nd;
+  m->lam_dlo = -(2 * d.w_c + 2);
+  LamParamArgs a{};
+  a.taps = m->t64.taps; a.Pq = m->t64.Pq; a.Ut = m->t64.Ut;
+  a.N = d.N; a.Np = m->Np; a.d = d.d; a.DP = m->DP; a.logn = logn; a.ND = nd; a.dlo = m->lam_dlo;
+  a.periodic = d.bc == DN_BC_PERIODIC; a.Mr = m->lamM64r; a.Mi = m->lamM64i;
+  const int nseq = std::max(1, std::min(m->DP, 4096 >> logn));
+  const size_t lds = ((size_t)2 * nseq * (n + 1) + n) * sizeof(double);
+  {
+    PScope ps(m, DN_K_PREP, st, 5.0 * n * logn * (double)nd * m->DP * m->DP, (double)elems * 16);
+    allow_lds(lam_param_kernel, lds);
+    lam_param_kernel<<<dim3(nd, m->DP), 256, lds, st>>>(a);
+  }
+  HIPCHK(hipGetLastError());
+  if (d.prec != DN_PREC_FP64) {
+    convert_kernel<<<1024, 256, 0, st>>>(m->lamM64r, m->lamM32r, (long)elems);
+    convert_kernel<<<1024, 256, 0, st>>>(m->lamM64i, m->lamM32i, (long)elems);
+    HIPCHK(hipGetLastError());
+  }
+  return DN_OK;
+}
+
+template <typename T> void lam_spectra(const dn_model* m, const T** r, const T** i);
+template <> void lam_spectra<double>(const dn_model* m, const double** r, const double** i) { *r = m->lamM64r; *i = m->lamM64i; }
+template <> void lam_spectra<float>(const dn_model* m, const float** r, const float** i) { *r = m->lamM32r; *i = m->lamM32i; }
+
+// Channels per workgroup of the per-sample transforms: pairs of channels per complex
+// transform, a power of two that keeps the transforms' LDS within 64 KB.
+int lam_chf(int DP, int logn, size_t elem) {
+  const size_t per_pair = (size_t)2 * ((1 << logn) + 1) * elem;
+  int np = 1;
+  while (2 * np <= DP / 2 && (size_t)(2 * np) * per_pair <= 65536) np *= 2;
+  return 2 * np;
+}
+
+// Block 2's pivot-0 link for the background samples of one forward chunk: lam[b][z][delta][c]
+// for delta in [dlo, dlo + ND), in passes that keep the spectra of a pass within ~1 GiB.
+template <typename T, int DP>
+dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam, hipStream_t st) {
+  const dn_model_desc& d = m->desc;
+  const int logn = m->lam_logn, n = 1 << logn, nh = n / 2 + 1;
+  const size_t per = (size_t)(ND + 1) * nh * DP * 2 * sizeof(T);
+  const int Bs_max = (int)std::max<size_t>(64, std::min<size_t>(Bf, ((size_t)1 << 30) / per));
+  void *pxr, *pxi, *pzr, *pzi;
+  const size_t nx = (size_t)nh * Bs_max * DP, nz = (size_t)ND * nx;
+  STCHK(ws_get(m, "lam_Xr", nx * sizeof(T), &pxr));
+  STCHK(ws_get(m, "lam_Xi", nx * sizeof(T), &pxi));
+  STCHK(ws_get(m, "lam_Zr", nz * sizeof(T), &pzr));
+  STCHK(ws_get(m, "lam_Zi", nz * sizeof(T), &pzi));
+  const T *Mr, *Mi;
+  lam_spectra<T>(m, &Mr, &Mi);
+  const int chf = lam_chf(DP, logn, sizeof(T));
+  const size_t lds_t = ((size_t)chf * (n + 1) + n) * sizeof(T);
+  const size_t lds_g = ((size_t)2 * DP * 65 + 2 * DP * DP) * sizeof(T);
+  allow_lds(lam_fwd_kernel<T>, lds_t);
+  allow_lds(lam_inv_kernel<T>, lds_t);
+  allow_lds(lam_gemm_kernel<T, DP>, lds_g);
+  const double dr = d.d, fft = 5.0 * n * logn;  // flops of one complex transform
+  for (int s0 = 0; s0 < Bf; s0 += Bs_max) {
+    const int Bs = std::min(Bs_max, Bf - s0);
+    LamArgs<T> a{};
+    a.N = d.N; a.Np = m->Np; a.DP = DP; a.logn = logn; a.ND = ND; a.periodic = d.bc == DN_BC_PERIODIC;
+    a.di0 = dlo - m->lam_dlo; a.Bc = Bs; a.chf = chf;
+    a.chi1 = chi1 + (long)s0 * DP * m->Np;
+    a.Xr = (T*)pxr; a.Xi = (T*)pxi; a.Mr = Mr; a.Mi = Mi; a.Zr = (T*)pzr; a.Zi = (T*)pzi;
+    a.lam = lam + (long)s0 * d.N * ND * DP;
+    {
+      PScope ps(m, DN_K_LINK, st, Bs * (dr / 2) * fft, (double)Bs * (d.N * dr + 2.0 * nh * dr) * sizeof(T));
+      lam_fwd_kernel<T><<<dim3(Bs, DP / chf), 256, lds_t, st>>>(a);
+    }
+    {
+      PScope ps(m, DN_K_LINK, st, 8.0 * ND * nh * dr * dr * Bs,
+                (double)(2.0 * nh * dr * Bs + 2.0 * ND * nh * dr * dr + 2.0 * ND * nh * dr * Bs) * sizeof(T));
+      lam_gemm_kernel<T, DP><<<dim3(nh, (Bs + 63) / 64), 256, lds_g, st>>>(a);
+    }
+    {
+      PScope ps(m, DN_K_LINK, st, (double)Bs * ND * (dr / 2) * fft,
+                (double)Bs * ND * (2.0 * nh * dr + d.N * dr) * sizeof(T));
+      lam_inv_kernel<T><<<dim3(Bs, ND, DP / chf), 256, lds_t, st>>>(a);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  return DN_OK;
+}
+
+// Persistent launch of the per-flip update of one- and two-block networks.
+template <typename T, int DP, bool TWO>
+dn_status launch_flip12(dn_model* m, const Flip12Args<T>& a, int F, hipStream_t st, int ext) {
+  if (F <= 0) return DN_OK;
+  const size_t lds = (size_t)flip12_lds_elems<DP>(TWO) * sizeof(T);
+  static int per_cu = 0;
+  if (!per_cu) {
+    allow_lds(flip12_kernel<T, DP, TWO>, lds);
+    int n = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, flip12_kernel<T, DP, TWO>, 256, lds));
+    per_cu = std::max(n, 1);
+  }
+  const int grid = (int)std::max<long>(1, std::min<long>((F + 3) / 4, (long)cu_count() * per_cu));
+  const dn_model_desc& d = m->desc;
+  const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;
+  const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
+  // per flip: the slice operands, links and read-out weights it reads (the caches p0 on the
+  // slices, Lam on S_2, T^(1) on S_1, T^(0) at the cluster)
+  const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
+  PScope ps(m, DN_K_TAIL, st, fl * F, by * F);
+  flip12_kernel<T, DP, TWO><<<grid, 256, lds, st>>>(a);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+// ABACUS: background forward with caches, the output links, the slice recompute and the
+// per-flip update, then the float64 log-ratio. With h_offs the flip counts of each chunk are
+// host values; without it every flip launch is sized for Bc * M_max and reads its count from
+// the device work list, so the sequence has no host round trip. The error word ab_err is set
+// for clusters wider than the slice recurrence covers. ext_max: the widest cluster extent in
+// the work list (0 single flips, 2 pairs up to two sites apart).
+//   L <= 2: per-sample output links T^(0), T^(1) and block 2's pivot-0 link Lam, then
+//           flip12_kernel: per-flip work on the slices only (independent of N).
+//   L >= 3: the adjoint tau of the last block, then the exact background propagation of each
+//           flip's perturbation through blocks 1..L-1 (deep_kernel), finished per flip.
 template <typename T, int DP>
 dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* sites, int M_max,
                       const int32_t* offs, const int32_t* cb, const int32_t* cm, const int32_t* h_offs,
-                      double* logpsi, double* logratio, hipStream_t st) {
+                      double* logpsi, double* logratio, int ext_max, hipStream_t st) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
+  const bool shallow = L <= 2;
   // identity map for the background forward
   int32_t *idb, *idm;
   STCHK(identity_map(m, "ab_idb", "ab_idm", B, &idb, &idm, st));
@@ -617,15 +771,19 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
   const Tables<T>& tb = tables_of<T>(m);
   const int Wmax = 2 + 2 * L * wc + 1;
-  // samples per chunk: the flip fields dominate (2 fields of [F][DP][Np])
-  const size_t per_flip = (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T) +
-                          (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
+  const int ND = lam_nd(wc, ext_max), dlo = -(2 * wc + ext_max);
+  // samples per chunk: the flip fields dominate (deep networks: 2 fields of [F][DP][Np])
+  const size_t per_flip = shallow ? (size_t)L * Wmax * DP * sizeof(T) + sizeof(int4)
+                                  : (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T) +
+                                        (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
   const size_t flips_budget = std::max<size_t>(1024, m->flip_budget / per_flip);
-  const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, flips_budget / std::max(M_max, 1)));
+  const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(shallow ? 4096 : 1024, flips_budget / std::max(M_max, 1)));
   // background samples per forward chunk: its caches (a0, chi0, p0 per block, tau and its
-  // mixer input) take (3L + 4) fields per sample; a large chunk keeps the forward launches
-  // wide, the flips then run in chunks of Bc_max samples inside it
-  const size_t per_sample = (size_t)(3 * L + 4) * DP * Np * sizeof(T);
+  // mixer input; two-block networks also T^(0) with its mixer input and Lam) per sample; a
+  // large chunk keeps the forward launches wide, the flips then run in chunks of Bc_max
+  // samples inside it
+  const size_t per_sample = (size_t)(3 * L + 4 + (L == 2 ? 4 : 0)) * DP * Np * sizeof(T) +
+                            (L == 2 ? (size_t)d.N * ND * DP * sizeof(T) : 0);
   const int Bf_max = (int)std::max<size_t>(1, std::min<size_t>(B, ((size_t)6 << 30) / per_sample));
   for (int bf0 = 0; bf0 < B; bf0 += Bf_max) {
   const int Bf = std::min(Bf_max, B - bf0);
@@ -638,15 +796,33 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   STCHK(ws_get(m, "ab_tau", (size_t)2 * fldB * sizeof(T), &ptau));
   T *a0 = (T*)pa, *chi0 = (T*)pc, *p0 = (T*)pp, *tz = (T*)ptz, *tau = (T*)ptau;
   STCHK((forward_chunk<T, DP>(m, spins, idmap, bf0, Bf, Om0 + 2L * bf0, a0, chi0, p0, st)));
-  // tau = G^(L)T D0^(L)T Wk
+  // tau = G^(L)T D0^(L)T Wk; deep networks read out the last block with Wk + tau, and for
+  // shallow ones Wk + tau is the output link of the input (L = 1) or of block 1 (L = 2): the
+  // conv adds Wk
   {
     MixArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = L - 1; a.L = L; a.w_c = wc;
     a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bf; a.chi = chi0 + (long)(L - 1) * fldB; a.out = tz;
     STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bf, st)));
-    // with deep blocks the last one reads out with Wk + tau: the conv adds Wk to tau
     STCHK(launch_conv<T>(m, tz, tau, tb.tapsR + (long)(L - 1) * DP * tap_stride(Np), 2 * Bf, st,
-                         DynRange{nullptr, 0, 0}, L >= 2 ? tb.Wk : nullptr));
+                         DynRange{nullptr, 0, 0}, tb.Wk));
+  }
+  T* T0 = tau;  // output link of the input change
+  T* lam = nullptr;
+  if (L == 2) {
+    // T^(0) = Wk + G^(1)T D0^(1)T T^(1), T^(1) = Wk + tau
+    void *pt0z, *pt0, *plam;
+    STCHK(ws_get(m, "ab_t0z", (size_t)2 * fldB * sizeof(T), &pt0z));
+    STCHK(ws_get(m, "ab_t0", (size_t)2 * fldB * sizeof(T), &pt0));
+    STCHK(ws_get(m, "ab_lam", (size_t)Bf * d.N * ND * DP * sizeof(T), &plam));
+    MixArgs<T> a{};
+    a.tb = tb; a.N = d.N; a.Np = Np; a.l = 0; a.L = L; a.w_c = wc;
+    a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bf; a.chi = chi0; a.X = tau; a.out = (T*)pt0z;
+    STCHK((launch_mix<T, DP, MIX_TAU>(m, a, 2 * Bf, st)));
+    STCHK(launch_conv<T>(m, (T*)pt0z, (T*)pt0, tb.tapsR, 2 * Bf, st, DynRange{nullptr, 0, 0}, tb.Wk));
+    T0 = (T*)pt0;
+    lam = (T*)plam;
+    STCHK((build_lam<T, DP>(m, chi0, Bf, ND, dlo, lam, st)));
   }
   for (int b0 = bf0; b0 < bf0 + Bf; b0 += Bc_max) {
     const int Bc = std::min(Bc_max, bf0 + Bf - b0);
@@ -658,17 +834,14 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
     STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
     const int nt = Np / 64;
-    // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
-    STCHK(ws_get(m, "ab_rho", (size_t)std::max(L - 1, 1) * F * nt * 2 * sizeof(double), &prho));
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
-    double* rho = (double*)prho;
     {
       SliceArgs<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.act = d.act; a.F = F; a.f0 = f0; a.b0 = bf0; a.Bc = Bf; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
-      a.dyn = dyn;
+      a.ext_max = ext_max; a.dyn = dyn;
       const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
       double fl = 0.0;
       for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
@@ -676,41 +849,37 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
       HIPCHK(hipGetLastError());
     }
-    if (L >= 2) {
-      void* psp;
-      STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
-      STCHK(ws_get(m, "ab_w", (size_t)F * DP * Np * sizeof(T), &pw));
-      STCHK(ws_get(m, "ab_spart", (size_t)F * nt * SLICE_WIN * DP * sizeof(T), &psp));
-      T* du = (T*)pdu;
-      T* w = (T*)pw;
-      for (int l = 1; l <= L - 1; ++l) {
-        MixArgs<T> a{};
-        a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
-        a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_blk = 2L * F * nt;
-        a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
-        a.out = du; a.rho = rho; a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom;
-        a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
-        a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
-        a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.slice_part = (T*)psp;
-        const bool first = (l == 1), last = (l == L - 1);
-        if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
-        // l-1 is the 0-based index of block l in the tables
-        a.l = l;
-        dn_status s;
-        s = launch_deep_any<T, DP>(m, a, F, st, Bc, first, last);
-        STCHK(s);
-      }
-    }
-    if (L == 1) {
-      TailArgs<T> a{};
+    if (shallow) {
+      Flip12Args<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
-      a.p0L = p0 + (long)(L - 1) * fldB; a.tau = tau; a.taps1 = tb.taps;
-      a.Om0 = Om0; a.logratio = logratio; a.Wmax = Wmax; a.dyn = dyn;
-      const int WL = 2 * L * wc + 1;
-      PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d, (double)F * (WL * 2 + 1) * d.d * sizeof(T));
-      tail_kernel<T, DP><<<F, 64, 2 * DP * sizeof(T), st>>>(a);
-      HIPCHK(hipGetLastError());
+      a.Wmax = Wmax; a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
+      a.Om0 = Om0; a.logratio = logratio; a.dyn = dyn;
+      if (L == 2) STCHK((launch_flip12<T, DP, true>(m, a, F, st, ext_max)));
+      else STCHK((launch_flip12<T, DP, false>(m, a, F, st, ext_max)));
+      continue;
+    }
+    // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
+    STCHK(ws_get(m, "ab_rho", (size_t)std::max(L - 1, 1) * F * nt * 2 * sizeof(double), &prho));
+    double* rho = (double*)prho;
+    void* psp;
+    STCHK(ws_get(m, "ab_du", (size_t)F * DP * Np * sizeof(T), &pdu));
+    STCHK(ws_get(m, "ab_w", (size_t)F * DP * Np * sizeof(T), &pw));
+    STCHK(ws_get(m, "ab_spart", (size_t)F * nt * SLICE_WIN * DP * sizeof(T), &psp));
+    T* du = (T*)pdu;
+    T* w = (T*)pw;
+    for (int l = 1; l <= L - 1; ++l) {
+      MixArgs<T> a{};
+      a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = wc;
+      a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn; a.rho_blk = 2L * F * nt;
+      a.X = w; a.chi = chi0 + (long)(l - 1) * fldB; a.p0 = p0 + (long)(l - 1) * fldB;
+      a.out = du; a.rho = rho; a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom;
+      a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
+      a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
+      a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.slice_part = (T*)psp;
+      const bool first = (l == 1), last = (l == L - 1);
+      if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
+      STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
     }
   }
   }
@@ -744,7 +913,8 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
   int32_t *offs, *cb, *cm;
   std::vector<int32_t> h_offs;
   STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
-  STCHK((abacus_exec<T, DP>(m, spins, B, sites, M_max, offs, cb, cm, h_offs.data(), logpsi, logratio, st)));
+  const int ext_max = (h_offs[B + 1] & 4) ? 2 : 0;
+  STCHK((abacus_exec<T, DP>(m, spins, B, sites, M_max, offs, cb, cm, h_offs.data(), logpsi, logratio, ext_max, st)));
   return abacus_check(m, st);
 }
 
@@ -1071,7 +1241,9 @@ template <typename T, int DP> struct RunInst {
     }
     int32_t *offs, *cb, *cm;
     STCHK(plan_launch(m, nconn, sites, B, M, 0, &offs, &cb, &cm, std::max(B * M, 1), st));
-    STCHK((abacus_exec<T, DP>(m, in->spins, B, sites, M, offs, cb, cm, nullptr, in->logpsi, (double*)pl, st)));
+    // the J1-J2 generator emits pairs up to two sites apart, the Ising one single flips
+    const int ext_max = in->ham.kind == DN_H_J1J2 ? 2 : 0;
+    STCHK((abacus_exec<T, DP>(m, in->spins, B, sites, M, offs, cb, cm, nullptr, in->logpsi, (double*)pl, ext_max, st)));
     PScope e(m, DN_K_ELOC, st, 3.0 * B * M, (double)B * M * 16.0 + B * 20.0);
     eloc_kernel<<<B, 64, 0, st>>>((double*)pd, (double*)ph, nconn, (double*)pl, M, in->eloc);
     HIPCHK(hipGetLastError());
@@ -1331,6 +1503,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   }
   HIPCHK(hipGetLastError());
   if (d.prec != DN_PREC_FP64) STCHK(convert_tables(m, st));
+  STCHK(build_lam_tables(m, st));
   void* pbad;
   STCHK(ws_get(m, "sp_bad", 4, &pbad));
   fill_kernel<int><<<1, 64, 0, st>>>((int*)pbad, 1, 0);

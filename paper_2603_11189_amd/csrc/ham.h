@@ -98,8 +98,8 @@ __global__ __launch_bounds__(64) void eloc_kernel(const double* __restrict__ hdi
 // validated on the way (the host reads offs[B+1] before any other launch): offs[B+1] gets bit
 // 1 if some n_conn is outside [0, M_max], bit 2 if a listed site is outside the chain (the
 // second site may be -1, and must differ from the first). plan_kernel (one block) counts and
-// scans; plan_fill_kernel (one thread per (sample, slot)) writes the entries and checks the
-// sites.
+// scans; plan_fill_kernel (one thread per (sample, slot)) writes the entries, checks the
+// sites (bit 2 of the error word) and notes whether any cluster has two sites (bit 4).
 __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ n_conn, int B, int M_max,
                                                     int with_base, int32_t* __restrict__ offs) {
   __shared__ int part[1024];
@@ -137,6 +137,7 @@ __global__ void plan_fill_kernel(const int32_t* __restrict__ n_conn, const int32
                                  int N, int M_max, int with_base, int32_t* __restrict__ offs,
                                  int32_t* __restrict__ cb, int32_t* __restrict__ cm) {
   const int S = M_max + with_base;  // slots per sample
+  bool any_pair = false;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)B * S; i += (long)gridDim.x * blockDim.x) {
     const int b = (int)(i / S), slot = (int)(i % S);
     int n = n_conn[b];
@@ -148,8 +149,11 @@ __global__ void plan_fill_kernel(const int32_t* __restrict__ n_conn, const int32
     if (m >= 0) {
       const int j0 = sites[((long)b * M_max + m) * 2], j1 = sites[((long)b * M_max + m) * 2 + 1];
       if (j0 < 0 || j0 >= N || j1 < -1 || j1 >= N || j1 == j0) atomicOr(&offs[B + 1], 2);
+      any_pair = any_pair || j1 >= 0;
     }
   }
+  // bit 4: the list holds two-site clusters (one request per wave)
+  if (__ballot(any_pair) && (threadIdx.x & 63) == 0) atomicOr(&offs[B + 1], 4);
 }
 
 // Probe configurations for launch tuning: spin i = +-1 from the low bit of a 32-bit integer

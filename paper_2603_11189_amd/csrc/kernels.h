@@ -585,9 +585,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 // Modes:
 //   FWD:  X = v, x = chi * q (q = V v cached as p0 when requested), y = h = U x;
 //         out = h (+ phi^(l+1) when injected) as the next mixer input; rho += Wk . h.
-//   TAU:  X = Wk[k] (cfg = 2b + k), x = chi0[b] * (U^T X), y = V^T x  (the adjoint
-//         D0^T of the last block applied to the read-out weights; a conv with reversed
-//         taps then gives tau = G^T D0^T Wk).
+//   TAU:  X = Wk[k] (cfg = 2b + k), or the field X[2b + k] when given, x = chi0[b] * (U^T X),
+//         y = V^T x  (the adjoint D0^T of a block applied to the read-out weights or to the
+//         next block's output link; a conv with reversed taps then gives G^T D0^T X).
 // The per-flip blocks of ABACUS run in deep_kernel.
 enum { MIX_FWD = 0, MIX_TAU = 1 };
 
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(512) void mix_kernel(MixArgs<T> A) {
   const T* M1 = (MODE == MIX_TAU) ? A.tb.Um + (long)l * DP * DP : A.tb.Vt + (long)l * DP * DP;
   const T* M2 = (MODE == MIX_TAU) ? A.tb.Vm + (long)l * DP * DP : A.tb.Ut + (long)l * DP * DP;
   const int s0 = 64 * wave + 4 * j;  // first of this lane's 4 sites
-  const T* X = (MODE == MIX_TAU) ? A.tb.Wk + (long)kk_tau * DP * Np : A.X + fo;
+  const T* X = (MODE == MIX_TAU) ? (A.X ? A.X + fo : A.tb.Wk + (long)kk_tau * DP * Np) : A.X + fo;
   // ---- phase 1
   acc_t acc[MT][4];
 #pragma unroll
@@ -1546,6 +1546,7 @@ template <typename T> struct SliceArgs {
   int4* geom;             // [F]
   int Wmax;
   int* err;               // set to 1 for a cluster the slice recurrence does not cover
+  int ext_max;            // widest cluster extent the launch's links were built for
   DynRange dyn;           // flips counted on the device (nullable)
 };
 
@@ -1579,7 +1580,7 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
       if (ext > 2) ext = -1;
     }
   }
-  if (ext < 0 || (A.periodic && ext + 2 * L * wc + 1 > N)) {
+  if (ext < 0 || ext > A.ext_max || (A.periodic && ext + 2 * L * wc + 1 > N)) {
     if (c == 0) atomicOr(A.err, 1);
     ext = 0;
   }
@@ -1659,94 +1660,6 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
       }
     }
     __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// ABACUS for one-block networks (L = 1), one wave per flip: the block's mixer output on
-// the slice is y_1 = G^(1) e^(0) with e^(0) = -2 s_j E on the cluster; the vertex change
-// e^(1) = U (dchi^(1) * (p0^(1) + V y_1)); dOmega = (Wk + tau) . e^(0) + Wk . e^(1);
-// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64. (Deeper networks finish
-// their flips in last_finish_kernel.)
-template <typename T> struct TailArgs {
-  Tables<T> tb;
-  int N, Np, L, w_c, periodic;
-  int F, f0, b0;
-  CfgMap map;
-  const int8_t* spins;
-  const int4* geom;
-  const T* dchi;        // [F][L][Wmax][DP]
-  const T* p0L;         // [Bc][DP][Np] p0 of the block
-  const T* tau;         // [Bc][2][DP][Np]
-  const T* taps1;       // taps of the block's mixer
-  const double* Om0;    // [B][2] global
-  double* logratio;     // [B][M_max] global
-  int Wmax;
-  DynRange dyn;         // flips counted on the device (nullable)
-};
-
-template <typename T, int DP>
-__global__ __launch_bounds__(64) void tail_kernel(TailArgs<T> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* ys = reinterpret_cast<T*>(smem_raw);  // [DP]
-  T* xs = ys + DP;                          // [DP]
-  const int f = blockIdx.x, c = threadIdx.x;
-  const bool on = c < DP;                   // lanes c >= DP contribute zeros
-  const int N = A.N, Np = A.Np, L = A.L, wc = A.w_c;
-  if (f >= A.dyn.count(A.F)) return;
-  const int f0 = A.dyn.first(A.f0);
-  const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
-  const int bl = b - A.b0;
-  const int4 gm = A.geom[f];
-  const int8_t* sp = A.spins + (long)b * N;
-  auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
-  auto inside = [&](int i) { return A.periodic || (i >= 0 && i < N); };
-  const long DPNp = (long)DP * Np;
-  double o0 = 0.0, o1 = 0.0;
-  // e^(0) read-out (and tau . e^(0) when the cluster feeds the last block directly)
-  for (int q = 0; q < 2 && on; ++q) {
-    const int j = q == 0 ? gm.z : gm.w;
-    if (j < 0) continue;
-    const T e0 = (T)(-2 * sp[j]) * A.tb.E[c];
-    const T w0 = A.tb.Wk[(long)c * Np + j] + A.tau[(2L * bl) * DPNp + (long)c * Np + j];
-    const T w1 = A.tb.Wk[DPNp + (long)c * Np + j] + A.tau[(2L * bl + 1) * DPNp + (long)c * Np + j];
-    o0 += (double)w0 * (double)e0;
-    o1 += (double)w1 * (double)e0;
-  }
-  const int lo = gm.x - L * wc, WL = gm.y + 2 * L * wc + 1;
-  const T* Vt = A.tb.Vt + (long)(L - 1) * DP * DP;
-  const T* Ut = A.tb.Ut + (long)(L - 1) * DP * DP;
-  const T* dchi = A.dchi + ((long)f * L + (L - 1)) * A.Wmax * DP;
-  for (int t = 0; t < WL; ++t) {
-    const int ii = lo + t;
-    if (!inside(ii)) continue;  // uniform across the wave
-    const int site = wrap(ii);
-    if (on) {
-      const T* t1 = A.taps1 + (long)c * tap_stride(Np) + tap_off(Np);
-      T y = t1[site - gm.z] * (T)(-2 * sp[gm.z]) * A.tb.E[c];
-      if (gm.w >= 0) y += t1[site - gm.w] * (T)(-2 * sp[gm.w]) * A.tb.E[c];
-      ys[c] = y;
-    }
-    __syncthreads();
-    if (on) {
-      T q = 0;
-      for (int k = 0; k < DP; ++k) q += Vt[k * DP + c] * ys[k];
-      xs[c] = dchi[t * DP + c] * (A.p0L[(long)bl * DPNp + (long)c * Np + site] + q);
-    }
-    __syncthreads();
-    if (on) {
-      T e = 0;
-      for (int k = 0; k < DP; ++k) e += Ut[k * DP + c] * xs[k];
-      o0 += (double)A.tb.Wk[(long)c * Np + site] * (double)e;
-      o1 += (double)A.tb.Wk[DPNp + (long)c * Np + site] * (double)e;
-    }
-    __syncthreads();
-  }
-  o0 = wave_sum(o0);
-  o1 = wave_sum(o1);
-  if (c == 0) {
-    const double a0 = A.Om0[2 * b], a1 = A.Om0[2 * b + 1];
-    A.logratio[(long)b * A.map.M_max + m] = lcd_d(a0, o0) + lcd_d(a1, o1);
   }
 }
 

@@ -77,6 +77,24 @@ def test_weighted_sum_and_autograd(L):
     assert torch.allclose(p.grad, ws, rtol=1e-12, atol=1e-14)
 
 
+def test_autograd_backward_uses_forward_params(L):
+    """A forward at parameters A, then new parameters B given to the model, then the backward
+    of the first forward: the gradient is the one at A, and the model holds B afterwards."""
+    from paper_2603_11189_amd.autograd import logpsi as lp_fn
+    shape = di.ModelShape(16, 2, 8, 4, act="silu", bc="open")
+    thA = torch.tensor(di.draw_params(shape, 3, "stress"))
+    thB = torch.tensor(di.draw_params(shape, 4, "stress"))
+    m = L.Model(shape, "fp64")
+    sp = torch.tensor(di.uniform_spins(5, 16, 2), device="cuda")
+    pA = thA.clone().cuda().requires_grad_(True)
+    outA = lp_fn(m, pA, sp)
+    lpB = lp_fn(m, thB.clone().cuda(), sp).detach()
+    outA.sum().backward()
+    ref = grad_logpsi_batched(ModelDesc.of(shape), thA, sp.cpu().numpy()).sum(0)
+    assert torch.allclose(pA.grad.cpu(), ref, rtol=1e-10, atol=1e-12)
+    assert torch.allclose(m.logpsi(sp), lpB, rtol=0, atol=0)
+
+
 def test_grad_rejects_periodic(L):
     shape = di.ModelShape(12, 1, 4, 2, bc="periodic")
     m = L.Model(shape, "fp64")
