@@ -126,6 +126,18 @@ dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream);
  * stream. */
 dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
 
+/* dn_logpsi for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight sampling or serving loops, harnesses that forbid hipMalloc. The same values as
+ * dn_logpsi (the same kernels), but every buffer beyond the caller's inputs and outputs --
+ * the forward's fields, its work list and read-out sums -- lives in one file-scope device
+ * array of 32 MiB (each GPU the library runs on holds its own copy until the process ends);
+ * the call allocates and frees nothing. B is processed in chunks that fit the array; a
+ * shape whose single configuration needs more than the array holds gets DN_EUNSUPPORTED
+ * (none the library supports does: at most 1.3 MiB). The array keeps the last call's
+ * contents, and calls that overlap on one GPU (several streams or host threads) race on
+ * it: serialise them. No profiling events are recorded. */
+dn_status dn_logpsi_noalloc(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
+
 /* Connected configurations, matrix elements and diagonal energies of H for B samples.
  * M_max must be >= N (Ising) or >= 2N (J1-J2). Outputs: sites [B,M_max,2] (unused rows
  * set to -1), helem [B,M_max] (0 beyond n_conn), n_conn [B], hdiag [B]. */

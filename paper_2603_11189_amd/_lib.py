@@ -23,7 +23,7 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
-           "dn_model_get_taps", "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy",
+           "dn_model_get_taps", "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
            "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
            "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
@@ -68,6 +68,7 @@ def lib():
         L.dn_model_set_params.argtypes = [vp, vp, ctypes.c_int, vp]
         L.dn_model_get_taps.argtypes = [vp, vp, vp]
         L.dn_logpsi.argtypes = [vp, vp, i32, vp, vp]
+        L.dn_logpsi_noalloc.argtypes = [vp, vp, i32, vp, vp]
         L.dn_connected.argtypes = [ctypes.POINTER(HamDesc), vp, i32, i32, i32, vp, vp, vp, vp, vp]
         L.dn_logratio.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp]
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
@@ -85,7 +86,7 @@ def lib():
         L.dn_model_destroy.argtypes = [vp]
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
-                   "dn_logpsi", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
+                   "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
                    "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
                    "dn_ragged_eloc", "dn_profile_enable",
                    "dn_profile_read"):
@@ -163,6 +164,15 @@ class Model:
         B = spins.shape[0]
         out = torch.empty(B, dtype=torch.float64, device=spins.device)
         _check(lib().dn_logpsi(self.handle, _ptr(spins), B, _ptr(out), _stream()))
+        return out
+
+    def logpsi_noalloc(self, spins: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """dn_logpsi_noalloc: log psi with the library's scratch array (no device allocation
+        inside the call; `out` may be given to avoid torch's own allocation too)."""
+        B = spins.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=spins.device)
+        _check(lib().dn_logpsi_noalloc(self.handle, _ptr(spins), B, _ptr(out), _stream()))
         return out
 
     def logratio(self, spins, sites, n_conn, path: str = "abacus", want_logpsi: bool = True):

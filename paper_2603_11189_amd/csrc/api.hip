@@ -30,6 +30,8 @@ namespace {
 thread_local std::string g_err = "no error";
 // true while this thread records launches into a graph (profiling events are skipped)
 thread_local bool g_capturing = false;
+// true while this thread runs the entry point that allocates nothing (no profiling events)
+thread_local bool g_noalloc = false;
 std::atomic<uint64_t> g_next_uid{1};
 
 dn_status fail(dn_status st, const std::string& msg) {
@@ -184,7 +186,7 @@ struct PScope {
   double fl, by;
   hipEvent_t a = nullptr;
   PScope(dn_model* m_, int k, hipStream_t s, double f, double b) : m(m_), kind(k), st(s), fl(f), by(b) {
-    if (m && m->prof.on && !g_capturing) { a = prof_event(m); (void)hipEventRecord(a, st); }
+    if (m && m->prof.on && !g_capturing && !g_noalloc) { a = prof_event(m); (void)hipEventRecord(a, st); }
   }
   ~PScope() {
     if (a) {
@@ -474,18 +476,24 @@ template <typename T> struct Ckpt {
   T *h = nullptr, *phi = nullptr, *R = nullptr;
 };
 
+// fields: nullable; five [C][DP][Np] fields the caller provides (otherwise the workspace's).
 template <typename T, int DP>
 dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, int C, double* rho,
-                        T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st, Ckpt<T> ck = Ckpt<T>()) {
+                        T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st, Ckpt<T> ck = Ckpt<T>(),
+                        T* fields = nullptr) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L;
   const long fld = (long)C * DP * Np;
   void *pphi, *pchi0, *pchi1, *pu, *pv;
-  STCHK(ws_get(m, "fw_phi", fld * sizeof(T), &pphi));
-  STCHK(ws_get(m, "fw_chi0", fld * sizeof(T), &pchi0));
-  STCHK(ws_get(m, "fw_chi1", fld * sizeof(T), &pchi1));
-  STCHK(ws_get(m, "fw_u", fld * sizeof(T), &pu));
-  STCHK(ws_get(m, "fw_v", fld * sizeof(T), &pv));
+  if (fields) {
+    pphi = fields; pchi0 = fields + fld; pchi1 = fields + 2 * fld; pu = fields + 3 * fld; pv = fields + 4 * fld;
+  } else {
+    STCHK(ws_get(m, "fw_phi", fld * sizeof(T), &pphi));
+    STCHK(ws_get(m, "fw_chi0", fld * sizeof(T), &pchi0));
+    STCHK(ws_get(m, "fw_chi1", fld * sizeof(T), &pchi1));
+    STCHK(ws_get(m, "fw_u", fld * sizeof(T), &pu));
+    STCHK(ws_get(m, "fw_v", fld * sizeof(T), &pv));
+  }
   T* phi = (T*)pphi;
   T* chib[2] = {(T*)pchi0, (T*)pchi1};
   T* u = (T*)pu;
@@ -1163,6 +1171,67 @@ template <typename T, int DP> struct RunAbacus {
     return logratio_abacus<T, DP>(m, s, B, si, nc, M, lp, lr, st);
   }
 };
+// ------------------------------------------------------------------------------------------
+// Entry point that allocates nothing: log psi with its forward fields, work list and read-out
+// sums in a file-scope device array. Each GPU holds its own copy for the life of the process;
+// host code uses the address hipGetSymbolAddress reports for the current device, never the
+// array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's scratch address, taken once per device with that device current.
+dn_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DN_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DN_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DN_OK;
+}
+
+// Bytes of scratch one configuration of this model needs: the five forward fields, its
+// work-list entry and its two read-out sums.
+size_t noalloc_bytes_per_config(const dn_model* m) {
+  const size_t elem = m->desc.prec == DN_PREC_FP64 ? 8 : 4;
+  return 5 * (size_t)m->DP * m->Np * elem + 2 * sizeof(int32_t) + 2 * sizeof(double);
+}
+
+// log psi of B configurations in chunks that fit the scratch array (layout per chunk of C:
+// fields [5][C][DP][Np], read-out sums [C][2] float64, work list cb [C], cm [C]).
+template <typename T, int DP> struct RunLogpsiNoAlloc {
+  static dn_status run(dn_model* m, const int8_t* spins, int B, double* logpsi, hipStream_t st) {
+    void* base;
+    STCHK(scratch_address(&base));
+    const int C_max = (int)std::min<size_t>(B, NOALLOC_SCRATCH_BYTES / noalloc_bytes_per_config(m));
+    const long fld = (long)C_max * DP * m->Np;
+    T* fields = (T*)base;
+    double* rho = (double*)(fields + 5 * fld);
+    int32_t* cb = (int32_t*)(rho + 2L * C_max);
+    int32_t* cm = cb + C_max;
+    for (int c0 = 0; c0 < B; c0 += C_max) {
+      const int C = std::min(C_max, B - c0);
+      identity_map_kernel<<<(C + 255) / 256, 256, 0, st>>>(cb, cm, C);
+      CfgMap idmap{cb, cm, nullptr, 0};
+      STCHK((forward_chunk<T, DP>(m, spins + (long)c0 * m->desc.N, idmap, 0, C, rho, nullptr, nullptr, nullptr, st,
+                                  Ckpt<T>(), fields)));
+      logpsi_kernel<<<(C + 255) / 256, 256, 0, st>>>(rho, nullptr, C, logpsi + c0);
+      HIPCHK(hipGetLastError());
+    }
+    return DN_OK;
+  }
+};
+
 template <typename T, int DP> struct RunLogpsi {
   static dn_status run(dn_model* m, const int8_t* s, int B, double* lp, hipStream_t st) {
     return logpsi_only<T, DP>(m, s, B, lp, st);
@@ -1533,6 +1602,22 @@ dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi,
   if (B == 0) return DN_OK;
   if (!spins || !logpsi) return fail(DN_EINVAL, "null argument");
   return dispatch<RunLogpsi>(m, spins, (int)B, logpsi, (hipStream_t)stream);
+}
+
+dn_status dn_logpsi_noalloc(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0) return fail(DN_EINVAL, "B < 0");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if (B == 0) return DN_OK;
+  if (!spins || !logpsi) return fail(DN_EINVAL, "null argument");
+  const size_t per = noalloc_bytes_per_config(m);
+  if (per > NOALLOC_SCRATCH_BYTES)
+    return fail(DN_EUNSUPPORTED, "one configuration needs " + std::to_string(per) + " bytes of scratch; the array holds " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES));
+  g_noalloc = true;
+  const dn_status st = dispatch<RunLogpsiNoAlloc>(m, spins, (int)B, logpsi, (hipStream_t)stream);
+  g_noalloc = false;
+  return st;
 }
 
 dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, int32_t N, int32_t M_max,
