@@ -126,6 +126,26 @@ dn_status dn_model_get_taps(dn_model* m, double* taps_out, void* stream);
  * stream. */
 dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream);
 
+/* One half-sweep of the screened typewriter Metropolis sampler over B independent chains
+ * (Sec. IV, Algorithm 2; App. "Screened Metropolis sampler is exact"; App. "Practical
+ * implementation of the screened typewriter sampler"). The chain is cut into blocks of
+ * `spacing` sites; the visited blocks are b = parity, parity + 2, ... (K = (ceil(N / spacing)
+ * - parity + 1) / 2 of them, in that order) and block b proposes flipping site
+ * b*spacing + floor(r * width), width = min(spacing, N - b*spacing). The proposals' output changes
+ * come from ABACUS against one background; proposal k is judged with the independent-scattering
+ * ratio R~ = prod_units cosh^2(Omega + dOmega_k) / cosh^2(Omega), Omega accumulating the
+ * accepted changes. A draw with |u - min(1, R~)| <= eps freezes the chain there: its background
+ * is rebuilt at its current configuration and the remaining proposals recomputed, the frozen
+ * one then decided with its exact ratio; otherwise accept iff u < min(1, R~). When eps bounds
+ * |R~ - R| the decisions are exact Metropolis-Hastings decisions for the same draws.
+ * spins: device int8 [B][N], updated in place. r_site, u: device float64 [B][K] (uniform draws
+ * in [0, 1), supplied by the caller). accepted: device int32 [B][K] (1 = accepted); refreshes:
+ * device int32 [B] (background rebuilds per chain). The sampler's ABACUS uses the model's
+ * workspace; one host synchronisation per refresh round. Requirements as for DN_PATH_ABACUS. */
+dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spacing, int32_t parity,
+                            const double* r_site, const double* u, double eps, int32_t* accepted,
+                            int32_t* refreshes, void* stream);
+
 /* dn_logpsi for callers that cannot allocate device memory: code under HIP graph capture,
  * tight sampling or serving loops, harnesses that forbid hipMalloc. The same values as
  * dn_logpsi (the same kernels), but every buffer beyond the caller's inputs and outputs --

@@ -25,7 +25,7 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
            "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-           "dn_ragged_eloc", "dn_profile_enable", "dn_profile_read",
+           "dn_ragged_eloc", "dn_screened_sweep", "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
 RAGGED_MODE = {"eager": 0, "graph": 1}
 PRODUCT_MODE = {"split3": 0, "fp32": 1}
@@ -79,6 +79,7 @@ def lib():
         L.dn_set_product_mode.argtypes = [vp, i32]
         L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
+        L.dn_screened_sweep.argtypes = [vp, vp, i32, i32, i32, vp, vp, ctypes.c_double, vp, vp, vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dn_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -88,7 +89,7 @@ def lib():
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
                    "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-                   "dn_ragged_eloc", "dn_profile_enable",
+                   "dn_ragged_eloc", "dn_screened_sweep", "dn_profile_enable",
                    "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -207,6 +208,21 @@ class Model:
         w = weights.to(torch.float64).contiguous() if weights is not None else None
         _check(lib().dn_grad_logpsi(self.handle, _ptr(spins), B, _ptr(lp), _ptr(g), _ptr(w), _ptr(ws), _stream()))
         return lp, g, ws
+
+    def screened_sweep(self, spins: torch.Tensor, spacing: int, parity: int, r_site: torch.Tensor,
+                       u: torch.Tensor, eps: float):
+        """One half-sweep of the screened typewriter sampler (dn_screened_sweep); spins are updated
+        in place. Returns (accepted int32 [B, K], refreshes int32 [B])."""
+        B, N = spins.shape
+        K = ((N + spacing - 1) // spacing - parity + 1) // 2
+        acc = torch.zeros((B, K), dtype=torch.int32, device=spins.device)
+        ref = torch.zeros(B, dtype=torch.int32, device=spins.device)
+        r = r_site.to(torch.float64).contiguous()
+        uu = u.to(torch.float64).contiguous()
+        assert r.shape == (B, K) and uu.shape == (B, K)
+        _check(lib().dn_screened_sweep(self.handle, _ptr(spins), B, spacing, parity, _ptr(r), _ptr(uu), eps,
+                                       _ptr(acc), _ptr(ref), _stream()))
+        return acc, ref
 
     def autotune(self, ham, B_probe: int = 256):
         """Pick this model's launch shapes by timing; returns (conv_nt, flip_budget_bytes)."""

@@ -22,6 +22,7 @@
 #include "s4gen.h"
 #include "grad.h"
 #include "link2.h"
+#include "sampler.h"
 
 using namespace dn;
 
@@ -726,17 +727,21 @@ dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam,
 
 // Persistent launch of the per-flip update of one- and two-block networks.
 template <typename T, int DP, bool TWO>
-dn_status launch_flip12(dn_model* m, const Flip12Args<T>& a, int F, hipStream_t st, int ext) {
+dn_status launch_flip12(dn_model* m, Flip12Args<T> a, int F, hipStream_t st, int ext) {
   if (F <= 0) return DN_OK;
-  const size_t lds = (size_t)flip12_lds_elems<DP>(TWO) * sizeof(T);
+  const size_t lds = flip12_lds_bytes<T, DP>(TWO);
+  constexpr int NW = flip12_waves<T>();
   static int per_cu = 0;
   if (!per_cu) {
     allow_lds(flip12_kernel<T, DP, TWO>, lds);
     int n = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, flip12_kernel<T, DP, TWO>, 256, lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, flip12_kernel<T, DP, TWO>, 64 * NW, lds));
     per_cu = std::max(n, 1);
   }
-  const int grid = (int)std::max<long>(1, std::min<long>((F + 3) / 4, (long)cu_count() * per_cu));
+  // matrix-core columns per flip: the widest last slice of the launch
+  a.colw = ext + 2 * (TWO ? 2 : 1) * m->desc.w_c + 1;
+  const int P = 16 / a.colw;
+  const int grid = (int)std::max<long>(1, std::min<long>((F + NW * P - 1) / (NW * P), (long)cu_count() * per_cu));
   const dn_model_desc& d = m->desc;
   const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;
   const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
@@ -744,7 +749,7 @@ dn_status launch_flip12(dn_model* m, const Flip12Args<T>& a, int F, hipStream_t 
   // slices, Lam on S_2, T^(1) on S_1, T^(0) at the cluster)
   const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
   PScope ps(m, DN_K_TAIL, st, fl * F, by * F);
-  flip12_kernel<T, DP, TWO><<<grid, 256, lds, st>>>(a);
+  flip12_kernel<T, DP, TWO><<<grid, 64 * NW, lds, st>>>(a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -762,7 +767,7 @@ dn_status launch_flip12(dn_model* m, const Flip12Args<T>& a, int F, hipStream_t 
 template <typename T, int DP>
 dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* sites, int M_max,
                       const int32_t* offs, const int32_t* cb, const int32_t* cm, const int32_t* h_offs,
-                      double* logpsi, double* logratio, int ext_max, hipStream_t st) {
+                      double* logpsi, double* logratio, int ext_max, hipStream_t st, double* dom = nullptr) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
   const bool shallow = L <= 2;
@@ -862,7 +867,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
       a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
       a.Wmax = Wmax; a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
-      a.Om0 = Om0; a.logratio = logratio; a.dyn = dyn;
+      a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.dyn = dyn;
       if (L == 2) STCHK((launch_flip12<T, DP, true>(m, a, F, st, ext_max)));
       else STCHK((launch_flip12<T, DP, false>(m, a, F, st, ext_max)));
       continue;
@@ -884,7 +889,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.out = du; a.rho = rho; a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom;
       a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
       a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
-      a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.slice_part = (T*)psp;
+      a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.slice_part = (T*)psp;
       const bool first = (l == 1), last = (l == L - 1);
       if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
@@ -1165,6 +1170,55 @@ template <typename T, int DP> struct RunFull {
     return logratio_full<T, DP>(m, s, B, si, nc, M, lp, lr, st);
   }
 };
+// One half-sweep of the screened typewriter sampler over B chains (see sampler.h): rounds of
+// (background + ABACUS changes of every chain's remaining proposals, sequential screened
+// acceptance per chain) until no chain froze; one host synchronisation per round.
+template <typename T, int DP> struct RunSweep {
+  static dn_status run(dn_model* m, int8_t* spins, int B, int spacing, int parity, const double* r_site,
+                       const double* u, double eps, int32_t* accepted, int32_t* refreshes, hipStream_t st) {
+    const int N = m->desc.N;
+    const int nblk = (N + spacing - 1) / spacing;
+    const int K = (nblk - parity + 1) / 2;
+    if (K <= 0) return DN_OK;
+    void *psi, *psr, *pnc, *pks, *ppe, *pfr, *plr, *pdom;
+    STCHK(ws_get(m, "sw_sites", (size_t)B * K * 2 * 4, &psi));
+    STCHK(ws_get(m, "sw_sites_r", (size_t)B * K * 2 * 4, &psr));
+    STCHK(ws_get(m, "sw_nconn", (size_t)B * 4, &pnc));
+    STCHK(ws_get(m, "sw_kstart", (size_t)B * 4, &pks));
+    STCHK(ws_get(m, "sw_pending", (size_t)B * 4, &ppe));
+    STCHK(ws_get(m, "sw_frozen", 4, &pfr));
+    STCHK(ws_get(m, "sw_lr", (size_t)B * K * 8, &plr));
+    STCHK(ws_get(m, "sw_dom", (size_t)B * K * 2 * 8, &pdom));
+    SweepArgs a{};
+    a.B = B; a.N = N; a.K = K; a.spacing = spacing; a.parity = parity; a.eps = eps; a.r_site = r_site; a.u = u;
+    a.spins = spins; a.sites = (int32_t*)psi; a.sites_r = (int32_t*)psr; a.n_conn = (int32_t*)pnc;
+    a.kstart = (int32_t*)pks; a.pending = (int32_t*)ppe; a.accepted = accepted; a.refreshes = refreshes;
+    a.frozen = (int32_t*)pfr; a.dom = (double*)pdom;
+    const int gs = (int)std::min<long>(4096, ((long)B * K + 255) / 256);
+    sweep_init_kernel<<<gs, 256, 0, st>>>(a);
+    HIPCHK(hipGetLastError());
+    for (int round = 0;; ++round) {
+      sweep_round_kernel<<<gs, 256, 0, st>>>(a);
+      HIPCHK(hipGetLastError());
+      int32_t *offs, *cb, *cm;
+      std::vector<int32_t> h_offs;
+      STCHK(plan(m, a.n_conn, a.sites_r, B, K, 0, &offs, &cb, &cm, std::max(B * K, 1), &h_offs, st));
+      STCHK((abacus_exec<T, DP>(m, spins, B, a.sites_r, K, offs, cb, cm, h_offs.data(), nullptr, (double*)plr, 0, st,
+                                (double*)pdom)));
+      void* pOm;
+      STCHK(ws_get(m, "ab_Om0", (size_t)B * 2 * sizeof(double), &pOm));
+      a.Om0 = (const double*)pOm;
+      sweep_accept_kernel<<<(B + 255) / 256, 256, 0, st>>>(a);
+      HIPCHK(hipGetLastError());
+      int frozen = 0;
+      HIPCHK(hipMemcpyAsync(&frozen, a.frozen, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (!frozen) break;
+    }
+    return abacus_check(m, st);
+  }
+};
+
 template <typename T, int DP> struct RunAbacus {
   static dn_status run(dn_model* m, const int8_t* s, int B, const int32_t* si, const int32_t* nc, int M,
                        double* lp, double* lr, hipStream_t st) {
@@ -1602,6 +1656,19 @@ dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi,
   if (B == 0) return DN_OK;
   if (!spins || !logpsi) return fail(DN_EINVAL, "null argument");
   return dispatch<RunLogpsi>(m, spins, (int)B, logpsi, (hipStream_t)stream);
+}
+
+dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spacing, int32_t parity, const double* r_site,
+                            const double* u, double eps, int32_t* accepted, int32_t* refreshes, void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0 || spacing < 1 || (parity != 0 && parity != 1) || !(eps >= 0.0))
+    return fail(DN_EINVAL, "bad B, spacing, parity or eps");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if (B == 0) return DN_OK;
+  if (!spins || !r_site || !u || !accepted || !refreshes) return fail(DN_EINVAL, "null argument");
+  STCHK(abacus_supported(m));
+  return dispatch<RunSweep>(m, spins, (int)B, (int)spacing, (int)parity, r_site, u, eps, accepted, refreshes,
+                            (hipStream_t)stream);
 }
 
 dn_status dn_logpsi_noalloc(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream) {

@@ -618,6 +618,7 @@ template <typename T> struct MixArgs {
   const T* p0L;          // last block: V v0 of block L [Bc][DP][Np]
   const double* Om0;     // last block: [B][2]
   double* logratio;      // last block: [B][M_max]
+  double* dom;           // last block, nullable: [B][M_max][2] the output changes dOmega
   DynRange dyn;          // flips counted on the device (nullable)
   T* slice_part;         // last block: [F][Np/64][SLICE_WIN][DP] partial slices
 };
@@ -1525,8 +1526,11 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   }
   o0 = wave_sum(o0);
   o1 = wave_sum(o1);
-  if (lane == 0)
-    A.logratio[(long)bg * A.map.M_max + m] = lcd_d(A.Om0[2 * bg], o0) + lcd_d(A.Om0[2 * bg + 1], o1);
+  if (lane == 0) {
+    const long o = (long)bg * A.map.M_max + m;
+    A.logratio[o] = lcd_d(A.Om0[2 * bg], o0) + lcd_d(A.Om0[2 * bg + 1], o1);
+    if (A.dom) { A.dom[2 * o] = o0; A.dom[2 * o + 1] = o1; }
+  }
 }
 
 // ---------------------------------------------------------------------------------------

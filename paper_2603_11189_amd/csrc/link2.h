@@ -294,6 +294,7 @@ template <typename T> struct Flip12Args {
   const int4* geom;     // [F] (clo, ext, j0, j1) from slice_kernel
   const T* dchi;        // [F][L][Wmax][DP]
   int Wmax;
+  int colw;             // matrix-core columns per flip (the widest last slice); 16 / colw flips per step
   const T* p0;          // [L][Bf][DP][Np]: V v0 of every block
   long fldB;            // Bf DP Np
   const T* T0;          // [Bf][2][DP][Np]: output link of the input change (h^(0))
@@ -302,28 +303,35 @@ template <typename T> struct Flip12Args {
   int ND, dlo;
   const double* Om0;    // [B][2]
   double* logratio;     // [B][M_max]
+  double* dom;          // nullable: [B][M_max][2] the output changes dOmega themselves
   DynRange dyn;
 };
 
-template <int DP> constexpr int flip12_lds_elems(bool two) { return (two ? 3 : 1) * DP * DP + (two ? 4 * DP * 17 : 0); }
+// waves per workgroup (they share one copy of the weight operands in LDS)
+template <typename T> constexpr int flip12_waves() { return sizeof(T) == 4 ? 8 : 4; }
+template <typename T, int DP> constexpr size_t flip12_lds_bytes(bool two) {
+  return ((two ? 3 : 1) * DP * DP + (two ? flip12_waves<T>() * DP * 17 : 0)) * sizeof(T) +
+         (size_t)flip12_waves<T>() * 32 * sizeof(double);
+}
 
-// Persistent workgroups of four waves; the weight operands live in LDS in fragment order, each
-// wave takes one flip at a time. The matrix-core columns are the slice positions (<= 16).
+// Persistent workgroups; the weight operands live in LDS in fragment order. A wave takes
+// 16 / colw flips at a time: flip p of the step owns matrix-core columns p colw .. p colw +
+// colw - 1, column t of them being slice position t, so one product serves several flips.
 template <typename T, int DP, bool TWO>
-__global__ __launch_bounds__(256) void flip12_kernel(Flip12Args<T> A) {
+__global__ __launch_bounds__(64 * flip12_waves<T>()) void flip12_kernel(Flip12Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  constexpr int MT = DP / 16, KS = DP / 4;
+  constexpr int MT = DP / 16, KS = DP / 4, NW = flip12_waves<T>();
   T* FU1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of U^(1)
   T* FV2 = FU1 + DP * DP;                   // [KS][64][MT]: operand A of V^(2)
   T* FU2 = FV2 + DP * DP;                   // [MT][MT][64][4]: U^(2) in accumulator channel order
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
-  T* E1s = FU2 + DP * DP + wave * DP * 17;  // [DP][17]: this wave's e1 on S_1
-  const T* Ut1 = A.tb.Ut;
+  T* E1s = FU1 + (TWO ? 3 : 1) * DP * DP + wave * DP * 17;  // [DP][17]: this wave's e1 (TWO)
+  double* red = reinterpret_cast<double*>(FU1 + (TWO ? 3 * DP * DP + NW * DP * 17 : DP * DP)) + wave * 32;
   for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
     const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
-    FU1[idx] = Ut1[(4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
+    FU1[idx] = A.tb.Ut[(4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
     if constexpr (TWO) {
       FV2[idx] = A.tb.Vt[(long)DP * DP + (4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
       const int r = idx & 3, l2 = (idx >> 2) & 63, mi = (idx >> 8) % MT, mo = (idx >> 8) / MT;
@@ -335,55 +343,65 @@ __global__ __launch_bounds__(256) void flip12_kernel(Flip12Args<T> A) {
   const int TS = tap_stride(Np), TO = tap_off(Np);
   const int F = A.dyn.count(A.F);
   const int cfg0 = A.dyn.first(A.f0);
+  const int W = A.colw, P = 16 / W;
+  const int p = j / W, t = j - p * W;  // this lane's flip slot and slice position
   auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
-  for (int g = blockIdx.x * 4 + wave; g < F; g += gridDim.x * 4) {
-    const int4 sg = A.geom[g];
-    const int bglob = A.map.cb[cfg0 + g], m = A.map.cm[cfg0 + g];
-    const int bl = bglob - A.b0;
+  for (int gb = (blockIdx.x * NW + wave) * P; gb < F; gb += gridDim.x * NW * P) {
+    const int g = gb + p;
+    const bool have = p < P && g < F;
+    int4 sg = make_int4(0, 0, 0, -1);
+    int bglob = 0, bl = 0;
+    if (have) {
+      sg = A.geom[g];
+      bglob = A.map.cb[cfg0 + g];
+      bl = bglob - A.b0;
+    }
     const int8_t* sp = A.spins + (long)bglob * N;
     // cluster sites (unwrapped): za = clo, zb = clo + ext for a pair
     const int za = sg.x, zb = sg.x + sg.y;
     const bool pair = sg.w >= 0;
-    const T ca = (T)(-2 * sp[za]);
-    const T cb = pair ? (T)(-2 * sp[wrap(zb)]) : T(0);
-    // ---- block 1 on S_1 (column j = slice position)
+    const T ca = have ? (T)(-2 * sp[za]) : T(0);
+    const T cb = have && pair ? (T)(-2 * sp[wrap(zb)]) : T(0);
+    // ---- block 1 on S_1
     const int lo1 = sg.x - wc, W1 = sg.y + 2 * wc + 1;
-    const int s1u = lo1 + j;
-    const bool v1 = j < W1 && (A.periodic || (s1u >= 0 && s1u < N));
+    const int s1u = lo1 + t;
+    const bool v1 = have && t < W1 && (A.periodic || (s1u >= 0 && s1u < N));
     const int s1 = v1 ? wrap(s1u) : 0;
-    const T* dchi1 = A.dchi + (long)g * A.L * A.Wmax * DP;
+    const T* dchi1 = A.dchi + (long)(have ? g : 0) * A.L * A.Wmax * DP;
     const T* p01 = A.p0 + (long)bl * DP * Np;
-    T x1[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int c = 4 * ks + kq;
-      T v = 0;
-      if (v1) {
-        const T* pq = A.tb.Pq + (long)c * TS + TO + s1u;
-        v = dchi1[j * DP + c] * (p01[(long)c * Np + s1] + ca * pq[-za] + cb * pq[-zb]);
-      }
-      x1[ks] = v;
-    }
     acc_t e1[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) e1[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + kq;
+      T x = 0;
+      if (v1) {
+        const T* pq = A.tb.Pq + (long)c * TS + TO + s1u;
+        x = dchi1[t * DP + c] * (p01[(long)c * Np + s1] + ca * pq[-za] + cb * pq[-zb]);
+      }
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) e1[mt] = M::mma(FU1[(ks * 64 + lane) * MT + mt], x1[ks], e1[mt]);
+      for (int mt = 0; mt < MT; ++mt) e1[mt] = M::mma(FU1[(ks * 64 + lane) * MT + mt], x, e1[mt]);
+      // keep the scheduler from hoisting every later operand load (register pressure)
+      if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    // read-outs: a lane's partial over its channels in the field precision, float64 across
+    // lanes and stages
     double o0 = 0.0, o1 = 0.0;
-    {
+    if (v1) {
       const T* r0 = TWO ? A.T1 + (long)2 * bl * DP * Np : A.tb.Wk;
       const T* r1 = r0 + (long)DP * Np;
-      if (v1) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
+        T q0 = 0, q1 = 0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const long o = (long)(16 * mt + M::row(lane, r)) * Np + s1;
-            o0 += (double)r0[o] * (double)e1[mt][r];
-            o1 += (double)r1[o] * (double)e1[mt][r];
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * mt + M::row(lane, r)) * Np + s1;
+          q0 += r0[o] * e1[mt][r];
+          q1 += r1[o] * e1[mt][r];
+        }
+        o0 += (double)q0;
+        o1 += (double)q1;
       }
     }
     if constexpr (TWO) {
@@ -394,32 +412,30 @@ __global__ __launch_bounds__(256) void flip12_kernel(Flip12Args<T> A) {
         for (int r = 0; r < 4; ++r) E1s[(16 * mt + M::row(lane, r)) * 17 + j] = e1[mt][r];
       wave_sync();
       const int lo2 = sg.x - 2 * wc, W2 = sg.y + 4 * wc + 1;
-      const int s2u = lo2 + j;
-      const bool v2 = j < W2 && (A.periodic || (s2u >= 0 && s2u < N));
+      const int s2u = lo2 + t;
+      const bool v2 = have && t < W2 && (A.periodic || (s2u >= 0 && s2u < N));
       const int s2 = v2 ? wrap(s2u) : 0;
       const T* lamb = A.lam + (long)bl * N * A.ND * DP;
       const T* la = lamb + ((long)za * A.ND + (s2u - za - A.dlo)) * DP;
       const T* lb = lamb + ((long)wrap(zb) * A.ND + (s2u - zb - A.dlo)) * DP;
-      T x2[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = 4 * ks + kq;
-        T v = 0;
-        if (v2) {
-          const T* g2 = A.tb.taps + ((long)DP + c) * TS + TO + s2u - lo1;
-          for (int t = 0; t < W1; ++t) v += g2[-t] * E1s[c * 17 + t];
-          v += ca * la[c];
-          if (pair) v += cb * lb[c];
-        }
-        x2[ks] = v;
-      }
+      const T* e1c = E1s + p * W;  // this flip's columns of e1
       acc_t q2[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) q2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = 4 * ks + kq;
+        T x = 0;
+        if (v2) {
+          const T* g2 = A.tb.taps + ((long)DP + c) * TS + TO + s2u - lo1;
+          for (int u = 0; u < W1; ++u) x += g2[-u] * e1c[c * 17 + u];
+          x += ca * la[c];
+          if (pair) x += cb * lb[c];
+        }
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) q2[mt] = M::mma(FV2[(ks * 64 + lane) * MT + mt], x2[ks], q2[mt]);
+        for (int mt = 0; mt < MT; ++mt) q2[mt] = M::mma(FV2[(ks * 64 + lane) * MT + mt], x, q2[mt]);
+        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
       // x = dchi2 * (p0^(2) + V x2), in accumulator order
       const T* dchi2 = dchi1 + (long)A.Wmax * DP;
       const T* p02 = A.p0 + A.fldB + (long)bl * DP * Np;
@@ -428,11 +444,11 @@ __global__ __launch_bounds__(256) void flip12_kernel(Flip12Args<T> A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int c = 16 * mt + M::row(lane, r);
-          q2[mt][r] = v2 ? dchi2[j * DP + c] * (p02[(long)c * Np + s2] + q2[mt][r]) : T(0);
+          q2[mt][r] = v2 ? dchi2[t * DP + c] * (p02[(long)c * Np + s2] + q2[mt][r]) : T(0);
         }
       const T* w0 = A.tb.Wk;
       const T* w1 = w0 + (long)DP * Np;
-#pragma unroll
+#pragma unroll 1
       for (int mo = 0; mo < MT; ++mo) {
         acc_t e2 = acc_t{0, 0, 0, 0};
 #pragma unroll
@@ -440,35 +456,47 @@ __global__ __launch_bounds__(256) void flip12_kernel(Flip12Args<T> A) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) e2 = M::mma(FU2[((mo * MT + mi) * 64 + lane) * 4 + r], q2[mi][r], e2);
         if (v2) {
+          T q0 = 0, q1 = 0;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const long o = (long)(16 * mo + M::row(lane, r)) * Np + s2;
-            o0 += (double)w0[o] * (double)e2[r];
-            o1 += (double)w1[o] * (double)e2[r];
+            const int o = (16 * mo + M::row(lane, r)) * Np + s2;
+            q0 += w0[o] * e2[r];
+            q1 += w1[o] * e2[r];
           }
+          o0 += (double)q0;
+          o1 += (double)q1;
         }
       }
-      wave_sync();  // E1s is rewritten by the wave's next flip
     }
-    // the input change e^(0) = c_z E at the cluster sites, read out with T^(0)
-    {
+    // the input change e^(0) = c_z E at the cluster sites, read out with T^(0): the lanes of
+    // a flip's first column take the channels 4 ks + kq
+    if (have && t == 0) {
       const T* t0 = A.T0 + (long)2 * bl * DP * Np;
-      for (int c = lane; c < DP; c += 64) {
+      const int zbw = wrap(zb);
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = 4 * ks + kq;
         const double e = (double)A.tb.E[c];
-        const long oa = (long)c * Np + za;
-        o0 += (double)ca * e * (double)t0[oa];
-        o1 += (double)ca * e * (double)t0[(long)DP * Np + oa];
-        if (pair) {
-          const long ob = (long)c * Np + wrap(zb);
-          o0 += (double)cb * e * (double)t0[ob];
-          o1 += (double)cb * e * (double)t0[(long)DP * Np + ob];
-        }
+        const long oa = (long)c * Np + za, ob = (long)c * Np + zbw;
+        o0 += e * ((double)ca * (double)t0[oa] + (double)cb * (double)t0[ob]);
+        o1 += e * ((double)ca * (double)t0[(long)DP * Np + oa] + (double)cb * (double)t0[(long)DP * Np + ob]);
       }
     }
-    o0 = wave_sum(o0);
-    o1 = wave_sum(o1);
-    if (lane == 0)
-      A.logratio[(long)bglob * A.map.M_max + m] = lcd_d(A.Om0[2 * bglob], o0) + lcd_d(A.Om0[2 * bglob + 1], o1);
+    // column sums (lanes 16 and 32 apart share a column), then each flip's columns
+    o0 = swap_sum<32>(swap_sum<16>(o0));
+    o1 = swap_sum<32>(swap_sum<16>(o1));
+    if (lane < 16) { red[lane] = o0; red[16 + lane] = o1; }
+    wave_sync();
+    if (lane < P && gb + lane < F) {
+      double s0 = 0.0, s1v = 0.0;
+      for (int u = 0; u < W; ++u) { s0 += red[lane * W + u]; s1v += red[16 + lane * W + u]; }
+      const int gg = gb + lane;
+      const int bg = A.map.cb[cfg0 + gg], mm = A.map.cm[cfg0 + gg];
+      const long o = (long)bg * A.map.M_max + mm;
+      A.logratio[o] = lcd_d(A.Om0[2 * bg], s0) + lcd_d(A.Om0[2 * bg + 1], s1v);
+      if (A.dom) { A.dom[2 * o] = s0; A.dom[2 * o + 1] = s1v; }
+    }
+    wave_sync();  // red and E1s are rewritten by the wave's next step
   }
 }
 

@@ -1,0 +1,97 @@
+// Screened typewriter Metropolis sampler (Sec. IV, Algorithm 2; App. "Screened Metropolis
+// sampler is exact"; App. "Practical implementation of the screened typewriter sampler").
+//
+// One half-sweep over B independent chains: the chain is cut into blocks of `spacing` sites,
+// every other block (parity 0: blocks 0, 2, ...; 1: blocks 1, 3, ...) proposes one single-site
+// flip at floor(r * width) inside it (r uniform in [0, 1), an input). The proposals' output
+// changes dOmega_k come from ABACUS against one background configuration; proposal k is then
+// judged with the independent-scattering ratio R~ = |f(Omega + dOmega_k) / f(Omega)|^2, Omega
+// being the background's output plus the changes of the flips accepted since, f = prod cosh, so
+// R~ = exp(2 sum_units lcd(Omega, dOmega_k)). With P = min(1, R~) a draw u with |u - P| <= eps is
+// ambiguous: the chain freezes there (masking, the other chains go on), its background is
+// rebuilt at its current configuration and the remaining proposals' changes are recomputed;
+// the frozen proposal is then decided with its exact ratio. Otherwise accept iff u < P. When eps
+// bounds |R~ - R| the decisions are those of exact Metropolis-Hastings for the same draws.
+#pragma once
+#include "common.h"
+
+namespace dn {
+
+struct SweepArgs {
+  int B, N, K, spacing, parity;
+  double eps;
+  const double* r_site;  // [B][K] proposal draws
+  const double* u;       // [B][K] acceptance draws
+  int8_t* spins;         // [B][N] chains, updated in place
+  int32_t* sites;        // [B][K][2] proposals (second site -1)
+  int32_t* sites_r;      // [B][K][2] this round's remaining proposals, from kstart
+  int32_t* n_conn;       // [B] this round's count
+  int32_t* kstart;       // [B] first proposal not yet decided (K: done)
+  int32_t* pending;      // [B] 1: the proposal at kstart froze the chain (decide it exactly next)
+  int32_t* accepted;     // [B][K] 0/1
+  int32_t* refreshes;    // [B]
+  int32_t* frozen;       // [1] chains that froze in this round
+  const double* Om0;     // [B][2] output of this round's background
+  const double* dom;     // [B][K][2] this round's changes (index k - kstart)
+};
+
+// Proposals of the half-sweep and the initial state of every chain.
+__global__ void sweep_init_kernel(SweepArgs a) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)a.B * a.K; i += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / a.K), k = (int)(i % a.K);
+    const int lo = (a.parity + 2 * k) * a.spacing;
+    const int width = min(a.spacing, a.N - lo);
+    const int off = min((int)floor(a.r_site[i] * width), width - 1);
+    a.sites[2 * i] = lo + max(off, 0);
+    a.sites[2 * i + 1] = -1;
+    a.accepted[i] = 0;
+    if (k == 0) { a.kstart[b] = 0; a.pending[b] = 0; a.refreshes[b] = 0; }
+  }
+}
+
+// The remaining proposals of every chain as this round's work list.
+__global__ void sweep_round_kernel(SweepArgs a) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)a.B * a.K; i += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / a.K), m = (int)(i % a.K);
+    const int k0 = a.kstart[b];
+    const int k = k0 + m;
+    a.sites_r[2 * i] = k < a.K ? a.sites[2 * ((long)b * a.K + k)] : -1;
+    a.sites_r[2 * i + 1] = -1;
+    if (m == 0) a.n_conn[b] = a.K - min(k0, a.K);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.frozen[0] = 0;
+}
+
+// Sequential screened acceptance, one thread per chain.
+__global__ void sweep_accept_kernel(SweepArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  const int k0 = a.kstart[b];
+  if (k0 >= a.K) return;
+  double om0 = a.Om0[2 * b], om1 = a.Om0[2 * b + 1];
+  const bool exact_first = a.pending[b] != 0;
+  for (int k = k0; k < a.K; ++k) {
+    const long o = (long)b * a.K + (k - k0);
+    const double d0 = a.dom[2 * o], d1 = a.dom[2 * o + 1];
+    const double P = fmin(1.0, exp(2.0 * (lcd_d(om0, d0) + lcd_d(om1, d1))));
+    const double uu = a.u[(long)b * a.K + k];
+    if (!(exact_first && k == k0) && fabs(uu - P) <= a.eps) {
+      a.kstart[b] = k;
+      a.pending[b] = 1;
+      a.refreshes[b] += 1;
+      atomicAdd(a.frozen, 1);
+      return;
+    }
+    if (uu < P) {
+      a.accepted[(long)b * a.K + k] = 1;
+      const int j = a.sites[2 * ((long)b * a.K + k)];
+      a.spins[(long)b * a.N + j] = (int8_t)(-a.spins[(long)b * a.N + j]);
+      om0 += d0;
+      om1 += d1;
+    }
+  }
+  a.kstart[b] = a.K;
+  a.pending[b] = 0;
+}
+
+}  // namespace dn
