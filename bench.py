@@ -33,12 +33,15 @@ HBM_PEAK = 8000.0                      # GB/s
 def mfma_peak(kind: str, prec: str, products: str, d: int):
     """(peak TFLOP/s, basis) for the algorithmic (float) flops of a kernel class. With
     three-term splits every float product costs six bf16 products, so the float-equivalent
-    peak is the bf16 dense peak / 6."""
+    peak is the bf16 dense peak / 6; BF16-mixed models split into hi + lo terms (three bf16
+    products per product: the bf16 dense peak / 3)."""
     split = products == "split3" and prec != "fp64"
+    two = prec == "bf16"
     if kind == "conv" and split:
-        return PEAK["bf16"] / 6, "bf16 dense peak / 6 (three-term split products)"
-    if kind == "mix_deep" and prec == "bf16" and d > 16:
-        return PEAK["bf16"], "bf16 dense peak"
+        return ((PEAK["bf16"] / 3, "bf16 dense peak / 3 (hi + lo split products)") if two else
+                (PEAK["bf16"] / 6, "bf16 dense peak / 6 (three-term split products)"))
+    if kind == "mix_deep" and two and d > 16:
+        return PEAK["bf16"] / 3, "bf16 dense peak / 3 (hi + lo split products)"
     if kind == "mix_deep" and split and d > 16:
         return PEAK["bf16"] / 6, "bf16 dense peak / 6 (three-term split products)"
     return PEAK[prec if prec != "bf16" else "fp32"], ("fp64" if prec == "fp64" else "fp32") + " dense peak"
@@ -51,9 +54,10 @@ def products_label(prec: str, products: str, d: int) -> str:
     if prec == "fp64":
         return "f64 matrix cores"
     split = "three-term bf16 splits (six partial products, f32 accumulate: f32 error bound)"
-    toeplitz = split if products == "split3" else "f32 matrix cores"
+    hilo = "hi + lo bf16 splits (three partial products, f32 accumulate: 16-bit operands)"
+    toeplitz = (hilo if prec == "bf16" else split) if products == "split3" else "f32 matrix cores"
     if prec == "bf16" and d > 16:
-        mix = "bf16-rounded operands, f32 accumulate"
+        mix = hilo
     elif products == "split3" and d > 16:
         mix = split
     else:
@@ -90,16 +94,45 @@ def kernel_class(name: str) -> str:
     return "other"
 
 
-def summarize(args) -> None:
-    """Turn raw rocprofv3 CSVs (gpurun_out/) into the short summaries kept in profiles/."""
+def _db(d: str):
+    """The rocprofv3 database (rocpd, SQLite) in directory d, or None."""
+    import glob
+    import sqlite3
+    dbs = sorted(glob.glob(os.path.join(d, "*.db")))
+    return sqlite3.connect(dbs[0]) if dbs else None
+
+
+def _kernel_stats(d: str):
+    """Per-kernel calls and durations of a rocprofv3 run: the CSV summary or the database."""
     import csv
+    con = _db(d)
+    if con is None:
+        return list(csv.DictReader(open(os.path.join(d, "kt_kernel_stats.csv"))))
+    out = []
+    for name, n, tot in con.execute("select name, count(*), sum(duration) from kernels group by name"):
+        out.append({"Name": name, "Calls": n, "TotalDurationNs": tot, "AverageNs": tot / n})
+    return out
+
+
+def _pmc_rows(d: str):
+    """(kernel name, counter, value) per dispatch of a rocprofv3 --pmc run."""
+    import csv
+    con = _db(d)
+    if con is None:
+        return list(csv.DictReader(open(os.path.join(d, "pmc_counter_collection.csv"))))
+    return [{"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v}
+            for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection")]
+
+
+def summarize(args) -> None:
+    """Turn raw rocprofv3 output (gpurun_out/) into the short summaries kept in profiles/."""
     import collections
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     wl = args.workload
     if args.stats_dir:
-        rows = list(csv.DictReader(open(os.path.join(args.stats_dir, "kt_kernel_stats.csv"))))
+        rows = _kernel_stats(args.stats_dir)
         total = sum(float(r["TotalDurationNs"]) for r in rows)
-        out = [f"# Kernel time, {wl}, ABACUS path\n",
+        out = [f"# Kernel time, {wl}, {args.stats_path} path\n",
                f"Command: `{args.stats_cmd}`\n",
                f"Source hash of csrc/: `{source_hash()}`\n",
                "| kernel | class | calls | total ms | avg us | share |", "|---|---|---|---|---|---|"]
@@ -116,12 +149,41 @@ def summarize(args) -> None:
                 "| class | calls | avg us per launch |", "|---|---|---|"]
         for k, (ns, n) in sorted(cls.items(), key=lambda kv: -kv[1][0]):
             out.append(f"| {k} | {n} | {ns / n / 1e3:.1f} |")
-        with open(os.path.join(ROOT, "profiles", f"kernel_stats_{wl}.md"), "w") as f:
+        sfx = "" if args.stats_path == "ABACUS" else "_" + args.stats_path.lower().replace(" ", "_")
+        with open(os.path.join(ROOT, "profiles", f"kernel_stats_{wl}{sfx}.md"), "w") as f:
             f.write("\n".join(out) + "\n")
+    if args.util_dirs:
+        # matrix-core and vector-ALU busy percentages (rocprofv3's derived MfmaUtil and VALUBusy)
+        # per kernel class, averaged over the class's dispatches
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for d in args.util_dirs.split(","):
+            for r in _pmc_rows(d):
+                per[kernel_class(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        res = {"source_hash": source_hash(), "command": args.util_cmd, wl: {}}
+        md = [f"# Matrix-core and vector-ALU busy, {wl}, ABACUS path\n", f"Command: `{args.util_cmd}`\n",
+              f"Source hash of csrc/: `{source_hash()}`\n",
+              "MfmaUtil = 100 * sum SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE * SIMDs); "
+              "VALUBusy = 100 * sum SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE (rocprofv3's definitions).\n",
+              "| class | dispatches | MfmaUtil % | VALUBusy % |", "|---|---|---|---|"]
+        for k, v in sorted(per.items()):
+            if "MfmaUtil" in v and "VALUBusy" in v:
+                mu = sum(v["MfmaUtil"]) / len(v["MfmaUtil"])
+                vb = sum(v["VALUBusy"]) / len(v["VALUBusy"])
+                res[wl][k] = {"mfma_util_pct": mu, "valu_busy_pct": vb, "dispatches": len(v["MfmaUtil"])}
+                md.append(f"| {k} | {len(v['MfmaUtil'])} | {mu:.1f} | {vb:.1f} |")
+        path = os.path.join(ROOT, "profiles", "counters.json")
+        old = json.load(open(path)) if os.path.exists(path) else {}
+        if old.get("source_hash") == res["source_hash"]:
+            old.update(res)
+            res = old
+        with open(path, "w") as f:
+            json.dump(res, f, indent=1)
+        with open(os.path.join(ROOT, "profiles", f"util_{wl}.md"), "w") as f:
+            f.write("\n".join(md) + "\n")
     if args.pmc_dirs:
         per = {}
         for d in args.pmc_dirs.split(","):
-            rows = list(csv.DictReader(open(os.path.join(d, "pmc_counter_collection.csv"))))
+            rows = _pmc_rows(d)
             for r in rows:
                 per.setdefault(r["Counter_Name"], []).append(r)
         calib = {}
@@ -182,8 +244,11 @@ def main():
     ap.add_argument("--summarize", action="store_true", help="write profiles/ summaries from raw rocprofv3 CSVs")
     ap.add_argument("--stats-dir", default="")
     ap.add_argument("--stats-cmd", default="")
+    ap.add_argument("--stats-path", default="ABACUS", help="the estimator path the stats run timed")
     ap.add_argument("--pmc-dirs", default="")
     ap.add_argument("--pmc-cmd", default="")
+    ap.add_argument("--util-dirs", default="", help="rocprofv3 --pmc MfmaUtil VALUBusy output directories")
+    ap.add_argument("--util-cmd", default="")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
@@ -297,7 +362,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mixed (bf16 channel mixing, f32 accumulate)"}[prec],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mixed (hi + lo bf16 operands, f32 accumulate)"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "N": shape.N, "L": shape.L, "d": shape.d, "s": shape.s,
                    "B": B, "hamiltonian": f"{ham.kind} {ham.bc} J={ham.J} alpha={ham.alpha} h={ham.h}"
@@ -339,10 +404,25 @@ def main():
             ent = tj.get(args.workload, {}).get(dom)
             if ent and tj.get("source_hash") == source_hash():
                 traffic = ent["bytes_per_launch"]
-        out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
+        # the binding unit from the committed counters of the same sources (matrix-core busy,
+        # vector-ALU busy, HBM bandwidth of the measured traffic), when they are there
+        bound, util = "mfma", None
+        cpath = os.path.join(ROOT, "profiles", "counters.json")
+        if os.path.exists(cpath):
+            with open(cpath) as f:
+                cj = json.load(f)
+            ent = cj.get(args.workload, {}).get(dom)
+            if ent and cj.get("source_hash") == source_hash():
+                hbm_pct = 100.0 * traffic / (ms / n * 1e-3) / (HBM_PEAK * 1e9) if traffic else 0.0
+                util = {"mfma_util_pct": ent["mfma_util_pct"], "valu_busy_pct": ent["valu_busy_pct"],
+                        "hbm_pct": hbm_pct, "source": "profiles/counters.json"}
+                score = {"mfma": ent["mfma_util_pct"], "alu": ent["valu_busy_pct"], "hbm": hbm_pct}
+                bound = max(score, key=score.get)
+        out["roofline"] = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak,
                            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                            "peak_basis": basis, "avg_launch_ms": ms / n,
-                           "algorithmic_flops_per_launch": fl / n, "algorithmic_bytes_per_launch": by / n}
+                           "algorithmic_flops_per_launch": fl / n, "algorithmic_bytes_per_launch": by / n,
+                           "counters": util}
 
     # error of both GPU paths against the float64 oracle at the stress draw (every block
     # carries order-one signal there; at the baseline draw the network is nearly linear)

@@ -55,10 +55,10 @@ typedef enum { DN_ACT_SILU = 0, DN_ACT_TANH = 1, DN_ACT_IDENTITY = 2 } dn_act;
  * propagation) run on the bf16 matrix cores with float32 accumulation, each operand split
  * into hi + lo bfloat16 terms (round to nearest even; 16 significant bits) and the three
  * partial products hi*hi, hi*lo, lo*hi accumulated (relative error of a product below
- * 3 * 2^-17); everything else as FP32 (phi stream, Green's-function mixer, slices, the
- * per-flip update of one- and two-block networks; per-sample gradients run entirely in
- * float32). Kernel generation, the read-out sums and the log-ratio are float64 in every
- * mode. */
+ * 3 * 2^-17), and so do the Green's-function (Toeplitz) products (hi + lo terms of both the
+ * field and the taps); everything else as FP32 (phi stream, slices, the per-flip update of
+ * one- and two-block networks; per-sample gradients run entirely in float32). Kernel
+ * generation, the read-out sums and the log-ratio are float64 in every mode. */
 typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_prec;
 typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
 
@@ -146,6 +146,22 @@ dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spaci
                             const double* r_site, const double* u, double eps, int32_t* accepted,
                             int32_t* refreshes, void* stream);
 
+/* One stochastic-reconfiguration (natural-gradient) update of variational Monte Carlo (Sec. II
+ * and VI; App. "Network parameters": standard SR with a diagonal shift). Inputs: the per-sample
+ * log-derivatives O [B][P] as dn_grad_logpsi writes them (device, the model's field type: float
+ * for FP32 / BF16-mixed models, double for FP64), local energies eloc [B] (device float64) and
+ * sample weights [B] (device float64 summing to 1; NULL = 1/B each, Monte Carlo samples).
+ * With Ebar = sum_b w_b E_b, F = sum_b w_b O_b (E_b - Ebar) and
+ * S = sum_b w_b O_b O_b^T - Obar Obar^T (Obar = sum_b w_b O_b), the system (S + shift I) x = F
+ * is solved by conjugate gradients (at most max_iter iterations, until |r| <= tol |F|) and
+ * delta = -eta x is written (device float64 [P]); the caller adds it to the parameters and calls
+ * dn_model_set_params. energy (device float64 [1], nullable) receives Ebar; iters (host,
+ * nullable) the iterations taken. Every sum is float64; S is never formed (each iteration reads
+ * O twice). Synchronises the stream every 8 iterations. */
+dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const double* weights, int32_t B,
+                       double shift, double eta, int32_t max_iter, double tol, double* delta,
+                       double* energy, int32_t* iters, void* stream);
+
 /* dn_logpsi for callers that cannot allocate device memory: code under HIP graph capture,
  * tight sampling or serving loops, harnesses that forbid hipMalloc. The same values as
  * dn_logpsi (the same kernels), but every buffer beyond the caller's inputs and outputs --
@@ -232,8 +248,10 @@ dn_status dn_set_launch_shapes(dn_model* m, int32_t conv_nt, int64_t flip_budget
  * products x_a y_b with a + b <= 2 run on the bf16 matrix cores with float32 accumulation;
  * the dropped ones are below 2^-24 |x y|, so the result has the error bound of a float32
  * dot product. DN_PRODUCT_FP32: the float32 matrix cores (one product per term).
- * Float32 models use the setting for both kinds of product; BF16-mixed models for the
- * Toeplitz products (their channel mixing is bf16 by definition); float64 models ignore it;
+ * Float32 models use the setting for both kinds of product; BF16-mixed models take hi + lo
+ * bf16 terms (three partial products) where the float models take three terms, for both kinds,
+ * and DN_PRODUCT_FP32 moves their Toeplitz products to the float32 matrix cores; float64 models
+ * ignore it;
  * the forward and adjoint background passes and the gradients stay on float32 matrix cores.
  * DN_EINVAL for another value. Takes effect on the next call. */
 typedef enum { DN_PRODUCT_SPLIT3 = 0, DN_PRODUCT_FP32 = 1 } dn_product_mode;

@@ -25,7 +25,7 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
            "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-           "dn_ragged_eloc", "dn_screened_sweep", "dn_profile_enable", "dn_profile_read",
+           "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
 RAGGED_MODE = {"eager": 0, "graph": 1}
 PRODUCT_MODE = {"split3": 0, "fp32": 1}
@@ -80,6 +80,8 @@ def lib():
         L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
         L.dn_screened_sweep.argtypes = [vp, vp, i32, i32, i32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.dn_sr_update.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, i32, ctypes.c_double, vp,
+                                   vp, ctypes.POINTER(i32), vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dn_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -89,7 +91,7 @@ def lib():
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
                    "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
                    "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-                   "dn_ragged_eloc", "dn_screened_sweep", "dn_profile_enable",
+                   "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable",
                    "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -223,6 +225,19 @@ class Model:
         _check(lib().dn_screened_sweep(self.handle, _ptr(spins), B, spacing, parity, _ptr(r), _ptr(uu), eps,
                                        _ptr(acc), _ptr(ref), _stream()))
         return acc, ref
+
+    def sr_update(self, grads: torch.Tensor, eloc: torch.Tensor, weights: torch.Tensor | None = None,
+                  shift: float = 1e-3, eta: float = 0.05, max_iter: int = 200, tol: float = 1e-10):
+        """dn_sr_update: (delta [P] float64, energy float64 scalar tensor, CG iterations)."""
+        B, P = grads.shape
+        delta = torch.empty(P, dtype=torch.float64, device=grads.device)
+        energy = torch.empty(1, dtype=torch.float64, device=grads.device)
+        it = ctypes.c_int32()
+        w = weights.to(torch.float64).contiguous() if weights is not None else None
+        g, e = grads.contiguous(), eloc.to(torch.float64).contiguous()
+        _check(lib().dn_sr_update(self.handle, _ptr(g), _ptr(e), _ptr(w), B, shift, eta, max_iter, tol, _ptr(delta),
+                                  _ptr(energy), ctypes.byref(it), _stream()))
+        return delta, energy[0], it.value
 
     def autotune(self, ham, B_probe: int = 256):
         """Pick this model's launch shapes by timing; returns (conv_nt, flip_budget_bytes)."""

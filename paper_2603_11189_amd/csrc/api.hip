@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +24,7 @@
 #include "grad.h"
 #include "link2.h"
 #include "sampler.h"
+#include "sr.h"
 
 using namespace dn;
 
@@ -297,7 +299,8 @@ template <> const Tables<double>& tables_of<double>(dn_model* m) { return m->t64
 template <> const Tables<float>& tables_of<float>(dn_model* m) { return m->t32.tb; }
 
 template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const T* taps, int C, hipStream_t st,
-                                            DynRange dyn = DynRange{nullptr, 0, 0}, const T* add = nullptr) {
+                                            DynRange dyn = DynRange{nullptr, 0, 0}, const T* add = nullptr,
+                                            bool exact = false) {
   if (C <= 0) return DN_OK;
   const int Np = m->Np;
   ConvArgs<T> a{X, Y, taps, m->desc.N, Np, C, m->DP, dyn, add};
@@ -310,16 +313,28 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
   dim3 grid((C + CONV_MC - 1) / CONV_MC, m->DP, (Np + 64 * nt - 1) / (64 * nt));
   if constexpr (std::is_same<T, float>::value) {
     if (m->split3) {
-      const size_t lds3 = (3 * (size_t)CONV_MC * CS_LD + 3 * 8 * (size_t)(2 * Np + 16)) * sizeof(__bf16);
+      // BF16-mixed models: hi + lo terms (three partial products); float models and the
+      // gradients of any model (exact): the three-term split (six)
+      const int ns = m->desc.prec == DN_PREC_BF16_MIXED && !exact ? 2 : 3;
+      const size_t lds3 = (ns * (size_t)CONV_MC * CS_LD + ns * 8 * (size_t)(2 * Np + 16)) * sizeof(__bf16);
       // workgroups run over configuration blocks: about two per CU in all (the split taps
       // are then built once per workgroup)
       const long nblk = grid.x;
       grid.x = (unsigned)std::max<long>(1, std::min<long>(nblk, (2L * cu_count() + (long)m->DP * grid.z - 1) / ((long)m->DP * grid.z)));
-      switch (nt) {
-        case 1: allow_lds(conv_split_kernel<1>, lds3); conv_split_kernel<1><<<grid, 256, lds3, st>>>(a); break;
-        case 2: allow_lds(conv_split_kernel<2>, lds3); conv_split_kernel<2><<<grid, 256, lds3, st>>>(a); break;
-        case 3: allow_lds(conv_split_kernel<3>, lds3); conv_split_kernel<3><<<grid, 256, lds3, st>>>(a); break;
-        default: allow_lds(conv_split_kernel<4>, lds3); conv_split_kernel<4><<<grid, 256, lds3, st>>>(a); break;
+      if (ns == 2) {
+        switch (nt) {
+          case 1: allow_lds(conv_split_kernel<1, 2>, lds3); conv_split_kernel<1, 2><<<grid, 256, lds3, st>>>(a); break;
+          case 2: allow_lds(conv_split_kernel<2, 2>, lds3); conv_split_kernel<2, 2><<<grid, 256, lds3, st>>>(a); break;
+          case 3: allow_lds(conv_split_kernel<3, 2>, lds3); conv_split_kernel<3, 2><<<grid, 256, lds3, st>>>(a); break;
+          default: allow_lds(conv_split_kernel<4, 2>, lds3); conv_split_kernel<4, 2><<<grid, 256, lds3, st>>>(a); break;
+        }
+      } else {
+        switch (nt) {
+          case 1: allow_lds(conv_split_kernel<1>, lds3); conv_split_kernel<1><<<grid, 256, lds3, st>>>(a); break;
+          case 2: allow_lds(conv_split_kernel<2>, lds3); conv_split_kernel<2><<<grid, 256, lds3, st>>>(a); break;
+          case 3: allow_lds(conv_split_kernel<3>, lds3); conv_split_kernel<3><<<grid, 256, lds3, st>>>(a); break;
+          default: allow_lds(conv_split_kernel<4>, lds3); conv_split_kernel<4><<<grid, 256, lds3, st>>>(a); break;
+        }
       }
       HIPCHK(hipGetLastError());
       return DN_OK;
@@ -517,7 +532,8 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
   STCHK(phi_pass(0));
   for (int l = 0; l < L; ++l) {
     const T* hin = ck.h ? ck.h + (long)l * fld : u;
-    STCHK(launch_conv<T>(m, hin, v, tb.taps + (long)l * DP * tap_stride(Np), C, st));
+    STCHK(launch_conv<T>(m, hin, v, tb.taps + (long)l * DP * tap_stride(Np), C, st, DynRange{nullptr, 0, 0}, nullptr,
+                         ck.h != nullptr));
     if (l + 1 < L) STCHK(phi_pass(l + 1));
     MixArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = d.w_c;
@@ -1049,7 +1065,8 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
       a.z_out = tz; a.zeta_out = tzeta;
       STCHK((launch_phi<T, DP>(m, a, Bc, st)));
     }
-    STCHK(launch_conv<T>(m, ckh + (long)tl * fld, tv, tb.taps + (long)tl * DP * tap_stride(Np), Bc, st));
+    STCHK(launch_conv<T>(m, ckh + (long)tl * fld, tv, tb.taps + (long)tl * DP * tap_stride(Np), Bc, st,
+                         DynRange{nullptr, 0, 0}, nullptr, true));
     {
       MixArgs<T> a{};
       a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
@@ -1074,7 +1091,8 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
       tapgrad_kernel<T><<<dim3(Bc, dd), 256, 2 * (size_t)Np * sizeof(T), st>>>(a);
     }
     T* du_cur = du[flip];
-    STCHK(launch_conv<T>(m, dv, du_cur, tb.tapsR + (long)tl * DP * tap_stride(Np), Bc, st));
+    STCHK(launch_conv<T>(m, dv, du_cur, tb.tapsR + (long)tl * DP * tap_stride(Np), Bc, st, DynRange{nullptr, 0, 0},
+                         nullptr, true));
     // phi stream backward
     T* dph_cur = dph[flip];
     {
@@ -1216,6 +1234,59 @@ template <typename T, int DP> struct RunSweep {
       if (!frozen) break;
     }
     return abacus_check(m, st);
+  }
+};
+
+// Stochastic-reconfiguration update by conjugate gradients (see sr.h); the residual norm is
+// checked on the host every 8 iterations (one synchronisation each).
+template <typename T, int DP> struct RunSR {
+  static dn_status run(dn_model* m, const void* Ov, const double* E, const double* w, int B, double shift, double eta,
+                       int max_iter, double tol, double* delta, double* energy, int32_t* iters, hipStream_t st) {
+    const T* O = (const T*)Ov;
+    const long P = m->lay.P;
+    void *pv, *pb, *psc;
+    STCHK(ws_get(m, "sr_vec", (size_t)6 * P * 8, &pv));
+    STCHK(ws_get(m, "sr_smp", (size_t)3 * B * 8, &pb));
+    STCHK(ws_get(m, "sr_sc", 8 * 8, &psc));
+    double *x = (double*)pv, *r = x + P, *p = r + P, *Ap = p + P, *F = Ap + P, *Ob = F + P;
+    double *wv = (double*)pb, *we = wv + B, *t = we + B, *sc = (double*)psc;
+    const int gp = (int)((P + 255) / 256), gv = (int)std::min<long>(1024, (P + 255) / 256);
+    sr_energy_kernel<<<1, 1024, 0, st>>>(E, w, B, wv, we, sc + 5);
+    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, wv, nullptr, 0.0, Ob);
+    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, we, nullptr, 0.0, F);
+    sr_init_kernel<<<gv, 256, 0, st>>>(x, r, p, F, P);
+    sr_dot_kernel<<<1, 1024, 0, st>>>(F, F, P, sc + 0);
+    sr_dot_kernel<<<1, 1024, 0, st>>>(F, F, P, sc + 4);
+    HIPCHK(hipGetLastError());
+    double h[8] = {};
+    HIPCHK(hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double fnorm = std::sqrt(h[4]);
+    int it = 0;
+    if (fnorm > 0.0) {
+      for (it = 1; it <= max_iter; ++it) {
+        sr_dot_kernel<<<1, 1024, 0, st>>>(Ob, p, P, sc + 3);
+        sr_rowdot_kernel<T><<<B, 256, 0, st>>>(O, P, p, sc + 3, wv, t);
+        sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, t, p, shift, Ap);
+        sr_dot_kernel<<<1, 1024, 0, st>>>(p, Ap, P, sc + 1);
+        sr_step_kernel<<<gv, 256, 0, st>>>(x, r, p, Ap, P, sc);
+        sr_dot_kernel<<<1, 1024, 0, st>>>(r, r, P, sc + 2);
+        sr_dir_kernel<<<gv, 256, 0, st>>>(p, r, P, sc);
+        sr_roll_kernel<<<1, 1, 0, st>>>(sc);
+        HIPCHK(hipGetLastError());
+        if (it % 8 == 0 || it == max_iter) {
+          HIPCHK(hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          if (std::sqrt(h[0]) <= tol * fnorm) break;
+        }
+      }
+      if (it > max_iter) it = max_iter;
+    }
+    sr_scale_kernel<<<gv, 256, 0, st>>>(x, eta, P, delta);
+    if (energy) HIPCHK(hipMemcpyAsync(energy, sc + 5, 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipGetLastError());
+    if (iters) *iters = it;
+    return DN_OK;
   }
 };
 
@@ -1669,6 +1740,17 @@ dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spaci
   STCHK(abacus_supported(m));
   return dispatch<RunSweep>(m, spins, (int)B, (int)spacing, (int)parity, r_site, u, eps, accepted, refreshes,
                             (hipStream_t)stream);
+}
+
+dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const double* weights, int32_t B, double shift,
+                       double eta, int32_t max_iter, double tol, double* delta, double* energy, int32_t* iters,
+                       void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 1 || !(shift >= 0.0) || !std::isfinite(eta) || max_iter < 1 || !(tol >= 0.0))
+    return fail(DN_EINVAL, "bad B, shift, eta, max_iter or tol");
+  if (!O || !eloc || !delta) return fail(DN_EINVAL, "null argument");
+  return dispatch<RunSR>(m, O, eloc, weights, (int)B, shift, eta, (int)max_iter, tol, delta, energy, iters,
+                         (hipStream_t)stream);
 }
 
 dn_status dn_logpsi_noalloc(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* stream) {

@@ -378,11 +378,14 @@ template <int NS> __device__ inline void splitnx2(f2v v, bf2* b) {
   }
 }
 
-template <int NT>
+// NS: bf16 terms per operand: 3 (exact split, float32 error bound, six partial products) or
+// 2 (hi + lo, 16 significant bits, three partial products: the BF16-mixed mode).
+template <int NT, int NS = 3>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv_split_kernel(ConvArgs<float> A) {
+  static_assert(NS == 2 || NS == 3, "two or three bf16 terms");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __bf16* xs = reinterpret_cast<__bf16*>(smem_raw);  // [3][CONV_MC][CS_LD]
-  __bf16* tsh = xs + 3 * CONV_MC * CS_LD;            // [3][8][TL]
+  __bf16* xs = reinterpret_cast<__bf16*>(smem_raw);  // [NS][CONV_MC][CS_LD]
+  __bf16* tsh = xs + NS * CONV_MC * CS_LD;           // [NS][8][TL]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.y;
   const int C = A.dyn.count(A.C);
@@ -409,11 +412,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       for (int e = 0; e < PER; ++e) {
         const int idx = base + e * 256 + threadIdx.x;
         if (idx < 8 * TL) {
-          __bf16 b0, b1, b2;
-          split3(v[e], b0, b1, b2);
-          tsh[idx] = b0;  // idx = s TL + q
-          tsh[8 * TL + idx] = b1;
-          tsh[16 * TL + idx] = b2;
+          __bf16 b[NS];
+          splitn<NS>(v[e], b);
+#pragma unroll
+          for (int q = 0; q < NS; ++q) tsh[q * 8 * TL + idx] = b[q];  // idx = s TL + q
         }
       }
     }
@@ -473,14 +475,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     lds_barrier();  // the previous chunk is consumed (and the taps are in place)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      bf2 a0, a1, a2, b0, b1, b2;
-      split3x2(f2v{p[u].x, p[u].y}, a0, a1, a2);
-      split3x2(f2v{p[u].z, p[u].w}, b0, b1, b2);
+      bf2 a[NS], b[NS];
+      splitnx2<NS>(f2v{p[u].x, p[u].y}, a);
+      splitnx2<NS>(f2v{p[u].z, p[u].w}, b);
       typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
       __bf16* d = xs + (srow + 16 * u) * CS_LD + scol;
-      *reinterpret_cast<bf4*>(d) = bf4{a0[0], a0[1], b0[0], b0[1]};
-      *reinterpret_cast<bf4*>(d + CONV_MC * CS_LD) = bf4{a1[0], a1[1], b1[0], b1[1]};
-      *reinterpret_cast<bf4*>(d + 2 * CONV_MC * CS_LD) = bf4{a2[0], a2[1], b2[0], b2[1]};
+#pragma unroll
+      for (int q = 0; q < NS; ++q) *reinterpret_cast<bf4*>(d + q * CONV_MC * CS_LD) = bf4{a[q][0], a[q][1], b[q][0], b[q][1]};
     }
     lds_barrier();
     fetch(p, ci + 2);
@@ -494,23 +495,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       auto ldb = [&](int b, int ks, int n) {
         return *reinterpret_cast<const bf8*>(tsh + b * 8 * TL + tbase[n] + k0 + 32 * ks);
       };
-      bf8 xa[3][4], tb[3][NT];
+      bf8 xa[NS][4], tb[NS][NT];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
+      for (int b = 0; b < NS; ++b) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) xa[b][mt] = lda(b, 0, mt);
 #pragma unroll
         for (int n = 0; n < NT; ++n) tb[b][n] = ldb(b, 0, n);
       }
-      // the six products of a step, smallest first; an operand term is replaced by the next
-      // step's as soon as its last product of this step is issued
+      // the products of a step (six or three), smallest first; an operand term is replaced by
+      // the next step's as soon as its last product of this step is issued
 #pragma unroll
-      for (int ks = 0; ks < CS_KC / 32; ++ks) {
+      for (int ks = 0; ks < CS_KC / 32 && NS == 2; ++ks) {
         const bool more = ks + 1 < CS_KC / 32;
 #pragma unroll
-        for (int term = 0; term < 6; ++term) {
-          const int ta = term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0;
-          const int tg = term == 0 ? 0 : term == 1 ? 1 : term == 2 ? 2 : term == 3 ? 0 : term == 4 ? 1 : 0;
+        for (int term = 0; term < 3; ++term) {
+          const int ta = term == 0 ? 1 : 0, tg = term == 1 ? 1 : 0;
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -518,10 +518,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
           if (more) {
             if (term == 0) {
 #pragma unroll
-              for (int mt = 0; mt < 4; ++mt) xa[2][mt] = lda(2, ks + 1, mt);
+              for (int mt = 0; mt < 4; ++mt) xa[1 % NS][mt] = lda(1, ks + 1, mt);
+            } else if (term == 1) {
+#pragma unroll
+              for (int n = 0; n < NT; ++n) tb[1 % NS][n] = ldb(1, ks + 1, n);
+            } else {
+#pragma unroll
+              for (int mt = 0; mt < 4; ++mt) xa[0][mt] = lda(0, ks + 1, mt);
+#pragma unroll
+              for (int n = 0; n < NT; ++n) tb[0][n] = ldb(0, ks + 1, n);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int ks = 0; ks < CS_KC / 32 && NS == 3; ++ks) {
+        const bool more = ks + 1 < CS_KC / 32;
+#pragma unroll
+        for (int term = 0; term < 6; ++term) {
+          const int ta = (term == 0 ? 2 : term == 1 ? 1 : term == 2 ? 0 : term == 3 ? 1 : 0) % NS;
+          const int tg = (term == 0 ? 0 : term == 1 ? 1 : term == 2 ? 2 : term == 3 ? 0 : term == 4 ? 1 : 0) % NS;
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[mt][n] = mma_bf16(xa[ta][mt], tb[tg][n], acc[mt][n]);
+          if (more) {
+            if (term == 0) {
+#pragma unroll
+              for (int mt = 0; mt < 4; ++mt) xa[2 % NS][mt] = lda(2, ks + 1, mt);
             } else if (term == 2) {
 #pragma unroll
-              for (int n = 0; n < NT; ++n) tb[2][n] = ldb(2, ks + 1, n);
+              for (int n = 0; n < NT; ++n) tb[2 % NS][n] = ldb(2, ks + 1, n);
             } else if (term == 3) {
 #pragma unroll
               for (int mt = 0; mt < 4; ++mt) xa[1][mt] = lda(1, ks + 1, mt);

@@ -1,0 +1,115 @@
+// Stochastic reconfiguration (natural-gradient) update of VMC (Sec. II and VI; App. "Network
+// parameters": standard SR with a diagonal shift). With samples of weight w_b (sum 1),
+// log-derivatives O [B][P] and local energies E_b:
+//   Ebar = sum_b w_b E_b,  F = O^T (w * (E - Ebar)),  Obar = O^T w,
+//   S v = O^T (w * t),  t_b = (O v)_b - Obar . v          (= Oc^T W Oc v, Oc = O - 1 Obar^T)
+//   (S + shift I) x = F by conjugate gradients,  delta = -eta x.
+// O is read in the model's field type and every sum is float64. The passes over O are
+// bandwidth bound: one thread per parameter for the column sums (coalesced rows), one
+// workgroup per sample for the row products.
+#pragma once
+#include "common.h"
+
+namespace dn {
+
+// Ebar and the weighted centred energies we_b = w_b (E_b - Ebar); w = 1/B when not given.
+__global__ __launch_bounds__(1024) void sr_energy_kernel(const double* __restrict__ E, const double* __restrict__ w,
+                                                         int B, double* __restrict__ wout, double* __restrict__ we,
+                                                         double* __restrict__ ebar) {
+  __shared__ double part[1024];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) s += (w ? w[b] : 1.0 / B) * E[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double eb = part[0];
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const double wb = w ? w[b] : 1.0 / B;
+    wout[b] = wb;
+    we[b] = wb * (E[b] - eb);
+  }
+  if (threadIdx.x == 0) *ebar = eb;
+}
+
+// out_k = sum_b coef_b O_bk (+ shift v_k when v is given), one thread per parameter.
+template <typename T>
+__global__ __launch_bounds__(256) void sr_colsum_kernel(const T* __restrict__ O, long P, int B,
+                                                        const double* __restrict__ coef, const double* __restrict__ v,
+                                                        double shift, double* __restrict__ out) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += coef[b] * (double)O[(long)b * P + k];
+  if (v) s += shift * v[k];
+  out[k] = s;
+}
+
+// t_b = sum_k O_bk v_k - *sub (one workgroup per sample), scaled by w_b.
+template <typename T>
+__global__ __launch_bounds__(256) void sr_rowdot_kernel(const T* __restrict__ O, long P, const double* __restrict__ v,
+                                                        const double* __restrict__ sub, const double* __restrict__ w,
+                                                        double* __restrict__ t) {
+  __shared__ double part[4];
+  const int b = blockIdx.x;
+  const T* row = O + (long)b * P;
+  double s = 0.0;
+  for (long k = threadIdx.x; k < P; k += blockDim.x) s += (double)row[k] * v[k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) t[b] = w[b] * (part[0] + part[1] + part[2] + part[3] - *sub);
+}
+
+// *out = a . b in a fixed order (one workgroup).
+__global__ __launch_bounds__(1024) void sr_dot_kernel(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                                      double* __restrict__ out) {
+  __shared__ double part[1024];
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) s += a[i] * b[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
+// CG scalars in one small array: [0] r.r, [1] p.Ap, [2] new r.r, [3] Obar.p
+// x += alpha p, r -= alpha Ap with alpha = r.r / p.Ap.
+__global__ void sr_step_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                               const double* __restrict__ Ap, long n, const double* __restrict__ sc) {
+  const double alpha = sc[1] > 0.0 ? sc[0] / sc[1] : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * Ap[i];
+  }
+}
+
+// p = r + beta p with beta = new r.r / r.r (a last workgroup-independent read of sc[0]).
+__global__ void sr_dir_kernel(double* __restrict__ p, const double* __restrict__ r, long n,
+                              const double* __restrict__ sc) {
+  const double beta = sc[0] > 0.0 ? sc[2] / sc[0] : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * p[i];
+}
+
+// sc[0] = sc[2] (after the direction update), and the initial copies x = 0, r = p = F.
+__global__ void sr_roll_kernel(double* sc) { sc[0] = sc[2]; }
+__global__ void sr_init_kernel(double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+                               const double* __restrict__ F, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] = 0.0;
+    r[i] = F[i];
+    p[i] = F[i];
+  }
+}
+__global__ void sr_scale_kernel(const double* __restrict__ x, double eta, long n, double* __restrict__ out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = -eta * x[i];
+}
+
+}  // namespace dn

@@ -26,7 +26,9 @@ def test_split_peak_is_a_sixth_of_bf16(bench):
     assert bench.mfma_peak("mix_deep", "fp32", "split3", 16)[0] == bench.PEAK["fp32"]
     assert bench.mfma_peak("conv", "fp32", "fp32", 64)[0] == bench.PEAK["fp32"]
     assert bench.mfma_peak("conv", "fp64", "split3", 64)[0] == bench.PEAK["fp64"]
-    assert bench.mfma_peak("mix_deep", "bf16", "split3", 64)[0] == bf16
+    # BF16-mixed models: hi + lo splits, three bf16 products per product
+    assert bench.mfma_peak("mix_deep", "bf16", "split3", 64)[0] == pytest.approx(bf16 / 3)
+    assert bench.mfma_peak("conv", "bf16", "split3", 64)[0] == pytest.approx(bf16 / 3)
 
 
 @pytest.mark.parametrize("prec,products,d", [(p, m, d) for p in ("fp32", "bf16", "fp64")
@@ -37,11 +39,12 @@ def test_products_label_matches_peaks(bench, prec, products, d):
         assert label == "f64 matrix cores"
         return
     toeplitz, mix = label.split("; channel mixing: ")
-    conv_split = "/ 6" in bench.mfma_peak("conv", prec, products, d)[1]
-    assert ("three-term" in toeplitz) == conv_split
+    conv_basis = bench.mfma_peak("conv", prec, products, d)[1]
+    assert ("three-term" in toeplitz) == ("/ 6" in conv_basis)
+    assert ("hi + lo" in toeplitz) == ("/ 3" in conv_basis)
     deep_peak, deep_basis = bench.mfma_peak("mix_deep", prec, products, d)
     if prec == "bf16" and d > 16:
-        assert mix.startswith("bf16-rounded") and deep_peak == bench.PEAK["bf16"]
+        assert mix.startswith("hi + lo") and deep_peak == pytest.approx(bench.PEAK["bf16"] / 3)
     elif products == "split3" and d > 16:
         assert "three-term" in mix and "/ 6" in deep_basis
     else:
