@@ -357,7 +357,7 @@ template <typename T, int DP, int NT> void phi_go(const PhiArgs<T>& a, int C, si
 
 template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>& a, int C, hipStream_t st) {
   if (C <= 0) return DN_OK;
-  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c + 1) + m->Np) * sizeof(T);
+  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c + 1) + m->Np + (2 * m->desc.w_c + 2) * DP) * sizeof(T);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "phi stream tile exceeds LDS");
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T);
   const double nfield = (a.first ? 0 : 1) + (a.phi_out ? 1 : 0) + 1 + (a.a_out ? 1 : 0) + (a.first ? 1 : 0);
@@ -365,7 +365,7 @@ template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>
   if constexpr (std::is_same<T, double>::value) {
     phi_go<T, DP, 1>(a, C, lds, st);
   } else {
-    // 64 channels: at most two site tiles per wave (more spill the weight fragments)
+    // 64 channels: at most two site tiles per wave (four leave one wave per SIMD)
     switch (DP >= 64 ? std::min(2, tiles_per_wave(m->Np)) : tiles_per_wave(m->Np)) {
       case 1: phi_go<T, DP, 1>(a, C, lds, st); break;
       case 2: phi_go<T, DP, 2>(a, C, lds, st); break;

@@ -30,6 +30,16 @@ struct CfgMap {
   int M_max;
 };
 
+// Element i of an array at a workgroup-uniform base with a 32-bit offset: the address is a
+// scalar base plus one vector register, instead of a 64-bit vector address per array and
+// index (the phi stream touches up to seven [DP][Np] arrays per channel).
+template <typename T> __device__ inline T& elem(T* base, unsigned i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ inline const T& elem(const T* base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
 // ---------------------------------------------------------------------------------------
 // Channel-mixing tile on the matrix cores: acc[mt][n] += W x for the DP x DP weight W whose
 // operand table Wt (row = input channel) is given, over NT 16-site tiles starting at site i0.
@@ -62,6 +72,31 @@ __device__ inline void mix_tile(const WFrag<T, DP>& w, BL bload, typename Mma<T>
     for (int n = 0; n < NT; ++n)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt][n] = Mma<T>::mma(w.f[mt][ks], bv[n], acc[mt][n]);
+  }
+}
+
+// mix_tile with the weight operands read from the table at each step instead of held in
+// registers (kernels whose register budget has no room for a whole fragment set).
+template <typename T, int DP, int NT, typename BL>
+__device__ inline void mix_tile_ptr(const T* __restrict__ Wt, BL bload, typename Mma<T>::acc (&acc)[DP / 16][NT]) {
+  constexpr int MT = DP / 16, KS = DP / 4;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[mt][n] = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    T bv[NT], af[MT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) bv[n] = bload(4 * ks + (lane >> 4), n);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) af[mt] = elem(Wt, (4 * ks + (lane >> 4)) * DP + 16 * mt + (lane & 15));
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][n] = Mma<T>::mma(af[mt], bv[n], acc[mt][n]);
+    if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -98,16 +133,23 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
   T* as = reinterpret_cast<T*>(smem_raw);
   const int g = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, col = lane & 15;
   const int N = A.N, Np = A.Np, wc = A.w_c;
   const int ld = Np + 2 * wc + 1;  // odd row stride
   T* sp_s = as + DP * ld;          // s' (first block), [Np]
   __shared__ double red[2][4];
-  const long fo = (long)g * DP * Np;
   constexpr int MT = DP / 16;
   using M = Mma<T>;
   using acc_t = typename M::acc;
   const int l = A.l;
   const int span = 16 * NT;  // sites per wave per pass
+  // this configuration's [DP][Np] slices (workgroup-uniform bases)
+  const long fo = (long)g * DP * Np;
+  T* a_out = A.a_out ? A.a_out + fo : nullptr;
+  T* phi_out = A.phi_out ? A.phi_out + fo : nullptr;
+  T* z_out = A.z_out ? A.z_out + fo : nullptr;
+  T* zeta_out = A.zeta_out ? A.zeta_out + fo : nullptr;
+  T* chi_out = A.chi_out + fo;
   if (A.first) {
     const int gg = A.cfg0 + g;
     const int b = A.map.cb[gg], m = A.map.cm[gg];
@@ -130,18 +172,17 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
       int c = idx / Np, i = idx % Np;
       T v = (i < N) ? sp_s[i] * A.tb.wE1[c] + A.tb.wv[c] : T(0);
       as[c * ld + i + wc] = v;
-      if (A.a_out) A.a_out[fo + idx] = v;
+      if (a_out) elem(a_out, idx) = v;
     }
   } else {
-    WFrag<T, DP> wd;
-    wd.load(A.tb.WDt + (long)l * DP * DP, lane);
+    const T* Wd = A.tb.WDt + (long)l * DP * DP;
     const T* x = A.phi_in + fo;
     for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
       acc_t acc[MT][NT];
-      mix_tile<T, DP, NT>(wd, [&](int kc, int n) { return x[(long)kc * Np + i0 + 16 * n + (lane & 15)]; }, acc);
+      mix_tile_ptr<T, DP, NT>(Wd, [&](int kc, int n) { return elem(x, kc * Np + i0 + 16 * n + col); }, acc);
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
-        const int i = i0 + 16 * n + (lane & 15);
+        const int i = i0 + 16 * n + col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -149,7 +190,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
             const int ch = 16 * mt + M::row(lane, r);
             T v = (i < N) ? acc[mt][n][r] + A.tb.wv[l * DP + ch] : T(0);
             as[ch * ld + i + wc] = v;
-            if (A.a_out) A.a_out[fo + (long)ch * Np + i] = v;
+            if (a_out) elem(a_out, ch * Np + i) = v;
           }
       }
     }
@@ -159,53 +200,75 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
   if (wc > 0) {
     for (int idx = threadIdx.x; idx < DP * 2 * wc; idx += 256) {
       int c = idx / (2 * wc), h = idx % (2 * wc);
-      int col, src;
-      if (h < wc) { col = h; src = N - wc + h; }           // sites -wc..-1
-      else { col = N + wc + (h - wc); src = h - wc; }      // sites N..N+wc-1
-      as[c * ld + col] = A.periodic ? as[c * ld + src + wc] : T(0);
+      int cl, src;
+      if (h < wc) { cl = h; src = N - wc + h; }           // sites -wc..-1
+      else { cl = N + wc + (h - wc); src = h - wc; }      // sites N..N+wc-1
+      as[c * ld + cl] = A.periodic ? as[c * ld + src + wc] : T(0);
     }
   }
+  // the block's per-channel vectors in LDS: k [DP], then K_r [2 w_c + 1][DP]
+  T* kvs = sp_s + Np;
+  for (int idx = threadIdx.x; idx < (2 * wc + 2) * DP; idx += 256)
+    kvs[idx] = idx < DP ? A.tb.kv[l * DP + idx] : A.tb.Kc[(long)l * (2 * wc + 1) * DP + idx - DP];
   __syncthreads();
-  WFrag<T, DP> ad;
-  ad.load(A.tb.ADt + (long)l * DP * DP, lane);
-  const T* Kc = A.tb.Kc + (long)l * (2 * wc + 1) * DP;
+  const T* Ad = A.tb.ADt + (long)l * DP * DP;
   double part0 = 0.0, part1 = 0.0;
   for (int i0 = wave * span; i0 < Np; i0 += 4 * span) {
-    acc_t acc[MT][NT];
-    auto phi_at = [&](int kc, int n) -> T {
-      const int i = i0 + 16 * n + (lane & 15);
-      T ph = 0;
-      if (i < N) {
-        T s = A.tb.kv[l * DP + kc];
-        for (int r = -wc; r <= wc; ++r) s += Kc[(r + wc) * DP + kc] * as[kc * ld + i + r + wc];
-        ph = act_fn<T>(A.act, s);
-        if (A.z_out) A.z_out[fo + (long)kc * Np + i] = s;
-      } else if (A.z_out) {
-        A.z_out[fo + (long)kc * Np + i] = T(0);
+    // phi of the tile in operand-B layout (channel 4 ks + lane / 16, site i0 + 16 n + lane % 16):
+    // the taps run outermost so that the lane's DP / 4 channels accumulate side by side
+    T xb[DP / 4][NT];
+#pragma unroll
+    for (int ks = 0; ks < DP / 4; ++ks)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) xb[ks][n] = kvs[4 * ks + q];
+    for (int r = 0; r <= 2 * wc; ++r) {
+      const T* kr = kvs + (r + 1) * DP + q;
+      const T* ar = as + q * ld + i0 + col + r;
+#pragma unroll
+      for (int ks = 0; ks < DP / 4; ++ks) {
+        const T kk = kr[4 * ks];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) xb[ks][n] += kk * ar[4 * ks * ld + 16 * n];
       }
-      if (A.phi_out) A.phi_out[fo + (long)kc * Np + i] = ph;
-      if (A.first) {
-        T h0 = (i < N) ? A.tb.E[kc] * sp_s[i] : T(0);
-        if (A.R_out) A.R_out[fo + (long)kc * Np + i] = h0;
-        A.u_out[fo + (long)kc * Np + i] = h0 + (A.inject ? ph : T(0));
-        part0 += (double)A.tb.Wk[(long)kc * Np + i] * (double)h0;
-        part1 += (double)A.tb.Wk[(long)(DP + kc) * Np + i] * (double)h0;
-      }
-      return ph;
-    };
-    mix_tile<T, DP, NT>(ad, phi_at, acc);
+    }
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
-      const int i = i0 + 16 * n + (lane & 15);
+      const int i = i0 + 16 * n + col;
+      const bool in = i < N;
+      const T h0s = (A.first && in) ? sp_s[i] : T(0);
+#pragma unroll
+      for (int ks = 0; ks < DP / 4; ++ks) {
+        const int kc = 4 * ks + q;
+        const unsigned o = kc * Np + i;
+        const T s = xb[ks][n];
+        const T ph = in ? act_fn<T>(A.act, s) : T(0);
+        if (z_out) elem(z_out, o) = in ? s : T(0);
+        if (phi_out) elem(phi_out, o) = ph;
+        if (A.first) {
+          const T h0 = A.tb.E[kc] * h0s;
+          if (A.R_out) elem(A.R_out + fo, o) = h0;
+          elem(A.u_out + fo, o) = h0 + (A.inject ? ph : T(0));
+          part0 += (double)elem(A.tb.Wk, o) * (double)h0;
+          part1 += (double)elem(A.tb.Wk, DP * Np + o) * (double)h0;
+        }
+        xb[ks][n] = ph;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    acc_t acc[MT][NT];
+    mix_tile_ptr<T, DP, NT>(Ad, [&](int kc, int n) { return xb[kc >> 2][n]; }, acc);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int i = i0 + 16 * n + col;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ch = 16 * mt + M::row(lane, r);
+          const unsigned o = ch * Np + i;
           const T zt = acc[mt][n][r] + A.tb.bv[l * DP + ch];
-          T v = (i < N) ? act_fn<T>(A.act, zt) : T(0);
-          A.chi_out[fo + (long)ch * Np + i] = v;
-          if (A.zeta_out) A.zeta_out[fo + (long)ch * Np + i] = (i < N) ? zt : T(0);
+          elem(chi_out, o) = (i < N) ? act_fn<T>(A.act, zt) : T(0);
+          if (zeta_out) elem(zeta_out, o) = (i < N) ? zt : T(0);
         }
     }
   }
@@ -1693,5 +1756,6 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
     __syncthreads();
   }
 }
+
 
 }  // namespace dn
