@@ -871,11 +871,17 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.act = d.act; a.F = F; a.f0 = f0; a.b0 = bf0; a.Bc = Bf; a.map = fmap; a.spins = spins;
       a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
       a.ext_max = ext_max; a.dyn = dyn;
-      const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
       double fl = 0.0;
       for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
       PScope ps(m, DN_K_SLICE, st, fl * F, (double)F * L * Wmax * d.d * sizeof(T));
-      slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
+      const int Wc = ext_max + 2 * L * wc + 1;
+      const int P = slm_flips(Wc);
+      if (P >= 1 && slm_lds_bytes<T>(DP, P, Wc, wc) <= LDS_MAX) {  // P flips side by side per product
+        slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, slm_lds_bytes<T>(DP, P, Wc, wc), st>>>(a);
+      } else {
+        const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
+        slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
+      }
       HIPCHK(hipGetLastError());
     }
     if (shallow) {

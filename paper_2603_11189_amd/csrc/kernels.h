@@ -1758,4 +1758,240 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
 }
 
 
+// The same slice recompute with its two channel mixes on the matrix cores. A workgroup takes
+// P flips at a time and lays them side by side as the columns of one SLM_CAP-column product
+// per mix: block l forms a' = W_D phi'^(l-1) + w on S_{l-1} (block 1: from s'), the phi
+// stream on S_l from a' with its background halo, and chi' = g(A_D phi'^(l) + b) on S_l,
+// column j = p * W + t for flip p and slice position t (W: the launch's widest slice of
+// that block). Wave w owns output channels 16 w .. 16 w + 15 of both products and holds
+// those rows of W_D and A_D in registers; the element-wise steps use every thread.
+constexpr int SLM_NT = 4;              // 16-column tiles per product
+constexpr int SLM_CAP = 16 * SLM_NT;   // columns per product
+constexpr int SLM_LDC = SLM_CAP + 17;  // odd LDS row stride of the product operand
+
+// Flips per workgroup for slices of at most Wc sites (0: too wide for one product).
+__host__ __device__ inline int slm_flips(int Wc) { return SLM_CAP / Wc; }
+
+// LDS bytes: phi' [DP][SLM_LDC], a' with halo [DP][lda], geometry [P][6].
+__host__ __device__ inline int slm_lda(int P, int Wc, int wc) { return (P * (Wc + 2 * wc)) | 1; }
+template <typename T> __host__ __device__ inline size_t slm_lds_bytes(int DP, int P, int Wc, int wc) {
+  return ((size_t)DP * (SLM_LDC + slm_lda(P, Wc, wc))) * sizeof(T) + (size_t)P * 6 * sizeof(int);
+}
+
+// acc[n] = W x over the first NTU column tiles of phi' (the others are zero).
+template <typename T, int DP, int NTU>
+__device__ inline void slm_prod(const T (&w)[DP / 4], const T* ph, int q, int col,
+                                typename Mma<T>::acc (&acc)[SLM_NT]) {
+#pragma unroll
+  for (int n = 0; n < SLM_NT; ++n) acc[n] = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < DP / 4; ++ks)
+#pragma unroll
+    for (int n = 0; n < NTU; ++n) acc[n] = Mma<T>::mma(w[ks], ph[(4 * ks + q) * SLM_LDC + 16 * n + col], acc[n]);
+}
+
+template <typename T, int DP>
+__global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NTH = 4 * DP;  // DP / 16 waves
+  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
+  const int Wc = A.ext_max + 2 * L * wc + 1;  // widest S_L of the launch
+  const int P = slm_flips(Wc);
+  const int lda = slm_lda(P, Wc, wc);
+  T* ph = reinterpret_cast<T*>(smem_raw);      // phi' [DP][SLM_LDC], column p * W + t
+  T* ab = ph + DP * SLM_LDC;                   // a' [DP][lda], flip p at columns p * AW ..
+  int* gs = reinterpret_cast<int*>(ab + DP * lda);  // per flip: b (-1: none), clo, ext, j0, j1, f
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nfl = A.dyn.count(A.F);
+  const int fg = blockIdx.x * P;
+  if (fg >= nfl) return;
+  const int f0 = A.dyn.first(A.f0);
+  const bool per = A.periodic != 0;
+  auto wrap = [&](int i) { if (per) { i %= N; if (i < 0) i += N; } return i; };
+  auto inside = [&](int i) { return per || (i >= 0 && i < N); };
+  if (tid < P) {
+    const int f = fg + tid;
+    int* g = gs + 6 * tid;
+    if (f < nfl) {
+      const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
+      const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
+      const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
+      int clo = j0, ext = 0;
+      if (j1 >= 0) {
+        if (per) {
+          int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
+          if (d1 <= 2) { clo = j0; ext = d1; }
+          else if (d2 <= 2) { clo = j1; ext = d2; }
+          else ext = -1;
+        } else {
+          clo = j0 < j1 ? j0 : j1;
+          ext = j0 < j1 ? j1 - j0 : j0 - j1;
+          if (ext > 2) ext = -1;
+        }
+      }
+      if (ext < 0 || ext > A.ext_max || (per && ext + 2 * L * wc + 1 > N)) {
+        atomicOr(A.err, 1);
+        ext = 0;
+      }
+      A.geom[f] = make_int4(clo, ext, j0, j1);
+      g[0] = b; g[1] = clo; g[2] = ext; g[3] = j0; g[4] = j1; g[5] = f;
+    } else {
+      g[0] = -1; g[1] = 0; g[2] = 0; g[3] = -1; g[4] = -1; g[5] = -1;
+    }
+  }
+  __syncthreads();
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  const int col = lane & 15, q = lane >> 4;
+  const int AW = Wc + 2 * wc;  // a' block of a flip (the widest)
+  for (int l = 1; l <= L; ++l) {
+    const int lp = l - 1;
+    const int WPm = A.ext_max + 2 * lp * wc + 1;  // column stride of S_{l-1}
+    const int Wlm = WPm + 2 * wc;                 // column stride of S_l
+    // this wave's rows of the block's weights, requested first
+    T wa[DP / 4], wd[DP / 4];
+    {
+      const T* Ad = A.tb.ADt + (long)lp * DP * DP + 16 * wave + col;
+      const T* Wd = A.tb.WDt + (long)lp * DP * DP + 16 * wave + col;
+#pragma unroll
+      for (int ks = 0; ks < DP / 4; ++ks) wa[ks] = Ad[(4 * ks + q) * DP];
+      if (l > 1) {
+#pragma unroll
+        for (int ks = 0; ks < DP / 4; ++ks) wd[ks] = Wd[(4 * ks + q) * DP];
+      }
+    }
+    // the lane's output columns of the A_D product (flip, slice position) and the background
+    // gate of its channels there
+    int pq[SLM_NT], tq[SLM_NT];
+    T c0v[SLM_NT][4];
+#pragma unroll
+    for (int n = 0; n < SLM_NT; ++n) {
+      const int j = 16 * n + col;
+      int p = j / Wlm, t = j - p * Wlm;
+      bool ok = p < P;
+      const int* g = gs + 6 * (ok ? p : 0);
+      ok = ok && g[0] >= 0 && t < g[2] + 2 * l * wc + 1;
+      const int ii = g[1] - l * wc + t;
+      const int site = ok && inside(ii) ? wrap(ii) : g[1];
+      const int bb = g[0] >= 0 ? g[0] - A.b0 : 0;
+      pq[n] = ok ? p : -1;
+      tq[n] = t;
+      const T* chi0 = A.chi0 + ((long)lp * A.Bc + bb) * DP * Np + site;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c0v[n][r] = chi0[(long)(16 * wave + M::row(lane, r)) * Np];
+    }
+    // a' on S_{l-1} at block columns 2 w_c + t
+    if (l == 1) {
+      const int nt1 = A.ext_max + 1;
+#pragma unroll 2
+      for (int idx = tid; idx < DP * P * nt1; idx += NTH) {
+        const int c = idx % DP, pt = idx / DP;
+        const int p = pt / nt1, t = pt - p * nt1;
+        const int* g = gs + 6 * p;
+        if (g[0] < 0 || t > g[2]) continue;
+        const int site = wrap(g[1] + t);
+        T v = 0;
+        if (inside(g[1] + t)) {
+          T sv = (T)A.spins[(long)g[0] * N + site];
+          if (site == g[3] || site == g[4]) sv = -sv;
+          v = sv * A.tb.wE1[c] + A.tb.wv[c];
+        }
+        ab[c * lda + p * AW + 2 * wc + t] = v;
+      }
+    } else {
+      acc_t acc[SLM_NT];
+      const int ntw = (P * WPm + 15) / 16;  // column tiles holding S_{l-1}
+      switch (ntw) {
+        case 1: slm_prod<T, DP, 1>(wd, ph, q, col, acc); break;
+        case 2: slm_prod<T, DP, 2>(wd, ph, q, col, acc); break;
+        case 3: slm_prod<T, DP, 3>(wd, ph, q, col, acc); break;
+        default: slm_prod<T, DP, SLM_NT>(wd, ph, q, col, acc); break;
+      }
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        const int j = 16 * n + col;
+        const int p = j / WPm, t = j - p * WPm;
+        if (p < P) {
+          const int* g = gs + 6 * p;
+          const int WP = g[2] + 2 * lp * wc + 1;
+          const int lo = g[1] - lp * wc;
+          if (g[0] >= 0 && t < WP) {
+            const bool in = inside(lo + t);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ch = 16 * wave + M::row(lane, r);
+              ab[ch * lda + p * AW + 2 * wc + t] = in ? acc[n][r] + A.tb.wv[lp * DP + ch] : T(0);
+            }
+          }
+        }
+      }
+    }
+    // the background halo: 2 w_c sites on either side of S_{l-1}
+    {
+      const int nh = 4 * wc;
+#pragma unroll 4
+      for (int idx = tid; idx < DP * P * nh; idx += NTH) {
+        const int c = idx % DP, hp = idx / DP;
+        const int p = hp / nh, h = hp - p * nh;
+        const int* g = gs + 6 * p;
+        if (g[0] < 0) continue;
+        const int WP = g[2] + 2 * lp * wc + 1;
+        const int u = h < 2 * wc ? h : WP + h;
+        const int jj = g[1] - lp * wc - 2 * wc + u;  // block column 0 is site clo - (l + 1) w_c
+        ab[c * lda + p * AW + u] =
+            inside(jj) ? A.a0[(((long)lp * A.Bc + (g[0] - A.b0)) * DP + c) * Np + wrap(jj)] : T(0);
+      }
+    }
+    __syncthreads();
+    // phi' on S_l: thread (channel c, part k) takes columns k, k + 4, ... of the channel;
+    // the channel's taps in registers (w_c <= 3)
+    {
+      const int c = tid % DP, part = tid / DP;
+      T kr[7];
+#pragma unroll
+      for (int u = 0; u < 7; ++u) kr[u] = u <= 2 * wc ? A.tb.Kc[((long)lp * (2 * wc + 1) + u) * DP + c] : T(0);
+      const T kv = A.tb.kv[lp * DP + c];
+      const T* ar = ab + c * lda;
+      T* pr = ph + c * SLM_LDC;
+      for (int j = part; j < P * Wlm; j += 4) {
+        const int p = j / Wlm, t = j - p * Wlm;
+        const int* g = gs + 6 * p;
+        if (g[0] < 0 || t >= g[2] + 2 * l * wc + 1) continue;
+        const T* a = ar + p * AW + t;
+        T sacc = kv;
+#pragma unroll
+        for (int u = 0; u < 7; ++u)
+          if (u <= 2 * wc) sacc += kr[u] * a[u];
+        pr[j] = inside(g[1] - l * wc + t) ? act_fn<T>(A.act, sacc) : T(0);
+      }
+    }
+    __syncthreads();
+    // chi' and dchi = chi' - chi0 on S_l
+    {
+      acc_t acc[SLM_NT];
+      const int nta = (P * Wlm + 15) / 16;  // column tiles holding S_l
+      switch (nta) {
+        case 1: slm_prod<T, DP, 1>(wa, ph, q, col, acc); break;
+        case 2: slm_prod<T, DP, 2>(wa, ph, q, col, acc); break;
+        case 3: slm_prod<T, DP, 3>(wa, ph, q, col, acc); break;
+        default: slm_prod<T, DP, SLM_NT>(wa, ph, q, col, acc); break;
+      }
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        if (pq[n] < 0) continue;
+        const int* g = gs + 6 * pq[n];
+        const int t = tq[n];
+        const bool in = inside(g[1] - l * wc + t);
+        T* out = A.dchi + (((long)g[5] * L + lp) * A.Wmax + t) * DP;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * wave + M::row(lane, r);
+          out[ch] = in ? act_fn<T>(A.act, acc[n][r] + A.tb.bv[lp * DP + ch]) - c0v[n][r] : T(0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dn
