@@ -10,7 +10,9 @@ The default workload is the long-range Ising chain with N=256, four blocks, d=64
 
 With --workload ragged32 it measures the ragged batch instead: 32 instances of different
 chain lengths, depths and batch sizes (one model each) submitted together as one recorded
-HIP graph; a step is one pass over all 37011 samples.
+HIP graph; a step is one pass over all 37011 samples. --workload ragged64_small does the same
+for 64 small instances (N <= 128, one or two blocks, d of 16 or 32, at most 256 samples each),
+where the host work of per-instance calls matters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -265,7 +267,7 @@ def main():
     import dn_inputs as di
     from paper_2603_11189_amd import _lib as L
 
-    if args.workload == "ragged32":
+    if args.workload in ("ragged32", "ragged64_small"):
         bench_ragged(args)
         return
     if args.sweep:
@@ -561,7 +563,9 @@ def bench_ragged(args) -> None:
     import dn_inputs as di
     from paper_2603_11189_amd import _lib as L
 
-    ws = di.ragged_instances()
+    small = args.workload == "ragged64_small"
+    ws = di.ragged_small_instances() if small else di.ragged_instances()
+    tag = args.workload
     dev = torch.device("cuda")
     torch.cuda.init()
     L.lib()
@@ -587,15 +591,15 @@ def bench_ragged(args) -> None:
         return (time.perf_counter() - t0) / steps
 
     graph = lambda: L.ragged_eloc(models, hams, spins, lps, els, n_streams=4, mode="graph")
-    log(f"[bench] ragged32: {len(ws)} instances, {Btot} samples; recording + warmup {args.warmup}")
+    log(f"[bench] {tag}: {len(ws)} instances, {Btot} samples; recording + warmup {args.warmup}")
     for _ in range(max(1, args.warmup)):
         graph()
     sec = timed(graph, args.steps)
-    log(f"[bench] ragged32 graph: {sec * 1e3:.1f} ms/step, {Btot / sec:.1f} samples/s")
+    log(f"[bench] {tag} graph: {sec * 1e3:.1f} ms/step, {Btot / sec:.1f} samples/s")
     eager = lambda: L.ragged_eloc(models, hams, spins, lps, els, n_streams=4, mode="eager")
     eager()
     sec_eager = timed(eager, max(1, args.steps // 2))
-    log(f"[bench] ragged32 eager 4 streams: {sec_eager * 1e3:.1f} ms/step")
+    log(f"[bench] {tag} eager 4 streams: {sec_eager * 1e3:.1f} ms/step")
     bufs = [(lps[i], torch.empty((w.B, w.model.N), dtype=torch.float64, device=dev), els[i])
             for i, w in enumerate(ws)]
 
@@ -605,15 +609,19 @@ def bench_ragged(args) -> None:
 
     per_instance()
     sec_seq = timed(per_instance, max(1, args.steps // 2))
-    log(f"[bench] ragged32 per-instance calls: {sec_seq * 1e3:.1f} ms/step")
+    log(f"[bench] {tag} per-instance calls: {sec_seq * 1e3:.1f} ms/step")
     out = {
-        "metric": "E_loc samples/sec, ragged batch of 32 instances, ABACUS",
+        "metric": f"E_loc samples/sec, ragged batch of {len(ws)} instances, ABACUS",
         "value": Btot / sec, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "ragged32", "instances": len(ws), "N": "U{32..512}", "L": "U{2,3,4}",
-                   "B": "U{256..2048}", "samples": Btot, "d": 64, "s": 32,
-                   "hamiltonian": "lrtfim open J=1 alpha=3 h=1", "submission": "one HIP graph, 4 streams"},
+        "config": ({"workload": tag, "instances": len(ws), "N": "U{16..128}", "L": "U{1,2}",
+                    "B": "U{32..256}", "samples": Btot, "d": "{16,32}", "s": "d/2",
+                    "hamiltonian": "lrtfim open J=1 alpha=3 h=1", "submission": "one HIP graph, 4 streams"}
+                   if small else
+                   {"workload": tag, "instances": len(ws), "N": "U{32..512}", "L": "U{2,3,4}",
+                    "B": "U{256..2048}", "samples": Btot, "d": 64, "s": 32,
+                    "hamiltonian": "lrtfim open J=1 alpha=3 h=1", "submission": "one HIP graph, 4 streams"}),
         "eager_4_streams": {"ms_per_step": sec_eager * 1e3, "value": Btot / sec_eager},
         "per_instance_calls": {"ms_per_step": sec_seq * 1e3, "value": Btot / sec_seq},
     }
@@ -632,7 +640,7 @@ def bench_ragged(args) -> None:
         dom = max(tot, key=lambda k: tot[k][0])
         ms, n, fl, by = tot[dom]
         achieved = fl / (ms * 1e-3) / 1e12
-        peak, basis = mfma_peak(dom, "fp32", "split3", 64)
+        peak, basis = mfma_peak(dom, "fp32", "split3", max(w.model.d for w in ws))
         out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
                            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None, "peak_basis": basis,
                            "avg_launch_ms": ms / n, "algorithmic_flops_per_launch": fl / n,

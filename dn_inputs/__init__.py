@@ -170,6 +170,22 @@ WORKLOADS: Dict[str, Workload] = {
 }
 
 
+def ragged_small_instances(n_inst: int = 64, base_seed: int = 3500):
+    """Many small instances, where per-call host work matters: N ~ U{16..128}, L ~ U{1,2},
+    d ~ {16, 32} (state size d / 2), B ~ U{32..256}."""
+    out = []
+    for i in range(n_inst):
+        rng = np.random.Generator(np.random.PCG64(base_seed + i))
+        N = int(rng.integers(16, 129))
+        L = int(rng.integers(1, 3))
+        d = int(rng.choice([16, 32]))
+        B = int(rng.integers(32, 257))
+        out.append(Workload(f"ragged_small_{i}", ModelShape(N, L, d, d // 2, act="silu", bc="open"),
+                            HamSpec("lrtfim", "open", J=1.0, alpha=3.0, h=1.0), B,
+                            6000 + i, 7000 + i))
+    return out
+
+
 def ragged_instances(n_inst: int = 32, base_seed: int = 3000):
     """The ragged batch: instance i draws N ~ U{32..512}, L ~ U{2,3,4}, B ~ U{256..2048}."""
     out = []
