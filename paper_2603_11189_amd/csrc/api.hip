@@ -770,6 +770,24 @@ dn_status launch_flip12(dn_model* m, Flip12Args<T> a, int F, hipStream_t st, int
   return DN_OK;
 }
 
+// The fused slice recompute + per-flip update of one- and two-block networks (shallow_kernel):
+// one workgroup of DP / 16 waves per P flips.
+template <typename T, int DP, bool TWO>
+dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, int F, int P, int Wc, double slice_fl,
+                         hipStream_t st, int ext) {
+  if (F <= 0) return DN_OK;
+  const size_t lds = slm_lds_bytes<T>(DP, P, Wc, m->desc.w_c);
+  allow_lds(shallow_kernel<T, DP, TWO>, lds);
+  const dn_model_desc& d = m->desc;
+  const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;
+  const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
+  const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
+  PScope ps(m, DN_K_TAIL, st, (fl + slice_fl) * F, by * F);
+  shallow_kernel<T, DP, TWO><<<(F + P - 1) / P, 4 * DP, lds, st>>>(sa, a);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
 // ABACUS: background forward with caches, the output links, the slice recompute and the
 // per-flip update, then the float64 log-ratio. With h_offs the flip counts of each chunk are
 // host values; without it every flip launch is sized for Bc * M_max and reads its count from
@@ -865,22 +883,37 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     const int nt = Np / 64;
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
-    {
-      SliceArgs<T> a{};
+    SliceArgs<T> sa{};
+    sa.tb = tb; sa.N = d.N; sa.Np = Np; sa.L = L; sa.w_c = wc; sa.periodic = d.bc == DN_BC_PERIODIC;
+    sa.act = d.act; sa.F = F; sa.f0 = f0; sa.b0 = bf0; sa.Bc = Bf; sa.map = fmap; sa.spins = spins;
+    sa.a0 = a0; sa.chi0 = chi0; sa.dchi = dchi; sa.geom = geom; sa.Wmax = Wmax; sa.err = (int*)perr;
+    sa.ext_max = ext_max; sa.dyn = dyn;
+    double slice_fl = 0.0;
+    for (int l = 1; l <= L; ++l) slice_fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
+    const int Wc = ext_max + 2 * L * wc + 1;
+    const int P = slm_flips(Wc);
+    const bool slm = P >= 1 && slm_lds_bytes<T>(DP, P, Wc, wc) <= LDS_MAX;  // P flips side by side per product
+    if (shallow) {
+      Flip12Args<T> a{};
       a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
-      a.act = d.act; a.F = F; a.f0 = f0; a.b0 = bf0; a.Bc = Bf; a.map = fmap; a.spins = spins;
-      a.a0 = a0; a.chi0 = chi0; a.dchi = dchi; a.geom = geom; a.Wmax = Wmax; a.err = (int*)perr;
-      a.ext_max = ext_max; a.dyn = dyn;
-      double fl = 0.0;
-      for (int l = 1; l <= L; ++l) fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
-      PScope ps(m, DN_K_SLICE, st, fl * F, (double)F * L * Wmax * d.d * sizeof(T));
-      const int Wc = ext_max + 2 * L * wc + 1;
-      const int P = slm_flips(Wc);
-      if (P >= 1 && slm_lds_bytes<T>(DP, P, Wc, wc) <= LDS_MAX) {  // P flips side by side per product
-        slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, slm_lds_bytes<T>(DP, P, Wc, wc), st>>>(a);
+      a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
+      a.Wmax = Wmax; a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
+      a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.dyn = dyn;
+      if (slm) {  // slice recompute and per-flip update in one kernel
+        if (L == 2) STCHK((launch_shallow<T, DP, true>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
+        else STCHK((launch_shallow<T, DP, false>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
+        continue;
+      }
+    }
+    {
+      PScope ps(m, DN_K_SLICE, st, slice_fl * F, (double)F * L * Wmax * d.d * sizeof(T));
+      if (slm) {
+        const size_t lds = slm_lds_bytes<T>(DP, P, Wc, wc);
+        allow_lds(slice_mma_kernel<T, DP>, lds);
+        slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, lds, st>>>(sa);
       } else {
         const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
-        slice_kernel<T, DP><<<F, 64, lds, st>>>(a);
+        slice_kernel<T, DP><<<F, 64, lds, st>>>(sa);
       }
       HIPCHK(hipGetLastError());
     }

@@ -1768,98 +1768,118 @@ __global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
 constexpr int SLM_NT = 4;              // 16-column tiles per product
 constexpr int SLM_CAP = 16 * SLM_NT;   // columns per product
 constexpr int SLM_LDC = SLM_CAP + 17;  // odd LDS row stride of the product operand
+constexpr int SLM_GS = 8;              // per flip: b (-1: none), clo, ext, j0, j1, f, c_a, c_b
 
 // Flips per workgroup for slices of at most Wc sites (0: too wide for one product).
 __host__ __device__ inline int slm_flips(int Wc) { return SLM_CAP / Wc; }
 
-// LDS bytes: phi' [DP][SLM_LDC], a' with halo [DP][lda], geometry [P][6].
-__host__ __device__ inline int slm_lda(int P, int Wc, int wc) { return (P * (Wc + 2 * wc)) | 1; }
+// LDS bytes: phi' [DP][SLM_LDC], a' with halo [DP][lda], geometry [P][SLM_GS].
+// (at least SLM_CAP columns, so that a product may also read its operand from this buffer)
+__host__ __device__ inline int slm_lda(int P, int Wc, int wc) {
+  const int w = P * (Wc + 2 * wc);
+  return (w > SLM_CAP ? w : SLM_CAP) | 1;
+}
 template <typename T> __host__ __device__ inline size_t slm_lds_bytes(int DP, int P, int Wc, int wc) {
-  return ((size_t)DP * (SLM_LDC + slm_lda(P, Wc, wc))) * sizeof(T) + (size_t)P * 6 * sizeof(int);
+  return ((size_t)DP * (SLM_LDC + slm_lda(P, Wc, wc))) * sizeof(T) + (size_t)P * SLM_GS * sizeof(int);
 }
 
-// acc[n] = W x over the first NTU column tiles of phi' (the others are zero).
+// acc[n] = W x over the first NTU column tiles of x (row stride ldx; the other tiles are zero).
 template <typename T, int DP, int NTU>
-__device__ inline void slm_prod(const T (&w)[DP / 4], const T* ph, int q, int col,
+__device__ inline void slm_prod(const T (&w)[DP / 4], const T* x, int ldx, int q, int col,
                                 typename Mma<T>::acc (&acc)[SLM_NT]) {
 #pragma unroll
   for (int n = 0; n < SLM_NT; ++n) acc[n] = typename Mma<T>::acc{0, 0, 0, 0};
 #pragma unroll
   for (int ks = 0; ks < DP / 4; ++ks)
 #pragma unroll
-    for (int n = 0; n < NTU; ++n) acc[n] = Mma<T>::mma(w[ks], ph[(4 * ks + q) * SLM_LDC + 16 * n + col], acc[n]);
+    for (int n = 0; n < NTU; ++n) acc[n] = Mma<T>::mma(w[ks], x[(4 * ks + q) * ldx + 16 * n + col], acc[n]);
+}
+template <typename T, int DP>
+__device__ inline void slm_prod_n(int nt, const T (&w)[DP / 4], const T* x, int ldx, int q, int col,
+                                  typename Mma<T>::acc (&acc)[SLM_NT]) {
+  switch (nt) {
+    case 1: slm_prod<T, DP, 1>(w, x, ldx, q, col, acc); break;
+    case 2: slm_prod<T, DP, 2>(w, x, ldx, q, col, acc); break;
+    case 3: slm_prod<T, DP, 3>(w, x, ldx, q, col, acc); break;
+    default: slm_prod<T, DP, SLM_NT>(w, x, ldx, q, col, acc); break;
+  }
 }
 
-template <typename T, int DP>
-__global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int NTH = 4 * DP;  // DP / 16 waves
-  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
-  const int Wc = A.ext_max + 2 * L * wc + 1;  // widest S_L of the launch
-  const int P = slm_flips(Wc);
-  const int lda = slm_lda(P, Wc, wc);
-  T* ph = reinterpret_cast<T*>(smem_raw);      // phi' [DP][SLM_LDC], column p * W + t
-  T* ab = ph + DP * SLM_LDC;                   // a' [DP][lda], flip p at columns p * AW ..
-  int* gs = reinterpret_cast<int*>(ab + DP * lda);  // per flip: b (-1: none), clo, ext, j0, j1, f
+// This wave's 16 rows of a weight operand table (row = input channel) in operand-A order.
+template <typename T, int DP> __device__ inline void slm_rows(const T* Wt, int wave, int lane, T (&w)[DP / 4]) {
+#pragma unroll
+  for (int ks = 0; ks < DP / 4; ++ks) w[ks] = Wt[(4 * ks + (lane >> 4)) * DP + 16 * wave + (lane & 15)];
+}
+
+// Cluster geometry of flips fg .. fg + P - 1 into gs (threads < P; c_a, c_b = -2 s at the
+// cluster sites, c_b = 0 for one site). Clusters the slice recurrence does not cover set err.
+template <typename T>
+__device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int fg, int nfl, int f0, bool write_geom) {
+  const int N = A.N, L = A.L, wc = A.w_c;
+  const bool per = A.periodic != 0;
+  const int tid = threadIdx.x;
+  if (tid >= P) return;
+  const int f = fg + tid;
+  int* g = gs + SLM_GS * tid;
+  if (f >= nfl) {
+    g[0] = -1; g[1] = 0; g[2] = 0; g[3] = -1; g[4] = -1; g[5] = -1; g[6] = 0; g[7] = 0;
+    return;
+  }
+  const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
+  const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
+  const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
+  int clo = j0, ext = 0;
+  if (j1 >= 0) {
+    if (per) {
+      int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
+      if (d1 <= 2) { clo = j0; ext = d1; }
+      else if (d2 <= 2) { clo = j1; ext = d2; }
+      else ext = -1;
+    } else {
+      clo = j0 < j1 ? j0 : j1;
+      ext = j0 < j1 ? j1 - j0 : j0 - j1;
+      if (ext > 2) ext = -1;
+    }
+  }
+  if (ext < 0 || ext > A.ext_max || (per && ext + 2 * L * wc + 1 > N)) {
+    atomicOr(A.err, 1);
+    ext = 0;
+  }
+  if (write_geom) A.geom[f] = make_int4(clo, ext, j0, j1);
+  const int8_t* sp = A.spins + (long)b * N;
+  int zb = clo + ext;
+  if (per) zb %= N;
+  g[0] = b; g[1] = clo; g[2] = ext; g[3] = j0; g[4] = j1; g[5] = f;
+  g[6] = -2 * sp[clo];
+  g[7] = j1 >= 0 ? -2 * sp[zb] : 0;
+}
+
+// Blocks 1 .. L of the slice recompute (L = LF when LF > 0). epi(l, n, r, v) receives the
+// vertex change v = chi'(l) - chi0(l) of the lane's channel 16 w + row(lane, r) at its
+// column 16 n + lane % 16 of S_l (zero for columns that hold no slice site of a flip).
+template <typename T, int DP, int LF, typename EPI>
+__device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int* gs, int P, int lda, EPI&& epi) {
+  constexpr int NTH = 4 * DP;
+  const int N = A.N, Np = A.Np, wc = A.w_c;
+  const int L = LF > 0 ? LF : A.L;
+  const int Wc = A.ext_max + 2 * L * wc + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nfl = A.dyn.count(A.F);
-  const int fg = blockIdx.x * P;
-  if (fg >= nfl) return;
-  const int f0 = A.dyn.first(A.f0);
   const bool per = A.periodic != 0;
   auto wrap = [&](int i) { if (per) { i %= N; if (i < 0) i += N; } return i; };
   auto inside = [&](int i) { return per || (i >= 0 && i < N); };
-  if (tid < P) {
-    const int f = fg + tid;
-    int* g = gs + 6 * tid;
-    if (f < nfl) {
-      const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
-      const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
-      const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
-      int clo = j0, ext = 0;
-      if (j1 >= 0) {
-        if (per) {
-          int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
-          if (d1 <= 2) { clo = j0; ext = d1; }
-          else if (d2 <= 2) { clo = j1; ext = d2; }
-          else ext = -1;
-        } else {
-          clo = j0 < j1 ? j0 : j1;
-          ext = j0 < j1 ? j1 - j0 : j0 - j1;
-          if (ext > 2) ext = -1;
-        }
-      }
-      if (ext < 0 || ext > A.ext_max || (per && ext + 2 * L * wc + 1 > N)) {
-        atomicOr(A.err, 1);
-        ext = 0;
-      }
-      A.geom[f] = make_int4(clo, ext, j0, j1);
-      g[0] = b; g[1] = clo; g[2] = ext; g[3] = j0; g[4] = j1; g[5] = f;
-    } else {
-      g[0] = -1; g[1] = 0; g[2] = 0; g[3] = -1; g[4] = -1; g[5] = -1;
-    }
-  }
-  __syncthreads();
   using M = Mma<T>;
   using acc_t = typename M::acc;
   const int col = lane & 15, q = lane >> 4;
   const int AW = Wc + 2 * wc;  // a' block of a flip (the widest)
-  for (int l = 1; l <= L; ++l) {
+#pragma unroll
+  for (int l = 1; l <= (LF > 0 ? LF : A.L); ++l) {
     const int lp = l - 1;
     const int WPm = A.ext_max + 2 * lp * wc + 1;  // column stride of S_{l-1}
     const int Wlm = WPm + 2 * wc;                 // column stride of S_l
     // this wave's rows of the block's weights, requested first
     T wa[DP / 4], wd[DP / 4];
-    {
-      const T* Ad = A.tb.ADt + (long)lp * DP * DP + 16 * wave + col;
-      const T* Wd = A.tb.WDt + (long)lp * DP * DP + 16 * wave + col;
-#pragma unroll
-      for (int ks = 0; ks < DP / 4; ++ks) wa[ks] = Ad[(4 * ks + q) * DP];
-      if (l > 1) {
-#pragma unroll
-        for (int ks = 0; ks < DP / 4; ++ks) wd[ks] = Wd[(4 * ks + q) * DP];
-      }
-    }
+    slm_rows<T, DP>(A.tb.ADt + (long)lp * DP * DP, wave, lane, wa);
+    if (l > 1) slm_rows<T, DP>(A.tb.WDt + (long)lp * DP * DP, wave, lane, wd);
     // the lane's output columns of the A_D product (flip, slice position) and the background
     // gate of its channels there
     int pq[SLM_NT], tq[SLM_NT];
@@ -1869,7 +1889,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
       const int j = 16 * n + col;
       int p = j / Wlm, t = j - p * Wlm;
       bool ok = p < P;
-      const int* g = gs + 6 * (ok ? p : 0);
+      const int* g = gs + SLM_GS * (ok ? p : 0);
       ok = ok && g[0] >= 0 && t < g[2] + 2 * l * wc + 1;
       const int ii = g[1] - l * wc + t;
       const int site = ok && inside(ii) ? wrap(ii) : g[1];
@@ -1887,7 +1907,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
       for (int idx = tid; idx < DP * P * nt1; idx += NTH) {
         const int c = idx % DP, pt = idx / DP;
         const int p = pt / nt1, t = pt - p * nt1;
-        const int* g = gs + 6 * p;
+        const int* g = gs + SLM_GS * p;
         if (g[0] < 0 || t > g[2]) continue;
         const int site = wrap(g[1] + t);
         T v = 0;
@@ -1900,19 +1920,13 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
       }
     } else {
       acc_t acc[SLM_NT];
-      const int ntw = (P * WPm + 15) / 16;  // column tiles holding S_{l-1}
-      switch (ntw) {
-        case 1: slm_prod<T, DP, 1>(wd, ph, q, col, acc); break;
-        case 2: slm_prod<T, DP, 2>(wd, ph, q, col, acc); break;
-        case 3: slm_prod<T, DP, 3>(wd, ph, q, col, acc); break;
-        default: slm_prod<T, DP, SLM_NT>(wd, ph, q, col, acc); break;
-      }
+      slm_prod_n<T, DP>((P * WPm + 15) / 16, wd, ph, SLM_LDC, q, col, acc);
 #pragma unroll
       for (int n = 0; n < SLM_NT; ++n) {
         const int j = 16 * n + col;
         const int p = j / WPm, t = j - p * WPm;
         if (p < P) {
-          const int* g = gs + 6 * p;
+          const int* g = gs + SLM_GS * p;
           const int WP = g[2] + 2 * lp * wc + 1;
           const int lo = g[1] - lp * wc;
           if (g[0] >= 0 && t < WP) {
@@ -1933,7 +1947,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
       for (int idx = tid; idx < DP * P * nh; idx += NTH) {
         const int c = idx % DP, hp = idx / DP;
         const int p = hp / nh, h = hp - p * nh;
-        const int* g = gs + 6 * p;
+        const int* g = gs + SLM_GS * p;
         if (g[0] < 0) continue;
         const int WP = g[2] + 2 * lp * wc + 1;
         const int u = h < 2 * wc ? h : WP + h;
@@ -1955,7 +1969,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
       T* pr = ph + c * SLM_LDC;
       for (int j = part; j < P * Wlm; j += 4) {
         const int p = j / Wlm, t = j - p * Wlm;
-        const int* g = gs + 6 * p;
+        const int* g = gs + SLM_GS * p;
         if (g[0] < 0 || t >= g[2] + 2 * l * wc + 1) continue;
         const T* a = ar + p * AW + t;
         T sacc = kv;
@@ -1969,29 +1983,48 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
     // chi' and dchi = chi' - chi0 on S_l
     {
       acc_t acc[SLM_NT];
-      const int nta = (P * Wlm + 15) / 16;  // column tiles holding S_l
-      switch (nta) {
-        case 1: slm_prod<T, DP, 1>(wa, ph, q, col, acc); break;
-        case 2: slm_prod<T, DP, 2>(wa, ph, q, col, acc); break;
-        case 3: slm_prod<T, DP, 3>(wa, ph, q, col, acc); break;
-        default: slm_prod<T, DP, SLM_NT>(wa, ph, q, col, acc); break;
-      }
+      slm_prod_n<T, DP>((P * Wlm + 15) / 16, wa, ph, SLM_LDC, q, col, acc);
 #pragma unroll
       for (int n = 0; n < SLM_NT; ++n) {
-        if (pq[n] < 0) continue;
-        const int* g = gs + 6 * pq[n];
-        const int t = tq[n];
-        const bool in = inside(g[1] - l * wc + t);
-        T* out = A.dchi + (((long)g[5] * L + lp) * A.Wmax + t) * DP;
+        const bool ok = pq[n] >= 0;
+        const int* g = gs + SLM_GS * (ok ? pq[n] : 0);
+        const bool in = ok && inside(g[1] - l * wc + tq[n]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ch = 16 * wave + M::row(lane, r);
-          out[ch] = in ? act_fn<T>(A.act, acc[n][r] + A.tb.bv[lp * DP + ch]) - c0v[n][r] : T(0);
+          epi(l, n, r, in ? act_fn<T>(A.act, acc[n][r] + A.tb.bv[lp * DP + ch]) - c0v[n][r] : T(0));
         }
       }
     }
     __syncthreads();
   }
+}
+
+template <typename T, int DP>
+__global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int Wc = A.ext_max + 2 * A.L * A.w_c + 1;  // widest S_L of the launch
+  const int P = slm_flips(Wc);
+  const int lda = slm_lda(P, Wc, A.w_c);
+  T* ph = reinterpret_cast<T*>(smem_raw);      // phi' [DP][SLM_LDC], column p * W + t
+  T* ab = ph + DP * SLM_LDC;                   // a' [DP][lda], flip p at columns p * AW ..
+  int* gs = reinterpret_cast<int*>(ab + DP * lda);
+  const int nfl = A.dyn.count(A.F);
+  const int fg = blockIdx.x * P;
+  if (fg >= nfl) return;
+  slm_geometry(A, gs, P, fg, nfl, A.dyn.first(A.f0), true);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, wc = A.w_c;
+  slm_layers<T, DP, 0>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) {
+    const int Wlm = A.ext_max + 2 * l * wc + 1;
+    const int j = 16 * n + col;
+    const int p = j / Wlm, t = j - p * Wlm;
+    if (p >= P) return;
+    const int* g = gs + SLM_GS * p;
+    if (g[0] < 0 || t >= g[2] + 2 * l * wc + 1) return;
+    const int ch = 16 * wave + Mma<T>::row(lane, r);
+    A.dchi[(((long)g[5] * A.L + (l - 1)) * A.Wmax + t) * DP + ch] = v;
+  });
 }
 
 }  // namespace dn

@@ -500,4 +500,226 @@ __global__ __launch_bounds__(64 * flip12_waves<T>()) void flip12_kernel(Flip12Ar
   }
 }
 
+// One or two blocks in one kernel per group of flips: the slice recompute (slm_layers) keeps
+// each flip's vertex changes in registers, and the per-flip update of flip12_kernel follows on
+// the same matrix-core columns (flip p, slice position t), so neither the vertex changes nor
+// the cluster geometry go through HBM. Wave w owns channels 16 w .. 16 w + 15 of every
+// product (U^(1); V^(2) and U^(2) for two blocks) with those weight rows in registers; the
+// read-outs are summed per column over the wave's channels, then over waves and a flip's
+// columns in LDS.
+template <typename T, int DP, bool TWO>
+__global__ __launch_bounds__(4 * DP) void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int LF = TWO ? 2 : 1, NW = DP / 16;
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  const int N = A.N, Np = A.Np, wc = A.w_c;
+  const int Wc = A.ext_max + 2 * LF * wc + 1;  // widest S_L of the launch
+  const int P = slm_flips(Wc);
+  const int lda = slm_lda(P, Wc, wc);
+  T* ph = reinterpret_cast<T*>(smem_raw);      // [DP][SLM_LDC]
+  T* ab = ph + DP * SLM_LDC;                   // [DP][lda]
+  int* gs = reinterpret_cast<int*>(ab + DP * lda);
+  const int nfl = A.dyn.count(A.F);
+  const int fg = blockIdx.x * P;
+  if (fg >= nfl) return;
+  const int f0 = A.dyn.first(A.f0);
+  slm_geometry(A, gs, P, fg, nfl, f0, false);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
+  T dch[LF][SLM_NT][4];
+  slm_layers<T, DP, LF>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) { dch[l - 1][n][r] = v; });
+  const bool per = A.periodic != 0;
+  auto wrap = [&](int i) { if (per) { i %= N; if (i < 0) i += N; } return i; };
+  auto inside = [&](int i) { return per || (i >= 0 && i < N); };
+  const int TS = tap_stride(Np), TO = tap_off(Np);
+  const long fld = (long)DP * Np;
+  const int W1m = A.ext_max + 2 * wc + 1, W2m = W1m + 2 * wc;  // column strides of S_1, S_2
+  T u1[DP / 4], v2[DP / 4], u2[DP / 4];
+  slm_rows<T, DP>(A.tb.Ut, wave, lane, u1);
+  if constexpr (TWO) {
+    slm_rows<T, DP>(A.tb.Vt + (long)DP * DP, wave, lane, v2);
+    slm_rows<T, DP>(A.tb.Ut + (long)DP * DP, wave, lane, u2);
+  }
+  // the lane's S_1 columns: x1 = dchi1 (p0^(1) + c_a Pq(i - z_a) + c_b Pq(i - z_b)) to LDS
+#pragma unroll
+  for (int n = 0; n < SLM_NT; ++n) {
+    const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
+    const int* g = gs + SLM_GS * (p < P ? p : 0);
+    const int s1u = g[1] - wc + t;
+    const bool v1 = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
+    const int s1 = v1 ? wrap(s1u) : 0;
+    const T* p01 = F.p0 + (long)(v1 ? g[0] - A.b0 : 0) * fld + s1;
+    const T ca = (T)g[6], cb = (T)g[7];
+    const int za = g[1], zb = g[1] + g[2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ch = 16 * wave + M::row(lane, r);
+      T x = 0;
+      if (v1) {
+        const T* pq = A.tb.Pq + (long)ch * TS + TO + s1u;
+        x = dch[0][n][r] * (p01[(long)ch * Np] + ca * pq[-za] + cb * pq[-zb]);
+      }
+      ph[ch * SLM_LDC + j] = x;
+    }
+  }
+  __syncthreads();
+  // e1 = U^(1) x1; its read-out with T^(1) (one block: Wk), and e^(0) = c_z E at the cluster
+  // sites with T^(0), per column
+  double oa0[SLM_NT], oa1[SLM_NT];
+  {
+    acc_t e1[SLM_NT];
+    slm_prod_n<T, DP>((P * W1m + 15) / 16, u1, ph, SLM_LDC, q, col, e1);
+#pragma unroll
+    for (int n = 0; n < SLM_NT; ++n) {
+      oa0[n] = 0.0;
+      oa1[n] = 0.0;
+      const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
+      const int* g = gs + SLM_GS * (p < P ? p : 0);
+      const int s1u = g[1] - wc + t;
+      const bool v1 = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
+      if (v1) {
+        const int s1 = wrap(s1u);
+        const long bl = g[0] - A.b0;
+        const T* r0 = (TWO ? F.T1 + 2 * bl * fld : A.tb.Wk) + s1;
+        T q0 = 0, q1 = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long o = (long)(16 * wave + M::row(lane, r)) * Np;
+          q0 += r0[o] * e1[n][r];
+          q1 += r0[fld + o] * e1[n][r];
+        }
+        oa0[n] = (double)q0;
+        oa1[n] = (double)q1;
+        const bool at_a = s1u == g[1], at_b = g[4] >= 0 && s1u == g[1] + g[2];
+        if (at_a || at_b) {
+          const double cz = at_a ? (double)g[6] : (double)g[7];
+          const T* t0 = F.T0 + 2 * bl * fld + s1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ch = 16 * wave + M::row(lane, r);
+            const double e = cz * (double)A.tb.E[ch];
+            oa0[n] += e * (double)t0[(long)ch * Np];
+            oa1[n] += e * (double)t0[fld + (long)ch * Np];
+          }
+        }
+      }
+      if constexpr (TWO) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ab[(16 * wave + M::row(lane, r)) * lda + j] = e1[n][r];
+      }
+    }
+  }
+  double ob0[SLM_NT], ob1[SLM_NT];
+#pragma unroll
+  for (int n = 0; n < SLM_NT; ++n) { ob0[n] = 0.0; ob1[n] = 0.0; }
+  if constexpr (TWO) {
+    __syncthreads();
+    // x2 = G^(2) e1 + Lam on S_2: thread (channel c, part k) takes columns k, k + 4, ...
+    {
+      const int c = tid % DP, part = tid / DP;
+      const T* g2c = A.tb.taps + ((long)DP + c) * TS + TO;
+      for (int j2 = part; j2 < P * W2m; j2 += 4) {
+        const int p = j2 / W2m, t2 = j2 - p * W2m;
+        const int* g = gs + SLM_GS * p;
+        const int s2u = g[1] - 2 * wc + t2;
+        T x = 0;
+        if (g[0] >= 0 && t2 < g[2] + 4 * wc + 1 && inside(s2u)) {
+          const int lo1 = g[1] - wc, W1 = g[2] + 2 * wc + 1;
+          const T* g2 = g2c + s2u - lo1;
+          const T* e1c = ab + c * lda + p * W1m;
+          for (int u = 0; u < W1; ++u) x += g2[-u] * e1c[u];
+          const T* lamb = F.lam + (long)(g[0] - A.b0) * N * F.ND * DP + c;
+          const int za = g[1], zb = g[1] + g[2];
+          x += (T)g[6] * lamb[((long)za * F.ND + (s2u - za - F.dlo)) * DP];
+          if (g[4] >= 0) x += (T)g[7] * lamb[((long)wrap(zb) * F.ND + (s2u - zb - F.dlo)) * DP];
+        }
+        ph[c * SLM_LDC + j2] = x;
+      }
+    }
+    __syncthreads();
+    // q2 = V^(2) x2; x = dchi2 (p0^(2) + q2) to LDS (over e1, whose readers are done)
+    {
+      acc_t q2[SLM_NT];
+      slm_prod_n<T, DP>((P * W2m + 15) / 16, v2, ph, SLM_LDC, q, col, q2);
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        const int j = 16 * n + col, p = j / W2m, t = j - p * W2m;
+        const int* g = gs + SLM_GS * (p < P ? p : 0);
+        const int s2u = g[1] - 2 * wc + t;
+        const bool v2ok = p < P && g[0] >= 0 && t < g[2] + 4 * wc + 1 && inside(s2u);
+        const T* p02 = F.p0 + F.fldB + (long)(v2ok ? g[0] - A.b0 : 0) * fld + (v2ok ? wrap(s2u) : 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * wave + M::row(lane, r);
+          ab[ch * lda + j] = v2ok ? dch[LF - 1][n][r] * (p02[(long)ch * Np] + q2[n][r]) : T(0);
+        }
+      }
+    }
+    __syncthreads();
+    // e2 = U^(2) x, read out with Wk on S_2
+    {
+      acc_t e2[SLM_NT];
+      slm_prod_n<T, DP>((P * W2m + 15) / 16, u2, ab, lda, q, col, e2);
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        const int j = 16 * n + col, p = j / W2m, t = j - p * W2m;
+        const int* g = gs + SLM_GS * (p < P ? p : 0);
+        const int s2u = g[1] - 2 * wc + t;
+        if (p < P && g[0] >= 0 && t < g[2] + 4 * wc + 1 && inside(s2u)) {
+          const T* w0 = A.tb.Wk + wrap(s2u);
+          T q0 = 0, q1 = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const long o = (long)(16 * wave + M::row(lane, r)) * Np;
+            q0 += w0[o] * e2[n][r];
+            q1 += w0[fld + o] * e2[n][r];
+          }
+          ob0[n] = (double)q0;
+          ob1[n] = (double)q1;
+        }
+      }
+    }
+  }
+  // column sums over the wave's channels (lanes 16 and 32 apart share a column), then over the
+  // waves and each flip's columns; red[layout][output][wave][column]
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(ph);
+#pragma unroll
+  for (int n = 0; n < SLM_NT; ++n) {
+    const double a0 = swap_sum<32>(swap_sum<16>(oa0[n])), a1 = swap_sum<32>(swap_sum<16>(oa1[n]));
+    const double b0 = swap_sum<32>(swap_sum<16>(ob0[n])), b1 = swap_sum<32>(swap_sum<16>(ob1[n]));
+    if (lane < 16) {
+      const int j = 16 * n + lane;
+      red[(0 * NW + wave) * SLM_CAP + j] = a0;
+      red[(1 * NW + wave) * SLM_CAP + j] = a1;
+      red[(2 * NW + wave) * SLM_CAP + j] = b0;
+      red[(3 * NW + wave) * SLM_CAP + j] = b1;
+    }
+  }
+  __syncthreads();
+  if (tid < P) {
+    const int* g = gs + SLM_GS * tid;
+    if (g[0] >= 0) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        for (int t = 0; t < W1m; ++t) {
+          s0 += red[(0 * NW + w) * SLM_CAP + tid * W1m + t];
+          s1 += red[(1 * NW + w) * SLM_CAP + tid * W1m + t];
+        }
+        if (TWO)
+          for (int t = 0; t < W2m; ++t) {
+            s0 += red[(2 * NW + w) * SLM_CAP + tid * W2m + t];
+            s1 += red[(3 * NW + w) * SLM_CAP + tid * W2m + t];
+          }
+      }
+      const int gg = f0 + g[5];
+      const int bg = A.map.cb[gg], mm = A.map.cm[gg];
+      const long o = (long)bg * A.map.M_max + mm;
+      F.logratio[o] = lcd_d(F.Om0[2 * bg], s0) + lcd_d(F.Om0[2 * bg + 1], s1);
+      if (F.dom) { F.dom[2 * o] = s0; F.dom[2 * o + 1] = s1; }
+    }
+  }
+}
+
 }  // namespace dn
