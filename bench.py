@@ -86,8 +86,8 @@ def kernel_class(name: str) -> str:
     if "mix_kernel" in name:
         mode = name.split("mix_kernel<")[1].split(",")[2].strip()
         return {"0": "mix_fwd", "1": "mix_tau", "2": "mix_deep"}[mode]
-    for key, cls in (("conv_kernel", "conv"), ("conv_split_kernel", "conv"), ("phi_kernel", "phi"), ("slice_kernel", "slice"),
-                     ("deep_kernel", "mix_deep"), ("last_finish_kernel", "tail"), ("flip12_kernel", "tail"), ("shallow_kernel", "tail"),
+    for key, cls in (("conv_kernel", "conv"), ("conv_split_kernel", "conv"), ("phi_kernel", "phi"), ("slice_mma_kernel", "slice"),
+                     ("deep_kernel", "mix_deep"), ("last_finish_kernel", "tail"), ("shallow_kernel", "tail"),
                      ("lam_fwd_kernel", "link"), ("lam_gemm_kernel", "link"), ("lam_inv_kernel", "link"),
                      ("lam_param_kernel", "prep"), ("s4_taps_kernel", "s4gen"), ("prep_kernel", "prep"),
                      ("connected_kernel", "gen"), ("eloc_kernel", "eloc")):

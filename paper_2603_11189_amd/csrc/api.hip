@@ -741,35 +741,6 @@ dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam,
   return DN_OK;
 }
 
-// Persistent launch of the per-flip update of one- and two-block networks.
-template <typename T, int DP, bool TWO>
-dn_status launch_flip12(dn_model* m, Flip12Args<T> a, int F, hipStream_t st, int ext) {
-  if (F <= 0) return DN_OK;
-  const size_t lds = flip12_lds_bytes<T, DP>(TWO);
-  constexpr int NW = flip12_waves<T>();
-  static int per_cu = 0;
-  if (!per_cu) {
-    allow_lds(flip12_kernel<T, DP, TWO>, lds);
-    int n = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, flip12_kernel<T, DP, TWO>, 64 * NW, lds));
-    per_cu = std::max(n, 1);
-  }
-  // matrix-core columns per flip: the widest last slice of the launch
-  a.colw = ext + 2 * (TWO ? 2 : 1) * m->desc.w_c + 1;
-  const int P = 16 / a.colw;
-  const int grid = (int)std::max<long>(1, std::min<long>((F + NW * P - 1) / (NW * P), (long)cu_count() * per_cu));
-  const dn_model_desc& d = m->desc;
-  const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;
-  const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
-  // per flip: the slice operands, links and read-out weights it reads (the caches p0 on the
-  // slices, Lam on S_2, T^(1) on S_1, T^(0) at the cluster)
-  const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
-  PScope ps(m, DN_K_TAIL, st, fl * F, by * F);
-  flip12_kernel<T, DP, TWO><<<grid, 64 * NW, lds, st>>>(a);
-  HIPCHK(hipGetLastError());
-  return DN_OK;
-}
-
 // The fused slice recompute + per-flip update of one- and two-block networks (shallow_kernel):
 // one workgroup of DP / 16 waves per P flips.
 template <typename T, int DP, bool TWO>
@@ -795,7 +766,7 @@ dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, i
 // for clusters wider than the slice recurrence covers. ext_max: the widest cluster extent in
 // the work list (0 single flips, 2 pairs up to two sites apart).
 //   L <= 2: per-sample output links T^(0), T^(1) and block 2's pivot-0 link Lam, then
-//           flip12_kernel: per-flip work on the slices only (independent of N).
+//           shallow_kernel: per-flip work on the slices only (independent of N).
 //   L >= 3: the adjoint tau of the last block, then the exact background propagation of each
 //           flip's perturbation through blocks 1..L-1 (deep_kernel), finished per flip.
 template <typename T, int DP>
@@ -877,9 +848,11 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     const int F = h_offs ? h_offs[b0 + Bc] - f0 : Bc * M_max;
     const DynRange dyn{h_offs ? nullptr : offs, b0, Bc};
     if (F == 0) continue;
-    void *pdchi, *pgeom, *prho, *pdu, *pw;
-    STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
-    STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
+    void *pdchi = nullptr, *pgeom = nullptr, *prho, *pdu, *pw;
+    if (!shallow) {  // the deep path keeps the slices and the cluster geometry for its later kernels
+      STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
+      STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
+    }
     const int nt = Np / 64;
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
@@ -890,42 +863,24 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     sa.ext_max = ext_max; sa.dyn = dyn;
     double slice_fl = 0.0;
     for (int l = 1; l <= L; ++l) slice_fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
+    // P flips side by side per product (slices are at most 16 sites wide: P >= 4)
     const int Wc = ext_max + 2 * L * wc + 1;
     const int P = slm_flips(Wc);
-    const bool slm = P >= 1 && slm_lds_bytes<T>(DP, P, Wc, wc) <= LDS_MAX;  // P flips side by side per product
-    if (shallow) {
+    const size_t slds = slm_lds_bytes<T>(DP, P, Wc, wc);
+    if (P < 1 || slds > LDS_MAX) return fail(DN_EUNSUPPORTED, "ABACUS slice too wide for one matrix-core product");
+    if (shallow) {  // slice recompute and per-flip update in one kernel
       Flip12Args<T> a{};
-      a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
-      a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
-      a.Wmax = Wmax; a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
-      a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.dyn = dyn;
-      if (slm) {  // slice recompute and per-flip update in one kernel
-        if (L == 2) STCHK((launch_shallow<T, DP, true>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
-        else STCHK((launch_shallow<T, DP, false>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
-        continue;
-      }
+      a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
+      a.Om0 = Om0; a.logratio = logratio; a.dom = dom;
+      if (L == 2) STCHK((launch_shallow<T, DP, true>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
+      else STCHK((launch_shallow<T, DP, false>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
+      continue;
     }
     {
       PScope ps(m, DN_K_SLICE, st, slice_fl * F, (double)F * L * Wmax * d.d * sizeof(T));
-      if (slm) {
-        const size_t lds = slm_lds_bytes<T>(DP, P, Wc, wc);
-        allow_lds(slice_mma_kernel<T, DP>, lds);
-        slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, lds, st>>>(sa);
-      } else {
-        const size_t lds = (2 * (size_t)Wmax + 4 * wc) * DP * sizeof(T);  // phi', and a' with its halo
-        slice_kernel<T, DP><<<F, 64, lds, st>>>(sa);
-      }
+      allow_lds(slice_mma_kernel<T, DP>, slds);
+      slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, slds, st>>>(sa);
       HIPCHK(hipGetLastError());
-    }
-    if (shallow) {
-      Flip12Args<T> a{};
-      a.tb = tb; a.N = d.N; a.Np = Np; a.L = L; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC;
-      a.F = F; a.f0 = f0; a.b0 = bf0; a.map = fmap; a.spins = spins; a.geom = geom; a.dchi = dchi;
-      a.Wmax = Wmax; a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
-      a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.dyn = dyn;
-      if (L == 2) STCHK((launch_flip12<T, DP, true>(m, a, F, st, ext_max)));
-      else STCHK((launch_flip12<T, DP, false>(m, a, F, st, ext_max)));
-      continue;
     }
     // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
     STCHK(ws_get(m, "ab_rho", (size_t)std::max(L - 1, 1) * F * nt * 2 * sizeof(double), &prho));

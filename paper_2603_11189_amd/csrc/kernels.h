@@ -1625,9 +1625,9 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
 
 // ---------------------------------------------------------------------------------------
 // Per-flip slice recompute of the phi stream and vertices (ABACUS, Sec. III: the vertex
-// changes only on S_l = sites within l*w_c of the cluster). One wave per flip; lanes
-// own output channels. Writes dchi^(l) = chi'^(l) - chi0^(l) on S_l for l = 1..L and the
-// cluster geometry (clo, ext, j0, j1): S_l covers sites clo - l*w_c .. clo + ext + l*w_c.
+// changes only on S_l = sites within l*w_c of the cluster). Writes dchi^(l) = chi'^(l) -
+// chi0^(l) on S_l for l = 1..L and the cluster geometry (clo, ext, j0, j1): S_l covers sites
+// clo - l*w_c .. clo + ext + l*w_c.
 template <typename T> struct SliceArgs {
   Tables<T> tb;
   int N, Np, L, w_c, periodic, act;
@@ -1644,121 +1644,7 @@ template <typename T> struct SliceArgs {
   DynRange dyn;           // flips counted on the device (nullable)
 };
 
-template <typename T, int DP>
-__global__ __launch_bounds__(64) void slice_kernel(SliceArgs<T> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int N = A.N, Np = A.Np, wc = A.w_c, L = A.L;
-  // phi' on the current slice [Wmax][DP]; a on the previous slice with a halo of 2 w_c
-  // background sites on either side [2 w_c + Wmax + 2 w_c][DP] (as[t] = row t + 2 w_c)
-  T* phs = reinterpret_cast<T*>(smem_raw);
-  T* as = phs + A.Wmax * DP + 2 * wc * DP;
-  const int f = blockIdx.x;
-  const int c = threadIdx.x;  // channel; lanes c >= DP only join the barriers
-  const bool on = c < DP;
-  if (f >= A.dyn.count(A.F)) return;
-  const int f0 = A.dyn.first(A.f0);
-  const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
-  const int bl = b - A.b0;
-  const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
-  const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
-  int clo = j0, ext = 0;
-  if (j1 >= 0) {
-    if (A.periodic) {
-      int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
-      if (d1 <= 2) { clo = j0; ext = d1; }
-      else if (d2 <= 2) { clo = j1; ext = d2; }
-      else ext = -1;
-    } else {
-      clo = j0 < j1 ? j0 : j1;
-      ext = j0 < j1 ? j1 - j0 : j0 - j1;
-      if (ext > 2) ext = -1;
-    }
-  }
-  if (ext < 0 || ext > A.ext_max || (A.periodic && ext + 2 * L * wc + 1 > N)) {
-    if (c == 0) atomicOr(A.err, 1);
-    ext = 0;
-  }
-  if (c == 0) A.geom[f] = make_int4(clo, ext, j0, j1);
-  if (!on) {  // idle lanes still take part in every barrier below
-    for (int l = 1; l <= L; ++l) { __syncthreads(); __syncthreads(); __syncthreads(); }
-    return;
-  }
-  const int8_t* sp = A.spins + (long)b * N;
-  auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
-  auto inside = [&](int i) { return A.periodic || (i >= 0 && i < N); };
-  for (int l = 1; l <= L; ++l) {
-    const int lp = l - 1;  // layer index into tables
-    const int loP = clo - lp * wc, WP = ext + 2 * lp * wc + 1;  // S_{l-1}
-    const int lo = clo - l * wc, Wl = ext + 2 * l * wc + 1;     // S_l
-    // a' on S_{l-1}; this lane's column of the block's weight matrix stays in registers
-    T wcol[DP];
-    if (l > 1) {
-      const T* Wt = A.tb.WDt + (long)lp * DP * DP;
-#pragma unroll
-      for (int k = 0; k < DP; ++k) wcol[k] = Wt[k * DP + c];
-    }
-    // the halo: background a at the 2 w_c sites on either side of S_{l-1}, requested before
-    // the products and stored with them
-    const T* a0 = A.a0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
-    for (int h = 0; h < 4 * wc; ++h) {
-      const int tp = h < 2 * wc ? h - 2 * wc : WP + h - 2 * wc;
-      const int jj = loP + tp;
-      as[tp * DP + c] = inside(jj) ? a0[wrap(jj)] : T(0);
-    }
-    for (int t = 0; t < WP; ++t) {
-      const int site = wrap(loP + t);
-      T v = 0;
-      if (inside(loP + t)) {
-        if (l == 1) {
-          T s = (T)sp[site];
-          if (site == j0 || site == j1) s = -s;
-          v = s * A.tb.wE1[c] + A.tb.wv[c];
-        } else {
-          T acc = A.tb.wv[lp * DP + c];
-#pragma unroll
-          for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
-          v = acc;
-        }
-      }
-      as[t * DP + c] = v;
-    }
-    __syncthreads();
-    // phi' and chi' on S_l
-    const T* Kc = A.tb.Kc + (long)lp * (2 * wc + 1) * DP;
-    for (int t = 0; t < Wl; ++t) {
-      const int ii = lo + t;
-      T s = A.tb.kv[lp * DP + c];
-      for (int r = -wc; r <= wc; ++r) s += Kc[(r + wc) * DP + c] * as[(t + r - wc) * DP + c];
-      phs[t * DP + c] = inside(ii) ? act_fn<T>(A.act, s) : T(0);  // phs no longer read above
-    }
-    __syncthreads();
-    const T* Adt = A.tb.ADt + (long)lp * DP * DP;
-    const T* chi0 = A.chi0 + (((long)lp * A.Bc + bl) * DP + c) * Np;
-    T* out = A.dchi + ((long)f * L + lp) * A.Wmax * DP;
-    // the background gate on S_l, requested together (positions past Wl read the slice's
-    // first site and are not used)
-    T c0v[SLICE_WIN];
-#pragma unroll
-    for (int t = 0; t < SLICE_WIN; ++t) c0v[t] = chi0[wrap(t < Wl && inside(lo + t) ? lo + t : clo)];
-#pragma unroll
-    for (int k = 0; k < DP; ++k) wcol[k] = Adt[k * DP + c];
-#pragma unroll
-    for (int t = 0; t < SLICE_WIN; ++t) {
-      if (t < Wl) {
-        const int ii = lo + t;
-        T acc = A.tb.bv[lp * DP + c];
-#pragma unroll
-        for (int k = 0; k < DP; ++k) acc += wcol[k] * phs[t * DP + k];
-        T dc = inside(ii) ? act_fn<T>(A.act, acc) - c0v[t] : T(0);
-        out[t * DP + c] = dc;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-
-// The same slice recompute with its two channel mixes on the matrix cores. A workgroup takes
+// The slice recompute with its two channel mixes on the matrix cores. A workgroup takes
 // P flips at a time and lays them side by side as the columns of one SLM_CAP-column product
 // per mix: block l forms a' = W_D phi'^(l-1) + w on S_{l-1} (block 1: from s'), the phi
 // stream on S_l from a' with its background halo, and chi' = g(A_D phi'^(l) + b) on S_l,

@@ -18,7 +18,7 @@
 // circular correlation equals the linear one (open chains: u in [-(N-1), N-1]; periodic
 // chains: u in [0, N) over the gate extended periodically to 2N - 1 sites).
 //
-// Per flip (flip12_kernel) only slice-sized work remains:
+// Per flip (shallow_kernel) only slice-sized work remains:
 //   e1_i = U^(1) (dchi1_i * (p0^(1)_i + sum_z c_z Pq(i - z))),                i in S_1
 //   x2_a = v0^(2)_a + sum_(i in S_1) g^(2)(a - i) e1_i + sum_z c_z Lam(z, a - z), a in S_2
 //   e2_a = U^(2) (dchi2_a * V^(2) x2_a)
@@ -284,17 +284,8 @@ template <typename T> __global__ __launch_bounds__(256) void lam_inv_kernel(LamA
   }
 }
 
-// ---- per-flip update (one or two blocks)
+// ---- per-flip update (one or two blocks): the per-sample operands beside the slice's
 template <typename T> struct Flip12Args {
-  Tables<T> tb;
-  int N, Np, L, w_c, periodic;
-  int F, f0, b0;        // flips [f0, f0 + F) of the work list; b0: first sample of the background chunk
-  CfgMap map;
-  const int8_t* spins;
-  const int4* geom;     // [F] (clo, ext, j0, j1) from slice_kernel
-  const T* dchi;        // [F][L][Wmax][DP]
-  int Wmax;
-  int colw;             // matrix-core columns per flip (the widest last slice); 16 / colw flips per step
   const T* p0;          // [L][Bf][DP][Np]: V v0 of every block
   long fldB;            // Bf DP Np
   const T* T0;          // [Bf][2][DP][Np]: output link of the input change (h^(0))
@@ -304,205 +295,11 @@ template <typename T> struct Flip12Args {
   const double* Om0;    // [B][2]
   double* logratio;     // [B][M_max]
   double* dom;          // nullable: [B][M_max][2] the output changes dOmega themselves
-  DynRange dyn;
 };
 
-// waves per workgroup (they share one copy of the weight operands in LDS)
-template <typename T> constexpr int flip12_waves() { return sizeof(T) == 4 ? 8 : 4; }
-template <typename T, int DP> constexpr size_t flip12_lds_bytes(bool two) {
-  return ((two ? 3 : 1) * DP * DP + (two ? flip12_waves<T>() * DP * 17 : 0)) * sizeof(T) +
-         (size_t)flip12_waves<T>() * 32 * sizeof(double);
-}
-
-// Persistent workgroups; the weight operands live in LDS in fragment order. A wave takes
-// 16 / colw flips at a time: flip p of the step owns matrix-core columns p colw .. p colw +
-// colw - 1, column t of them being slice position t, so one product serves several flips.
-template <typename T, int DP, bool TWO>
-__global__ __launch_bounds__(64 * flip12_waves<T>()) void flip12_kernel(Flip12Args<T> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  using M = Mma<T>;
-  using acc_t = typename M::acc;
-  constexpr int MT = DP / 16, KS = DP / 4, NW = flip12_waves<T>();
-  T* FU1 = reinterpret_cast<T*>(smem_raw);  // [KS][64][MT]: operand A of U^(1)
-  T* FV2 = FU1 + DP * DP;                   // [KS][64][MT]: operand A of V^(2)
-  T* FU2 = FV2 + DP * DP;                   // [MT][MT][64][4]: U^(2) in accumulator channel order
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
-  T* E1s = FU1 + (TWO ? 3 : 1) * DP * DP + wave * DP * 17;  // [DP][17]: this wave's e1 (TWO)
-  double* red = reinterpret_cast<double*>(FU1 + (TWO ? 3 * DP * DP + NW * DP * 17 : DP * DP)) + wave * 32;
-  for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
-    const int mt = idx % MT, ln = (idx / MT) % 64, ks = idx / (MT * 64);
-    FU1[idx] = A.tb.Ut[(4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
-    if constexpr (TWO) {
-      FV2[idx] = A.tb.Vt[(long)DP * DP + (4 * ks + (ln >> 4)) * DP + 16 * mt + (ln & 15)];
-      const int r = idx & 3, l2 = (idx >> 2) & 63, mi = (idx >> 8) % MT, mo = (idx >> 8) / MT;
-      FU2[idx] = A.tb.Ut[(long)DP * DP + (16 * mi + M::row(l2, r)) * DP + 16 * mo + (l2 & 15)];
-    }
-  }
-  __syncthreads();
-  const int N = A.N, Np = A.Np, wc = A.w_c;
-  const int TS = tap_stride(Np), TO = tap_off(Np);
-  const int F = A.dyn.count(A.F);
-  const int cfg0 = A.dyn.first(A.f0);
-  const int W = A.colw, P = 16 / W;
-  const int p = j / W, t = j - p * W;  // this lane's flip slot and slice position
-  auto wrap = [&](int i) { if (A.periodic) { i %= N; if (i < 0) i += N; } return i; };
-  for (int gb = (blockIdx.x * NW + wave) * P; gb < F; gb += gridDim.x * NW * P) {
-    const int g = gb + p;
-    const bool have = p < P && g < F;
-    int4 sg = make_int4(0, 0, 0, -1);
-    int bglob = 0, bl = 0;
-    if (have) {
-      sg = A.geom[g];
-      bglob = A.map.cb[cfg0 + g];
-      bl = bglob - A.b0;
-    }
-    const int8_t* sp = A.spins + (long)bglob * N;
-    // cluster sites (unwrapped): za = clo, zb = clo + ext for a pair
-    const int za = sg.x, zb = sg.x + sg.y;
-    const bool pair = sg.w >= 0;
-    const T ca = have ? (T)(-2 * sp[za]) : T(0);
-    const T cb = have && pair ? (T)(-2 * sp[wrap(zb)]) : T(0);
-    // ---- block 1 on S_1
-    const int lo1 = sg.x - wc, W1 = sg.y + 2 * wc + 1;
-    const int s1u = lo1 + t;
-    const bool v1 = have && t < W1 && (A.periodic || (s1u >= 0 && s1u < N));
-    const int s1 = v1 ? wrap(s1u) : 0;
-    const T* dchi1 = A.dchi + (long)(have ? g : 0) * A.L * A.Wmax * DP;
-    const T* p01 = A.p0 + (long)bl * DP * Np;
-    acc_t e1[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) e1[mt] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int ks = 0; ks < KS; ++ks) {
-      const int c = 4 * ks + kq;
-      T x = 0;
-      if (v1) {
-        const T* pq = A.tb.Pq + (long)c * TS + TO + s1u;
-        x = dchi1[t * DP + c] * (p01[(long)c * Np + s1] + ca * pq[-za] + cb * pq[-zb]);
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) e1[mt] = M::mma(FU1[(ks * 64 + lane) * MT + mt], x, e1[mt]);
-      // keep the scheduler from hoisting every later operand load (register pressure)
-      if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
-    // read-outs: a lane's partial over its channels in the field precision, float64 across
-    // lanes and stages
-    double o0 = 0.0, o1 = 0.0;
-    if (v1) {
-      const T* r0 = TWO ? A.T1 + (long)2 * bl * DP * Np : A.tb.Wk;
-      const T* r1 = r0 + (long)DP * Np;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        T q0 = 0, q1 = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = (16 * mt + M::row(lane, r)) * Np + s1;
-          q0 += r0[o] * e1[mt][r];
-          q1 += r1[o] * e1[mt][r];
-        }
-        o0 += (double)q0;
-        o1 += (double)q1;
-      }
-    }
-    if constexpr (TWO) {
-      // e1 to LDS, then x2 = G^(2) e1 + pivot-0 link on S_2 in operand-B layout
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) E1s[(16 * mt + M::row(lane, r)) * 17 + j] = e1[mt][r];
-      wave_sync();
-      const int lo2 = sg.x - 2 * wc, W2 = sg.y + 4 * wc + 1;
-      const int s2u = lo2 + t;
-      const bool v2 = have && t < W2 && (A.periodic || (s2u >= 0 && s2u < N));
-      const int s2 = v2 ? wrap(s2u) : 0;
-      const T* lamb = A.lam + (long)bl * N * A.ND * DP;
-      const T* la = lamb + ((long)za * A.ND + (s2u - za - A.dlo)) * DP;
-      const T* lb = lamb + ((long)wrap(zb) * A.ND + (s2u - zb - A.dlo)) * DP;
-      const T* e1c = E1s + p * W;  // this flip's columns of e1
-      acc_t q2[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) q2[mt] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = 4 * ks + kq;
-        T x = 0;
-        if (v2) {
-          const T* g2 = A.tb.taps + ((long)DP + c) * TS + TO + s2u - lo1;
-          for (int u = 0; u < W1; ++u) x += g2[-u] * e1c[c * 17 + u];
-          x += ca * la[c];
-          if (pair) x += cb * lb[c];
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) q2[mt] = M::mma(FV2[(ks * 64 + lane) * MT + mt], x, q2[mt]);
-        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
-      // x = dchi2 * (p0^(2) + V x2), in accumulator order
-      const T* dchi2 = dchi1 + (long)A.Wmax * DP;
-      const T* p02 = A.p0 + A.fldB + (long)bl * DP * Np;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int c = 16 * mt + M::row(lane, r);
-          q2[mt][r] = v2 ? dchi2[t * DP + c] * (p02[(long)c * Np + s2] + q2[mt][r]) : T(0);
-        }
-      const T* w0 = A.tb.Wk;
-      const T* w1 = w0 + (long)DP * Np;
-#pragma unroll 1
-      for (int mo = 0; mo < MT; ++mo) {
-        acc_t e2 = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int mi = 0; mi < MT; ++mi)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) e2 = M::mma(FU2[((mo * MT + mi) * 64 + lane) * 4 + r], q2[mi][r], e2);
-        if (v2) {
-          T q0 = 0, q1 = 0;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int o = (16 * mo + M::row(lane, r)) * Np + s2;
-            q0 += w0[o] * e2[r];
-            q1 += w1[o] * e2[r];
-          }
-          o0 += (double)q0;
-          o1 += (double)q1;
-        }
-      }
-    }
-    // the input change e^(0) = c_z E at the cluster sites, read out with T^(0): the lanes of
-    // a flip's first column take the channels 4 ks + kq
-    if (have && t == 0) {
-      const T* t0 = A.T0 + (long)2 * bl * DP * Np;
-      const int zbw = wrap(zb);
-#pragma unroll 4
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = 4 * ks + kq;
-        const double e = (double)A.tb.E[c];
-        const long oa = (long)c * Np + za, ob = (long)c * Np + zbw;
-        o0 += e * ((double)ca * (double)t0[oa] + (double)cb * (double)t0[ob]);
-        o1 += e * ((double)ca * (double)t0[(long)DP * Np + oa] + (double)cb * (double)t0[(long)DP * Np + ob]);
-      }
-    }
-    // column sums (lanes 16 and 32 apart share a column), then each flip's columns
-    o0 = swap_sum<32>(swap_sum<16>(o0));
-    o1 = swap_sum<32>(swap_sum<16>(o1));
-    if (lane < 16) { red[lane] = o0; red[16 + lane] = o1; }
-    wave_sync();
-    if (lane < P && gb + lane < F) {
-      double s0 = 0.0, s1v = 0.0;
-      for (int u = 0; u < W; ++u) { s0 += red[lane * W + u]; s1v += red[16 + lane * W + u]; }
-      const int gg = gb + lane;
-      const int bg = A.map.cb[cfg0 + gg], mm = A.map.cm[cfg0 + gg];
-      const long o = (long)bg * A.map.M_max + mm;
-      A.logratio[o] = lcd_d(A.Om0[2 * bg], s0) + lcd_d(A.Om0[2 * bg + 1], s1v);
-      if (A.dom) { A.dom[2 * o] = s0; A.dom[2 * o + 1] = s1v; }
-    }
-    wave_sync();  // red and E1s are rewritten by the wave's next step
-  }
-}
-
 // One or two blocks in one kernel per group of flips: the slice recompute (slm_layers) keeps
-// each flip's vertex changes in registers, and the per-flip update of flip12_kernel follows on
-// the same matrix-core columns (flip p, slice position t), so neither the vertex changes nor
+// each flip's vertex changes in registers, and the per-flip update below follows on the same
+// matrix-core columns (flip p, slice position t), so neither the vertex changes nor
 // the cluster geometry go through HBM. Wave w owns channels 16 w .. 16 w + 15 of every
 // product (U^(1); V^(2) and U^(2) for two blocks) with those weight rows in registers; the
 // read-outs are summed per column over the wave's channels, then over waves and a flip's
