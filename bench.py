@@ -236,6 +236,10 @@ def main():
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
     ap.add_argument("--products", default="split3", choices=["split3", "fp32"],
                     help="float matrix-core products: three-term bf16 splits (default) or float32 matrix cores")
+    ap.add_argument("--sampler", action="store_true",
+                    help="screened typewriter sampler: Metropolis proposals per second on the workload")
+    ap.add_argument("--sr", action="store_true",
+                    help="stochastic-reconfiguration update from the workload's per-sample log-derivatives")
     ap.add_argument("--sweep", action="store_true",
                     help="ABACUS vs full re-evaluation for N in 64..512 at L = 2 and 4 (one JSON line each)")
     ap.add_argument("--paper-shapes", action="store_true",
@@ -272,6 +276,12 @@ def main():
         return
     if args.sweep:
         bench_sweep(args)
+        return
+    if args.sampler:
+        bench_sampler(args)
+        return
+    if args.sr:
+        bench_sr(args)
         return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
@@ -502,6 +512,131 @@ def stress_errors(args, w, shape, ham, prec, M_max, paths, B_s: int = 8) -> dict
                   "eloc": d_el / ref["eloc"].abs().max().item(), "eloc_net": d_el / net}
     m.close()
     return res
+
+
+def _profiled(model, fn, steps):
+    """Per-class (ms, launches, flops, bytes) of `steps` calls of fn, from the library's events."""
+    import torch
+    model.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = model.profile_read()
+    model.profile_enable(False)
+    return prof
+
+
+def bench_sampler(args) -> None:
+    """Screened typewriter sampler (dn_screened_sweep) on the workload's model at the stress draw
+    (order-one signal in every block, so that proposals are rejected and the screen refreshes):
+    B chains, blocks of 8 sites, one proposal per visited block, eps = 0.01; a step is one sweep
+    (both parities)."""
+    import numpy as np
+    import torch
+
+    import dn_inputs as di
+    from paper_2603_11189_amd import _lib as L
+
+    w = di.WORKLOADS[args.workload]
+    shape = w.model
+    prec = args.prec or w.prec
+    spacing, eps = 8, 0.01
+    dev = torch.device("cuda")
+    torch.cuda.init()
+    L.lib()
+    m = L.Model(shape, prec)
+    m.set_params(torch.tensor(w.params("stress")))
+    spins = torch.tensor(w.spin_batch(), device=dev)
+    B, N = spins.shape
+    nblk = (N + spacing - 1) // spacing
+    K = [((nblk - par) + 1) // 2 for par in (0, 1)]
+    rng = np.random.Generator(np.random.PCG64(w.spin_seed + 77))
+    draws = [[(torch.tensor(rng.random((B, K[par])), device=dev), torch.tensor(rng.random((B, K[par])), device=dev))
+              for par in (0, 1)] for _ in range(4)]
+    acc_n, ref_n = [0], [0]
+
+    def sweep(i):
+        for par in (0, 1):
+            r, u = draws[i % 4][par]
+            a, rf = m.screened_sweep(spins, spacing, par, r, u, eps)
+            acc_n[0] += a
+            ref_n[0] += rf
+
+    for i in range(args.warmup):
+        sweep(i)
+    torch.cuda.synchronize()
+    acc_n[0], ref_n[0] = 0, 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sweep(i)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    props = B * (K[0] + K[1])
+    acc_tot = int(acc_n[0].sum().item()) if torch.is_tensor(acc_n[0]) else 0
+    ref_tot = int(ref_n[0].sum().item()) if torch.is_tensor(ref_n[0]) else 0
+    prof = _profiled(m, lambda: sweep(0), 1)
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, n, fl, by = prof[dom]
+    peak, basis = mfma_peak(dom, prec, "split3", shape.d)
+    out = {
+        "metric": "Metropolis proposals/sec, screened typewriter sampler (ISA ratios by ABACUS)",
+        "value": props / sec, "unit": "proposals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-mixed"}[prec], "data": "synthetic",
+        "config": {"workload": args.workload + "_sampler", "N": N, "L": shape.L, "d": shape.d, "chains": B,
+                   "spacing": spacing, "eps": eps, "params": "stress draw", "step": "one sweep (both parities)"},
+        "acceptance": acc_tot / (props * args.steps), "refreshes_per_proposal": ref_tot / (props * args.steps),
+        "roofline": {"kernel": dom, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                     "frac": fl / (ms * 1e-3) / 1e12 / peak, "peak_basis": basis, "avg_launch_ms": ms / n},
+        "per_kernel": {k: {"ms_per_step": v[0], "launches_per_step": v[1]} for k, v in prof.items() if v[1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sr(args) -> None:
+    """One stochastic-reconfiguration update (dn_sr_update) from the workload's per-sample
+    log-derivatives O [B x P] and local energies: conjugate gradients on (S + shift I) x = F, two
+    passes over O per iteration; the roofline is HBM (O read twice per iteration)."""
+    import torch
+
+    import dn_inputs as di
+    from paper_2603_11189_amd import _lib as L
+
+    w = di.WORKLOADS[args.workload]
+    shape, ham = w.model, w.ham
+    prec = args.prec or w.prec
+    dev = torch.device("cuda")
+    torch.cuda.init()
+    L.lib()
+    m = L.Model(shape, prec)
+    m.set_params(torch.tensor(w.params(args.scale)))
+    spins = torch.tensor(w.spin_batch(), device=dev)
+    M_max = shape.N if ham.kind == "lrtfim" else 2 * shape.N
+    _, g, _ = m.grad_logpsi(spins)
+    _, _, el = m.eloc(ham, spins, M_max, path="abacus")
+    B, P = g.shape
+    iters = 50
+    for _ in range(args.warmup):
+        m.sr_update(g, el, max_iter=iters, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, it = m.sr_update(g, el, max_iter=iters, tol=0.0)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    passes = 2 * it + 2  # F and Obar, then a row and a column pass per iteration
+    gbs = passes * g.numel() * g.element_size() / sec / 1e9
+    out = {
+        "metric": "SR updates/sec (conjugate gradients, fixed iteration count)",
+        "value": 1.0 / sec, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32"}[prec], "data": "synthetic",
+        "config": {"workload": args.workload + "_sr", "samples": B, "params": P, "cg_iterations": it,
+                   "O_bytes": g.numel() * g.element_size()},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK,
+                     "traffic": None, "basis": f"{passes} passes over O per update"},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_sweep(args) -> None:

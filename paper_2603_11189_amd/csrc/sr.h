@@ -41,10 +41,20 @@ __global__ __launch_bounds__(256) void sr_colsum_kernel(const T* __restrict__ O,
                                                         double shift, double* __restrict__ out) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
-  double s = 0.0;
-  for (int b = 0; b < B; ++b) s += coef[b] * (double)O[(long)b * P + k];
-  if (v) s += shift * v[k];
-  out[k] = s;
+  // four partial sums, eight rows requested together (the loads, not the adds, set the pace)
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int b = 0;
+  for (; b + 8 <= B; b += 8) {
+    T o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = O[(long)(b + i) * P + k];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i & 3] += coef[b + i] * (double)o[i];
+  }
+  for (; b < B; ++b) s[0] += coef[b] * (double)O[(long)b * P + k];
+  double r = (s[0] + s[1]) + (s[2] + s[3]);
+  if (v) r += shift * v[k];
+  out[k] = r;
 }
 
 // t_b = sum_k O_bk v_k - *sub (one workgroup per sample), scaled by w_b.
@@ -55,9 +65,14 @@ __global__ __launch_bounds__(256) void sr_rowdot_kernel(const T* __restrict__ O,
   __shared__ double part[4];
   const int b = blockIdx.x;
   const T* row = O + (long)b * P;
-  double s = 0.0;
-  for (long k = threadIdx.x; k < P; k += blockDim.x) s += (double)row[k] * v[k];
-  s = wave_sum(s);
+  double s0 = 0.0, s1 = 0.0;
+  long k = threadIdx.x;
+  for (; k + blockDim.x < P; k += 2 * blockDim.x) {
+    s0 += (double)row[k] * v[k];
+    s1 += (double)row[k + blockDim.x] * v[k + blockDim.x];
+  }
+  if (k < P) s0 += (double)row[k] * v[k];
+  double s = wave_sum(s0 + s1);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) t[b] = w[b] * (part[0] + part[1] + part[2] + part[3] - *sub);
