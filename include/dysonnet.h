@@ -20,7 +20,10 @@
  *  - The library owns each model: its parameters, the derived tables (Green's-function
  *    taps, transposed weights) and a growable workspace. A model must not be used from
  *    two streams at the same time.
- *  - spins: int8, values +1/-1, row-major [B, N]. Other values give undefined results.
+ *  - spins: int8, values +1/-1, row-major [B, N]. dn_logratio and dn_eloc reject other
+ *    values with DN_EINVAL (checked on the device with the work list, before any network
+ *    kernel runs); the calls without a work list (dn_logpsi, dn_grad_logpsi, the sampler,
+ *    the ragged batch) do not check them and give undefined results for them.
  *  - sites: int32 [B, M_max, 2]; element m of sample b flips sites[b,m,0] and, unless it
  *    is -1, sites[b,m,1]. Entries m >= n_conn[b] are ignored on input.
  *  - logpsi, logratio, eloc, helem, hdiag are float64 in every precision mode.

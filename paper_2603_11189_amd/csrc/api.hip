@@ -567,15 +567,22 @@ dn_status plan_launch(dn_model* m, const int32_t* n_conn, const int32_t* sites, 
 dn_status plan_errors(int bits) {
   if (bits & 1) return fail(DN_EINVAL, "n_conn outside [0, M_max]");
   if (bits & 2) return fail(DN_EINVAL, "a site index is outside the chain (or a pair repeats a site)");
+  if (bits & 8) return fail(DN_EINVAL, "a spin is neither +1 nor -1");
   return DN_OK;
 }
 
 // The work list with its offsets brought back to the host (one stream synchronisation) to
 // size the launches exactly.
+// The spins of the batch are checked on the way (bit 8 of the error word).
 dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, int M_max, int with_base,
                int32_t** offs, int32_t** cb, int32_t** cm, int upper, std::vector<int32_t>* h_offs,
-               hipStream_t st) {
+               hipStream_t st, const int8_t* spins = nullptr) {
   STCHK(plan_launch(m, n_conn, sites, B, M_max, with_base, offs, cb, cm, upper, st));
+  if (spins) {
+    const long n = (long)B * m->desc.N;
+    spin_check_kernel<<<(int)std::min<long>(1024, (n + 1023) / 1024), 256, 0, st>>>(spins, n, *offs + B + 1);
+    HIPCHK(hipGetLastError());
+  }
   h_offs->resize(B + 2);
   HIPCHK(hipMemcpyAsync(h_offs->data(), *offs, (size_t)(B + 2) * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -606,7 +613,7 @@ dn_status logratio_full(dn_model* m, const int8_t* spins, int B, const int32_t* 
                         int M_max, double* logpsi, double* logratio, hipStream_t st) {
   int32_t *offs, *cb, *cm;
   std::vector<int32_t> h_offs;
-  STCHK(plan(m, n_conn, sites, B, M_max, 1, &offs, &cb, &cm, B * (M_max + 1), &h_offs, st));
+  STCHK(plan(m, n_conn, sites, B, M_max, 1, &offs, &cb, &cm, B * (M_max + 1), &h_offs, st, spins));
   const int total = h_offs[B];
   void* prho;
   STCHK(ws_get(m, "full_rho", (size_t)std::max(total, 1) * 2 * sizeof(double), &prho));
@@ -935,7 +942,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
   STCHK(abacus_supported(m));
   int32_t *offs, *cb, *cm;
   std::vector<int32_t> h_offs;
-  STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st));
+  STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st, spins));
   const int ext_max = (h_offs[B + 1] & 4) ? 2 : 0;
   STCHK((abacus_exec<T, DP>(m, spins, B, sites, M_max, offs, cb, cm, h_offs.data(), logpsi, logratio, ext_max, st)));
   return abacus_check(m, st);

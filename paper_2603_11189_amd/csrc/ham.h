@@ -97,7 +97,8 @@ __global__ __launch_bounds__(64) void eloc_kernel(const double* __restrict__ hdi
 // unflipped sample; offs[b] = first entry of sample b, offs[B] = total. The inputs are
 // validated on the way (the host reads offs[B+1] before any other launch): offs[B+1] gets bit
 // 1 if some n_conn is outside [0, M_max], bit 2 if a listed site is outside the chain (the
-// second site may be -1, and must differ from the first). plan_kernel (one block) counts and
+// second site may be -1, and must differ from the first), bit 8 if a spin is not +-1
+// (spin_check_kernel). plan_kernel (one block) counts and
 // scans; plan_fill_kernel (one thread per (sample, slot)) writes the entries, checks the
 // sites (bit 2 of the error word) and notes whether any cluster has two sites (bit 4).
 __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* __restrict__ n_conn, int B, int M_max,
@@ -154,6 +155,16 @@ __global__ void plan_fill_kernel(const int32_t* __restrict__ n_conn, const int32
   }
   // bit 4: the list holds two-site clusters (one request per wave)
   if (__ballot(any_pair) && (threadIdx.x & 63) == 0) atomicOr(&offs[B + 1], 4);
+}
+
+// Bit 8 of the work list's error word when a spin is neither +1 nor -1 (one request per wave).
+__global__ void spin_check_kernel(const int8_t* __restrict__ spins, long n, int32_t* __restrict__ err) {
+  bool bad = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int v = spins[i];
+    bad = bad || (v != 1 && v != -1);
+  }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(err, 8);
 }
 
 // Probe configurations for launch tuning: spin i = +-1 from the low bit of a 32-bit integer

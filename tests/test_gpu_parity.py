@@ -205,18 +205,20 @@ def test_abacus_rejects_wide_pairs(L):
     assert eps(lr.cpu(), ref) <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["n_conn_high", "n_conn_negative", "site_outside", "pair_repeats"])
+@pytest.mark.parametrize("case", ["n_conn_high", "n_conn_negative", "site_outside", "pair_repeats", "spin_zero"])
 @pytest.mark.parametrize("path", ["abacus", "full"])
 def test_logratio_rejects_bad_work_lists(L, case, path):
-    # the work list is validated on the device before any kernel reads it; a good list after
-    # a bad one still gives the oracle's values
+    # the work list and the spins are validated on the device before any kernel reads them; a
+    # good list after a bad one still gives the oracle's values
     shape = di.ModelShape(20, 2, 8, 4, bc="open")
     m, th = _model(L, shape, 3, "stress", "fp64")
     sp = torch.tensor(di.uniform_spins(2, 20, 1), device="cuda")
     sites = torch.tensor([[[2, -1], [5, 6]], [[7, -1], [0, -1]]], dtype=torch.int32, device="cuda")
     n_conn = torch.tensor([2, 2], dtype=torch.int32, device="cuda")
-    bad_sites, bad_n = sites.clone(), n_conn.clone()
-    if case == "n_conn_high":
+    bad_sites, bad_n, bad_sp = sites.clone(), n_conn.clone(), sp.clone()
+    if case == "spin_zero":
+        bad_sp[1, 11] = 0
+    elif case == "n_conn_high":
         bad_n[1] = 3
     elif case == "n_conn_negative":
         bad_n[0] = -1
@@ -225,7 +227,7 @@ def test_logratio_rejects_bad_work_lists(L, case, path):
     else:
         bad_sites[0, 1, 1] = 5
     with pytest.raises(L.DysonNetError) as ei:
-        m.logratio(sp, bad_sites, bad_n, path=path)
+        m.logratio(bad_sp, bad_sites, bad_n, path=path)
     assert ei.value.status == L.DN_EINVAL
     _, lr = m.logratio(sp, sites, n_conn, path=path)
     _, ref = O.plain_logratio(ModelDesc.of(shape), th, sp.cpu().numpy(), sites.cpu().long(), n_conn.cpu().long())
