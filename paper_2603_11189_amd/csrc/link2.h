@@ -305,7 +305,8 @@ template <typename T> struct Flip12Args {
 // read-outs are summed per column over the wave's channels, then over waves and a flip's
 // columns in LDS.
 template <typename T, int DP, bool TWO>
-__global__ __launch_bounds__(4 * DP) void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
+__global__ __launch_bounds__(4 * DP) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int LF = TWO ? 2 : 1, NW = DP / 16;
   using M = Mma<T>;
@@ -413,25 +414,43 @@ __global__ __launch_bounds__(4 * DP) void shallow_kernel(SliceArgs<T> A, Flip12A
   if constexpr (TWO) {
     __syncthreads();
     // x2 = G^(2) e1 + Lam on S_2: thread (channel c, part k) takes columns k, k + 4, ...
+    // The mixer taps g2(s2 - s1) = g2(t2 - w_c - u) depend on the slice positions only; the
+    // link rows of four columns are requested together (offsets t2 + ext_max - ext from dlo
+    // lie inside [0, ND) for every column of the widest slice).
     {
       const int c = tid % DP, part = tid / DP;
       const T* g2c = A.tb.taps + ((long)DP + c) * TS + TO;
-      for (int j2 = part; j2 < P * W2m; j2 += 4) {
-        const int p = j2 / W2m, t2 = j2 - p * W2m;
-        const int* g = gs + SLM_GS * p;
-        const int s2u = g[1] - 2 * wc + t2;
-        T x = 0;
-        if (g[0] >= 0 && t2 < g[2] + 4 * wc + 1 && inside(s2u)) {
-          const int lo1 = g[1] - wc, W1 = g[2] + 2 * wc + 1;
-          const T* g2 = g2c + s2u - lo1;
-          const T* e1c = ab + c * lda + p * W1m;
-          for (int u = 0; u < W1; ++u) x += g2[-u] * e1c[u];
-          const T* lamb = F.lam + (long)(g[0] - A.b0) * N * F.ND * DP + c;
-          const int za = g[1], zb = g[1] + g[2];
-          x += (T)g[6] * lamb[((long)za * F.ND + (s2u - za - F.dlo)) * DP];
-          if (g[4] >= 0) x += (T)g[7] * lamb[((long)wrap(zb) * F.ND + (s2u - zb - F.dlo)) * DP];
+      const int ncol = P * W2m;
+      for (int j0 = part; j0 < ncol; j0 += 16) {
+        T la[4], lb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j2 = j0 + 4 * i;
+          const int p = j2 / W2m, t2 = j2 - p * W2m;
+          const int* g = gs + SLM_GS * (j2 < ncol ? p : 0);
+          const long bl = g[0] >= 0 ? g[0] - A.b0 : 0;
+          const T* lamb = F.lam + bl * N * F.ND * DP + c;
+          la[i] = lamb[((long)g[1] * F.ND + (t2 - 2 * wc - F.dlo)) * DP];
+          lb[i] = lamb[((long)wrap(g[1] + g[2]) * F.ND + (t2 - 2 * wc - g[2] - F.dlo)) * DP];
         }
-        ph[c * SLM_LDC + j2] = x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j2 = j0 + 4 * i;
+          if (j2 >= ncol) break;
+          const int p = j2 / W2m, t2 = j2 - p * W2m;
+          const int* g = gs + SLM_GS * p;
+          const int s2u = g[1] - 2 * wc + t2;
+          T x = 0;
+          if (g[0] >= 0 && t2 < g[2] + 4 * wc + 1 && inside(s2u)) {
+            const int W1 = g[2] + 2 * wc + 1;
+            const T* g2 = g2c + t2 - wc;
+            const T* e1c = ab + c * lda + p * W1m;
+            for (int u = 0; u < W1; ++u) x += g2[-u] * e1c[u];
+            x += (T)g[6] * la[i];
+            if (g[4] >= 0) x += (T)g[7] * lb[i];
+          }
+          ph[c * SLM_LDC + j2] = x;
+        }
       }
     }
     __syncthreads();
