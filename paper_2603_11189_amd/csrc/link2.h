@@ -339,26 +339,38 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
     slm_rows<T, DP>(A.tb.Vt + (long)DP * DP, wave, lane, v2);
     slm_rows<T, DP>(A.tb.Ut + (long)DP * DP, wave, lane, u2);
   }
-  // the lane's S_1 columns: x1 = dchi1 (p0^(1) + c_a Pq(i - z_a) + c_b Pq(i - z_b)) to LDS
+  // the lane's S_1 columns: x1 = dchi1 (p0^(1) + c_a Pq(i - z_a) + c_b Pq(i - z_b)) to LDS;
+  // operands of all columns are requested first (addresses clamped to valid ones for columns
+  // that hold no slice site; the Pq offsets t - w_c and t - w_c - ext stay in its margins)
+  {
+    T pv[SLM_NT][4], qa[SLM_NT][4], qb[SLM_NT][4];
+    bool v1q[SLM_NT];
 #pragma unroll
-  for (int n = 0; n < SLM_NT; ++n) {
-    const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
-    const int* g = gs + SLM_GS * (p < P ? p : 0);
-    const int s1u = g[1] - wc + t;
-    const bool v1 = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
-    const int s1 = v1 ? wrap(s1u) : 0;
-    const T* p01 = F.p0 + (long)(v1 ? g[0] - A.b0 : 0) * fld + s1;
-    const T ca = (T)g[6], cb = (T)g[7];
-    const int za = g[1], zb = g[1] + g[2];
+    for (int n = 0; n < SLM_NT; ++n) {
+      const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
+      const int* g = gs + SLM_GS * (p < P ? p : 0);
+      const int s1u = g[1] - wc + t;
+      v1q[n] = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
+      const int s1 = v1q[n] ? wrap(s1u) : g[1];
+      const T* p01 = F.p0 + (long)(g[0] >= 0 ? g[0] - A.b0 : 0) * fld + s1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ch = 16 * wave + M::row(lane, r);
-      T x = 0;
-      if (v1) {
-        const T* pq = A.tb.Pq + (long)ch * TS + TO + s1u;
-        x = dch[0][n][r] * (p01[(long)ch * Np] + ca * pq[-za] + cb * pq[-zb]);
+      for (int r = 0; r < 4; ++r) {
+        const long ch = 16 * wave + M::row(lane, r);
+        pv[n][r] = p01[ch * Np];
+        const T* pq = A.tb.Pq + ch * TS + TO + t - wc;
+        qa[n][r] = pq[0];
+        qb[n][r] = pq[-g[2]];
       }
-      ph[ch * SLM_LDC + j] = x;
+    }
+#pragma unroll
+    for (int n = 0; n < SLM_NT; ++n) {
+      const int j = 16 * n + col, p = j / W1m;
+      const int* g = gs + SLM_GS * (p < P ? p : 0);
+      const T ca = (T)g[6], cb = (T)g[7];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ph[(16 * wave + M::row(lane, r)) * SLM_LDC + j] =
+            v1q[n] ? dch[0][n][r] * (pv[n][r] + ca * qa[n][r] + cb * qb[n][r]) : T(0);
     }
   }
   __syncthreads();
@@ -454,42 +466,55 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
       }
     }
     __syncthreads();
-    // q2 = V^(2) x2; x = dchi2 (p0^(2) + q2) to LDS (over e1, whose readers are done)
+    // q2 = V^(2) x2; x = dchi2 (p0^(2) + q2) to LDS (over e1, whose readers are done). The
+    // operands of all columns are requested before the products (clamped addresses).
     {
+      bool v2q[SLM_NT];
+      int s2q[SLM_NT];
+      T p2v[SLM_NT][4];
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        const int j = 16 * n + col, p = j / W2m, t = j - p * W2m;
+        const int* g = gs + SLM_GS * (p < P ? p : 0);
+        const int s2u = g[1] - 2 * wc + t;
+        v2q[n] = p < P && g[0] >= 0 && t < g[2] + 4 * wc + 1 && inside(s2u);
+        s2q[n] = v2q[n] ? wrap(s2u) : g[1];
+        const T* p02 = F.p0 + F.fldB + (long)(g[0] >= 0 ? g[0] - A.b0 : 0) * fld + s2q[n];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p2v[n][r] = p02[(long)(16 * wave + M::row(lane, r)) * Np];
+      }
       acc_t q2[SLM_NT];
       slm_prod_n<T, DP>((P * W2m + 15) / 16, v2, ph, SLM_LDC, q, col, q2);
 #pragma unroll
       for (int n = 0; n < SLM_NT; ++n) {
-        const int j = 16 * n + col, p = j / W2m, t = j - p * W2m;
-        const int* g = gs + SLM_GS * (p < P ? p : 0);
-        const int s2u = g[1] - 2 * wc + t;
-        const bool v2ok = p < P && g[0] >= 0 && t < g[2] + 4 * wc + 1 && inside(s2u);
-        const T* p02 = F.p0 + F.fldB + (long)(v2ok ? g[0] - A.b0 : 0) * fld + (v2ok ? wrap(s2u) : 0);
+        const int j = 16 * n + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          ab[(16 * wave + M::row(lane, r)) * lda + j] = v2q[n] ? dch[LF - 1][n][r] * (p2v[n][r] + q2[n][r]) : T(0);
+      }
+      T w0v[SLM_NT][4], w1v[SLM_NT][4];
+#pragma unroll
+      for (int n = 0; n < SLM_NT; ++n) {
+        const T* w0 = A.tb.Wk + s2q[n];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ch = 16 * wave + M::row(lane, r);
-          ab[ch * lda + j] = v2ok ? dch[LF - 1][n][r] * (p02[(long)ch * Np] + q2[n][r]) : T(0);
+          const long o = (long)(16 * wave + M::row(lane, r)) * Np;
+          w0v[n][r] = w0[o];
+          w1v[n][r] = w0[fld + o];
         }
       }
-    }
-    __syncthreads();
-    // e2 = U^(2) x, read out with Wk on S_2
-    {
+      __syncthreads();
+      // e2 = U^(2) x, read out with Wk on S_2
       acc_t e2[SLM_NT];
       slm_prod_n<T, DP>((P * W2m + 15) / 16, u2, ab, lda, q, col, e2);
 #pragma unroll
       for (int n = 0; n < SLM_NT; ++n) {
-        const int j = 16 * n + col, p = j / W2m, t = j - p * W2m;
-        const int* g = gs + SLM_GS * (p < P ? p : 0);
-        const int s2u = g[1] - 2 * wc + t;
-        if (p < P && g[0] >= 0 && t < g[2] + 4 * wc + 1 && inside(s2u)) {
-          const T* w0 = A.tb.Wk + wrap(s2u);
+        if (v2q[n]) {
           T q0 = 0, q1 = 0;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const long o = (long)(16 * wave + M::row(lane, r)) * Np;
-            q0 += w0[o] * e2[n][r];
-            q1 += w0[fld + o] * e2[n][r];
+            q0 += w0v[n][r] * e2[n][r];
+            q1 += w1v[n][r] * e2[n][r];
           }
           ob0[n] = (double)q0;
           ob1[n] = (double)q1;
