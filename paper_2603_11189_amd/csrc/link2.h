@@ -155,6 +155,7 @@ template <typename T> __global__ __launch_bounds__(256) void lam_fwd_kernel(LamA
   const int b = blockIdx.x, c0 = blockIdx.y * a.chf;
   const T* x = a.chi1 + (long)b * a.DP * a.Np;
   fft_twiddles(twr, twi, logn);
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < np * n; idx += blockDim.x) {
     const int p = idx >> logn, k = idx & (n - 1);
     int src;
@@ -201,12 +202,38 @@ template <typename T, int DP> __global__ __launch_bounds__(256) void lam_gemm_ke
   const int nh = (1 << a.logn) / 2 + 1;
   const int w = blockIdx.x, b0 = blockIdx.y * 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
-  for (int idx = threadIdx.x; idx < 64 * DP; idx += blockDim.x) {
-    const int bl = idx / DP, cp = idx % DP, b = b0 + bl;
-    const long o = ((long)w * a.Bc + b) * DP + cp;
-    xsr[cp * LDX + bl] = b < a.Bc ? a.Xr[o] : T(0);
-    xsi[cp * LDX + bl] = b < a.Bc ? a.Xi[o] : T(0);
+  // every thread's share of the samples' spectra requested at once (64 DP / 256 per part)
+  constexpr int XPT = 64 * DP / 256, MPT = DP * DP / 256;
+  {
+    T vr[XPT], vi[XPT];
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      const int bl = idx / DP, cp = idx % DP, b = b0 + bl;
+      const long o = ((long)w * a.Bc + (b < a.Bc ? b : 0)) * DP + cp;
+      vr[k] = a.Xr[o];
+      vi[k] = a.Xi[o];
+    }
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      const int bl = idx / DP, cp = idx % DP;
+      const bool ok = b0 + bl < a.Bc;
+      xsr[cp * LDX + bl] = ok ? vr[k] : T(0);
+      xsi[cp * LDX + bl] = ok ? vi[k] : T(0);
+    }
   }
+  // the parameter-only operand of the next offset is requested while the current one is used
+  T mr[MPT], mi[MPT];
+  auto fetch_m = [&](int di) {
+    const long mo = ((long)(a.di0 + di) * nh + w) * DP * DP;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      mr[k] = a.Mr[mo + threadIdx.x + 256 * k];
+      mi[k] = a.Mi[mo + threadIdx.x + 256 * k];
+    }
+  };
+  fetch_m(0);
   __syncthreads();
   T br[KS], bi[KS];
 #pragma unroll
@@ -217,12 +244,13 @@ template <typename T, int DP> __global__ __launch_bounds__(256) void lam_gemm_ke
   const int b = b0 + 16 * wave + j;
   for (int di = 0; di < a.ND; ++di) {
     __syncthreads();  // the previous offset's operand is consumed
-    const long mo = ((long)(a.di0 + di) * nh + w) * DP * DP;
-    for (int idx = threadIdx.x; idx < DP * DP; idx += blockDim.x) {
-      msr[idx] = a.Mr[mo + idx];
-      msi[idx] = a.Mi[mo + idx];
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      msr[threadIdx.x + 256 * k] = mr[k];
+      msi[threadIdx.x + 256 * k] = mi[k];
     }
     __syncthreads();
+    if (di + 1 < a.ND) fetch_m(di + 1);
     acc_t cr[MT], ci[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) cr[mt] = ci[mt] = acc_t{0, 0, 0, 0};
@@ -262,6 +290,7 @@ template <typename T> __global__ __launch_bounds__(256) void lam_inv_kernel(LamA
   T* twi = twr + n / 2;
   const int b = blockIdx.x, di = blockIdx.y, c0 = blockIdx.z * a.chf;
   fft_twiddles(twr, twi, logn);
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < np * n; idx += blockDim.x) {
     const int w = idx / np, p = idx % np;
     const bool lo = w <= n / 2;
