@@ -754,7 +754,10 @@ template <typename T, int DP, bool TWO>
 dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, int F, int P, int Wc, double slice_fl,
                          hipStream_t st, int ext) {
   if (F <= 0) return DN_OK;
-  const size_t lds = slm_lds_bytes<T>(DP, P, Wc, m->desc.w_c);
+  // plus block 2's taps over the offsets between S_1 and S_2 (two blocks)
+  const int W1m = ext + 2 * m->desc.w_c + 1, W2m = W1m + 2 * m->desc.w_c;
+  const size_t lds = slm_lds_bytes<T>(DP, P, Wc, m->desc.w_c) + (TWO ? (size_t)DP * (W1m + W2m - 1) * sizeof(T) : 0);
+  if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "ABACUS slice too wide for one matrix-core product");
   allow_lds(shallow_kernel<T, DP, TWO>, lds);
   const dn_model_desc& d = m->desc;
   const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;

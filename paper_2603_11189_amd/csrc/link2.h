@@ -347,10 +347,18 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   T* ph = reinterpret_cast<T*>(smem_raw);      // [DP][SLM_LDC]
   T* ab = ph + DP * SLM_LDC;                   // [DP][lda]
   int* gs = reinterpret_cast<int*>(ab + DP * lda);
+  // two blocks: block 2's mixer taps at the offsets S_2 - S_1 takes, [DP][TW] from offset g_lo
+  const int W1m = A.ext_max + 2 * wc + 1, W2m = W1m + 2 * wc;  // column strides of S_1, S_2
+  const int TW = W1m + W2m - 1, g_lo = -wc - (W1m - 1);
+  T* g2s = reinterpret_cast<T*>(gs + SLM_GS * P);
   const int nfl = A.dyn.count(A.F);
   const int fg = blockIdx.x * P;
   if (fg >= nfl) return;
   const int f0 = A.dyn.first(A.f0);
+  const int TS = tap_stride(Np), TO = tap_off(Np);
+  if constexpr (TWO)
+    for (int idx = threadIdx.x; idx < DP * TW; idx += blockDim.x)
+      g2s[idx] = A.tb.taps[((long)DP + idx / TW) * TS + TO + g_lo + idx % TW];
   slm_geometry(A, gs, P, fg, nfl, f0, false);
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -359,9 +367,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   const bool per = A.periodic != 0;
   auto wrap = [&](int i) { if (per) { i %= N; if (i < 0) i += N; } return i; };
   auto inside = [&](int i) { return per || (i >= 0 && i < N); };
-  const int TS = tap_stride(Np), TO = tap_off(Np);
   const long fld = (long)DP * Np;
-  const int W1m = A.ext_max + 2 * wc + 1, W2m = W1m + 2 * wc;  // column strides of S_1, S_2
   T u1[DP / 4], v2[DP / 4], u2[DP / 4];
   slm_rows<T, DP>(A.tb.Ut, wave, lane, u1);
   if constexpr (TWO) {
@@ -460,7 +466,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
     // lie inside [0, ND) for every column of the widest slice).
     {
       const int c = tid % DP, part = tid / DP;
-      const T* g2c = A.tb.taps + ((long)DP + c) * TS + TO;
+      const T* g2c = g2s + c * TW - g_lo;  // g2c[r] = tap r of channel c
       const int ncol = P * W2m;
       for (int j0 = part; j0 < ncol; j0 += 16) {
         T la[4], lb[4];
