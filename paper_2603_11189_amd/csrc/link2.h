@@ -415,31 +415,44 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   {
     acc_t e1[SLM_NT];
     slm_prod_n<T, DP>((P * W1m + 15) / 16, u1, ph, SLM_LDC, q, col, e1);
+    // the read-out weights of all columns requested together (clamped addresses)
+    T r0v[SLM_NT][4], r1v[SLM_NT][4];
+    bool v1q[SLM_NT];
+#pragma unroll
+    for (int n = 0; n < SLM_NT; ++n) {
+      const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
+      const int* g = gs + SLM_GS * (p < P ? p : 0);
+      const int s1u = g[1] - wc + t;
+      v1q[n] = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
+      const long bl = g[0] >= 0 ? g[0] - A.b0 : 0;
+      const T* r0 = (TWO ? F.T1 + 2 * bl * fld : A.tb.Wk) + (v1q[n] ? wrap(s1u) : g[1]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long o = (long)(16 * wave + M::row(lane, r)) * Np;
+        r0v[n][r] = r0[o];
+        r1v[n][r] = r0[fld + o];
+      }
+    }
 #pragma unroll
     for (int n = 0; n < SLM_NT; ++n) {
       oa0[n] = 0.0;
       oa1[n] = 0.0;
       const int j = 16 * n + col, p = j / W1m, t = j - p * W1m;
       const int* g = gs + SLM_GS * (p < P ? p : 0);
-      const int s1u = g[1] - wc + t;
-      const bool v1 = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
-      if (v1) {
-        const int s1 = wrap(s1u);
-        const long bl = g[0] - A.b0;
-        const T* r0 = (TWO ? F.T1 + 2 * bl * fld : A.tb.Wk) + s1;
+      if (v1q[n]) {
         T q0 = 0, q1 = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const long o = (long)(16 * wave + M::row(lane, r)) * Np;
-          q0 += r0[o] * e1[n][r];
-          q1 += r0[fld + o] * e1[n][r];
+          q0 += r0v[n][r] * e1[n][r];
+          q1 += r1v[n][r] * e1[n][r];
         }
         oa0[n] = (double)q0;
         oa1[n] = (double)q1;
+        const int s1u = g[1] - wc + t;
         const bool at_a = s1u == g[1], at_b = g[4] >= 0 && s1u == g[1] + g[2];
         if (at_a || at_b) {
           const double cz = at_a ? (double)g[6] : (double)g[7];
-          const T* t0 = F.T0 + 2 * bl * fld + s1;
+          const T* t0 = F.T0 + 2 * (long)(g[0] - A.b0) * fld + wrap(s1u);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int ch = 16 * wave + M::row(lane, r);
