@@ -209,7 +209,12 @@ def summarize(args) -> None:
                 res[wl][k] = {"fetch_bytes_per_launch": fe, "write_bytes_per_launch": wr, "bytes_per_launch": fe + wr,
                               "launches": len(v["FETCH_SIZE"])}
                 md.append(f"| {k} | {len(v['FETCH_SIZE'])} | {fe / 1e6:.1f} | {wr / 1e6:.1f} | {(fe + wr) / 1e6:.1f} |")
-        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        old = json.load(open(path)) if os.path.exists(path) else {}
+        if old.get("source_hash") == res["source_hash"]:  # other workloads of the same sources
+            old.update(res)
+            res = old
+        with open(path, "w") as f:
             json.dump(res, f, indent=1)
         with open(os.path.join(ROOT, "profiles", f"traffic_{wl}.md"), "w") as f:
             f.write("\n".join(md) + "\n")
