@@ -764,7 +764,7 @@ dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, i
   const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
   const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
   PScope ps(m, DN_K_TAIL, st, (fl + slice_fl) * F, by * F);
-  shallow_kernel<T, DP, TWO><<<(F + P - 1) / P, 4 * DP, lds, st>>>(sa, a);
+  shallow_kernel<T, DP, TWO><<<slm_grid((F + P - 1) / P), 4 * DP, lds, st>>>(sa, a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -889,7 +889,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     {
       PScope ps(m, DN_K_SLICE, st, slice_fl * F, (double)F * L * Wmax * d.d * sizeof(T));
       allow_lds(slice_mma_kernel<T, DP>, slds);
-      slice_mma_kernel<T, DP><<<(F + P - 1) / P, 4 * DP, slds, st>>>(sa);
+      slice_mma_kernel<T, DP><<<slm_grid((F + P - 1) / P), 4 * DP, slds, st>>>(sa);
       HIPCHK(hipGetLastError());
     }
     // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once

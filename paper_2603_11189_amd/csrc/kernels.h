@@ -1659,6 +1659,14 @@ constexpr int SLM_GS = 8;              // per flip: b (-1: none), clo, ext, j0, 
 // Flips per workgroup for slices of at most Wc sites (0: too wide for one product).
 __host__ __device__ inline int slm_flips(int Wc) { return SLM_CAP / Wc; }
 
+// Workgroups for G flip groups: a multiple of the XCD count. Workgroup i runs on XCD i % NXCD,
+// so group (i % NXCD) * (grid / NXCD) + i / NXCD keeps consecutive groups -- mostly the flips
+// of one sample, which read the same per-sample caches -- on one XCD and its L2.
+__host__ __device__ inline int slm_grid(int G) { return (G + NXCD - 1) / NXCD * NXCD; }
+__device__ inline int slm_group() {
+  return (int)(blockIdx.x % NXCD) * (int)(gridDim.x / NXCD) + (int)(blockIdx.x / NXCD);
+}
+
 // LDS bytes: phi' [DP][SLM_LDC], a' with halo [DP][lda], geometry [P][SLM_GS].
 // (at least SLM_CAP columns, so that a product may also read its operand from this buffer)
 __host__ __device__ inline int slm_lda(int P, int Wc, int wc) {
@@ -1896,7 +1904,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
   T* ab = ph + DP * SLM_LDC;                   // a' [DP][lda], flip p at columns p * AW ..
   int* gs = reinterpret_cast<int*>(ab + DP * lda);
   const int nfl = A.dyn.count(A.F);
-  const int fg = blockIdx.x * P;
+  const int fg = slm_group() * P;
   if (fg >= nfl) return;
   slm_geometry(A, gs, P, fg, nfl, A.dyn.first(A.f0), true);
   __syncthreads();

@@ -352,7 +352,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   const int TW = W1m + W2m - 1, g_lo = -wc - (W1m - 1);
   T* g2s = reinterpret_cast<T*>(gs + SLM_GS * P);
   const int nfl = A.dyn.count(A.F);
-  const int fg = blockIdx.x * P;
+  const int fg = slm_group() * P;
   if (fg >= nfl) return;
   const int f0 = A.dyn.first(A.f0);
   const int TS = tap_stride(Np), TO = tap_off(Np);
