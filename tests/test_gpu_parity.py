@@ -131,6 +131,8 @@ LR_CASES = [
     (di.ModelShape(19, 2, 4, 2, act="identity", bc="periodic"), di.HamSpec("lrtfim", "periodic", paper_form=1), "fp64", 3),
     (di.ModelShape(64, 2, 32, 16, bc="open"), di.HamSpec("lrtfim", "open"), "fp32", 4),
     (di.ModelShape(70, 3, 20, 8, bc="periodic"), di.HamSpec("j1j2", "periodic"), "fp32", 3),
+    # two blocks with pair exchanges (clusters two sites wide), 64 channels, across the seam
+    (di.ModelShape(40, 2, 64, 32, bc="periodic"), di.HamSpec("j1j2", "periodic"), "fp32", 3),
 ]
 
 
@@ -305,7 +307,7 @@ def test_fp64_multi_tile_match_oracle(L, shape, ham, B):
         assert d_lr <= 1e-10 * lr_scale + floor
 
 
-@pytest.mark.parametrize("name", ["tfim_n256_l4_d64", "j1j2_n128_l4_d64", "tfim_n64_l2_d32"])
+@pytest.mark.parametrize("name", ["tfim_n256_l4_d64", "j1j2_n128_l4_d64", "tfim_n64_l2_d32", "tfim_n256_l2_d64"])
 def test_full_size_sampled(L, name):
     """Benchmark-sized batch in the benchmark's launch configuration, stress draw. The oracle
     recomputes a few samples' log-ratios one by one: ABACUS is held to them element by
