@@ -45,27 +45,55 @@ template <typename T> __device__ inline void fft_twiddles(T* twr, T* twi, int lo
   }
 }
 
-// In-place radix-2 decimation-in-time transforms of nseq complex sequences of length n = 2^logn
-// held in LDS at row stride ld, already in bit-reversed order. Forward: sum_k x_k w^(jk);
-// inverse: the conjugate twiddles (unscaled). Ends with a workgroup barrier.
+// In-place decimation-in-time transforms of nseq complex sequences of length n = 2^logn held
+// in LDS at row stride ld, already in bit-reversed order. Forward: sum_k x_k w^(jk); inverse:
+// the conjugate twiddles (unscaled). Two radix-2 stages at a time (spans h and 2h) as one
+// radix-4 step per thread, after a first radix-2 stage when logn is odd: half the LDS passes
+// and barriers of stage-by-stage butterflies. Ends with a workgroup barrier.
 template <typename T>
 __device__ void fft_stages(T* xr, T* xi, const T* twr, const T* twi, int logn, int ld, int nseq, bool inverse) {
-  const int hn = 1 << (logn - 1);
-  for (int ls = 1; ls <= logn; ++ls) {
-    const int half = 1 << (ls - 1), sh = logn - ls;
+  int ls = 1;
+  if (logn & 1) {  // span-1 stage (twiddle 1)
+    const int hn = 1 << (logn - 1);
     for (int idx = threadIdx.x; idx < nseq * hn; idx += blockDim.x) {
       const int s = idx >> (logn - 1), b = idx & (hn - 1);
-      const int k = b & (half - 1), grp = b >> (ls - 1);
-      const int i = s * ld + (grp << ls) + k, jj = i + half;
-      const T wr = twr[k << sh];
-      const T wi = inverse ? -twi[k << sh] : twi[k << sh];
-      const T xjr = xr[jj], xji = xi[jj];
-      const T tr = wr * xjr - wi * xji, ti = wr * xji + wi * xjr;
-      const T ur = xr[i], ui = xi[i];
-      xr[i] = ur + tr;
-      xi[i] = ui + ti;
-      xr[jj] = ur - tr;
-      xi[jj] = ui - ti;
+      const int i = s * ld + 2 * b;
+      const T ur = xr[i], ui = xi[i], vr = xr[i + 1], vi = xi[i + 1];
+      xr[i] = ur + vr;
+      xi[i] = ui + vi;
+      xr[i + 1] = ur - vr;
+      xi[i + 1] = ui - vi;
+    }
+    __syncthreads();
+    ls = 2;
+  }
+  const int qn = logn >= 2 ? 1 << (logn - 2) : 0;
+  for (; ls < logn; ls += 2) {
+    const int h = 1 << (ls - 1);
+    for (int idx = threadIdx.x; idx < nseq * qn; idx += blockDim.x) {
+      const int s = idx >> (logn - 2), b = idx & (qn - 1);
+      const int k = b & (h - 1), grp = b >> (ls - 1);
+      const int i0 = s * ld + (grp << (ls + 1)) + k, i1 = i0 + h, i2 = i1 + h, i3 = i2 + h;
+      // w1 = W_(2h)^k for the span-h stage, w2 = W_(4h)^k and w3 = W_(4h)^(k+h) = w2 (-+ i)
+      const T w1r = twr[k << (logn - ls)], w1i = inverse ? -twi[k << (logn - ls)] : twi[k << (logn - ls)];
+      const T w2r = twr[k << (logn - ls - 1)], w2i = inverse ? -twi[k << (logn - ls - 1)] : twi[k << (logn - ls - 1)];
+      const T w3r = inverse ? -w2i : w2i, w3i = inverse ? w2r : -w2r;
+      const T a0r = xr[i0], a0i = xi[i0], a1r = xr[i1], a1i = xi[i1];
+      const T a2r = xr[i2], a2i = xi[i2], a3r = xr[i3], a3i = xi[i3];
+      const T t1r = w1r * a1r - w1i * a1i, t1i = w1r * a1i + w1i * a1r;
+      const T t3r = w1r * a3r - w1i * a3i, t3i = w1r * a3i + w1i * a3r;
+      const T b0r = a0r + t1r, b0i = a0i + t1i, b1r = a0r - t1r, b1i = a0i - t1i;
+      const T b2r = a2r + t3r, b2i = a2i + t3i, b3r = a2r - t3r, b3i = a2i - t3i;
+      const T u2r = w2r * b2r - w2i * b2i, u2i = w2r * b2i + w2i * b2r;
+      const T u3r = w3r * b3r - w3i * b3i, u3i = w3r * b3i + w3i * b3r;
+      xr[i0] = b0r + u2r;
+      xi[i0] = b0i + u2i;
+      xr[i2] = b0r - u2r;
+      xi[i2] = b0i - u2i;
+      xr[i1] = b1r + u3r;
+      xi[i1] = b1i + u3i;
+      xr[i3] = b1r - u3r;
+      xi[i3] = b1i - u3i;
     }
     __syncthreads();
   }
