@@ -1202,7 +1202,7 @@ template <typename T, int DP> struct RunSweep {
     const int nblk = (N + spacing - 1) / spacing;
     const int K = (nblk - parity + 1) / 2;
     if (K <= 0) return DN_OK;
-    void *psi, *psr, *pnc, *pks, *ppe, *pfr, *plr, *pdom;
+    void *psi, *psr, *pnc, *pks, *ppe, *pfr, *plr, *pdom, *pch, *prs;
     STCHK(ws_get(m, "sw_sites", (size_t)B * K * 2 * 4, &psi));
     STCHK(ws_get(m, "sw_sites_r", (size_t)B * K * 2 * 4, &psr));
     STCHK(ws_get(m, "sw_nconn", (size_t)B * 4, &pnc));
@@ -1211,6 +1211,8 @@ template <typename T, int DP> struct RunSweep {
     STCHK(ws_get(m, "sw_frozen", 4, &pfr));
     STCHK(ws_get(m, "sw_lr", (size_t)B * K * 8, &plr));
     STCHK(ws_get(m, "sw_dom", (size_t)B * K * 2 * 8, &pdom));
+    STCHK(ws_get(m, "sw_chain", (size_t)B * 4, &pch));
+    STCHK(ws_get(m, "sw_rows", (size_t)B * N, &prs));
     SweepArgs a{};
     a.B = B; a.N = N; a.K = K; a.spacing = spacing; a.parity = parity; a.eps = eps; a.r_site = r_site; a.u = u;
     a.spins = spins; a.sites = (int32_t*)psi; a.sites_r = (int32_t*)psr; a.n_conn = (int32_t*)pnc;
@@ -1219,23 +1221,32 @@ template <typename T, int DP> struct RunSweep {
     const int gs = (int)std::min<long>(4096, ((long)B * K + 255) / 256);
     sweep_init_kernel<<<gs, 256, 0, st>>>(a);
     HIPCHK(hipGetLastError());
+    // the first round takes every chain; a refresh round only the chains that froze, gathered
+    // into rows of their own (so the background forward and links are rebuilt for them alone)
+    int rows = B;
     for (int round = 0;; ++round) {
-      sweep_round_kernel<<<gs, 256, 0, st>>>(a);
+      a.rows = rows;
+      a.chain = round == 0 ? nullptr : (const int32_t*)pch;
+      if (round > 0) sweep_list_kernel<<<1, 1024, 0, st>>>(a.kstart, B, K, (int32_t*)pch);
+      const int gr = (int)std::min<long>(4096, ((long)rows * std::max(K, N) + 255) / 256);
+      sweep_round_kernel<<<gr, 256, 0, st>>>(a, (int8_t*)prs);
       HIPCHK(hipGetLastError());
+      const int8_t* rs = round == 0 ? spins : (const int8_t*)prs;
       int32_t *offs, *cb, *cm;
       std::vector<int32_t> h_offs;
-      STCHK(plan(m, a.n_conn, a.sites_r, B, K, 0, &offs, &cb, &cm, std::max(B * K, 1), &h_offs, st));
-      STCHK((abacus_exec<T, DP>(m, spins, B, a.sites_r, K, offs, cb, cm, h_offs.data(), nullptr, (double*)plr, 0, st,
+      STCHK(plan(m, a.n_conn, a.sites_r, rows, K, 0, &offs, &cb, &cm, std::max(rows * K, 1), &h_offs, st));
+      STCHK((abacus_exec<T, DP>(m, rs, rows, a.sites_r, K, offs, cb, cm, h_offs.data(), nullptr, (double*)plr, 0, st,
                                 (double*)pdom)));
       void* pOm;
-      STCHK(ws_get(m, "ab_Om0", (size_t)B * 2 * sizeof(double), &pOm));
+      STCHK(ws_get(m, "ab_Om0", (size_t)rows * 2 * sizeof(double), &pOm));
       a.Om0 = (const double*)pOm;
-      sweep_accept_kernel<<<(B + 255) / 256, 256, 0, st>>>(a);
+      sweep_accept_kernel<<<(rows + 255) / 256, 256, 0, st>>>(a);
       HIPCHK(hipGetLastError());
       int frozen = 0;
       HIPCHK(hipMemcpyAsync(&frozen, a.frozen, 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (!frozen) break;
+      rows = frozen;  // the chains that froze are exactly those with proposals left
     }
     return abacus_check(m, st);
   }

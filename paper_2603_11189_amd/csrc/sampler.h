@@ -19,20 +19,22 @@ namespace dn {
 
 struct SweepArgs {
   int B, N, K, spacing, parity;
+  int rows;              // chains this round (all of them in the first round, then the frozen ones)
+  const int32_t* chain;  // [rows] chain of each row (nullable: row b is chain b)
   double eps;
   const double* r_site;  // [B][K] proposal draws
   const double* u;       // [B][K] acceptance draws
   int8_t* spins;         // [B][N] chains, updated in place
   int32_t* sites;        // [B][K][2] proposals (second site -1)
-  int32_t* sites_r;      // [B][K][2] this round's remaining proposals, from kstart
-  int32_t* n_conn;       // [B] this round's count
+  int32_t* sites_r;      // [rows][K][2] this round's remaining proposals, from kstart
+  int32_t* n_conn;       // [rows] this round's count
   int32_t* kstart;       // [B] first proposal not yet decided (K: done)
   int32_t* pending;      // [B] 1: the proposal at kstart froze the chain (decide it exactly next)
   int32_t* accepted;     // [B][K] 0/1
   int32_t* refreshes;    // [B]
   int32_t* frozen;       // [1] chains that froze in this round
-  const double* Om0;     // [B][2] output of this round's background
-  const double* dom;     // [B][K][2] this round's changes (index k - kstart)
+  const double* Om0;     // [rows][2] output of this round's background
+  const double* dom;     // [rows][K][2] this round's changes (index k - kstart)
 };
 
 // Proposals of the half-sweep and the initial state of every chain.
@@ -49,29 +51,56 @@ __global__ void sweep_init_kernel(SweepArgs a) {
   }
 }
 
-// The remaining proposals of every chain as this round's work list.
-__global__ void sweep_round_kernel(SweepArgs a) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)a.B * a.K; i += (long)gridDim.x * blockDim.x) {
-    const int b = (int)(i / a.K), m = (int)(i % a.K);
+// The rows of the next round: the chains that froze, in chain order (one workgroup scans).
+__global__ __launch_bounds__(1024) void sweep_list_kernel(const int32_t* __restrict__ kstart, int B, int K,
+                                                          int32_t* __restrict__ chain) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, per = (B + 1023) / 1024;
+  const int b0 = t * per, b1 = min(B, b0 + per);
+  int cnt = 0;
+  for (int b = b0; b < b1; ++b) cnt += kstart[b] < K;
+  part[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int pos = part[t] - cnt;
+  for (int b = b0; b < b1; ++b)
+    if (kstart[b] < K) chain[pos++] = b;
+}
+
+// The remaining proposals of every row's chain as this round's work list, and the row's
+// configuration (rows that are not chains of the same index take a copy of their chain).
+__global__ void sweep_round_kernel(SweepArgs a, int8_t* __restrict__ row_spins) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)a.rows * a.K; i += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / a.K), m = (int)(i % a.K);
+    const int b = a.chain ? a.chain[row] : row;
     const int k0 = a.kstart[b];
     const int k = k0 + m;
     a.sites_r[2 * i] = k < a.K ? a.sites[2 * ((long)b * a.K + k)] : -1;
     a.sites_r[2 * i + 1] = -1;
-    if (m == 0) a.n_conn[b] = a.K - min(k0, a.K);
+    if (m == 0) a.n_conn[row] = a.K - min(k0, a.K);
   }
+  if (a.chain)
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)a.rows * a.N; i += (long)gridDim.x * blockDim.x)
+      row_spins[i] = a.spins[(long)a.chain[i / a.N] * a.N + i % a.N];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.frozen[0] = 0;
 }
 
-// Sequential screened acceptance, one thread per chain.
+// Sequential screened acceptance, one thread per row (chain).
 __global__ void sweep_accept_kernel(SweepArgs a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.B) return;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.rows) return;
+  const int b = a.chain ? a.chain[row] : row;
   const int k0 = a.kstart[b];
   if (k0 >= a.K) return;
-  double om0 = a.Om0[2 * b], om1 = a.Om0[2 * b + 1];
+  double om0 = a.Om0[2 * row], om1 = a.Om0[2 * row + 1];
   const bool exact_first = a.pending[b] != 0;
   for (int k = k0; k < a.K; ++k) {
-    const long o = (long)b * a.K + (k - k0);
+    const long o = (long)row * a.K + (k - k0);
     const double d0 = a.dom[2 * o], d1 = a.dom[2 * o + 1];
     const double P = fmin(1.0, exp(2.0 * (lcd_d(om0, d0) + lcd_d(om1, d1))));
     const double uu = a.u[(long)b * a.K + k];
