@@ -1262,16 +1262,20 @@ template <typename T, int DP> struct RunSR {
     void *pv, *pb, *psc;
     STCHK(ws_get(m, "sr_vec", (size_t)6 * P * 8, &pv));
     STCHK(ws_get(m, "sr_smp", (size_t)3 * B * 8, &pb));
-    STCHK(ws_get(m, "sr_sc", 8 * 8, &psc));
+    STCHK(ws_get(m, "sr_sc", (8 + SR_DOT_WG) * 8, &psc));
     double *x = (double*)pv, *r = x + P, *p = r + P, *Ap = p + P, *F = Ap + P, *Ob = F + P;
-    double *wv = (double*)pb, *we = wv + B, *t = we + B, *sc = (double*)psc;
+    double *wv = (double*)pb, *we = wv + B, *t = we + B, *sc = (double*)psc, *dpart = sc + 8;
+    auto dot = [&](const double* u, const double* v, double* out) {
+      sr_dot_kernel<<<SR_DOT_WG, 256, 0, st>>>(u, v, P, dpart);
+      sr_dot_sum_kernel<<<1, 256, 0, st>>>(dpart, out);
+    };
     const int gp = (int)((P + 255) / 256), gv = (int)std::min<long>(1024, (P + 255) / 256);
     sr_energy_kernel<<<1, 1024, 0, st>>>(E, w, B, wv, we, sc + 5);
     sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, wv, nullptr, 0.0, Ob);
     sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, we, nullptr, 0.0, F);
     sr_init_kernel<<<gv, 256, 0, st>>>(x, r, p, F, P);
-    sr_dot_kernel<<<1, 1024, 0, st>>>(F, F, P, sc + 0);
-    sr_dot_kernel<<<1, 1024, 0, st>>>(F, F, P, sc + 4);
+    dot(F, F, sc + 0);
+    dot(F, F, sc + 4);
     HIPCHK(hipGetLastError());
     double h[8] = {};
     HIPCHK(hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, st));
@@ -1280,12 +1284,12 @@ template <typename T, int DP> struct RunSR {
     int it = 0;
     if (fnorm > 0.0) {
       for (it = 1; it <= max_iter; ++it) {
-        sr_dot_kernel<<<1, 1024, 0, st>>>(Ob, p, P, sc + 3);
+        dot(Ob, p, sc + 3);
         sr_rowdot_kernel<T><<<B, 256, 0, st>>>(O, P, p, sc + 3, wv, t);
         sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, t, p, shift, Ap);
-        sr_dot_kernel<<<1, 1024, 0, st>>>(p, Ap, P, sc + 1);
+        dot(p, Ap, sc + 1);
         sr_step_kernel<<<gv, 256, 0, st>>>(x, r, p, Ap, P, sc);
-        sr_dot_kernel<<<1, 1024, 0, st>>>(r, r, P, sc + 2);
+        dot(r, r, sc + 2);
         sr_dir_kernel<<<gv, 256, 0, st>>>(p, r, P, sc);
         sr_roll_kernel<<<1, 1, 0, st>>>(sc);
         HIPCHK(hipGetLastError());

@@ -41,15 +41,15 @@ __global__ __launch_bounds__(256) void sr_colsum_kernel(const T* __restrict__ O,
                                                         double shift, double* __restrict__ out) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
-  // four partial sums, eight rows requested together (the loads, not the adds, set the pace)
+  // four partial sums, sixteen rows requested together (the loads, not the adds, set the pace)
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   int b = 0;
-  for (; b + 8 <= B; b += 8) {
-    T o[8];
+  for (; b + 16 <= B; b += 16) {
+    T o[16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = O[(long)(b + i) * P + k];
+    for (int i = 0; i < 16; ++i) o[i] = O[(long)(b + i) * P + k];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s[i & 3] += coef[b + i] * (double)o[i];
+    for (int i = 0; i < 16; ++i) s[i & 3] += coef[b + i] * (double)o[i];
   }
   for (; b < B; ++b) s[0] += coef[b] * (double)O[(long)b * P + k];
   double r = (s[0] + s[1]) + (s[2] + s[3]);
@@ -65,32 +65,43 @@ __global__ __launch_bounds__(256) void sr_rowdot_kernel(const T* __restrict__ O,
   __shared__ double part[4];
   const int b = blockIdx.x;
   const T* row = O + (long)b * P;
-  double s0 = 0.0, s1 = 0.0;
+  // eight elements of the row requested together, four partial sums
+  double sp[4] = {0.0, 0.0, 0.0, 0.0};
+  const long st = blockDim.x;
   long k = threadIdx.x;
-  for (; k + blockDim.x < P; k += 2 * blockDim.x) {
-    s0 += (double)row[k] * v[k];
-    s1 += (double)row[k + blockDim.x] * v[k + blockDim.x];
+  for (; k + 7 * st < P; k += 8 * st) {
+    T o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = row[k + i * st];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sp[i & 3] += (double)o[i] * v[k + i * st];
   }
-  if (k < P) s0 += (double)row[k] * v[k];
-  double s = wave_sum(s0 + s1);
+  for (; k < P; k += st) sp[0] += (double)row[k] * v[k];
+  double s = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) t[b] = w[b] * (part[0] + part[1] + part[2] + part[3] - *sub);
 }
 
-// *out = a . b in a fixed order (one workgroup).
-__global__ __launch_bounds__(1024) void sr_dot_kernel(const double* __restrict__ a, const double* __restrict__ b, long n,
-                                                      double* __restrict__ out) {
-  __shared__ double part[1024];
+// a . b in a fixed order, in two steps: SR_DOT_WG workgroups of 256 threads form partial sums
+// (sr_dot_kernel), one workgroup adds them (sr_dot_sum_kernel).
+constexpr int SR_DOT_WG = 256;
+__global__ __launch_bounds__(256) void sr_dot_kernel(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
   double s = 0.0;
-  for (long i = threadIdx.x; i < n; i += blockDim.x) s += a[i] * b[i];
-  part[threadIdx.x] = s;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)SR_DOT_WG * 256) s += a[i] * b[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = part[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ __launch_bounds__(256) void sr_dot_sum_kernel(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = wave_sum(part[threadIdx.x]);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // CG scalars in one small array: [0] r.r, [1] p.Ap, [2] new r.r, [3] Obar.p
