@@ -220,8 +220,9 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
  * the Jacobian of the Green's-function taps (float64, shared by all samples, rebuilt after each
  * dn_model_set_params). grads: [B][P] in the model's field type (float for DN_PREC_FP32, double
  * for DN_PREC_FP64), nullable (then kept in the workspace); logpsi [B] nullable; weights [B] and
- * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open chains with
- * inject_phi = 0 only (DN_EUNSUPPORTED otherwise). Asynchronous on the stream. */
+ * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open and periodic
+ * chains (periodic: the Jacobian of the aliased kernel, Sec. V); inject_phi = 0 only
+ * (DN_EUNSUPPORTED otherwise). Asynchronous on the stream. */
 dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
                          const double* weights, double* wsum, void* stream);
 

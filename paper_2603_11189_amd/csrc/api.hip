@@ -981,13 +981,32 @@ dn_status ensure_jac(dn_model* m, hipStream_t st) {
   if (d.prec != DN_PREC_FP64 && !m->jac32 && hipMalloc(&m->jac32, n * sizeof(float)) != hipSuccess)
     return fail(DN_ENOMEM, "hipMalloc failed for the S4 tap Jacobian");
   void* pws;
-  const long per = 2L * (2L * d.s * d.s + d.s + 5L * d.N * d.s);
+  const bool per_bc = d.bc == DN_BC_PERIODIC;
+  const long per = per_bc ? 2L * (4L * d.s * d.s + d.s + (long)d.s * (9L * d.N + 3))
+                          : 2L * (2L * d.s * d.s + d.s + 5L * d.N * d.s);
+  // The direction kernels keep 3N (open) or 7N (periodic) complex projections in LDS; the
+  // periodic prep kernel adds 2(N+1) doubles to its static arrays. Within the model's N limit
+  // both fit; the check keeps a raised limit from turning into a failed launch.
+  const size_t dir_lds = (per_bc ? 7 : 3) * (size_t)d.N * sizeof(cx);
+  const size_t prep_lds = per_bc ? 2 * ((size_t)d.N + 1) * sizeof(double) : 0;
+  if (S4JAC_DIR_STATIC_LDS + dir_lds > LDS_MAX || S4JACP_STATIC_LDS + prep_lds > LDS_MAX)
+    return fail(DN_EUNSUPPORTED, "the S4 tap Jacobian of this chain length does not fit in LDS");
   STCHK(ws_get(m, "jac_ws", (size_t)nch * per * sizeof(double), &pws));
   {
     PScope ps(m, DN_K_S4GEN, st, 8.0 * nch * (double)d.N * d.s * d.s * 6, (double)n * 8);
-    s4jac_prep_kernel<<<nch, S4_THREADS, 0, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws, m->jac64);
-    s4jac_dir_kernel<<<dim3(nch, 12 * d.s), 256, 3 * (size_t)d.N * sizeof(cx), st>>>(
-        m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws, m->jac64);
+    if (per_bc) {  // the aliased kernel of periodic chains
+      allow_lds(s4jacp_prep_kernel, prep_lds);
+      allow_lds(s4jacp_dir_kernel, dir_lds);
+      s4jacp_prep_kernel<<<nch, S4_THREADS, prep_lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws,
+                                                            m->jac64);
+      s4jacp_dir_kernel<<<dim3(nch, 12 * d.s), 256, dir_lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s,
+                                                                   (double*)pws, m->jac64);
+    } else {
+      allow_lds(s4jac_dir_kernel, dir_lds);
+      s4jac_prep_kernel<<<nch, S4_THREADS, 0, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s, (double*)pws, m->jac64);
+      s4jac_dir_kernel<<<dim3(nch, 12 * d.s), 256, dir_lds, st>>>(m->params, m->lay.off_s4, d.N, d.d, d.s,
+                                                                  (double*)pws, m->jac64);
+    }
   }
   if (d.prec != DN_PREC_FP64) convert_kernel<<<1024, 256, 0, st>>>(m->jac64, m->jac32, n);
   HIPCHK(hipGetLastError());
@@ -1142,7 +1161,6 @@ template <typename T, int DP>
 dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, void* grads_out, const double* w,
                       double* wsum, hipStream_t st) {
   const dn_model_desc& d = m->desc;
-  if (d.bc != DN_BC_OPEN) return fail(DN_EUNSUPPORTED, "per-sample gradients are implemented for open chains only");
   if (d.inject_phi) return fail(DN_EUNSUPPORTED, "per-sample gradients need inject_phi = 0");
   STCHK(ensure_jac(m, st));
   T* grads = (T*)grads_out;

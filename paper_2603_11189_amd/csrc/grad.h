@@ -679,6 +679,343 @@ __global__ __launch_bounds__(256) void s4jac_dir_kernel(const double* __restrict
 }
 
 // ------------------------------------------------------------------------------------------
+// S4 tap Jacobian of periodic chains (the aliased kernel), float64:
+//   g_p = Re(C+^T A_d^p Q B_d) + Re(C-^T A_d^(N-p) Q B_d),  Q = (I - A_d^N)^-1,  p = 0..N-1,
+// stored at the Toeplitz rows r = p and r = p - N of the open layout (the kernel tables hold
+// the circulant as a Toeplitz matrix with g_(r mod N) at offset r). Q is a function of A_d and
+// commutes with it, so with Xt_m = A_d^m Q B_d, w+-_m = C+-^T A_d^m, wt+-_m = C+-^T Q A_d^m:
+//  * C+- directions: Re(e_n . Xt_p), Re(e_n . Xt_(N-p));
+//  * Bbar directions: d(Q B_d) = Q M^-1 Delta e_n, so d g_p = Re(Delta (wt+_p M^-1)_n) +
+//    Re(Delta (wt-_(N-p) M^-1)_n);
+//  * rank-one directions dA_d = alpha beta^T, dB_d = alpha b0 (b0 = b^T B_d): with
+//    dQ = Q d(A_d^N) Q and c_m = beta^T Xt_m,
+//      C^T d(A_d^j Q B_d) = sum_(k<j) (w_k.alpha) c_(j-1-k) + sum_(k<N) (wt_(j+k).alpha) c_(N-1-k)
+//                           + (wt_j.alpha) b0,  j = p (C+) or N - p (C-);
+//  * the step offset: the tangent of A_d^N Q B_d by the recurrence T_(j+1) = dA Xt_j + A_d T_j,
+//    d(Q B_d) = Q (T_N + dB_d), dXt_(p+1) = dA Xt_p + A_d dXt_p.
+__device__ inline long s4pp_stride(int N, int s) { return 2L * (4L * s * s + s + (long)s * (9L * N + 3)); }
+
+struct S4PerPtr {
+  cx *Minv, *Ad, *Q, *dA, *Bd, *Xt, *Wp, *Wm, *Wtp, *Wtm, *Utp, *Utm;
+};
+__device__ inline S4PerPtr s4pp_ptrs(double* ws, int ch, int N, int s) {
+  S4PerPtr q;
+  cx* b = reinterpret_cast<cx*>(ws + (long)ch * s4pp_stride(N, s));
+  q.Minv = b; q.Ad = q.Minv + s * s; q.Q = q.Ad + s * s; q.dA = q.Q + s * s; q.Bd = q.dA + s * s;
+  q.Xt = q.Bd + s;                      // [N+1][s]
+  q.Wp = q.Xt + (long)(N + 1) * s;      // [N][s]
+  q.Wm = q.Wp + (long)N * s;            // [N][s]
+  q.Wtp = q.Wm + (long)N * s;           // [2N][s]
+  q.Wtm = q.Wtp + 2L * N * s;           // [2N][s]
+  q.Utp = q.Wtm + 2L * N * s;           // [N+1][s]
+  q.Utm = q.Utp + (long)(N + 1) * s;    // [N+1][s]
+  return q;
+}
+
+// Value v of direction k at circulant offset p, written to both Toeplitz rows.
+__device__ inline void s4pp_put(double* Jc, int N, int NP, int p, int k, double v) {
+  Jc[(long)(p + N - 1) * NP + k] = v;
+  if (p >= 1) Jc[(long)(p - 1) * NP + k] = v;
+}
+
+// Static LDS of s4jacp_prep_kernel (its dynamic part is 2(N+1) doubles) and of the direction
+// kernels s4jac_dir_kernel / s4jacp_dir_kernel (their dynamic part is 3N / 7N complex values).
+constexpr size_t S4JACP_STATIC_LDS =
+    sizeof(cx) * (S4_SMAX * (2 * S4_SMAX + 1) + 4 * S4_SMAX * S4_SMAX + 7 * S4_SMAX) + sizeof(int);
+constexpr size_t S4JAC_DIR_STATIC_LDS = sizeof(cx) * (4 * S4_SMAX + 1);
+
+// One wave per (mixer, channel): M^-1, A_d, Q, B_d, Xt, w+-, wt+-, wt+- M^-1 and the step direction.
+__global__ __launch_bounds__(S4_THREADS) void s4jacp_prep_kernel(const double* __restrict__ params, long s4_off,
+                                                                 int N, int d, int s, double* __restrict__ ws,
+                                                                 double* __restrict__ J) {
+  __shared__ cx G[S4_SMAX * (2 * S4_SMAX + 1)];
+  __shared__ cx Abar[S4_SMAX * S4_SMAX];
+  __shared__ cx W1[S4_SMAX * S4_SMAX], W2[S4_SMAX * S4_SMAX], W3[S4_SMAX * S4_SMAX];
+  __shared__ cx xa[S4_SMAX], xb[S4_SMAX], ya[S4_SMAX], yb[S4_SMAX], Cp[S4_SMAX], Cm[S4_SMAX], fac[S4_SMAX];
+  __shared__ int piv_s;
+  extern __shared__ double resp[];  // [2][N+1]: Re(C+ . dXt_p), Re(C- . dXt_p)
+  const int t = threadIdx.x;
+  const int ch = blockIdx.x, c = ch % d;
+  const int NP = 12 * s + 1;
+  const double* p = params + s4_off + (long)ch * NP;
+  const double delta = exp(log(1e-2) + log(10.0) * (double)c / (double)(d > 1 ? d - 1 : 1) + p[12 * s]);
+  const S4PerPtr w = s4pp_ptrs(ws, ch, N, s);
+  const int ld = 2 * s + 1;
+  // M^-1 from [M | I], M = I - Delta/2 Abar
+  for (int idx = t; idx < s * s; idx += S4_THREADS) {
+    int i = idx / s, jj = idx % s;
+    cx a = cmul(cx{p[2 * s + i], p[3 * s + i]}, cx{p[4 * s + jj], p[5 * s + jj]});
+    if (i == jj) a = cadd(a, cx{-exp(p[i]), p[s + i]});
+    Abar[i * S4_SMAX + jj] = a;
+    G[i * ld + jj] = cx{(i == jj ? 1.0 : 0.0) - 0.5 * delta * a.re, -0.5 * delta * a.im};
+    G[i * ld + s + jj] = cx{i == jj ? 1.0 : 0.0, 0.0};
+  }
+  for (int i = t; i < s; i += S4_THREADS) {
+    G[i * ld + 2 * s] = cx{0.0, 0.0};
+    Cp[i] = cx{p[8 * s + i], p[9 * s + i]};
+    Cm[i] = cx{p[10 * s + i], p[11 * s + i]};
+  }
+  __syncthreads();
+  gauss_jordan(G, s, 2 * s, ld, fac, &piv_s);
+  for (int idx = t; idx < s * s; idx += S4_THREADS) w.Minv[idx] = G[(idx / s) * ld + s + idx % s];
+  __threadfence_block();
+  __syncthreads();
+  // A_d = M^-1 (I + Delta/2 Abar), B_d = M^-1 Delta Bbar; A_d also into W2 for the powering
+  for (int idx = t; idx < s * s; idx += S4_THREADS) {
+    int i = idx / s, jj = idx % s;
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) {
+      cx r = Abar[k * S4_SMAX + jj];
+      r = cx{0.5 * delta * r.re + (k == jj ? 1.0 : 0.0), 0.5 * delta * r.im};
+      acc = cadd(acc, cmul(w.Minv[i * s + k], r));
+    }
+    w.Ad[idx] = acc;
+    W2[i * S4_SMAX + jj] = acc;
+    W1[i * S4_SMAX + jj] = cx{i == jj ? 1.0 : 0.0, 0.0};
+  }
+  for (int i = t; i < s; i += S4_THREADS) {
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(w.Minv[i * s + k], cx{delta * p[6 * s + k], delta * p[7 * s + k]}));
+    w.Bd[i] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // A_d^N by binary powering (W1), then Q = (I - A_d^N)^-1 from [I - A_d^N | I]
+  for (int e = N; e > 0; e >>= 1) {
+    if (e & 1) {
+      cmatmul(W1, W2, W3, s, S4_SMAX);
+      for (int idx = t; idx < s * s; idx += S4_THREADS) W1[(idx / s) * S4_SMAX + idx % s] = W3[(idx / s) * S4_SMAX + idx % s];
+      __syncthreads();
+    }
+    if (e > 1) {
+      cmatmul(W2, W2, W3, s, S4_SMAX);
+      for (int idx = t; idx < s * s; idx += S4_THREADS) W2[(idx / s) * S4_SMAX + idx % s] = W3[(idx / s) * S4_SMAX + idx % s];
+      __syncthreads();
+    }
+  }
+  for (int idx = t; idx < s * s; idx += S4_THREADS) {
+    int i = idx / s, jj = idx % s;
+    cx a = W1[i * S4_SMAX + jj];
+    G[i * ld + jj] = cx{(i == jj ? 1.0 : 0.0) - a.re, -a.im};
+    G[i * ld + s + jj] = cx{i == jj ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  gauss_jordan(G, s, 2 * s, ld, fac, &piv_s);
+  for (int idx = t; idx < s * s; idx += S4_THREADS) w.Q[idx] = G[(idx / s) * ld + s + idx % s];
+  __threadfence_block();
+  __syncthreads();
+  // Xt_m = A_d^m Q B_d, m = 0..N
+  if (t < s) {
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(w.Q[t * s + k], w.Bd[k]));
+    xa[t] = acc;
+  }
+  __syncthreads();
+  for (int m = 0; m <= N; ++m) {
+    if (t < s) w.Xt[(long)m * s + t] = xa[t];
+    cx nx{0.0, 0.0};
+    if (t < s) for (int k = 0; k < s; ++k) nx = cadd(nx, cmul(w.Ad[t * s + k], xa[k]));
+    __syncthreads();
+    if (t < s) xa[t] = nx;
+    __syncthreads();
+  }
+  // w+-_m = C+-^T A_d^m (m < N)
+  for (int i = t; i < s; i += S4_THREADS) { ya[i] = Cp[i]; yb[i] = Cm[i]; }
+  __syncthreads();
+  for (int m = 0; m < N; ++m) {
+    cx np{0.0, 0.0}, nm{0.0, 0.0};
+    if (t < s) {
+      w.Wp[(long)m * s + t] = ya[t];
+      w.Wm[(long)m * s + t] = yb[t];
+      for (int k = 0; k < s; ++k) { np = cadd(np, cmul(ya[k], w.Ad[k * s + t])); nm = cadd(nm, cmul(yb[k], w.Ad[k * s + t])); }
+    }
+    __syncthreads();
+    if (t < s) { ya[t] = np; yb[t] = nm; }
+    __syncthreads();
+  }
+  // wt+-_m = C+-^T Q A_d^m (m < 2N) and wt+-_m M^-1 (m <= N)
+  if (t < s) {
+    cx np{0.0, 0.0}, nm{0.0, 0.0};
+    for (int k = 0; k < s; ++k) { np = cadd(np, cmul(Cp[k], w.Q[k * s + t])); nm = cadd(nm, cmul(Cm[k], w.Q[k * s + t])); }
+    ya[t] = np;
+    yb[t] = nm;
+  }
+  __syncthreads();
+  for (int m = 0; m < 2 * N; ++m) {
+    cx np{0.0, 0.0}, nm{0.0, 0.0};
+    if (t < s) {
+      w.Wtp[(long)m * s + t] = ya[t];
+      w.Wtm[(long)m * s + t] = yb[t];
+      if (m <= N) {
+        cx up{0.0, 0.0}, um{0.0, 0.0};
+        for (int k = 0; k < s; ++k) { up = cadd(up, cmul(ya[k], w.Minv[k * s + t])); um = cadd(um, cmul(yb[k], w.Minv[k * s + t])); }
+        w.Utp[(long)m * s + t] = up;
+        w.Utm[(long)m * s + t] = um;
+      }
+      for (int k = 0; k < s; ++k) { np = cadd(np, cmul(ya[k], w.Ad[k * s + t])); nm = cadd(nm, cmul(yb[k], w.Ad[k * s + t])); }
+    }
+    __syncthreads();
+    if (t < s) { ya[t] = np; yb[t] = nm; }
+    __syncthreads();
+  }
+  // step direction: dA = Delta/2 M^-1 Abar (I + A_d), dB_d = Delta M^-1 (Bbar + Abar B_d / 2)
+  for (int idx = t; idx < s * s; idx += S4_THREADS) {
+    int i = idx / s, jj = idx % s;
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) {
+      cx ia = w.Ad[k * s + jj];
+      if (k == jj) ia.re += 1.0;
+      acc = cadd(acc, cmul(Abar[i * S4_SMAX + k], ia));
+    }
+    W3[i * S4_SMAX + jj] = acc;
+  }
+  __syncthreads();
+  for (int idx = t; idx < s * s; idx += S4_THREADS) {
+    int i = idx / s, jj = idx % s;
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(w.Minv[i * s + k], W3[k * S4_SMAX + jj]));
+    w.dA[idx] = cx{0.5 * delta * acc.re, 0.5 * delta * acc.im};
+  }
+  for (int i = t; i < s; i += S4_THREADS) {
+    cx ab{0.0, 0.0};
+    for (int k = 0; k < s; ++k) ab = cadd(ab, cmul(Abar[i * S4_SMAX + k], w.Bd[k]));
+    fac[i] = cx{p[6 * s + i] + 0.5 * ab.re, p[7 * s + i] + 0.5 * ab.im};
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (t < s) {
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(w.Minv[t * s + k], fac[k]));
+    ya[t] = cx{delta * acc.re, delta * acc.im};  // dB_d
+    xb[t] = cx{0.0, 0.0};                          // T_0
+  }
+  __syncthreads();
+  for (int jj = 0; jj < N; ++jj) {  // T_(j+1) = dA Xt_j + A_d T_j
+    cx nx{0.0, 0.0};
+    if (t < s)
+      for (int k = 0; k < s; ++k)
+        nx = cadd(nx, cadd(cmul(w.dA[t * s + k], w.Xt[(long)jj * s + k]), cmul(w.Ad[t * s + k], xb[k])));
+    __syncthreads();
+    if (t < s) xb[t] = nx;
+    __syncthreads();
+  }
+  if (t < s) {  // d(Q B_d) = Q (T_N + dB_d)
+    cx acc{0.0, 0.0};
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(w.Q[t * s + k], cadd(xb[k], ya[k])));
+    xa[t] = acc;
+  }
+  __syncthreads();
+  double* rp = resp;
+  double* rm = resp + N + 1;
+  for (int m = 0; m <= N; ++m) {
+    const double gp = cdot_re(Cp, xa, s), gm = cdot_re(Cm, xa, s);
+    if (t == 0) { rp[m] = gp; rm[m] = gm; }
+    cx nx{0.0, 0.0};
+    if (t < s && m < N)
+      for (int k = 0; k < s; ++k)
+        nx = cadd(nx, cadd(cmul(w.dA[t * s + k], w.Xt[(long)m * s + k]), cmul(w.Ad[t * s + k], xa[k])));
+    __syncthreads();
+    if (t < s) xa[t] = nx;
+    __syncthreads();
+  }
+  double* Jc = J + (long)ch * (2 * N - 1) * NP;
+  for (int pp = t; pp < N; pp += S4_THREADS) s4pp_put(Jc, N, NP, pp, 12 * s, rp[pp] + rm[N - pp]);
+}
+
+// One block per (mixer, channel, direction): the C, Bbar and rank-one directions (periodic).
+__global__ __launch_bounds__(256) void s4jacp_dir_kernel(const double* __restrict__ params, long s4_off, int N, int d,
+                                                         int s, double* __restrict__ ws, double* __restrict__ J) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx* ap = reinterpret_cast<cx*>(smem_raw);  // [N] w+_k . alpha
+  cx* am = ap + N;                            // [N] w-_k . alpha
+  cx* tp = am + N;                            // [2N] wt+_m . alpha
+  cx* tm = tp + 2 * N;                        // [2N] wt-_m . alpha
+  cx* cc = tm + 2 * N;                        // [N] beta^T Xt_m
+  __shared__ cx alpha[S4_SMAX], beta[S4_SMAX], avec[S4_SMAX], bvec[S4_SMAX];
+  __shared__ cx beta0;
+  const int t = threadIdx.x;
+  const int ch = blockIdx.x, dir = blockIdx.y;
+  const int c = ch % d;
+  const int NP = 12 * s + 1;
+  const double* p = params + s4_off + (long)ch * NP;
+  const double delta = exp(log(1e-2) + log(10.0) * (double)c / (double)(d > 1 ? d - 1 : 1) + p[12 * s]);
+  const S4PerPtr w = s4pp_ptrs(ws, ch, N, s);
+  double* Jc = J + (long)ch * (2 * N - 1) * NP;
+  const int grp = dir / s, n = dir % s;
+  const bool imag = grp & 1;
+  if (grp >= 8) {  // C+ (8,9) and C- (10,11)
+    const bool plus = grp < 10;
+    for (int pp = t; pp < N; pp += 256) {
+      const cx x = w.Xt[(long)(plus ? pp : N - pp) * s + n];
+      s4pp_put(Jc, N, NP, pp, dir, imag ? -x.im : x.re);
+    }
+    return;
+  }
+  if (grp >= 6) {  // Bbar (6,7)
+    for (int pp = t; pp < N; pp += 256) {
+      const cx u = cadd(w.Utp[(long)pp * s + n], w.Utm[(long)(N - pp) * s + n]);
+      s4pp_put(Jc, N, NP, pp, dir, imag ? -delta * u.im : delta * u.re);
+    }
+    return;
+  }
+  for (int i = t; i < s; i += 256) {
+    cx a{0.0, 0.0}, b{0.0, 0.0};
+    if (grp < 2) {
+      if (i == n) { a = imag ? cx{0.0, 1.0} : cx{-exp(p[n]), 0.0}; b = cx{1.0, 0.0}; }
+    } else if (grp < 4) {
+      if (i == n) a = imag ? cx{0.0, 1.0} : cx{1.0, 0.0};
+      b = cx{p[4 * s + i], p[5 * s + i]};
+    } else {
+      a = cx{p[2 * s + i], p[3 * s + i]};
+      if (i == n) b = imag ? cx{0.0, 1.0} : cx{1.0, 0.0};
+    }
+    avec[i] = a;
+    bvec[i] = b;
+  }
+  __syncthreads();
+  for (int i = t; i < s; i += 256) {
+    cx al{0.0, 0.0}, be{0.0, 0.0};
+    for (int k = 0; k < s; ++k) {
+      al = cadd(al, cmul(w.Minv[i * s + k], avec[k]));
+      cx ia = w.Ad[k * s + i];
+      if (k == i) ia.re += 1.0;
+      be = cadd(be, cmul(bvec[k], ia));
+    }
+    alpha[i] = cx{0.5 * delta * al.re, 0.5 * delta * al.im};
+    beta[i] = be;
+  }
+  if (t == 0) {
+    cx b0{0.0, 0.0};
+    for (int k = 0; k < s; ++k) b0 = cadd(b0, cmul(bvec[k], w.Bd[k]));
+    beta0 = b0;
+  }
+  __syncthreads();
+  for (int k = t; k < 2 * N; k += 256) {
+    cx sp{0.0, 0.0}, sm{0.0, 0.0}, ep{0.0, 0.0}, em{0.0, 0.0}, sc{0.0, 0.0};
+    for (int i = 0; i < s; ++i) {
+      ep = cadd(ep, cmul(w.Wtp[(long)k * s + i], alpha[i]));
+      em = cadd(em, cmul(w.Wtm[(long)k * s + i], alpha[i]));
+      if (k < N) {
+        sp = cadd(sp, cmul(w.Wp[(long)k * s + i], alpha[i]));
+        sm = cadd(sm, cmul(w.Wm[(long)k * s + i], alpha[i]));
+        sc = cadd(sc, cmul(beta[i], w.Xt[(long)k * s + i]));
+      }
+    }
+    tp[k] = ep;
+    tm[k] = em;
+    if (k < N) { ap[k] = sp; am[k] = sm; cc[k] = sc; }
+  }
+  __syncthreads();
+  auto f = [&](int j, const cx* a, const cx* at) {
+    cx acc = cmul(at[j], beta0);
+    for (int k = 0; k < j; ++k) acc = cadd(acc, cmul(a[k], cc[j - 1 - k]));
+    for (int k = 0; k < N; ++k) acc = cadd(acc, cmul(at[j + k], cc[N - 1 - k]));
+    return acc.re;
+  };
+  for (int pp = t; pp < N; pp += 256) s4pp_put(Jc, N, NP, pp, dir, f(pp, ap, tp) + f(N - pp, am, tm));
+}
+
+// ------------------------------------------------------------------------------------------
 // Per-sample S4 parameter gradients: for every mixer channel, grads[b][off(ch) + k] =
 // sum_r dg[b][ch][r] J[ch][r][k] (a [B x (2N-1)] x [(2N-1) x (12s+1)] product on the matrix cores).
 template <typename T> struct S4GradArgs {

@@ -1,9 +1,13 @@
 """GPU parity of the per-sample log-derivatives O_theta(s) = d log psi / d theta against the
 oracle's reverse-mode gradient (itself pinned to central differences).
 
-Measure: eps_grad = max_b ||g_b - g*_b||_2 / ||g*_b||_2. float64 mode: 1e-10. float32 mode:
-each gradient entry is a site sum of products of float32 fields (relative rounding ~sqrt(N) u),
-so 1e-4 is the bound checked here; the measured value is printed.
+Measure: eps_grad = max_b ||g_b - g*_b||_2 / max(||g*_b||_2, 1e-3 max_b' ||g*_b'||_2). A sample
+whose gradient is far below the batch's is judged against that floor: on a periodic chain a
+zero-magnetisation sample has Omega ~ 0 at the baseline draw (translation invariance cancels the
+linear part), so its gradient tanh(Omega) dOmega/dtheta sits at the rounding level of the
+others. float64 mode: 1e-10. float32 mode: each gradient entry is a site sum of products of
+float32 fields (relative rounding ~sqrt(N) u), so 1e-4 is the bound checked here; the measured
+value is printed.
 """
 import sys
 
@@ -32,7 +36,8 @@ def L():
 
 def eps_grad(g, ref):
     g, ref = g.double().cpu(), ref.double().cpu()
-    return ((g - ref).norm(dim=1) / ref.norm(dim=1).clamp_min(1e-300)).max().item()
+    nrm = ref.norm(dim=1)
+    return ((g - ref).norm(dim=1) / nrm.clamp_min(max(1e-3 * nrm.max().item(), 1e-300))).max().item()
 
 
 CASES = [
@@ -41,6 +46,11 @@ CASES = [
     (di.ModelShape(16, 3, 8, 4, act="identity", bc="open"), "fp64"),
     (di.ModelShape(20, 2, 16, 4, act="silu", bc="open", w_c=2), "fp64"),
     (di.ModelShape(40, 2, 20, 6, act="silu", bc="open"), "fp32"),
+    # periodic chains: circulant mixers from the aliased kernel, wrapped CNN windows
+    (di.ModelShape(12, 1, 4, 2, act="tanh", bc="periodic"), "fp64"),
+    (di.ModelShape(14, 2, 6, 3, act="silu", bc="periodic"), "fp64"),
+    (di.ModelShape(13, 3, 5, 3, act="identity", bc="periodic", w_c=2), "fp64"),
+    (di.ModelShape(40, 2, 20, 6, act="silu", bc="periodic"), "fp32"),
 ]
 
 
@@ -95,13 +105,6 @@ def test_autograd_backward_uses_forward_params(L):
     assert torch.allclose(m.logpsi(sp), lpB, rtol=0, atol=0)
 
 
-def test_grad_rejects_periodic(L):
-    shape = di.ModelShape(12, 1, 4, 2, bc="periodic")
-    m = L.Model(shape, "fp64")
-    m.set_params(torch.tensor(di.draw_params(shape, 1, "baseline")))
-    with pytest.raises(L.DysonNetError) as ei:
-        m.grad_logpsi(torch.tensor(di.uniform_spins(2, 12, 1), device="cuda"))
-    assert ei.value.status == L.DN_EUNSUPPORTED
 
 
 def _fd_indices(P):
@@ -164,3 +167,20 @@ def test_grad_full_size_sampled(L, prec):
     _say(f"full size {prec}: eps_grad {e:.3e}")
     assert torch.isfinite(g).all()
     assert e <= (1e-10 if prec == "fp64" else 1e-6)
+
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_grad_long_periodic_chain(L, prec):
+    """N=512 periodic (the longest chain a model takes), two blocks: the aliased kernel's
+    tap Jacobian at its largest A^N power and LDS footprint."""
+    shape = di.ModelShape(512, 2, 4, 2, act="silu", bc="periodic")
+    th = torch.tensor(di.draw_params(shape, 11, "stress"))
+    m = L.Model(shape, prec)
+    m.set_params(th)
+    sp = di.uniform_spins(3, shape.N, 5)
+    _, g, _ = m.grad_logpsi(torch.tensor(sp, device="cuda"))
+    ref = grad_logpsi_batched(ModelDesc.of(shape), th, sp)
+    e = eps_grad(g, ref)
+    _say(f"periodic N=512 {prec}: eps_grad {e:.3e}")
+    assert e <= (1e-10 if prec == "fp64" else 1e-4)
