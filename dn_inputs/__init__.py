@@ -32,6 +32,7 @@ class ModelShape:
     bc: str = "open"  # network boundary condition: "open" (zero padding) or "periodic"
     act: str = "silu"  # local nonlinearity g: "silu" | "tanh" | "identity"
     inject_phi: int = 0  # 1: add phi^(l) to the h stream before the mixer (Fig. 1c form)
+    complex_out: int = 0  # 1: complex read-out matrix A (column pairs as real and imaginary parts)
 
     def __post_init__(self):
         assert self.act in ACTS and self.bc in BCS

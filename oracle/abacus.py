@@ -28,7 +28,7 @@ from typing import List
 
 import torch
 
-from .model import DT, forward, lcd, unpack, mixers
+from .model import CT, DT, forward, ratio, unpack, mixers
 
 
 def _slice(desc, cluster: List[int], radius: int) -> List[int]:
@@ -118,7 +118,7 @@ def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = Fals
     B, N = s.shape
     M = sites.shape[1]
     d, L, wc = desc.d, desc.L, desc.w_c
-    out = torch.zeros(B, M, dtype=DT)
+    out = torch.zeros(B, M, dtype=CT if desc.complex_out else DT)
     parts = []
     for b in range(B):
         ops = background_operators(desc, theta, s[b])
@@ -162,7 +162,7 @@ def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = Fals
             dOm = sum(ops["Pw"] @ e[l].reshape(-1) for l in range(L + 1))
             for m in range(L):
                 dOm = dOm + Ttil[m] @ z[m].reshape(-1)
-            out[b, mi] = lcd(Om0, dOm).sum()
+            out[b, mi] = ratio(desc, Om0, dOm)
             if return_parts:
                 parts.append({"b": b, "m": mi, "dOmega": dOm, "slices": S})
     if return_parts:

@@ -3,7 +3,8 @@
 Reverse-mode automatic differentiation of ``model.forward`` (including the S4 kernel
 generation, in complex128) with PyTorch's autograd on the CPU. These are the
 log-derivatives that variational Monte Carlo with stochastic reconfiguration consumes
-(Sec. VI, training paragraph). Pinned against central finite differences.
+(Sec. VI, training paragraph). Pinned against central finite differences. For a
+complex-output network O = d Re(log psi)/d theta + i d Im(log psi)/d theta (complex [B, P]).
 """
 from __future__ import annotations
 
@@ -20,8 +21,13 @@ def grad_logpsi(desc, theta, spins) -> torch.Tensor:
     for b in range(s.shape[0]):
         th = theta.clone().requires_grad_(True)
         lp = forward(desc, th, s[b:b + 1])["logpsi"][0]
-        (g,) = torch.autograd.grad(lp, th)
-        rows.append(g)
+        if lp.is_complex():
+            (gr,) = torch.autograd.grad(lp.real, th, retain_graph=True)
+            (gi,) = torch.autograd.grad(lp.imag, th)
+            rows.append(torch.complex(gr, gi))
+        else:
+            (g,) = torch.autograd.grad(lp, th)
+            rows.append(g)
     return torch.stack(rows)
 
 
@@ -31,6 +37,12 @@ def grad_logpsi_batched(desc, theta, spins) -> torch.Tensor:
     lp = forward(desc, theta, torch.as_tensor(spins))["logpsi"]
     rows = []
     for b in range(lp.shape[0]):
-        (g,) = torch.autograd.grad(lp[b], theta, retain_graph=b + 1 < lp.shape[0])
-        rows.append(g)
+        keep = b + 1 < lp.shape[0]
+        if lp.is_complex():
+            (gr,) = torch.autograd.grad(lp[b].real, theta, retain_graph=True)
+            (gi,) = torch.autograd.grad(lp[b].imag, theta, retain_graph=keep)
+            rows.append(torch.complex(gr, gi))
+        else:
+            (g,) = torch.autograd.grad(lp[b], theta, retain_graph=keep)
+            rows.append(g)
     return torch.stack(rows)

@@ -100,7 +100,8 @@ def local_energy(hdiag, helem, n_conn, logratio):
     """E_loc = hdiag + sum_{m < n_conn} helem_m exp(logratio_m) (Eq. (local-estimator))."""
     M = helem.shape[1]
     mask = torch.arange(M)[None, :] < torch.as_tensor(n_conn)[:, None]
-    terms = torch.where(mask, helem * torch.exp(logratio), torch.zeros_like(helem))
+    t = helem * torch.exp(logratio)
+    terms = torch.where(mask, t, torch.zeros_like(t))
     return hdiag + terms.sum(-1)
 
 

@@ -22,6 +22,10 @@ Readings of the paper used here (each listed in the design doc):
   * Lambda = -exp(raw) + i*raw', A-bar = diag(Lambda) + p q^T, step
     Delta_c = exp(ln 0.01 + ln 10 * c/(d-1) + raw);
   * f = log cosh on each of d_out read-out units, log psi = sum_k logcosh(Omega_k);
+  * complex_out = 1 makes A complex (Sec. II, below Eq. (wavefunc): a complex A gives a
+    complex wavefunction): the d_out real columns pair up as A[:, 2j] + i A[:, 2j+1], so
+    there are d_out/2 complex units and log psi = sum_j logcosh(Omega_2j + i Omega_2j+1)
+    is complex; its imaginary part (the phase) is reported in (-pi, pi];
   * inject_phi adds phi^(l) to the h stream before the mixer (Fig. 1c); the residual
     sum holds only the h stream.
 """
@@ -48,11 +52,12 @@ class ModelDesc:
     bc: str = "open"
     act: str = "silu"
     inject_phi: int = 0
+    complex_out: int = 0
 
     @staticmethod
     def of(shape) -> "ModelDesc":
         return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c,
-                         shape.bc, shape.act, shape.inject_phi)
+                         shape.bc, shape.act, shape.inject_phi, getattr(shape, "complex_out", 0))
 
 
 def act(name: str, x: torch.Tensor) -> torch.Tensor:
@@ -199,6 +204,84 @@ def lcd(a: torch.Tensor, delta: torch.Tensor) -> torch.Tensor:
     return torch.where(small, torch.log1p(inner), logcosh(a + delta) - logcosh(a))
 
 
+def wrap_phase(y: torch.Tensor) -> torch.Tensor:
+    """The representative of y modulo 2 pi in [-pi, pi]."""
+    return y - (2 * math.pi) * torch.round(y / (2 * math.pi))
+
+
+def _ctanh(z: torch.Tensor) -> torch.Tensor:
+    """tanh(x + iy) = (sinh 2x + i sin 2y) / (cosh 2x + cos 2y); +-1 once |x| > 20."""
+    x, y = z.real, z.imag
+    big = x.abs() > 20.0
+    xs = torch.where(big, torch.zeros_like(x), x)
+    den = torch.cosh(2 * xs) + torch.cos(2 * y)
+    re = torch.where(big, torch.sign(x), torch.sinh(2 * xs) / den)
+    im = torch.where(big, torch.zeros_like(y), torch.sin(2 * y) / den)
+    return torch.complex(re, im)
+
+
+def logcosh_c(z: torch.Tensor) -> torch.Tensor:
+    """log cosh(x + iy) for complex z, phase in (-pi, pi].
+
+    cosh(x + iy) = cosh x cos y + i sinh x sin y, so |cosh z|^2 / cosh^2 x equals both
+    1 - (sin y / cosh x)^2 and tanh^2 x + (cos y / cosh x)^2. log|cosh z| = logcosh(x) + 1/2 log
+    of that ratio, taken as log1p of the first form while (sin y / cosh x)^2 <= 1/2 and as the
+    log of the second (a sum of squares, no cancellation near the zeros of cosh) beyond;
+    arg cosh z = atan2(tanh x sin y, cos y).
+    """
+    x, y = z.real, z.imag
+    ch = torch.cosh(x)
+    q = torch.sin(y) / ch
+    c = torch.cos(y) / ch
+    th = torch.tanh(x)
+    near_zero = q * q > 0.5
+    ratio = torch.where(near_zero, torch.log(th * th + c * c), torch.log1p(-q * q))
+    re = logcosh(x) + 0.5 * ratio
+    im = torch.atan2(th * torch.sin(y), torch.cos(y))
+    return torch.complex(re, im)
+
+
+def lcd_c(a: torch.Tensor, delta: torch.Tensor) -> torch.Tensor:
+    """log cosh(a + delta) - log cosh(a) for complex a, delta, phase in [-pi, pi].
+
+    For |delta| <= 1: cosh(a + delta)/cosh(a) = 1 + w, w = 2 sinh^2(delta/2) + tanh(a) sinh(delta),
+    and log(1 + w) = 1/2 log|1 + w|^2 + i atan2(Im w, 1 + Re w); otherwise the difference of
+    logcosh_c with the phase wrapped.
+    """
+    small = delta.abs() <= 1.0
+    ds = torch.where(small, delta, torch.zeros_like(delta))
+    w = 2 * torch.sinh(ds / 2) ** 2 + _ctanh(a) * torch.sinh(ds)
+    # |1 + w|^2 = 1 + u, u = 2 Re w + |w|^2: log1p(u) while |u| <= 1/2, else the log of the sum
+    # of squares (1 + Re w)^2 + (Im w)^2 (no cancellation when 1 + w is near zero)
+    u = 2 * w.real + w.real ** 2 + w.imag ** 2
+    mod = torch.where(u.abs() <= 0.5, torch.log1p(u), torch.log((1 + w.real) ** 2 + w.imag ** 2))
+    near = torch.complex(0.5 * mod, torch.atan2(w.imag, 1 + w.real))
+    far = logcosh_c(a + delta) - logcosh_c(a)
+    far = torch.complex(far.real, wrap_phase(far.imag))
+    return torch.where(small, near, far)
+
+
+def _units(desc: ModelDesc, Om: torch.Tensor) -> torch.Tensor:
+    """The complex read-out units Omega_2j + i Omega_2j+1 of a complex-output network."""
+    return torch.complex(Om[..., 0::2], Om[..., 1::2])
+
+
+def readout(desc: ModelDesc, Omega: torch.Tensor) -> torch.Tensor:
+    """log psi from the read-out pre-activations Omega [..., d_out]."""
+    if desc.complex_out:
+        lp = logcosh_c(_units(desc, Omega)).sum(-1)
+        return torch.complex(lp.real, wrap_phase(lp.imag))
+    return logcosh(Omega).sum(-1)
+
+
+def ratio(desc: ModelDesc, Om0: torch.Tensor, dOm: torch.Tensor) -> torch.Tensor:
+    """log psi(s')/psi(s) from Omega(s) and dOmega = Omega(s') - Omega(s)."""
+    if desc.complex_out:
+        lr = lcd_c(_units(desc, Om0), _units(desc, dOm)).sum(-1)
+        return torch.complex(lr.real, wrap_phase(lr.imag))
+    return lcd(Om0, dOm).sum(-1)
+
+
 def _shift(desc: ModelDesc, a: torch.Tensor, r: int) -> torch.Tensor:
     """out[:, i] = a[:, i + r] with zero padding (open) or wrap-around (periodic)."""
     if r == 0:
@@ -264,7 +347,7 @@ def forward(desc: ModelDesc, theta: torch.Tensor, spins, cache: bool = False, T=
     omega = T[desc.L].sum(dim=1)                          # [d, N]: sum_j g^f_c(j - i)
     Omega = torch.einsum("bic,ci,ck->bk", R, omega, prm["A"]) / N
     out["Omega"] = Omega
-    out["logpsi"] = logcosh(Omega).sum(-1)
+    out["logpsi"] = readout(desc, Omega)
     out["omega"] = omega
     out["T"] = T
     out["prm"] = prm
@@ -314,5 +397,7 @@ def plain_logratio(desc: ModelDesc, theta, spins, sites, n_conn, chunk: int = 51
         vals.append(forward(desc, theta, sp[c0:c0 + chunk], T=T)["logpsi"])
     lp = torch.cat(vals).reshape(B, M)
     lr = lp - base[:, None]
+    if desc.complex_out:
+        lr = torch.complex(lr.real, wrap_phase(lr.imag))
     mask = torch.arange(M)[None, :] < torch.as_tensor(n_conn)[:, None]
     return base, torch.where(mask, lr, torch.zeros_like(lr))

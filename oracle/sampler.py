@@ -19,7 +19,8 @@ sampler is exact" and App. "Practical implementation of the screened typewriter 
   exact Metropolis-Hastings decision for the same u.
 The reference chain is plain Metropolis-Hastings: R = |psi(s')|^2 / |psi(s)|^2 from two full
 evaluations, accept iff u < min(1, R). f = prod_k cosh (log psi = sum_k log cosh Omega_k), so
-R~ = exp(2 sum_k lcd(Omega_k, dOmega_k)).
+R~ = exp(2 sum_k lcd(Omega_k, dOmega_k)) (for a complex-output network the real part of the
+complex log-ratio of its units: |psi|^2 decides).
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ from typing import Dict, List
 import torch
 
 from .abacus import abacus_logratio
-from .model import DT, forward, lcd
+from .model import DT, forward, ratio
 
 
 def typewriter_sites(N: int, spacing: int, parity: int, r) -> List[int]:
@@ -45,7 +46,7 @@ def typewriter_sites(N: int, spacing: int, parity: int, r) -> List[int]:
 
 
 def _logpsi(desc, theta, s) -> float:
-    return forward(desc, theta, torch.as_tensor(s)[None])["logpsi"][0].item()
+    return forward(desc, theta, torch.as_tensor(s)[None])["logpsi"][0].real.item()
 
 
 def exact_mh_sweep(desc, theta, spins, sites: List[int], u) -> Dict:
@@ -90,14 +91,14 @@ def screened_sweep(desc, theta, spins, sites: List[int], u, eps: float, track: b
     base = 0                      # index of the first proposal the current updates cover
     acc, refreshes, isa_err, unscreened = [], 0, 0.0, 0.0
     for k, j in enumerate(sites):
-        Rt = math.exp(2.0 * lcd(Om, dOm[k - base]).sum().item())
+        Rt = math.exp(2.0 * ratio(desc, Om, dOm[k - base]).real.item())
         P = min(1.0, Rt)
         if abs(float(u[k]) - P) <= eps:
             # ambiguous: rebuild the background at the current configuration
             refreshes += 1
             Om, dOm = _updates(desc, theta, s, sites[k:])
             base = k
-            R = math.exp(2.0 * lcd(Om, dOm[0]).sum().item())
+            R = math.exp(2.0 * ratio(desc, Om, dOm[0]).real.item())
             isa_err = max(isa_err, abs(Rt - R))
             P = min(1.0, R)
         elif track:

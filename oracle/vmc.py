@@ -57,13 +57,13 @@ def exact_energy(desc, ham, theta) -> float:
     sites, helem, n_conn, hdiag = connected(ham, s)
     lp, lr = plain_logratio(desc, theta, s, sites, n_conn)
     el = local_energy(hdiag, helem, n_conn, lr)
-    p = torch.exp(2 * (lp - lp.max()))
-    return float((p * el).sum() / p.sum())
+    p = torch.exp(2 * (lp.real - lp.real.max()))
+    return float(((p * el).sum() / p.sum()).real)
 
 
 def exact_weights(desc, theta, s) -> torch.Tensor:
     """|psi(s)|^2 / Z over the given (complete) set of configurations."""
-    lp = forward(desc, torch.as_tensor(theta, dtype=DT), s)["logpsi"]
+    lp = forward(desc, torch.as_tensor(theta, dtype=DT), s)["logpsi"].real
     p = torch.exp(2 * (lp - lp.max()))
     return p / p.sum()
 
