@@ -26,7 +26,10 @@
  *    the ragged batch) do not check them and give undefined results for them.
  *  - sites: int32 [B, M_max, 2]; element m of sample b flips sites[b,m,0] and, unless it
  *    is -1, sites[b,m,1]. Entries m >= n_conn[b] are ignored on input.
- *  - logpsi, logratio, eloc, helem, hdiag are float64 in every precision mode.
+ *  - logpsi, logratio, eloc, helem, hdiag are float64 in every precision mode. For a model
+ *    with complex_out = 1, logpsi, logratio and eloc hold complex values instead: (re, im)
+ *    float64 pairs, i.e. logpsi [B][2], logratio [B, M_max][2], eloc [B][2] (the layout of
+ *    C99 double complex); a phase is reported in [-pi, pi].
  */
 #ifndef DYSONNET_H
 #define DYSONNET_H
@@ -70,10 +73,14 @@ typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
  * d_out log-cosh read-out units (must be 2); w_c half-width of the phi-stream CNN
  * (0..3); bc network boundary condition (dn_bc); act local nonlinearity g (dn_act);
  * inject_phi 1 adds phi^(l) to the h stream before each mixer (Fig. 1c form);
- * prec arithmetic (dn_prec). */
+ * prec arithmetic (dn_prec); complex_out 1 makes the read-out matrix A complex (Sec. II: a
+ * complex A gives a complex wavefunction): its two columns are Re A and Im A, the two
+ * pre-activations form one complex unit Omega = Omega_0 + i Omega_1 and
+ * log psi = log cosh(Omega) is complex (0: two real units, log psi = sum_k log cosh Omega_k). */
 typedef struct {
   int32_t N, L, d, s, d_out, w_c;
   int32_t bc, act, inject_phi, prec;
+  int32_t complex_out;
 } dn_model_desc;
 
 typedef enum { DN_H_LRTFIM = 0, DN_H_J1J2 = 1 } dn_ham_kind;
@@ -205,6 +212,12 @@ dn_status dn_logratio(dn_model* m, int32_t path, const int8_t* spins, int32_t B,
 dn_status dn_local_energy(const double* hdiag, const double* helem, const int32_t* n_conn,
                           const double* logratio, int32_t B, int32_t M_max, double* eloc,
                           void* stream);
+
+/* dn_local_energy for complex log-ratios (a complex_out model): logratio [B, M_max][2] and
+ * eloc [B][2] hold (re, im) pairs; E_loc = hdiag + sum_m helem_m exp(logratio_m). */
+dn_status dn_local_energy_complex(const double* hdiag, const double* helem, const int32_t* n_conn,
+                                  const double* logratio, int32_t B, int32_t M_max, double* eloc,
+                                  void* stream);
 
 /* Whole local estimator: connected elements, log-ratios by `path`, E_loc. logpsi [B]
  * and eloc [B] are required; logratio [B, M_max] may be NULL (then the library keeps it

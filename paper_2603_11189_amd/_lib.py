@@ -24,6 +24,7 @@ HAM = {"lrtfim": 0, "j1j2": 1}
 # Names declared in include/dysonnet.h (checked against the shared library by the tests).
 EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_model_set_params",
            "dn_model_get_taps", "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
+           "dn_local_energy_complex",
            "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
            "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable", "dn_profile_read",
            "dn_last_error", "dn_model_destroy")
@@ -35,7 +36,7 @@ KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep"
 
 class ModelDesc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("N", "L", "d", "s", "d_out", "w_c", "bc", "act", "inject_phi", "prec")]
+                ("N", "L", "d", "s", "d_out", "w_c", "bc", "act", "inject_phi", "prec", "complex_out")]
 
 
 class HamDesc(ctypes.Structure):
@@ -72,6 +73,7 @@ def lib():
         L.dn_connected.argtypes = [ctypes.POINTER(HamDesc), vp, i32, i32, i32, vp, vp, vp, vp, vp]
         L.dn_logratio.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp]
         L.dn_local_energy.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+        L.dn_local_energy_complex.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.dn_eloc.argtypes = [vp, i32, ctypes.POINTER(HamDesc), vp, i32, i32, vp, vp, vp, vp]
         L.dn_grad_logpsi.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.dn_autotune.argtypes = [vp, ctypes.POINTER(HamDesc), i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
@@ -89,7 +91,8 @@ def lib():
         L.dn_model_destroy.argtypes = [vp]
         L.dn_model_destroy.restype = None
         for fn in ("dn_model_create", "dn_set_workspace_limit", "dn_model_set_params", "dn_model_get_taps",
-                   "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy", "dn_eloc",
+                   "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
+                   "dn_local_energy_complex", "dn_eloc",
                    "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
                    "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable",
                    "dn_profile_read"):
@@ -113,7 +116,7 @@ def _ptr(t):
 
 def make_desc(shape, prec: str = "fp32") -> ModelDesc:
     return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c, BC[shape.bc],
-                     ACT[shape.act], shape.inject_phi, PREC[prec])
+                     ACT[shape.act], shape.inject_phi, PREC[prec], getattr(shape, "complex_out", 0))
 
 
 def make_ham(ham) -> HamDesc:
@@ -125,10 +128,12 @@ def param_count(shape) -> int:
 
 
 class Model:
-    """Owner of one dn_model handle."""
+    """Owner of one dn_model handle. A complex-output model returns log psi, the log-ratios and
+    E_loc as complex128 tensors (the library's (re, im) pairs)."""
 
     def __init__(self, shape, prec: str = "fp32"):
         self.shape, self.prec = shape, prec
+        self.out_dtype = torch.complex128 if getattr(shape, "complex_out", 0) else torch.float64
         self._desc = make_desc(shape, prec)
         h = ctypes.c_void_p()
         _check(lib().dn_model_create(ctypes.byref(self._desc), ctypes.byref(h)))
@@ -165,7 +170,7 @@ class Model:
 
     def logpsi(self, spins: torch.Tensor) -> torch.Tensor:
         B = spins.shape[0]
-        out = torch.empty(B, dtype=torch.float64, device=spins.device)
+        out = torch.empty(B, dtype=self.out_dtype, device=spins.device)
         _check(lib().dn_logpsi(self.handle, _ptr(spins), B, _ptr(out), _stream()))
         return out
 
@@ -174,14 +179,15 @@ class Model:
         inside the call; `out` may be given to avoid torch's own allocation too)."""
         B = spins.shape[0]
         if out is None:
-            out = torch.empty(B, dtype=torch.float64, device=spins.device)
+            out = torch.empty(B, dtype=self.out_dtype, device=spins.device)
+        assert out.dtype == self.out_dtype and out.is_contiguous()
         _check(lib().dn_logpsi_noalloc(self.handle, _ptr(spins), B, _ptr(out), _stream()))
         return out
 
     def logratio(self, spins, sites, n_conn, path: str = "abacus", want_logpsi: bool = True):
         B, M_max = sites.shape[0], sites.shape[1]
-        lr = torch.empty((B, M_max), dtype=torch.float64, device=spins.device)
-        lp = torch.empty(B, dtype=torch.float64, device=spins.device) if want_logpsi else None
+        lr = torch.empty((B, M_max), dtype=self.out_dtype, device=spins.device)
+        lp = torch.empty(B, dtype=self.out_dtype, device=spins.device) if want_logpsi else None
         _check(lib().dn_logratio(self.handle, PATH[path], _ptr(spins), B, _ptr(sites), _ptr(n_conn), M_max,
                                  _ptr(lp), _ptr(lr), _stream()))
         return lp, lr
@@ -189,10 +195,11 @@ class Model:
     def eloc(self, ham, spins, M_max: int, path: str = "abacus", out=None):
         B = spins.shape[0]
         if out is None:
-            out = (torch.empty(B, dtype=torch.float64, device=spins.device),
-                   torch.empty((B, M_max), dtype=torch.float64, device=spins.device),
-                   torch.empty(B, dtype=torch.float64, device=spins.device))
+            out = (torch.empty(B, dtype=self.out_dtype, device=spins.device),
+                   torch.empty((B, M_max), dtype=self.out_dtype, device=spins.device),
+                   torch.empty(B, dtype=self.out_dtype, device=spins.device))
         lp, lr, el = out
+        assert all(t is None or t.dtype == self.out_dtype for t in out)
         hd = make_ham(ham)
         _check(lib().dn_eloc(self.handle, PATH[path], ctypes.byref(hd), _ptr(spins), B, M_max, _ptr(lp), _ptr(lr),
                              _ptr(el), _stream()))
@@ -283,10 +290,11 @@ def connected(ham, spins: torch.Tensor, M_max: int):
 
 
 def local_energy(hdiag, helem, n_conn, logratio):
+    """E_loc from log-ratios: float64, or complex128 for complex log-ratios."""
     B, M_max = helem.shape
-    out = torch.empty(B, dtype=torch.float64, device=helem.device)
-    _check(lib().dn_local_energy(_ptr(hdiag), _ptr(helem), _ptr(n_conn), _ptr(logratio), B, M_max, _ptr(out),
-                                 _stream()))
+    out = torch.empty(B, dtype=logratio.dtype, device=helem.device)
+    fn = lib().dn_local_energy_complex if logratio.is_complex() else lib().dn_local_energy
+    _check(fn(_ptr(hdiag), _ptr(helem), _ptr(n_conn), _ptr(logratio.contiguous()), B, M_max, _ptr(out), _stream()))
     return out
 
 
@@ -294,10 +302,13 @@ def ragged_eloc(models, hams, spins, logpsi, eloc, n_streams: int = 0, mode: str
     """Local estimator over a ragged batch in one submission (dn_ragged_eloc).
 
     models: list of Model (distinct); hams: HamSpec per instance; spins: int8 [B_i, N_i] device
-    tensors; logpsi (list or None) and eloc: float64 [B_i] device tensors written in place. In
+    tensors; logpsi (list or None) and eloc: float64 [B_i] device tensors (complex128 for a
+    complex-output model) written in place. In
     graph mode the submission is recorded on the first call with these exact tensors and
     replayed afterwards, so keep the tensors and refill the spins in place."""
     n = len(models)
+    for i, m in enumerate(models):  # complex-output models take complex128 outputs
+        assert eloc[i].dtype == m.out_dtype and (logpsi is None or logpsi[i] is None or logpsi[i].dtype == m.out_dtype)
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     mh = (vp * n)(*[m.handle for m in models])
     hd = (HamDesc * n)(*[make_ham(h) for h in hams])

@@ -624,9 +624,10 @@ dn_status logratio_full(dn_model* m, const int8_t* spins, int B, const int32_t* 
     const int C = (int)std::min<size_t>(chunk, total - c0);
     STCHK((forward_chunk<T, DP>(m, spins, map, c0, C, rho + 2L * c0, nullptr, nullptr, nullptr, st)));
   }
-  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
-  plain_ratio_kernel<<<(total + 255) / 256, 256, 0, st>>>(rho, offs, cb, cm, total, M_max, logratio);
-  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(rho, offs, B, logpsi);
+  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max * (1 + m->desc.complex_out), 0.0);
+  plain_ratio_kernel<<<(total + 255) / 256, 256, 0, st>>>(rho, offs, cb, cm, total, M_max, logratio,
+                                                          m->desc.complex_out);
+  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(rho, offs, B, logpsi, m->desc.complex_out);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -796,7 +797,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   double* Om0 = (double*)pOm;
   CfgMap idmap{idb, idm, sites, M_max};
   CfgMap fmap{cb, cm, sites, M_max};
-  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max, 0.0);
+  fill_kernel<double><<<256, 256, 0, st>>>(logratio, (long)B * M_max * (1 + m->desc.complex_out), 0.0);
   const Tables<T>& tb = tables_of<T>(m);
   const int Wmax = 2 + 2 * L * wc + 1;
   const int ND = lam_nd(wc, ext_max), dlo = -(2 * wc + ext_max);
@@ -881,7 +882,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     if (shallow) {  // slice recompute and per-flip update in one kernel
       Flip12Args<T> a{};
       a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
-      a.Om0 = Om0; a.logratio = logratio; a.dom = dom;
+      a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.cplx = d.complex_out;
       if (L == 2) STCHK((launch_shallow<T, DP, true>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
       else STCHK((launch_shallow<T, DP, false>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
       continue;
@@ -910,13 +911,14 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.dchi = dchi; a.Wmax = Wmax; a.tau = tau;
       a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
       a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.slice_part = (T*)psp;
+      a.cplx = d.complex_out;
       const bool first = (l == 1), last = (l == L - 1);
       if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
     }
   }
   }
-  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(Om0, nullptr, B, logpsi);
+  if (logpsi) logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>(Om0, nullptr, B, logpsi, m->desc.complex_out);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -963,7 +965,7 @@ dn_status logpsi_only(dn_model* m, const int8_t* spins, int B, double* logpsi, h
     const int C = (int)std::min<size_t>(chunk, B - c0);
     STCHK((forward_chunk<T, DP>(m, spins, idmap, c0, C, (double*)prho + 2L * c0, nullptr, nullptr, nullptr, st)));
   }
-  logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>((double*)prho, nullptr, B, logpsi);
+  logpsi_kernel<<<(B + 255) / 256, 256, 0, st>>>((double*)prho, nullptr, B, logpsi, m->desc.complex_out);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -1053,7 +1055,9 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
   Ckpt<T> ck;
   ck.h = ckh; ck.phi = ckphi; ck.R = R;
   STCHK((forward_chunk<T, DP>(m, spins, idmap, b0, Bc, rho, nullptr, nullptr, nullptr, st, ck)));
-  if (logpsi) logpsi_kernel<<<(Bc + 255) / 256, 256, 0, st>>>(rho, nullptr, Bc, logpsi + b0);
+  if (logpsi)
+    logpsi_kernel<<<(Bc + 255) / 256, 256, 0, st>>>(rho, nullptr, Bc, logpsi + (long)b0 * (1 + m->desc.complex_out),
+                                                    m->desc.complex_out);
   // read-out: dOmega, dA and the final mixer's tap gradients
   {
     ReadoutGradArgs<T> a{R, rho, m->omega, m->A64, N, Np, dd, DP, nmix, grads, Pn, m->lay.off_A, dg, dOm};
@@ -1162,6 +1166,7 @@ dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, v
                       double* wsum, hipStream_t st) {
   const dn_model_desc& d = m->desc;
   if (d.inject_phi) return fail(DN_EUNSUPPORTED, "per-sample gradients need inject_phi = 0");
+  if (d.complex_out) return fail(DN_EUNSUPPORTED, "per-sample gradients of a complex read-out are not implemented");
   STCHK(ensure_jac(m, st));
   T* grads = (T*)grads_out;
   const long Pn = m->lay.P;
@@ -1227,7 +1232,7 @@ template <typename T, int DP> struct RunSweep {
     STCHK(ws_get(m, "sw_kstart", (size_t)B * 4, &pks));
     STCHK(ws_get(m, "sw_pending", (size_t)B * 4, &ppe));
     STCHK(ws_get(m, "sw_frozen", 4, &pfr));
-    STCHK(ws_get(m, "sw_lr", (size_t)B * K * 8, &plr));
+    STCHK(ws_get(m, "sw_lr", (size_t)B * K * 8 * (1 + m->desc.complex_out), &plr));
     STCHK(ws_get(m, "sw_dom", (size_t)B * K * 2 * 8, &pdom));
     STCHK(ws_get(m, "sw_chain", (size_t)B * 4, &pch));
     STCHK(ws_get(m, "sw_rows", (size_t)B * N, &prs));
@@ -1235,7 +1240,7 @@ template <typename T, int DP> struct RunSweep {
     a.B = B; a.N = N; a.K = K; a.spacing = spacing; a.parity = parity; a.eps = eps; a.r_site = r_site; a.u = u;
     a.spins = spins; a.sites = (int32_t*)psi; a.sites_r = (int32_t*)psr; a.n_conn = (int32_t*)pnc;
     a.kstart = (int32_t*)pks; a.pending = (int32_t*)ppe; a.accepted = accepted; a.refreshes = refreshes;
-    a.frozen = (int32_t*)pfr; a.dom = (double*)pdom;
+    a.frozen = (int32_t*)pfr; a.dom = (double*)pdom; a.cplx = m->desc.complex_out;
     const int gs = (int)std::min<long>(4096, ((long)B * K + 255) / 256);
     sweep_init_kernel<<<gs, 256, 0, st>>>(a);
     HIPCHK(hipGetLastError());
@@ -1387,7 +1392,8 @@ template <typename T, int DP> struct RunLogpsiNoAlloc {
       CfgMap idmap{cb, cm, nullptr, 0};
       STCHK((forward_chunk<T, DP>(m, spins + (long)c0 * m->desc.N, idmap, 0, C, rho, nullptr, nullptr, nullptr, st,
                                   Ckpt<T>(), fields)));
-      logpsi_kernel<<<(C + 255) / 256, 256, 0, st>>>(rho, nullptr, C, logpsi + c0);
+      logpsi_kernel<<<(C + 255) / 256, 256, 0, st>>>(rho, nullptr, C, logpsi + (long)c0 * (1 + m->desc.complex_out),
+                                                     m->desc.complex_out);
       HIPCHK(hipGetLastError());
     }
     return DN_OK;
@@ -1413,6 +1419,7 @@ bool check_desc(const dn_model_desc* d, std::string* why) {
   if (d->act < 0 || d->act > 2) { *why = "bad act"; return false; }
   if (d->inject_phi != 0 && d->inject_phi != 1) { *why = "inject_phi must be 0 or 1"; return false; }
   if (d->prec < 0 || d->prec > 2) { *why = "bad prec"; return false; }
+  if (d->complex_out != 0 && d->complex_out != 1) { *why = "complex_out must be 0 or 1"; return false; }
   return true;
 }
 
@@ -1460,7 +1467,7 @@ template <typename T, int DP> struct RunInst {
     STCHK(ws_get(m, "rg_helem", (size_t)B * M * 8, &ph));
     STCHK(ws_get(m, "rg_nconn", (size_t)B * 4, &pn));
     STCHK(ws_get(m, "rg_hdiag", (size_t)B * 8, &pd));
-    STCHK(ws_get(m, "rg_lr", (size_t)B * M * 8, &pl));
+    STCHK(ws_get(m, "rg_lr", (size_t)B * M * 8 * (1 + m->desc.complex_out), &pl));
     STCHK(ws_get(m, "rg_Jr", (size_t)N * 8, &pj));
     int32_t* sites = (int32_t*)ps;
     int32_t* nconn = (int32_t*)pn;
@@ -1476,7 +1483,7 @@ template <typename T, int DP> struct RunInst {
     const int ext_max = in->ham.kind == DN_H_J1J2 ? 2 : 0;
     STCHK((abacus_exec<T, DP>(m, in->spins, B, sites, M, offs, cb, cm, nullptr, in->logpsi, (double*)pl, ext_max, st)));
     PScope e(m, DN_K_ELOC, st, 3.0 * B * M, (double)B * M * 16.0 + B * 20.0);
-    eloc_kernel<<<B, 64, 0, st>>>((double*)pd, (double*)ph, nconn, (double*)pl, M, in->eloc);
+    eloc_kernel<<<B, 64, 0, st>>>((double*)pd, (double*)ph, nconn, (double*)pl, M, in->eloc, m->desc.complex_out);
     HIPCHK(hipGetLastError());
     return DN_OK;
   }
@@ -1786,6 +1793,7 @@ dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const dou
   if (B < 1 || !(shift >= 0.0) || !std::isfinite(eta) || max_iter < 1 || !(tol >= 0.0))
     return fail(DN_EINVAL, "bad B, shift, eta, max_iter or tol");
   if (!O || !eloc || !delta) return fail(DN_EINVAL, "null argument");
+  if (m->desc.complex_out) return fail(DN_EUNSUPPORTED, "SR of a complex read-out is not implemented");
   return dispatch<RunSR>(m, O, eloc, weights, (int)B, shift, eta, (int)max_iter, tol, delta, energy, iters,
                          (hipStream_t)stream);
 }
@@ -1843,7 +1851,17 @@ dn_status dn_local_energy(const double* hdiag, const double* helem, const int32_
   if (B < 0 || M_max < 1) return fail(DN_EINVAL, "bad B or M_max");
   if (B == 0) return DN_OK;
   if (!hdiag || !helem || !n_conn || !logratio || !eloc) return fail(DN_EINVAL, "null argument");
-  eloc_kernel<<<B, 64, 0, (hipStream_t)stream>>>(hdiag, helem, n_conn, logratio, M_max, eloc);
+  eloc_kernel<<<B, 64, 0, (hipStream_t)stream>>>(hdiag, helem, n_conn, logratio, M_max, eloc, 0);
+  HIPCHK(hipGetLastError());
+  return DN_OK;
+}
+
+dn_status dn_local_energy_complex(const double* hdiag, const double* helem, const int32_t* n_conn,
+                                  const double* logratio, int32_t B, int32_t M_max, double* eloc, void* stream) {
+  if (B < 0 || M_max < 1) return fail(DN_EINVAL, "bad B or M_max");
+  if (B == 0) return DN_OK;
+  if (!hdiag || !helem || !n_conn || !logratio || !eloc) return fail(DN_EINVAL, "null argument");
+  eloc_kernel<<<B, 64, 0, (hipStream_t)stream>>>(hdiag, helem, n_conn, logratio, M_max, eloc, 1);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -1861,7 +1879,7 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
   STCHK(ws_get(m, "el_nconn", (size_t)B * 4, &pn));
   STCHK(ws_get(m, "el_hdiag", (size_t)B * 8, &pd));
   if (!logratio) {
-    STCHK(ws_get(m, "el_lr", (size_t)B * M_max * 8, &pl));
+    STCHK(ws_get(m, "el_lr", (size_t)B * M_max * 8 * (1 + m->desc.complex_out), &pl));
     logratio = (double*)pl;
   }
   {
@@ -1872,6 +1890,8 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
   }
   STCHK(dn_logratio(m, path, spins, B, (int32_t*)ps, (int32_t*)pn, M_max, logpsi, logratio, stream));
   PScope e(m, DN_K_ELOC, st, 3.0 * B * M_max, (double)B * M_max * 16.0 + B * 20.0);
+  if (m->desc.complex_out)
+    return dn_local_energy_complex((double*)pd, (double*)ph, (int32_t*)pn, logratio, B, M_max, eloc, stream);
   return dn_local_energy((double*)pd, (double*)ph, (int32_t*)pn, logratio, B, M_max, eloc, stream);
 }
 
@@ -1919,8 +1939,8 @@ dn_status dn_autotune(dn_model* m, const dn_ham_desc* ham, int32_t B_probe, int3
   hipStream_t st = (hipStream_t)stream;
   void *ps, *pl, *pe;
   STCHK(ws_get(m, "tu_spins", (size_t)B_probe * N, &ps));
-  STCHK(ws_get(m, "tu_lp", (size_t)B_probe * 8, &pl));
-  STCHK(ws_get(m, "tu_el", (size_t)B_probe * 8, &pe));
+  STCHK(ws_get(m, "tu_lp", (size_t)B_probe * 8 * (1 + m->desc.complex_out), &pl));
+  STCHK(ws_get(m, "tu_el", (size_t)B_probe * 8 * (1 + m->desc.complex_out), &pe));
   probe_spins_kernel<<<256, 256, 0, st>>>((int8_t*)ps, (long)B_probe * N, 0x9e3779b9u);
   HIPCHK(hipGetLastError());
   const bool prof = m->prof.on;

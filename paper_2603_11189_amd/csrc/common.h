@@ -77,6 +77,94 @@ __device__ inline double lcd_d(double a, double d) {
   return logcosh_d(a + d) - logcosh_d(a);
 }
 
+// ---- complex read-out (a complex output matrix A: Omega_0 + i Omega_1 is one complex unit) ----
+
+// x - 2 pi k with k the nearest integer: the phase representative in [-pi, pi].
+__device__ inline double wrap_phase_d(double y) {
+  const double two_pi = 6.28318530717958647692;
+  return y - two_pi * rint(y / two_pi);
+}
+
+// tanh(x + iy) = (sinh 2x + i sin 2y) / (cosh 2x + cos 2y), and +-1 once |x| > 20 (the
+// remainder is below e^-40).
+__device__ inline void ctanh_d(double x, double y, double* tr, double* ti) {
+  if (fabs(x) > 20.0) {
+    *tr = copysign(1.0, x);
+    *ti = 0.0;
+    return;
+  }
+  const double den = cosh(2.0 * x) + cos(2.0 * y);
+  *tr = sinh(2.0 * x) / den;
+  *ti = sin(2.0 * y) / den;
+}
+
+// log cosh(x + iy). |cosh z|^2 / cosh^2 x is both 1 - (sin y / cosh x)^2 and
+// tanh^2 x + (cos y / cosh x)^2: log1p of the first while (sin y / cosh x)^2 <= 1/2, the log
+// of the second (no cancellation next to a zero of cosh) beyond. arg = atan2(tanh x sin y, cos y).
+__device__ inline void logcosh_cd(double x, double y, double* re, double* im) {
+  const double ch = cosh(x), sy = sin(y), cy = cos(y), th = tanh(x);
+  const double q = sy / ch, c = cy / ch;
+  const double r = q * q > 0.5 ? log(th * th + c * c) : log1p(-q * q);
+  *re = logcosh_d(x) + 0.5 * r;
+  *im = atan2(th * sy, cy);
+}
+
+// log cosh(a + d) - log cosh(a) for complex a, d, phase in [-pi, pi]. For |d| <= 1:
+// cosh(a + d)/cosh(a) = 1 + w with w = 2 sinh^2(d/2) + tanh(a) sinh(d), and
+// log|1 + w| = 1/2 log1p(u), u = 2 Re w + |w|^2, while |u| <= 1/2 (else the log of
+// (1 + Re w)^2 + (Im w)^2); otherwise the difference of two log cosh values.
+__device__ inline void lcd_cd(double ar, double ai, double dr, double di, double* re, double* im) {
+  if (hypot(dr, di) <= 1.0) {
+    const double p = 0.5 * dr, q = 0.5 * di;
+    const double hr = sinh(p) * cos(q), hi = cosh(p) * sin(q);  // sinh(d/2)
+    double wr = 2.0 * (hr * hr - hi * hi), wi = 4.0 * hr * hi;
+    const double sr = sinh(dr) * cos(di), si = cosh(dr) * sin(di);  // sinh(d)
+    double tr, ti;
+    ctanh_d(ar, ai, &tr, &ti);
+    wr += tr * sr - ti * si;
+    wi += tr * si + ti * sr;
+    const double u = 2.0 * wr + wr * wr + wi * wi;
+    const double lm = fabs(u) <= 0.5 ? log1p(u) : log((1.0 + wr) * (1.0 + wr) + wi * wi);
+    *re = 0.5 * lm;
+    *im = atan2(wi, 1.0 + wr);
+    return;
+  }
+  double r1, i1, r0, i0;
+  logcosh_cd(ar + dr, ai + di, &r1, &i1);
+  logcosh_cd(ar, ai, &r0, &i0);
+  *re = r1 - r0;
+  *im = wrap_phase_d(i1 - i0);
+}
+
+// The read-out of the two output pre-activations (a0, a1): two real log-cosh units (cplx = 0,
+// one double at lp[b]) or one complex unit a0 + i a1 (cplx = 1, (re, im) at lp[2b], lp[2b+1]).
+__device__ inline void put_logpsi(double* lp, long b, double a0, double a1, int cplx) {
+  if (cplx) {
+    logcosh_cd(a0, a1, &lp[2 * b], &lp[2 * b + 1]);
+  } else {
+    lp[b] = logcosh_d(a0) + logcosh_d(a1);
+  }
+}
+
+// log psi(s')/psi(s) from Omega(s) = (a0, a1) and dOmega = (d0, d1), stored like put_logpsi.
+__device__ inline void put_ratio(double* lr, long o, double a0, double a1, double d0, double d1, int cplx) {
+  if (cplx) {
+    lcd_cd(a0, a1, d0, d1, &lr[2 * o], &lr[2 * o + 1]);
+  } else {
+    lr[o] = lcd_d(a0, d0) + lcd_d(a1, d1);
+  }
+}
+
+// log |psi(s')/psi(s)|: the real part of put_ratio's value.
+__device__ inline double ratio_re(double a0, double a1, double d0, double d1, int cplx) {
+  if (cplx) {
+    double re, im;
+    lcd_cd(a0, a1, d0, d1, &re, &im);
+    return re;
+  }
+  return lcd_d(a0, d0) + lcd_d(a1, d1);
+}
+
 // Workgroup barrier that orders LDS only: global requests stay in flight across it (for
 // kernels whose waves share no global data within the launch).
 __device__ inline void lds_barrier() {

@@ -79,18 +79,36 @@ __global__ __launch_bounds__(64) void connected_kernel(int kind, int periodic, d
   if (t == 0) { n_conn[b] = base < M_max ? base : M_max; hdiag[b] = e; }
 }
 
-// E_loc = hdiag + sum_{m < n_conn} helem_m exp(logratio_m), one wave per sample.
+// E_loc = hdiag + sum_{m < n_conn} helem_m exp(logratio_m), one wave per sample. cplx = 1: the
+// log-ratios are complex (re, im pairs) and so is E_loc ([B][2]).
 __global__ __launch_bounds__(64) void eloc_kernel(const double* __restrict__ hdiag,
                                                   const double* __restrict__ helem,
                                                   const int32_t* __restrict__ n_conn,
                                                   const double* __restrict__ lr, int M_max,
-                                                  double* __restrict__ eloc) {
+                                                  double* __restrict__ eloc, int cplx) {
   const int b = blockIdx.x, t = threadIdx.x;
   const int n = n_conn[b];
-  double acc = 0.0;
-  for (int m = t; m < n; m += WAVE) acc += helem[(long)b * M_max + m] * exp(lr[(long)b * M_max + m]);
+  double acc = 0.0, acc_i = 0.0;
+  if (cplx) {
+    for (int m = t; m < n; m += WAVE) {
+      const long o = (long)b * M_max + m;
+      const double mag = helem[o] * exp(lr[2 * o]);
+      acc += mag * cos(lr[2 * o + 1]);
+      acc_i += mag * sin(lr[2 * o + 1]);
+    }
+    acc_i = wave_sum(acc_i);
+  } else {
+    for (int m = t; m < n; m += WAVE) acc += helem[(long)b * M_max + m] * exp(lr[(long)b * M_max + m]);
+  }
   acc = wave_sum(acc);
-  if (t == 0) eloc[b] = hdiag[b] + acc;
+  if (t == 0) {
+    if (cplx) {
+      eloc[2 * b] = hdiag[b] + acc;
+      eloc[2 * b + 1] = acc_i;
+    } else {
+      eloc[b] = hdiag[b] + acc;
+    }
+  }
 }
 
 // Work list: for each sample b, (with_base ? 1 : 0) + n_conn[b] entries (b, m), m = -1 for the
@@ -189,26 +207,27 @@ template <typename T> __global__ void fill_kernel(T* __restrict__ x, long n, T v
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
 }
 
-// log psi = sum_k logcosh(Omega_k) for B samples whose Omega sits at rows idx[b] (or b).
+// log psi = sum_k logcosh(Omega_k) (or the complex unit's log cosh, cplx = 1) for B samples
+// whose Omega sits at rows idx[b] (or b).
 __global__ void logpsi_kernel(const double* __restrict__ Om, const int32_t* __restrict__ idx, int B,
-                              double* __restrict__ logpsi) {
+                              double* __restrict__ logpsi, int cplx) {
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
     const int r = idx ? idx[b] : b;
-    logpsi[b] = logcosh_d(Om[2 * r]) + logcosh_d(Om[2 * r + 1]);
+    put_logpsi(logpsi, b, Om[2 * r], Om[2 * r + 1], cplx);
   }
 }
 
 // Plain path: logratio[b, m] = sum_k lcd(Omega(s)_k, Omega(s'_m)_k - Omega(s)_k).
 __global__ void plain_ratio_kernel(const double* __restrict__ Om, const int32_t* __restrict__ offs,
                                    const int32_t* __restrict__ cb, const int32_t* __restrict__ cm,
-                                   int total, int M_max, double* __restrict__ lr) {
+                                   int total, int M_max, double* __restrict__ lr, int cplx) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
     const int m = cm[g];
     if (m < 0) continue;
     const int b = cb[g];
     const int base = offs[b];
     const double a0 = Om[2 * base], a1 = Om[2 * base + 1];
-    lr[(long)b * M_max + m] = lcd_d(a0, Om[2 * g] - a0) + lcd_d(a1, Om[2 * g + 1] - a1);
+    put_ratio(lr, (long)b * M_max + m, a0, a1, Om[2 * g] - a0, Om[2 * g + 1] - a1, cplx);
   }
 }
 

@@ -707,10 +707,11 @@ template <typename T> struct MixArgs {
   const T* taps1;        // taps of block 1 [DP][tap_stride] (first block)
   const T* p0L;          // last block: V v0 of block L [Bc][DP][Np]
   const double* Om0;     // last block: [B][2]
-  double* logratio;      // last block: [B][M_max]
+  double* logratio;      // last block: [B][M_max] ([B][M_max][2] with a complex read-out)
   double* dom;           // last block, nullable: [B][M_max][2] the output changes dOmega
   DynRange dyn;          // flips counted on the device (nullable)
   T* slice_part;         // last block: [F][Np/64][SLICE_WIN][DP] partial slices
+  int cplx;              // 1: complex read-out unit Omega_0 + i Omega_1
 };
 
 constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4; gradient kernels)
@@ -1499,7 +1500,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 // Finishes each flip after the tiled last block (one wave per flip): sums the tiles' partial
 // slices into y_L, forms e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, reads out e^(L)
 // and e^(0), adds the deep blocks' read-outs rho[l][f][t] and writes
-// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64.
+// log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64 (complex read-out: put_ratio).
 template <typename T, int DP>
 __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1618,7 +1619,7 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   o1 = wave_sum(o1);
   if (lane == 0) {
     const long o = (long)bg * A.map.M_max + m;
-    A.logratio[o] = lcd_d(A.Om0[2 * bg], o0) + lcd_d(A.Om0[2 * bg + 1], o1);
+    put_ratio(A.logratio, o, A.Om0[2 * bg], A.Om0[2 * bg + 1], o0, o1, A.cplx);
     if (A.dom) { A.dom[2 * o] = o0; A.dom[2 * o + 1] = o1; }
   }
 }

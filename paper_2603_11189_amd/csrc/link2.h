@@ -350,8 +350,9 @@ template <typename T> struct Flip12Args {
   const T* lam;         // [Bf][N][ND][DP]: pivot-0 link of block 2
   int ND, dlo;
   const double* Om0;    // [B][2]
-  double* logratio;     // [B][M_max]
+  double* logratio;     // [B][M_max] ([B][M_max][2] with a complex read-out)
   double* dom;          // nullable: [B][M_max][2] the output changes dOmega themselves
+  int cplx;             // 1: complex read-out unit Omega_0 + i Omega_1
 };
 
 // One or two blocks in one kernel per group of flips: the slice recompute (slm_layers) keeps
@@ -633,7 +634,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
       const int gg = f0 + g[5];
       const int bg = A.map.cb[gg], mm = A.map.cm[gg];
       const long o = (long)bg * A.map.M_max + mm;
-      F.logratio[o] = lcd_d(F.Om0[2 * bg], s0) + lcd_d(F.Om0[2 * bg + 1], s1);
+      put_ratio(F.logratio, o, F.Om0[2 * bg], F.Om0[2 * bg + 1], s0, s1, F.cplx);
       if (F.dom) { F.dom[2 * o] = s0; F.dom[2 * o + 1] = s1; }
     }
   }

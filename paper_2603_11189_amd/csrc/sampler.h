@@ -35,6 +35,7 @@ struct SweepArgs {
   int32_t* frozen;       // [1] chains that froze in this round
   const double* Om0;     // [rows][2] output of this round's background
   const double* dom;     // [rows][K][2] this round's changes (index k - kstart)
+  int cplx;              // 1: complex read-out unit (|psi|^2 decides: the ratio's real part)
 };
 
 // Proposals of the half-sweep and the initial state of every chain.
@@ -102,7 +103,7 @@ __global__ void sweep_accept_kernel(SweepArgs a) {
   for (int k = k0; k < a.K; ++k) {
     const long o = (long)row * a.K + (k - k0);
     const double d0 = a.dom[2 * o], d1 = a.dom[2 * o + 1];
-    const double P = fmin(1.0, exp(2.0 * (lcd_d(om0, d0) + lcd_d(om1, d1))));
+    const double P = fmin(1.0, exp(2.0 * ratio_re(om0, om1, d0, d1, a.cplx)));
     const double uu = a.u[(long)b * a.K + k];
     if (!(exact_first && k == k0) && fabs(uu - P) <= a.eps) {
       a.kstart[b] = k;
