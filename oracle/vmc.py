@@ -10,8 +10,12 @@ log-derivatives O_bk = d log psi(s_b) / d theta_k and local energies E_b:
     F_k     = sum_b w_b O_bk E_b - (sum_b w_b O_bk) E           (half the energy gradient)
     S_kl    = sum_b w_b O_bk O_bl - (sum_b w_b O_bk)(sum_b w_b O_bl)
     Delta   = -(S + shift * I)^-1 F,   theta <- theta + eta * Delta
-(real parameters and a real, positive psi: no complex conjugates). The solve here is a dense
-Cholesky factorisation; the GPU solves the same system by conjugate gradients.
+(real parameters and a real, positive psi: no complex conjugates). A complex psi (complex read-out)
+with real parameters has complex O and E_b; then F and S are the real parts of the same
+moments with O conjugated on the left: F = Re sum_b w_b conj(O_b - Obar) (E_b - E),
+S = Re sum_b w_b conj(O_b - Obar) (O_b - Obar)^T, and E is real up to sampling noise (its
+imaginary part is reported as it comes). The solve here is a dense Cholesky factorisation; the
+GPU solves the same system by conjugate gradients.
 """
 from __future__ import annotations
 
@@ -26,9 +30,19 @@ from .model import DT, forward, plain_logratio
 
 def sr_moments(O, E, w):
     """(E, F, S) of the definitions above."""
-    O = torch.as_tensor(O, dtype=DT)
-    E = torch.as_tensor(E, dtype=DT)
+    O = torch.as_tensor(O)
+    E = torch.as_tensor(E)
     w = torch.as_tensor(w, dtype=DT)
+    if O.is_complex() or E.is_complex():
+        O = O.to(torch.complex128)
+        E = E.to(torch.complex128)
+        Ebar = (w * E).sum()
+        Oc = O - (w[:, None] * O).sum(0)
+        F = (w[:, None] * Oc.conj() * (E - Ebar)[:, None]).sum(0).real
+        S = (Oc.conj().T @ (w[:, None] * Oc)).real
+        return Ebar, F, S
+    O = O.to(DT)
+    E = E.to(DT)
     Ebar = (w * E).sum()
     Obar = (w[:, None] * O).sum(0)
     Oc = O - Obar
