@@ -167,7 +167,10 @@ dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spaci
  * delta = -eta x is written (device float64 [P]); the caller adds it to the parameters and calls
  * dn_model_set_params. energy (device float64 [1], nullable) receives Ebar; iters (host,
  * nullable) the iterations taken. Every sum is float64; S is never formed (each iteration reads
- * O twice). Synchronises the stream every 8 iterations. */
+ * O twice). Synchronises the stream every 8 iterations. A complex_out model (complex psi, real
+ * parameters) takes O as dn_grad_logpsi writes it, [2][B][P], eloc [B][2] complex, and uses
+ * F = Re sum_b w_b conj(O_b - Obar)(E_b - Ebar), S = Re sum_b w_b conj(O_b - Obar)(O_b - Obar)^T;
+ * energy is then [2] (re, im). */
 dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const double* weights, int32_t B,
                        double shift, double eta, int32_t max_iter, double tol, double* delta,
                        double* energy, int32_t* iters, void* stream);
@@ -235,7 +238,9 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
  * for DN_PREC_FP64), nullable (then kept in the workspace); logpsi [B] nullable; weights [B] and
  * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open and periodic
  * chains (periodic: the Jacobian of the aliased kernel, Sec. V); inject_phi = 0 only
- * (DN_EUNSUPPORTED otherwise). Asynchronous on the stream. */
+ * (DN_EUNSUPPORTED otherwise). A complex_out model has complex O = d Re log psi + i d Im log psi
+ * (the parameters are real): grads is then [2][B][P] (all real parts, then all imaginary
+ * parts; two reverse passes), wsum [2][P] likewise, logpsi [B][2]. Asynchronous on the stream. */
 dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,
                          const double* weights, double* wsum, void* stream);
 

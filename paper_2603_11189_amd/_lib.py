@@ -207,16 +207,21 @@ class Model:
 
 
     def grad_logpsi(self, spins: torch.Tensor, weights: torch.Tensor | None = None, want_grads: bool = True):
-        """(logpsi [B], grads [B, P] or None, wsum [P] or None) of d log psi / d theta per sample."""
+        """(logpsi [B], grads [B, P] or None, wsum [P] or None) of d log psi / d theta per sample.
+        A complex-output model gives complex logpsi, grads (d Re + i d Im) and wsum."""
         B = spins.shape[0]
         P = param_count(self.shape)
+        parts = 2 if self.out_dtype == torch.complex128 else 1
         dt = torch.float64 if self.prec == "fp64" else torch.float32
-        lp = torch.empty(B, dtype=torch.float64, device=spins.device)
-        g = torch.empty((B, P), dtype=dt, device=spins.device) if want_grads else None
-        ws = torch.empty(P, dtype=torch.float64, device=spins.device) if weights is not None else None
+        lp = torch.empty(B, dtype=self.out_dtype, device=spins.device)
+        g = torch.empty((parts, B, P), dtype=dt, device=spins.device) if want_grads else None
+        ws = torch.empty((parts, P), dtype=torch.float64, device=spins.device) if weights is not None else None
         w = weights.to(torch.float64).contiguous() if weights is not None else None
         _check(lib().dn_grad_logpsi(self.handle, _ptr(spins), B, _ptr(lp), _ptr(g), _ptr(w), _ptr(ws), _stream()))
-        return lp, g, ws
+        if parts == 1:
+            return lp, (g[0] if g is not None else None), (ws[0] if ws is not None else None)
+        return lp, (torch.complex(g[0], g[1]) if g is not None else None), \
+            (torch.complex(ws[0], ws[1]) if ws is not None else None)
 
     def screened_sweep(self, spins: torch.Tensor, spacing: int, parity: int, r_site: torch.Tensor,
                        u: torch.Tensor, eps: float):
@@ -235,16 +240,23 @@ class Model:
 
     def sr_update(self, grads: torch.Tensor, eloc: torch.Tensor, weights: torch.Tensor | None = None,
                   shift: float = 1e-3, eta: float = 0.05, max_iter: int = 200, tol: float = 1e-10):
-        """dn_sr_update: (delta [P] float64, energy float64 scalar tensor, CG iterations)."""
+        """dn_sr_update: (delta [P] float64, energy scalar tensor, CG iterations). A complex-output
+        model takes complex grads and eloc (as grad_logpsi and eloc return them) and reports a
+        complex energy."""
         B, P = grads.shape
+        cplx = self.out_dtype == torch.complex128
         delta = torch.empty(P, dtype=torch.float64, device=grads.device)
-        energy = torch.empty(1, dtype=torch.float64, device=grads.device)
+        energy = torch.empty(2 if cplx else 1, dtype=torch.float64, device=grads.device)
         it = ctypes.c_int32()
         w = weights.to(torch.float64).contiguous() if weights is not None else None
-        g, e = grads.contiguous(), eloc.to(torch.float64).contiguous()
+        if cplx:  # the library's layout: O [2][B][P] (real parts, then imaginary parts), E [B][2]
+            g = torch.stack([grads.real, grads.imag]).contiguous()
+            e = torch.view_as_real(eloc.to(torch.complex128).contiguous()).contiguous()
+        else:
+            g, e = grads.contiguous(), eloc.to(torch.float64).contiguous()
         _check(lib().dn_sr_update(self.handle, _ptr(g), _ptr(e), _ptr(w), B, shift, eta, max_iter, tol, _ptr(delta),
                                   _ptr(energy), ctypes.byref(it), _stream()))
-        return delta, energy[0], it.value
+        return delta, (torch.complex(energy[0], energy[1]) if cplx else energy[0]), it.value
 
     def autotune(self, ham, B_probe: int = 256):
         """Pick this model's launch shapes by timing; returns (conv_nt, flip_budget_bytes)."""

@@ -33,7 +33,15 @@ class _LogPsi(torch.autograd.Function):
         if newer is not None:
             model.set_params(ctx.params)
         try:
-            _, _, wsum = model.grad_logpsi(spins, weights=grad_out.detach(), want_grads=False)
+            g = grad_out.detach()
+            if g.is_complex():
+                # complex log psi of real parameters: the incoming gradient is
+                # dL/dRe log psi + i dL/dIm log psi, so dL/dtheta = sum_b Re(g_b) dRe O_b + Im(g_b) dIm O_b
+                _, _, ws_r = model.grad_logpsi(spins, weights=g.real, want_grads=False)
+                _, _, ws_i = model.grad_logpsi(spins, weights=g.imag, want_grads=False)
+                wsum = ws_r.real + ws_i.imag
+            else:
+                _, _, wsum = model.grad_logpsi(spins, weights=g, want_grads=False)
         finally:
             if newer is not None:
                 model.set_params(newer)
@@ -41,5 +49,6 @@ class _LogPsi(torch.autograd.Function):
 
 
 def logpsi(model: Model, params: torch.Tensor, spins: torch.Tensor) -> torch.Tensor:
-    """log psi(s) [B] (float64), differentiable with respect to the flat parameter vector."""
+    """log psi(s) [B] (float64; complex128 for a complex-output model), differentiable with
+    respect to the flat (real) parameter vector."""
     return _LogPsi.apply(params, spins, model)

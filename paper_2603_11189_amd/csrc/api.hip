@@ -1022,7 +1022,7 @@ template <> const float* jac_of<float>(dn_model* m) { return m->jac32; }
 
 template <typename T, int DP>
 dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int Bc, double* logpsi, T* grads,
-                     hipStream_t st) {
+                     hipStream_t st, int part = 0) {
   const dn_model_desc& d = m->desc;
   const int N = d.N, Np = m->Np, L = d.L, wc = d.w_c, dd = d.d, Wc = 2 * wc + 1;
   const long fld = (long)Bc * DP * Np;
@@ -1061,6 +1061,8 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
   // read-out: dOmega, dA and the final mixer's tap gradients
   {
     ReadoutGradArgs<T> a{R, rho, m->omega, m->A64, N, Np, dd, DP, nmix, grads, Pn, m->lay.off_A, dg, dOm};
+    a.cplx = d.complex_out;
+    a.part = part;
     PScope ps(m, DN_K_OTHER, st, 4.0 * Bc * dd * (double)N, (double)fld * sizeof(T));
     readout_grad_kernel<T><<<dim3(Bc, dd), 256, (size_t)(Np + 1) * sizeof(double), st>>>(a);
   }
@@ -1166,13 +1168,13 @@ dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, v
                       double* wsum, hipStream_t st) {
   const dn_model_desc& d = m->desc;
   if (d.inject_phi) return fail(DN_EUNSUPPORTED, "per-sample gradients need inject_phi = 0");
-  if (d.complex_out) return fail(DN_EUNSUPPORTED, "per-sample gradients of a complex read-out are not implemented");
   STCHK(ensure_jac(m, st));
   T* grads = (T*)grads_out;
   const long Pn = m->lay.P;
+  const int parts = 1 + d.complex_out;  // a complex read-out: real part, then imaginary part
   if (!grads) {
     void* p;
-    STCHK(ws_get(m, "g_out", (size_t)B * Pn * sizeof(T), &p));
+    STCHK(ws_get(m, "g_out", (size_t)parts * B * Pn * sizeof(T), &p));
     grads = (T*)p;
   }
   int32_t *idb, *idm;
@@ -1181,11 +1183,16 @@ dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, v
   const size_t per = (size_t)DP * m->Np * sizeof(T) * (2 * d.L + 19) +
                      (size_t)(d.L + 1) * d.d * (2 * d.N - 1) * sizeof(T);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)2 << 30) / per));
-  for (int b0 = 0; b0 < B; b0 += Bc_max) {
-    const int Bc = std::min(Bc_max, B - b0);
-    STCHK((grad_chunk<T, DP>(m, spins, idmap, b0, Bc, logpsi, grads + (long)b0 * Pn, st)));
-  }
-  if (w && wsum) wsum_kernel<T><<<(int)std::min<long>(4096, (Pn + 255) / 256), 256, 0, st>>>(grads, w, B, Pn, wsum);
+  for (int part = 0; part < parts; ++part)
+    for (int b0 = 0; b0 < B; b0 += Bc_max) {
+      const int Bc = std::min(Bc_max, B - b0);
+      STCHK((grad_chunk<T, DP>(m, spins, idmap, b0, Bc, part ? nullptr : logpsi,
+                               grads + ((long)part * B + b0) * Pn, st, part)));
+    }
+  if (w && wsum)
+    for (int part = 0; part < parts; ++part)
+      wsum_kernel<T><<<(int)std::min<long>(4096, (Pn + 255) / 256), 256, 0, st>>>(grads + (long)part * B * Pn, w, B,
+                                                                                     Pn, wsum + (long)part * Pn);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -1282,20 +1289,24 @@ template <typename T, int DP> struct RunSR {
                        int max_iter, double tol, double* delta, double* energy, int32_t* iters, hipStream_t st) {
     const T* O = (const T*)Ov;
     const long P = m->lay.P;
+    const int parts = 1 + m->desc.complex_out;  // complex: rows Or then Oi, energies Re E then Im E
     void *pv, *pb, *psc;
-    STCHK(ws_get(m, "sr_vec", (size_t)6 * P * 8, &pv));
-    STCHK(ws_get(m, "sr_smp", (size_t)3 * B * 8, &pb));
+    STCHK(ws_get(m, "sr_vec", (size_t)(5 + parts) * P * 8, &pv));
+    STCHK(ws_get(m, "sr_smp", (size_t)(1 + 2 * parts) * B * 8, &pb));
     STCHK(ws_get(m, "sr_sc", (8 + SR_DOT_WG) * 8, &psc));
-    double *x = (double*)pv, *r = x + P, *p = r + P, *Ap = p + P, *F = Ap + P, *Ob = F + P;
-    double *wv = (double*)pb, *we = wv + B, *t = we + B, *sc = (double*)psc, *dpart = sc + 8;
+    double *x = (double*)pv, *r = x + P, *p = r + P, *Ap = p + P, *F = Ap + P, *Ob = F + P;  // Ob [parts][P]
+    double *wv = (double*)pb, *we = wv + B, *t = we + (long)parts * B, *sc = (double*)psc, *dpart = sc + 8;
+    const int rows = parts * B;
     auto dot = [&](const double* u, const double* v, double* out) {
       sr_dot_kernel<<<SR_DOT_WG, 256, 0, st>>>(u, v, P, dpart);
       sr_dot_sum_kernel<<<1, 256, 0, st>>>(dpart, out);
     };
     const int gp = (int)((P + 255) / 256), gv = (int)std::min<long>(1024, (P + 255) / 256);
-    sr_energy_kernel<<<1, 1024, 0, st>>>(E, w, B, wv, we, sc + 5);
-    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, wv, nullptr, 0.0, Ob);
-    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, we, nullptr, 0.0, F);
+    for (int q = 0; q < parts; ++q) {
+      sr_energy_kernel<<<1, 1024, 0, st>>>(E + q, parts, w, B, wv, we + (long)q * B, sc + 5 + q);
+      sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O + (long)q * B * P, P, B, wv, nullptr, 0.0, Ob + (long)q * P);
+    }
+    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, rows, we, nullptr, 0.0, F);
     sr_init_kernel<<<gv, 256, 0, st>>>(x, r, p, F, P);
     dot(F, F, sc + 0);
     dot(F, F, sc + 4);
@@ -1307,9 +1318,12 @@ template <typename T, int DP> struct RunSR {
     int it = 0;
     if (fnorm > 0.0) {
       for (it = 1; it <= max_iter; ++it) {
-        dot(Ob, p, sc + 3);
-        sr_rowdot_kernel<T><<<B, 256, 0, st>>>(O, P, p, sc + 3, wv, t);
-        sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, B, t, p, shift, Ap);
+        for (int q = 0; q < parts; ++q) {
+          double* sub = sc + (q ? 7 : 3);
+          dot(Ob + (long)q * P, p, sub);
+          sr_rowdot_kernel<T><<<B, 256, 0, st>>>(O + (long)q * B * P, P, p, sub, wv, t + (long)q * B);
+        }
+        sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, rows, t, p, shift, Ap);
         dot(p, Ap, sc + 1);
         sr_step_kernel<<<gv, 256, 0, st>>>(x, r, p, Ap, P, sc);
         dot(r, r, sc + 2);
@@ -1325,7 +1339,7 @@ template <typename T, int DP> struct RunSR {
       if (it > max_iter) it = max_iter;
     }
     sr_scale_kernel<<<gv, 256, 0, st>>>(x, eta, P, delta);
-    if (energy) HIPCHK(hipMemcpyAsync(energy, sc + 5, 8, hipMemcpyDeviceToDevice, st));
+    if (energy) HIPCHK(hipMemcpyAsync(energy, sc + 5, 8 * parts, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipGetLastError());
     if (iters) *iters = it;
     return DN_OK;
@@ -1793,7 +1807,6 @@ dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const dou
   if (B < 1 || !(shift >= 0.0) || !std::isfinite(eta) || max_iter < 1 || !(tol >= 0.0))
     return fail(DN_EINVAL, "bad B, shift, eta, max_iter or tol");
   if (!O || !eloc || !delta) return fail(DN_EINVAL, "null argument");
-  if (m->desc.complex_out) return fail(DN_EUNSUPPORTED, "SR of a complex read-out is not implemented");
   return dispatch<RunSR>(m, O, eloc, weights, (int)B, shift, eta, (int)max_iter, tol, delta, energy, iters,
                          (hipStream_t)stream);
 }

@@ -376,6 +376,9 @@ __global__ __launch_bounds__(256) void tapgrad_kernel(TapGradArgs<T> A) {
 
 // ------------------------------------------------------------------------------------------
 // Read-out gradients per sample: dOmega_k = tanh(Omega_k); rho_c = (1/N) sum_i omega_{i,c} R_{i,c};
+// a complex read-out (one unit z = Omega_0 + i Omega_1, t = tanh z) has d log psi = t (dOmega_0 +
+// i dOmega_1), so part 0 (the real part) seeds (Re t, -Im t) and part 1 (the imaginary part)
+// (Im t, Re t); everything below is linear in the seed;
 // dA[c][k] = rho_c dOmega_k; the final mixer enters only through omega_{i,c} = sum_j g^f_c(j - i),
 // so dg^f_c(r) = sum_{i : 0 <= i + r < N} R_{i,c} drho_c / N with drho_c = sum_k A[c][k] dOmega_k.
 template <typename T> struct ReadoutGradArgs {
@@ -388,6 +391,7 @@ template <typename T> struct ReadoutGradArgs {
   long Pn, offA;
   T* dg;                  // [C][nmix][d][2N-1], final mixer = nmix-1
   double* dOm;            // [C][2] out
+  int cplx, part;         // complex read-out; which part of log psi is differentiated
 };
 
 template <typename T>
@@ -396,7 +400,16 @@ __global__ __launch_bounds__(256) void readout_grad_kernel(ReadoutGradArgs<T> A)
   double* pre = reinterpret_cast<double*>(smem_raw);  // prefix sums of R_{.,c}, [Np+1]
   const int g = blockIdx.x, c = blockIdx.y;
   const int N = A.N, Np = A.Np;
-  const double t0 = tanh(A.Om[2 * g]), t1 = tanh(A.Om[2 * g + 1]);
+  double t0, t1;
+  if (A.cplx) {
+    double tr, ti;
+    ctanh_d(A.Om[2 * g], A.Om[2 * g + 1], &tr, &ti);
+    t0 = A.part ? ti : tr;
+    t1 = A.part ? tr : -ti;
+  } else {
+    t0 = tanh(A.Om[2 * g]);
+    t1 = tanh(A.Om[2 * g + 1]);
+  }
   if (c == 0 && threadIdx.x == 0) { A.dOm[2 * g] = t0; A.dOm[2 * g + 1] = t1; }
   if (c >= A.d) return;
   const long ro = ((long)g * A.DP + c) * Np;

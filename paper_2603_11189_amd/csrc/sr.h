@@ -7,18 +7,24 @@
 // O is read in the model's field type and every sum is float64. The passes over O are
 // bandwidth bound: one thread per parameter for the column sums (coalesced rows), one
 // workgroup per sample for the row products.
+// A complex wavefunction with real parameters (complex read-out) has O = Or + i Oi and complex
+// E_b; its force and SR matrix are the real parts of the conjugated moments, which split into
+// the real problem of the rows Or (energies Re E) plus that of the rows Oi (energies Im E), each
+// centred by its own mean: O is then [2][B][P] (2B rows) and every row pass covers both halves.
 #pragma once
 #include "common.h"
 
 namespace dn {
 
-// Ebar and the weighted centred energies we_b = w_b (E_b - Ebar); w = 1/B when not given.
-__global__ __launch_bounds__(1024) void sr_energy_kernel(const double* __restrict__ E, const double* __restrict__ w,
-                                                         int B, double* __restrict__ wout, double* __restrict__ we,
+// Ebar and the weighted centred energies we_b = w_b (E_b - Ebar) of the energies E[b * stride];
+// w = 1/B when not given.
+__global__ __launch_bounds__(1024) void sr_energy_kernel(const double* __restrict__ E, int stride,
+                                                         const double* __restrict__ w, int B,
+                                                         double* __restrict__ wout, double* __restrict__ we,
                                                          double* __restrict__ ebar) {
   __shared__ double part[1024];
   double s = 0.0;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) s += (w ? w[b] : 1.0 / B) * E[b];
+  for (int b = threadIdx.x; b < B; b += blockDim.x) s += (w ? w[b] : 1.0 / B) * E[(long)b * stride];
   part[threadIdx.x] = s;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
@@ -29,7 +35,7 @@ __global__ __launch_bounds__(1024) void sr_energy_kernel(const double* __restric
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     const double wb = w ? w[b] : 1.0 / B;
     wout[b] = wb;
-    we[b] = wb * (E[b] - eb);
+    we[b] = wb * (E[(long)b * stride] - eb);
   }
   if (threadIdx.x == 0) *ebar = eb;
 }
@@ -104,7 +110,8 @@ __global__ __launch_bounds__(256) void sr_dot_sum_kernel(const double* __restric
   if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// CG scalars in one small array: [0] r.r, [1] p.Ap, [2] new r.r, [3] Obar.p
+// CG scalars in one small array: [0] r.r, [1] p.Ap, [2] new r.r, [3] Obar.p, [4] F.F, [5] Ebar
+// (real part), [6] Ebar (imaginary part), [7] Obar.p of the imaginary rows
 // x += alpha p, r -= alpha Ap with alpha = r.r / p.Ap.
 __global__ void sr_step_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                                const double* __restrict__ Ap, long n, const double* __restrict__ sc) {
