@@ -21,6 +21,16 @@ The reference chain is plain Metropolis-Hastings: R = |psi(s')|^2 / |psi(s)|^2 f
 evaluations, accept iff u < min(1, R). f = prod_k cosh (log psi = sum_k log cosh Omega_k), so
 R~ = exp(2 sum_k lcd(Omega_k, dOmega_k)) (for a complex-output network the real part of the
 complex log-ratio of its units: |psi|^2 decides).
+
+The practical tolerance schedule of the same appendix: a buffer eps(n) indexed by the number n
+of flips accepted since the current background (the last entry serves every larger n), read
+when a proposal is screened. At each refresh the frozen proposal's approximate and exact
+acceptance probabilities give the empirical error e~ = |min(1, R~) - min(1, R)|, recorded with
+the n at which the chain froze. The buffer entries start at a conservative default; an entry
+still at its default is overwritten with e~, any other becomes max(eps(n), gamma e~) with
+gamma > 1. Here the buffer is one per sampler (shared by its chains) and held fixed during a
+half-sweep; the half-sweep's events are applied afterwards, chain by chain in chain order and
+in order of occurrence within a chain (``update_eps_buffer``).
 """
 from __future__ import annotations
 
@@ -79,37 +89,60 @@ def _updates(desc, theta, s, sites: List[int]):
     return Om, [p["dOmega"] for p in parts]
 
 
-def screened_sweep(desc, theta, spins, sites: List[int], u, eps: float, track: bool = False) -> Dict:
+def screened_sweep(desc, theta, spins, sites: List[int], u, eps: float, track: bool = False,
+                   eps_buf=None) -> Dict:
     """Algorithm 2 on one chain: returns the final spins, the decisions, the number of refreshes,
-    the largest |R~ - R| seen at a refresh (R exact at the refreshed background) and, with
-    track, the largest |min(1, R~) - min(1, R)| over the decisions taken without a refresh (R
-    from two full evaluations): a decision taken without a refresh has |u - min(1, R~)| > eps,
-    so it is the exact one whenever that difference is <= eps."""
+    the largest |R~ - R| seen at a refresh (R exact at the refreshed background), the refresh
+    events [(n, e~)] (n flips accepted since the background when the chain froze, e~ the
+    empirical error of its acceptance probability) and, with track, the largest
+    |min(1, R~) - min(1, R)| over the decisions taken without a refresh (R from two full
+    evaluations) and the largest excess of that difference over the tolerance the decision used:
+    a decision taken without a refresh has |u - min(1, R~)| > eps, so it is the exact one
+    whenever the difference is <= eps. The tolerance is eps, or eps_buf[min(n, len - 1)] when a
+    buffer is given."""
     theta = torch.as_tensor(theta, dtype=DT)
     s = torch.as_tensor(spins).to(torch.int64).clone()
     Om, dOm = _updates(desc, theta, s, sites)
     base = 0                      # index of the first proposal the current updates cover
-    acc, refreshes, isa_err, unscreened = [], 0, 0.0, 0.0
+    n = 0                         # flips accepted since the current background
+    acc, refreshes, isa_err, unscreened, excess, events = [], 0, 0.0, 0.0, -math.inf, []
     for k, j in enumerate(sites):
         Rt = math.exp(2.0 * ratio(desc, Om, dOm[k - base]).real.item())
         P = min(1.0, Rt)
-        if abs(float(u[k]) - P) <= eps:
+        tol = eps if eps_buf is None else float(eps_buf[min(n, len(eps_buf) - 1)])
+        if abs(float(u[k]) - P) <= tol:
             # ambiguous: rebuild the background at the current configuration
             refreshes += 1
             Om, dOm = _updates(desc, theta, s, sites[k:])
             base = k
             R = math.exp(2.0 * ratio(desc, Om, dOm[0]).real.item())
             isa_err = max(isa_err, abs(Rt - R))
+            events.append((n, abs(P - min(1.0, R))))
             P = min(1.0, R)
+            n = 0
         elif track:
             sp = s.clone()
             sp[j] = -sp[j]
             R = math.exp(2.0 * (_logpsi(desc, theta, sp) - _logpsi(desc, theta, s)))
             unscreened = max(unscreened, abs(P - min(1.0, R)))
+            excess = max(excess, abs(P - min(1.0, R)) - tol)
         a = float(u[k]) < P
         acc.append(a)
         if a:
             s[j] = -s[j]
             Om = Om + dOm[k - base]
+            n += 1
     return {"spins": s, "accepted": acc, "refreshes": refreshes, "isa_err": isa_err,
-            "unscreened_err": unscreened}
+            "unscreened_err": unscreened, "unscreened_excess": excess, "events": events}
+
+
+def update_eps_buffer(buf: List[float], is_set: List[bool], events, gamma: float) -> None:
+    """Apply refresh events [(n, e~)] in order: the entry min(n, len - 1) takes e~ if it still
+    holds its default, else max(entry, gamma e~)."""
+    for n, e in events:
+        i = min(n, len(buf) - 1)
+        if not is_set[i]:
+            buf[i] = e
+            is_set[i] = True
+        else:
+            buf[i] = max(buf[i], gamma * e)

@@ -13,13 +13,15 @@ Metropolis sampler is exact"; App. "Practical implementation of the screened typ
   updates from full evaluations of single flips of the starting configuration, ratios
   prod_units cosh^2(Omega + dOmega) / cosh^2(Omega) with Omega accumulating the accepted updates.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
 
 import dn_inputs as di
 from oracle.model import ModelDesc, forward
-from oracle.sampler import exact_mh_sweep, screened_sweep, typewriter_sites
+from oracle.sampler import exact_mh_sweep, screened_sweep, typewriter_sites, update_eps_buffer
 
 
 def _draws(shape, K, seed):
@@ -129,3 +131,76 @@ def test_zero_tolerance_is_the_independent_scattering_chain():
             s[j] = -s[j]
             Om = Om + dO
     assert torch.equal(s, got["spins"])
+
+
+# ---- the practical tolerance schedule eps(n) (App. "Practical implementation of the screened
+# typewriter sampler"): a buffer indexed by the flips accepted since the background
+
+
+def test_constant_buffer_equals_fixed_tolerance():
+    shape, spacing, eps = CASES[1]
+    desc = ModelDesc.of(shape)
+    th = _peaked(shape, 17)
+    s0 = torch.tensor(di.uniform_spins(1, shape.N, 4)[0]).long()
+    rng = np.random.Generator(np.random.PCG64(71))
+    K = len(range(0, shape.N, 2))
+    r, u = rng.random(K), rng.random(K)
+    sites = typewriter_sites(shape.N, spacing, 0, r)
+    a = screened_sweep(desc, th, s0, sites, u, eps)
+    b = screened_sweep(desc, th, s0, sites, u, 0.0, eps_buf=[eps] * 5)
+    assert a["accepted"] == b["accepted"] and torch.equal(a["spins"], b["spins"])
+    assert a["refreshes"] == b["refreshes"] and a["events"] == b["events"]
+
+
+def test_buffer_update_rule_worked_example():
+    # entries start at the default 0.2 (not yet set); gamma = 1.5; n beyond the buffer uses its
+    # last entry
+    buf, is_set = [0.2] * 3, [False] * 3
+    update_eps_buffer(buf, is_set, [(1, 0.03)], 1.5)
+    assert buf == [0.2, 0.03, 0.2] and is_set == [False, True, False]   # first visit: e~ itself
+    update_eps_buffer(buf, is_set, [(1, 0.05), (1, 0.01)], 1.5)
+    assert math.isclose(buf[1], 0.075)                                    # max(0.03, 1.5 * 0.05)
+    update_eps_buffer(buf, is_set, [(7, 0.004), (2, 0.001)], 1.5)
+    assert buf[2] == 0.004 and is_set[2]       # n = 7 -> entry 2 (first visit), then max(0.004, 0.0015)
+    update_eps_buffer(buf, is_set, [(0, 0.0)], 1.5)
+    assert buf[0] == 0.0 and is_set[0]
+
+
+def _adaptive_run(shape, spacing, sweeps, B, gamma, default, seed):
+    desc = ModelDesc.of(shape)
+    th = _peaked(shape, 17)
+    chains = [torch.tensor(x).long() for x in di.uniform_spins(B, shape.N, 4)]
+    buf, is_set = [default] * 6, [False] * 6
+    refreshes, out = [], []
+    for sweep in range(sweeps):
+        parity = sweep % 2
+        K = len(range(parity, (shape.N + spacing - 1) // spacing, 2))
+        rng = np.random.Generator(np.random.PCG64(seed + sweep))
+        r, u = rng.random((B, K)), rng.random((B, K))
+        events, nref = [], 0
+        for b in range(B):
+            sites = typewriter_sites(shape.N, spacing, parity, r[b])
+            got = screened_sweep(desc, th, chains[b], sites, u[b], 0.0, track=True, eps_buf=list(buf))
+            ref = exact_mh_sweep(desc, th, chains[b], sites, u[b])
+            out.append((ref, got))
+            events += got["events"]
+            nref += got["refreshes"]
+            chains[b] = got["spins"]
+        update_eps_buffer(buf, is_set, events, gamma)
+        refreshes.append(nref)
+    return out, refreshes, buf, is_set
+
+
+def test_adaptive_schedule_calibrates_and_stays_exact():
+    shape = di.ModelShape(16, 2, 4, 3, act="silu", bc="open")
+    out, refreshes, buf, is_set = _adaptive_run(shape, 1, 6, 3, 1.5, 0.2, 930)
+    for ref, got in out:
+        for n, e in got["events"]:
+            if n == 0:  # no accepted flip since the background: the approximate ratio is exact
+                assert e <= 1e-12
+        if got["unscreened_excess"] <= 0.0:  # every unscreened decision's error within its tolerance
+            assert got["accepted"] == ref["accepted"]
+    assert any(is_set) and max(b for b, s_ in zip(buf, is_set) if s_) < 0.2
+    # the conservative default freezes at every ambiguous draw within 0.2; calibrated entries
+    # freeze far less often
+    assert refreshes[-1] < refreshes[0]
