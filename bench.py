@@ -243,6 +243,8 @@ def main():
                     help="float matrix-core products: three-term bf16 splits (default) or float32 matrix cores")
     ap.add_argument("--sampler", action="store_true",
                     help="screened typewriter sampler: Metropolis proposals per second on the workload")
+    ap.add_argument("--eps-adaptive", action="store_true",
+                    help="with --sampler: the tolerance buffer eps(n) instead of a fixed eps")
     ap.add_argument("--sr", action="store_true",
                     help="stochastic-reconfiguration update from the workload's per-sample log-derivatives")
     ap.add_argument("--sweep", action="store_true",
@@ -535,7 +537,9 @@ def bench_sampler(args) -> None:
     """Screened typewriter sampler (dn_screened_sweep) on the workload's model at the stress draw
     (order-one signal in every block, so that proposals are rejected and the screen refreshes):
     B chains, blocks of 8 sites, one proposal per visited block, eps = 0.01; a step is one sweep
-    (both parities)."""
+    (both parities). With --eps-adaptive the tolerance is the buffer eps(n) (16 entries, default
+    0.2, gamma 1.5), calibrated during the warmup sweeps (the burn-in) and kept updating while
+    timed."""
     import numpy as np
     import torch
 
@@ -559,11 +563,16 @@ def bench_sampler(args) -> None:
     draws = [[(torch.tensor(rng.random((B, K[par])), device=dev), torch.tensor(rng.random((B, K[par])), device=dev))
               for par in (0, 1)] for _ in range(4)]
     acc_n, ref_n = [0], [0]
+    ebuf = torch.full((16,), 0.2, dtype=torch.float64, device=dev)
+    eset = torch.zeros(16, dtype=torch.int32, device=dev)
 
     def sweep(i):
         for par in (0, 1):
             r, u = draws[i % 4][par]
-            a, rf = m.screened_sweep(spins, spacing, par, r, u, eps)
+            if args.eps_adaptive:
+                a, rf = m.screened_sweep_adaptive(spins, spacing, par, r, u, ebuf, eset, 1.5)
+            else:
+                a, rf = m.screened_sweep(spins, spacing, par, r, u, eps)
             acc_n[0] += a
             ref_n[0] += rf
 
@@ -589,7 +598,8 @@ def bench_sampler(args) -> None:
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-mixed"}[prec], "data": "synthetic",
         "config": {"workload": args.workload + "_sampler", "N": N, "L": shape.L, "d": shape.d, "chains": B,
-                   "spacing": spacing, "eps": eps, "params": "stress draw", "step": "one sweep (both parities)"},
+                   "spacing": spacing, "eps": "adaptive eps(n), default 0.2, gamma 1.5" if args.eps_adaptive else eps,
+                   "params": "stress draw", "step": "one sweep (both parities)"},
         "acceptance": acc_tot / (props * args.steps), "refreshes_per_proposal": ref_tot / (props * args.steps),
         "roofline": {"kernel": dom, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
                      "frac": fl / (ms * 1e-3) / 1e12 / peak, "peak_basis": basis, "avg_launch_ms": ms / n},

@@ -156,6 +156,22 @@ dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spaci
                             const double* r_site, const double* u, double eps, int32_t* accepted,
                             int32_t* refreshes, void* stream);
 
+/* dn_screened_sweep with the practical tolerance schedule of App. "Practical implementation of
+ * the screened typewriter sampler": a proposal is screened with eps_buf[min(n, n_eps - 1)], n
+ * the flips accepted since the chain's current background. Every refresh records the frozen
+ * proposal's empirical error e~ = |min(1, R~) - min(1, R)| (R its exact ratio at the refreshed
+ * background) with the n at which the chain froze. After the half-sweep the events are applied
+ * to the buffer, chain by chain in chain order and in order within a chain: an entry whose
+ * eps_set flag is 0 (still at the caller's default) takes e~ and its flag becomes 1; any other
+ * becomes max(entry, gamma e~). eps_buf (device float64 [n_eps]) and eps_set (device int32
+ * [n_eps]) are the caller's, updated in place and shared by all chains of the call; the buffer
+ * is fixed while the half-sweep runs. gamma >= 1 (the paper takes gamma > 1). Other arguments,
+ * outputs and requirements as for dn_screened_sweep. */
+dn_status dn_screened_sweep_adaptive(dn_model* m, int8_t* spins, int32_t B, int32_t spacing, int32_t parity,
+                                     const double* r_site, const double* u, double* eps_buf, int32_t* eps_set,
+                                     int32_t n_eps, double gamma, int32_t* accepted, int32_t* refreshes,
+                                     void* stream);
+
 /* One stochastic-reconfiguration (natural-gradient) update of variational Monte Carlo (Sec. II
  * and VI; App. "Network parameters": standard SR with a diagonal shift). Inputs: the per-sample
  * log-derivatives O [B][P] as dn_grad_logpsi writes them (device, the model's field type: float

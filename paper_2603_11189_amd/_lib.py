@@ -26,8 +26,8 @@ EXPORTS = ("dn_param_count", "dn_model_create", "dn_set_workspace_limit", "dn_mo
            "dn_model_get_taps", "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
            "dn_local_energy_complex",
            "dn_eloc", "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-           "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable", "dn_profile_read",
-           "dn_last_error", "dn_model_destroy")
+           "dn_ragged_eloc", "dn_screened_sweep", "dn_screened_sweep_adaptive", "dn_sr_update", "dn_profile_enable",
+           "dn_profile_read", "dn_last_error", "dn_model_destroy")
 RAGGED_MODE = {"eager": 0, "graph": 1}
 PRODUCT_MODE = {"split3": 0, "fp32": 1}
 KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep", "slice", "tail", "gen",
@@ -82,6 +82,8 @@ def lib():
         L.dn_ragged_eloc.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(HamDesc), ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp]
         L.dn_screened_sweep.argtypes = [vp, vp, i32, i32, i32, vp, vp, ctypes.c_double, vp, vp, vp]
+        L.dn_screened_sweep_adaptive.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, i32, ctypes.c_double, vp,
+                                                 vp, vp]
         L.dn_sr_update.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, i32, ctypes.c_double, vp,
                                    vp, ctypes.POINTER(i32), vp]
         L.dn_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -94,8 +96,8 @@ def lib():
                    "dn_logpsi", "dn_logpsi_noalloc", "dn_connected", "dn_logratio", "dn_local_energy",
                    "dn_local_energy_complex", "dn_eloc",
                    "dn_grad_logpsi", "dn_autotune", "dn_set_launch_shapes", "dn_set_product_mode",
-                   "dn_ragged_eloc", "dn_screened_sweep", "dn_sr_update", "dn_profile_enable",
-                   "dn_profile_read"):
+                   "dn_ragged_eloc", "dn_screened_sweep", "dn_screened_sweep_adaptive", "dn_sr_update",
+                   "dn_profile_enable", "dn_profile_read"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -236,6 +238,24 @@ class Model:
         assert r.shape == (B, K) and uu.shape == (B, K)
         _check(lib().dn_screened_sweep(self.handle, _ptr(spins), B, spacing, parity, _ptr(r), _ptr(uu), eps,
                                        _ptr(acc), _ptr(ref), _stream()))
+        return acc, ref
+
+    def screened_sweep_adaptive(self, spins: torch.Tensor, spacing: int, parity: int, r_site: torch.Tensor,
+                                u: torch.Tensor, eps_buf: torch.Tensor, eps_set: torch.Tensor, gamma: float):
+        """dn_screened_sweep_adaptive: the half-sweep with the tolerance buffer eps_buf (float64)
+        and its flags eps_set (int32), both device tensors updated in place."""
+        B, N = spins.shape
+        K = ((N + spacing - 1) // spacing - parity + 1) // 2
+        acc = torch.zeros((B, K), dtype=torch.int32, device=spins.device)
+        ref = torch.zeros(B, dtype=torch.int32, device=spins.device)
+        r = r_site.to(torch.float64).contiguous()
+        uu = u.to(torch.float64).contiguous()
+        assert r.shape == (B, K) and uu.shape == (B, K)
+        assert eps_buf.dtype == torch.float64 and eps_set.dtype == torch.int32 and eps_buf.shape == eps_set.shape
+        assert eps_buf.is_contiguous() and eps_set.is_contiguous()
+        _check(lib().dn_screened_sweep_adaptive(self.handle, _ptr(spins), B, spacing, parity, _ptr(r), _ptr(uu),
+                                                _ptr(eps_buf), _ptr(eps_set), eps_buf.numel(), gamma, _ptr(acc),
+                                                _ptr(ref), _stream()))
         return acc, ref
 
     def sr_update(self, grads: torch.Tensor, eloc: torch.Tensor, weights: torch.Tensor | None = None,

@@ -1227,7 +1227,8 @@ template <typename T, int DP> struct RunFull {
 // acceptance per chain) until no chain froze; one host synchronisation per round.
 template <typename T, int DP> struct RunSweep {
   static dn_status run(dn_model* m, int8_t* spins, int B, int spacing, int parity, const double* r_site,
-                       const double* u, double eps, int32_t* accepted, int32_t* refreshes, hipStream_t st) {
+                       const double* u, double eps, int32_t* accepted, int32_t* refreshes, hipStream_t st,
+                       double* eps_buf = nullptr, int32_t* eps_set = nullptr, int n_eps = 0, double gamma = 1.0) {
     const int N = m->desc.N;
     const int nblk = (N + spacing - 1) / spacing;
     const int K = (nblk - parity + 1) / 2;
@@ -1248,6 +1249,17 @@ template <typename T, int DP> struct RunSweep {
     a.spins = spins; a.sites = (int32_t*)psi; a.sites_r = (int32_t*)psr; a.n_conn = (int32_t*)pnc;
     a.kstart = (int32_t*)pks; a.pending = (int32_t*)ppe; a.accepted = accepted; a.refreshes = refreshes;
     a.frozen = (int32_t*)pfr; a.dom = (double*)pdom; a.cplx = m->desc.complex_out;
+    if (eps_buf) {  // the tolerance buffer and this half-sweep's refresh events
+      void *pnf, *ppf, *pen, *pee, *pec;
+      STCHK(ws_get(m, "sw_nfrz", (size_t)B * 4, &pnf));
+      STCHK(ws_get(m, "sw_pfrz", (size_t)B * 8, &ppf));
+      STCHK(ws_get(m, "sw_evn", (size_t)B * K * 4, &pen));
+      STCHK(ws_get(m, "sw_eve", (size_t)B * K * 8, &pee));
+      STCHK(ws_get(m, "sw_evc", (size_t)B * 4, &pec));
+      a.eps_buf = eps_buf; a.n_eps = n_eps;
+      a.nfrz = (int32_t*)pnf; a.pfrz = (double*)ppf; a.ev_n = (int32_t*)pen; a.ev_e = (double*)pee;
+      a.ev_cnt = (int32_t*)pec;
+    }
     const int gs = (int)std::min<long>(4096, ((long)B * K + 255) / 256);
     sweep_init_kernel<<<gs, 256, 0, st>>>(a);
     HIPCHK(hipGetLastError());
@@ -1277,6 +1289,10 @@ template <typename T, int DP> struct RunSweep {
       HIPCHK(hipStreamSynchronize(st));
       if (!frozen) break;
       rows = frozen;  // the chains that froze are exactly those with proposals left
+    }
+    if (eps_buf) {
+      sweep_eps_kernel<<<1, 1, 0, st>>>(eps_buf, eps_set, n_eps, gamma, a.ev_n, a.ev_e, a.ev_cnt, B, K);
+      HIPCHK(hipGetLastError());
     }
     return abacus_check(m, st);
   }
@@ -1798,6 +1814,21 @@ dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spaci
   STCHK(abacus_supported(m));
   return dispatch<RunSweep>(m, spins, (int)B, (int)spacing, (int)parity, r_site, u, eps, accepted, refreshes,
                             (hipStream_t)stream);
+}
+
+dn_status dn_screened_sweep_adaptive(dn_model* m, int8_t* spins, int32_t B, int32_t spacing, int32_t parity,
+                                     const double* r_site, const double* u, double* eps_buf, int32_t* eps_set,
+                                     int32_t n_eps, double gamma, int32_t* accepted, int32_t* refreshes,
+                                     void* stream) {
+  if (!m) return fail(DN_EINVAL, "null model");
+  if (B < 0 || spacing < 1 || (parity != 0 && parity != 1) || n_eps < 1 || !(gamma >= 1.0) || !std::isfinite(gamma))
+    return fail(DN_EINVAL, "bad B, spacing, parity, n_eps or gamma");
+  if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
+  if (B == 0) return DN_OK;
+  if (!spins || !r_site || !u || !eps_buf || !eps_set || !accepted || !refreshes) return fail(DN_EINVAL, "null argument");
+  STCHK(abacus_supported(m));
+  return dispatch<RunSweep>(m, spins, (int)B, (int)spacing, (int)parity, r_site, u, 0.0, accepted, refreshes,
+                            (hipStream_t)stream, eps_buf, eps_set, (int)n_eps, gamma);
 }
 
 dn_status dn_sr_update(dn_model* m, const void* O, const double* eloc, const double* weights, int32_t B, double shift,

@@ -12,6 +12,11 @@
 // rebuilt at its current configuration and the remaining proposals' changes are recomputed;
 // the frozen proposal is then decided with its exact ratio. Otherwise accept iff u < P. When eps
 // bounds |R~ - R| the decisions are those of exact Metropolis-Hastings for the same draws.
+// The tolerance is one eps, or (the appendix's practical schedule) eps_buf[min(n, n_eps - 1)]
+// with n the flips accepted since the chain's current background. Each refresh then records the
+// event (n at the freeze, |min(1, R~) - min(1, R)|) with R the frozen proposal's exact ratio, and
+// after the half-sweep sweep_eps_kernel applies the events, chain by chain in chain order, to
+// the buffer: an entry still at its default takes the error, any other max(entry, gamma error).
 #pragma once
 #include "common.h"
 
@@ -36,6 +41,13 @@ struct SweepArgs {
   const double* Om0;     // [rows][2] output of this round's background
   const double* dom;     // [rows][K][2] this round's changes (index k - kstart)
   int cplx;              // 1: complex read-out unit (|psi|^2 decides: the ratio's real part)
+  const double* eps_buf;  // nullable: tolerance buffer [n_eps] indexed by n (else eps)
+  int n_eps;
+  int32_t* nfrz;          // [B] n when the chain froze
+  double* pfrz;           // [B] min(1, R~) of the proposal that froze it
+  int32_t* ev_n;          // [B][K] refresh events of this half-sweep: n
+  double* ev_e;           // [B][K] and the empirical error
+  int32_t* ev_cnt;        // [B]
 };
 
 // Proposals of the half-sweep and the initial state of every chain.
@@ -48,7 +60,12 @@ __global__ void sweep_init_kernel(SweepArgs a) {
     a.sites[2 * i] = lo + max(off, 0);
     a.sites[2 * i + 1] = -1;
     a.accepted[i] = 0;
-    if (k == 0) { a.kstart[b] = 0; a.pending[b] = 0; a.refreshes[b] = 0; }
+    if (k == 0) {
+      a.kstart[b] = 0;
+      a.pending[b] = 0;
+      a.refreshes[b] = 0;
+      if (a.eps_buf) a.ev_cnt[b] = 0;
+    }
   }
 }
 
@@ -100,17 +117,31 @@ __global__ void sweep_accept_kernel(SweepArgs a) {
   if (k0 >= a.K) return;
   double om0 = a.Om0[2 * row], om1 = a.Om0[2 * row + 1];
   const bool exact_first = a.pending[b] != 0;
+  int n = 0;  // flips accepted since this round's background
   for (int k = k0; k < a.K; ++k) {
     const long o = (long)row * a.K + (k - k0);
     const double d0 = a.dom[2 * o], d1 = a.dom[2 * o + 1];
     const double P = fmin(1.0, exp(2.0 * ratio_re(om0, om1, d0, d1, a.cplx)));
     const double uu = a.u[(long)b * a.K + k];
-    if (!(exact_first && k == k0) && fabs(uu - P) <= a.eps) {
-      a.kstart[b] = k;
-      a.pending[b] = 1;
-      a.refreshes[b] += 1;
-      atomicAdd(a.frozen, 1);
-      return;
+    if (exact_first && k == k0) {
+      if (a.eps_buf) {  // the frozen proposal's exact probability against the approximate one
+        const int e = a.ev_cnt[b]++;
+        a.ev_n[(long)b * a.K + e] = a.nfrz[b];
+        a.ev_e[(long)b * a.K + e] = fabs(a.pfrz[b] - P);
+      }
+    } else {
+      const double tol = a.eps_buf ? a.eps_buf[min(n, a.n_eps - 1)] : a.eps;
+      if (fabs(uu - P) <= tol) {
+        a.kstart[b] = k;
+        a.pending[b] = 1;
+        a.refreshes[b] += 1;
+        if (a.eps_buf) {
+          a.nfrz[b] = n;
+          a.pfrz[b] = P;
+        }
+        atomicAdd(a.frozen, 1);
+        return;
+      }
     }
     if (uu < P) {
       a.accepted[(long)b * a.K + k] = 1;
@@ -118,10 +149,30 @@ __global__ void sweep_accept_kernel(SweepArgs a) {
       a.spins[(long)b * a.N + j] = (int8_t)(-a.spins[(long)b * a.N + j]);
       om0 += d0;
       om1 += d1;
+      ++n;
     }
   }
   a.kstart[b] = a.K;
   a.pending[b] = 0;
+}
+
+// The half-sweep's refresh events applied to the tolerance buffer in chain order (one thread:
+// a few events per chain, and the order fixes the result).
+__global__ void sweep_eps_kernel(double* __restrict__ eps_buf, int32_t* __restrict__ eps_set, int n_eps,
+                                 double gamma, const int32_t* __restrict__ ev_n, const double* __restrict__ ev_e,
+                                 const int32_t* __restrict__ ev_cnt, int B, int K) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int b = 0; b < B; ++b)
+    for (int e = 0; e < ev_cnt[b]; ++e) {
+      const int i = min(ev_n[(long)b * K + e], n_eps - 1);
+      const double err = ev_e[(long)b * K + e];
+      if (!eps_set[i]) {
+        eps_buf[i] = err;
+        eps_set[i] = 1;
+      } else {
+        eps_buf[i] = fmax(eps_buf[i], gamma * err);
+      }
+    }
 }
 
 }  // namespace dn

@@ -17,7 +17,7 @@ import torch
 
 import dn_inputs as di
 from oracle.model import ModelDesc
-from oracle.sampler import exact_mh_sweep, screened_sweep, typewriter_sites
+from oracle.sampler import exact_mh_sweep, screened_sweep, typewriter_sites, update_eps_buffer
 
 pytestmark = pytest.mark.gpu
 
@@ -103,4 +103,53 @@ def test_sweep_argument_errors(L):
                 L._check(L.lib().dn_screened_sweep(m.handle, L._ptr(sp), 2, spacing, parity, L._ptr(r), L._ptr(r),
                                                    eps, L._ptr(r), L._ptr(r), None))
         assert ei.value.status == L.DN_EINVAL
+    m.close()
+
+
+@pytest.mark.parametrize("shape,spacing,prec", [
+    (di.ModelShape(16, 2, 4, 3, act="silu", bc="open"), 1, "fp64"),
+    (di.ModelShape(15, 2, 3, 2, act="silu", bc="periodic"), 2, "fp64"),
+    (di.ModelShape(14, 3, 3, 2, act="tanh", bc="open"), 1, "fp64"),
+], ids=lambda x: str(x)[:40])
+def test_adaptive_sweep_matches_oracle(L, shape, spacing, prec):
+    """The tolerance buffer eps(n) (App. "Practical implementation of the screened typewriter
+    sampler"): decisions, refresh counts and configurations equal the oracle's after every
+    half-sweep, and so does the buffer (its flags exactly, its values to 1e-12 absolute: the
+    errors are differences of float64 acceptance probabilities formed on both sides)."""
+    desc = ModelDesc.of(shape)
+    th = _peaked(shape, 17)
+    m = L.Model(shape, prec)
+    m.set_params(th)
+    B, n_eps, gamma, default = 4, 5, 1.5, 0.2
+    spins = torch.tensor(di.uniform_spins(B, shape.N, 4), device="cuda")
+    host = [spins[b].cpu().long() for b in range(B)]
+    buf = torch.full((n_eps,), default, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(n_eps, dtype=torch.int32, device="cuda")
+    hbuf, hset = [default] * n_eps, [False] * n_eps
+    refr = []
+    for sweep in range(6):
+        parity = sweep % 2
+        K = len(range(parity, (shape.N + spacing - 1) // spacing, 2))
+        rng = np.random.Generator(np.random.PCG64(930 + sweep))
+        r, u = rng.random((B, K)), rng.random((B, K))
+        acc, ref = m.screened_sweep_adaptive(spins, spacing, parity, torch.tensor(r, device="cuda"),
+                                             torch.tensor(u, device="cuda"), buf, flag, gamma)
+        acc, ref = acc.cpu(), ref.cpu()
+        events, total = [], 0
+        for b in range(B):
+            sites = typewriter_sites(shape.N, spacing, parity, r[b])
+            want = screened_sweep(desc, th, host[b], sites, u[b], 0.0, eps_buf=list(hbuf))
+            assert acc[b].tolist() == [int(x) for x in want["accepted"]], (sweep, b)
+            assert int(ref[b]) == want["refreshes"], (sweep, b)
+            host[b] = want["spins"]
+            events += want["events"]
+            total += want["refreshes"]
+        update_eps_buffer(hbuf, hset, events, gamma)
+        assert torch.equal(spins.cpu().long(), torch.stack(host)), sweep
+        assert flag.cpu().tolist() == [int(x) for x in hset], sweep
+        assert (buf.cpu() - torch.tensor(hbuf, dtype=torch.float64)).abs().max().item() <= 1e-12, sweep
+        refr.append(total)
+    _say(f"adaptive sampler N={shape.N} L={shape.L}: refreshes per half-sweep {refr}, "
+         f"buffer {[round(x, 4) for x in hbuf]}")
+    assert any(hset)
     m.close()
