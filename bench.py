@@ -239,6 +239,8 @@ def main():
                     help="autotune the launch shapes of the measured model first (default: the library's "
                          "default shapes, so that repeated runs and their profiles use the same launches)")
     ap.add_argument("--shapes", default="", help="CONV_NT,FLIP_MIB: set launch shapes instead of tuning")
+    ap.add_argument("--flip-mib", type=int, default=16384,
+                    help="without --shapes or --tune: HBM budget of the per-flip fields of one chunk (MiB)")
     ap.add_argument("--products", default="split3", choices=["split3", "fp32"],
                     help="float matrix-core products: three-term bf16 splits (default) or float32 matrix cores")
     ap.add_argument("--sampler", action="store_true",
@@ -330,6 +332,11 @@ def main():
         tuned = {"conv_tiles_per_wave": nt, "flip_chunk_MiB": bud >> 20,
                  "tuning_s": round(time.perf_counter() - t0, 3)}
         log(f"[bench] autotuned launch shapes: {tuned}")
+    else:
+        # one model holds the GPU: its flip fields may take a larger share of HBM than the
+        # library's default (sized for many models side by side)
+        model.set_launch_shapes(0, args.flip_mib << 20)
+        tuned = {"flip_chunk_MiB": args.flip_mib, "set_by": "--flip-mib"}
     results = {}
     for path in args.paths.split(","):
         log(f"[bench] {args.workload} path={path} warmup={args.warmup}")
