@@ -23,7 +23,7 @@ BCS = ("open", "periodic")
 class ModelShape:
     """Hyper-parameters of one DysonNet (names follow the paper's notation)."""
 
-    N: int            # chain length
+    N: int            # chain length in tokens (network sites); the chain holds N * token spins
     L: int            # number of DysonNet blocks
     d: int            # embedding (channel) dimension
     s: int            # S4 state size per channel
@@ -33,10 +33,15 @@ class ModelShape:
     act: str = "silu"  # local nonlinearity g: "silu" | "tanh" | "identity"
     inject_phi: int = 0  # 1: add phi^(l) to the h stream before the mixer (Fig. 1c form)
     complex_out: int = 0  # 1: complex read-out matrix A (column pairs as real and imaginary parts)
+    token: int = 1    # spins per token (patching): token tau embeds spins token*tau .. token*tau + token - 1
 
     def __post_init__(self):
         assert self.act in ACTS and self.bc in BCS
-        assert self.N >= 1 and self.L >= 1 and self.d >= 1 and self.s >= 1
+        assert self.N >= 1 and self.L >= 1 and self.d >= 1 and self.s >= 1 and self.token >= 1
+
+    @property
+    def n_spins(self) -> int:
+        return self.N * self.token
 
 
 @dataclasses.dataclass(frozen=True)
@@ -63,7 +68,7 @@ class HamSpec:
 def param_blocks(m: ModelShape) -> List[Tuple[str, int, float]]:
     """(name, length, stress-draw std) for every block of the flat parameter vector.
 
-    Order: E[d], E_phi[d];
+    Order: E[token, d], E_phi[token, d] (one embedding vector per position inside a token);
       per block l=1..L: W_D[d,d], w[d], K[2w_c+1,d], k[d], A_D[d,d], b[d], U[d,d], V[d,d];
       per mixer (blocks 1..L, then the final mixer f), per channel c:
         Lambda_re-raw[s], Lambda_im[s], p_re[s], p_im[s], q_re[s], q_im[s],
@@ -73,7 +78,8 @@ def param_blocks(m: ModelShape) -> List[Tuple[str, int, float]]:
     """
     d, s, Wc = m.d, m.s, 2 * m.w_c + 1
     rd = 1.0 / math.sqrt(d)
-    out = [("E", d, 1.0), ("E_phi", d, 1.0)]
+    te = 1.0 / math.sqrt(m.token)  # a token sums `token` embedded spins
+    out = [("E", m.token * d, te), ("E_phi", m.token * d, te)]
     for l in range(m.L):
         out += [
             (f"W_D{l}", d * d, rd), (f"w{l}", d, 0.5), (f"K{l}", Wc * d, 1.0 / math.sqrt(Wc)),

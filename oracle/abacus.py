@@ -104,8 +104,9 @@ def output_links(desc, ops) -> List[torch.Tensor]:
 def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = False):
     """log psi(s')/psi(s) for every listed cluster update by the ABACUS recurrence.
 
-    For each sample: materialise background operators; for each cluster C:
-      e^(0) = E (s' - s) on C;
+    For each sample: materialise background operators; for each cluster C (the tokens of the
+    flipped spins):
+      e^(0) = E (s' - s) on C (each flipped spin through the embedding of its token position);
       for l = 1..L:  x^(l) = P_S v0^(l) + sum_{m<l} P_{S_l} G^(l) X_{m+1..l-1} z^(m)
                      e^(l) = Delta-D^(l) x^(l) on S_l,  Delta-D_i = U diag(chi'_i - chi0_i) V
       dOmega = A^T P_omega sum_l e^(l) + sum_m T~^(m) z^(m)
@@ -115,7 +116,7 @@ def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = Fals
     """
     theta = torch.as_tensor(theta, dtype=DT)
     s = torch.as_tensor(spins).to(torch.int64)
-    B, N = s.shape
+    B, N = s.shape[0], desc.N   # N tokens (N * token spins)
     M = sites.shape[1]
     d, L, wc = desc.d, desc.L, desc.w_c
     out = torch.zeros(B, M, dtype=CT if desc.complex_out else DT)
@@ -130,9 +131,10 @@ def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = Fals
             for m in range(0, l):
                 Y[(l, m)] = ops["G"][l - 1] @ chain(ops, m + 1, l - 1)
         for mi in range(int(n_conn[b])):
-            C = [int(x) for x in sites[b, mi] if int(x) >= 0]
+            flips = [int(x) for x in sites[b, mi] if int(x) >= 0]   # spin indices
+            C = sorted({j // desc.token for j in flips})            # the cluster, in tokens
             sp = s[b].clone()
-            for j in C:
+            for j in flips:
                 sp[j] = -sp[j]
             fw1 = forward(desc, theta, sp[None], cache=True, T=ops["T"])
             S = [_slice(desc, C, l * wc) for l in range(L + 1)]
@@ -144,8 +146,8 @@ def abacus_logratio(desc, theta, spins, sites, n_conn, return_parts: bool = Fals
                     assert dchi[l - 1][outside].abs().max() <= 1e-13, "vertex change leaks"
                     assert dphi[l][outside].abs().max() <= 1e-13, "phi change leaks"
             e = [torch.zeros(N, d, dtype=DT) for _ in range(L + 1)]
-            for j in C:
-                e[0][j] = prm["E"] * float(sp[j] - s[b, j])
+            for j in flips:
+                e[0][j // desc.token] += prm["E"][j % desc.token] * float(sp[j] - s[b, j])
             z, zs = [], []
             for l in range(1, L + 1):
                 z.append(e[l - 1] + (dphi[l] if desc.inject_phi else 0.0))

@@ -27,7 +27,11 @@ Readings of the paper used here (each listed in the design doc):
     there are d_out/2 complex units and log psi = sum_j logcosh(Omega_2j + i Omega_2j+1)
     is complex; its imaginary part (the phase) is reported in (-pi, pi];
   * inject_phi adds phi^(l) to the h stream before the mixer (Fig. 1c); the residual
-    sum holds only the h stream.
+    sum holds only the h stream;
+  * token size t (patching, Sec. V on the efficiency trade-off): the network runs on N tokens,
+    token tau holding the spins t tau .. t tau + t - 1, embedded as h^(0)_tau = sum_k E_k s_(t tau + k)
+    and phi^(0)_tau = sum_k E_phi,k s_(t tau + k) (one embedding vector per position k inside a
+    token; t = 1 is the per-site embedding).
 """
 from __future__ import annotations
 
@@ -53,11 +57,13 @@ class ModelDesc:
     act: str = "silu"
     inject_phi: int = 0
     complex_out: int = 0
+    token: int = 1
 
     @staticmethod
     def of(shape) -> "ModelDesc":
         return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c,
-                         shape.bc, shape.act, shape.inject_phi, getattr(shape, "complex_out", 0))
+                         shape.bc, shape.act, shape.inject_phi, getattr(shape, "complex_out", 0),
+                         getattr(shape, "token", 1))
 
 
 def act(name: str, x: torch.Tensor) -> torch.Tensor:
@@ -84,7 +90,7 @@ def unpack(desc: ModelDesc, theta: torch.Tensor) -> Dict:
         pos[0] += n
         return t
 
-    prm = {"E": take(d), "E_phi": take(d), "layers": [], "s4": []}
+    prm = {"E": take(desc.token, d), "E_phi": take(desc.token, d), "layers": [], "s4": []}
     for _ in range(L):
         prm["layers"].append({
             "W_D": take(d, d), "w": take(d), "K": take(Wc, d), "k": take(d),
@@ -305,7 +311,7 @@ def mixers(desc: ModelDesc, prm: Dict, check_stable: bool = True) -> List[torch.
 def forward(desc: ModelDesc, theta: torch.Tensor, spins, cache: bool = False, T=None):
     """Evaluate the network on a batch of configurations (Sec. II, Eq. (wavefunc)).
 
-    phi^(0) = E_phi s, h^(0) = E s; for each block l:
+    phi^(0) = E_phi s, h^(0) = E s (per token: sum_k E_k s_(t tau + k)); for each block l:
       a = W_D phi + w,  phi <- g(sum_r K_r * a_{i+r} + k)          (phi-stream CNN)
       chi = g(A_D phi + b)                                          (Eq. (Dpractical))
       v = G^(l) u with u = h (+ phi if inject_phi)                   (Green's-function mixer)
@@ -323,8 +329,9 @@ def forward(desc: ModelDesc, theta: torch.Tensor, spins, cache: bool = False, T=
         s = s[None]
     N = desc.N
     g = lambda x: act(desc.act, x)  # noqa: E731
-    phi = s[..., None] * prm["E_phi"]
-    h = s[..., None] * prm["E"]
+    st = s.reshape(s.shape[0], N, desc.token)         # [B, token index, position in the token]
+    phi = st @ prm["E_phi"]
+    h = st @ prm["E"]
     R = h
     out = {"h": [h], "phi": [phi], "a": [], "chi": [], "v": [], "u": []}
     for l, lay in enumerate(prm["layers"]):

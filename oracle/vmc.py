@@ -67,7 +67,7 @@ def all_configs(N: int) -> torch.Tensor:
 def exact_energy(desc, ham, theta) -> float:
     """<psi|H|psi> / <psi|psi> by enumeration: sum_s |psi(s)|^2 E_loc(s) / sum_s |psi(s)|^2."""
     theta = torch.as_tensor(theta, dtype=DT)
-    s = all_configs(desc.N)
+    s = all_configs(desc.N * desc.token)
     sites, helem, n_conn, hdiag = connected(ham, s)
     lp, lr = plain_logratio(desc, theta, s, sites, n_conn)
     el = local_energy(hdiag, helem, n_conn, lr)
@@ -85,7 +85,7 @@ def exact_weights(desc, theta, s) -> torch.Tensor:
 def exact_sr_inputs(desc, ham, theta):
     """(configurations, weights, O, E_loc) of exact enumeration."""
     theta = torch.as_tensor(theta, dtype=DT)
-    s = all_configs(desc.N)
+    s = all_configs(desc.N * desc.token)
     sites, helem, n_conn, hdiag = connected(ham, s)
     _, lr = plain_logratio(desc, theta, s, sites, n_conn)
     el = local_energy(hdiag, helem, n_conn, lr)
