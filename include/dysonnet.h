@@ -69,18 +69,22 @@ typedef enum { DN_PREC_FP64 = 0, DN_PREC_FP32 = 1, DN_PREC_BF16_MIXED = 2 } dn_p
 typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
 
 /* Network hyper-parameters (Sec. II; App. "Details on the implementation ...").
- * N chain length; L blocks; d channels (d <= 64); s S4 state size (s <= 32);
+ * N chain length in tokens (network sites); L blocks; d channels (d <= 64); s S4 state size (s <= 32);
  * d_out log-cosh read-out units (must be 2); w_c half-width of the phi-stream CNN
  * (0..3); bc network boundary condition (dn_bc); act local nonlinearity g (dn_act);
  * inject_phi 1 adds phi^(l) to the h stream before each mixer (Fig. 1c form);
  * prec arithmetic (dn_prec); complex_out 1 makes the read-out matrix A complex (Sec. II: a
  * complex A gives a complex wavefunction): its two columns are Re A and Im A, the two
  * pre-activations form one complex unit Omega = Omega_0 + i Omega_1 and
- * log psi = log cosh(Omega) is complex (0: two real units, log psi = sum_k log cosh Omega_k). */
+ * log psi = log cosh(Omega) is complex (0: two real units, log psi = sum_k log cosh Omega_k);
+ * token spins per token (patching, Sec. V; 0 or 1 = one spin per site, at most 4): token tau
+ * holds spins token*tau .. token*tau + token - 1 and is embedded as sum_k E_k s_(token*tau + k),
+ * likewise the phi stream with E_phi,k. Spin arrays then hold N * token spins per sample and
+ * sites index spins; a flip changes one token, a pair exchange one token or two. */
 typedef struct {
   int32_t N, L, d, s, d_out, w_c;
   int32_t bc, act, inject_phi, prec;
-  int32_t complex_out;
+  int32_t complex_out, token;
 } dn_model_desc;
 
 typedef enum { DN_H_LRTFIM = 0, DN_H_J1J2 = 1 } dn_ham_kind;
@@ -103,7 +107,7 @@ typedef struct {
 typedef struct dn_model dn_model; /* opaque */
 
 /* Length of the flat float64 parameter vector for this shape (-1 if the shape is
- * invalid). Order: E[d], E_phi[d]; per block: W_D[d,d], w[d], K[2w_c+1,d], k[d],
+ * invalid). Order: E[token][d], E_phi[token][d]; per block: W_D[d,d], w[d], K[2w_c+1,d], k[d],
  * A_D[d,d], b[d], U[d,d], V[d,d]; per mixer (blocks 1..L then the final mixer), per
  * channel: 12 vectors of length s (Lambda raw real part, Lambda imaginary part, p re/im,
  * q re/im, B re/im, C+ re/im, C- re/im) and one step offset; A[d, d_out]. Matrices are

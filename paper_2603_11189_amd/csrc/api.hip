@@ -64,7 +64,7 @@ struct Layout {
 bool layout_of(const dn_model_desc& d, Layout* lo) {
   if (d.N < 1 || d.L < 1 || d.d < 1 || d.s < 1 || d.d_out < 1 || d.w_c < 0) return false;
   const long dd = d.d, Wc = 2 * d.w_c + 1;
-  lo->off_layers = 2 * dd;
+  lo->off_layers = 2 * dd * (d.token > 1 ? d.token : 1);  // E, E_phi: one vector per token position
   const long lay = 4 * dd * dd + 3 * dd + Wc * dd;
   lo->off_s4 = lo->off_layers + d.L * lay;
   lo->off_A = lo->off_s4 + (long)(d.L + 1) * dd * (12L * d.s + 1);
@@ -225,13 +225,14 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
     *p = (T*)q;
     return true;
   };
-  bool ok = get(&tb.E, DP) && get(&tb.Ephi, DP) && get(&tb.wE1, DP) && get(&tb.WDt, L * DP * DP) &&
+  const int tk = m.desc.token;
+  bool ok = get(&tb.E, tk * DP) && get(&tb.Ephi, tk * DP) && get(&tb.wE1, tk * DP) && get(&tb.WDt, L * DP * DP) &&
             get(&tb.ADt, L * DP * DP) && get(&tb.Ut, L * DP * DP) && get(&tb.Vt, L * DP * DP) &&
             get(&tb.Um, L * DP * DP) && get(&tb.Vm, L * DP * DP) && get(&tb.wv, L * DP) &&
             get(&tb.Kc, L * Wc * DP) && get(&tb.kv, L * DP) && get(&tb.bv, L * DP) &&
             get(&tb.taps, L * DP * tap_stride(Np)) && get(&tb.tapsR, L * DP * tap_stride(Np)) &&
             get(&tb.Wk, 2 * DP * Np) && get(&tb.ADm, L * DP * DP) && get(&tb.WDm, L * DP * DP) &&
-            get(&tb.Pq, 4 * DP * tap_stride(Np)) && get(&tb.omN, DP * Np) && get(&tb.Ac, 2 * DP);
+            get(&tb.Pq, tk * 4 * DP * tap_stride(Np)) && get(&tb.omN, DP * Np) && get(&tb.Ac, 2 * DP);
   if (!ok) return fail(DN_ENOMEM, "hipMalloc failed for parameter tables");
   tb.tb = Tables<T>{tb.E, tb.Ephi, tb.wE1, tb.WDt, tb.ADt, tb.Ut, tb.Vt, tb.Um, tb.Vm,
                     tb.wv, tb.Kc, tb.kv, tb.bv, tb.taps, tb.tapsR, tb.Wk, tb.ADm, tb.WDm, tb.Pq, tb.omN, tb.Ac};
@@ -239,22 +240,23 @@ template <typename T> dn_status alloc_tables(TableBufs<T>& tb, const dn_model& m
 }
 
 long table_elems(const dn_model& m) {
-  const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc;
-  return 3 * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + (2 * L + 4) * DP * tap_stride(Np) + 2 * DP * Np;
+  const long DP = m.DP, Np = m.Np, L = m.desc.L, Wc = m.Wc, tk = m.desc.token;
+  return 3 * tk * DP + 8 * L * DP * DP + 3 * L * DP + L * Wc * DP + (2 * L + 4 * tk) * DP * tap_stride(Np) +
+         2 * DP * Np;
 }
 
 // Copy double tables into float tables (same member order).
 dn_status convert_tables(dn_model* m, hipStream_t st) {
   TableBufs<double>& a = m->t64;
   TableBufs<float>& b = m->t32;
-  const long DP = m->DP, Np = m->Np, L = m->desc.L, Wc = m->Wc;
+  const long DP = m->DP, Np = m->Np, L = m->desc.L, Wc = m->Wc, tk = m->desc.token;
   struct P { double* s; float* d; long n; } items[] = {
-      {a.E, b.E, DP}, {a.Ephi, b.Ephi, DP}, {a.wE1, b.wE1, DP}, {a.WDt, b.WDt, L * DP * DP},
+      {a.E, b.E, tk * DP}, {a.Ephi, b.Ephi, tk * DP}, {a.wE1, b.wE1, tk * DP}, {a.WDt, b.WDt, L * DP * DP},
       {a.ADt, b.ADt, L * DP * DP}, {a.Ut, b.Ut, L * DP * DP}, {a.Vt, b.Vt, L * DP * DP},
       {a.Um, b.Um, L * DP * DP}, {a.Vm, b.Vm, L * DP * DP}, {a.wv, b.wv, L * DP},
       {a.Kc, b.Kc, L * Wc * DP}, {a.kv, b.kv, L * DP}, {a.bv, b.bv, L * DP},
       {a.taps, b.taps, L * DP * tap_stride(Np)}, {a.tapsR, b.tapsR, L * DP * tap_stride(Np)}, {a.Wk, b.Wk, 2 * DP * Np},
-      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, 4 * DP * tap_stride(Np)},
+      {a.ADm, b.ADm, L * DP * DP}, {a.WDm, b.WDm, L * DP * DP}, {a.Pq, b.Pq, tk * 4 * DP * tap_stride(Np)},
       {a.omN, b.omN, DP * Np}, {a.Ac, b.Ac, 2 * DP}};
   for (auto& it : items) {
     int grid = (int)std::min<long>(1024, (it.n + 255) / 256);
@@ -357,7 +359,9 @@ template <typename T, int DP, int NT> void phi_go(const PhiArgs<T>& a, int C, si
 
 template <typename T, int DP> dn_status launch_phi(dn_model* m, const PhiArgs<T>& a, int C, hipStream_t st) {
   if (C <= 0) return DN_OK;
-  const size_t lds = ((size_t)DP * (m->Np + 2 * m->desc.w_c + 1) + m->Np + (2 * m->desc.w_c + 2) * DP) * sizeof(T);
+  const size_t lds =
+      ((size_t)DP * (m->Np + 2 * m->desc.w_c + 1) + (size_t)m->desc.token * m->Np + (2 * m->desc.w_c + 2) * DP) *
+      sizeof(T);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "phi stream tile exceeds LDS");
   const double Nr = m->desc.N, dr = m->desc.d, e = sizeof(T);
   const double nfield = (a.first ? 0 : 1) + (a.phi_out ? 1 : 0) + 1 + (a.a_out ? 1 : 0) + (a.first ? 1 : 0);
@@ -519,7 +523,7 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
   auto phi_pass = [&](int l) -> dn_status {
     PhiArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.w_c = d.w_c; a.periodic = d.bc == DN_BC_PERIODIC;
-    a.act = d.act; a.inject = d.inject_phi; a.first = (l == 0); a.spins = spins; a.map = map;
+    a.act = d.act; a.inject = d.inject_phi; a.first = (l == 0); a.spins = spins; a.map = map; a.tok = d.token;
     a.cfg0 = cfg0; a.C = C; a.phi_in = phi;
     a.phi_out = (l + 1 < L || d.inject_phi) ? phi : nullptr;
     a.chi_out = chi_of(l);
@@ -558,7 +562,8 @@ dn_status plan_launch(dn_model* m, const int32_t* n_conn, const int32_t* sites, 
   *offs = (int32_t*)po; *cb = (int32_t*)pb; *cm = (int32_t*)pm;
   plan_kernel<<<1, 1024, 0, st>>>(n_conn, B, M_max, with_base, *offs);
   const long slots = (long)B * (M_max + with_base);
-  plan_fill_kernel<<<(int)std::min<long>(4096, (slots + 255) / 256), 256, 0, st>>>(n_conn, sites, B, m->desc.N, M_max,
+  plan_fill_kernel<<<(int)std::min<long>(4096, (slots + 255) / 256), 256, 0, st>>>(n_conn, sites, B,
+                                                                                  m->desc.N * m->desc.token, M_max,
                                                                                   with_base, *offs, *cb, *cm);
   HIPCHK(hipGetLastError());
   return DN_OK;
@@ -579,7 +584,7 @@ dn_status plan(dn_model* m, const int32_t* n_conn, const int32_t* sites, int B, 
                hipStream_t st, const int8_t* spins = nullptr) {
   STCHK(plan_launch(m, n_conn, sites, B, M_max, with_base, offs, cb, cm, upper, st));
   if (spins) {
-    const long n = (long)B * m->desc.N;
+    const long n = (long)B * m->desc.N * m->desc.token;
     spin_check_kernel<<<(int)std::min<long>(1024, (n + 1023) / 1024), 256, 0, st>>>(spins, n, *offs + B + 1);
     HIPCHK(hipGetLastError());
   }
@@ -640,7 +645,8 @@ dn_status build_lam_tables(dn_model* m, hipStream_t st) {
   int logn = 1;
   while ((1 << logn) < 2 * d.N - 1) ++logn;
   const int nd = lam_nd(d.w_c, 2), n = 1 << logn, nh = n / 2 + 1;
-  const size_t elems = (size_t)nd * nh * m->DP * m->DP;
+  const size_t per_k = (size_t)nd * nh * m->DP * m->DP;  // one position inside a token
+  const size_t elems = per_k * d.token;
   if (!m->lamM64r) {
     void *a = nullptr, *b = nullptr;
     if (hipMalloc(&a, elems * 8) != hipSuccess || hipMalloc(&b, elems * 8) != hipSuccess) {
@@ -666,15 +672,15 @@ dn_status build_lam_tables(dn_model* m, hipStream_t st) {
   m->lam_logn = logn;
   m->lam_nd = nd;
   m->lam_dlo = -(2 * d.w_c + 2);
-  LamParamArgs a{};
-  a.taps = m->t64.taps; a.Pq = m->t64.Pq; a.Ut = m->t64.Ut;
-  a.N = d.N; a.Np = m->Np; a.d = d.d; a.DP = m->DP; a.logn = logn; a.ND = nd; a.dlo = m->lam_dlo;
-  a.periodic = d.bc == DN_BC_PERIODIC; a.Mr = m->lamM64r; a.Mi = m->lamM64i;
   const int nseq = std::max(1, std::min(m->DP, 4096 >> logn));
   const size_t lds = ((size_t)2 * nseq * (n + 1) + n) * sizeof(double);
-  {
-    PScope ps(m, DN_K_PREP, st, 5.0 * n * logn * (double)nd * m->DP * m->DP, (double)elems * 16);
-    allow_lds(lam_param_kernel, lds);
+  allow_lds(lam_param_kernel, lds);
+  for (int k = 0; k < d.token; ++k) {  // the composite spectra of each position's unit flip
+    LamParamArgs a{};
+    a.taps = m->t64.taps; a.Pq = m->t64.Pq + (long)k * 4 * m->DP * tap_stride(m->Np); a.Ut = m->t64.Ut;
+    a.N = d.N; a.Np = m->Np; a.d = d.d; a.DP = m->DP; a.logn = logn; a.ND = nd; a.dlo = m->lam_dlo;
+    a.periodic = d.bc == DN_BC_PERIODIC; a.Mr = m->lamM64r + k * per_k; a.Mi = m->lamM64i + k * per_k;
+    PScope ps(m, DN_K_PREP, st, 5.0 * n * logn * (double)nd * m->DP * m->DP, (double)per_k * 16);
     lam_param_kernel<<<dim3(nd, m->DP), 256, lds, st>>>(a);
   }
   HIPCHK(hipGetLastError());
@@ -713,8 +719,10 @@ dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam,
   STCHK(ws_get(m, "lam_Xi", nx * sizeof(T), &pxi));
   STCHK(ws_get(m, "lam_Zr", nz * sizeof(T), &pzr));
   STCHK(ws_get(m, "lam_Zi", nz * sizeof(T), &pzi));
-  const T *Mr, *Mi;
-  lam_spectra<T>(m, &Mr, &Mi);
+  const T *Mr0, *Mi0;
+  lam_spectra<T>(m, &Mr0, &Mi0);
+  const size_t per_k = (size_t)m->lam_nd * nh * DP * DP;  // spectra of one position in a token
+  const long lamk = (long)Bf * d.N * ND * DP;             // links of one position
   const int chf = lam_chf(DP, logn, sizeof(T));
   const size_t lds_t = ((size_t)chf * (n + 1) + n) * sizeof(T);
   const size_t lds_g = ((size_t)2 * DP * 65 + 2 * DP * DP) * sizeof(T);
@@ -728,12 +736,14 @@ dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam,
     a.N = d.N; a.Np = m->Np; a.DP = DP; a.logn = logn; a.ND = ND; a.periodic = d.bc == DN_BC_PERIODIC;
     a.di0 = dlo - m->lam_dlo; a.Bc = Bs; a.chf = chf;
     a.chi1 = chi1 + (long)s0 * DP * m->Np;
-    a.Xr = (T*)pxr; a.Xi = (T*)pxi; a.Mr = Mr; a.Mi = Mi; a.Zr = (T*)pzr; a.Zi = (T*)pzi;
-    a.lam = lam + (long)s0 * d.N * ND * DP;
+    a.Xr = (T*)pxr; a.Xi = (T*)pxi; a.Zr = (T*)pzr; a.Zi = (T*)pzi;
     {
       PScope ps(m, DN_K_LINK, st, Bs * (dr / 2) * fft, (double)Bs * (d.N * dr + 2.0 * nh * dr) * sizeof(T));
       lam_fwd_kernel<T><<<dim3(Bs, DP / chf), 256, lds_t, st>>>(a);
     }
+    for (int k = 0; k < d.token; ++k) {  // the spectra of chi0 serve every position's link
+    a.Mr = Mr0 + k * per_k; a.Mi = Mi0 + k * per_k;
+    a.lam = lam + k * lamk + (long)s0 * d.N * ND * DP;
     {
       PScope ps(m, DN_K_LINK, st, 8.0 * ND * nh * dr * dr * Bs,
                 (double)(2.0 * nh * dr * Bs + 2.0 * ND * nh * dr * dr + 2.0 * ND * nh * dr * Bs) * sizeof(T));
@@ -743,6 +753,7 @@ dn_status build_lam(dn_model* m, const T* chi1, int Bf, int ND, int dlo, T* lam,
       PScope ps(m, DN_K_LINK, st, (double)Bs * ND * (dr / 2) * fft,
                 (double)Bs * ND * (2.0 * nh * dr + d.N * dr) * sizeof(T));
       lam_inv_kernel<T><<<dim3(Bs, ND, DP / chf), 256, lds_t, st>>>(a);
+    }
     }
     HIPCHK(hipGetLastError());
   }
@@ -843,7 +854,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     void *pt0z, *pt0, *plam;
     STCHK(ws_get(m, "ab_t0z", (size_t)2 * fldB * sizeof(T), &pt0z));
     STCHK(ws_get(m, "ab_t0", (size_t)2 * fldB * sizeof(T), &pt0));
-    STCHK(ws_get(m, "ab_lam", (size_t)Bf * d.N * ND * DP * sizeof(T), &plam));
+    STCHK(ws_get(m, "ab_lam", (size_t)d.token * Bf * d.N * ND * DP * sizeof(T), &plam));
     MixArgs<T> a{};
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = 0; a.L = L; a.w_c = wc;
     a.periodic = d.bc == DN_BC_PERIODIC; a.C = 2 * Bf; a.chi = chi0; a.X = tau; a.out = (T*)pt0z;
@@ -871,7 +882,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     sa.tb = tb; sa.N = d.N; sa.Np = Np; sa.L = L; sa.w_c = wc; sa.periodic = d.bc == DN_BC_PERIODIC;
     sa.act = d.act; sa.F = F; sa.f0 = f0; sa.b0 = bf0; sa.Bc = Bf; sa.map = fmap; sa.spins = spins;
     sa.a0 = a0; sa.chi0 = chi0; sa.dchi = dchi; sa.geom = geom; sa.Wmax = Wmax; sa.err = (int*)perr;
-    sa.ext_max = ext_max; sa.dyn = dyn;
+    sa.ext_max = ext_max; sa.dyn = dyn; sa.tok = d.token;
     double slice_fl = 0.0;
     for (int l = 1; l <= L; ++l) slice_fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
     // P flips side by side per product (slices are at most 16 sites wide: P >= 4)
@@ -882,6 +893,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     if (shallow) {  // slice recompute and per-flip update in one kernel
       Flip12Args<T> a{};
       a.p0 = p0; a.fldB = fldB; a.T0 = T0; a.T1 = tau; a.lam = lam; a.ND = ND; a.dlo = dlo;
+      a.lamk = (long)Bf * d.N * ND * DP;
       a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.cplx = d.complex_out;
       if (L == 2) STCHK((launch_shallow<T, DP, true>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
       else STCHK((launch_shallow<T, DP, false>(m, sa, a, F, P, Wc, slice_fl, st, ext_max)));
@@ -912,6 +924,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.tapsL = tb.taps + (long)(L - 1) * DP * tap_stride(Np); a.taps1 = tb.taps;
       a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.slice_part = (T*)psp;
       a.cplx = d.complex_out;
+      a.tok = d.token;
       const bool first = (l == 1), last = (l == L - 1);
       if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
@@ -948,7 +961,7 @@ dn_status logratio_abacus(dn_model* m, const int8_t* spins, int B, const int32_t
   int32_t *offs, *cb, *cm;
   std::vector<int32_t> h_offs;
   STCHK(plan(m, n_conn, sites, B, M_max, 0, &offs, &cb, &cm, std::max(B * M_max, 1), &h_offs, st, spins));
-  const int ext_max = (h_offs[B + 1] & 4) ? 2 : 0;
+  const int ext_max = (h_offs[B + 1] & 4) ? (m->desc.token > 1 ? 1 : 2) : 0;
   STCHK((abacus_exec<T, DP>(m, spins, B, sites, M_max, offs, cb, cm, h_offs.data(), logpsi, logratio, ext_max, st)));
   return abacus_check(m, st);
 }
@@ -1067,13 +1080,14 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
     readout_grad_kernel<T><<<dim3(Bc, dd), 256, (size_t)(Np + 1) * sizeof(double), st>>>(a);
   }
   auto outer = [&](const T* P, const T* Q1, const T* Q2, const T* emb, long off) {
-    OuterArgs<T> a{P, Q1, Q2, emb, spins, b0, N, Np, dd, DP, grads, Pn, off};
+    OuterArgs<T> a{P, Q1, Q2, emb, spins, b0, N, Np, dd, DP, grads, Pn, off, d.token};
     PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * dd * dd * (double)N, 2.0 * fld * sizeof(T));
     outer_kernel<T, DP><<<Bc, 256, 0, st>>>(a);
   };
-  auto rowdot = [&](const T* P, const T* Q, int use_spins, int shift0, int nshift, long off, const double* dom) {
+  auto rowdot = [&](const T* P, const T* Q, int use_spins, int shift0, int nshift, long off, const double* dom,
+                    int kpos = 0) {
     RowdotArgs<T> a{P, Q, spins, use_spins, b0, N, Np, dd, DP, d.bc == DN_BC_PERIODIC, shift0, nshift, grads, Pn,
-                    off, 0, dom ? tb.Wk : nullptr, dom};
+                    off, 0, dom ? tb.Wk : nullptr, dom, d.token, kpos};
     rowdot_kernel<T><<<dim3(Bc, dd), 64, 0, st>>>(a);
   };
   T* du_next = nullptr;
@@ -1081,14 +1095,14 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
   int flip = 0;
   for (int l = L; l >= 1; --l) {
     const int tl = l - 1;
-    const long base = 2L * dd + (long)tl * lay;
+    const long base = m->lay.off_layers + (long)tl * lay;
     const long offWD = base, offw = base + dd * dd, offK = offw + dd, offk = offK + (long)Wc * dd,
                offAD = offk + dd, offb = offAD + (long)dd * dd, offU = offb + dd, offV = offU + (long)dd * dd;
     // recompute block l from its checkpoints
     {
       PhiArgs<T> a{};
       a.tb = tb; a.N = N; a.Np = Np; a.l = tl; a.w_c = wc; a.periodic = d.bc == DN_BC_PERIODIC; a.act = d.act;
-      a.inject = 0; a.first = (l == 1); a.spins = spins; a.map = idmap; a.cfg0 = b0; a.C = Bc;
+      a.inject = 0; a.first = (l == 1); a.spins = spins; a.map = idmap; a.cfg0 = b0; a.C = Bc; a.tok = d.token;
       a.phi_in = (l >= 2) ? ckphi + (long)(l - 1) * fld : nullptr;
       a.phi_out = tphi; a.chi_out = tchi; a.a_out = ta; a.u_out = tq; a.rho = rho2;
       a.z_out = tz; a.zeta_out = tzeta;
@@ -1152,8 +1166,11 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
     dph_next = dph_cur;
     flip ^= 1;
   }
-  rowdot(du_next, nullptr, 1, 0, 1, 0, dOm);  // dE: h^(0) = E s gets du^(1) + the read-out adjoint
-  rowdot(dph_next, nullptr, 1, 0, 1, dd, nullptr);  // dE_phi: phi^(0) = E_phi s
+  // dE_k: h^(0) = sum_k E_k s(tok i + k) gets du^(1) + the read-out adjoint; dE_phi,k likewise
+  for (int k = 0; k < d.token; ++k) {
+    rowdot(du_next, nullptr, 1, 0, 1, (long)k * dd, dOm, k);
+    rowdot(dph_next, nullptr, 1, 0, 1, (long)(d.token + k) * dd, nullptr, k);
+  }
   {
     S4GradArgs<T> a{dg, jac_of<T>(m), Bc, nmix * dd, TG, NPc, grads, Pn, m->lay.off_s4};
     PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * nmix * dd * (double)TG * NPc, (double)Bc * nmix * dd * TG * sizeof(T));
@@ -1229,7 +1246,7 @@ template <typename T, int DP> struct RunSweep {
   static dn_status run(dn_model* m, int8_t* spins, int B, int spacing, int parity, const double* r_site,
                        const double* u, double eps, int32_t* accepted, int32_t* refreshes, hipStream_t st,
                        double* eps_buf = nullptr, int32_t* eps_set = nullptr, int n_eps = 0, double gamma = 1.0) {
-    const int N = m->desc.N;
+    const int N = m->desc.N * m->desc.token;  // spins per chain
     const int nblk = (N + spacing - 1) / spacing;
     const int K = (nblk - parity + 1) / 2;
     if (K <= 0) return DN_OK;
@@ -1420,7 +1437,8 @@ template <typename T, int DP> struct RunLogpsiNoAlloc {
       const int C = std::min(C_max, B - c0);
       identity_map_kernel<<<(C + 255) / 256, 256, 0, st>>>(cb, cm, C);
       CfgMap idmap{cb, cm, nullptr, 0};
-      STCHK((forward_chunk<T, DP>(m, spins + (long)c0 * m->desc.N, idmap, 0, C, rho, nullptr, nullptr, nullptr, st,
+      STCHK((forward_chunk<T, DP>(m, spins + (long)c0 * m->desc.N * m->desc.token, idmap, 0, C, rho, nullptr, nullptr,
+                                  nullptr, st,
                                   Ckpt<T>(), fields)));
       logpsi_kernel<<<(C + 255) / 256, 256, 0, st>>>(rho, nullptr, C, logpsi + (long)c0 * (1 + m->desc.complex_out),
                                                      m->desc.complex_out);
@@ -1450,6 +1468,7 @@ bool check_desc(const dn_model_desc* d, std::string* why) {
   if (d->inject_phi != 0 && d->inject_phi != 1) { *why = "inject_phi must be 0 or 1"; return false; }
   if (d->prec < 0 || d->prec > 2) { *why = "bad prec"; return false; }
   if (d->complex_out != 0 && d->complex_out != 1) { *why = "complex_out must be 0 or 1"; return false; }
+  if (d->token < 0 || d->token > 4) { *why = "token must be in [0, 4] (0 = 1)"; return false; }
   return true;
 }
 
@@ -1491,7 +1510,7 @@ struct RaggedInst {
 // workspace has reached this instance's size.
 template <typename T, int DP> struct RunInst {
   static dn_status run(dn_model* m, const RaggedInst* in, hipStream_t st) {
-    const int B = in->B, M = in->M_max, N = m->desc.N;
+    const int B = in->B, M = in->M_max, N = m->desc.N * m->desc.token;  // spins
     void *ps, *ph, *pn, *pd, *pl, *pj;
     STCHK(ws_get(m, "rg_sites", (size_t)B * M * 2 * 4, &ps));
     STCHK(ws_get(m, "rg_helem", (size_t)B * M * 8, &ph));
@@ -1510,7 +1529,7 @@ template <typename T, int DP> struct RunInst {
     int32_t *offs, *cb, *cm;
     STCHK(plan_launch(m, nconn, sites, B, M, 0, &offs, &cb, &cm, std::max(B * M, 1), st));
     // the J1-J2 generator emits pairs up to two sites apart, the Ising one single flips
-    const int ext_max = in->ham.kind == DN_H_J1J2 ? 2 : 0;
+    const int ext_max = in->ham.kind == DN_H_J1J2 ? (m->desc.token > 1 ? 1 : 2) : 0;
     STCHK((abacus_exec<T, DP>(m, in->spins, B, sites, M, offs, cb, cm, nullptr, in->logpsi, (double*)pl, ext_max, st)));
     PScope e(m, DN_K_ELOC, st, 3.0 * B * M, (double)B * M * 16.0 + B * 20.0);
     eloc_kernel<<<B, 64, 0, st>>>((double*)pd, (double*)ph, nconn, (double*)pl, M, in->eloc, m->desc.complex_out);
@@ -1709,6 +1728,7 @@ dn_status dn_model_create(const dn_model_desc* desc, dn_model** out) {
     return fail(DN_EUNSUPPORTED, "BF16-mixed precision needs d > 16 (k-steps of 32 channels)");
   dn_model* m = new dn_model();
   m->desc = *desc;
+  if (m->desc.token < 1) m->desc.token = 1;
   layout_of(*desc, &m->lay);
   m->DP = desc->d <= 16 ? 16 : desc->d <= 32 ? 32 : 64;
   m->Np = pad_to(desc->N, 64);
@@ -1759,6 +1779,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   PrepArgs a{};
   a.params = m->params; a.taps64 = m->taps64; a.N = d.N; a.Np = m->Np; a.L = d.L; a.d = d.d; a.DP = m->DP;
   a.s = d.s; a.w_c = d.w_c; a.d_out = d.d_out; a.periodic = d.bc == DN_BC_PERIODIC; a.off_layers = m->lay.off_layers; a.off_A = m->lay.off_A;
+  a.tok = d.token;
   TableBufs<double>& t = m->t64;
   a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
   a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;
@@ -1767,7 +1788,9 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   {
     PScope ps(m, DN_K_PREP, st, 0.0, (double)table_elems(*m) * 8);
     prep_kernel<<<256, 256, 0, st>>>(a);
-    ptab_kernel<<<256, 256, 0, st>>>(t.taps, t.Vt, t.E, m->DP, tap_stride(m->Np), t.Pq);
+    for (int k = 0; k < d.token; ++k)  // one unit-flip table per position inside a token
+      ptab_kernel<<<256, 256, 0, st>>>(t.taps, t.Vt, t.E + (long)k * m->DP, m->DP, tap_stride(m->Np),
+                                       t.Pq + (long)k * 4 * m->DP * tap_stride(m->Np));
   }
   HIPCHK(hipGetLastError());
   if (d.prec != DN_PREC_FP64) STCHK(convert_tables(m, st));
@@ -1930,7 +1953,8 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
     const double N = m->desc.N;
     PScope g(m, DN_K_GEN, st, ham->kind == DN_H_LRTFIM ? (double)B * N * N : (double)B * 8 * N,
              (double)B * (N + M_max * 16.0 + 12));
-    STCHK(dn_connected(ham, spins, B, m->desc.N, M_max, (int32_t*)ps, (double*)ph, (int32_t*)pn, (double*)pd, stream));
+    STCHK(dn_connected(ham, spins, B, m->desc.N * m->desc.token, M_max, (int32_t*)ps, (double*)ph, (int32_t*)pn,
+                       (double*)pd, stream));
   }
   STCHK(dn_logratio(m, path, spins, B, (int32_t*)ps, (int32_t*)pn, M_max, logpsi, logratio, stream));
   PScope e(m, DN_K_ELOC, st, 3.0 * B * M_max, (double)B * M_max * 16.0 + B * 20.0);
@@ -1977,7 +2001,7 @@ dn_status dn_autotune(dn_model* m, const dn_ham_desc* ham, int32_t B_probe, int3
   if (!m || !ham) return fail(DN_EINVAL, "null argument");
   if (B_probe < 1) return fail(DN_EINVAL, "B_probe < 1");
   if (!m->have_params) return fail(DN_ESTATE, "parameters not set");
-  const int N = m->desc.N, M = ham->kind == DN_H_J1J2 ? 2 * N : N;
+  const int N = m->desc.N * m->desc.token, M = ham->kind == DN_H_J1J2 ? 2 * N : N;  // spins
   STCHK(check_ham(ham, N, M));
   STCHK(abacus_supported(m));
   hipStream_t st = (hipStream_t)stream;
@@ -2070,7 +2094,7 @@ dn_status dn_ragged_eloc(int32_t n_inst, dn_model* const* models, const dn_ham_d
     for (int j = 0; j < i; ++j)
       if (models[j] == m) return fail(DN_EINVAL, "each instance needs its own model" + at);
     if (!m->have_params) return fail(DN_ESTATE, "parameters not set" + at);
-    const int N = m->desc.N;
+    const int N = m->desc.N * m->desc.token;  // spins
     const int M = hams[i].kind == DN_H_J1J2 ? 2 * N : N;
     STCHK(check_ham(&hams[i], N, M));
     STCHK(abacus_supported(m));

@@ -235,6 +235,7 @@ template <typename T> struct OuterArgs {
   int N, Np, d, DP;
   T* grads;
   long Pn, off;
+  int tok;                // spins per token: the embedding is sum_k emb[k][c] s(tok i + k)
 };
 
 template <typename T, int DP>
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs<T> A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int N = A.N, Np = A.Np, j = lane & 15, kq = lane >> 4;
   const long fo = (long)g * DP * Np;
-  const int8_t* sp = A.spins ? A.spins + (long)(A.b0 + g) * N : nullptr;
+  const int8_t* sp = A.spins ? A.spins + (long)(A.b0 + g) * N * A.tok : nullptr;
   // wave w owns output column tile nt = w % MT and row tiles mt; waves split the sites when MT < 4
   const int nt = wave % MT;
   const int sgrp = wave / MT, nsg = 4 / MT;  // site groups (1 for DP=64, 2 for 32, 4 for 16)
@@ -258,7 +259,10 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs<T> A) {
     const int cq = 16 * nt + j;
     T bq = 0;
     if (i < N) {
-      if (A.emb) bq = A.emb[cq] * (T)sp[i];
+      if (A.emb) {
+        bq = A.emb[cq] * (T)sp[i * A.tok];
+        for (int k = 1; k < A.tok; ++k) bq += A.emb[k * DP + cq] * (T)sp[i * A.tok + k];
+      }
       else {
         bq = A.Q1[fo + (long)cq * Np + i];
         if (A.Q2) bq *= A.Q2[fo + (long)cq * Np + i];
@@ -310,6 +314,7 @@ template <typename T> struct RowdotArgs {
   int accumulate;
   const T* Wk;            // with dOm: P_eff = P + dOm_0 Wk_0 + dOm_1 Wk_1 (read-out adjoint)
   const double* dOm;
+  int tok, kpos;          // use_spins: the spin at position kpos of each token (spins per token tok)
 };
 
 template <typename T>
@@ -318,14 +323,14 @@ __global__ __launch_bounds__(64) void rowdot_kernel(RowdotArgs<T> A) {
   const int lane = threadIdx.x;
   const int N = A.N, Np = A.Np;
   const long ro = ((long)g * A.DP + c) * Np;
-  const int8_t* sp = A.use_spins ? A.spins + (long)(A.b0 + g) * N : nullptr;
+  const int8_t* sp = A.use_spins ? A.spins + (long)(A.b0 + g) * N * A.tok + A.kpos : nullptr;
   const T d0 = A.dOm ? (T)A.dOm[2 * g] : T(0), d1 = A.dOm ? (T)A.dOm[2 * g + 1] : T(0);
   for (int si = 0; si < A.nshift; ++si) {
     const int sh = A.shift0 + si;
     T acc = 0;
     for (int i = lane; i < N; i += 64) {
       T q = 1;
-      if (A.use_spins) q = (T)sp[i];
+      if (A.use_spins) q = (T)sp[i * A.tok];
       else if (A.Q) {
         int k = i + sh;
         if (A.periodic) { k %= N; if (k < 0) k += N; q = A.Q[ro + k]; }

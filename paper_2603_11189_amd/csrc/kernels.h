@@ -11,13 +11,13 @@
 namespace dn {
 
 template <typename T> struct Tables {
-  const T *E, *Ephi, *wE1;
+  const T *E, *Ephi, *wE1;                 // [token][DP]: one vector per position inside a token
   const T *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP] operand tables (row = input channel)
   const T *wv, *Kc, *kv, *bv;              // [L][DP], K [L][2w_c+1][DP]
   const T *taps, *tapsR;                   // [L][DP][tap_stride]: mixers and their transposes
   const T *Wk;                             // [2][DP][Np]
   const T *ADm, *WDm;                      // operand tables of A_D^T and W_D^T
-  const T *Pq;                             // [4][DP][tap_stride]: V^(1) (E * g^(1)(r)), see ptab_kernel
+  const T *Pq;                             // [token][4][DP][tap_stride]: V^(1) (E_k * g^(1)(r)), see ptab_kernel
   const T *omN, *Ac;                       // omega / N [DP][Np] and A^T [2][DP]: Wk = Ac omN
 };
 
@@ -113,7 +113,8 @@ template <typename T> struct PhiArgs {
   Tables<T> tb;
   int N, Np, l, w_c, periodic, act, inject;
   int first;
-  const int8_t* spins;  // [B][N]
+  int tok;              // spins per token
+  const int8_t* spins;  // [B][N * tok]
   CfgMap map;
   int cfg0, C;          // configurations [cfg0, cfg0 + C)
   const T* phi_in;      // [C][DP][Np]
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
   const int q = lane >> 4, col = lane & 15;
   const int N = A.N, Np = A.Np, wc = A.w_c;
   const int ld = Np + 2 * wc + 1;  // odd row stride
-  T* sp_s = as + DP * ld;          // s' (first block), [Np]
+  T* sp_s = as + DP * ld;          // s' (first block), [tok][Np]: spin k of every token
   __shared__ double red[2][4];
   constexpr int MT = DP / 16;
   using M = Mma<T>;
@@ -158,19 +159,26 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
       f0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
       f1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
     }
-    const int8_t* sp = A.spins + (long)b * N;
-    for (int i = threadIdx.x; i < Np; i += 256) {
+    const int tk = A.tok;
+    const int8_t* sp = A.spins + (long)b * N * tk;
+    for (int i = threadIdx.x; i < tk * Np; i += 256) {
+      const int k = i / Np, ti = i - k * Np;  // position inside the token, token
       T v = 0;
-      if (i < N) {
-        v = (T)sp[i];
-        if (i == f0 || i == f1) v = -v;
+      if (ti < N) {
+        const int si = ti * tk + k;
+        v = (T)sp[si];
+        if (si == f0 || si == f1) v = -v;
       }
       sp_s[i] = v;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < DP * Np; idx += 256) {
       int c = idx / Np, i = idx % Np;
-      T v = (i < N) ? sp_s[i] * A.tb.wE1[c] + A.tb.wv[c] : T(0);
+      T v = 0;
+      if (i < N) {
+        v = sp_s[i] * A.tb.wE1[c] + A.tb.wv[c];
+        for (int k = 1; k < tk; ++k) v += sp_s[k * Np + i] * A.tb.wE1[k * DP + c];
+      }
       as[c * ld + i + wc] = v;
       if (a_out) elem(a_out, idx) = v;
     }
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
     }
   }
   // the block's per-channel vectors in LDS: k [DP], then K_r [2 w_c + 1][DP]
-  T* kvs = sp_s + Np;
+  T* kvs = sp_s + A.tok * Np;
   for (int idx = threadIdx.x; idx < (2 * wc + 2) * DP; idx += 256)
     kvs[idx] = idx < DP ? A.tb.kv[l * DP + idx] : A.tb.Kc[(long)l * (2 * wc + 1) * DP + idx - DP];
   __syncthreads();
@@ -245,7 +253,8 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
         if (z_out) elem(z_out, o) = in ? s : T(0);
         if (phi_out) elem(phi_out, o) = ph;
         if (A.first) {
-          const T h0 = A.tb.E[kc] * h0s;
+          T h0 = A.tb.E[kc] * h0s;
+          for (int k = 1; k < A.tok; ++k) h0 += A.tb.E[k * DP + kc] * (in ? sp_s[k * Np + i] : T(0));
           if (A.R_out) elem(A.R_out + fo, o) = h0;
           elem(A.u_out + fo, o) = h0 + (A.inject ? ph : T(0));
           part0 += (double)elem(A.tb.Wk, o) * (double)h0;
@@ -712,6 +721,7 @@ template <typename T> struct MixArgs {
   DynRange dyn;          // flips counted on the device (nullable)
   T* slice_part;         // last block: [F][Np/64][SLICE_WIN][DP] partial slices
   int cplx;              // 1: complex read-out unit Omega_0 + i Omega_1
+  int tok;               // spins per token (spins: [B][N * tok]; geom's flip sites index spins)
 };
 
 constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4; gradient kernels)
@@ -1128,14 +1138,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
     if constexpr (FIRST) {
       // w = G^(1) e^(0) with e^(0)_c = -2 s_z E_c at the cluster sites z, so
       // q(i) = -2 s_z Pq(i - z) summed over the cluster (Pq: parameter-only table)
-      const int8_t* sp = A.spins + (long)bglob * N;
+      // (with tokens: the flipped spin's token z and its position's table Pq_k)
+      const int8_t* sp = A.spins + (long)bglob * N * A.tok;
       const T c0 = (T)(-2 * sp[sg.z]);
       const bool pair = sg.w >= 0;
       const T c1 = pair ? (T)(-2 * sp[sg.w]) : T(0);
+      const int za = sg.z / A.tok, ka = sg.z - za * A.tok;
+      const int jw = pair ? sg.w : sg.z, z1 = jw / A.tok, kb = jw - z1 * A.tok;
       // the copy shifted by (TO - z) mod 4 makes the four sites one aligned vector
-      const int z1 = pair ? sg.w : sg.z, shz = (TO - sg.z) & 3, shw = (TO - z1) & 3;
-      const T* pz = A.tb.Pq + ((long)shz * DP + lrow) * TS + TO + s0 - sg.z - shz;
-      const T* pw = A.tb.Pq + ((long)shw * DP + lrow) * TS + TO + s0 - z1 - shw;
+      const int shz = (TO - za) & 3, shw = (TO - z1) & 3;
+      const long PK = 4L * DP * TS;
+      const T* pz = A.tb.Pq + ka * PK + ((long)shz * DP + lrow) * TS + TO + s0 - za - shz;
+      const T* pw = A.tb.Pq + kb * PK + ((long)shw * DP + lrow) * TS + TO + s0 - z1 - shw;
       if constexpr (EC) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -1598,14 +1612,15 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   }
   // e^(0) = -2 s_j E on the cluster, read out directly (lanes over channels)
   {
-    const int8_t* spb = A.spins + (long)bg * N;
+    const int8_t* spb = A.spins + (long)bg * N * A.tok;
     for (int q = 0; q < 2; ++q) {
-      const int js = q == 0 ? sg.z : sg.w;
+      const int js = q == 0 ? sg.z : sg.w;  // a flipped spin: its token jt, its position jk
       if (js < 0) continue;
+      const int jt = js / A.tok, jk = js - jt * A.tok;
       for (int c = lane; c < DP; c += 64) {
-        const double e0 = (double)(-2 * spb[js]) * (double)A.tb.E[c];
-        o0 += (double)A.tb.Wk[(long)c * Np + js] * e0;
-        o1 += (double)A.tb.Wk[(long)DP * Np + (long)c * Np + js] * e0;
+        const double e0 = (double)(-2 * spb[js]) * (double)A.tb.E[jk * DP + c];
+        o0 += (double)A.tb.Wk[(long)c * Np + jt] * e0;
+        o1 += (double)A.tb.Wk[(long)DP * Np + (long)c * Np + jt] * e0;
       }
     }
   }
@@ -1643,6 +1658,7 @@ template <typename T> struct SliceArgs {
   int* err;               // set to 1 for a cluster the slice recurrence does not cover
   int ext_max;            // widest cluster extent the launch's links were built for
   DynRange dyn;           // flips counted on the device (nullable)
+  int tok;                // spins per token (spins: [B][N * tok]; sites index spins)
 };
 
 // The slice recompute with its two channel mixes on the matrix cores. A workgroup takes
@@ -1723,30 +1739,35 @@ __device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int f
   const int b = A.map.cb[f0 + f], m = A.map.cm[f0 + f];
   const int j0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
   const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
-  int clo = j0, ext = 0;
+  // the cluster in tokens: clo its first token, ext its extent; ja flips a spin of token clo,
+  // jb (or -1) the other flipped spin, of token clo + ext
+  const int tk = A.tok, NS = N * tk, z0 = j0 / tk;
+  int clo = z0, ext = 0, ja = j0, jb = j1;
   if (j1 >= 0) {
-    if (per) {
-      int d1 = ((j1 - j0) % N + N) % N, d2 = ((j0 - j1) % N + N) % N;
-      if (d1 <= 2) { clo = j0; ext = d1; }
-      else if (d2 <= 2) { clo = j1; ext = d2; }
-      else ext = -1;
+    const int z1 = j1 / tk;
+    int ds = j1 > j0 ? j1 - j0 : j0 - j1;  // spin distance: at most 2
+    if (per && NS - ds < ds) ds = NS - ds;
+    if (ds > 2) {
+      ext = -1;
+    } else if (per) {
+      const int d1 = ((z1 - z0) % N + N) % N, d2 = ((z0 - z1) % N + N) % N;
+      if (d1 <= d2) { clo = z0; ext = d1; }
+      else { clo = z1; ext = d2; ja = j1; jb = j0; }
+    } else if (z1 < z0) {
+      clo = z1; ext = z0 - z1; ja = j1; jb = j0;
     } else {
-      clo = j0 < j1 ? j0 : j1;
-      ext = j0 < j1 ? j1 - j0 : j0 - j1;
-      if (ext > 2) ext = -1;
+      ext = z1 - z0;
     }
   }
   if (ext < 0 || ext > A.ext_max || (per && ext + 2 * L * wc + 1 > N)) {
     atomicOr(A.err, 1);
     ext = 0;
   }
-  if (write_geom) A.geom[f] = make_int4(clo, ext, j0, j1);
-  const int8_t* sp = A.spins + (long)b * N;
-  int zb = clo + ext;
-  if (per) zb %= N;
-  g[0] = b; g[1] = clo; g[2] = ext; g[3] = j0; g[4] = j1; g[5] = f;
-  g[6] = -2 * sp[clo];
-  g[7] = j1 >= 0 ? -2 * sp[zb] : 0;
+  if (write_geom) A.geom[f] = make_int4(clo, ext, ja, jb);
+  const int8_t* sp = A.spins + (long)b * NS;
+  g[0] = b; g[1] = clo; g[2] = ext; g[3] = ja; g[4] = jb; g[5] = f;
+  g[6] = -2 * sp[ja];
+  g[7] = jb >= 0 ? -2 * sp[jb] : 0;
 }
 
 // Blocks 1 .. L of the slice recompute (L = LF when LF > 0). epi(l, n, r, v) receives the
@@ -1804,12 +1825,19 @@ __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int
         const int p = pt / nt1, t = pt - p * nt1;
         const int* g = gs + SLM_GS * p;
         if (g[0] < 0 || t > g[2]) continue;
-        const int site = wrap(g[1] + t);
+        const int site = wrap(g[1] + t);  // a token of the cluster
         T v = 0;
         if (inside(g[1] + t)) {
-          T sv = (T)A.spins[(long)g[0] * N + site];
-          if (site == g[3] || site == g[4]) sv = -sv;
+          const int tk = A.tok, s0 = site * tk;
+          const int8_t* sr = A.spins + (long)g[0] * N * tk + s0;
+          T sv = (T)sr[0];
+          if (s0 == g[3] || s0 == g[4]) sv = -sv;
           v = sv * A.tb.wE1[c] + A.tb.wv[c];
+          for (int k = 1; k < tk; ++k) {
+            T sk = (T)sr[k];
+            if (s0 + k == g[3] || s0 + k == g[4]) sk = -sk;
+            v += sk * A.tb.wE1[k * DP + c];
+          }
         }
         ab[c * lda + p * AW + 2 * wc + t] = v;
       }

@@ -347,7 +347,8 @@ template <typename T> struct Flip12Args {
   long fldB;            // Bf DP Np
   const T* T0;          // [Bf][2][DP][Np]: output link of the input change (h^(0))
   const T* T1;          // [Bf][2][DP][Np]: output link of block 1 (two blocks; one block: Wk)
-  const T* lam;         // [Bf][N][ND][DP]: pivot-0 link of block 2
+  const T* lam;         // [tok][Bf][N][ND][DP]: pivot-0 link of block 2, per position in a token
+  long lamk;            // elements between the positions' links
   int ND, dlo;
   const double* Om0;    // [B][2]
   double* logratio;     // [B][M_max] ([B][M_max][2] with a complex read-out)
@@ -417,13 +418,16 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
       v1q[n] = p < P && g[0] >= 0 && t < g[2] + 2 * wc + 1 && inside(s1u);
       const int s1 = v1q[n] ? wrap(s1u) : g[1];
       const T* p01 = F.p0 + (long)(g[0] >= 0 ? g[0] - A.b0 : 0) * fld + s1;
+      // the unit-flip tables of the flipped spins' positions inside their tokens
+      const int ka = g[3] >= 0 ? g[3] % A.tok : 0, kb = g[4] >= 0 ? g[4] % A.tok : ka;
+      const T* pqa = A.tb.Pq + (long)ka * 4 * DP * TS;
+      const T* pqb = A.tb.Pq + (long)kb * 4 * DP * TS;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long ch = 16 * wave + M::row(lane, r);
         pv[n][r] = p01[ch * Np];
-        const T* pq = A.tb.Pq + ch * TS + TO + t - wc;
-        qa[n][r] = pq[0];
-        qb[n][r] = pq[-g[2]];
+        qa[n][r] = pqa[ch * TS + TO + t - wc];
+        qb[n][r] = pqb[ch * TS + TO + t - wc - g[2]];
       }
     }
 #pragma unroll
@@ -478,14 +482,18 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
         oa0[n] = (double)q0;
         oa1[n] = (double)q1;
         const int s1u = g[1] - wc + t;
+        // e^(0) at the cluster's tokens: both flips may sit in one token
         const bool at_a = s1u == g[1], at_b = g[4] >= 0 && s1u == g[1] + g[2];
         if (at_a || at_b) {
-          const double cz = at_a ? (double)g[6] : (double)g[7];
           const T* t0 = F.T0 + 2 * (long)(g[0] - A.b0) * fld + wrap(s1u);
+          const T* Ea = A.tb.E + (g[3] % A.tok) * DP;
+          const T* Eb = A.tb.E + (g[4] >= 0 ? g[4] % A.tok : 0) * DP;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int ch = 16 * wave + M::row(lane, r);
-            const double e = cz * (double)A.tb.E[ch];
+            double e = 0.0;
+            if (at_a) e += (double)g[6] * (double)Ea[ch];
+            if (at_b) e += (double)g[7] * (double)Eb[ch];
             oa0[n] += e * (double)t0[(long)ch * Np];
             oa1[n] += e * (double)t0[fld + (long)ch * Np];
           }
@@ -518,9 +526,10 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
           const int p = j2 / W2m, t2 = j2 - p * W2m;
           const int* g = gs + SLM_GS * (j2 < ncol ? p : 0);
           const long bl = g[0] >= 0 ? g[0] - A.b0 : 0;
+          const int ka = g[3] >= 0 ? g[3] % A.tok : 0, kb = g[4] >= 0 ? g[4] % A.tok : ka;
           const T* lamb = F.lam + bl * N * F.ND * DP + c;
-          la[i] = lamb[((long)g[1] * F.ND + (t2 - 2 * wc - F.dlo)) * DP];
-          lb[i] = lamb[((long)wrap(g[1] + g[2]) * F.ND + (t2 - 2 * wc - g[2] - F.dlo)) * DP];
+          la[i] = lamb[ka * F.lamk + ((long)g[1] * F.ND + (t2 - 2 * wc - F.dlo)) * DP];
+          lb[i] = lamb[kb * F.lamk + ((long)wrap(g[1] + g[2]) * F.ND + (t2 - 2 * wc - g[2] - F.dlo)) * DP];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

@@ -199,10 +199,10 @@ __global__ __launch_bounds__(S4_THREADS) void s4_taps_kernel(const double* __res
 struct PrepArgs {
   const double* params;
   const double* taps64;  // [L+1][d][2N-1]
-  int N, Np, L, d, DP, s, w_c, d_out, periodic;
+  int N, Np, L, d, DP, s, w_c, d_out, periodic, tok;
   long off_layers, off_A;
   // outputs (double tables)
-  double *E, *Ephi, *wE1;
+  double *E, *Ephi, *wE1;                  // [tok][DP]: per position inside a token
   double *WDt, *ADt, *Ut, *Vt, *Um, *Vm;  // [L][DP][DP]; *t transposed (t[k][m] = M[m][k])
   double *wv, *Kc, *kv, *bv;               // [L][DP], K: [L][2w_c+1][DP]
   double *taps, *tapsR;                    // [L][DP][TS] mixers and their transposes
@@ -216,16 +216,20 @@ __global__ void prep_kernel(PrepArgs a) {
   const long nth = (long)gridDim.x * blockDim.x;
   const int d = a.d, DP = a.DP, L = a.L, Wc = 2 * a.w_c + 1;
   const long lay_sz = 4L * d * d + 6L * d + (long)(Wc - 3) * d;  // W_D,w,K,k,A_D,b,U,V
-  for (long i = tid; i < DP; i += nth) {
-    a.E[i] = i < d ? a.params[i] : 0.0;
-    a.Ephi[i] = i < d ? a.params[d + i] : 0.0;
+  for (long i = tid; i < DP; i += nth)
     for (int k = 0; k < 2; ++k) a.A[i * 2 + k] = i < d ? a.params[a.off_A + i * a.d_out + k] : 0.0;
+  for (long ik = tid; ik < (long)a.tok * DP; ik += nth) {
+    const int k = (int)(ik / DP), i = (int)(ik % DP);  // position inside the token, channel
+    const double* Ek = a.params + (long)k * d;
+    const double* Fk = a.params + (long)(a.tok + k) * d;
+    a.E[ik] = i < d ? Ek[i] : 0.0;
+    a.Ephi[ik] = i < d ? Fk[i] : 0.0;
     double acc = 0.0;
     if (i < d) {
       const double* WD = a.params + a.off_layers;  // block 1
-      for (int j = 0; j < d; ++j) acc += WD[i * d + j] * a.params[d + j];
+      for (int j = 0; j < d; ++j) acc += WD[i * d + j] * Fk[j];
     }
-    a.wE1[i] = acc;
+    a.wE1[ik] = acc;
   }
   // Operand tables of out = M in: table[kin][mout] = M[mout][kin] (row = input channel).
   // WDt, ADt, Ut, Vt hold W_D, A_D, U, V; Um, Vm hold U^T, V^T (table[kin][mout] = U[kin][mout]).
