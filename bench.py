@@ -664,7 +664,8 @@ def bench_sr(args) -> None:
 def bench_sweep(args) -> None:
     """Speedup of ABACUS over full re-evaluation on the same GPU across chain lengths: the
     long-range Ising chain (alpha=2, h=0.5), d=64, state 32, float32, B samples per N; or,
-    with --paper-shapes, the paper's matched runtime shapes (L=2, d=2, state 12, periodic)."""
+    with --paper-shapes, the paper's matched runtime shapes (L=2, d=2, state 12, token size 2,
+    periodic, N = 100 .. 1000 spins)."""
     import torch
 
     import dn_inputs as di
@@ -676,14 +677,15 @@ def bench_sweep(args) -> None:
     if args.paper_shapes:
         B = 1024
         ham = di.HamSpec("lrtfim", "periodic", J=-5.0, alpha=6.0, h=1.0, paper_form=1)
-        grid = [(di.ModelShape(N, 2, 2, 12, act="silu", bc="periodic"), 2) for N in (100, 250, 500)]
+        grid = [(di.ModelShape(N // 2, 2, 2, 12, act="silu", bc="periodic", token=2), 2)
+                for N in (100, 250, 500, 1000)]
     else:
         B = 512
         ham = di.HamSpec("lrtfim", "open", J=1.0, alpha=2.0, h=0.5)
         grid = [(di.ModelShape(N, depth, 64, 32, act="silu", bc="open"), depth)
                 for depth in (2, 4) for N in (64, 128, 256, 512)]
     for shape, depth in grid:
-        N = shape.N
+        N = shape.n_spins  # spins: one connected element per spin
         m = L.Model(shape, "fp32")
         m.set_params(torch.tensor(di.draw_params(shape, 1005, "baseline")))
         spins = torch.tensor(di.uniform_spins(B, N, 2005), device=dev)
@@ -704,7 +706,8 @@ def bench_sweep(args) -> None:
             rate[path] = B * steps / (time.perf_counter() - t0)
         m.close()
         line = {"metric": "E_loc samples/sec, ABACUS vs full re-eval (sweep)", "N": N, "L": depth,
-                "d": shape.d, "s": shape.s, "bc": shape.bc, "B": B, "dtype": "f32", "abacus": rate["abacus"],
+                "token": shape.token, "d": shape.d, "s": shape.s, "bc": shape.bc, "B": B, "dtype": "f32",
+                "abacus": rate["abacus"],
                 "full": rate["full"], "speedup": rate["abacus"] / rate["full"],
                 "us_per_element": {p: 1e6 / (rate[p] * N) for p in rate}, "unit": "samples/s",
                 "data": "synthetic"}
