@@ -353,6 +353,11 @@ template <typename T> dn_status launch_conv(dn_model* m, const T* X, T* Y, const
 }
 
 template <typename T, int DP, int NT> void phi_go(const PhiArgs<T>& a, int C, size_t lds, hipStream_t st) {
+  if (a.tok > 1) {  // tokens of several spins: the general embedding
+    allow_lds(phi_kernel<T, DP, NT, true>, lds);
+    phi_kernel<T, DP, NT, true><<<C, 256, lds, st>>>(a);
+    return;
+  }
   allow_lds(phi_kernel<T, DP, NT>, lds);
   phi_kernel<T, DP, NT><<<C, 256, lds, st>>>(a);
 }
@@ -771,12 +776,16 @@ dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, i
   const size_t lds = slm_lds_bytes<T>(DP, P, Wc, m->desc.w_c) + (TWO ? (size_t)DP * (W1m + W2m - 1) * sizeof(T) : 0);
   if (lds > LDS_MAX) return fail(DN_EUNSUPPORTED, "ABACUS slice too wide for one matrix-core product");
   allow_lds(shallow_kernel<T, DP, TWO>, lds);
+  allow_lds(shallow_kernel<T, DP, TWO, true>, lds);
   const dn_model_desc& d = m->desc;
   const double dr = d.d, W1 = ext + 2 * d.w_c + 1, W2 = ext + 4 * d.w_c + 1;
   const double fl = 2.0 * dr * dr * (W1 + (TWO ? 2.0 * W2 : 0.0)) + (TWO ? 2.0 * dr * W1 * W2 : 0.0);
   const double by = (TWO ? (2.0 * W1 + 4.0 * W2 + 2.0 * 5) : (3.0 * W1 + 2.0)) * dr * sizeof(T);
   PScope ps(m, DN_K_TAIL, st, (fl + slice_fl) * F, by * F);
-  shallow_kernel<T, DP, TWO><<<slm_grid((F + P - 1) / P), 4 * DP, lds, st>>>(sa, a);
+  if (sa.tok > 1)  // tokens of several spins: per-position tables and links
+    shallow_kernel<T, DP, TWO, true><<<slm_grid((F + P - 1) / P), 4 * DP, lds, st>>>(sa, a);
+  else
+    shallow_kernel<T, DP, TWO><<<slm_grid((F + P - 1) / P), 4 * DP, lds, st>>>(sa, a);
   HIPCHK(hipGetLastError());
   return DN_OK;
 }

@@ -128,7 +128,8 @@ template <typename T> struct PhiArgs {
   T* R_out;             // first block: residual sum initialised with h^(0) (nullable)
 };
 
-template <typename T, int DP, int NT>
+// TOK: tokens of more than one spin (A.tok); without it the embedding is the per-site one.
+template <typename T, int DP, int NT, bool TOK = false>
 __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* as = reinterpret_cast<T*>(smem_raw);
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
       f0 = A.map.sites[((long)b * A.map.M_max + m) * 2];
       f1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
     }
-    const int tk = A.tok;
+    const int tk = TOK ? A.tok : 1;
     const int8_t* sp = A.spins + (long)b * N * tk;
     for (int i = threadIdx.x; i < tk * Np; i += 256) {
       const int k = i / Np, ti = i - k * Np;  // position inside the token, token
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
     }
   }
   // the block's per-channel vectors in LDS: k [DP], then K_r [2 w_c + 1][DP]
-  T* kvs = sp_s + A.tok * Np;
+  T* kvs = sp_s + (TOK ? A.tok : 1) * Np;
   for (int idx = threadIdx.x; idx < (2 * wc + 2) * DP; idx += 256)
     kvs[idx] = idx < DP ? A.tb.kv[l * DP + idx] : A.tb.Kc[(long)l * (2 * wc + 1) * DP + idx - DP];
   __syncthreads();
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(256) void phi_kernel(PhiArgs<T> A) {
         if (phi_out) elem(phi_out, o) = ph;
         if (A.first) {
           T h0 = A.tb.E[kc] * h0s;
-          for (int k = 1; k < A.tok; ++k) h0 += A.tb.E[k * DP + kc] * (in ? sp_s[k * Np + i] : T(0));
+          if constexpr (TOK)
+            for (int k = 1; k < A.tok; ++k) h0 += A.tb.E[k * DP + kc] * (in ? sp_s[k * Np + i] : T(0));
           if (A.R_out) elem(A.R_out + fo, o) = h0;
           elem(A.u_out + fo, o) = h0 + (A.inject ? ph : T(0));
           part0 += (double)elem(A.tb.Wk, o) * (double)h0;
@@ -1724,7 +1726,7 @@ template <typename T, int DP> __device__ inline void slm_rows(const T* Wt, int w
 
 // Cluster geometry of flips fg .. fg + P - 1 into gs (threads < P; c_a, c_b = -2 s at the
 // cluster sites, c_b = 0 for one site). Clusters the slice recurrence does not cover set err.
-template <typename T>
+template <bool TOK, typename T>
 __device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int fg, int nfl, int f0, bool write_geom) {
   const int N = A.N, L = A.L, wc = A.w_c;
   const bool per = A.periodic != 0;
@@ -1741,7 +1743,7 @@ __device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int f
   const int j1 = A.map.sites[((long)b * A.map.M_max + m) * 2 + 1];
   // the cluster in tokens: clo its first token, ext its extent; ja flips a spin of token clo,
   // jb (or -1) the other flipped spin, of token clo + ext
-  const int tk = A.tok, NS = N * tk, z0 = j0 / tk;
+  const int tk = TOK ? A.tok : 1, NS = N * tk, z0 = j0 / tk;
   int clo = z0, ext = 0, ja = j0, jb = j1;
   if (j1 >= 0) {
     const int z1 = j1 / tk;
@@ -1773,7 +1775,7 @@ __device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int f
 // Blocks 1 .. L of the slice recompute (L = LF when LF > 0). epi(l, n, r, v) receives the
 // vertex change v = chi'(l) - chi0(l) of the lane's channel 16 w + row(lane, r) at its
 // column 16 n + lane % 16 of S_l (zero for columns that hold no slice site of a flip).
-template <typename T, int DP, int LF, typename EPI>
+template <typename T, int DP, int LF, bool TOK, typename EPI>
 __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int* gs, int P, int lda, EPI&& epi) {
   constexpr int NTH = 4 * DP;
   const int N = A.N, Np = A.Np, wc = A.w_c;
@@ -1828,7 +1830,7 @@ __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int
         const int site = wrap(g[1] + t);  // a token of the cluster
         T v = 0;
         if (inside(g[1] + t)) {
-          const int tk = A.tok, s0 = site * tk;
+          const int tk = TOK ? A.tok : 1, s0 = site * tk;
           const int8_t* sr = A.spins + (long)g[0] * N * tk + s0;
           T sv = (T)sr[0];
           if (s0 == g[3] || s0 == g[4]) sv = -sv;
@@ -1935,10 +1937,10 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
   const int nfl = A.dyn.count(A.F);
   const int fg = slm_group() * P;
   if (fg >= nfl) return;
-  slm_geometry(A, gs, P, fg, nfl, A.dyn.first(A.f0), true);
+  slm_geometry<true>(A, gs, P, fg, nfl, A.dyn.first(A.f0), true);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, wc = A.w_c;
-  slm_layers<T, DP, 0>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) {
+  slm_layers<T, DP, 0, true>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) {
     const int Wlm = A.ext_max + 2 * l * wc + 1;
     const int j = 16 * n + col;
     const int p = j / Wlm, t = j - p * Wlm;

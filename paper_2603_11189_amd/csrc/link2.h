@@ -363,7 +363,7 @@ template <typename T> struct Flip12Args {
 // product (U^(1); V^(2) and U^(2) for two blocks) with those weight rows in registers; the
 // read-outs are summed per column over the wave's channels, then over waves and a flip's
 // columns in LDS.
-template <typename T, int DP, bool TWO>
+template <typename T, int DP, bool TWO, bool TOK = false>
 __global__ __launch_bounds__(4 * DP) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -389,11 +389,11 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
   if constexpr (TWO)
     for (int idx = threadIdx.x; idx < DP * TW; idx += blockDim.x)
       g2s[idx] = A.tb.taps[((long)DP + idx / TW) * TS + TO + g_lo + idx % TW];
-  slm_geometry(A, gs, P, fg, nfl, f0, false);
+  slm_geometry<TOK>(A, gs, P, fg, nfl, f0, false);
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
   T dch[LF][SLM_NT][4];
-  slm_layers<T, DP, LF>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) { dch[l - 1][n][r] = v; });
+  slm_layers<T, DP, LF, TOK>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) { dch[l - 1][n][r] = v; });
   const bool per = A.periodic != 0;
   auto wrap = [&](int i) { if (per) { i %= N; if (i < 0) i += N; } return i; };
   auto inside = [&](int i) { return per || (i >= 0 && i < N); };
@@ -419,7 +419,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
       const int s1 = v1q[n] ? wrap(s1u) : g[1];
       const T* p01 = F.p0 + (long)(g[0] >= 0 ? g[0] - A.b0 : 0) * fld + s1;
       // the unit-flip tables of the flipped spins' positions inside their tokens
-      const int ka = g[3] >= 0 ? g[3] % A.tok : 0, kb = g[4] >= 0 ? g[4] % A.tok : ka;
+      const int ka = TOK && g[3] >= 0 ? g[3] % A.tok : 0, kb = TOK && g[4] >= 0 ? g[4] % A.tok : ka;
       const T* pqa = A.tb.Pq + (long)ka * 4 * DP * TS;
       const T* pqb = A.tb.Pq + (long)kb * 4 * DP * TS;
 #pragma unroll
@@ -486,8 +486,8 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
         const bool at_a = s1u == g[1], at_b = g[4] >= 0 && s1u == g[1] + g[2];
         if (at_a || at_b) {
           const T* t0 = F.T0 + 2 * (long)(g[0] - A.b0) * fld + wrap(s1u);
-          const T* Ea = A.tb.E + (g[3] % A.tok) * DP;
-          const T* Eb = A.tb.E + (g[4] >= 0 ? g[4] % A.tok : 0) * DP;
+          const T* Ea = A.tb.E + (TOK ? g[3] % A.tok : 0) * DP;
+          const T* Eb = A.tb.E + (TOK && g[4] >= 0 ? g[4] % A.tok : 0) * DP;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int ch = 16 * wave + M::row(lane, r);
@@ -526,7 +526,7 @@ void shallow_kernel(SliceArgs<T> A, Flip12Args<T> F) {
           const int p = j2 / W2m, t2 = j2 - p * W2m;
           const int* g = gs + SLM_GS * (j2 < ncol ? p : 0);
           const long bl = g[0] >= 0 ? g[0] - A.b0 : 0;
-          const int ka = g[3] >= 0 ? g[3] % A.tok : 0, kb = g[4] >= 0 ? g[4] % A.tok : ka;
+          const int ka = TOK && g[3] >= 0 ? g[3] % A.tok : 0, kb = TOK && g[4] >= 0 ? g[4] % A.tok : ka;
           const T* lamb = F.lam + bl * N * F.ND * DP + c;
           la[i] = lamb[ka * F.lamk + ((long)g[1] * F.ND + (t2 - 2 * wc - F.dlo)) * DP];
           lb[i] = lamb[kb * F.lamk + ((long)wrap(g[1] + g[2]) * F.ND + (t2 - 2 * wc - g[2] - F.dlo)) * DP];
