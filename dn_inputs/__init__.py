@@ -34,6 +34,7 @@ class ModelShape:
     inject_phi: int = 0  # 1: add phi^(l) to the h stream before the mixer (Fig. 1c form)
     complex_out: int = 0  # 1: complex read-out matrix A (column pairs as real and imaginary parts)
     token: int = 1    # spins per token (patching): token tau embeds spins token*tau .. token*tau + token - 1
+    d_block: int = 0  # > 0: the vertex acts within channel blocks of this size (U, V block-diagonal)
 
     def __post_init__(self):
         assert self.act in ACTS and self.bc in BCS

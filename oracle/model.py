@@ -31,7 +31,11 @@ Readings of the paper used here (each listed in the design doc):
   * token size t (patching, Sec. V on the efficiency trade-off): the network runs on N tokens,
     token tau holding the spins t tau .. t tau + t - 1, embedded as h^(0)_tau = sum_k E_k s_(t tau + k)
     and phi^(0)_tau = sum_k E_phi,k s_(t tau + k) (one embedding vector per position k inside a
-    token; t = 1 is the per-site embedding).
+    token; t = 1 is the per-site embedding);
+  * block-diagonal vertex (Sec. V, the mixture-of-experts remark): with d_block = b > 0 the
+    vertex D = U diag(chi) V acts within channel blocks of b: U and V are block-diagonal, their
+    off-block entries of the parameter vector are not used (zero), chi and the phi stream are
+    unchanged.
 """
 from __future__ import annotations
 
@@ -58,12 +62,13 @@ class ModelDesc:
     inject_phi: int = 0
     complex_out: int = 0
     token: int = 1
+    d_block: int = 0
 
     @staticmethod
     def of(shape) -> "ModelDesc":
         return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c,
                          shape.bc, shape.act, shape.inject_phi, getattr(shape, "complex_out", 0),
-                         getattr(shape, "token", 1))
+                         getattr(shape, "token", 1), getattr(shape, "d_block", 0))
 
 
 def act(name: str, x: torch.Tensor) -> torch.Tensor:
@@ -75,6 +80,14 @@ def act(name: str, x: torch.Tensor) -> torch.Tensor:
     if name == "identity":
         return x
     raise ValueError(name)
+
+
+def block_mask(desc: ModelDesc):
+    """1 on the channel blocks of the vertex (d_block > 0), else None."""
+    if not desc.d_block:
+        return None
+    c = torch.arange(desc.d) // desc.d_block
+    return (c[:, None] == c[None, :]).to(DT)
 
 
 def unpack(desc: ModelDesc, theta: torch.Tensor) -> Dict:
@@ -91,10 +104,14 @@ def unpack(desc: ModelDesc, theta: torch.Tensor) -> Dict:
         return t
 
     prm = {"E": take(desc.token, d), "E_phi": take(desc.token, d), "layers": [], "s4": []}
+    blk = block_mask(desc)
     for _ in range(L):
-        prm["layers"].append({
-            "W_D": take(d, d), "w": take(d), "K": take(Wc, d), "k": take(d),
-            "A_D": take(d, d), "b": take(d), "U": take(d, d), "V": take(d, d)})
+        lay = {"W_D": take(d, d), "w": take(d), "K": take(Wc, d), "k": take(d),
+               "A_D": take(d, d), "b": take(d), "U": take(d, d), "V": take(d, d)}
+        if blk is not None:
+            lay["U"] = lay["U"] * blk
+            lay["V"] = lay["V"] * blk
+        prm["layers"].append(lay)
     for _ in range(L + 1):
         rows = [take(12 * s + 1) for _ in range(d)]
         blk = torch.stack(rows)  # [d, 12s+1]
