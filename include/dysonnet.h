@@ -80,11 +80,14 @@ typedef enum { DN_PATH_ABACUS = 0, DN_PATH_FULL = 1 } dn_path;
  * token spins per token (patching, Sec. V; 0 or 1 = one spin per site, at most 4): token tau
  * holds spins token*tau .. token*tau + token - 1 and is embedded as sum_k E_k s_(token*tau + k),
  * likewise the phi stream with E_phi,k. Spin arrays then hold N * token spins per sample and
- * sites index spins; a flip changes one token, a pair exchange one token or two. */
+ * sites index spins; a flip changes one token, a pair exchange one token or two;
+ * d_block > 0 makes the vertex D = U diag(chi) V block-diagonal in channel blocks of d_block
+ * (Sec. V, the mixture-of-experts remark; d_block divides d): the off-block entries of U and V
+ * in the parameter vector are not used and get zero log-derivatives. */
 typedef struct {
   int32_t N, L, d, s, d_out, w_c;
   int32_t bc, act, inject_phi, prec;
-  int32_t complex_out, token;
+  int32_t complex_out, token, d_block;
 } dn_model_desc;
 
 typedef enum { DN_H_LRTFIM = 0, DN_H_J1J2 = 1 } dn_ham_kind;

@@ -36,7 +36,7 @@ KERNEL_KINDS = ("s4gen", "prep", "phi", "conv", "mix_fwd", "mix_tau", "mix_deep"
 
 class ModelDesc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("N", "L", "d", "s", "d_out", "w_c", "bc", "act", "inject_phi", "prec", "complex_out", "token")]
+                ("N", "L", "d", "s", "d_out", "w_c", "bc", "act", "inject_phi", "prec", "complex_out", "token", "d_block")]
 
 
 class HamDesc(ctypes.Structure):
@@ -119,7 +119,7 @@ def _ptr(t):
 def make_desc(shape, prec: str = "fp32") -> ModelDesc:
     return ModelDesc(shape.N, shape.L, shape.d, shape.s, shape.d_out, shape.w_c, BC[shape.bc],
                      ACT[shape.act], shape.inject_phi, PREC[prec], getattr(shape, "complex_out", 0),
-                     getattr(shape, "token", 1))
+                     getattr(shape, "token", 1), getattr(shape, "d_block", 0))
 
 
 def make_ham(ham) -> HamDesc:

@@ -1185,6 +1185,11 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
     PScope ps(m, DN_K_OTHER, st, 2.0 * Bc * nmix * dd * (double)TG * NPc, (double)Bc * nmix * dd * TG * sizeof(T));
     s4grad_kernel<T><<<dim3(nmix * dd, (Bc + 63) / 64, (NPc + 63) / 64), 256, 0, st>>>(a);
   }
+  if (d.d_block > 0 && d.d_block < dd)
+    for (int tl = 0; tl < L; ++tl) {
+      const long offU = m->lay.off_layers + (long)tl * lay + 2L * dd * dd + 3L * dd + (long)Wc * dd;
+      block_grad_mask_kernel<T><<<256, 256, 0, st>>>(grads, Bc, Pn, offU, dd, d.d_block);
+    }
   HIPCHK(hipGetLastError());
   return DN_OK;
 }
@@ -1478,6 +1483,10 @@ bool check_desc(const dn_model_desc* d, std::string* why) {
   if (d->prec < 0 || d->prec > 2) { *why = "bad prec"; return false; }
   if (d->complex_out != 0 && d->complex_out != 1) { *why = "complex_out must be 0 or 1"; return false; }
   if (d->token < 0 || d->token > 4) { *why = "token must be in [0, 4] (0 = 1)"; return false; }
+  if (d->d_block < 0 || (d->d_block > 0 && d->d % d->d_block != 0)) {
+    *why = "d_block must be 0 or divide d";
+    return false;
+  }
   return true;
 }
 
@@ -1789,6 +1798,7 @@ dn_status dn_model_set_params(dn_model* m, const double* params, int on_device, 
   a.params = m->params; a.taps64 = m->taps64; a.N = d.N; a.Np = m->Np; a.L = d.L; a.d = d.d; a.DP = m->DP;
   a.s = d.s; a.w_c = d.w_c; a.d_out = d.d_out; a.periodic = d.bc == DN_BC_PERIODIC; a.off_layers = m->lay.off_layers; a.off_A = m->lay.off_A;
   a.tok = d.token;
+  a.dblk = d.d_block;
   TableBufs<double>& t = m->t64;
   a.E = t.E; a.Ephi = t.Ephi; a.wE1 = t.wE1; a.WDt = t.WDt; a.ADt = t.ADt; a.Ut = t.Ut; a.Vt = t.Vt;
   a.Um = t.Um; a.Vm = t.Vm; a.wv = t.wv; a.Kc = t.Kc; a.kv = t.kv; a.bv = t.bv; a.taps = t.taps;

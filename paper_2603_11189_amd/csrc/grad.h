@@ -379,6 +379,18 @@ __global__ __launch_bounds__(256) void tapgrad_kernel(TapGradArgs<T> A) {
   }
 }
 
+// The off-block entries of U and V of a block-diagonal vertex are not parameters: their
+// gradients (U then V, d x d each, from offU) are set to zero.
+template <typename T>
+__global__ void block_grad_mask_kernel(T* __restrict__ grads, int B, long Pn, long offU, int d, int dblk) {
+  const long per = 2L * d * d, n = (long)B * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long b = i / per, e = i - b * per;
+    const int mo = (int)(e % ((long)d * d)), r = mo / d, c = mo - r * d;
+    if (r / dblk != c / dblk) grads[b * Pn + offU + e] = T(0);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Read-out gradients per sample: dOmega_k = tanh(Omega_k); rho_c = (1/N) sum_i omega_{i,c} R_{i,c};
 // a complex read-out (one unit z = Omega_0 + i Omega_1, t = tanh z) has d log psi = t (dOmega_0 +

@@ -200,6 +200,7 @@ struct PrepArgs {
   const double* params;
   const double* taps64;  // [L+1][d][2N-1]
   int N, Np, L, d, DP, s, w_c, d_out, periodic, tok;
+  int dblk;                                // > 0: U and V block-diagonal in channel blocks of dblk
   long off_layers, off_A;
   // outputs (double tables)
   double *E, *Ephi, *wE1;                  // [tok][DP]: per position inside a token
@@ -241,12 +242,14 @@ __global__ void prep_kernel(PrepArgs a) {
     const double* U = AD + d * d + d;
     const double* V = U + d * d;
     bool in = (row < d && col < d);
+    // the block-diagonal vertex: U and V vanish off the channel blocks
+    const bool uv = in && (a.dblk <= 0 || row / a.dblk == col / a.dblk);
     a.WDt[idx] = in ? WD[col * d + row] : 0.0;
     a.ADt[idx] = in ? AD[col * d + row] : 0.0;
-    a.Ut[idx] = in ? U[col * d + row] : 0.0;
-    a.Vt[idx] = in ? V[col * d + row] : 0.0;
-    a.Um[idx] = in ? U[row * d + col] : 0.0;
-    a.Vm[idx] = in ? V[row * d + col] : 0.0;
+    a.Ut[idx] = uv ? U[col * d + row] : 0.0;
+    a.Vt[idx] = uv ? V[col * d + row] : 0.0;
+    a.Um[idx] = uv ? U[row * d + col] : 0.0;
+    a.Vm[idx] = uv ? V[row * d + col] : 0.0;
     a.ADm[idx] = in ? AD[row * d + col] : 0.0;
     a.WDm[idx] = in ? WD[row * d + col] : 0.0;
   }
