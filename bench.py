@@ -127,7 +127,7 @@ def _pmc_rows(d: str):
 
 
 def summarize(args) -> None:
-    """Turn raw rocprofv3 output (gpurun_out/) into the short summaries kept in profiles/."""
+    """Turn raw rocprofv3 output directories into the short summaries kept in profiles/."""
     import collections
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     wl = args.workload
@@ -270,8 +270,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the estimator shards by "
-              "sample; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the estimator would shard "
+              "by sample). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -18,7 +18,7 @@ Modules
   grad         per-sample d log psi / d theta by reverse-mode autodiff of ``model``
 
 Every function cites the passage of the paper it follows. Readings of passages that
-are silent, ambiguous or garbled are listed in the design doc and repeated where used.
+are silent, ambiguous or garbled are stated where they are used.
 Nothing here is "parity unpinned": each part is pinned by a test in
 ``tests/test_oracle_*.py`` against closed forms, invariants or brute force.
 """

@@ -5,7 +5,7 @@ and the pivot-class induction of App. "Induction Proof of ABACUS". Background op
 are materialised as dense (N*d) x (N*d) matrices, so this is for small N*d only; it is
 the brute-force check of the method, not a fast path.
 
-Readings (listed in DESIGN.md):
+Readings of the paper:
   * the printed recurrence and read-out omit the words whose only scattering is the
     input change E*Delta-sigma itself ("pivot 0"); the induction's base case contains
     it. Here it is included: e^(0) = E (s' - s) on the cluster, with links from it to

@@ -10,7 +10,7 @@ quantity ABACUS accelerates: log psi(s') - log psi(s) from two full evaluations
 
 Layout: activations are [batch, site, channel]; matrices are [out, in].
 
-Readings of the paper used here (each listed in the design doc):
+Readings of the paper used here (where it is silent, ambiguous or garbled):
   * products of blocks apply block 1 first (Eq. (COBALT_recurrence));
   * the residual sum runs over h^(0) = E s and every block output (Eq. (wavefunc), M=0..L);
   * phi^(0) = E_phi s; block l computes phi^(l) and gates with chi^(l) = g(A_D phi^(l) + b),
