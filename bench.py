@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -251,6 +252,8 @@ def main():
                     help="stochastic-reconfiguration update from the workload's per-sample log-derivatives")
     ap.add_argument("--sweep", action="store_true",
                     help="ABACUS vs full re-evaluation for N in 64..512 at L = 2 and 4 (one JSON line each)")
+    ap.add_argument("--inject", action="store_true",
+                    help="the workload's network with phi injected into the h stream (Fig. 1c block)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="with --sweep: the paper's matched runtime shapes instead (L=2, d=2, s=12, periodic, "
                          "Kac-normalised Ising J=-5, alpha=6, 1024 samples; N up to the library's 512)")
@@ -294,6 +297,8 @@ def main():
         return
     w = di.WORKLOADS[args.workload]
     shape, ham = w.model, w.ham
+    if args.inject:  # same parameter layout, phi added to each mixer input
+        shape = dataclasses.replace(shape, inject_phi=1)
     Np = (shape.N + 63) // 64 * 64  # the library's padded chain length
     prec = args.prec or w.prec
     B = w.B
@@ -390,7 +395,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mixed (hi + lo bf16 operands, f32 accumulate)"}[prec],
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": shape.N, "L": shape.L, "d": shape.d, "s": shape.s,
+        "config": {"workload": args.workload + ("_inject_phi" if args.inject else ""), "N": shape.N, "L": shape.L,
+                   "d": shape.d, "s": shape.s,
                    "B": B, "hamiltonian": f"{ham.kind} {ham.bc} J={ham.J} alpha={ham.alpha} h={ham.h}"
                    if ham.kind == "lrtfim" else f"j1j2 {ham.bc} J1={ham.J1} J2={ham.J2}",
                    "params": f"N(0,0.1^2) seed {w.param_seed}" if args.scale == "baseline" else "stress draw",

@@ -457,7 +457,8 @@ dn_status launch_deep(dn_model* m, const MixArgs<T>& a, int F, hipStream_t st, i
   if (LAST) {
     PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * dr * dr,
               (double)F * (m->Np / 64) * SLICE_WIN * dr * sizeof(T) + (double)F * WL * dr * sizeof(T) * 2);
-    last_finish_kernel<T, DP><<<F, 64, 2 * DP * SLICE_WIN * sizeof(T), st>>>(a);
+    if (a.dphi) last_finish_kernel<T, DP, true><<<F, 64, 2 * DP * SLICE_WIN * sizeof(T), st>>>(a);
+    else last_finish_kernel<T, DP><<<F, 64, 2 * DP * SLICE_WIN * sizeof(T), st>>>(a);
     HIPCHK(hipGetLastError());
   }
   return DN_OK;
@@ -493,8 +494,8 @@ dn_status launch_deep_any(dn_model* m, const MixArgs<T>& a, int F, hipStream_t s
 }
 
 // Forward of C configurations listed by `map` entries [cfg0, cfg0+C). rho[C][2] receives
-// Omega. With caches (ABACUS background), a/chi/p0 of every block are written layer-major
-// [L][C][DP][Np].
+// Omega. With caches (ABACUS background), a/chi/p0 of every block (and phi^(1..L) when
+// cache_phi is given) are written layer-major [L][C][DP][Np].
 // Checkpoints of the gradient forward: h^(l) for l = 0..L-1 and phi^(l) for l = 1..L-1
 // ([L][C][DP][Np] each, phi slot 0 unused) and the residual sum R ([C][DP][Np]).
 template <typename T> struct Ckpt {
@@ -505,7 +506,7 @@ template <typename T> struct Ckpt {
 template <typename T, int DP>
 dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, int C, double* rho,
                         T* cache_a, T* cache_chi, T* cache_p0, hipStream_t st, Ckpt<T> ck = Ckpt<T>(),
-                        T* fields = nullptr) {
+                        T* fields = nullptr, T* cache_phi = nullptr) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L;
   const long fld = (long)C * DP * Np;
@@ -536,7 +537,10 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
     a.u_out = ck.h ? ck.h : u; a.rho = rho; a.R_out = ck.R;
     if (ck.phi && l >= 1) a.phi_in = ck.phi + (long)l * fld;       // phi^(l) checkpoint (block l+1 reads it)
     if (ck.phi && l + 1 < L) a.phi_out = ck.phi + (long)(l + 1) * fld;
-    return launch_phi<T, DP>(m, a, C, st);
+    STCHK((launch_phi<T, DP>(m, a, C, st)));
+    // phi^(l+1) of the background (phi injected: ABACUS needs it on the slices)
+    if (cache_phi) HIPCHK(hipMemcpyAsync(cache_phi + (long)l * fld, phi, fld * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return DN_OK;
   };
   STCHK(phi_pass(0));
   for (int l = 0; l < L; ++l) {
@@ -806,7 +810,11 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
                       double* logpsi, double* logratio, int ext_max, hipStream_t st, double* dom = nullptr) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
-  const bool shallow = L <= 2;
+  // phi injected into the h stream: the input change of block l + 1 is dh^(l) + dphi^(l+1),
+  // a vector on S_(l+1) rather than a multiple of E at the cluster, so every depth takes the
+  // full-chain propagation (L >= 2)
+  const bool inj = d.inject_phi != 0;
+  const bool shallow = L <= 2 && !inj;
   // identity map for the background forward
   int32_t *idb, *idm;
   STCHK(identity_map(m, "ab_idb", "ab_idm", B, &idb, &idm, st));
@@ -823,7 +831,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   const int ND = lam_nd(wc, ext_max), dlo = -(2 * wc + ext_max);
   // samples per chunk: the flip fields dominate (deep networks: 2 fields of [F][DP][Np])
   const size_t per_flip = shallow ? (size_t)L * Wmax * DP * sizeof(T) + sizeof(int4)
-                                  : (size_t)DP * Np * sizeof(T) * 2 + (size_t)L * Wmax * DP * sizeof(T) +
+                                  : (size_t)DP * Np * sizeof(T) * 2 + (size_t)(inj ? 2 : 1) * L * Wmax * DP * sizeof(T) +
                                         (size_t)(Np / 64) * SLICE_WIN * DP * sizeof(T);
   const size_t flips_budget = std::max<size_t>(1024, m->flip_budget / per_flip);
   const int Bc_max = (int)std::max<size_t>(1, std::min<size_t>(shallow ? 4096 : 1024, flips_budget / std::max(M_max, 1)));
@@ -831,8 +839,9 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   // mixer input; two-block networks also T^(0) with its mixer input and Lam) per sample; a
   // large chunk keeps the forward launches wide, the flips then run in chunks of Bc_max
   // samples inside it
-  const size_t per_sample = (size_t)(3 * L + 4 + (L == 2 ? 4 : 0)) * DP * Np * sizeof(T) +
-                            (L == 2 ? (size_t)d.N * ND * DP * sizeof(T) : 0);
+  const bool two = shallow && L == 2;
+  const size_t per_sample = (size_t)((inj ? 4 : 3) * L + 4 + (two ? 4 : 0)) * DP * Np * sizeof(T) +
+                            (two ? (size_t)d.token * d.N * ND * DP * sizeof(T) : 0);
   const int Bf_max = (int)std::max<size_t>(1, std::min<size_t>(B, ((size_t)6 << 30) / per_sample));
   for (int bf0 = 0; bf0 < B; bf0 += Bf_max) {
   const int Bf = std::min(Bf_max, B - bf0);
@@ -844,7 +853,13 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   STCHK(ws_get(m, "ab_tz", (size_t)2 * fldB * sizeof(T), &ptz));
   STCHK(ws_get(m, "ab_tau", (size_t)2 * fldB * sizeof(T), &ptau));
   T *a0 = (T*)pa, *chi0 = (T*)pc, *p0 = (T*)pp, *tz = (T*)ptz, *tau = (T*)ptau;
-  STCHK((forward_chunk<T, DP>(m, spins, idmap, bf0, Bf, Om0 + 2L * bf0, a0, chi0, p0, st)));
+  T* phi0 = nullptr;
+  if (inj) {
+    void* pph;
+    STCHK(ws_get(m, "ab_phi0", (size_t)L * fldB * sizeof(T), &pph));
+    phi0 = (T*)pph;
+  }
+  STCHK((forward_chunk<T, DP>(m, spins, idmap, bf0, Bf, Om0 + 2L * bf0, a0, chi0, p0, st, Ckpt<T>(), nullptr, phi0)));
   // tau = G^(L)T D0^(L)T Wk; deep networks read out the last block with Wk + tau, and for
   // shallow ones Wk + tau is the output link of the input (L = 1) or of block 1 (L = 2): the
   // conv adds Wk
@@ -858,7 +873,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   }
   T* T0 = tau;  // output link of the input change
   T* lam = nullptr;
-  if (L == 2) {
+  if (two) {
     // T^(0) = Wk + G^(1)T D0^(1)T T^(1), T^(1) = Wk + tau
     void *pt0z, *pt0, *plam;
     STCHK(ws_get(m, "ab_t0z", (size_t)2 * fldB * sizeof(T), &pt0z));
@@ -879,11 +894,12 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     const int F = h_offs ? h_offs[b0 + Bc] - f0 : Bc * M_max;
     const DynRange dyn{h_offs ? nullptr : offs, b0, Bc};
     if (F == 0) continue;
-    void *pdchi = nullptr, *pgeom = nullptr, *prho, *pdu, *pw;
+    void *pdchi = nullptr, *pgeom = nullptr, *prho, *pdu, *pw, *pdphi = nullptr;
     if (!shallow) {  // the deep path keeps the slices and the cluster geometry for its later kernels
       STCHK(ws_get(m, "ab_dchi", (size_t)F * L * Wmax * DP * sizeof(T), &pdchi));
       STCHK(ws_get(m, "ab_geom", (size_t)F * sizeof(int4), &pgeom));
     }
+    if (inj) STCHK(ws_get(m, "ab_dphi", (size_t)F * L * Wmax * DP * sizeof(T), &pdphi));
     const int nt = Np / 64;
     T* dchi = (T*)pdchi;
     int4* geom = (int4*)pgeom;
@@ -891,7 +907,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     sa.tb = tb; sa.N = d.N; sa.Np = Np; sa.L = L; sa.w_c = wc; sa.periodic = d.bc == DN_BC_PERIODIC;
     sa.act = d.act; sa.F = F; sa.f0 = f0; sa.b0 = bf0; sa.Bc = Bf; sa.map = fmap; sa.spins = spins;
     sa.a0 = a0; sa.chi0 = chi0; sa.dchi = dchi; sa.geom = geom; sa.Wmax = Wmax; sa.err = (int*)perr;
-    sa.ext_max = ext_max; sa.dyn = dyn; sa.tok = d.token;
+    sa.ext_max = ext_max; sa.dyn = dyn; sa.tok = d.token; sa.phi0 = phi0; sa.dphi = (T*)pdphi;
     double slice_fl = 0.0;
     for (int l = 1; l <= L; ++l) slice_fl += 2.0 * (2 * (l - 1) * wc + 1 + 2 * l * wc + 1) * d.d * d.d;
     // P flips side by side per product (slices are at most 16 sites wide: P >= 4)
@@ -910,8 +926,13 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
     }
     {
       PScope ps(m, DN_K_SLICE, st, slice_fl * F, (double)F * L * Wmax * d.d * sizeof(T));
-      allow_lds(slice_mma_kernel<T, DP>, slds);
-      slice_mma_kernel<T, DP><<<slm_grid((F + P - 1) / P), 4 * DP, slds, st>>>(sa);
+      if (inj) {
+        allow_lds(slice_mma_kernel<T, DP, true>, slds);
+        slice_mma_kernel<T, DP, true><<<slm_grid((F + P - 1) / P), 4 * DP, slds, st>>>(sa);
+      } else {
+        allow_lds(slice_mma_kernel<T, DP>, slds);
+        slice_mma_kernel<T, DP><<<slm_grid((F + P - 1) / P), 4 * DP, slds, st>>>(sa);
+      }
       HIPCHK(hipGetLastError());
     }
     // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
@@ -934,9 +955,19 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.p0L = p0 + (long)(L - 1) * fldB; a.Om0 = Om0; a.logratio = logratio; a.dom = dom; a.slice_part = (T*)psp;
       a.cplx = d.complex_out;
       a.tok = d.token;
-      const bool first = (l == 1), last = (l == L - 1);
+      a.dphi = (T*)pdphi;
+      // phi injected: block 1 mixes the field e^(0) + dphi^(1) like any later block
+      const bool first = (l == 1) && !inj, last = (l == L - 1);
+      if (inj && l == 1) {
+        inject_source_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * DP * (Np / 4) + 255) / 256), 256, 0, st>>>(a);
+        HIPCHK(hipGetLastError());
+      }
       if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
+      if (inj && !last) {
+        inject_add_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * Wmax * DP + 255) / 256), 256, 0, st>>>(a);
+        HIPCHK(hipGetLastError());
+      }
     }
   }
   }
@@ -947,7 +978,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
 
 dn_status abacus_supported(const dn_model* m) {
   const dn_model_desc& d = m->desc;
-  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 is not implemented on the GPU");
+  if (d.inject_phi && d.L < 2) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 needs L >= 2");
   if (2 + 2 * d.L * d.w_c + 1 > SLICE_WIN) return fail(DN_EUNSUPPORTED, "ABACUS slice wider than 16 sites (needs L * w_c <= 6)");
   return DN_OK;
 }

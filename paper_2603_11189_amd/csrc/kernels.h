@@ -724,6 +724,7 @@ template <typename T> struct MixArgs {
   T* slice_part;         // last block: [F][Np/64][SLICE_WIN][DP] partial slices
   int cplx;              // 1: complex read-out unit Omega_0 + i Omega_1
   int tok;               // spins per token (spins: [B][N * tok]; geom's flip sites index spins)
+  const T* dphi;         // phi injected: dphi^(l) on S_l [F][L][Wmax][DP] (slice recompute)
 };
 
 constexpr int MIX_XS = 68;      // LDS row stride of a wave tile (64 sites + 4; gradient kernels)
@@ -1517,7 +1518,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 // slices into y_L, forms e^(L) = U (dchi^(L) * (p0^(L) + V y_L)) on S_L, reads out e^(L)
 // and e^(0), adds the deep blocks' read-outs rho[l][f][t] and writes
 // log psi(s')/psi(s) = sum_k lcd(Omega0_k, dOmega_k) in float64 (complex read-out: put_ratio).
-template <typename T, int DP>
+// INJ (phi injected into the h stream, Fig. 1c): the input change of block L is
+// dh^(L-1) + dphi^(L); the tiled block read dh^(L-1) out and mixed it, here the dphi^(L) part
+// joins y_L (its mixer output on S_L, the taps g^(L)(t - t') of slice positions t, t') and
+// the read-out through tau = G^(L)T D0^(L)T Wk alone (phi is not part of the residual sum).
+template <typename T, int DP, bool INJ = false>
 __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using M = Mma<T>;
@@ -1559,6 +1564,15 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
       for (int t = 0; t < SLICE_WIN; ++t) v[t] = pp[((long)tile * SLICE_WIN + min(t, WL - 1)) * DP + c];
 #pragma unroll
       for (int t = 0; t < SLICE_WIN; ++t) s[t] += v[t];
+    }
+    if constexpr (INJ) {
+      const T* dp = A.dphi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP + c;
+      const T* tc = A.tapsL + (long)c * tap_stride(Np) + tap_off(Np);
+      for (int t2 = 0; t2 < WL; ++t2) {
+        const T x = dp[(long)t2 * DP];
+#pragma unroll
+        for (int t = 0; t < SLICE_WIN; ++t) s[t] += tc[t - t2] * x;
+      }
     }
 #pragma unroll
     for (int t = 0; t < SLICE_WIN; ++t) Y[c * SLICE_WIN + t] = (t < WL) ? s[t] : T(0);
@@ -1626,6 +1640,19 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
       }
     }
   }
+  if constexpr (INJ) {  // dphi^(L) read out through tau = (Wk + tau) - Wk
+    const T* dp = A.dphi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP;
+    for (int c = lane; c < DP; c += 64)
+      for (int t = 0; t < WL; ++t) {
+        int st = loL + t;
+        if (A.periodic) st %= N;
+        else if (st < 0 || st >= N) continue;
+        const long o = (long)c * Np + st;
+        const double x = (double)dp[(long)t * DP + c];
+        o0 += ((double)A.tau[2 * bL + o] - (double)A.tb.Wk[o]) * x;
+        o1 += ((double)A.tau[2 * bL + (long)DP * Np + o] - (double)A.tb.Wk[(long)DP * Np + o]) * x;
+      }
+  }
   // read-outs of the tiled deep blocks 1 .. L-1, lanes over (block, tile)
   for (int bt = lane; bt < (A.L - 1) * nt; bt += 64) {
     const double* rp = A.rho + (long)(bt / nt) * A.rho_blk + ((long)g * nt + bt % nt) * 2;
@@ -1638,6 +1665,61 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     const long o = (long)bg * A.map.M_max + m;
     put_ratio(A.logratio, o, A.Om0[2 * bg], A.Om0[2 * bg + 1], o0, o1, A.cplx);
     if (A.dom) { A.dom[2 * o] = o0; A.dom[2 * o + 1] = o1; }
+  }
+}
+
+// phi injected into the h stream (Fig. 1c): the input change of block 1 is
+// du^(1) = e^(0) + dphi^(1), e^(0)_c = -2 s_j E_(k(j), c) at the tokens of the flipped spins
+// and dphi^(1) on S_1. Writes the whole field [F][DP][Np] (zero elsewhere, and past the
+// chain end). One thread per four sites.
+template <typename T, int DP>
+__global__ __launch_bounds__(256) void inject_source_kernel(MixArgs<T> A) {
+  const int F = A.dyn.count(A.C), cfg0 = A.dyn.first(A.cfg0);
+  const int N = A.N, Np = A.Np, wc = A.w_c, q4 = Np / 4;
+  const long n = (long)F * DP * q4;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+    const int i4 = (int)(idx % q4), c = (int)((idx / q4) % DP);
+    const int f = (int)(idx / ((long)q4 * DP));
+    const int4 sg = A.geom[f];
+    const int W1 = sg.y + 2 * wc + 1, lo = sg.x - wc;
+    const int8_t* sp = A.spins + (long)A.map.cb[cfg0 + f] * N * A.tok;
+    const T* dp = A.dphi + (long)f * A.L * A.Wmax * DP + c;  // block 1's slot
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 4 * i4 + e;
+      T x = 0;
+      if (i < N) {
+        int t = i - lo;
+        if (A.periodic) t = ((t % N) + N) % N;
+        if (t >= 0 && t < W1) x = dp[(long)t * DP];
+        for (int q = 0; q < 2; ++q) {
+          const int js = q == 0 ? sg.z : sg.w;
+          if (js >= 0 && js / A.tok == i) x += (T)(-2 * sp[js]) * A.tb.E[(js % A.tok) * DP + c];
+        }
+      }
+      v[e] = x;
+    }
+    st4(A.out + ((long)f * DP + c) * Np + 4 * i4, v);
+  }
+}
+
+// phi injected: the input change of block l + 1 is the tiled block's dh^(l) plus
+// dphi^(l+1) on S_(l+1); adds the latter to A.out (A.l = l).
+template <typename T, int DP>
+__global__ __launch_bounds__(256) void inject_add_kernel(MixArgs<T> A) {
+  const int F = A.dyn.count(A.C);
+  const int N = A.N, Np = A.Np, wc = A.w_c, l1 = A.l + 1;
+  const long n = (long)F * A.Wmax * DP;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % DP), t = (int)((idx / DP) % A.Wmax);
+    const int f = (int)(idx / ((long)DP * A.Wmax));
+    const int4 sg = A.geom[f];
+    if (t >= sg.y + 2 * l1 * wc + 1) continue;
+    int i = sg.x - l1 * wc + t;
+    if (A.periodic) i = ((i % N) + N) % N;
+    else if (i < 0 || i >= N) continue;
+    A.out[((long)f * DP + c) * Np + i] += A.dphi[(((long)f * A.L + (l1 - 1)) * A.Wmax + t) * DP + c];
   }
 }
 
@@ -1661,6 +1743,8 @@ template <typename T> struct SliceArgs {
   int ext_max;            // widest cluster extent the launch's links were built for
   DynRange dyn;           // flips counted on the device (nullable)
   int tok;                // spins per token (spins: [B][N * tok]; sites index spins)
+  const T* phi0;          // phi injected: background phi^(l), l = 1..L [L][Bc][DP][Np]
+  T* dphi;                // phi injected: dphi^(l) = phi'^(l) - phi0^(l) on S_l [F][L][Wmax][DP]
 };
 
 // The slice recompute with its two channel mixes on the matrix cores. A workgroup takes
@@ -1775,7 +1859,8 @@ __device__ inline void slm_geometry(const SliceArgs<T>& A, int* gs, int P, int f
 // Blocks 1 .. L of the slice recompute (L = LF when LF > 0). epi(l, n, r, v) receives the
 // vertex change v = chi'(l) - chi0(l) of the lane's channel 16 w + row(lane, r) at its
 // column 16 n + lane % 16 of S_l (zero for columns that hold no slice site of a flip).
-template <typename T, int DP, int LF, bool TOK, typename EPI>
+// INJ: the phi-stream change dphi^(l) on S_l is also written (zero outside an open chain).
+template <typename T, int DP, int LF, bool TOK, bool INJ = false, typename EPI>
 __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int* gs, int P, int lda, EPI&& epi) {
   constexpr int NTH = 4 * DP;
   const int N = A.N, Np = A.Np, wc = A.w_c;
@@ -1901,7 +1986,13 @@ __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int
 #pragma unroll
         for (int u = 0; u < 7; ++u)
           if (u <= 2 * wc) sacc += kr[u] * a[u];
-        pr[j] = inside(g[1] - l * wc + t) ? act_fn<T>(A.act, sacc) : T(0);
+        const int ii = g[1] - l * wc + t;
+        const T v = inside(ii) ? act_fn<T>(A.act, sacc) : T(0);
+        pr[j] = v;
+        if constexpr (INJ) {
+          const T v0 = inside(ii) ? A.phi0[(((long)lp * A.Bc + (g[0] - A.b0)) * DP + c) * Np + wrap(ii)] : T(0);
+          A.dphi[(((long)g[5] * A.L + lp) * A.Wmax + t) * DP + c] = v - v0;
+        }
       }
     }
     __syncthreads();
@@ -1925,7 +2016,7 @@ __device__ inline void slm_layers(const SliceArgs<T>& A, T* ph, T* ab, const int
   }
 }
 
-template <typename T, int DP>
+template <typename T, int DP, bool INJ = false>
 __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int Wc = A.ext_max + 2 * A.L * A.w_c + 1;  // widest S_L of the launch
@@ -1940,7 +2031,7 @@ __global__ __launch_bounds__(4 * DP) void slice_mma_kernel(SliceArgs<T> A) {
   slm_geometry<true>(A, gs, P, fg, nfl, A.dyn.first(A.f0), true);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, wc = A.w_c;
-  slm_layers<T, DP, 0, true>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) {
+  slm_layers<T, DP, 0, true, INJ>(A, ph, ab, gs, P, lda, [&](int l, int n, int r, T v) {
     const int Wlm = A.ext_max + 2 * l * wc + 1;
     const int j = 16 * n + col;
     const int p = j / Wlm, t = j - p * Wlm;
