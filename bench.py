@@ -89,6 +89,7 @@ def kernel_class(name: str) -> str:
         return {"0": "mix_fwd", "1": "mix_tau", "2": "mix_deep"}[mode]
     for key, cls in (("conv_kernel", "conv"), ("conv_split_kernel", "conv"), ("phi_kernel", "phi"), ("slice_mma_kernel", "slice"),
                      ("deep_kernel", "mix_deep"), ("last_finish_kernel", "tail"), ("shallow_kernel", "tail"),
+                     ("inject_w1_kernel", "conv"), ("inject_add_kernel", "mix_deep"),
                      ("lam_fwd_kernel", "link"), ("lam_gemm_kernel", "link"), ("lam_inv_kernel", "link"),
                      ("lam_param_kernel", "prep"), ("s4_taps_kernel", "s4gen"), ("prep_kernel", "prep"),
                      ("connected_kernel", "gen"), ("eloc_kernel", "eloc")):

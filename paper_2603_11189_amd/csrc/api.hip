@@ -956,15 +956,23 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       a.cplx = d.complex_out;
       a.tok = d.token;
       a.dphi = (T*)pdphi;
-      // phi injected: block 1 mixes the field e^(0) + dphi^(1) like any later block
+      // phi injected: block 1's mixer output G^(1) (e^(0) + dphi^(1)) is formed from the taps
+      // on S_1, then block 1 runs like any later block
       const bool first = (l == 1) && !inj, last = (l == L - 1);
       if (inj && l == 1) {
-        inject_source_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * DP * (Np / 4) + 255) / 256), 256, 0, st>>>(a);
+        MixArgs<T> aw = a;
+        aw.out = w;
+        const double Wl = 2 * wc + 1 + ext_max;
+        PScope ps(m, DN_K_CONV, st, 2.0 * F * Wl * d.N * d.d, (double)F * d.N * d.d * sizeof(T));
+        inject_w1_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * DP * (Np / 4) + 255) / 256), 256, 0, st>>>(aw);
         HIPCHK(hipGetLastError());
+      } else if (!first) {
+        STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       }
-      if (!first) STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
       STCHK((launch_deep_any<T, DP>(m, a, F, st, Bc, first, last)));
       if (inj && !last) {
+        const double Wl = 2 * (l + 1) * wc + 1 + ext_max;
+        PScope ps(m, DN_K_MIX_DEEP, st, (double)F * Wl * d.d, 3.0 * F * Wl * d.d * sizeof(T));
         inject_add_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * Wmax * DP + 255) / 256), 256, 0, st>>>(a);
         HIPCHK(hipGetLastError());
       }

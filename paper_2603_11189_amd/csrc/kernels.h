@@ -1566,12 +1566,19 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
       for (int t = 0; t < SLICE_WIN; ++t) s[t] += v[t];
     }
     if constexpr (INJ) {
+      // the channel's taps g^(L)(t - t') for |t - t'| < SLICE_WIN, held in registers
       const T* dp = A.dphi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP + c;
-      const T* tc = A.tapsL + (long)c * tap_stride(Np) + tap_off(Np);
-      for (int t2 = 0; t2 < WL; ++t2) {
-        const T x = dp[(long)t2 * DP];
+      const T* tc = A.tapsL + (long)c * tap_stride(Np) + tap_off(Np) - (SLICE_WIN - 1);
+      T tw[2 * SLICE_WIN - 1];
 #pragma unroll
-        for (int t = 0; t < SLICE_WIN; ++t) s[t] += tc[t - t2] * x;
+      for (int k = 0; k < 2 * SLICE_WIN - 1; ++k) tw[k] = tc[k];
+#pragma unroll
+      for (int t2 = 0; t2 < SLICE_WIN; ++t2) {
+        if (t2 < WL) {
+          const T x = dp[(long)t2 * DP];
+#pragma unroll
+          for (int t = 0; t < SLICE_WIN; ++t) s[t] += tw[t - t2 + SLICE_WIN - 1] * x;
+        }
       }
     }
 #pragma unroll
@@ -1641,12 +1648,15 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     }
   }
   if constexpr (INJ) {  // dphi^(L) read out through tau = (Wk + tau) - Wk
+    // lanes (channel c0 + lane / 16, slice position lane % 16): contiguous sites per channel
     const T* dp = A.dphi + ((long)g * A.L + (A.L - 1)) * A.Wmax * DP;
-    for (int c = lane; c < DP; c += 64)
-      for (int t = 0; t < WL; ++t) {
-        int st = loL + t;
-        if (A.periodic) st %= N;
-        else if (st < 0 || st >= N) continue;
+    const int t = lane & 15;
+    int st = loL + t;
+    bool ok = t < WL;
+    if (A.periodic) st %= N;
+    else ok = ok && st >= 0 && st < N;
+    if (ok)
+      for (int c = lane >> 4; c < DP; c += 4) {
         const long o = (long)c * Np + st;
         const double x = (double)dp[(long)t * DP + c];
         o0 += ((double)A.tau[2 * bL + o] - (double)A.tb.Wk[o]) * x;
@@ -1669,13 +1679,15 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
 }
 
 // phi injected into the h stream (Fig. 1c): the input change of block 1 is
-// du^(1) = e^(0) + dphi^(1), e^(0)_c = -2 s_j E_(k(j), c) at the tokens of the flipped spins
-// and dphi^(1) on S_1. Writes the whole field [F][DP][Np] (zero elsewhere, and past the
-// chain end). One thread per four sites.
+// z = e^(0) + dphi^(1) on S_1 (e^(0)_c = -2 s_j E_(k(j), c) at the tokens of the flipped
+// spins), and block 1 mixes it: w(i) = sum_(t in S_1) g^(1)(i - site_t) z_t, written as the
+// whole field [F][DP][Np] (zero past the chain end) that the mixer would produce from z,
+// without forming z as a field. One thread per four sites of one channel.
 template <typename T, int DP>
-__global__ __launch_bounds__(256) void inject_source_kernel(MixArgs<T> A) {
+__global__ __launch_bounds__(256) void inject_w1_kernel(MixArgs<T> A) {
   const int F = A.dyn.count(A.C), cfg0 = A.dyn.first(A.cfg0);
   const int N = A.N, Np = A.Np, wc = A.w_c, q4 = Np / 4;
+  const int TO = tap_off(Np), TS = tap_stride(Np);
   const long n = (long)F * DP * q4;
   for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
     const int i4 = (int)(idx % q4), c = (int)((idx / q4) % DP);
@@ -1684,22 +1696,23 @@ __global__ __launch_bounds__(256) void inject_source_kernel(MixArgs<T> A) {
     const int W1 = sg.y + 2 * wc + 1, lo = sg.x - wc;
     const int8_t* sp = A.spins + (long)A.map.cb[cfg0 + f] * N * A.tok;
     const T* dp = A.dphi + (long)f * A.L * A.Wmax * DP + c;  // block 1's slot
-    T v[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = 4 * i4 + e;
-      T x = 0;
-      if (i < N) {
-        int t = i - lo;
-        if (A.periodic) t = ((t % N) + N) % N;
-        if (t >= 0 && t < W1) x = dp[(long)t * DP];
-        for (int q = 0; q < 2; ++q) {
-          const int js = q == 0 ? sg.z : sg.w;
-          if (js >= 0 && js / A.tok == i) x += (T)(-2 * sp[js]) * A.tb.E[(js % A.tok) * DP + c];
-        }
+    const T* tc = A.taps1 + (long)c * TS + TO + 4 * i4;       // tc[e - site] = g^(1)(i - site)
+    T v[4] = {0, 0, 0, 0};
+    for (int t = 0; t < W1; ++t) {
+      int site = lo + t;
+      if (A.periodic) site = ((site % N) + N) % N;
+      else if (site < 0 || site >= N) continue;
+      T z = dp[(long)t * DP];
+      for (int q = 0; q < 2; ++q) {
+        const int js = q == 0 ? sg.z : sg.w;
+        if (js >= 0 && js / A.tok == site) z += (T)(-2 * sp[js]) * A.tb.E[(js % A.tok) * DP + c];
       }
-      v[e] = x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += tc[e - site] * z;
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (4 * i4 + e >= N) v[e] = 0;
     st4(A.out + ((long)f * DP + c) * Np + 4 * i4, v);
   }
 }
