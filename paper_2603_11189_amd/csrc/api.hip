@@ -964,7 +964,8 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
         aw.out = w;
         const double Wl = 2 * wc + 1 + ext_max;
         PScope ps(m, DN_K_CONV, st, 2.0 * F * Wl * d.N * d.d, (double)F * d.N * d.d * sizeof(T));
-        inject_w1_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * DP * (Np / 4) + 255) / 256), 256, 0, st>>>(aw);
+        if (ext_max + 2 * wc + 1 > INJ_W1) return fail(DN_EUNSUPPORTED, "slice S_1 wider than the injected source handles");
+        inject_w1_kernel<T, DP><<<std::min(F, 16384), 256, 0, st>>>(aw);
         HIPCHK(hipGetLastError());
       } else if (!first) {
         STCHK(launch_conv<T>(m, du, w, tb.taps + (long)(l - 1) * DP * tap_stride(Np), F, st, dyn));
@@ -973,7 +974,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       if (inj && !last) {
         const double Wl = 2 * (l + 1) * wc + 1 + ext_max;
         PScope ps(m, DN_K_MIX_DEEP, st, (double)F * Wl * d.d, 3.0 * F * Wl * d.d * sizeof(T));
-        inject_add_kernel<T, DP><<<(int)std::min<long>(8192, ((long)F * Wmax * DP + 255) / 256), 256, 0, st>>>(a);
+        inject_add_kernel<T, DP><<<std::min(F, 16384), 256, 0, st>>>(a);
         HIPCHK(hipGetLastError());
       }
     }

@@ -1682,57 +1682,73 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
 // z = e^(0) + dphi^(1) on S_1 (e^(0)_c = -2 s_j E_(k(j), c) at the tokens of the flipped
 // spins), and block 1 mixes it: w(i) = sum_(t in S_1) g^(1)(i - site_t) z_t, written as the
 // whole field [F][DP][Np] (zero past the chain end) that the mixer would produce from z,
-// without forming z as a field. One thread per four sites of one channel.
+// without forming z as a field. A lane takes four sites of one channel.
+constexpr int INJ_W1 = 9;  // widest S_1: a pair cluster two sites wide and w_c = 3
 template <typename T, int DP>
 __global__ __launch_bounds__(256) void inject_w1_kernel(MixArgs<T> A) {
   const int F = A.dyn.count(A.C), cfg0 = A.dyn.first(A.cfg0);
   const int N = A.N, Np = A.Np, wc = A.w_c, q4 = Np / 4;
   const int TO = tap_off(Np), TS = tap_stride(Np);
-  const long n = (long)F * DP * q4;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
-    const int i4 = (int)(idx % q4), c = (int)((idx / q4) % DP);
-    const int f = (int)(idx / ((long)q4 * DP));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // one flip per workgroup step: waves over channels, lanes over four-site groups
+  for (int f = blockIdx.x; f < F; f += gridDim.x) {
     const int4 sg = A.geom[f];
     const int W1 = sg.y + 2 * wc + 1, lo = sg.x - wc;
     const int8_t* sp = A.spins + (long)A.map.cb[cfg0 + f] * N * A.tok;
-    const T* dp = A.dphi + (long)f * A.L * A.Wmax * DP + c;  // block 1's slot
-    const T* tc = A.taps1 + (long)c * TS + TO + 4 * i4;       // tc[e - site] = g^(1)(i - site)
-    T v[4] = {0, 0, 0, 0};
-    for (int t = 0; t < W1; ++t) {
-      int site = lo + t;
-      if (A.periodic) site = ((site % N) + N) % N;
-      else if (site < 0 || site >= N) continue;
-      T z = dp[(long)t * DP];
-      for (int q = 0; q < 2; ++q) {
-        const int js = q == 0 ? sg.z : sg.w;
-        if (js >= 0 && js / A.tok == site) z += (T)(-2 * sp[js]) * A.tb.E[(js % A.tok) * DP + c];
+    // slot t holds site lo + t unwrapped (the taps of a ring are periodic; an open chain's
+    // slots outside it hold zero); e^(0) sits at the slots of the cluster's tokens, w_c (the
+    // first flipped spin's token clo) and w_c + ext (the second's)
+    const int t_a = wc, ka = sg.z % A.tok;
+    const int t_b = sg.w >= 0 ? wc + sg.y : -1, kb = sg.w >= 0 ? sg.w % A.tok : 0;
+    const T ca = (T)(-2 * sp[sg.z]), cbv = sg.w >= 0 ? (T)(-2 * sp[sg.w]) : T(0);
+    const T* dp = A.dphi + (long)f * A.L * A.Wmax * DP;  // block 1's slot
+    for (int c = wave; c < DP; c += 4) {
+      T z[INJ_W1];
+#pragma unroll
+      for (int t = 0; t < INJ_W1; ++t) {
+        T x = t < W1 ? dp[(long)t * DP + c] : T(0);
+        if (t == t_a) x += ca * A.tb.E[ka * DP + c];
+        if (t == t_b) x += cbv * A.tb.E[kb * DP + c];
+        z[t] = x;
       }
+      const T* tcc = A.taps1 + (long)c * TS + TO - lo - (INJ_W1 - 1);
+      for (int i4 = lane; i4 < q4; i4 += 64) {
+        // tw[k] = g^(1)(4 i4 + k - (INJ_W1 - 1) - lo): site 4 i4 + e against slot t at k = e - t + 8
+        T tw[INJ_W1 + 3];
+        const T* tc = tcc + 4 * i4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] += tc[e - site] * z;
+        for (int k = 0; k < INJ_W1 + 3; ++k) tw[k] = tc[k];
+        T v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < INJ_W1; ++t) acc += tw[e - t + INJ_W1 - 1] * z[t];
+          v[e] = 4 * i4 + e < N ? acc : T(0);
+        }
+        st4(A.out + ((long)f * DP + c) * Np + 4 * i4, v);
+      }
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (4 * i4 + e >= N) v[e] = 0;
-    st4(A.out + ((long)f * DP + c) * Np + 4 * i4, v);
   }
 }
 
 // phi injected: the input change of block l + 1 is the tiled block's dh^(l) plus
-// dphi^(l+1) on S_(l+1); adds the latter to A.out (A.l = l).
+// dphi^(l+1) on S_(l+1); adds the latter to A.out (A.l = l). One flip per workgroup step,
+// lanes (channel 4 w + lane / 16 + 16 k, slice position lane % 16): contiguous sites.
 template <typename T, int DP>
 __global__ __launch_bounds__(256) void inject_add_kernel(MixArgs<T> A) {
   const int F = A.dyn.count(A.C);
   const int N = A.N, Np = A.Np, wc = A.w_c, l1 = A.l + 1;
-  const long n = (long)F * A.Wmax * DP;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(idx % DP), t = (int)((idx / DP) % A.Wmax);
-    const int f = (int)(idx / ((long)DP * A.Wmax));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = lane & 15;
+  for (int f = blockIdx.x; f < F; f += gridDim.x) {
     const int4 sg = A.geom[f];
     if (t >= sg.y + 2 * l1 * wc + 1) continue;
     int i = sg.x - l1 * wc + t;
     if (A.periodic) i = ((i % N) + N) % N;
     else if (i < 0 || i >= N) continue;
-    A.out[((long)f * DP + c) * Np + i] += A.dphi[(((long)f * A.L + (l1 - 1)) * A.Wmax + t) * DP + c];
+    const T* dp = A.dphi + (((long)f * A.L + (l1 - 1)) * A.Wmax + t) * DP;
+    T* o = A.out + (long)f * DP * Np + i;
+    for (int c = 4 * wave + (lane >> 4); c < DP; c += 16) o[(long)c * Np] += dp[c];
   }
 }
 
