@@ -226,8 +226,8 @@ dn_status dn_connected(const dn_ham_desc* ham, const int8_t* spins, int32_t B, i
  * link tensors" -- are built once per sample); deeper networks also propagate each
  * element's change through the frozen blocks 1 .. L-1 over the whole chain (exact,
  * O(N d^2) per element). With inject_phi = 1 the input change of block l + 1 also holds the
- * phi-stream change on S_(l+1), so every depth takes the whole-chain propagation; one block
- * with inject_phi = 1 gets DN_EUNSUPPORTED on DN_PATH_ABACUS (DN_PATH_FULL takes it).
+ * phi-stream change on S_(l+1), so every depth from two blocks up takes the whole-chain
+ * propagation (one block: the slice work only).
  * logpsi (nullable) receives log psi(s); logratio [B, M_max] gets 0 beyond n_conn.
  * n_conn and sites are validated on the device (DN_EINVAL for n_conn outside [0, M_max],
  * a site outside [0, N) or a pair repeating a site); the per-sample work list comes back to

@@ -812,7 +812,7 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
   const int Np = m->Np, L = d.L, wc = d.w_c;
   // phi injected into the h stream: the input change of block l + 1 is dh^(l) + dphi^(l+1),
   // a vector on S_(l+1) rather than a multiple of E at the cluster, so every depth takes the
-  // full-chain propagation (L >= 2)
+  // full-chain propagation (one block: the slices and the per-flip finish)
   const bool inj = d.inject_phi != 0;
   const bool shallow = L <= 2 && !inj;
   // identity map for the background forward
@@ -935,6 +935,19 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
       }
       HIPCHK(hipGetLastError());
     }
+    if (L == 1) {  // phi injected, one block: no tiled block, the finish takes e^(0) + dphi^(1)
+      MixArgs<T> a{};
+      a.tb = tb; a.N = d.N; a.Np = Np; a.l = 0; a.L = L; a.w_c = wc;
+      a.periodic = d.bc == DN_BC_PERIODIC; a.C = F; a.cfg0 = f0; a.dyn = dyn;
+      a.map = fmap; a.b0 = bf0; a.spins = spins; a.geom = geom; a.dchi = dchi; a.Wmax = Wmax;
+      a.tau = tau; a.tapsL = tb.taps; a.p0L = p0; a.Om0 = Om0; a.logratio = logratio; a.dom = dom;
+      a.cplx = d.complex_out; a.tok = d.token; a.dphi = (T*)pdphi;
+      const int WL = 2 + 2 * wc + 1;
+      PScope ps(m, DN_K_TAIL, st, 4.0 * F * WL * d.d * d.d + 2.0 * F * WL * WL * d.d, (double)F * WL * d.d * sizeof(T) * 6);
+      last_finish_kernel<T, DP, true><<<F, 64, 2 * DP * SLICE_WIN * sizeof(T), st>>>(a);
+      HIPCHK(hipGetLastError());
+      continue;
+    }
     // read-outs of the deep blocks 1 .. L-1 per flip and tile, each stored once
     STCHK(ws_get(m, "ab_rho", (size_t)std::max(L - 1, 1) * F * nt * 2 * sizeof(double), &prho));
     double* rho = (double*)prho;
@@ -987,7 +1000,6 @@ dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* si
 
 dn_status abacus_supported(const dn_model* m) {
   const dn_model_desc& d = m->desc;
-  if (d.inject_phi && d.L < 2) return fail(DN_EUNSUPPORTED, "ABACUS path with inject_phi=1 needs L >= 2");
   if (2 + 2 * d.L * d.w_c + 1 > SLICE_WIN) return fail(DN_EUNSUPPORTED, "ABACUS slice wider than 16 sites (needs L * w_c <= 6)");
   return DN_OK;
 }

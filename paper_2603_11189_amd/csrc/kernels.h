@@ -1522,6 +1522,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deep_occ(si
 // dh^(L-1) + dphi^(L); the tiled block read dh^(L-1) out and mixed it, here the dphi^(L) part
 // joins y_L (its mixer output on S_L, the taps g^(L)(t - t') of slice positions t, t') and
 // the read-out through tau = G^(L)T D0^(L)T Wk alone (phi is not part of the residual sum).
+// With one block there is no tiled block: the input change is e^(0) + dphi^(1), all of it
+// taken here (no partial slices).
+// e^(0) of channel c at the q-th flipped spin of a cluster (zero for an absent second spin):
+// -2 s_j E_(k(j), c), k(j) the spin's position in its token.
+template <typename T, int DP>
+__device__ inline T inj_e0(const MixArgs<T>& A, int4 sg, int bg, int q, int c) {
+  const int js = q == 0 ? sg.z : sg.w;
+  if (js < 0) return T(0);
+  return (T)(-2 * A.spins[(long)bg * A.N * A.tok + js]) * A.tb.E[(js % A.tok) * DP + c];
+}
+
 template <typename T, int DP, bool INJ = false>
 __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1558,7 +1569,7 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     T s[SLICE_WIN];
 #pragma unroll
     for (int t = 0; t < SLICE_WIN; ++t) s[t] = 0;
-    for (int tile = 0; tile < nt; ++tile) {
+    for (int tile = 0; tile < ((!INJ || A.L > 1) ? nt : 0); ++tile) {
       T v[SLICE_WIN];
 #pragma unroll
       for (int t = 0; t < SLICE_WIN; ++t) v[t] = pp[((long)tile * SLICE_WIN + min(t, WL - 1)) * DP + c];
@@ -1572,10 +1583,14 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
       T tw[2 * SLICE_WIN - 1];
 #pragma unroll
       for (int k = 0; k < 2 * SLICE_WIN - 1; ++k) tw[k] = tc[k];
+      const T ea = A.L == 1 ? inj_e0<T, DP>(A, sg, bg, 0, c) : T(0);
+      const T eb = A.L == 1 ? inj_e0<T, DP>(A, sg, bg, 1, c) : T(0);
 #pragma unroll
       for (int t2 = 0; t2 < SLICE_WIN; ++t2) {
         if (t2 < WL) {
-          const T x = dp[(long)t2 * DP];
+          T x = dp[(long)t2 * DP];
+          if (t2 == A.w_c) x += ea;
+          if (t2 == A.w_c + sg.y) x += eb;
 #pragma unroll
           for (int t = 0; t < SLICE_WIN; ++t) s[t] += tw[t - t2 + SLICE_WIN - 1] * x;
         }
@@ -1658,7 +1673,10 @@ __global__ __launch_bounds__(64) void last_finish_kernel(MixArgs<T> A) {
     if (ok)
       for (int c = lane >> 4; c < DP; c += 4) {
         const long o = (long)c * Np + st;
-        const double x = (double)dp[(long)t * DP + c];
+        T xz = dp[(long)t * DP + c];
+        if (A.L == 1 && t == A.w_c) xz += inj_e0<T, DP>(A, sg, bg, 0, c);
+        if (A.L == 1 && t == A.w_c + sg.y) xz += inj_e0<T, DP>(A, sg, bg, 1, c);
+        const double x = (double)xz;
         o0 += ((double)A.tau[2 * bL + o] - (double)A.tb.Wk[o]) * x;
         o1 += ((double)A.tau[2 * bL + (long)DP * Np + o] - (double)A.tb.Wk[(long)DP * Np + o]) * x;
       }
