@@ -363,7 +363,7 @@ def main():
         log(f"[bench] {path}: {el / args.steps * 1e3:.2f} ms/step, {B * args.steps / el:.1f} samples/s")
 
     grad = None
-    if not args.no_grad and shape.bc == "open" and not shape.inject_phi:
+    if not args.no_grad and shape.bc == "open":
         # per-sample log-derivatives of the same batch (the consumer of E_loc in a VMC step)
         log(f"[bench] {args.workload} per-sample gradients")
         for _ in range(max(1, args.warmup)):

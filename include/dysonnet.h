@@ -262,8 +262,9 @@ dn_status dn_eloc(dn_model* m, int32_t path, const dn_ham_desc* ham, const int8_
  * dn_model_set_params). grads: [B][P] in the model's field type (float for DN_PREC_FP32, double
  * for DN_PREC_FP64), nullable (then kept in the workspace); logpsi [B] nullable; weights [B] and
  * wsum [P] (float64, both or neither): wsum = sum_b weights[b] O[b][.]. Open and periodic
- * chains (periodic: the Jacobian of the aliased kernel, Sec. V); inject_phi = 0 only
- * (DN_EUNSUPPORTED otherwise). A complex_out model has complex O = d Re log psi + i d Im log psi
+ * chains (periodic: the Jacobian of the aliased kernel, Sec. V); with inject_phi = 1 the
+ * checkpoints hold the mixer inputs h + phi and the phi stream also receives the mixer input's
+ * adjoint. A complex_out model has complex O = d Re log psi + i d Im log psi
  * (the parameters are real): grads is then [2][B][P] (all real parts, then all imaginary
  * parts; two reverse passes), wsum [2][P] likewise, logpsi [B][2]. Asynchronous on the stream. */
 dn_status dn_grad_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi, void* grads,

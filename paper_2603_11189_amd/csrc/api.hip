@@ -552,7 +552,9 @@ dn_status forward_chunk(dn_model* m, const int8_t* spins, CfgMap map, int cfg0, 
     a.tb = tb; a.N = d.N; a.Np = Np; a.l = l; a.L = L; a.w_c = d.w_c;
     a.periodic = d.bc == DN_BC_PERIODIC; a.inject = d.inject_phi; a.C = C; a.cfg0 = cfg0;
     a.X = v; a.chi = chi_of(l); a.p0_out = cache_p0 ? cache_p0 + (long)l * fld : nullptr;
-    a.phi_next = phi; a.out = (l + 1 < L) ? (ck.h ? ck.h + (long)(l + 1) * fld : u) : nullptr; a.rho = rho;
+    // phi^(l+2) (injected into the next mixer input): the checkpoint slot when it has one
+    a.phi_next = (ck.phi && l + 2 < L) ? ck.phi + (long)(l + 2) * fld : phi;
+    a.out = (l + 1 < L) ? (ck.h ? ck.h + (long)(l + 1) * fld : u) : nullptr; a.rho = rho;
     a.R_acc = ck.R;
     // the gradient's forward (checkpoints) stays in float: its backward is float
     STCHK((launch_mix<T, DP, MIX_FWD>(m, a, C, st, ck.h == nullptr)));
@@ -1201,7 +1203,8 @@ dn_status grad_chunk(dn_model* m, const int8_t* spins, CfgMap idmap, int b0, int
     T* dph_cur = dph[flip];
     {
       PhiBwdArgs<T> a{tb.ADm + (long)tl * DP * DP, tb.WDm + (long)tl * DP * DP, tb.Kc + (long)tl * Wc * DP,
-                      N, Np, wc, d.bc == DN_BC_PERIODIC, d.act, dchi, tzeta, tz, dph_next, dzeta, dz, da, dph_cur};
+                      N, Np, wc, d.bc == DN_BC_PERIODIC, d.act, dchi, tzeta, tz, dph_next, dzeta, dz, da, dph_cur,
+                      d.inject_phi ? du_cur : nullptr};
       const size_t lds = (size_t)DP * (Np + 2 * wc + 1) * sizeof(T);
       PScope ps(m, DN_K_OTHER, st, 4.0 * Bc * (double)N * dd * dd, 7.0 * fld * sizeof(T));
       if constexpr (std::is_same<T, double>::value) {
@@ -1250,7 +1253,6 @@ template <typename T, int DP>
 dn_status grad_logpsi(dn_model* m, const int8_t* spins, int B, double* logpsi, void* grads_out, const double* w,
                       double* wsum, hipStream_t st) {
   const dn_model_desc& d = m->desc;
-  if (d.inject_phi) return fail(DN_EUNSUPPORTED, "per-sample gradients need inject_phi = 0");
   STCHK(ensure_jac(m, st));
   T* grads = (T*)grads_out;
   const long Pn = m->lay.P;

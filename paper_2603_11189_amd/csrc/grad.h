@@ -122,7 +122,8 @@ __global__ __launch_bounds__(512) void mixbwd_kernel(MixBwdArgs<T> A) {
 
 // ------------------------------------------------------------------------------------------
 // Backward of the phi stream of block l, per configuration (one workgroup, 4 waves):
-//   dzeta = dchi * g'(zeta);  dphi = A_D^T dzeta + dphi_next;  dz = dphi * g'(z)
+//   dzeta = dchi * g'(zeta);  dphi = A_D^T dzeta + dphi_next (+ du^(l) with phi injected into
+//   the mixer input u^(l) = h^(l-1) + phi^(l), Fig. 1c);  dz = dphi * g'(z)
 //   da_i = sum_r K_r * dz_{i-r};  dphi_prev = W_D^T da
 template <typename T> struct PhiBwdArgs {
   const T *ADm, *WDm;      // operand tables of A_D^T, W_D^T for this block
@@ -130,6 +131,7 @@ template <typename T> struct PhiBwdArgs {
   int N, Np, w_c, periodic, act;
   const T *dchi, *zeta, *z, *dphi_next;  // dphi_next nullable
   T *dzeta, *dz, *da, *dphi_prev;        // dphi_prev nullable
+  const T* dphi_inj;                     // nullable: phi injected, the gradient of the mixer input u^(l)
 };
 
 template <typename T> __device__ inline T act_grad(int act, T x) {
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) void phibwd_kernel(PhiBwdArgs<T> A) {
           for (int r = 0; r < 4; ++r) {
             const int ch = 16 * mt + M::row(lane, r);
             const long o = fo + (long)ch * Np + i;
-            T dphi = acc[mt][n][r] + (A.dphi_next ? A.dphi_next[o] : T(0));
+            T dphi = acc[mt][n][r] + (A.dphi_next ? A.dphi_next[o] : T(0)) + (A.dphi_inj ? A.dphi_inj[o] : T(0));
             T dzv = (i < N) ? dphi * act_grad<T>(A.act, A.z[o]) : T(0);
             A.dz[o] = dzv;
             zs[ch * ld + i + wc] = dzv;

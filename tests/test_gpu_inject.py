@@ -27,6 +27,7 @@ import torch
 
 import dn_inputs as di
 import oracle as O
+from oracle.grad import grad_logpsi_batched
 from oracle.model import ModelDesc, forward
 from oracle.sampler import screened_sweep, typewriter_sites
 
@@ -173,3 +174,39 @@ def test_inject_ragged_matches_oracle(L):
         assert e_el <= tol and e_lp <= tol
     for m in models:
         m.close()
+
+
+GRAD_CASES = [
+    (di.ModelShape(12, 1, 4, 2, act="tanh", bc="open", inject_phi=1), "fp64"),
+    (di.ModelShape(14, 2, 6, 3, act="silu", bc="periodic", inject_phi=1), "fp64"),
+    (di.ModelShape(16, 3, 8, 4, act="identity", bc="open", w_c=2, inject_phi=1), "fp64"),
+    (di.ModelShape(15, 4, 6, 3, act="silu", bc="periodic", inject_phi=1), "fp64"),
+    (di.ModelShape(9, 3, 6, 3, act="tanh", bc="periodic", inject_phi=1, token=2), "fp64"),
+    (di.ModelShape(14, 2, 6, 3, act="silu", bc="open", inject_phi=1, complex_out=1), "fp64"),
+    (di.ModelShape(40, 3, 20, 6, act="silu", bc="open", inject_phi=1), "fp32"),
+]
+
+
+@pytest.mark.parametrize("shape,prec", GRAD_CASES, ids=lambda x: str(x)[:56])
+@pytest.mark.parametrize("scale", ["baseline", "stress"])
+def test_inject_grad_matches_oracle(L, shape, prec, scale):
+    """Log-derivatives with phi injected (the backward adds the mixer input's gradient to the
+    phi stream's) against the oracle's autodiff; measure and bounds of the per-site gradient
+    tests: eps_grad = max_b ||g_b - g*_b|| / max(||g*_b||, 1e-3 max_b' ||g*_b'||), 1e-10 in
+    float64 mode, 1e-4 in float32 mode."""
+    _say("inject grad", shape, prec, scale)
+    th = torch.tensor(di.draw_params(shape, 6105, scale))
+    m = L.Model(shape, prec)
+    m.set_params(th)
+    sp = di.uniform_spins(5, shape.n_spins, 7)
+    lp, g, _ = m.grad_logpsi(torch.tensor(sp, device="cuda"))
+    ref = grad_logpsi_batched(ModelDesc.of(shape), th, sp)
+    g = g.cpu()
+    if ref.is_complex():  # real and imaginary parts side by side
+        g, ref = torch.cat([g.real, g.imag], 1), torch.cat([ref.real, ref.imag], 1)
+    g, ref = g.double(), ref.double()
+    nrm = ref.norm(dim=1)
+    e = ((g - ref).norm(dim=1) / nrm.clamp_min(max(1e-3 * nrm.max().item(), 1e-300))).max().item()
+    _say(f"  eps_grad {e:.3e}")
+    assert e <= (1e-10 if prec == "fp64" else 1e-4)
+    m.close()

@@ -1,6 +1,8 @@
 """Pin of the oracle's per-sample log-derivatives (used by VMC/SR, Sec. VI): reverse-mode
-gradients against central finite differences (eps = 1e-6, FP64) on 16 random parameters."""
+gradients against central finite differences (eps = 1e-6, FP64) on 16 random parameters, for
+the Definition block and for phi injected into the h stream (Fig. 1c)."""
 import numpy as np
+import pytest
 import torch
 
 import dn_inputs as di
@@ -8,8 +10,9 @@ from oracle.grad import grad_logpsi, grad_logpsi_batched
 from oracle.model import ModelDesc, forward
 
 
-def test_gradient_matches_central_differences():
-    shape = di.ModelShape(12, 2, 4, 3, bc="open", act="silu")
+@pytest.mark.parametrize("inj,bc", [(0, "open"), (1, "open"), (1, "periodic")])
+def test_gradient_matches_central_differences(inj, bc):
+    shape = di.ModelShape(12, 2, 4, 3, bc=bc, act="silu", inject_phi=inj)
     desc = ModelDesc.of(shape)
     th = torch.tensor(di.draw_params(shape, 6005, "stress"))
     sp = torch.tensor(di.uniform_spins(2, 12, 3))
