@@ -54,6 +54,12 @@ CASES = [
     (di.ModelShape(96, 3, 32, 16, bc="open"), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6, "uniform", "baseline"),
     (di.ModelShape(70, 2, 48, 8, act="tanh", bc="open"), di.HamSpec("j1j2", "open"), 5, "uniform", "stress"),
     (di.ModelShape(70, 2, 48, 8, act="tanh", bc="open"), di.HamSpec("j1j2", "open"), 5, "uniform", "baseline"),
+    # phi injected into the h stream: two blocks take the deep path's last block with partial
+    # slices over at most 8 positions, three blocks the first block without the unit-flip table
+    (di.ModelShape(70, 2, 48, 8, act="tanh", bc="periodic", inject_phi=1), di.HamSpec("j1j2", "periodic"), 5,
+     "uniform", "stress"),
+    (di.ModelShape(96, 3, 32, 16, bc="open", inject_phi=1), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6,
+     "uniform", "stress"),
 ]
 
 
