@@ -6,7 +6,8 @@ oracle's dense solve (Sec. II and VI; App. "Network parameters": standard SR, di
   (S + shift I) x = F by Cholesky; float64: <= 1e-8 relative, float32 log-derivatives: 1e-4;
 * a VMC run with exact enumeration (every configuration, weights |psi|^2 / Z) on the GPU: the
   energy the update reports equals the oracle's exact energy at the same parameters at every
-  step, and it approaches the ground-state energy of the dense Hamiltonian.
+  step, and it approaches the ground-state energy of the dense Hamiltonian, with and without
+  phi injected into the h stream.
 """
 import sys
 
@@ -71,8 +72,10 @@ def test_sr_update_matches_dense_solve(L, prec, weighted):
     m.close()
 
 
-def test_vmc_with_exact_enumeration_approaches_ground_state(L):
-    shape = di.ModelShape(6, 1, 3, 2, act="tanh", bc="open")
+@pytest.mark.parametrize("inj", [0, 1])
+def test_vmc_with_exact_enumeration_approaches_ground_state(L, inj):
+    # inj: phi injected into the h stream (the estimator, gradients and SR of that block)
+    shape = di.ModelShape(6, 1, 3, 2, act="tanh", bc="open", inject_phi=inj)
     ham = di.HamSpec("lrtfim", "open", J=-1.0, alpha=2.0, h=-0.6)
     desc = ModelDesc.of(shape)
     th = torch.tensor(di.draw_params(shape, 31, "stress")).cuda()
@@ -92,7 +95,7 @@ def test_vmc_with_exact_enumeration_approaches_ground_state(L):
         assert abs(energy.item() - E_ref) <= 1e-10 * abs(E_ref)
         hist.append(energy.item())
         th = th + delta
-    _say(f"vmc: E {hist[0]:.6f} -> {hist[-1]:.6f} (ground state {e0:.6f})")
+    _say(f"vmc (inject {inj}): E {hist[0]:.6f} -> {hist[-1]:.6f} (ground state {e0:.6f})")
     assert hist[-1] < hist[0]
     assert hist[-1] - e0 <= 0.1 * (hist[0] - e0)
     m.close()
