@@ -45,6 +45,8 @@ CASES = [
     # shape, prec, first B (several scratch chunks), second B
     (di.ModelShape(256, 4, 64, 32, bc="open"), "fp32", 300, 37),
     (di.ModelShape(130, 2, 32, 16, bc="periodic", act="tanh"), "fp64", 90, 5),
+    # phi injected into the h stream
+    (di.ModelShape(100, 3, 32, 16, bc="periodic", inject_phi=1), "fp32", 120, 9),
 ]
 
 
