@@ -672,7 +672,7 @@ def bench_sweep(args) -> None:
     """Speedup of ABACUS over full re-evaluation on the same GPU across chain lengths: the
     long-range Ising chain (alpha=2, h=0.5), d=64, state 32, float32, B samples per N; or,
     with --paper-shapes, the paper's matched runtime shapes (L=2, d=2, state 12, token size 2,
-    periodic, N = 100 .. 1000 spins)."""
+    periodic, N = 100 .. 1000 spins). --inject: the same networks with phi injected."""
     import torch
 
     import dn_inputs as di
@@ -691,6 +691,8 @@ def bench_sweep(args) -> None:
         ham = di.HamSpec("lrtfim", "open", J=1.0, alpha=2.0, h=0.5)
         grid = [(di.ModelShape(N, depth, 64, 32, act="silu", bc="open"), depth)
                 for depth in (2, 4) for N in (64, 128, 256, 512)]
+    if args.inject:  # the same networks with phi injected into the h stream
+        grid = [(dataclasses.replace(shape, inject_phi=1), depth) for shape, depth in grid]
     for shape, depth in grid:
         N = shape.n_spins  # spins: one connected element per spin
         m = L.Model(shape, "fp32")
@@ -714,6 +716,7 @@ def bench_sweep(args) -> None:
         m.close()
         line = {"metric": "E_loc samples/sec, ABACUS vs full re-eval (sweep)", "N": N, "L": depth,
                 "token": shape.token, "d": shape.d, "s": shape.s, "bc": shape.bc, "B": B, "dtype": "f32",
+                "inject_phi": shape.inject_phi,
                 "abacus": rate["abacus"],
                 "full": rate["full"], "speedup": rate["abacus"] / rate["full"],
                 "us_per_element": {p: 1e6 / (rate[p] * N) for p in rate}, "unit": "samples/s",
