@@ -60,6 +60,8 @@ CASES = [
      "uniform", "stress"),
     (di.ModelShape(96, 3, 32, 16, bc="open", inject_phi=1), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 6,
      "uniform", "stress"),
+    # the headline shape (N=256, four blocks, d=64, s=32), four samples, stress draw
+    (di.ModelShape(256, 4, 64, 32, bc="open"), di.HamSpec("lrtfim", "open", alpha=2.0, h=0.5), 4, "uniform", "stress"),
 ]
 
 
