@@ -62,6 +62,10 @@ CASES = [
     (di.ModelShape(9, 1, 6, 3, act="silu", bc="periodic", inject_phi=1, token=2), di.HamSpec("j1j2", "periodic"),
      "fp64", 3),
     (di.ModelShape(70, 1, 32, 16, bc="periodic", inject_phi=1), di.HamSpec("j1j2", "periodic"), "fp32", 3),
+    # wider CNN windows: S_1 of a pair cluster nine sites wide at w_c = 3, S_2 eleven at w_c = 2
+    (di.ModelShape(19, 1, 6, 3, act="silu", bc="open", w_c=3, inject_phi=1), di.HamSpec("j1j2", "open"), "fp64", 3),
+    (di.ModelShape(21, 2, 6, 3, act="tanh", bc="periodic", w_c=2, inject_phi=1), di.HamSpec("j1j2", "periodic"),
+     "fp64", 3),
     (di.ModelShape(16, 2, 8, 4, act="tanh", bc="open", inject_phi=1), di.HamSpec("lrtfim", "open"), "fp64", 4),
     (di.ModelShape(18, 2, 6, 3, act="silu", bc="periodic", inject_phi=1), di.HamSpec("j1j2", "periodic"), "fp64", 3),
     (di.ModelShape(20, 3, 8, 4, act="silu", bc="open", inject_phi=1), di.HamSpec("j1j2", "open"), "fp64", 3),
