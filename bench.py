@@ -562,6 +562,8 @@ def bench_sampler(args) -> None:
 
     w = di.WORKLOADS[args.workload]
     shape = w.model
+    if args.inject:  # same parameter layout, phi added to each mixer input
+        shape = dataclasses.replace(shape, inject_phi=1)
     prec = args.prec or w.prec
     spacing, eps = 8, 0.01
     dev = torch.device("cuda")
@@ -611,7 +613,8 @@ def bench_sampler(args) -> None:
         "value": props / sec, "unit": "proposals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-mixed"}[prec], "data": "synthetic",
-        "config": {"workload": args.workload + "_sampler", "N": N, "L": shape.L, "d": shape.d, "chains": B,
+        "config": {"workload": args.workload + ("_inject_phi" if args.inject else "") + "_sampler", "N": N,
+                   "L": shape.L, "d": shape.d, "chains": B,
                    "spacing": spacing, "eps": "adaptive eps(n), default 0.2, gamma 1.5" if args.eps_adaptive else eps,
                    "params": "stress draw", "step": "one sweep (both parities)"},
         "acceptance": acc_tot / (props * args.steps), "refreshes_per_proposal": ref_tot / (props * args.steps),

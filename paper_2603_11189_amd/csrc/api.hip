@@ -809,14 +809,17 @@ dn_status launch_shallow(dn_model* m, const SliceArgs<T>& sa, Flip12Args<T> a, i
 template <typename T, int DP>
 dn_status abacus_exec(dn_model* m, const int8_t* spins, int B, const int32_t* sites, int M_max,
                       const int32_t* offs, const int32_t* cb, const int32_t* cm, const int32_t* h_offs,
-                      double* logpsi, double* logratio, int ext_max, hipStream_t st, double* dom = nullptr) {
+                      double* logpsi, double* logratio, int ext_max, hipStream_t st, double* dom = nullptr,
+                      bool few = false) {
   const dn_model_desc& d = m->desc;
   const int Np = m->Np, L = d.L, wc = d.w_c;
   // phi injected into the h stream: the input change of block l + 1 is dh^(l) + dphi^(l+1),
   // a vector on S_(l+1) rather than a multiple of E at the cluster, so every depth takes the
   // full-chain propagation (one block: the slices and the per-flip finish)
   const bool inj = d.inject_phi != 0;
-  const bool shallow = L <= 2 && !inj;
+  // few: a handful of flips per sample (the sampler's proposals), where building block 2's
+  // pivot-0 link per sample costs more than propagating each flip through block 1
+  const bool shallow = L <= 2 && !inj && !(few && L == 2);
   // identity map for the background forward
   int32_t *idb, *idm;
   STCHK(identity_map(m, "ab_idb", "ab_idm", B, &idb, &idm, st));
@@ -1310,6 +1313,10 @@ template <typename T, int DP> struct RunFull {
 // One half-sweep of the screened typewriter sampler over B chains (see sampler.h): rounds of
 // (background + ABACUS changes of every chain's remaining proposals, sequential screened
 // acceptance per chain) until no chain froze; one host synchronisation per round.
+// Proposals per chain and half-sweep up to which a two-block network's sweep propagates each
+// proposal through block 1 rather than building block 2's pivot-0 link per chain.
+constexpr int SWEEP_FEW = 32;
+
 template <typename T, int DP> struct RunSweep {
   static dn_status run(dn_model* m, int8_t* spins, int B, int spacing, int parity, const double* r_site,
                        const double* u, double eps, int32_t* accepted, int32_t* refreshes, hipStream_t st,
@@ -1363,7 +1370,7 @@ template <typename T, int DP> struct RunSweep {
       std::vector<int32_t> h_offs;
       STCHK(plan(m, a.n_conn, a.sites_r, rows, K, 0, &offs, &cb, &cm, std::max(rows * K, 1), &h_offs, st));
       STCHK((abacus_exec<T, DP>(m, rs, rows, a.sites_r, K, offs, cb, cm, h_offs.data(), nullptr, (double*)plr, 0, st,
-                                (double*)pdom)));
+                                (double*)pdom, K <= SWEEP_FEW)));
       void* pOm;
       STCHK(ws_get(m, "ab_Om0", (size_t)rows * 2 * sizeof(double), &pOm));
       a.Om0 = (const double*)pOm;
