@@ -158,7 +158,10 @@ dn_status dn_logpsi(dn_model* m, const int8_t* spins, int32_t B, double* logpsi,
  * spins: device int8 [B][N], updated in place. r_site, u: device float64 [B][K] (uniform draws
  * in [0, 1), supplied by the caller). accepted: device int32 [B][K] (1 = accepted); refreshes:
  * device int32 [B] (background rebuilds per chain). The sampler's ABACUS uses the model's
- * workspace; one host synchronisation per refresh round. Requirements as for DN_PATH_ABACUS. */
+ * workspace; one host synchronisation per refresh round. Requirements as for DN_PATH_ABACUS.
+ * A two-block network with at most 32 proposals per chain propagates each proposal through
+ * block 1 over the whole chain instead of building block 2's pivot-0 link per chain (cheaper
+ * at so few flips per background; same results). */
 dn_status dn_screened_sweep(dn_model* m, int8_t* spins, int32_t B, int32_t spacing, int32_t parity,
                             const double* r_site, const double* u, double eps, int32_t* accepted,
                             int32_t* refreshes, void* stream);
