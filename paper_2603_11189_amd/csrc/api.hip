@@ -1410,11 +1410,23 @@ template <typename T, int DP> struct RunSR {
       sr_dot_sum_kernel<<<1, 256, 0, st>>>(dpart, out);
     };
     const int gp = (int)((P + 255) / 256), gv = (int)std::min<long>(1024, (P + 255) / 256);
+    // partial sums of the split passes over O (column slices or row segments, one at a time)
+    void* ppart;
+    STCHK(ws_get(m, "sr_part", (size_t)std::max<long>((long)SR_ROW_SLICES * P, (long)B * SR_ROW_SEGS) * 8, &ppart));
+    double* part = (double*)ppart;
+    auto colsum = [&](const T* Oq, int nrows, const double* coef, const double* v, double sh, double* out) {
+      sr_colsum_part_kernel<T><<<dim3(gp, SR_ROW_SLICES), 256, 0, st>>>(Oq, P, nrows, coef, part);
+      sr_colsum_fin_kernel<<<gv, 256, 0, st>>>(part, P, v, sh, out);
+    };
+    auto rowdot = [&](const T* Oq, const double* v, const double* sub, double* tq) {
+      sr_rowdot_part_kernel<T><<<dim3((B + SR_ROW_BLK - 1) / SR_ROW_BLK, SR_ROW_SEGS), 256, 0, st>>>(Oq, P, B, v, part);
+      sr_rowdot_fin_kernel<<<(B + 255) / 256, 256, 0, st>>>(part, B, sub, wv, tq);
+    };
     for (int q = 0; q < parts; ++q) {
       sr_energy_kernel<<<1, 1024, 0, st>>>(E + q, parts, w, B, wv, we + (long)q * B, sc + 5 + q);
-      sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O + (long)q * B * P, P, B, wv, nullptr, 0.0, Ob + (long)q * P);
+      colsum(O + (long)q * B * P, B, wv, nullptr, 0.0, Ob + (long)q * P);
     }
-    sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, rows, we, nullptr, 0.0, F);
+    colsum(O, rows, we, nullptr, 0.0, F);
     sr_init_kernel<<<gv, 256, 0, st>>>(x, r, p, F, P);
     dot(F, F, sc + 0);
     dot(F, F, sc + 4);
@@ -1429,9 +1441,9 @@ template <typename T, int DP> struct RunSR {
         for (int q = 0; q < parts; ++q) {
           double* sub = sc + (q ? 7 : 3);
           dot(Ob + (long)q * P, p, sub);
-          sr_rowdot_kernel<T><<<B, 256, 0, st>>>(O + (long)q * B * P, P, p, sub, wv, t + (long)q * B);
+          rowdot(O + (long)q * B * P, p, sub, t + (long)q * B);
         }
-        sr_colsum_kernel<T><<<gp, 256, 0, st>>>(O, P, rows, t, p, shift, Ap);
+        colsum(O, rows, t, p, shift, Ap);
         dot(p, Ap, sc + 1);
         sr_step_kernel<<<gv, 256, 0, st>>>(x, r, p, Ap, P, sc);
         dot(r, r, sc + 2);

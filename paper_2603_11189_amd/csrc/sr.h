@@ -5,8 +5,8 @@
 //   S v = O^T (w * t),  t_b = (O v)_b - Obar . v          (= Oc^T W Oc v, Oc = O - 1 Obar^T)
 //   (S + shift I) x = F by conjugate gradients,  delta = -eta x.
 // O is read in the model's field type and every sum is float64. The passes over O are
-// bandwidth bound: one thread per parameter for the column sums (coalesced rows), one
-// workgroup per sample for the row products.
+// bandwidth bound: one thread per parameter for the column sums (coalesced rows), workgroups
+// over segments of each sample's row for the row products.
 // A complex wavefunction with real parameters (complex read-out) has O = Or + i Oi and complex
 // E_b; its force and SR matrix are the real parts of the conjugated moments, which split into
 // the real problem of the rows Or (energies Re E) plus that of the rows Oi (energies Im E), each
@@ -40,53 +40,106 @@ __global__ __launch_bounds__(1024) void sr_energy_kernel(const double* __restric
   if (threadIdx.x == 0) *ebar = eb;
 }
 
-// out_k = sum_b coef_b O_bk (+ shift v_k when v is given), one thread per parameter.
+// The passes over O split their reduction so that enough waves are in flight to keep HBM
+// busy: the column sums over SR_ROW_SLICES slices of the rows (partials [slice][P], added
+// in slice order by sr_colsum_fin_kernel), the row products over SR_ROW_SEGS segments of
+// each row, SR_ROW_BLK rows per workgroup (partials [row][segment], added in order by
+// sr_rowdot_fin_kernel).
+constexpr int SR_ROW_SLICES = 8;
+constexpr int SR_ROW_SEGS = 16;
+constexpr int SR_ROW_BLK = 4;  // rows per workgroup of the row products
+
+// part[y][k] = sum over rows b of slice y of coef_b O_bk, one thread per parameter.
 template <typename T>
-__global__ __launch_bounds__(256) void sr_colsum_kernel(const T* __restrict__ O, long P, int B,
-                                                        const double* __restrict__ coef, const double* __restrict__ v,
-                                                        double shift, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void sr_colsum_part_kernel(const T* __restrict__ O, long P, int B,
+                                                             const double* __restrict__ coef, double* __restrict__ part) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
-  // four partial sums, sixteen rows requested together (the loads, not the adds, set the pace)
+  const int per = (B + SR_ROW_SLICES - 1) / SR_ROW_SLICES;
+  const int b0 = blockIdx.y * per, b1 = min(B, b0 + per);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  int b = 0;
-  for (; b + 16 <= B; b += 16) {
+  int b = b0;
+  for (; b + 16 <= b1; b += 16) {
     T o[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) o[i] = O[(long)(b + i) * P + k];
 #pragma unroll
     for (int i = 0; i < 16; ++i) s[i & 3] += coef[b + i] * (double)o[i];
   }
-  for (; b < B; ++b) s[0] += coef[b] * (double)O[(long)b * P + k];
-  double r = (s[0] + s[1]) + (s[2] + s[3]);
-  if (v) r += shift * v[k];
-  out[k] = r;
+  for (; b < b1; ++b) s[0] += coef[b] * (double)O[(long)b * P + k];
+  part[(long)blockIdx.y * P + k] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// t_b = sum_k O_bk v_k - *sub (one workgroup per sample), scaled by w_b.
-template <typename T>
-__global__ __launch_bounds__(256) void sr_rowdot_kernel(const T* __restrict__ O, long P, const double* __restrict__ v,
-                                                        const double* __restrict__ sub, const double* __restrict__ w,
-                                                        double* __restrict__ t) {
-  __shared__ double part[4];
-  const int b = blockIdx.x;
-  const T* row = O + (long)b * P;
-  // eight elements of the row requested together, four partial sums
-  double sp[4] = {0.0, 0.0, 0.0, 0.0};
-  const long st = blockDim.x;
-  long k = threadIdx.x;
-  for (; k + 7 * st < P; k += 8 * st) {
-    T o[8];
+// out_k = sum_y part[y][k] in slice order (+ shift v_k when v is given).
+__global__ __launch_bounds__(256) void sr_colsum_fin_kernel(const double* __restrict__ part, long P,
+                                                            const double* __restrict__ v, double shift,
+                                                            double* __restrict__ out) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (long)gridDim.x * blockDim.x) {
+    double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = row[k + i * st];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) sp[i & 3] += (double)o[i] * v[k + i * st];
+    for (int y = 0; y < SR_ROW_SLICES; ++y) r += part[(long)y * P + k];
+    if (v) r += shift * v[k];
+    out[k] = r;
   }
-  for (; k < P; k += st) sp[0] += (double)row[k] * v[k];
-  double s = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+}
+
+// part[b][y] = sum over the y-th segment of row b of O_bk v_k. Workgroup (g, y) takes rows
+// SR_ROW_BLK g .. SR_ROW_BLK g + SR_ROW_BLK - 1, so every element of v read serves that many
+// rows (v, float64, would otherwise move twice the bytes of O through the caches).
+template <typename T>
+__global__ __launch_bounds__(256) void sr_rowdot_part_kernel(const T* __restrict__ O, long P, int B,
+                                                             const double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double red[SR_ROW_BLK][4];
+  const int b0 = blockIdx.x * SR_ROW_BLK, y = blockIdx.y;
+  const long seg = (P + SR_ROW_SEGS - 1) / SR_ROW_SEGS;
+  const long k0 = (long)y * seg, k1 = min(P, k0 + seg);
+  const T* rows[SR_ROW_BLK];
+#pragma unroll
+  for (int r = 0; r < SR_ROW_BLK; ++r) rows[r] = O + (long)min(b0 + r, B - 1) * P;  // a row past B repeats the last
+  double sp[SR_ROW_BLK][2] = {};
+  const long st = blockDim.x;
+  long k = k0 + threadIdx.x;
+  for (; k + 3 * st < k1; k += 4 * st) {
+    double vv[4];
+    T o[SR_ROW_BLK][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) vv[i] = v[k + i * st];
+#pragma unroll
+    for (int r = 0; r < SR_ROW_BLK; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[r][i] = rows[r][k + i * st];
+#pragma unroll
+    for (int r = 0; r < SR_ROW_BLK; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sp[r][i & 1] += (double)o[r][i] * vv[i];
+  }
+  for (; k < k1; k += st) {
+    const double vk = v[k];
+#pragma unroll
+    for (int r = 0; r < SR_ROW_BLK; ++r) sp[r][0] += (double)rows[r][k] * vk;
+  }
+#pragma unroll
+  for (int r = 0; r < SR_ROW_BLK; ++r) {
+    const double s = wave_sum(sp[r][0] + sp[r][1]);
+    if ((threadIdx.x & 63) == 0) red[r][threadIdx.x >> 6] = s;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) t[b] = w[b] * (part[0] + part[1] + part[2] + part[3] - *sub);
+  if (threadIdx.x < SR_ROW_BLK && b0 + (int)threadIdx.x < B) {
+    const int r = threadIdx.x;
+    part[(long)(b0 + r) * SR_ROW_SEGS + y] = (red[r][0] + red[r][1]) + (red[r][2] + red[r][3]);
+  }
+}
+
+// t_b = w_b (sum_y part[b][y] - *sub), the segments added in order.
+__global__ __launch_bounds__(256) void sr_rowdot_fin_kernel(const double* __restrict__ part, int B,
+                                                            const double* __restrict__ sub,
+                                                            const double* __restrict__ w, double* __restrict__ t) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+#pragma unroll
+  for (int y = 0; y < SR_ROW_SEGS; ++y) s += part[(long)b * SR_ROW_SEGS + y];
+  t[b] = w[b] * (s - *sub);
 }
 
 // a . b in a fixed order, in two steps: SR_DOT_WG workgroups of 256 threads form partial sums
