@@ -99,19 +99,20 @@ __global__ __launch_bounds__(256) void sr_rowdot_part_kernel(const T* __restrict
   double sp[SR_ROW_BLK][2] = {};
   const long st = blockDim.x;
   long k = k0 + threadIdx.x;
-  for (; k + 3 * st < k1; k += 4 * st) {
-    double vv[4];
-    T o[SR_ROW_BLK][4];
+  constexpr int U = 8;  // columns in flight per thread
+  for (; k + (U - 1) * st < k1; k += U * st) {
+    double vv[U];
+    T o[SR_ROW_BLK][U];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) vv[i] = v[k + i * st];
-#pragma unroll
-    for (int r = 0; r < SR_ROW_BLK; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) o[r][i] = rows[r][k + i * st];
+    for (int i = 0; i < U; ++i) vv[i] = v[k + i * st];
 #pragma unroll
     for (int r = 0; r < SR_ROW_BLK; ++r)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sp[r][i & 1] += (double)o[r][i] * vv[i];
+      for (int i = 0; i < U; ++i) o[r][i] = rows[r][k + i * st];
+#pragma unroll
+    for (int r = 0; r < SR_ROW_BLK; ++r)
+#pragma unroll
+      for (int i = 0; i < U; ++i) sp[r][i & 1] += (double)o[r][i] * vv[i];
   }
   for (; k < k1; k += st) {
     const double vk = v[k];
