@@ -49,3 +49,19 @@ def test_products_label_matches_peaks(bench, prec, products, d):
         assert "three-term" in mix and "/ 6" in deep_basis
     else:
         assert mix == "f32 matrix cores" and deep_peak == bench.PEAK["fp32"]
+
+
+@pytest.mark.parametrize("name,cls", [
+    ("void dn::deep_kernel<float, 64, true, false, 3, 16>(dn::MixArgs<float>)", "mix_deep"),
+    ("void dn::inject_add_kernel<float, 64>(dn::MixArgs<float>)", "mix_deep"),
+    ("void dn::inject_w1_kernel<float, 64>(dn::MixArgs<float>)", "conv"),
+    ("void dn::conv_split_kernel<4, 3>(dn::ConvArgs<float>)", "conv"),
+    ("void dn::last_finish_kernel<float, 64, true>(dn::MixArgs<float>)", "tail"),
+    ("void dn::slice_mma_kernel<float, 64, true>(dn::SliceArgs<float>)", "slice"),
+    ("void dn::mix_kernel<float, 64, 1, false>(dn::MixArgs<float>)", "mix_tau"),
+    ("dn::sr_rowdot_part_kernel<float>(float const*, long, int, double const*, double*)", "other"),
+])
+def test_kernel_class_of_profiler_names(bench, name, cls):
+    # the grouping the profile summaries and the roofline use, including the kernels of the
+    # phi-injected path (block 1's mixer output counts with the Toeplitz products it replaces)
+    assert bench.kernel_class(name) == cls
