@@ -153,3 +153,41 @@ def test_adaptive_sweep_matches_oracle(L, shape, spacing, prec):
          f"buffer {[round(x, 4) for x in hbuf]}")
     assert any(hset)
     m.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_two_block_sweep_few_proposals_matches_oracle(L, prec):
+    """A two-block network with few proposals per chain propagates them through block 1 over the
+    whole chain (no pivot-0 link): that path in float32 (three-term split products) and
+    BF16-mixed (hi + lo products) mode, decisions and refreshes against the float64 oracle. The
+    draws are fixed; a decision could only differ where u lies within the mode's rounding of the
+    ratio, which these draws do not meet."""
+    shape = di.ModelShape(40, 2, 32, 8, act="silu", bc="periodic")
+    desc = ModelDesc.of(shape)
+    th = _peaked(shape, 23)
+    m = L.Model(shape, prec)
+    m.set_params(th)
+    B, spacing, eps = 4, 4, 0.05
+    spins = torch.tensor(di.uniform_spins(B, shape.N, 9), device="cuda")
+    host = [spins[b].cpu().long() for b in range(B)]
+    total_acc = 0
+    for sweep in range(4):
+        parity = sweep % 2
+        nblk = (shape.N + spacing - 1) // spacing
+        K = len(range(parity, nblk, 2))
+        rng = np.random.Generator(np.random.PCG64(780 + sweep))
+        r, u = rng.random((B, K)), rng.random((B, K))
+        acc, ref = m.screened_sweep(spins, spacing, parity, torch.tensor(r, device="cuda"),
+                                    torch.tensor(u, device="cuda"), eps)
+        acc, ref = acc.cpu(), ref.cpu()
+        for b in range(B):
+            sites = typewriter_sites(shape.N, spacing, parity, r[b])
+            want = screened_sweep(desc, th, host[b], sites, u[b], eps)
+            assert acc[b].tolist() == [int(x) for x in want["accepted"]], (sweep, b)
+            assert int(ref[b]) == want["refreshes"], (sweep, b)
+            host[b] = want["spins"]
+            total_acc += sum(want["accepted"])
+        assert torch.equal(spins.cpu().long(), torch.stack(host)), sweep
+    _say(f"two-block sweep {prec}: accepted {total_acc}")
+    assert total_acc > 0
+    m.close()
